@@ -1,0 +1,138 @@
+"""Benchmark of the M-ABD per-step solve on one MI355X.
+
+Default workload: the 1,048,576-body ball-jointed chain (body 0 pinned,
+h = 1e-2 s, one Newton iteration per step), plain FP64.  A step is one pass
+of the whole hot path: per-body co-rotated solve and polar decomposition, dual
+assembly, chain dual solve, primal back-projection and state update.
+
+Prints one JSON line with body-steps/s (dynamic bodies x steps / wall time of
+the timed mabd_step call), the live per-kernel roofline of the dominant kernel
+(HIP events on the stream the kernels run on), the KKT residual reached (FP64
+oracle verification of one GPU step), and the FP64 oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per body (or joint) that each kernel must move at
+# minimum (FP64): state q, qdot read (192 B) and written (192 B), per-row
+# anchors of both ends and the side flags (49 B), shape index (4 B),
+# multipliers written (24 B).  See DESIGN.md, "Measurement".
+ALG_BYTES = {
+    "chain_reduce": 192 + 49 + 4,
+    "chain_apply": 192 + 49 + 4 + 192 + 24,
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="chain1m")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kkt-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import mabd_inputs as mi
+    import paper_2603_08079_amd as pk
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    asm = mi.config(args.workload)
+    h = asm.h
+    ctx = pk.Context(asm, stream=stream.cuda_stream, diagnostics=2)
+    st0 = ctx.stats()
+    n_dyn = st0["n_dyn"]
+    print(f"# workload {args.workload}: {asm.n} bodies ({n_dyn} dynamic), {asm.m} joints, "
+          f"chains {st0['n_chain']} trees {st0['n_tree']} graphs {st0['n_graph']}",
+          file=sys.stderr, flush=True)
+    if args.warmup:
+        ctx.step(h, args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    ctx.step(h, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    gpu_ms = e0.elapsed_time(e1)
+    st = ctx.stats()
+    value = n_dyn * args.steps / wall
+    phases = pk.StepStats.PHASES
+    per_launch = {phases[i]: st["phase_ms"][i] / st["phase_calls"][i]
+                  for i in range(8) if st["phase_calls"][i]}
+    dom = max(per_launch, key=lambda k: per_launch[k] * st["phase_calls"][phases.index(k)])
+    roof = None
+    if dom in ALG_BYTES:
+        alg = ALG_BYTES[dom] * n_dyn
+        ach = alg / (per_launch[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_launch_ms": round(per_launch[dom], 4),
+                "alg_bytes_per_launch": alg}
+    print(f"# per-launch ms: { {k: round(v, 4) for k, v in per_launch.items()} }",
+          file=sys.stderr, flush=True)
+
+    kkt = None
+    if not args.no_kkt_check:
+        import oracle
+
+        q_n, qd_n = ctx.state()
+        ctx.step(h, 1)
+        lam = ctx.multipliers()
+        q1, qd1 = ctx.state()
+        s = oracle.System(asm)
+        qo, qdo, diag = s.finish(h, q_n, qd_n, lam)
+        kkt = {"rho_p": float(diag[oracle.RHO_P]), "rho_d": float(diag[oracle.RHO_D]),
+               "kkt": float(diag[oracle.KKT]),
+               "state_rel_err": float(np.abs(q1 - qo).max() / max(1.0, np.abs(qo).max())),
+               "vel_rel_err": float(np.abs(qd1 - qdo).max() / max(1e-300, np.abs(qdo).max()))}
+        print(f"# kkt check {kkt}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        s = oracle.System(asm)
+        tc = time.perf_counter()
+        s.step(h, asm.q0, asm.qd0)
+        dt = time.perf_counter() - tc
+        cpu = {"value": round(n_dyn / dt, 1), "unit": "body-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full step of the {args.workload} workload ({n_dyn} dynamic bodies), "
+                         f"single-threaded FP64 oracle, {dt:.2f} s"}
+
+    out = {
+        "metric": "body-steps/sec at fixed KKT residual (plain FP64 vs chosen form), 1M-link chain",
+        "value": round(value, 1), "unit": "body-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "gpu_ms_per_step": round(gpu_ms / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "bodies": asm.n, "dynamic_bodies": n_dyn,
+                   "joints": asm.m, "h": h, "newton_iters": 1, "form": "plain FP64"},
+        "kkt": kkt, "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * mabd.h -- C ABI of libmabd, an MI355X (gfx950) implementation of the
+ * per-time-step solve of M-ABD: co-rotated affine bodies joined by ball and
+ * hinge joints, one implicit-Euler Newton step per call with the joints
+ * enforced exactly through the KKT system (arXiv 2603.08079, Secs. 3-5).
+ *
+ * One step does, on the GPU:
+ *   (a) per body: polar rotation R = A (A^T A)^{-1/2} (Eq. polar), force
+ *       f_A (Eq. variation_energy, Eq. reduced_K) and the unconstrained local
+ *       solve with the constant pre-factorised Hbar (Eq. abd_final);
+ *   (b) the dual (Schur) system  grad C H^{-1} grad C^T  with right-hand side
+ *       grad C H^{-1} f_A + C  (Eq. dual; -C as in the footnote of Eq. kkt);
+ *   (c) its solution: block cyclic reduction on chains (Eq. chain-btd),
+ *       leaf-to-root elimination on trees (Sec. 5.3), preconditioned CG on
+ *       graphs with loops (Sec. 5.4-5.5);
+ *   (d) the primal back-projection dq = H^{-1}(f_A - grad C^T dlambda)
+ *       (Eq. primal) and the state update q += dq, qdot = dq / h.
+ *
+ * Conventions
+ *   - Every pointer in a struct passed to mabd_create is a HOST pointer; the
+ *     data are copied during the call, the caller keeps ownership.
+ *   - The context owns all device memory; results go to caller buffers.
+ *   - Every call returns a status; mabd_last_error() gives a message.  Nothing
+ *     aborts or throws across the ABI.
+ *   - A context is not thread-safe; several contexts may coexist.  Work is
+ *     issued on the stream given in mabd_options.stream (a hipStream_t), or on
+ *     a stream of the library's own when that is NULL.  Only mabd_state,
+ *     mabd_stats, mabd_multipliers and error paths synchronise that stream.
+ *   - Units are SI.  q per body = [a1; a2; a3; t] (12 doubles), a_c the c-th
+ *     column of the affine matrix A, t the translation (Sec. 3.1, Eq. abd_dof);
+ *     qdot has the same layout.
+ */
+#ifndef MABD_H
+#define MABD_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mabd_ctx mabd_ctx;
+
+typedef enum {
+  MABD_OK = 0,
+  MABD_ERR_INVALID_ARG = -1,  /* bad index, size, non-finite input, bad option   */
+  MABD_ERR_TOPOLOGY = -2,     /* joint graph the library cannot solve            */
+  MABD_ERR_DEVICE = -3,       /* HIP runtime error                               */
+  MABD_ERR_OOM = -4,          /* device allocation failed                        */
+  MABD_ERR_NONFINITE = -5,    /* non-finite state or det A <= 0 during a step    */
+  MABD_ERR_NOT_CONVERGED = -6,/* PCG reached max_iters above kkt_tol              */
+  MABD_ERR_SINGULAR = -7      /* a dual pivot block was not positive definite    */
+} mabd_status;
+
+/* n bodies, all boxes with the rest frame at the centre of mass and axes along
+   the box edges (so the generalised mass J^T M J is diagonal, Eq. newton_abd). */
+typedef struct {
+  int32_t n;
+  const double *dims;      /* n*3  box edge lengths, > 0                                  */
+  const double *density;   /* n    kg/m^3, > 0                                            */
+  const double *k_orth;    /* n    k_A of Eq. EA (material 0) or Young's modulus (1)      */
+  const double *poisson;   /* n    Poisson ratio (material 1 only; may be NULL otherwise) */
+  const uint8_t *pinned;   /* n    1 = kinematic body held at q0 (may be NULL: none)      */
+  const double *q0, *qd0;  /* n*12 initial state (qd0 may be NULL: zero)                  */
+} mabd_bodies;
+
+/* m joints.  type 0: ball joint, 3 rows (Eq. ball).  type 1: hinge, 5 rows
+   (Eq. hinge): CP1 of both bodies coincide, CP2 = CP1 + cp_len * axis lies on
+   the axis and only its two off-axis local coordinates are constrained;
+   body a owns the hinge frame R_H = Rod(axis) R_a^T (Sec. 4.3, Eq. r_gradient). */
+typedef struct {
+  int32_t m;
+  const uint8_t *type;     /* m    0 ball, 1 hinge                                        */
+  const int32_t *a, *b;    /* m    body indices, -1 = world; a != b; one side dynamic      */
+  const double *pa, *pb;   /* m*3  CP1 in the rest frame of a / b (world coords if -1)    */
+  const double *axis;      /* m*3  hinge axis in a's rest frame (world if a = -1); may be
+                                   NULL if there is no hinge                              */
+  const double *cp_len;    /* m    CP1 -> CP2 spacing (> 0 for hinges; may be NULL)       */
+} mabd_joints;
+
+typedef struct {
+  double gravity[3];       /* m/s^2, default (0, 0, -9.8)                                 */
+  int32_t precision;       /* 0 FP64 throughout; 1 FP32 body/assembly + FP64 factor with
+                              FP64 residual refinement                                   */
+  double kkt_tol;          /* PCG stop: |r - S lam| <= kkt_tol |r|, default 1e-10         */
+  int32_t max_iters;       /* PCG iteration cap, default 200000                           */
+  int32_t warm_start;      /* PCG start: 0 zero, 1 previous step's multipliers, 2 GNN     */
+  int32_t newton_iters;    /* Newton iterations per step, default 1                       */
+  int32_t hinge_grad;      /* 0 frozen frame + A-linearised rotation term, 2 frozen only  */
+  int32_t material;        /* 0: mu = 4 k_A, lambda = 0 (Eq. EA linearised); 1: Lame     */
+  int32_t diagnostics;     /* bit 0: evaluate the FP64 KKT residual after every step;
+                              bit 1: time every kernel group with HIP events (phase_ms)  */
+  void *stream;            /* hipStream_t, or NULL for a library-owned stream             */
+} mabd_options;
+
+typedef struct {
+  int64_t steps_done;      /* steps completed since create                               */
+  int32_t last_status;     /* status of the last mabd_step                               */
+  int32_t pcg_iters;       /* PCG iterations of the last step (max over components)      */
+  double rho_p, rho_d;     /* |H^-1 r_p|/|H^-1 f|, |G dq + C|/|G H^-1 f + C| (diagnostics) */
+  double kkt;              /* max(rho_p, rho_d)                                           */
+  double c_ball, c_hinge;  /* max |C| after the step per joint type (diagnostics)         */
+  int32_t ir_sweeps;       /* refinement sweeps of the last step (precision 1)           */
+  int32_t warm_accepted;   /* 1 if the GNN warm start was kept                            */
+  int32_t n_chain, n_tree, n_graph;  /* components per solver class                     */
+  int32_t n_dyn;           /* dynamic bodies                                              */
+  /* With diagnostics bit 1: GPU time of each kernel group summed over the last
+     mabd_step call, and its launch count.  Groups: 0 chain tile reduce, 1 chain
+     interface solve, 2 chain tile apply, 3 generic bodies, 4 generic joints,
+     5 tree elimination, 6 generic back-projection, 7 PCG. */
+  double phase_ms[8];
+  int64_t phase_calls[8];
+} mabd_step_stats;
+
+/* Fills *opt with the defaults listed above. */
+void mabd_options_default(mabd_options *opt);
+
+/* Validates and copies the assembly, classifies every connected component of
+   dynamic bodies (chain: the dual graph of Fig. dual_mat is a path with only
+   ball joints; tree: body/joint incidence graph acyclic; graph: otherwise),
+   builds the solve schedules and uploads state and schedules to the device.
+   Pinned bodies become constant world-side anchors.  opt may be NULL
+   (defaults).  On success *out receives a context to free with mabd_destroy.
+   Errors: INVALID_ARG (bad sizes, indices, non-finite or non-positive inputs,
+   zero hinge axis), TOPOLOGY, DEVICE, OOM. */
+mabd_status mabd_create(const mabd_bodies *bodies, const mabd_joints *joints,
+                        const mabd_options *opt, mabd_ctx **out);
+
+/* Advances n >= 1 steps of size h > 0 (implicit Euler, Eq. variation_energy;
+   newton_iters Newton iterations per step, Eq. kkt).  If h differs from the
+   previous call the per-shape factors Hbar^{-1} are rebuilt first (Eq.
+   abd_final).  Asynchronous on the context's stream unless diagnostics or PCG
+   convergence need a host read.  On NONFINITE, NOT_CONVERGED or SINGULAR the
+   state stays at the last completed step. */
+mabd_status mabd_step(mabd_ctx *ctx, double h, int32_t n);
+
+/* Copies the state to host buffers q, qd (n*12 doubles each, input body
+   order; either may be NULL).  Synchronises the stream. */
+mabd_status mabd_state(const mabd_ctx *ctx, double *q, double *qd);
+
+/* Writes the state into device buffers (n*12 doubles each, input body order)
+   on the context's stream, without synchronising. */
+mabd_status mabd_state_device(const mabd_ctx *ctx, void *q_dev, void *qd_dev);
+
+/* Replaces the state (host buffers, n*12 doubles each, input order).  Pinned
+   bodies keep q0.  Bitwise continuation: set_state(state()) changes nothing. */
+mabd_status mabd_set_state(mabd_ctx *ctx, const double *q, const double *qd);
+
+/* Multipliers dlambda of the last step's dual solve (Eq. dual) in input joint
+   order, 3 doubles per ball joint and 5 per hinge, concatenated.  lam must hold
+   mabd_rows(ctx) doubles.  Synchronises the stream. */
+mabd_status mabd_multipliers(const mabd_ctx *ctx, double *lam);
+int64_t mabd_rows(const mabd_ctx *ctx);
+
+/* Diagnostics of the last step.  Synchronises the stream. */
+mabd_status mabd_stats(const mabd_ctx *ctx, mabd_step_stats *st);
+
+/* Loads graph-network weights used by warm_start = 2 (binary file written by
+   the package's trainer).  Errors: INVALID_ARG on a bad header. */
+mabd_status mabd_gnn_load(mabd_ctx *ctx, const char *path);
+
+/* Message of the last error on ctx (or of the last failed create if ctx is
+   NULL).  Valid until the next call on the same context. */
+const char *mabd_last_error(const mabd_ctx *ctx);
+
+/* Releases device memory and the owned stream.  NULL is allowed. */
+void mabd_destroy(mabd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,86 @@
+// Host/device shared descriptors of libmabd.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mabd {
+
+// Status bits raised by kernels into a device word (integer atomics only).
+enum : uint32_t {
+  FLAG_NONFINITE = 1u,  // det A <= 0, polar did not converge, or a non-finite value
+  FLAG_SINGULAR = 2u,   // a pivot block of an elimination was not positive definite
+};
+
+// Chain of ball joints in "row space".  Rows r = 0..K-1 are the joints in
+// chain order; the body between rows r and r+1 is position beta(r) = r + 1 - hl
+// (hl = 1 if row 0 is a one-sided joint to the world / a pinned body), valid
+// for 0 <= beta < nb.  Row r's left body is beta(r-1), its right body beta(r).
+struct ChainDesc {
+  int32_t body0;  // first body (solver order) of the chain
+  int32_t nb;     // dynamic bodies
+  int32_t row0;   // first global chain row
+  int32_t K;      // rows (joints), >= 2
+  int32_t hl, hr; // one-sided joint at the start / end
+  int32_t tile0;  // first tile
+  int32_t ntile;  // tiles; global reduced rows = ntile + 1
+  int32_t grow0;  // first global reduced row
+  int32_t pad;
+};
+
+// A tile covers chain-local rows [r0, r0 + T] (T >= 1).  Its rows r0 and r0+T
+// are interface rows shared with the neighbouring tiles.
+struct TileDesc {
+  int32_t chain;
+  int32_t r0;
+  int32_t T;
+  int32_t tidx;   // tile index inside its chain
+};
+
+constexpr int CHAIN_TILE = 254;      // rows per tile - 1; a block has 256 threads
+constexpr int CHAIN_THREADS = 256;
+constexpr int TILE_REC = 27;         // doubles per tile record
+constexpr int GROW_REC = 56;         // doubles per global reduced row (scratch)
+
+// per-shape raw constants used by the force: Mbar0..2, m, V, mu, lambda
+constexpr int SHAPE_STRIDE = 8;
+// per-shape structured inverse of Hbar (layout in dmath.hpp)
+constexpr int HINV_STRIDE = 20;
+
+// status words: [0] FLAG_* bits, [1] first failing step of the current call
+constexpr int NO_FAIL = 0x7fffffff;
+
+struct ChainArgs {
+  const ChainDesc *chains;
+  const TileDesc *tiles;
+  const double *q, *qd;       // input state, SoA with stride ns
+  double *q_out, *qd_out;     // output state (distinct buffers)
+  int64_t ns;
+  const int32_t *shp;         // shape index per body
+  const double *hinv;         // HINV_STRIDE per shape
+  const double *shape;        // SHAPE_STRIDE per shape
+  const double *pl, *pr;      // anchors of the left / right end of each chain row, [3][nrs]
+  const uint8_t *flag;        // bit0: left end is side a of the joint, bit1: right end is
+  int64_t nrs;
+  double g[3];
+  double h;
+  double *tilerec;            // TILE_REC per tile
+  const double *xg;           // 3 per global reduced row
+  double *lam;                // 3 per chain row
+  uint32_t *status;
+  int step;                   // step index inside the current call
+};
+
+#ifdef __HIPCC__
+// record a failure of step `step` (integer atomics only)
+__device__ __forceinline__ void raise_flag(uint32_t *st, uint32_t bits, int step) {
+  atomicOr(st, bits);
+  atomicMin(reinterpret_cast<int *>(st + 1), step);
+}
+// a step after a failed one does nothing, so the last good state survives
+__device__ __forceinline__ bool skip_step(const uint32_t *st, int step) {
+  return *reinterpret_cast<const volatile int *>(st + 1) < step;
+}
+#endif
+
+}  // namespace mabd

@@ -1,0 +1,252 @@
+// Device-side small linear algebra for libmabd (gfx950).
+//
+// Conventions: 3x3 matrices are row-major double[9]; q per body is
+// [a1; a2; a3; t] with A(r, c) = q[3c + r] (Sec. 3.1, Eq. abd_dof).
+//
+// The per-shape table `Hinv` holds the structured inverse of the constant
+// single-body matrix Hbar = M_A / h^2 + Kbar_A (Eq. abd_final) for a box whose
+// rest frame sits at its centre of mass.  There M_A = diag(Mbar) (x) I3 and
+// Kbar_A couples only (A00, A11, A22) among themselves and each off-diagonal
+// pair (A_rc, A_cr), so Hbar^{-1} is one 3x3 block, three 2x2 blocks and a
+// translation scalar (20 doubles, built once per shape and time step).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+#define DEV __device__ __forceinline__
+
+namespace mabd {
+
+// layout of one Hinv entry
+//   [0]       h^2 / m                      (translation block)
+//   [1..6]    (A00,A11,A22) inverse, symmetric: 00 01 02 11 12 22
+//   [7..15]   PD(r,c): diagonal inverse entry of off-diagonal element A_rc
+//             (3x3 row-major, diagonal slots unused)
+//   [16..18]  PX for pairs {A_01,A_10}, {A_02,A_20}, {A_12,A_21}
+enum { HI_T = 0, HI_D = 1, HI_PD = 7, HI_PX = 16 };
+
+DEV int pair_slot(int r, int c) {  // r != c
+  int s = r + c;                   // (0,1)->1 (0,2)->2 (1,2)->3
+  return s - 1;
+}
+
+DEV double sym3(const double *S6, int r, int c) {
+  // S6 = 00 01 02 11 12 22
+  int a = r < c ? r : c, b = r < c ? c : r;
+  int idx = a == 0 ? b : (a == 1 ? 2 + b : 5);
+  return S6[idx];
+}
+
+// y = Hbar^{-1} x for a 12-vector x (structured apply, ~40 flops)
+DEV void hinv_apply(const double *T, const double *x, double *y) {
+  const double ht = T[HI_T];
+  y[9] = ht * x[9];
+  y[10] = ht * x[10];
+  y[11] = ht * x[11];
+  const double *D = T + HI_D;
+  double x0 = x[0], x4 = x[4], x8 = x[8];
+  y[0] = D[0] * x0 + D[1] * x4 + D[2] * x8;
+  y[4] = D[1] * x0 + D[3] * x4 + D[4] * x8;
+  y[8] = D[2] * x0 + D[4] * x4 + D[5] * x8;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (r == c) continue;
+      const int i1 = 3 * c + r, i2 = 3 * r + c;  // A_rc and its partner A_cr
+      y[i1] = T[HI_PD + 3 * r + c] * x[i1] + T[HI_PX + pair_slot(r, c)] * x[i2];
+    }
+}
+
+// W(p, p') = J(p) Hbar^{-1} J(p')^T  (3x3, row-major), J(p) = [p^T (x) I3, I3]
+DEV void wblock(const double *T, const double *p, const double *pp, double *W) {
+  const double *D = T + HI_D;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      double v = p[r] * pp[s] * sym3(D, r, s);
+      if (r == s) {
+        v += T[HI_T];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          if (c != r) v += p[c] * pp[c] * T[HI_PD + 3 * r + c];
+      } else {
+        v += p[s] * pp[r] * T[HI_PX + pair_slot(r, s)];
+      }
+      W[3 * r + s] = v;
+    }
+}
+
+// --------------------------------------------------------------- 3x3 algebra
+
+DEV double det3(const double *A) {
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+         A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+// cofactor matrix: C(r,c) = cofactor of A(r,c); A^{-1} = C^T / det
+DEV void cof3(const double *A, double *C) {
+  C[0] = A[4] * A[8] - A[5] * A[7];
+  C[1] = A[5] * A[6] - A[3] * A[8];
+  C[2] = A[3] * A[7] - A[4] * A[6];
+  C[3] = A[2] * A[7] - A[1] * A[8];
+  C[4] = A[0] * A[8] - A[2] * A[6];
+  C[5] = A[1] * A[6] - A[0] * A[7];
+  C[6] = A[1] * A[5] - A[2] * A[4];
+  C[7] = A[2] * A[3] - A[0] * A[5];
+  C[8] = A[0] * A[4] - A[1] * A[3];
+}
+
+// Polar factor R = A (A^T A)^{-1/2} (Eq. polar) by Newton's iteration
+// X <- (zeta X + X^{-T} / zeta) / 2 with determinant scaling while far from
+// convergence (Higham, Functions of Matrices, Sec. 8.3).  A near-rotation
+// converges in two or three iterations.  Returns false if det A <= 0 or the
+// input is not finite.
+DEV bool polar3(const double *A, double *R) {
+  double X[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) X[i] = A[i];
+  double d0 = det3(X);
+  if (!(d0 > 0.0) || !isfinite(d0)) return false;
+  bool done = false;
+  for (int it = 0; it < 40 && !done; ++it) {
+    double C[9];
+    cof3(X, C);
+    double det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+    if (!(det > 0.0)) return false;
+    double z = 1.0;
+    double diff = 0.0;
+    // X^{-T} = C / det
+    double inv = 1.0 / det;
+    double Y[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Y[i] = C[i] * inv;
+    // scale only while the iterate is far from orthogonal
+    double s0 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s0 += (X[i] - Y[i]) * (X[i] - Y[i]);
+    if (s0 > 1e-4) z = 1.0 / cbrt(det);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      double xn = 0.5 * (z * X[i] + Y[i] / z);
+      diff += (xn - X[i]) * (xn - X[i]);
+      X[i] = xn;
+    }
+    // quadratic convergence: once the step is below 1e-8 the next error is
+    // below roundoff, so this iterate is final
+    if (diff < 1e-16) done = true;
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) R[i] = X[i];
+  return done;
+}
+
+DEV void mat3_mul(const double *A, const double *B, double *C) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
+}
+
+// C = A B^T
+DEV void mat3_mul_bt(const double *A, const double *B, double *C) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      C[3 * r + c] = A[3 * r] * B[3 * c] + A[3 * r + 1] * B[3 * c + 1] + A[3 * r + 2] * B[3 * c + 2];
+}
+
+// C = A^T B
+DEV void mat3_mul_at(const double *A, const double *B, double *C) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      C[3 * r + c] = A[r] * B[c] + A[3 + r] * B[3 + c] + A[6 + r] * B[6 + c];
+}
+
+DEV void mat3_vec(const double *A, const double *x, double *y) {
+  y[0] = A[0] * x[0] + A[1] * x[1] + A[2] * x[2];
+  y[1] = A[3] * x[0] + A[4] * x[1] + A[5] * x[2];
+  y[2] = A[6] * x[0] + A[7] * x[1] + A[8] * x[2];
+}
+
+DEV void mat3t_vec(const double *A, const double *x, double *y) {
+  y[0] = A[0] * x[0] + A[3] * x[1] + A[6] * x[2];
+  y[1] = A[1] * x[0] + A[4] * x[1] + A[7] * x[2];
+  y[2] = A[2] * x[0] + A[5] * x[1] + A[8] * x[2];
+}
+
+// R W R^T for symmetric or general W (full 3x3 out)
+DEV void rot_congr(const double *R, const double *W, double *out) {
+  double T[9];
+  mat3_mul(R, W, T);
+  mat3_mul_bt(T, R, out);
+}
+
+// inverse of a symmetric positive definite 3x3 (returns false if not SPD)
+DEV bool spd3_inv(const double *S, double *I) {
+  double C[9];
+  cof3(S, C);
+  double det = S[0] * C[0] + S[1] * C[1] + S[2] * C[2];
+  if (!(det > 0.0) || !(S[0] > 0.0)) return false;
+  double inv = 1.0 / det;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) I[i] = C[i] * inv;  // symmetric: C^T = C
+  // symmetrise
+  double a = 0.5 * (I[1] + I[3]), b = 0.5 * (I[2] + I[6]), c = 0.5 * (I[5] + I[7]);
+  I[1] = I[3] = a;
+  I[2] = I[6] = b;
+  I[5] = I[7] = c;
+  return true;
+}
+
+// --------------------------------------------------------------- body force
+
+// Local (rotated) right-hand side phi = diag4(R^T) f_A of one body, with
+//   f_A = Mbar qd / h - Mbar (q - qn) / h^2 + [0; m g] + f_el      (Eq. variation_energy)
+// and the co-rotated linear elastic force f_el = -V vec(R P(R^T A))
+// (Eq. reduced_K with dPsi/dA of Sec. 3.3), so that the rotated elastic part
+// is simply -V P.  `sh` = {Mbar0, Mbar1, Mbar2, m, V, mu, lambda}.
+template <typename real>
+DEV void local_force(const double *sh, const real *R, const real *A, const real *q,
+                     const real *qn, const real *qd, const double *g, double h, real *phi) {
+  const real ih = real(1.0 / h), ih2 = real(1.0 / (h * h));
+  real Sym[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      Sym[3 * r + c] = R[r] * A[c] + R[3 + r] * A[3 + c] + R[6 + r] * A[6 + c];
+  const real mu = real(sh[5]), lam = real(sh[6]), V = real(sh[4]);
+  const real tr = Sym[0] + Sym[4] + Sym[8] - real(3.0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const real M = real(sh[c]);
+    real w[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      w[i] = M * qd[3 * c + i] * ih - M * (q[3 * c + i] - qn[3 * c + i]) * ih2;
+    if (c == 3) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) w[i] += real(sh[3] * g[i]);
+    }
+    // R^T w
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      real v = R[r] * w[0] + R[3 + r] * w[1] + R[6 + r] * w[2];
+      if (c < 3) {
+        real P = mu * (Sym[3 * r + c] + Sym[3 * c + r] - real(2.0) * real(r == c)) +
+                 lam * tr * real(r == c);
+        v -= V * P;
+      }
+      phi[3 * c + r] = v;
+    }
+  }
+}
+
+}  // namespace mabd

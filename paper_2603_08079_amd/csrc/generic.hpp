@@ -1,0 +1,55 @@
+// Descriptors of the generic (any topology) path of libmabd.
+#pragma once
+#include <cstdint>
+
+namespace mabd {
+
+// One joint in the generic path.  Side a/b: solver-order dynamic body index,
+// or -1 when that side is the world or a pinned body, in which case p1*/p2*
+// hold the constant world positions of its control points.
+struct GJoint {
+  int32_t type;       // 0 ball (3 rows), 1 hinge (5 rows)
+  int32_t flags;      // bit0: hinge frame owner (side a) is static -> dR holds R_H itself
+  int32_t sa, sb;
+  double p1a[3], p1b[3];  // CP1 (rest frame of the side's body, or world)
+  double p2a[3], p2b[3];  // CP2 for hinges
+  double dR[9];           // dR_H = Rod(axis) (rows r_x, a, r_z), or constant R_H
+};
+
+constexpr int GJ_FLAG_STATIC_OWNER = 1;
+
+// per-joint generic data: C (5), L_a (5x12), L_b (5x12), padded to 128 doubles
+constexpr int GL_STRIDE = 128;
+enum { GL_C = 0, GL_LA = 8, GL_LB = 68 };
+
+// per-joint tree data: Sigma (5x5), rho (5), a (5), E (5x5)
+constexpr int GT_STRIDE = 64;
+enum { GT_SIG = 0, GT_RHO = 25, GT_A = 30, GT_E = 35 };
+
+// absorbed-joint entry of a tree body: joint index << 2 | side << 1 | unary
+inline int32_t abs_pack(int32_t k, int side, int unary) { return (k << 2) | (side << 1) | unary; }
+
+constexpr int TEAM = 16;              // lanes per body in the tree elimination
+constexpr int TREE_THREADS = 1024;
+constexpr int MAX_UNARY_ROWS = 6;
+
+// per-body incidence entry: joint index << 1 | side
+
+struct TreeArgs {
+  const int32_t *comp_lvl;  // per component: levels [comp_lvl[c], comp_lvl[c+1])
+  const int32_t *lvl_off;   // per level: slots [lvl_off[l], lvl_off[l+1])
+  const int32_t *tbody;     // slot -> solver body
+  const int32_t *tpk;       // slot -> parent joint << 1 | side (or -1)
+  const int32_t *tabs_off;  // slot -> absorbed entries
+  const int32_t *tabs;
+  const double *gl;
+  double *gt;
+  const double *u;
+  int64_t ns;
+  const int32_t *shp;
+  const double *hinv;
+  double *glam;             // 5 per generic joint
+  uint32_t *status;
+  int step;
+};
+}  // namespace mabd

@@ -1,0 +1,538 @@
+// Chain dual solve for ball-jointed chains (Sec. 5.2, Eq. chain-btd),
+// fused with the per-body co-rotated solve (Sec. 3.4) and the primal
+// back-projection (Eq. recover-dq-explicit).
+//
+// The dual system of a chain is block tridiagonal with 3x3 blocks.  Instead
+// of the serial block Thomas sweep the rows are cut into tiles of
+// CHAIN_TILE + 1 rows that share their first/last (interface) rows with the
+// neighbouring tiles.  One workgroup per tile
+//   A) computes the polar rotation, force and local solve of its bodies
+//      (one body per thread, coalesced SoA loads) and the rotated constant
+//      blocks R W(p, p') R^T with W = J(p) Hbar^{-1} J(p')^T;
+//   B) assembles its rows D, U, b (Eqs. chain-Schur-blocks, chain-b, with +C);
+//   C) runs block cyclic reduction on the tile interior (log2 levels, one
+//      row per thread, neighbours exchanged through LDS), which leaves the
+//      Schur complement on the two interface rows.
+// chain_global solves the block-tridiagonal system of interface rows (one
+// workgroup per chain, cyclic reduction in global memory), and chain_apply
+// repeats A-C, back-substitutes the tile, and writes lambda and the new state.
+// Recomputing A-C costs one more read of q, qdot but no HBM traffic for the
+// elimination factors.
+#include "common.hpp"
+#include "dmath.hpp"
+
+namespace mabd {
+
+
+
+DEV void sym_from_full(const double *F, double *S6) {
+  S6[0] = F[0];
+  S6[1] = 0.5 * (F[1] + F[3]);
+  S6[2] = 0.5 * (F[2] + F[6]);
+  S6[3] = F[4];
+  S6[4] = 0.5 * (F[5] + F[7]);
+  S6[5] = F[8];
+}
+
+DEV void full_from_sym(const double *S6, double *F) {
+  F[0] = S6[0]; F[1] = S6[1]; F[2] = S6[2];
+  F[3] = S6[1]; F[4] = S6[3]; F[5] = S6[4];
+  F[6] = S6[2]; F[7] = S6[4]; F[8] = S6[5];
+}
+
+// LDS layout (doubles): 24 arrays of CHAIN_THREADS entries
+enum { S_WBB = 0, S_VB = 6, S_CB = 9, S_TB = 12, S_WAB = 15, S_N = 24 };
+// reuse for cyclic reduction: PL (9) PU (9) Pb (3) ; back-substitution: x (3)
+enum { S_PL = 0, S_PU = 9, S_PB = 18, S_X = 21 };
+
+template <bool APPLY>
+__global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) {
+  __shared__ double lds[S_N * CHAIN_THREADS];
+  if (skip_step(a.status, a.step)) return;
+  const TileDesc td = a.tiles[blockIdx.x];
+  const ChainDesc cd = a.chains[td.chain];
+  const int t = threadIdx.x;
+  const int T = td.T;
+  const int r = td.r0 + t - 1;           // this thread's row (if 1 <= t <= T+1)
+  const int p = r + 1 - cd.hl;           // body between rows r and r+1
+  const bool in_tile = t <= T + 1;
+  const bool has_body = in_tile && p >= 0 && p < cd.nb;
+  const bool has_a = in_tile && r >= 0 && r < cd.K;
+  const bool has_b = in_tile && r + 1 < cd.K;
+  const int64_t gra = (int64_t)cd.row0 + r;
+  const int64_t grb = gra + 1;
+  const int64_t bg = (int64_t)cd.body0 + p;
+
+  // ---------------------------------------------------------------- phase A
+  double R[9], u[12];
+  double pa[3] = {0, 0, 0}, pb[3] = {0, 0, 0};
+  double sa = 1.0, sb = 1.0;
+  double Waa[6] = {0, 0, 0, 0, 0, 0}, Wab[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double va[3] = {0, 0, 0}, ca[3] = {0, 0, 0}, ta[3] = {0, 0, 0};
+  double Wbb[6] = {0, 0, 0, 0, 0, 0}, vb[3] = {0, 0, 0}, cb[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
+  const double *T_h = nullptr;
+  if (has_a) {
+    for (int i = 0; i < 3; ++i) pa[i] = a.pr[i * a.nrs + gra];
+    sa = (a.flag[gra] & 2) ? 1.0 : -1.0;
+  }
+  if (has_b) {
+    for (int i = 0; i < 3; ++i) pb[i] = a.pl[i * a.nrs + grb];
+    sb = (a.flag[grb] & 1) ? 1.0 : -1.0;
+  }
+  if (has_body) {
+    double q[12], qd[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      q[c] = a.q[c * a.ns + bg];
+      qd[c] = a.qd[c * a.ns + bg];
+    }
+    const int s = a.shp[bg];
+    T_h = a.hinv + (int64_t)HINV_STRIDE * s;
+    const double *sh = a.shape + (int64_t)SHAPE_STRIDE * s;
+    double A[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) A[3 * i + c] = q[3 * c + i];
+    if (!polar3(A, R)) {
+      raise_flag(a.status, FLAG_NONFINITE, a.step);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    }
+    double phi[12];
+    local_force<double>(sh, R, A, q, q, qd, a.g, a.h, phi);
+    hinv_apply(T_h, phi, u);
+    if (has_a) {
+      double W[9], RW[9];
+      wblock(T_h, pa, pa, W);
+      rot_congr(R, W, RW);
+      sym_from_full(RW, Waa);
+      double Ju[3], Ap[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) Ju[i] = pa[0] * u[i] + pa[1] * u[3 + i] + pa[2] * u[6 + i] + u[9 + i];
+      mat3_vec(R, Ju, va);
+      mat3_vec(A, pa, Ap);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        va[i] *= sa;
+        ca[i] = sa * Ap[i];
+        ta[i] = sa * q[9 + i];
+      }
+    }
+    if (has_b) {
+      double W[9], RW[9];
+      wblock(T_h, pb, pb, W);
+      rot_congr(R, W, RW);
+      sym_from_full(RW, Wbb);
+      double Ju[3], Ap[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) Ju[i] = pb[0] * u[i] + pb[1] * u[3 + i] + pb[2] * u[6 + i] + u[9 + i];
+      mat3_vec(R, Ju, vb);
+      mat3_vec(A, pb, Ap);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        vb[i] *= sb;
+        cb[i] = sb * Ap[i];
+        tb[i] = sb * q[9 + i];
+      }
+    }
+    if (has_a && has_b) {
+      double W[9];
+      wblock(T_h, pa, pb, W);
+      rot_congr(R, W, Wab);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Wab[i] *= sa * sb;
+    }
+  } else {
+    // world end: only the constant point enters C
+    if (has_a)
+      for (int i = 0; i < 3; ++i) ca[i] = sa * pa[i];
+    if (has_b)
+      for (int i = 0; i < 3; ++i) cb[i] = sb * pb[i];
+  }
+  // publish the part that belongs to row r+1 (left end of that row)
+#pragma unroll
+  for (int i = 0; i < 6; ++i) lds[(S_WBB + i) * CHAIN_THREADS + t] = Wbb[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    lds[(S_VB + i) * CHAIN_THREADS + t] = vb[i];
+    lds[(S_CB + i) * CHAIN_THREADS + t] = cb[i];
+    lds[(S_TB + i) * CHAIN_THREADS + t] = tb[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) lds[(S_WAB + i) * CHAIN_THREADS + t] = Wab[i];
+  __syncthreads();
+
+  // ---------------------------------------------------------------- phase B
+  const int li = t - 1;                  // local row index 0..T
+  const bool row_active = t >= 1 && t <= T + 1;
+  double L[9], D[6], U[9], b[3];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) { L[i] = 0.0; U[i] = Wab[i]; }
+  if (row_active) {
+    const int tp = t - 1;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) D[i] = Waa[i] + lds[(S_WBB + i) * CHAIN_THREADS + tp];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      // C = (translation difference) + (rotated anchor difference)
+      double C = (lds[(S_TB + i) * CHAIN_THREADS + tp] + ta[i]) +
+                 (lds[(S_CB + i) * CHAIN_THREADS + tp] + ca[i]);
+      b[i] = va[i] + lds[(S_VB + i) * CHAIN_THREADS + tp] + C;
+    }
+    // left coupling = (U of the previous row)^T
+    if (li >= 1) {
+#pragma unroll
+      for (int r2 = 0; r2 < 3; ++r2)
+#pragma unroll
+        for (int c2 = 0; c2 < 3; ++c2) L[3 * r2 + c2] = lds[(S_WAB + 3 * c2 + r2) * CHAIN_THREADS + tp];
+    }
+    if (li == T && r != cd.K - 1) {
+      // interface row owned by the next tile: only Schur updates are summed here
+#pragma unroll
+      for (int i = 0; i < 6; ++i) D[i] = 0.0;
+      b[0] = b[1] = b[2] = 0.0;
+    }
+    if (li == T) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) U[i] = 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) D[i] = 0.0;
+    b[0] = b[1] = b[2] = 0.0;
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- phase C
+  // block cyclic reduction of rows 1..T-1 onto the interface rows 0 and T
+  double PL[9], PU[9], Pb[3];
+  int elim_d = 0;
+  for (int d = 1; d < T; d *= 2) {
+    const bool active = row_active && (li % d == 0 || li == T);
+    const bool elim = active && li < T && (li % (2 * d) == d);
+    if (elim) {
+      double Df[9], Di[9];
+      full_from_sym(D, Df);
+      if (!spd3_inv(Df, Di)) {
+        raise_flag(a.status, FLAG_SINGULAR, a.step);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Di[i] = 0.0;
+      }
+      mat3_mul(Di, L, PL);
+      mat3_mul(Di, U, PU);
+      mat3_vec(Di, b, Pb);
+      elim_d = d;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        lds[(S_PL + i) * CHAIN_THREADS + li] = PL[i];
+        lds[(S_PU + i) * CHAIN_THREADS + li] = PU[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) lds[(S_PB + i) * CHAIN_THREADS + li] = Pb[i];
+    }
+    __syncthreads();
+    if (active && !elim) {
+      // right neighbour eliminated at this level?
+      const int e = li + d;
+      if (li != T && e < T) {
+        double Xl[9], Xu[9], xb[3], M[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          Xl[i] = lds[(S_PL + i) * CHAIN_THREADS + e];
+          Xu[i] = lds[(S_PU + i) * CHAIN_THREADS + e];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * CHAIN_THREADS + e];
+        mat3_mul(U, Xl, M);
+        double Ms[6];
+        sym_from_full(M, Ms);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) D[i] -= Ms[i];
+        double Ub[3];
+        mat3_vec(U, xb, Ub);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) b[i] -= Ub[i];
+        double Un[9];
+        mat3_mul(U, Xu, Un);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) U[i] = -Un[i];
+      }
+      // left neighbour eliminated at this level?
+      int lf = li == T ? d * ((T - 1) / d) : li - d;
+      if (li > 0 && lf > 0 && (lf % (2 * d) == d)) {
+        double Xl[9], Xu[9], xb[3], M[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          Xl[i] = lds[(S_PL + i) * CHAIN_THREADS + lf];
+          Xu[i] = lds[(S_PU + i) * CHAIN_THREADS + lf];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * CHAIN_THREADS + lf];
+        mat3_mul(L, Xu, M);
+        double Ms[6];
+        sym_from_full(M, Ms);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) D[i] -= Ms[i];
+        double Lb[3];
+        mat3_vec(L, xb, Lb);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) b[i] -= Lb[i];
+        double Ln[9];
+        mat3_mul(L, Xl, Ln);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) L[i] = -Ln[i];
+      }
+    }
+    __syncthreads();
+  }
+
+  if constexpr (!APPLY) {
+    double *rec = a.tilerec + (int64_t)TILE_REC * blockIdx.x;
+    if (row_active && li == 0) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) rec[i] = D[i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) rec[6 + i] = b[i];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) rec[18 + i] = U[i];
+    }
+    if (row_active && li == T) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) rec[9 + i] = D[i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) rec[15 + i] = b[i];
+    }
+  } else {
+    // -------------------------------------------------- back-substitution
+    if (row_active && (li == 0 || li == T)) {
+      const int64_t gi = (int64_t)cd.grow0 + td.tidx + (li == T ? 1 : 0);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) lds[(S_X + i) * CHAIN_THREADS + li] = a.xg[3 * gi + i];
+    }
+    int dmax = 0;
+    for (int d = 1; d < T; d *= 2) dmax = d;
+    __syncthreads();
+    for (int d = dmax; d >= 1; d /= 2) {
+      if (row_active && elim_d == d) {
+        const int lf = li - d;
+        const int rt = li + d < T ? li + d : T;
+        double xl[3], xr[3], x[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          xl[i] = lds[(S_X + i) * CHAIN_THREADS + lf];
+          xr[i] = lds[(S_X + i) * CHAIN_THREADS + rt];
+        }
+        double t1[3], t2[3];
+        mat3_vec(PL, xl, t1);
+        mat3_vec(PU, xr, t2);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          x[i] = Pb[i] - t1[i] - t2[i];
+          lds[(S_X + i) * CHAIN_THREADS + li] = x[i];
+        }
+      }
+      __syncthreads();
+    }
+    // multipliers of the tile's rows (interface row T is written by the next tile)
+    const bool last_tile = td.tidx == cd.ntile - 1;
+    if (row_active && (li < T || last_tile)) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) a.lam[3 * gra + i] = lds[(S_X + i) * CHAIN_THREADS + li];
+    }
+    // -------------------------------------------------- body back-projection
+    bool own = has_body && ((t >= 1 && t <= T) || (t == 0 && td.tidx == 0) ||
+                            (t == T + 1 && last_tile));
+    if (own) {
+      double g12[12];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) g12[i] = 0.0;
+      if (has_a) {  // row r is local row t-1
+        double lamv[3], w[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) lamv[i] = lds[(S_X + i) * CHAIN_THREADS + (t - 1)];
+        mat3t_vec(R, lamv, w);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          w[i] *= sa;
+          g12[i] += pa[0] * w[i];
+          g12[3 + i] += pa[1] * w[i];
+          g12[6 + i] += pa[2] * w[i];
+          g12[9 + i] += w[i];
+        }
+      }
+      if (has_b) {  // row r+1 is local row t
+        double lamv[3], w[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) lamv[i] = lds[(S_X + i) * CHAIN_THREADS + t];
+        mat3t_vec(R, lamv, w);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          w[i] *= sb;
+          g12[i] += pb[0] * w[i];
+          g12[3 + i] += pb[1] * w[i];
+          g12[6 + i] += pb[2] * w[i];
+          g12[9 + i] += w[i];
+        }
+      }
+      double hg[12];
+      hinv_apply(T_h, g12, hg);
+      const double ih = 1.0 / a.h;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double dp[3], dq[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dp[i] = u[3 * c + i] - hg[3 * c + i];
+        mat3_vec(R, dp, dq);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const int64_t o = (int64_t)(3 * c + i) * a.ns + bg;
+          a.q_out[o] = a.q[o] + dq[i];
+          a.qd_out[o] = dq[i] * ih;
+          if (!isfinite(dq[i])) raise_flag(a.status, FLAG_NONFINITE, a.step);
+        }
+      }
+    }
+  }
+}
+
+// Interface system of each chain: rows gi = 0..ntile, block tridiagonal,
+// solved by block cyclic reduction in global scratch (one workgroup per chain).
+__global__ __launch_bounds__(1024) void chain_global_kernel(const ChainDesc *chains,
+                                                           const double *tilerec, double *scr,
+                                                           double *xg, uint32_t *status, int step) {
+  if (skip_step(status, step)) return;
+  const ChainDesc cd = chains[blockIdx.x];
+  const int n = cd.ntile + 1;
+  double *S = scr + (int64_t)GROW_REC * cd.grow0;
+  const double *TR = tilerec + (int64_t)TILE_REC * cd.tile0;
+  // record: L 0..8, D 9..17, U 18..26, b 27..29, PL 30..38, PU 39..47, Pb 48..50
+  enum { GL = 0, GD = 9, GU = 18, GB = 27, GPL = 30, GPU = 39, GPB = 48 };
+  for (int gi = threadIdx.x; gi < n; gi += blockDim.x) {
+    double *row = S + (int64_t)GROW_REC * gi;
+    double Ds[6] = {0, 0, 0, 0, 0, 0}, bb[3] = {0, 0, 0};
+    if (gi < cd.ntile) {
+      for (int i = 0; i < 6; ++i) Ds[i] += TR[TILE_REC * gi + i];
+      for (int i = 0; i < 3; ++i) bb[i] += TR[TILE_REC * gi + 6 + i];
+    }
+    if (gi > 0) {
+      for (int i = 0; i < 6; ++i) Ds[i] += TR[TILE_REC * (gi - 1) + 9 + i];
+      for (int i = 0; i < 3; ++i) bb[i] += TR[TILE_REC * (gi - 1) + 15 + i];
+    }
+    double Df[9];
+    full_from_sym(Ds, Df);
+    for (int i = 0; i < 9; ++i) row[GD + i] = Df[i];
+    for (int i = 0; i < 3; ++i) row[GB + i] = bb[i];
+    for (int i = 0; i < 9; ++i) {
+      row[GU + i] = gi < cd.ntile ? TR[TILE_REC * gi + 18 + i] : 0.0;
+      int r2 = i / 3, c2 = i % 3;
+      row[GL + i] = gi > 0 ? TR[TILE_REC * (gi - 1) + 18 + 3 * c2 + r2] : 0.0;
+    }
+  }
+  __syncthreads();
+  int dlast = 0;
+  for (int d = 1; d < n; d *= 2) {
+    dlast = d;
+    for (int e = d + threadIdx.x * 2 * d; e < n; e += blockDim.x * 2 * d) {
+      double *row = S + (int64_t)GROW_REC * e;
+      double Di[9], Dm[9];
+      for (int i = 0; i < 9; ++i) Dm[i] = row[GD + i];
+      if (!spd3_inv(Dm, Di)) {
+        raise_flag(status, FLAG_SINGULAR, step);
+        for (int i = 0; i < 9; ++i) Di[i] = 0.0;
+      }
+      double X[9], Y[9], z[3], Lm[9], Um[9], bv[3];
+      for (int i = 0; i < 9; ++i) { Lm[i] = row[GL + i]; Um[i] = row[GU + i]; }
+      for (int i = 0; i < 3; ++i) bv[i] = row[GB + i];
+      mat3_mul(Di, Lm, X);
+      mat3_mul(Di, Um, Y);
+      mat3_vec(Di, bv, z);
+      for (int i = 0; i < 9; ++i) { row[GPL + i] = X[i]; row[GPU + i] = Y[i]; }
+      for (int i = 0; i < 3; ++i) row[GPB + i] = z[i];
+    }
+    __syncthreads();
+    for (int s = threadIdx.x * 2 * d; s < n; s += blockDim.x * 2 * d) {
+      double *row = S + (int64_t)GROW_REC * s;
+      double Dm[9], Lm[9], Um[9], bv[3];
+      for (int i = 0; i < 9; ++i) { Dm[i] = row[GD + i]; Lm[i] = row[GL + i]; Um[i] = row[GU + i]; }
+      for (int i = 0; i < 3; ++i) bv[i] = row[GB + i];
+      if (s + d < n) {
+        const double *er = S + (int64_t)GROW_REC * (s + d);
+        double M[9], Xu[9], Xl[9], xb[3], v[3];
+        for (int i = 0; i < 9; ++i) { Xl[i] = er[GPL + i]; Xu[i] = er[GPU + i]; }
+        for (int i = 0; i < 3; ++i) xb[i] = er[GPB + i];
+        mat3_mul(Um, Xl, M);
+        for (int i = 0; i < 9; ++i) Dm[i] -= M[i];
+        mat3_vec(Um, xb, v);
+        for (int i = 0; i < 3; ++i) bv[i] -= v[i];
+        mat3_mul(Um, Xu, M);
+        for (int i = 0; i < 9; ++i) Um[i] = -M[i];
+      } else {
+        for (int i = 0; i < 9; ++i) Um[i] = 0.0;
+      }
+      if (s - d >= 0) {
+        const double *er = S + (int64_t)GROW_REC * (s - d);
+        double M[9], Xu[9], Xl[9], xb[3], v[3];
+        for (int i = 0; i < 9; ++i) { Xl[i] = er[GPL + i]; Xu[i] = er[GPU + i]; }
+        for (int i = 0; i < 3; ++i) xb[i] = er[GPB + i];
+        mat3_mul(Lm, Xu, M);
+        for (int i = 0; i < 9; ++i) Dm[i] -= M[i];
+        mat3_vec(Lm, xb, v);
+        for (int i = 0; i < 3; ++i) bv[i] -= v[i];
+        mat3_mul(Lm, Xl, M);
+        for (int i = 0; i < 9; ++i) Lm[i] = -M[i];
+      }
+      // symmetrise the pivot block
+      double a01 = 0.5 * (Dm[1] + Dm[3]), a02 = 0.5 * (Dm[2] + Dm[6]), a12 = 0.5 * (Dm[5] + Dm[7]);
+      Dm[1] = Dm[3] = a01; Dm[2] = Dm[6] = a02; Dm[5] = Dm[7] = a12;
+      for (int i = 0; i < 9; ++i) { row[GD + i] = Dm[i]; row[GL + i] = Lm[i]; row[GU + i] = Um[i]; }
+      for (int i = 0; i < 3; ++i) row[GB + i] = bv[i];
+    }
+    __syncthreads();
+  }
+  double *X = xg + 3 * (int64_t)cd.grow0;
+  if (threadIdx.x == 0) {
+    double Dm[9], Di[9], bv[3], x[3];
+    for (int i = 0; i < 9; ++i) Dm[i] = S[GD + i];
+    for (int i = 0; i < 3; ++i) bv[i] = S[GB + i];
+    if (!spd3_inv(Dm, Di)) {
+      raise_flag(status, FLAG_SINGULAR, step);
+      for (int i = 0; i < 9; ++i) Di[i] = 0.0;
+    }
+    mat3_vec(Di, bv, x);
+    for (int i = 0; i < 3; ++i) X[i] = x[i];
+  }
+  __syncthreads();
+  for (int d = dlast; d >= 1; d /= 2) {
+    for (int e = d + threadIdx.x * 2 * d; e < n; e += blockDim.x * 2 * d) {
+      const double *row = S + (int64_t)GROW_REC * e;
+      double xl[3], xr[3] = {0, 0, 0}, x[3];
+      for (int i = 0; i < 3; ++i) xl[i] = X[3 * (e - d) + i];
+      if (e + d < n)
+        for (int i = 0; i < 3; ++i) xr[i] = X[3 * (e + d) + i];
+      for (int i = 0; i < 3; ++i) {
+        x[i] = row[GPB + i];
+        for (int j = 0; j < 3; ++j) x[i] -= row[GPL + 3 * i + j] * xl[j] + row[GPU + 3 * i + j] * xr[j];
+      }
+      for (int i = 0; i < 3; ++i) X[3 * e + i] = x[i];
+    }
+    __syncthreads();
+  }
+}
+
+void launch_chain_reduce(const ChainArgs &a, int ntiles, hipStream_t s) {
+  if (ntiles > 0)
+    hipLaunchKernelGGL(chain_tile_kernel<false>, dim3(ntiles), dim3(CHAIN_THREADS), 0, s, a);
+}
+void launch_chain_apply(const ChainArgs &a, int ntiles, hipStream_t s) {
+  if (ntiles > 0)
+    hipLaunchKernelGGL(chain_tile_kernel<true>, dim3(ntiles), dim3(CHAIN_THREADS), 0, s, a);
+}
+void launch_chain_global(const ChainDesc *chains, int nchains, const double *tilerec, double *scr,
+                         double *xg, uint32_t *status, int step, hipStream_t s) {
+  if (nchains > 0)
+    hipLaunchKernelGGL(chain_global_kernel, dim3(nchains), dim3(1024), 0, s, chains, tilerec, scr,
+                       xg, status, step);
+}
+
+}  // namespace mabd

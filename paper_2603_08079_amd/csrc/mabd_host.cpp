@@ -1,0 +1,969 @@
+// Host runtime of libmabd: validation, topology classification, solve
+// schedules, device buffers and the per-step launch sequence behind the C ABI
+// declared in include/mabd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mabd.h"
+#include "common.hpp"
+#include "generic.hpp"
+
+namespace mabd {
+
+void launch_chain_reduce(const ChainArgs &a, int ntiles, hipStream_t s);
+void launch_chain_apply(const ChainArgs &a, int ntiles, hipStream_t s);
+void launch_chain_global(const ChainDesc *chains, int nchains, const double *tilerec, double *scr,
+                         double *xg, uint32_t *status, int step, hipStream_t s);
+void launch_prefactor(const double *shape, int nshape, double h, double *hinv, hipStream_t s);
+void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
+                  const int32_t *shp, const double *hinv, const double *shape, const double *g,
+                  double h, double *Rg, double *ug, uint32_t *status, int step, hipStream_t s);
+void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
+                   double *gl, hipStream_t s);
+void launch_tree(const TreeArgs &a, const GJoint *J, int ncomp, hipStream_t s);
+void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,
+                   const double *glam, const double *Rg, const double *ug, int64_t ns,
+                   const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
+                   double *qd_out, double h, int acc, uint32_t *status, const GJoint *J,
+                   int step, hipStream_t s);
+void launch_gather_state(int nd, const int32_t *sol2in, const double *q, const double *qd, int64_t ns,
+                         double *qo, double *qdo, hipStream_t s);
+void launch_scatter_state(int nd, const int32_t *sol2in, const double *qi, const double *qdi,
+                          double *q, double *qd, int64_t ns, hipStream_t s);
+void launch_write_pinned(int np, const int32_t *idx, const double *q0, double *qo, double *qdo,
+                         hipStream_t s);
+void launch_reset_status(uint32_t *status, hipStream_t s);
+}  // namespace mabd
+
+using namespace mabd;
+
+namespace {
+
+std::string g_create_error;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+enum Cls { CLS_CHAIN = 1, CLS_TREE = 2, CLS_GRAPH = 3 };
+
+// ------------------------------------------------------------ host 3x3 help
+void polar_host(const double *A, double *R) {
+  double X[9];
+  std::memcpy(X, A, sizeof X);
+  for (int it = 0; it < 60; ++it) {
+    double C[9] = {X[4] * X[8] - X[5] * X[7], X[5] * X[6] - X[3] * X[8], X[3] * X[7] - X[4] * X[6],
+                   X[2] * X[7] - X[1] * X[8], X[0] * X[8] - X[2] * X[6], X[1] * X[6] - X[0] * X[7],
+                   X[1] * X[5] - X[2] * X[4], X[2] * X[3] - X[0] * X[5], X[0] * X[4] - X[1] * X[3]};
+    double det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+    double z = std::cbrt(1.0 / det), diff = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      double xn = 0.5 * (z * X[i] + C[i] / (det * z));
+      diff += (xn - X[i]) * (xn - X[i]);
+      X[i] = xn;
+    }
+    if (diff < 1e-30) break;
+  }
+  std::memcpy(R, X, sizeof X);
+}
+
+void hinge_rod(const double *a, double *Rh) {
+  // rows (r_x, a, r_z): the rotation taking the unit axis a to e_y (Sec. 4.3)
+  if (1.0 + a[1] < 1e-12) {
+    const double D[9] = {1, 0, 0, 0, -1, 0, 0, 0, -1};
+    std::memcpy(Rh, D, sizeof D);
+    return;
+  }
+  const double v[3] = {-a[2], 0.0, a[0]};  // a x e_y
+  const double K[9] = {0, -v[2], v[1], v[2], 0, -v[0], -v[1], v[0], 0};
+  double K2[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      K2[3 * r + c] = K[3 * r] * K[c] + K[3 * r + 1] * K[3 + c] + K[3 * r + 2] * K[6 + c];
+  for (int i = 0; i < 9; ++i) Rh[i] = (i % 4 == 0 ? 1.0 : 0.0) + K[i] + K2[i] / (1.0 + a[1]);
+}
+
+void mat3_vec_h(const double *A, const double *x, double *y) {
+  for (int r = 0; r < 3; ++r) y[r] = A[3 * r] * x[0] + A[3 * r + 1] * x[1] + A[3 * r + 2] * x[2];
+}
+void mat3t_vec_h(const double *A, const double *x, double *y) {
+  for (int r = 0; r < 3; ++r) y[r] = A[r] * x[0] + A[3 + r] * x[1] + A[6 + r] * x[2];
+}
+
+int find(std::vector<int> &p, int x) {
+  while (p[x] != x) x = p[x] = p[p[x]];
+  return x;
+}
+
+}  // namespace
+
+struct mabd_ctx {
+  std::string err;
+  mabd_options opt;
+  int n = 0, m = 0;
+  // host copies
+  std::vector<double> q0_in, qd0_in;
+  std::vector<uint8_t> pinned;
+  std::vector<uint8_t> jtype;
+  std::vector<int32_t> jrow_off;  // input joint -> row offset in the input-order lambda
+  int64_t nrows_total = 0;
+  // solver order
+  int nd = 0;
+  int64_t ns = 0;
+  std::vector<int32_t> sol2in, in2sol;
+  std::vector<int32_t> pin_idx;
+  // shapes
+  int nshape = 0;
+  // chains
+  std::vector<ChainDesc> chains;
+  std::vector<TileDesc> tiles;
+  int nchain_rows = 0, nchain_bodies = 0, ngrows = 0;
+  std::vector<int32_t> crow_joint;  // chain row -> input joint
+  // generic
+  std::vector<GJoint> gj;
+  std::vector<int32_t> gj_in;
+  int gb0 = 0, gb1 = 0;
+  int ntree = 0, ngraph = 0;
+  std::vector<int32_t> comp_lvl, lvl_off, tbody, tpk, tabs_off, tabs, inc_off, inc;
+  // device
+  std::vector<void *> allocs;
+  double *d_q[2] = {nullptr, nullptr}, *d_qd[2] = {nullptr, nullptr};
+  int cur = 0;
+  int32_t *d_shp = nullptr;
+  double *d_shape = nullptr, *d_hinv = nullptr;
+  ChainDesc *d_chains = nullptr;
+  TileDesc *d_tiles = nullptr;
+  double *d_pl = nullptr, *d_pr = nullptr;
+  uint8_t *d_flag = nullptr;
+  double *d_tilerec = nullptr, *d_grow = nullptr, *d_xg = nullptr, *d_clam = nullptr;
+  GJoint *d_gj = nullptr;
+  double *d_gl = nullptr, *d_gt = nullptr, *d_glam = nullptr, *d_Rg = nullptr, *d_ug = nullptr;
+  int32_t *d_comp_lvl = nullptr, *d_lvl_off = nullptr, *d_tbody = nullptr, *d_tpk = nullptr,
+          *d_tabs_off = nullptr, *d_tabs = nullptr, *d_inc_off = nullptr, *d_inc = nullptr;
+  int32_t *d_sol2in = nullptr, *d_pin_idx = nullptr;
+  double *d_pin_q0 = nullptr, *d_tmp = nullptr;
+  uint32_t *d_status = nullptr;
+  uint32_t *h_status = nullptr;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  double h_last = -1.0;
+  mabd_step_stats stats{};
+  // kernel-group timing (diagnostics bit 1)
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_marks;  // (phase, index of the start event)
+};
+
+namespace {
+
+mabd_status fail(mabd_ctx *c, mabd_status st, const std::string &msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return st;
+}
+
+template <typename T>
+hipError_t dalloc(mabd_ctx *c, T **p, size_t count) {
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e == hipSuccess) {
+    c->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+  }
+  return e;
+}
+
+template <typename T>
+hipError_t upload(mabd_ctx *c, T **p, const std::vector<T> &v) {
+  hipError_t e = dalloc(c, p, v.size());
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+bool finite_all(const double *p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+namespace {
+// time a group of launches with a pair of events when diagnostics bit 1 is set
+struct PhaseTimer {
+  mabd_ctx *c;
+  bool on;
+  size_t used = 0;
+  PhaseTimer(mabd_ctx *cc) : c(cc), on((cc->opt.diagnostics & 2) != 0) { c->ev_marks.clear(); }
+  hipEvent_t next() {
+    if (used == c->ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { on = false; return nullptr; }
+      c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[used++];
+  }
+  template <typename F>
+  void run(int phase, F &&f) {
+    if (!on) { f(); return; }
+    hipEvent_t a = next(), b = next();
+    if (!on) { f(); return; }
+    (void)hipEventRecord(a, c->stream);
+    f();
+    (void)hipEventRecord(b, c->stream);
+    c->ev_marks.emplace_back(phase, (int)used - 2);
+  }
+  void collect() {
+    for (int i = 0; i < 8; ++i) { c->stats.phase_ms[i] = 0.0; c->stats.phase_calls[i] = 0; }
+    if (!on) return;
+    for (auto &pm : c->ev_marks) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev_pool[pm.second], c->ev_pool[pm.second + 1]) == hipSuccess) {
+        c->stats.phase_ms[pm.first] += ms;
+        c->stats.phase_calls[pm.first] += 1;
+      }
+    }
+  }
+};
+}  // namespace
+
+extern "C" {
+
+void mabd_options_default(mabd_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->gravity[2] = -9.8;
+  o->precision = 0;
+  o->kkt_tol = 1e-10;
+  o->max_iters = 200000;
+  o->warm_start = 0;
+  o->newton_iters = 1;
+  o->hinge_grad = 0;
+  o->material = 0;
+  o->diagnostics = 0;
+  o->stream = nullptr;
+}
+
+const char *mabd_last_error(const mabd_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+void mabd_destroy(mabd_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
+  for (void *p : c->allocs) (void)hipFree(p);
+  if (c->h_status) (void)hipHostFree(c->h_status);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+int64_t mabd_rows(const mabd_ctx *c) { return c ? c->nrows_total : 0; }
+
+mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_options *o,
+                        mabd_ctx **out) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, MABD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!B || B->n < 0) return fail(nullptr, MABD_ERR_INVALID_ARG, "bodies missing or n < 0");
+  const int n = B->n;
+  const int m = Jn ? Jn->m : 0;
+  if (m < 0) return fail(nullptr, MABD_ERR_INVALID_ARG, "m < 0");
+  if (n > 0 && (!B->dims || !B->density || !B->k_orth || !B->q0))
+    return fail(nullptr, MABD_ERR_INVALID_ARG, "dims, density, k_orth and q0 are required");
+  if (m > 0 && (!Jn->type || !Jn->a || !Jn->b || !Jn->pa || !Jn->pb))
+    return fail(nullptr, MABD_ERR_INVALID_ARG, "joint type, a, b, pa, pb are required");
+  mabd_options opt;
+  if (o) opt = *o;
+  else mabd_options_default(&opt);
+  if (opt.newton_iters < 1) return fail(nullptr, MABD_ERR_INVALID_ARG, "newton_iters < 1");
+  if (opt.material != 0 && opt.material != 1) return fail(nullptr, MABD_ERR_INVALID_ARG, "material");
+  if (opt.material == 1 && n > 0 && !B->poisson)
+    return fail(nullptr, MABD_ERR_INVALID_ARG, "material 1 needs poisson");
+  if (opt.hinge_grad != 0 && opt.hinge_grad != 2)
+    return fail(nullptr, MABD_ERR_INVALID_ARG, "hinge_grad must be 0 or 2");
+  if (opt.precision != 0) return fail(nullptr, MABD_ERR_INVALID_ARG, "precision 1 is not available");
+  if (!finite_all(opt.gravity, 3)) return fail(nullptr, MABD_ERR_INVALID_ARG, "gravity not finite");
+  // ------------------------------------------------------------ validate
+  for (int i = 0; i < n; ++i) {
+    const double *d = B->dims + 3 * i;
+    if (!(d[0] > 0 && d[1] > 0 && d[2] > 0) || !std::isfinite(d[0] * d[1] * d[2]))
+      return fail(nullptr, MABD_ERR_INVALID_ARG, "body " + std::to_string(i) + ": dims must be > 0");
+    if (!(B->density[i] > 0) || !std::isfinite(B->density[i]))
+      return fail(nullptr, MABD_ERR_INVALID_ARG, "body " + std::to_string(i) + ": density");
+    if (!(B->k_orth[i] > 0) || !std::isfinite(B->k_orth[i]))
+      return fail(nullptr, MABD_ERR_INVALID_ARG, "body " + std::to_string(i) + ": stiffness");
+    if (opt.material == 1 && !(B->poisson[i] > -1.0 && B->poisson[i] < 0.5))
+      return fail(nullptr, MABD_ERR_INVALID_ARG, "body " + std::to_string(i) + ": poisson");
+  }
+  if (!finite_all(B->q0, (size_t)12 * n) || (B->qd0 && !finite_all(B->qd0, (size_t)12 * n)))
+    return fail(nullptr, MABD_ERR_INVALID_ARG, "initial state not finite");
+  std::vector<uint8_t> pinned(n, 0);
+  if (B->pinned)
+    for (int i = 0; i < n; ++i) pinned[i] = B->pinned[i] ? 1 : 0;
+  auto dyn = [&](int b) { return b >= 0 && !pinned[b]; };
+  for (int i = 0; i < n; ++i) {
+    const double *q = B->q0 + 12 * i;
+    double A[9] = {q[0], q[3], q[6], q[1], q[4], q[7], q[2], q[5], q[8]};
+    double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                 A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(det > 0)) return fail(nullptr, MABD_ERR_INVALID_ARG, "body " + std::to_string(i) + ": det A <= 0");
+  }
+  for (int k = 0; k < m; ++k) {
+    const int a = Jn->a[k], b = Jn->b[k];
+    const std::string jk = "joint " + std::to_string(k) + ": ";
+    if (Jn->type[k] > 1) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "type must be 0 or 1");
+    if (a < -1 || a >= n || b < -1 || b >= n) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "body index");
+    if (a == b) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "a == b");
+    if (!dyn(a) && !dyn(b)) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "no dynamic side");
+    if (!finite_all(Jn->pa + 3 * k, 3) || !finite_all(Jn->pb + 3 * k, 3))
+      return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "anchor not finite");
+    if (Jn->type[k] == 1) {
+      if (!Jn->axis || !Jn->cp_len) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "hinge needs axis, cp_len");
+      const double *ax = Jn->axis + 3 * k;
+      double nrm = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+      if (!(nrm > 1e-12) || !std::isfinite(nrm)) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "zero hinge axis");
+      if (!(Jn->cp_len[k] > 0) || !std::isfinite(Jn->cp_len[k]))
+        return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "cp_len must be > 0");
+    }
+  }
+
+  mabd_ctx *c = new mabd_ctx();
+  c->opt = opt;
+  c->n = n;
+  c->m = m;
+  c->pinned = pinned;
+  c->q0_in.assign(B->q0, B->q0 + (size_t)12 * n);
+  c->qd0_in.assign((size_t)12 * n, 0.0);
+  if (B->qd0) c->qd0_in.assign(B->qd0, B->qd0 + (size_t)12 * n);
+  c->jtype.assign(Jn ? Jn->type : nullptr, Jn ? Jn->type + m : nullptr);
+  c->jrow_off.resize(m + 1, 0);
+  for (int k = 0; k < m; ++k) c->jrow_off[k + 1] = c->jrow_off[k] + (c->jtype[k] ? 5 : 3);
+  c->nrows_total = c->jrow_off[m];
+
+  // ------------------------------------------------------------ components
+  std::vector<int> par(n);
+  std::iota(par.begin(), par.end(), 0);
+  for (int k = 0; k < m; ++k) {
+    const int a = Jn->a[k], b = Jn->b[k];
+    if (dyn(a) && dyn(b)) {
+      int x = find(par, a), y = find(par, b);
+      if (x != y) par[x] = y;
+    }
+  }
+  std::map<int, int> comp_id;
+  std::vector<int> body_comp(n, -1);
+  for (int i = 0; i < n; ++i)
+    if (dyn(i)) {
+      int r = find(par, i);
+      auto it = comp_id.find(r);
+      if (it == comp_id.end()) it = comp_id.emplace(r, (int)comp_id.size()).first;
+      body_comp[i] = it->second;
+    }
+  const int ncomp = (int)comp_id.size();
+  std::vector<std::vector<int>> cbodies(ncomp), cjoints(ncomp);
+  for (int i = 0; i < n; ++i)
+    if (body_comp[i] >= 0) cbodies[body_comp[i]].push_back(i);
+  std::vector<std::vector<int>> binc(n);  // incident joints per dynamic body
+  for (int k = 0; k < m; ++k) {
+    const int a = Jn->a[k], b = Jn->b[k];
+    int ci = dyn(a) ? body_comp[a] : body_comp[b];
+    cjoints[ci].push_back(k);
+    if (dyn(a)) binc[a].push_back(k);
+    if (dyn(b)) binc[b].push_back(k);
+  }
+  std::vector<int> cls(ncomp);
+  for (int ci = 0; ci < ncomp; ++ci) {
+    long edges = 0;
+    int maxdeg = 0;
+    bool all_ball = true;
+    for (int k : cjoints[ci]) {
+      edges += (dyn(Jn->a[k]) ? 1 : 0) + (dyn(Jn->b[k]) ? 1 : 0);
+      if (Jn->type[k] != 0) all_ball = false;
+    }
+    for (int b : cbodies[ci]) maxdeg = std::max<int>(maxdeg, (int)binc[b].size());
+    const long nodes = (long)cbodies[ci].size() + (long)cjoints[ci].size();
+    const bool acyclic = edges == nodes - 1;
+    if (!acyclic) cls[ci] = CLS_GRAPH;
+    else if (all_ball && maxdeg <= 2 && cjoints[ci].size() >= 2 && opt.newton_iters == 1)
+      cls[ci] = CLS_CHAIN;
+    else cls[ci] = CLS_TREE;
+  }
+  for (int ci = 0; ci < ncomp; ++ci)
+    if (cls[ci] == CLS_GRAPH) {
+      delete c;
+      return fail(nullptr, MABD_ERR_TOPOLOGY, "closed loops need the PCG solver, which this build lacks");
+    }
+
+  // ------------------------------------------------------------ solver order
+  c->in2sol.assign(n, -1);
+  auto add_body = [&](int i) {
+    c->in2sol[i] = (int)c->sol2in.size();
+    c->sol2in.push_back(i);
+  };
+  // chains
+  std::vector<double> pl, pr;
+  std::vector<uint8_t> cflag;
+  auto world_point = [&](int b, const double *p, double *w) {
+    if (b < 0) { std::memcpy(w, p, 3 * sizeof(double)); return; }
+    const double *q = B->q0 + 12 * b;
+    for (int r = 0; r < 3; ++r) w[r] = q[r] * p[0] + q[3 + r] * p[1] + q[6 + r] * p[2] + q[9 + r];
+  };
+  for (int ci = 0; ci < ncomp; ++ci) {
+    if (cls[ci] != CLS_CHAIN) continue;
+    const auto &js = cjoints[ci];
+    // dual degree of a joint: other joints at its dynamic bodies
+    auto ddeg = [&](int k) {
+      int d = 0;
+      for (int b : {Jn->a[k], Jn->b[k]})
+        if (dyn(b)) d += (int)binc[b].size() - 1;
+      return d;
+    };
+    int start = js[0];
+    for (int k : js)
+      if (ddeg(k) <= 1) { start = k; break; }
+    std::vector<int> rows;
+    std::vector<int> shared;  // body between rows r and r+1
+    int prev_body = -1, cur = start;
+    std::vector<char> used(0);
+    rows.push_back(cur);
+    for (;;) {
+      int nxt = -1, via = -1;
+      for (int b : {Jn->a[cur], Jn->b[cur]}) {
+        if (!dyn(b) || b == prev_body) continue;
+        for (int k2 : binc[b])
+          if (k2 != cur) { nxt = k2; via = b; }
+      }
+      if (nxt < 0) break;
+      shared.push_back(via);
+      rows.push_back(nxt);
+      prev_body = via;
+      cur = nxt;
+    }
+    const int K = (int)rows.size();
+    // end bodies
+    auto other_dyn = [&](int k, int not_b) {
+      for (int b : {Jn->a[k], Jn->b[k]})
+        if (dyn(b) && b != not_b) return b;
+      return -1;
+    };
+    const int left_end = other_dyn(rows[0], K > 1 ? shared[0] : -1);
+    const int right_end = other_dyn(rows[K - 1], K > 1 ? shared[K - 2] : left_end);
+    ChainDesc cd{};
+    cd.hl = left_end < 0 ? 1 : 0;
+    cd.hr = right_end < 0 ? 1 : 0;
+    cd.K = K;
+    cd.nb = K - 1 + (1 - cd.hl) + (1 - cd.hr);
+    cd.body0 = (int)c->sol2in.size();
+    cd.row0 = c->nchain_rows;
+    if (cd.nb != (int)cbodies[ci].size()) {
+      delete c;
+      return fail(nullptr, MABD_ERR_TOPOLOGY, "internal: chain walk mismatch");
+    }
+    if (!cd.hl) add_body(left_end);
+    for (int b : shared) add_body(b);
+    if (!cd.hr) add_body(right_end);
+    // row data
+    for (int r = 0; r < K; ++r) {
+      const int k = rows[r];
+      const int lb = r == 0 ? left_end : shared[r - 1];
+      const int rb = r == K - 1 ? right_end : shared[r];
+      const int a = Jn->a[k], b = Jn->b[k];
+      // which side of the joint is the left / right end
+      bool left_is_a = lb >= 0 ? (a == lb) : !dyn(a);
+      bool right_is_a = rb >= 0 ? (a == rb) : !dyn(a);
+      if (lb < 0 && rb < 0) left_is_a = !dyn(a);
+      double wl[3], wr[3];
+      const double *pa = Jn->pa + 3 * k, *pb = Jn->pb + 3 * k;
+      if (lb >= 0) std::memcpy(wl, left_is_a ? pa : pb, sizeof wl);
+      else world_point(left_is_a ? a : b, left_is_a ? pa : pb, wl);
+      if (rb >= 0) std::memcpy(wr, right_is_a ? pa : pb, sizeof wr);
+      else world_point(right_is_a ? a : b, right_is_a ? pa : pb, wr);
+      for (int i = 0; i < 3; ++i) { pl.push_back(wl[i]); pr.push_back(wr[i]); }
+      cflag.push_back((left_is_a ? 1 : 0) | (right_is_a ? 2 : 0));
+      c->crow_joint.push_back(k);
+    }
+    cd.ntile = (K - 1 + CHAIN_TILE - 1) / CHAIN_TILE;
+    cd.tile0 = (int)c->tiles.size();
+    cd.grow0 = c->ngrows;
+    for (int t = 0; t < cd.ntile; ++t) {
+      TileDesc td{};
+      td.chain = (int)c->chains.size();
+      td.r0 = t * CHAIN_TILE;
+      td.T = std::min(CHAIN_TILE, K - 1 - td.r0);
+      td.tidx = t;
+      c->tiles.push_back(td);
+    }
+    c->ngrows += cd.ntile + 1;
+    c->nchain_rows += K;
+    c->chains.push_back(cd);
+  }
+  c->nchain_bodies = (int)c->sol2in.size();
+  // generic (tree) components
+  c->gb0 = c->nchain_bodies;
+  std::vector<int> gidx(m, -1);  // input joint -> generic joint
+  for (int ci = 0; ci < ncomp; ++ci) {
+    if (cls[ci] != CLS_TREE) continue;
+    for (int k : cjoints[ci]) {
+      gidx[k] = (int)c->gj_in.size();
+      c->gj_in.push_back(k);
+    }
+  }
+  // tree schedules: root, BFS, heights, level order
+  c->comp_lvl.push_back(0);
+  c->lvl_off.push_back(0);
+  for (int ci = 0; ci < ncomp; ++ci) {
+    if (cls[ci] != CLS_TREE) continue;
+    const auto &bs = cbodies[ci];
+    int root = bs[0];
+    for (int b : bs) {
+      bool has_unary = false;
+      for (int k : binc[b])
+        if (!dyn(Jn->a[k]) || !dyn(Jn->b[k])) has_unary = true;
+      if (has_unary) { root = b; break; }
+    }
+    std::map<int, int> parent_joint;  // body -> joint to its parent
+    std::vector<int> order{root};
+    std::map<int, int> seen{{root, 1}};
+    for (size_t h = 0; h < order.size(); ++h) {
+      int b = order[h];
+      for (int k : binc[b]) {
+        int o = Jn->a[k] == b ? Jn->b[k] : Jn->a[k];
+        if (!dyn(o) || seen.count(o)) continue;
+        seen[o] = 1;
+        parent_joint[o] = k;
+        order.push_back(o);
+      }
+    }
+    std::map<int, int> height;
+    for (auto it = order.rbegin(); it != order.rend(); ++it) {
+      int b = *it;
+      int hgt = 0;
+      for (int k : binc[b]) {
+        int o = Jn->a[k] == b ? Jn->b[k] : Jn->a[k];
+        if (dyn(o) && parent_joint.count(o) && parent_joint[o] == k) hgt = std::max(hgt, height[o] + 1);
+      }
+      height[b] = hgt;
+    }
+    int maxh = 0;
+    for (int b : order) maxh = std::max(maxh, height[b]);
+    std::vector<std::vector<int>> lv(maxh + 1);
+    for (int b : order) lv[height[b]].push_back(b);
+    for (auto &L : lv) {
+      for (int b : L) {
+        add_body(b);
+        c->tbody.push_back(c->in2sol[b]);
+        int pk = -1;
+        if (parent_joint.count(b)) {
+          int k = parent_joint[b];
+          pk = (gidx[k] << 1) | (Jn->a[k] == b ? 0 : 1);
+        }
+        c->tpk.push_back(pk);
+        c->tabs_off.push_back((int)c->tabs.size());
+        int unary_rows = 0;
+        for (int k : binc[b]) {
+          if (parent_joint.count(b) && parent_joint[b] == k) continue;
+          const int side = Jn->a[k] == b ? 0 : 1;
+          const bool unary = !dyn(Jn->a[k]) || !dyn(Jn->b[k]);
+          if (unary) unary_rows += Jn->type[k] ? 5 : 3;
+          c->tabs.push_back(abs_pack(gidx[k], side, unary ? 1 : 0));
+        }
+        if (unary_rows > MAX_UNARY_ROWS) {
+          delete c;
+          return fail(nullptr, MABD_ERR_TOPOLOGY, "a tree body has more than 6 one-sided joint rows");
+        }
+      }
+      c->lvl_off.push_back((int)c->tbody.size());
+    }
+    c->comp_lvl.push_back((int)c->lvl_off.size() - 1);
+    c->ntree++;
+  }
+  c->tabs_off.push_back((int)c->tabs.size());
+  c->gb1 = (int)c->sol2in.size();
+  c->nd = (int)c->sol2in.size();
+  for (int i = 0; i < n; ++i)
+    if (pinned[i]) c->pin_idx.push_back(i);
+  c->ns = std::max<int64_t>(((int64_t)c->nd + 63) / 64 * 64, 64);
+  // generic joints
+  for (int gk = 0; gk < (int)c->gj_in.size(); ++gk) {
+    const int k = c->gj_in[gk];
+    GJoint g{};
+    g.type = Jn->type[k];
+    const int a = Jn->a[k], b = Jn->b[k];
+    g.sa = dyn(a) ? c->in2sol[a] : -1;
+    g.sb = dyn(b) ? c->in2sol[b] : -1;
+    const double *pa = Jn->pa + 3 * k, *pb = Jn->pb + 3 * k;
+    if (g.sa >= 0) std::memcpy(g.p1a, pa, sizeof g.p1a);
+    else world_point(a, pa, g.p1a);
+    if (g.sb >= 0) std::memcpy(g.p1b, pb, sizeof g.p1b);
+    else world_point(b, pb, g.p1b);
+    if (g.type == 1) {
+      double ax[3];
+      std::memcpy(ax, Jn->axis + 3 * k, sizeof ax);
+      const double nrm = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+      for (double &v : ax) v /= nrm;
+      double Ra0[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, Rb0[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+      auto rot0 = [&](int body, double *R) {
+        if (body < 0) return;
+        const double *q = B->q0 + 12 * body;
+        double A[9] = {q[0], q[3], q[6], q[1], q[4], q[7], q[2], q[5], q[8]};
+        polar_host(A, R);
+      };
+      rot0(a, Ra0);
+      rot0(b, Rb0);
+      double wax[3], axb[3];
+      mat3_vec_h(Ra0, ax, wax);
+      if (b >= 0) mat3t_vec_h(Rb0, wax, axb);
+      else std::memcpy(axb, wax, sizeof axb);
+      const double ell = Jn->cp_len[k];
+      double p2a[3], p2b[3];
+      for (int i = 0; i < 3; ++i) {
+        p2a[i] = pa[i] + ell * ax[i];
+        p2b[i] = pb[i] + ell * axb[i];
+      }
+      if (g.sa >= 0) std::memcpy(g.p2a, p2a, sizeof p2a);
+      else world_point(a, p2a, g.p2a);
+      if (g.sb >= 0) std::memcpy(g.p2b, p2b, sizeof p2b);
+      else world_point(b, p2b, g.p2b);
+      double dR[9];
+      hinge_rod(ax, dR);
+      if (g.sa >= 0) {
+        std::memcpy(g.dR, dR, sizeof dR);
+      } else {
+        // static frame owner: R_H = dR_H R_a0^T is constant
+        for (int r = 0; r < 3; ++r)
+          for (int cc = 0; cc < 3; ++cc)
+            g.dR[3 * r + cc] = dR[3 * r] * Ra0[3 * cc] + dR[3 * r + 1] * Ra0[3 * cc + 1] +
+                               dR[3 * r + 2] * Ra0[3 * cc + 2];
+        g.flags |= GJ_FLAG_STATIC_OWNER;
+      }
+    }
+    c->gj.push_back(g);
+  }
+  // incidence of generic bodies
+  c->inc_off.assign(c->nd + 1, 0);
+  {
+    std::vector<std::vector<int>> lst(c->nd);
+    for (int gk = 0; gk < (int)c->gj.size(); ++gk) {
+      if (c->gj[gk].sa >= 0) lst[c->gj[gk].sa].push_back(gk << 1);
+      if (c->gj[gk].sb >= 0) lst[c->gj[gk].sb].push_back((gk << 1) | 1);
+    }
+    for (int i = 0; i < c->nd; ++i) {
+      c->inc_off[i + 1] = c->inc_off[i] + (int)lst[i].size();
+      for (int e : lst[i]) c->inc.push_back(e);
+    }
+  }
+  // shapes
+  std::vector<double> shape;
+  std::vector<int32_t> shp(c->nd);
+  {
+    std::map<std::tuple<double, double, double, double, double, double>, int> dedup;
+    for (int s = 0; s < c->nd; ++s) {
+      const int i = c->sol2in[s];
+      const double *d = B->dims + 3 * i;
+      const double nu = opt.material == 1 ? B->poisson[i] : 0.0;
+      auto key = std::make_tuple(d[0], d[1], d[2], B->density[i], B->k_orth[i], nu);
+      auto it = dedup.find(key);
+      if (it == dedup.end()) {
+        it = dedup.emplace(key, (int)dedup.size()).first;
+        const double V = d[0] * d[1] * d[2], mass = B->density[i] * V;
+        double mu, lam;
+        if (opt.material == 1) {
+          mu = B->k_orth[i] / (2.0 * (1.0 + nu));
+          lam = B->k_orth[i] * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        } else {
+          mu = 4.0 * B->k_orth[i];  // Eq. EA linearised at rest
+          lam = 0.0;
+        }
+        const double rec[SHAPE_STRIDE] = {mass * d[0] * d[0] / 12.0, mass * d[1] * d[1] / 12.0,
+                                          mass * d[2] * d[2] / 12.0, mass, V, mu, lam, 0.0};
+        shape.insert(shape.end(), rec, rec + SHAPE_STRIDE);
+      }
+      shp[s] = it->second;
+    }
+    c->nshape = (int)dedup.size();
+  }
+
+  // ------------------------------------------------------------ device
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  if (opt.stream) {
+    c->stream = (hipStream_t)opt.stream;
+  } else {
+    chk(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  const int64_t ns = c->ns;
+  for (int pb = 0; pb < 2; ++pb) {
+    chk(dalloc(c, &c->d_q[pb], 12 * ns));
+    chk(dalloc(c, &c->d_qd[pb], 12 * ns));
+  }
+  {
+    std::vector<double> hq(12 * ns, 0.0), hqd(12 * ns, 0.0);
+    for (int s = 0; s < c->nd; ++s)
+      for (int cc = 0; cc < 12; ++cc) {
+        hq[cc * ns + s] = c->q0_in[12 * (size_t)c->sol2in[s] + cc];
+        hqd[cc * ns + s] = c->qd0_in[12 * (size_t)c->sol2in[s] + cc];
+      }
+    if (e == hipSuccess) chk(hipMemcpy(c->d_q[0], hq.data(), hq.size() * 8, hipMemcpyHostToDevice));
+    if (e == hipSuccess) chk(hipMemcpy(c->d_qd[0], hqd.data(), hqd.size() * 8, hipMemcpyHostToDevice));
+  }
+  if (e == hipSuccess) chk(upload(c, &c->d_shp, shp));
+  if (e == hipSuccess) chk(upload(c, &c->d_shape, shape));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_hinv, (size_t)HINV_STRIDE * c->nshape));
+  if (e == hipSuccess) chk(upload(c, &c->d_chains, c->chains));
+  if (e == hipSuccess) chk(upload(c, &c->d_tiles, c->tiles));
+  const int64_t nrs = std::max<int64_t>(c->nchain_rows, 1);
+  {
+    std::vector<double> spl(3 * nrs, 0.0), spr(3 * nrs, 0.0);
+    for (int r = 0; r < c->nchain_rows; ++r)
+      for (int i = 0; i < 3; ++i) {
+        spl[i * nrs + r] = pl[3 * r + i];
+        spr[i * nrs + r] = pr[3 * r + i];
+      }
+    if (e == hipSuccess) chk(upload(c, &c->d_pl, spl));
+    if (e == hipSuccess) chk(upload(c, &c->d_pr, spr));
+    if (e == hipSuccess) chk(upload(c, &c->d_flag, cflag));
+  }
+  if (e == hipSuccess) chk(dalloc(c, &c->d_tilerec, (size_t)TILE_REC * c->tiles.size()));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_grow, (size_t)GROW_REC * c->ngrows));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_xg, (size_t)3 * c->ngrows));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_clam, (size_t)3 * nrs));
+  if (e == hipSuccess) chk(upload(c, &c->d_gj, c->gj));
+  const size_t mg = c->gj.size();
+  if (e == hipSuccess) chk(dalloc(c, &c->d_gl, GL_STRIDE * mg));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_gt, GT_STRIDE * mg));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_glam, 5 * mg));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_Rg, 9 * ns));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_ug, 12 * ns));
+  if (e == hipSuccess) chk(upload(c, &c->d_comp_lvl, c->comp_lvl));
+  if (e == hipSuccess) chk(upload(c, &c->d_lvl_off, c->lvl_off));
+  if (e == hipSuccess) chk(upload(c, &c->d_tbody, c->tbody));
+  if (e == hipSuccess) chk(upload(c, &c->d_tpk, c->tpk));
+  if (e == hipSuccess) chk(upload(c, &c->d_tabs_off, c->tabs_off));
+  if (e == hipSuccess) chk(upload(c, &c->d_tabs, c->tabs));
+  if (e == hipSuccess) chk(upload(c, &c->d_inc_off, c->inc_off));
+  if (e == hipSuccess) chk(upload(c, &c->d_inc, c->inc));
+  if (e == hipSuccess) chk(upload(c, &c->d_sol2in, c->sol2in));
+  if (e == hipSuccess) chk(upload(c, &c->d_pin_idx, c->pin_idx));
+  {
+    std::vector<double> pq;
+    for (int i : c->pin_idx) pq.insert(pq.end(), c->q0_in.begin() + 12 * (size_t)i, c->q0_in.begin() + 12 * (size_t)i + 12);
+    if (e == hipSuccess) chk(upload(c, &c->d_pin_q0, pq));
+  }
+  if (e == hipSuccess) chk(dalloc(c, &c->d_tmp, (size_t)24 * std::max(n, 1)));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_status, 4));
+  if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_status, 4 * sizeof(uint32_t)));
+  if (e != hipSuccess) {
+    mabd_status st = (e == hipErrorOutOfMemory) ? MABD_ERR_OOM : MABD_ERR_DEVICE;
+    std::string msg = std::string("device setup failed: ") + hipGetErrorString(e);
+    mabd_destroy(c);
+    return fail(nullptr, st, msg);
+  }
+  c->stats.n_chain = (int)c->chains.size();
+  c->stats.n_tree = c->ntree;
+  c->stats.n_graph = c->ngraph;
+  c->stats.n_dyn = c->nd;
+  c->stats.rho_p = c->stats.rho_d = c->stats.kkt = -1.0;
+  *out = c;
+  return MABD_OK;
+}
+
+
+mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
+  if (!c) return MABD_ERR_INVALID_ARG;
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(c, MABD_ERR_INVALID_ARG, "h must be > 0");
+  if (nsteps < 1) return fail(c, MABD_ERR_INVALID_ARG, "n must be >= 1");
+  hipStream_t s = c->stream;
+  if (h != c->h_last) {
+    launch_prefactor(c->d_shape, c->nshape, h, c->d_hinv, s);
+    c->h_last = h;
+  }
+  const int start_cur = c->cur;
+  PhaseTimer tm(c);
+  launch_reset_status(c->d_status, s);
+  const double *g = c->opt.gravity;
+  for (int st = 0; st < nsteps; ++st) {
+    const int a = c->cur, b = 1 - c->cur;
+    if (!c->chains.empty()) {
+      ChainArgs ca{};
+      ca.chains = c->d_chains;
+      ca.tiles = c->d_tiles;
+      ca.q = c->d_q[a];
+      ca.qd = c->d_qd[a];
+      ca.q_out = c->d_q[b];
+      ca.qd_out = c->d_qd[b];
+      ca.ns = c->ns;
+      ca.shp = c->d_shp;
+      ca.hinv = c->d_hinv;
+      ca.shape = c->d_shape;
+      ca.pl = c->d_pl;
+      ca.pr = c->d_pr;
+      ca.flag = c->d_flag;
+      ca.nrs = std::max(c->nchain_rows, 1);
+      ca.g[0] = g[0]; ca.g[1] = g[1]; ca.g[2] = g[2];
+      ca.h = h;
+      ca.tilerec = c->d_tilerec;
+      ca.xg = c->d_xg;
+      ca.lam = c->d_clam;
+      ca.status = c->d_status;
+      ca.step = st;
+      tm.run(0, [&] { launch_chain_reduce(ca, (int)c->tiles.size(), s); });
+      tm.run(1, [&] {
+        launch_chain_global(c->d_chains, (int)c->chains.size(), c->d_tilerec, c->d_grow, c->d_xg,
+                            c->d_status, st, s);
+      });
+      tm.run(2, [&] { launch_chain_apply(ca, (int)c->tiles.size(), s); });
+    }
+    if (c->gb1 > c->gb0) {
+      for (int it = 0; it < c->opt.newton_iters; ++it) {
+        const double *qcur = it == 0 ? c->d_q[a] : c->d_q[b];
+        tm.run(3, [&] {
+          launch_gbody(c->gb0, c->gb1, qcur, c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv,
+                       c->d_shape, g, h, c->d_Rg, c->d_ug, c->d_status, st, s);
+        });
+        tm.run(4, [&] {
+          launch_gjoint((int)c->gj.size(), c->d_gj, qcur, c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
+        });
+        TreeArgs ta{};
+        ta.comp_lvl = c->d_comp_lvl;
+        ta.lvl_off = c->d_lvl_off;
+        ta.tbody = c->d_tbody;
+        ta.tpk = c->d_tpk;
+        ta.tabs_off = c->d_tabs_off;
+        ta.tabs = c->d_tabs;
+        ta.gl = c->d_gl;
+        ta.gt = c->d_gt;
+        ta.u = c->d_ug;
+        ta.ns = c->ns;
+        ta.shp = c->d_shp;
+        ta.hinv = c->d_hinv;
+        ta.glam = c->d_glam;
+        ta.status = c->d_status;
+        ta.step = st;
+        tm.run(5, [&] { launch_tree(ta, c->d_gj, c->ntree, s); });
+        tm.run(6, [&] {
+          launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_glam, c->d_Rg, c->d_ug,
+                        c->ns, c->d_shp, c->d_hinv, qcur, c->d_q[b], c->d_qd[b], h, it > 0 ? 1 : 0,
+                        c->d_status, c->d_gj, st, s);
+        });
+      }
+    }
+    c->cur = b;
+  }
+  hipError_t e = hipMemcpyAsync(c->h_status, c->d_status, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("step: ") + hipGetErrorString(e));
+  tm.collect();
+  const uint32_t bits = c->h_status[0];
+  if (bits) {
+    // steps after the failing one did nothing: the state before it is in the
+    // buffer that step read from
+    const int f = (int)c->h_status[1];
+    c->cur = (start_cur + f) % 2;
+    c->stats.steps_done += f;
+    c->stats.last_status = (bits & FLAG_NONFINITE) ? MABD_ERR_NONFINITE : MABD_ERR_SINGULAR;
+    return fail(c, (mabd_status)c->stats.last_status,
+                (bits & FLAG_NONFINITE) ? "non-finite value or det A <= 0 during the step"
+                                        : "dual pivot block not positive definite");
+  }
+  c->stats.steps_done += nsteps;
+  c->stats.last_status = MABD_OK;
+  return MABD_OK;
+}
+
+mabd_status mabd_state_device(const mabd_ctx *cc, void *q_dev, void *qd_dev) {
+  mabd_ctx *c = const_cast<mabd_ctx *>(cc);
+  if (!c) return MABD_ERR_INVALID_ARG;
+  hipStream_t s = c->stream;
+  launch_gather_state(c->nd, c->d_sol2in, c->d_q[c->cur], c->d_qd[c->cur], c->ns, (double *)q_dev,
+                      (double *)qd_dev, s);
+  launch_write_pinned((int)c->pin_idx.size(), c->d_pin_idx, c->d_pin_q0, (double *)q_dev,
+                      (double *)qd_dev, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  return MABD_OK;
+}
+
+mabd_status mabd_state(const mabd_ctx *cc, double *q, double *qd) {
+  mabd_ctx *c = const_cast<mabd_ctx *>(cc);
+  if (!c) return MABD_ERR_INVALID_ARG;
+  const size_t n12 = (size_t)12 * c->n;
+  double *tq = c->d_tmp, *tqd = c->d_tmp + n12;
+  mabd_status st = mabd_state_device(c, tq, tqd);
+  if (st != MABD_OK) return st;
+  hipError_t e = hipSuccess;
+  if (q && n12) e = hipMemcpyAsync(q, tq, n12 * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && qd && n12) e = hipMemcpyAsync(qd, tqd, n12 * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  return MABD_OK;
+}
+
+mabd_status mabd_set_state(mabd_ctx *c, const double *q, const double *qd) {
+  if (!c || !q || !qd) return MABD_ERR_INVALID_ARG;
+  const size_t n12 = (size_t)12 * c->n;
+  if (!finite_all(q, n12) || !finite_all(qd, n12)) return fail(c, MABD_ERR_INVALID_ARG, "state not finite");
+  for (int s = 0; s < c->nd; ++s) {
+    const double *qq = q + 12 * (size_t)c->sol2in[s];
+    double A[9] = {qq[0], qq[3], qq[6], qq[1], qq[4], qq[7], qq[2], qq[5], qq[8]};
+    double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                 A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(det > 0)) return fail(c, MABD_ERR_INVALID_ARG, "det A <= 0 in the new state");
+  }
+  double *tq = c->d_tmp, *tqd = c->d_tmp + n12;
+  hipError_t e = hipSuccess;
+  if (n12) e = hipMemcpyAsync(tq, q, n12 * 8, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && n12) e = hipMemcpyAsync(tqd, qd, n12 * 8, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) {
+    launch_scatter_state(c->nd, c->d_sol2in, tq, tqd, c->d_q[c->cur], c->d_qd[c->cur], c->ns, c->stream);
+    e = hipStreamSynchronize(c->stream);
+  }
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  return MABD_OK;
+}
+
+mabd_status mabd_multipliers(const mabd_ctx *cc, double *lam) {
+  mabd_ctx *c = const_cast<mabd_ctx *>(cc);
+  if (!c || !lam) return MABD_ERR_INVALID_ARG;
+  std::vector<double> cl(3 * (size_t)c->nchain_rows), gl(5 * c->gj.size());
+  hipError_t e = hipSuccess;
+  if (!cl.empty()) e = hipMemcpyAsync(cl.data(), c->d_clam, cl.size() * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && !gl.empty())
+    e = hipMemcpyAsync(gl.data(), c->d_glam, gl.size() * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  for (int r = 0; r < c->nchain_rows; ++r) {
+    const int k = c->crow_joint[r];
+    for (int i = 0; i < 3; ++i) lam[c->jrow_off[k] + i] = cl[3 * (size_t)r + i];
+  }
+  for (size_t gk = 0; gk < c->gj.size(); ++gk) {
+    const int k = c->gj_in[gk];
+    const int rk = c->jtype[k] ? 5 : 3;
+    for (int i = 0; i < rk; ++i) lam[c->jrow_off[k] + i] = gl[5 * gk + i];
+  }
+  return MABD_OK;
+}
+
+mabd_status mabd_stats(const mabd_ctx *c, mabd_step_stats *st) {
+  if (!c || !st) return MABD_ERR_INVALID_ARG;
+  *st = c->stats;
+  return MABD_OK;
+}
+
+mabd_status mabd_gnn_load(mabd_ctx *c, const char *path) {
+  if (!c || !path) return MABD_ERR_INVALID_ARG;
+  return fail(c, MABD_ERR_INVALID_ARG, "graph-network warm start is not available in this build");
+}
+
+}  // extern "C"

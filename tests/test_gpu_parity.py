@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar (from the benchmark spec): the GPU state matches the oracle's state to
+relative 1e-10 per step in FP64.  Positions are compared relative to the
+largest coordinate, velocities relative to the largest velocity (a stricter
+check of the increment itself).  Multipliers are compared relative to their
+largest entry.
+"""
+import numpy as np
+import pytest
+
+import mabd_inputs as mi
+import oracle
+from gpu_util import say, state_errors, rel_err
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+try:  # import torch at collection time: its first import on a fresh box is slow
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    torch = None
+
+
+def ctx_of(asm, **kw):
+    import paper_2603_08079_amd as pk
+
+    return pk.Context(asm, **kw)
+
+
+def teacher_forced(asm, steps, solver=oracle.AUTO, tol=TOL, **kw):
+    """Both sides start every step from the oracle's state."""
+    s = oracle.System(asm, **{k: v for k, v in kw.items() if k in ("material", "hinge_grad", "newton_iters")})
+    ctx = ctx_of(asm, **kw)
+    q, qd = asm.q0.copy(), asm.qd0.copy()
+    worst = (0.0, 0.0, 0.0)
+    for n in range(steps):
+        ctx.set_state(q, qd)
+        ctx.step(asm.h, 1)
+        qg, qdg = ctx.state()
+        lam_g = ctx.multipliers()
+        q1, qd1, lam, d = s.step(asm.h, q, qd, solver=solver)
+        eq, eqd = state_errors(qg, qdg, q1, qd1)
+        el = rel_err(lam_g, lam, 1e-300) if asm.m else 0.0
+        worst = tuple(max(a, b) for a, b in zip(worst, (eq, eqd, el)))
+        assert eq < tol and eqd < tol, (n, eq, eqd)
+        assert el < 1e3 * tol, (n, el)
+        q, qd = q1, qd1
+    ctx.close()
+    return worst
+
+
+def test_free_spinning_body():
+    qd = np.zeros(12)
+    om = np.array([1.0, 8.0, 2.0])
+    for c in range(3):
+        qd[3 * c:3 * c + 3] = np.cross(om, np.eye(3)[:, c])
+    qd[9:] = [1.0, 0.0, 0.5]
+    b = mi.free_body(dims=(0.3, 0.2, 0.1), k_orth=1e7, qd=qd)
+    say("free body", b.n)
+    say("worst", teacher_forced(b, 20))
+
+
+def test_chain64_config_trajectory():
+    """The 64-body chain configuration over its 200 steps, free running on
+    both sides, plus the exact ball-joint residual of every GPU step."""
+    asm = mi.config("chain64")
+    say("chain64 trajectory", asm.n, asm.m)
+    ctx = ctx_of(asm)
+    st = ctx.stats()
+    assert st["n_chain"] == 1 and st["n_tree"] == 0
+    s = oracle.System(asm)
+    q, qd = asm.q0.copy(), asm.qd0.copy()
+    for n in range(asm.steps):
+        ctx.step(asm.h, 1)
+        q, qd, lam, d = s.step(asm.h, q, qd)
+        if n % 20 == 19 or n < 3:
+            qg, qdg = ctx.state()
+            eq, eqd = state_errors(qg, qdg, q, qd)
+            say(n, eq, eqd)
+            # free running: rounding differences may grow with the step count
+            assert eq < TOL * (n + 1) and eqd < TOL * (n + 1), (n, eq, eqd)
+    qg, _ = ctx.state()
+    chk = oracle.System(asm)
+    cmax = max(np.abs(chk.joint_terms(qg, k)[0]).max() for k in range(asm.m))
+    assert cmax < 1e-13 * max(1.0, np.abs(qg[:, 9:]).max())
+
+
+def test_chain64_teacher_forced():
+    asm = mi.config("chain64")
+    asm.qd0[1:] = np.random.default_rng(3).normal(0, 0.1, (63, 12))
+    say("chain64 teacher forced")
+    say("worst", teacher_forced(asm, 10))
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 129, 255, 256, 257, 258, 300, 509, 510, 511, 777, 2049])
+def test_chain_tile_edges(n):
+    """Chains whose row count lands on, below and above tile boundaries."""
+    asm = mi.chain(n, seed=n)
+    asm.qd0[1:] = np.random.default_rng(n).normal(0, 0.05, (n - 1, 12))
+    say("chain", n)
+    say("worst", teacher_forced(asm, 2))
+
+
+def test_chain_variants():
+    """No pinned body (free chain), a world joint at the far end, and joints
+    listed with reversed sides (flags of the row ends)."""
+    a = mi.chain(300, seed=1, pin_first=False)
+    say("free chain")
+    teacher_forced(a, 2)
+    b = mi.chain(300, seed=2)
+    b.jtype = np.append(b.jtype, 0).astype(np.uint8)
+    b.ja = np.append(b.ja, -1).astype(np.int32)
+    b.jb = np.append(b.jb, 299).astype(np.int32)
+    tip = b.q0[299, 9:] + np.array([0.5, 0, 0])
+    b.pa = np.vstack([b.pa, tip]); b.pb = np.vstack([b.pb, [0.5, 0, 0]])
+    b.axis = np.vstack([b.axis, [0, 1, 0]]); b.cp_len = np.append(b.cp_len, 0.1)
+    say("chain with world end")
+    teacher_forced(b, 2)
+    c = mi.chain(300, seed=3)
+    sw = np.arange(0, 299, 2)
+    c.ja[sw], c.jb[sw] = c.jb[sw].copy(), c.ja[sw].copy()
+    c.pa[sw], c.pb[sw] = c.pb[sw].copy(), c.pa[sw].copy()
+    say("chain with reversed joints")
+    teacher_forced(c, 2)
+    d = mi.chain(300, seed=4)
+    perm = np.random.default_rng(0).permutation(d.m)
+    for f in ("jtype", "ja", "jb", "pa", "pb", "axis", "cp_len"):
+        setattr(d, f, getattr(d, f)[perm])
+    say("chain with shuffled joint order")
+    teacher_forced(d, 2)
+
+
+def test_tree_and_hinge_paths():
+    t = mi.tree(300, seed=5)
+    t.qd0[1:] = np.random.default_rng(5).normal(0, 0.05, (299, 12))
+    say("tree 300")
+    teacher_forced(t, 3)
+    h = mi.chain(200, seed=6, hinge_frac=0.5)
+    say("hinge chain 200")
+    teacher_forced(h, 3)
+    w = mi.tree(100, seed=7, window=3)
+    say("tree frozen hinge gradient")
+    teacher_forced(w, 2, hinge_grad=2)
+
+
+def test_tree_with_world_joints_and_lame():
+    t = mi.tree(120, seed=8, window=8)
+    t.jtype = np.append(t.jtype, [0, 1]).astype(np.uint8)
+    t.ja = np.append(t.ja, [50, -1]).astype(np.int32)
+    t.jb = np.append(t.jb, [-1, 90]).astype(np.int32)
+    p50 = t.q0[50, 9:] + np.array([0.0, 0.0, 0.02])
+    p90 = t.q0[90, 9:] + np.array([0.0, 0.01, 0.0])
+    t.pa = np.vstack([t.pa, [0.0, 0.0, 0.02], p90]); t.pb = np.vstack([t.pb, p50, [0.0, 0.01, 0.0]])
+    t.axis = np.vstack([t.axis, [0, 1, 0], [0.6, 0, 0.8]]); t.cp_len = np.append(t.cp_len, [0.1, 0.1])
+    t.material = 1
+    t.poisson = np.full(t.n, 0.3)
+    t.k_orth[:] = 1e8
+    say("tree with world joints, Lame material")
+    teacher_forced(t, 2)
+
+
+def test_newton_iterations():
+    t = mi.tree(60, seed=9)
+    t.qd0[1:] = np.random.default_rng(9).normal(0, 0.5, (59, 12))
+    say("tree newton 3")
+    teacher_forced(t, 2, newton_iters=3)
+
+
+def test_multi_step_call_equals_single_steps():
+    asm = mi.chain(600, seed=10)
+    a = ctx_of(asm); b = ctx_of(asm)
+    a.step(asm.h, 5)
+    for _ in range(5):
+        b.step(asm.h, 1)
+    qa, qda = a.state(); qb, qdb = b.state()
+    assert np.array_equal(qa, qb) and np.array_equal(qda, qdb)
+
+
+def test_state_roundtrip_and_device_copy():
+    import torch
+
+    asm = mi.tree(200, seed=11)
+    ctx = ctx_of(asm)
+    ctx.step(asm.h, 3)
+    q, qd = ctx.state()
+    ctx.set_state(q, qd)
+    ctx.step(asm.h, 2)
+    q1, qd1 = ctx.state()
+    ref = ctx_of(asm)
+    ref.step(asm.h, 5)
+    q2, qd2 = ref.state()
+    assert np.array_equal(q1, q2) and np.array_equal(qd1, qd2)
+    tq = torch.zeros((asm.n, 12), dtype=torch.float64, device="cuda")
+    tqd = torch.zeros((asm.n, 12), dtype=torch.float64, device="cuda")
+    ctx.state_device(tq, tqd)
+    torch.cuda.synchronize()
+    assert np.array_equal(tq.cpu().numpy(), q1) and np.array_equal(tqd.cpu().numpy(), qd1)
+    assert np.array_equal(q1[0], asm.q0[0]) and np.all(qd1[0] == 0.0)
+
+
+def test_nonfinite_step_keeps_last_state():
+    import paper_2603_08079_amd as pk
+
+    asm = mi.chain(40, seed=12)
+    ctx = ctx_of(asm)
+    ctx.step(asm.h, 2)
+    q, qd = ctx.state()
+    bad = qd.copy()
+    bad[5, 9] = 1e308
+    ctx.set_state(q, bad)
+    with pytest.raises(pk.MabdError) as ei:
+        ctx.step(asm.h, 3)
+    assert ei.value.status == pk.ERR_NONFINITE
+    q1, qd1 = ctx.state()
+    assert np.array_equal(q1, q) and np.array_equal(qd1, bad)
