@@ -52,4 +52,31 @@ struct TreeArgs {
   uint32_t *status;
   int step;
 };
+
+struct PcgArgs {
+  int nb;                    // generic bodies in [b0, b0 + nb)
+  int b0;
+  int mj;                    // generic joints (all, tree joints included but masked)
+  const int32_t *jmask;      // 1 if the joint belongs to a graph component
+  const int32_t *bmask;      // 1 if the body belongs to a graph component
+  const GJoint *J;
+  const double *gl;          // C, L_a, L_b per joint
+  const double *ug;          // local unconstrained increments (SoA)
+  int64_t ns;
+  const int32_t *shp;
+  const double *hinv;
+  const int32_t *inc_off, *inc;
+  double *lam;               // 5 per joint: in = warm start (or zero), out = solution
+  double *r, *p, *z, *sp;    // 5 per joint
+  double *dinv;              // 25 per joint
+  double *zb;                // 12 per body (SoA with stride ns)
+  double *partial;           // 4 per block
+  double tol;
+  int max_iters;
+  int warm;                  // lambda holds a start value
+  int *iters_out;
+  double *res_out;           // |r|/|b| reached
+  uint32_t *status;
+  int step;
+};
 }  // namespace mabd

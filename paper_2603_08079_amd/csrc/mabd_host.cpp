@@ -43,6 +43,8 @@ void launch_scatter_state(int nd, const int32_t *sol2in, const double *qi, const
 void launch_write_pinned(int np, const int32_t *idx, const double *q0, double *qo, double *qdo,
                          hipStream_t s);
 void launch_reset_status(uint32_t *status, hipStream_t s);
+hipError_t launch_pcg(const PcgArgs &a, int nblocks, hipStream_t s);
+int pcg_max_blocks();
 }  // namespace mabd
 
 using namespace mabd;
@@ -152,12 +154,21 @@ struct mabd_ctx {
   int32_t *d_comp_lvl = nullptr, *d_lvl_off = nullptr, *d_tbody = nullptr, *d_tpk = nullptr,
           *d_tabs_off = nullptr, *d_tabs = nullptr, *d_inc_off = nullptr, *d_inc = nullptr;
   int32_t *d_sol2in = nullptr, *d_pin_idx = nullptr;
+  // graph components (PCG)
+  std::vector<int32_t> jmask, bmask;
+  int32_t *d_jmask = nullptr, *d_bmask = nullptr;
+  double *d_pr_ = nullptr, *d_pp = nullptr, *d_pz = nullptr, *d_psp = nullptr, *d_dinv = nullptr,
+         *d_zb = nullptr, *d_partial = nullptr, *d_pcg_res = nullptr;
+  int32_t *d_pcg_it = nullptr;
+  int pcg_blocks = 0;
+  double *h_pcg = nullptr;
   double *d_pin_q0 = nullptr, *d_tmp = nullptr;
   uint32_t *d_status = nullptr;
   uint32_t *h_status = nullptr;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   double h_last = -1.0;
+  bool warm_valid = false;
   mabd_step_stats stats{};
   // kernel-group timing (diagnostics bit 1)
   std::vector<hipEvent_t> ev_pool;
@@ -264,6 +275,7 @@ void mabd_destroy(mabd_ctx *c) {
   for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->h_status) (void)hipHostFree(c->h_status);
+  if (c->h_pcg) (void)hipHostFree(c->h_pcg);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -399,11 +411,6 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       cls[ci] = CLS_CHAIN;
     else cls[ci] = CLS_TREE;
   }
-  for (int ci = 0; ci < ncomp; ++ci)
-    if (cls[ci] == CLS_GRAPH) {
-      delete c;
-      return fail(nullptr, MABD_ERR_TOPOLOGY, "closed loops need the PCG solver, which this build lacks");
-    }
 
   // ------------------------------------------------------------ solver order
   c->in2sol.assign(n, -1);
@@ -512,11 +519,13 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   // generic (tree) components
   c->gb0 = c->nchain_bodies;
   std::vector<int> gidx(m, -1);  // input joint -> generic joint
+  std::vector<int32_t> gj_graph;
   for (int ci = 0; ci < ncomp; ++ci) {
-    if (cls[ci] != CLS_TREE) continue;
+    if (cls[ci] != CLS_TREE && cls[ci] != CLS_GRAPH) continue;
     for (int k : cjoints[ci]) {
       gidx[k] = (int)c->gj_in.size();
       c->gj_in.push_back(k);
+      gj_graph.push_back(cls[ci] == CLS_GRAPH ? 1 : 0);
     }
   }
   // tree schedules: root, BFS, heights, level order
@@ -589,7 +598,20 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     c->ntree++;
   }
   c->tabs_off.push_back((int)c->tabs.size());
+  // graph components: bodies after the trees, solved by PCG
+  std::vector<int32_t> graph_bodies;
+  for (int ci = 0; ci < ncomp; ++ci) {
+    if (cls[ci] != CLS_GRAPH) continue;
+    for (int b : cbodies[ci]) {
+      add_body(b);
+      graph_bodies.push_back(c->in2sol[b]);
+    }
+    c->ngraph++;
+  }
   c->gb1 = (int)c->sol2in.size();
+  c->jmask = gj_graph;
+  c->bmask.assign(c->sol2in.size(), 0);
+  for (int b : graph_bodies) c->bmask[b] = 1;
   c->nd = (int)c->sol2in.size();
   for (int i = 0; i < n; ++i)
     if (pinned[i]) c->pin_idx.push_back(i);
@@ -762,6 +784,25 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     if (e == hipSuccess) chk(upload(c, &c->d_pin_q0, pq));
   }
   if (e == hipSuccess) chk(dalloc(c, &c->d_tmp, (size_t)24 * std::max(n, 1)));
+  if (c->ngraph > 0) {
+    if (e == hipSuccess) chk(upload(c, &c->d_jmask, c->jmask));
+    if (e == hipSuccess) chk(upload(c, &c->d_bmask, c->bmask));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_pr_, 5 * mg));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_pp, 5 * mg));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_pz, 5 * mg));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_psp, 5 * mg));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_dinv, 25 * mg));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_zb, 12 * ns));
+    if (e == hipSuccess) {
+      c->pcg_blocks = std::min(pcg_max_blocks(), (int)std::max<size_t>((mg + 255) / 256, 1));
+      if (c->pcg_blocks <= 0) e = hipErrorInvalidConfiguration;
+    }
+    if (e == hipSuccess) chk(dalloc(c, &c->d_partial, 4 * (size_t)std::max(c->pcg_blocks, 1)));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_pcg_res, 2));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_pcg_it, 2));
+    if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_pcg, 4 * sizeof(double)));
+  }
+  if (e == hipSuccess && mg) chk(hipMemset(c->d_glam, 0, 5 * mg * sizeof(double)));
   if (e == hipSuccess) chk(dalloc(c, &c->d_status, 4));
   if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_status, 4 * sizeof(uint32_t)));
   if (e != hipSuccess) {
@@ -852,6 +893,40 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
         ta.status = c->d_status;
         ta.step = st;
         tm.run(5, [&] { launch_tree(ta, c->d_gj, c->ntree, s); });
+        if (c->ngraph > 0) {
+          PcgArgs pa{};
+          pa.nb = c->gb1 - c->gb0;
+          pa.b0 = c->gb0;
+          pa.mj = (int)c->gj.size();
+          pa.jmask = c->d_jmask;
+          pa.bmask = c->d_bmask;
+          pa.J = c->d_gj;
+          pa.gl = c->d_gl;
+          pa.ug = c->d_ug;
+          pa.ns = c->ns;
+          pa.shp = c->d_shp;
+          pa.hinv = c->d_hinv;
+          pa.inc_off = c->d_inc_off;
+          pa.inc = c->d_inc;
+          pa.lam = c->d_glam;
+          pa.r = c->d_pr_;
+          pa.p = c->d_pp;
+          pa.z = c->d_pz;
+          pa.sp = c->d_psp;
+          pa.dinv = c->d_dinv;
+          pa.zb = c->d_zb;
+          pa.partial = c->d_partial;
+          pa.tol = c->opt.kkt_tol;
+          pa.max_iters = c->opt.max_iters;
+          pa.warm = (c->opt.warm_start == 1 && c->warm_valid) ? 1 : 0;
+          pa.iters_out = c->d_pcg_it;
+          pa.res_out = c->d_pcg_res;
+          pa.status = c->d_status;
+          pa.step = st;
+          hipError_t pe = hipSuccess;
+          tm.run(7, [&] { pe = launch_pcg(pa, c->pcg_blocks, s); });
+          if (pe != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("PCG launch: ") + hipGetErrorString(pe));
+        }
         tm.run(6, [&] {
           launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_glam, c->d_Rg, c->d_ug,
                         c->ns, c->d_shp, c->d_hinv, qcur, c->d_q[b], c->d_qd[b], h, it > 0 ? 1 : 0,
@@ -862,9 +937,20 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
     c->cur = b;
   }
   hipError_t e = hipMemcpyAsync(c->h_status, c->d_status, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && c->ngraph > 0) {
+    e = hipMemcpyAsync(c->h_pcg, c->d_pcg_res, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->h_pcg + 1, c->d_pcg_it, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("step: ") + hipGetErrorString(e));
   tm.collect();
+  if (c->ngraph > 0) {
+    int32_t its;
+    std::memcpy(&its, c->h_pcg + 1, sizeof its);
+    c->stats.pcg_iters = its;
+    c->stats.rho_d = c->h_pcg[0];
+  }
   const uint32_t bits = c->h_status[0];
   if (bits) {
     // steps after the failing one did nothing: the state before it is in the
@@ -872,13 +958,17 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
     const int f = (int)c->h_status[1];
     c->cur = (start_cur + f) % 2;
     c->stats.steps_done += f;
-    c->stats.last_status = (bits & FLAG_NONFINITE) ? MABD_ERR_NONFINITE : MABD_ERR_SINGULAR;
+    c->stats.last_status = (bits & FLAG_NONFINITE) ? MABD_ERR_NONFINITE
+                           : (bits & FLAG_SINGULAR) ? MABD_ERR_SINGULAR
+                                                    : MABD_ERR_NOT_CONVERGED;
     return fail(c, (mabd_status)c->stats.last_status,
                 (bits & FLAG_NONFINITE) ? "non-finite value or det A <= 0 during the step"
-                                        : "dual pivot block not positive definite");
+                : (bits & FLAG_SINGULAR) ? "dual pivot block not positive definite"
+                                         : "PCG reached max_iters above kkt_tol");
   }
   c->stats.steps_done += nsteps;
   c->stats.last_status = MABD_OK;
+  c->warm_valid = true;
   return MABD_OK;
 }
 

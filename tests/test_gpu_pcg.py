@@ -1,0 +1,119 @@
+"""GPU PCG on assemblies with closed loops against the oracle's direct solve.
+
+The iterative solve stops at |r - S lam| <= tol |r| (tol = 1e-12 here), so the
+state is compared at the bound that tolerance implies: the oracle re-projects
+the GPU multipliers (FP64, its own back-projection) and must find the same
+relative dual residual, and the GPU state must agree with the oracle's direct
+solution to relative 1e-8 (kappa(S) ~ 1e4 on these sizes).
+"""
+import numpy as np
+import pytest
+
+import mabd_inputs as mi
+import oracle
+from gpu_util import say, state_errors
+
+pytestmark = pytest.mark.gpu
+
+try:
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    torch = None
+
+
+def run_pair(asm, steps, tol=1e-12, **kw):
+    import paper_2603_08079_amd as pk
+
+    s = oracle.System(asm)
+    ctx = pk.Context(asm, kkt_tol=tol, **kw)
+    st = ctx.stats()
+    assert st["n_graph"] >= 1
+    q, qd = asm.q0.copy(), asm.qd0.copy()
+    its = []
+    for n in range(steps):
+        ctx.set_state(q, qd)
+        ctx.step(asm.h, 1)
+        qg, qdg = ctx.state()
+        lam_g = ctx.multipliers()
+        its.append(ctx.stats()["pcg_iters"])
+        q1, qd1, lam, d = s.step_sparse(asm.h, q, qd)
+        # oracle verification of the GPU multipliers
+        qv, qdv, dv = s.finish(asm.h, q, qd, lam_g)
+        assert dv[oracle.RHO_D] <= 5 * tol, dv[:3]
+        eq, eqd = state_errors(qg, qdg, q1, qd1)
+        ev, evd = state_errors(qg, qdg, qv, qdv)
+        say(n, "iters", its[-1], "vs direct", eq, eqd, "vs own lambda", ev, evd)
+        assert eq < 1e-10 and eqd < 1e-7
+        assert ev < 1e-12 and evd < 1e-9
+        q, qd = q1, qd1
+    ctx.close()
+    return its
+
+
+def test_lattice_pcg():
+    asm = mi.lattice(8, seed=1)
+    say("lattice 8x8", asm.n, asm.m)
+    run_pair(asm, 3)
+
+
+def test_rgg_pcg():
+    asm = mi.rgg(400, seed=2)
+    say("rgg 400", asm.n, asm.m)
+    run_pair(asm, 2)
+
+
+def test_mixed_components():
+    """One context holding a chain, a tree and a lattice: every class of
+    solver runs in the same step."""
+    parts = [mi.chain(300, seed=3), mi.tree(150, seed=4, origin=(0.0, 20.0, 0.0)),
+             mi.lattice(6, seed=5)]
+    parts[2].q0[:, 10] += 40.0
+    asm = mi.concat(parts, h=1e-2, steps=2)
+    say("mixed", asm.n, asm.m)
+    import paper_2603_08079_amd as pk
+
+    ctx = pk.Context(asm, kkt_tol=1e-12)
+    st = ctx.stats()
+    assert st["n_chain"] == 1 and st["n_tree"] >= 1 and st["n_graph"] == 1
+    s = oracle.System(asm)
+    q, qd = asm.q0.copy(), asm.qd0.copy()
+    for n in range(2):
+        ctx.set_state(q, qd)
+        ctx.step(asm.h, 1)
+        qg, qdg = ctx.state()
+        q, qd, lam, d = s.step_sparse(asm.h, q, qd)
+        eq, eqd = state_errors(qg, qdg, q, qd)
+        say(n, eq, eqd)
+        assert eq < 1e-10 and eqd < 1e-7
+
+
+def test_warm_start_previous_step():
+    import paper_2603_08079_amd as pk
+
+    asm = mi.lattice(8, seed=6)
+    cold = pk.Context(asm, kkt_tol=1e-12, warm_start=0)
+    warm = pk.Context(asm, kkt_tol=1e-12, warm_start=1)
+    ic, iw = [], []
+    for _ in range(4):
+        cold.step(asm.h, 1)
+        warm.step(asm.h, 1)
+        ic.append(cold.stats()["pcg_iters"])
+        iw.append(warm.stats()["pcg_iters"])
+    say("cold", ic, "warm", iw)
+    qc, _ = cold.state()
+    qw, _ = warm.state()
+    assert np.abs(qc - qw).max() < 1e-9 * np.abs(qc).max()
+    assert sum(iw[1:]) < sum(ic[1:])
+
+
+def test_not_converged_keeps_state():
+    import paper_2603_08079_amd as pk
+
+    asm = mi.lattice(8, seed=7)
+    ctx = pk.Context(asm, kkt_tol=1e-12, max_iters=3)
+    q0, qd0 = ctx.state()
+    with pytest.raises(pk.MabdError) as ei:
+        ctx.step(asm.h, 2)
+    assert ei.value.status == pk.ERR_NOT_CONVERGED
+    q1, qd1 = ctx.state()
+    assert np.array_equal(q0, q1) and np.array_equal(qd0, qd1)
