@@ -22,7 +22,7 @@ constexpr int GJ_FLAG_STATIC_OWNER = 1;
 constexpr int GL_STRIDE = 128;
 enum { GL_C = 0, GL_LA = 8, GL_LB = 68 };
 
-// per-joint tree data: Sigma (5x5), rho (5), a (5), E (5x5)
+// per-joint tree data: Sigma (5x5), rho (5) of the condensed child side
 constexpr int GT_STRIDE = 64;
 enum { GT_SIG = 0, GT_RHO = 25, GT_A = 30, GT_E = 35 };
 
@@ -30,8 +30,8 @@ enum { GT_SIG = 0, GT_RHO = 25, GT_A = 30, GT_E = 35 };
 inline int32_t abs_pack(int32_t k, int side, int unary) { return (k << 2) | (side << 1) | unary; }
 
 constexpr int TEAM = 16;              // lanes per body in the tree elimination
-constexpr int TREE_THREADS = 1024;
-constexpr int MAX_UNARY_ROWS = 6;
+constexpr int TREE_KLDS = 16;         // cliques up to this many rows are factored in LDS
+constexpr int TREE_KMAX = 64;         // largest clique (absorbed + parent rows) accepted
 
 // per-body incidence entry: joint index << 1 | side
 
@@ -51,6 +51,9 @@ struct TreeArgs {
   double *glam;             // 5 per generic joint
   uint32_t *status;
   int step;
+  const int32_t *tne;       // slot -> absorbed rows
+  const int64_t *foff;      // slot -> offset of its factor in fac
+  double *fac;
 };
 
 struct PcgArgs {
@@ -68,6 +71,7 @@ struct PcgArgs {
   const int32_t *inc_off, *inc;
   double *lam;               // 5 per joint: in = warm start (or zero), out = solution
   double *r, *p, *z, *sp;    // 5 per joint
+  double *bv;                // right-hand side, 5 per joint
   double *dinv;              // 25 per joint
   double *zb;                // 12 per body (SoA with stride ns)
   double *partial;           // 4 per block

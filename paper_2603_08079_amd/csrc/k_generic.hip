@@ -185,78 +185,37 @@ __global__ void gjoint_kernel(int m, const GJoint *J, const double *q, const dou
 }
 
 // ------------------------------------------------------ (c2) tree solve
-// Leaf-to-root elimination in dual form.  Each body j keeps its condensed
-// local inverse P (12x12, one row per lane of a 16-lane team) and free
-// response w.  Absorbing a joint i whose far side is already condensed into
-// (Sigma_i, rho_i) is the Woodbury update
-//   M = L P L^T + Sigma,  a = M^{-1}(L w + rho),  w -= P L^T a,  P -= P L^T M^{-1} L P,
-// the exact elimination of that joint's multipliers (Sec. 5.3, Eq. module3-kkt;
-// one-sided joints have Sigma = 0).  For the parent joint k the body then
-// reports Sigma_k = L_k P L_k^T and rho_k = L_k w + C_k.  Multipliers follow
-// root to leaf as lambda_i = a_i - E_i lambda_k.
+// Leaf-to-root block elimination of the dual system (Sec. 5.3; the exact tree
+// KKT solution of Eq. module3-kkt).  In the dual graph the joints incident to
+// one body form a clique (Fig. dual_mat).  Body j gathers the rows of its
+// absorbed joints e (joints to its children, whose far side is already
+// condensed into (Sigma, rho), and one-sided joints) and of its parent joint k:
+//   K = [L_e; L_k] Hbar_j^{-1} [L_e; L_k]^T + diag(Sigma_e, 0),
+//   y = [L_e; L_k] u_j + [rho_e or C_e; C_k],
+// and factors the e-block by Cholesky: K_ee = Lc Lc^T, X = Lc^{-1} K_ek,
+// z = Lc^{-1} y_e.  The Schur complement Sigma_k = K_kk - X^T X and
+// rho_k = y_k - X^T z are the condensed far side of joint k seen from its
+// parent.  Root to leaf, lambda_e = Lc^{-T} (z - X lambda_k).  This is block
+// Cholesky of the SPD dual matrix in a perfect elimination order, so it keeps
+// the backward stability of a dense Cholesky of S.
+// A team of 16 lanes handles one body; cliques of up to TREE_KLDS rows are
+// factored in LDS, larger ones in the body's global slot.
 constexpr int TEAMS = 16;
 constexpr int TREE_BLOCK = TEAMS * TEAM;
-constexpr int MR = MAX_UNARY_ROWS;  // max rows absorbed at once
 
 struct TeamLds {
-  double L[MR * 12];
-  double Lk[5 * 12];
-  double Y[12 * MR];
-  double w[12];
-  double M[MR * MR];
-  double Mi[MR * MR];
-  double y[MR];
-  double a[MR];
-  double Tk[12 * 5];
-  double Z[MR * 5];
+  double L[TREE_KLDS * 12];
+  double Y[12 * TREE_KLDS];
+  double K[TREE_KLDS * TREE_KLDS];
+  double y[TREE_KLDS];
+  int32_t rowk[TREE_KLDS];   // joint of each clique row
+  int32_t rowi[TREE_KLDS];   // row index inside that joint
 };
 
 DEV void team_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
-
-// in-place inverse of an SPD n x n (n <= MR) by Cholesky; false if not SPD
-DEV bool spd_inverse(int n, const double *M, double *Mi) {
-  double Lc[MR * MR];
-  for (int i = 0; i < n * n; ++i) Lc[i] = M[i];
-  for (int j = 0; j < n; ++j) {
-    double d = Lc[j * n + j];
-    for (int k = 0; k < j; ++k) d -= Lc[j * n + k] * Lc[j * n + k];
-    if (!(d > 0.0)) return false;
-    d = sqrt(d);
-    Lc[j * n + j] = d;
-    for (int i = j + 1; i < n; ++i) {
-      double s = Lc[i * n + j];
-      for (int k = 0; k < j; ++k) s -= Lc[i * n + k] * Lc[j * n + k];
-      Lc[i * n + j] = s / d;
-    }
-  }
-  // inverse column by column
-  for (int c = 0; c < n; ++c) {
-    double x[MR];
-    for (int i = 0; i < n; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = 0; k < i; ++k) s -= Lc[i * n + k] * x[k];
-      x[i] = s / Lc[i * n + i];
-    }
-    for (int i = n - 1; i >= 0; --i) {
-      double s = x[i];
-      for (int k = i + 1; k < n; ++k) s -= Lc[k * n + i] * x[k];
-      x[i] = s / Lc[i * n + i];
-    }
-    for (int i = 0; i < n; ++i) Mi[i * n + c] = x[i];
-  }
-  for (int i = 0; i < n; ++i)
-    for (int j = i + 1; j < n; ++j) {
-      double v = 0.5 * (Mi[i * n + j] + Mi[j * n + i]);
-      Mi[i * n + j] = Mi[j * n + i] = v;
-    }
-  return true;
-}
-
-
-
 
 __global__ __launch_bounds__(TREE_BLOCK) void tree_forward_kernel(TreeArgs a, const GJoint *J) {
   __shared__ TeamLds team_lds[TEAMS];
@@ -269,259 +228,135 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_forward_kernel(TreeArgs a, co
     for (int slot = s0 + tm; slot < s1; slot += TEAMS) {
       const int64_t b = a.tbody[slot];
       const double *Th = a.hinv + (int64_t)HINV_STRIDE * a.shp[b];
-      double P[12];
-      double wr = 0.0;
-      if (ln < 12) {
-        double e[12];
-        for (int i = 0; i < 12; ++i) e[i] = (i == ln) ? 1.0 : 0.0;
-        hinv_apply(Th, e, P);  // row ln of Hbar^{-1} (symmetric)
-        wr = a.u[ln * a.ns + b];
-        S.w[ln] = wr;
-      }
       const int pk = a.tpk[slot];
       const int kpar = pk >= 0 ? (pk >> 1) : -1;
       const int ck = kpar >= 0 ? (J[kpar].type ? 5 : 3) : 0;
-      if (kpar >= 0) {
-        const double *Lsrc = a.gl + (int64_t)GL_STRIDE * kpar + ((pk & 1) ? GL_LB : GL_LA);
-        for (int i = ln; i < ck * 12; i += TEAM) S.Lk[i] = Lsrc[i];
+      const int e0 = a.tabs_off[slot], e1 = a.tabs_off[slot + 1];
+      const int ne = a.tne[slot];
+      const int nr = ne + ck;
+      double *fac = a.fac + a.foff[slot];  // nr*nr K, nr y, then (big cliques) L, Y
+      const bool big = nr > TREE_KLDS;
+      double *Lm = big ? fac + nr * nr + nr : S.L;
+      double *Ym = big ? fac + nr * nr + nr + 12 * nr : S.Y;
+      double *Km = big ? fac : S.K;
+      double *ym = big ? fac + nr * nr : S.y;
+      // 1) clique rows: absorbed joints in list order, then the parent joint
+      {
+        int r0 = 0;
+        for (int e = e0; e <= e1; ++e) {
+          int k, side;
+          if (e < e1) {
+            k = a.tabs[e] >> 2;
+            side = (a.tabs[e] >> 1) & 1;
+          } else {
+            if (kpar < 0) break;
+            k = kpar;
+            side = pk & 1;
+          }
+          const int c = J[k].type ? 5 : 3;
+          const double *Lsrc = a.gl + (int64_t)GL_STRIDE * k + (side ? GL_LB : GL_LA);
+          for (int i = ln; i < c * 12; i += TEAM) Lm[r0 * 12 + i] = Lsrc[i];
+          if (!big && ln < c) {
+            S.rowk[r0 + ln] = k;
+            S.rowi[r0 + ln] = ln;
+          }
+          r0 += c;
+        }
       }
       team_sync();
-      const int e0 = a.tabs_off[slot], e1 = a.tabs_off[slot + 1];
-      // children first, then the stacked one-sided rows
-      for (int pass = 0; pass < 2; ++pass) {
-        int nrow = 0;
-        if (pass == 0) {
-          // one child joint at a time
-          for (int e = e0; e < e1; ++e) {
-            const int ent = a.tabs[e];
-            if (ent & 1) continue;
-            const int k = ent >> 2, side = (ent >> 1) & 1;
-            const int c = J[k].type ? 5 : 3;
-            const double *Lsrc = a.gl + (int64_t)GL_STRIDE * k + (side ? GL_LB : GL_LA);
+      // 2) Y = Hbar^{-1} L^T, one clique row per lane
+      for (int col = ln; col < nr; col += TEAM) {
+        double yv[12];
+        hinv_apply(Th, Lm + 12 * col, yv);
+        for (int s = 0; s < 12; ++s) Ym[s * nr + col] = yv[s];
+      }
+      team_sync();
+      // 3) K = L Y (lower triangle), y = L u + constants
+      for (int idx = ln; idx < nr * nr; idx += TEAM) {
+        const int i = idx / nr, jj = idx % nr;
+        if (jj > i) continue;
+        double v = 0.0;
+        for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * Ym[s * nr + jj];
+        Km[i * nr + jj] = v;
+      }
+      for (int i = ln; i < nr; i += TEAM) {
+        double v = 0.0;
+        for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * a.u[s * a.ns + b];
+        ym[i] = v;
+      }
+      team_sync();
+      // far-side terms: Sigma and rho of child joints, C of one-sided and parent joints
+      if (ln == 0) {
+        int r0 = 0;
+        for (int e = e0; e <= e1; ++e) {
+          int k, unary;
+          if (e < e1) {
+            k = a.tabs[e] >> 2;
+            unary = a.tabs[e] & 1;
+          } else {
+            if (kpar < 0) break;
+            k = kpar;
+            unary = 1;  // parent rows take C_k only
+          }
+          const int c = J[k].type ? 5 : 3;
+          if (e < e1 && !unary) {
             const double *gtk = a.gt + (int64_t)GT_STRIDE * k;
-            for (int i = ln; i < c * 12; i += TEAM) S.L[i] = Lsrc[i];
-            for (int i = ln; i < c * c; i += TEAM) S.M[i] = gtk[GT_SIG + (i / c) * 5 + (i % c)];
-            if (ln < c) S.y[ln] = gtk[GT_RHO + ln];
-            team_sync();
-            if (ln < 12)
-              for (int cc = 0; cc < c; ++cc) {
-                double v = 0.0;
-                for (int s = 0; s < 12; ++s) v += P[s] * S.L[cc * 12 + s];
-                S.Y[ln * MR + cc] = v;
-              }
-            team_sync();
-            for (int i = ln; i < c * c; i += TEAM) {
-              const int r = i / c, d = i % c;
-              double v = S.M[i];
-              for (int s = 0; s < 12; ++s) v += S.L[r * 12 + s] * S.Y[s * MR + d];
-              S.M[i] = v;
+            for (int i = 0; i < c; ++i) {
+              for (int jj = 0; jj <= i; ++jj) Km[(r0 + i) * nr + r0 + jj] += gtk[GT_SIG + 5 * i + jj];
+              ym[r0 + i] += gtk[GT_RHO + i];
             }
-            if (ln < c) {
-              double v = S.y[ln];
-              for (int s = 0; s < 12; ++s) v += S.L[ln * 12 + s] * S.w[s];
-              S.y[ln] = v;
-            }
-            team_sync();
-            if (ln == 0) {
-              if (!spd_inverse(c, S.M, S.Mi)) {
-                raise_flag(a.status, FLAG_SINGULAR, a.step);
-                for (int i = 0; i < c * c; ++i) S.Mi[i] = 0.0;
-              }
-              for (int r = 0; r < c; ++r) {
-                double v = 0.0;
-                for (int d = 0; d < c; ++d) v += S.Mi[r * c + d] * S.y[d];
-                S.a[r] = v;
-              }
-            }
-            team_sync();
-            if (ln < 12) {
-              double G[MR];
-              double dw = 0.0;
-              for (int d = 0; d < c; ++d) {
-                double v = 0.0;
-                for (int cc = 0; cc < c; ++cc) v += S.Y[ln * MR + cc] * S.Mi[cc * c + d];
-                G[d] = v;
-                dw += S.Y[ln * MR + d] * S.a[d];
-              }
-              wr -= dw;
-              for (int s = 0; s < 12; ++s) {
-                double v = 0.0;
-                for (int d = 0; d < c; ++d) v += G[d] * S.Y[s * MR + d];
-                P[s] -= v;
-              }
-            }
-            team_sync();
-            if (ln < 12) S.w[ln] = wr;
-            team_sync();
+          } else {
+            for (int i = 0; i < c; ++i) ym[r0 + i] += a.gl[(int64_t)GL_STRIDE * k + GL_C + i];
           }
-        } else {
-          // stack the one-sided rows
-          for (int e = e0; e < e1; ++e) {
-            const int ent = a.tabs[e];
-            if (!(ent & 1)) continue;
-            const int k = ent >> 2, side = (ent >> 1) & 1;
-            const int c = J[k].type ? 5 : 3;
-            const double *Lsrc = a.gl + (int64_t)GL_STRIDE * k + (side ? GL_LB : GL_LA);
-            for (int i = ln; i < c * 12; i += TEAM) S.L[nrow * 12 + i] = Lsrc[i];
-            if (ln < c) S.y[nrow + ln] = a.gl[(int64_t)GL_STRIDE * k + GL_C + ln];
-            nrow += c;
-          }
-          if (nrow == 0) break;
-          const int c = nrow;
-          for (int i = ln; i < c * c; i += TEAM) S.M[i] = 0.0;
-          team_sync();
-          if (ln < 12)
-            for (int cc = 0; cc < c; ++cc) {
-              double v = 0.0;
-              for (int s = 0; s < 12; ++s) v += P[s] * S.L[cc * 12 + s];
-              S.Y[ln * MR + cc] = v;
-            }
-          team_sync();
-          for (int i = ln; i < c * c; i += TEAM) {
-            const int r = i / c, d = i % c;
-            double v = 0.0;
-            for (int s = 0; s < 12; ++s) v += S.L[r * 12 + s] * S.Y[s * MR + d];
-            S.M[i] = v;
-          }
-          if (ln < c) {
-            double v = S.y[ln];
-            for (int s = 0; s < 12; ++s) v += S.L[ln * 12 + s] * S.w[s];
-            S.y[ln] = v;
-          }
-          // Z = Y^T L_k^T  (coupling of these rows to the parent joint)
-          for (int i = ln; i < c * ck; i += TEAM) {
-            const int r = i / ck, f = i % ck;
-            double v = 0.0;
-            for (int s = 0; s < 12; ++s) v += S.Y[s * MR + r] * S.Lk[f * 12 + s];
-            S.Z[r * 5 + f] = v;
-          }
-          team_sync();
-          if (ln == 0) {
-            if (!spd_inverse(c, S.M, S.Mi)) {
-              raise_flag(a.status, FLAG_SINGULAR, a.step);
-              for (int i = 0; i < c * c; ++i) S.Mi[i] = 0.0;
-            }
-            for (int r = 0; r < c; ++r) {
-              double v = 0.0;
-              for (int d = 0; d < c; ++d) v += S.Mi[r * c + d] * S.y[d];
-              S.a[r] = v;
-            }
-          }
-          team_sync();
-          // a_u, E_u = M^{-1} Z, scattered to the individual joints
-          {
-            int off = 0;
-            for (int e = e0; e < e1; ++e) {
-              const int ent = a.tabs[e];
-              if (!(ent & 1)) continue;
-              const int k = ent >> 2;
-              const int cj = J[k].type ? 5 : 3;
-              double *gtk = a.gt + (int64_t)GT_STRIDE * k;
-              if (ln < cj) gtk[GT_A + ln] = S.a[off + ln];
-              for (int i = ln; i < cj * 5; i += TEAM) {
-                const int r = i / 5, f = i % 5;
-                double v = 0.0;
-                if (f < ck)
-                  for (int d = 0; d < c; ++d) v += S.Mi[(off + r) * c + d] * S.Z[d * 5 + f];
-                gtk[GT_E + i] = v;
-              }
-              off += cj;
-            }
-          }
-          if (ln < 12) {
-            double G[MR];
-            double dw = 0.0;
-            for (int d = 0; d < c; ++d) {
-              double v = 0.0;
-              for (int cc = 0; cc < c; ++cc) v += S.Y[ln * MR + cc] * S.Mi[cc * c + d];
-              G[d] = v;
-              dw += S.Y[ln * MR + d] * S.a[d];
-            }
-            wr -= dw;
-            for (int s = 0; s < 12; ++s) {
-              double v = 0.0;
-              for (int d = 0; d < c; ++d) v += G[d] * S.Y[s * MR + d];
-              P[s] -= v;
-            }
-          }
-          team_sync();
-          if (ln < 12) S.w[ln] = wr;
-          team_sync();
+          r0 += c;
         }
       }
-      // parent joint: T_k = P L_k^T, Sigma_k = L_k T_k, rho_k = L_k w + C_k
-      if (kpar >= 0) {
-        if (ln < 12)
-          for (int f = 0; f < ck; ++f) {
-            double v = 0.0;
-            for (int s = 0; s < 12; ++s) v += P[s] * S.Lk[f * 12 + s];
-            S.Tk[ln * 5 + f] = v;
-          }
-        team_sync();
-        double *gtk = a.gt + (int64_t)GT_STRIDE * kpar;
-        for (int i = ln; i < ck * ck; i += TEAM) {
-          const int r = i / ck, f = i % ck;
-          double v = 0.0;
-          for (int s = 0; s < 12; ++s) v += S.Lk[r * 12 + s] * S.Tk[s * 5 + f];
-          gtk[GT_SIG + r * 5 + f] = v;
-        }
-        if (ln < ck) {
-          double v = a.gl[(int64_t)GL_STRIDE * kpar + GL_C + ln];
-          for (int s = 0; s < 12; ++s) v += S.Lk[ln * 12 + s] * S.w[s];
-          gtk[GT_RHO + ln] = v;
-        }
-        team_sync();
-      }
-      // child joints: lambda_i = Sigma_i^{-1}(L_i dp_j + rho_i), dp_j = w - P L_k^T lambda_k
-      for (int e = e0; e < e1; ++e) {
-        const int ent = a.tabs[e];
-        if (ent & 1) continue;
-        const int k = ent >> 2, side = (ent >> 1) & 1;
-        const int c = J[k].type ? 5 : 3;
-        const double *Lsrc = a.gl + (int64_t)GL_STRIDE * k + (side ? GL_LB : GL_LA);
-        double *gtk = a.gt + (int64_t)GT_STRIDE * k;
-        for (int i = ln; i < c * 12; i += TEAM) S.L[i] = Lsrc[i];
-        for (int i = ln; i < c * c; i += TEAM) S.M[i] = gtk[GT_SIG + (i / c) * 5 + (i % c)];
-        team_sync();
-        // y = L w + rho ; Z = L T_k
-        if (ln < c) {
-          double v = gtk[GT_RHO + ln];
-          for (int s = 0; s < 12; ++s) v += S.L[ln * 12 + s] * S.w[s];
-          S.y[ln] = v;
-        }
-        for (int i = ln; i < c * ck; i += TEAM) {
-          const int r = i / ck, f = i % ck;
-          double v = 0.0;
-          for (int s = 0; s < 12; ++s) v += S.L[r * 12 + s] * S.Tk[s * 5 + f];
-          S.Z[r * 5 + f] = v;
-        }
-        team_sync();
+      team_sync();
+      // 4) partial Cholesky over the ne absorbed rows (lower triangle, in place)
+      for (int p = 0; p < ne; ++p) {
         if (ln == 0) {
-          if (!spd_inverse(c, S.M, S.Mi)) {
+          double d = Km[p * nr + p];
+          if (!(d > 0.0)) {
             raise_flag(a.status, FLAG_SINGULAR, a.step);
-            for (int i = 0; i < c * c; ++i) S.Mi[i] = 0.0;
+            d = 1.0;
           }
+          d = sqrt(d);
+          Km[p * nr + p] = d;
+          ym[p] /= d;
         }
         team_sync();
-        if (ln < c) {
-          double v = 0.0;
-          for (int d = 0; d < c; ++d) v += S.Mi[ln * c + d] * S.y[d];
-          gtk[GT_A + ln] = v;
-        }
-        for (int i = ln; i < c * 5; i += TEAM) {
-          const int r = i / 5, f = i % 5;
-          double v = 0.0;
-          if (f < ck)
-            for (int d = 0; d < c; ++d) v += S.Mi[r * c + d] * S.Z[d * 5 + f];
-          gtk[GT_E + i] = v;
+        const double d = Km[p * nr + p];
+        for (int i = p + 1 + ln; i < nr; i += TEAM) Km[i * nr + p] /= d;
+        team_sync();
+        for (int i = p + 1 + ln; i < nr; i += TEAM) {
+          const double lip = Km[i * nr + p];
+          for (int jj = p + 1; jj <= i; ++jj) Km[i * nr + jj] -= lip * Km[jj * nr + p];
+          ym[i] -= lip * ym[p];
         }
         team_sync();
       }
+      // 5) Schur complement on the parent joint; factor to the body's slot
+      if (kpar >= 0) {
+        double *gtk = a.gt + (int64_t)GT_STRIDE * kpar;
+        for (int idx = ln; idx < 25; idx += TEAM) {
+          const int i = idx / 5, jj = idx % 5;
+          double v = 0.0;
+          if (i < ck && jj < ck) v = jj <= i ? Km[(ne + i) * nr + ne + jj] : Km[(ne + jj) * nr + ne + i];
+          gtk[GT_SIG + idx] = v;
+        }
+        if (ln < 5) gtk[GT_RHO + ln] = ln < ck ? ym[ne + ln] : 0.0;
+      }
+      if (!big) {
+        for (int idx = ln; idx < nr * nr; idx += TEAM) fac[idx] = Km[idx];
+        for (int i = ln; i < nr; i += TEAM) fac[nr * nr + i] = ym[i];
+      }
+      team_sync();
     }
     __syncthreads();
   }
 }
 
+// root to leaf: lambda_e = Lc^{-T} (z - X lambda_k), one thread per body
 __global__ __launch_bounds__(256) void tree_backward_kernel(TreeArgs a, const GJoint *J) {
   if (skip_step(a.status, a.step)) return;
   const int l0 = a.comp_lvl[blockIdx.x], l1 = a.comp_lvl[blockIdx.x + 1];
@@ -531,17 +366,32 @@ __global__ __launch_bounds__(256) void tree_backward_kernel(TreeArgs a, const GJ
       const int pk = a.tpk[slot];
       const int kpar = pk >= 0 ? (pk >> 1) : -1;
       const int ck = kpar >= 0 ? (J[kpar].type ? 5 : 3) : 0;
+      const int ne = a.tne[slot];
+      const int nr = ne + ck;
+      if (ne == 0) continue;
+      const double *K = a.fac + a.foff[slot];
+      const double *y = K + nr * nr;
       double lk[5] = {0, 0, 0, 0, 0};
       for (int i = 0; i < ck; ++i) lk[i] = a.glam[5 * (int64_t)kpar + i];
+      // t = z - X lambda_k, X^T stored in rows ne.. of the factor
+      double t[TREE_KMAX];
+      for (int i = 0; i < ne; ++i) {
+        double v = y[i];
+        for (int f = 0; f < ck; ++f) v -= K[(ne + f) * nr + i] * lk[f];
+        t[i] = v;
+      }
+      for (int i = ne - 1; i >= 0; --i) {
+        double v = t[i];
+        for (int l = i + 1; l < ne; ++l) v -= K[l * nr + i] * t[l];
+        t[i] = v / K[i * nr + i];
+      }
+      int r0 = 0;
       for (int e = a.tabs_off[slot]; e < a.tabs_off[slot + 1]; ++e) {
         const int k = a.tabs[e] >> 2;
         const int c = J[k].type ? 5 : 3;
-        const double *gtk = a.gt + (int64_t)GT_STRIDE * k;
-        for (int r = 0; r < c; ++r) {
-          double v = gtk[GT_A + r];
-          for (int f = 0; f < ck; ++f) v -= gtk[GT_E + 5 * r + f] * lk[f];
-          a.glam[5 * (int64_t)k + r] = v;
-        }
+        for (int i = 0; i < c; ++i) a.glam[5 * (int64_t)k + i] = t[r0 + i];
+        for (int i = c; i < 5; ++i) a.glam[5 * (int64_t)k + i] = 0.0;
+        r0 += c;
       }
     }
     __syncthreads();

@@ -183,6 +183,7 @@ __global__ __launch_bounds__(PCG_THREADS) void pcg_kernel(PcgArgs a) {
     }
     for (int rr = 0; rr < 5; ++rr) {
       a.r[5 * (int64_t)k + rr] = rr < c ? bk[rr] : 0.0;
+      a.bv[5 * (int64_t)k + rr] = rr < c ? bk[rr] : 0.0;
       if (!a.warm) a.lam[5 * (int64_t)k + rr] = 0.0;
     }
   }
@@ -227,6 +228,7 @@ __global__ __launch_bounds__(PCG_THREADS) void pcg_kernel(PcgArgs a) {
   int it = 0;
   const double thresh = a.tol * bnorm;
   grid.sync();  // partials are rewritten below
+  for (int restart = 0; restart < 4; ++restart) {
   while (rnorm > thresh && it < a.max_iters) {
     body_pass(a, a.p, tid, nth);
     grid.sync();
@@ -287,6 +289,47 @@ __global__ __launch_bounds__(PCG_THREADS) void pcg_kernel(PcgArgs a) {
     }
     ++it;
     grid.sync();
+  }
+  // The recursively updated residual drifts from b - S lambda; test the true
+  // residual and, if it is above the tolerance, restart from it.
+  if (it >= a.max_iters) break;
+  body_pass(a, a.lam, tid, nth);
+  grid.sync();
+  double ptr = 0.0, ptz = 0.0;
+  for (int k = tid; k < a.mj; k += nth) {
+    if (!a.jmask[k]) continue;
+    const int c = jrows(a.J, k);
+    double y[5], rk[5], zk[5];
+    joint_pass_one(a, k, y);
+    for (int rr = 0; rr < 5; ++rr) rk[rr] = rr < c ? a.bv[5 * (int64_t)k + rr] - y[rr] : 0.0;
+    precond(a, k, rk, zk);
+    for (int rr = 0; rr < 5; ++rr) {
+      a.r[5 * (int64_t)k + rr] = rk[rr];
+      a.z[5 * (int64_t)k + rr] = zk[rr];
+      a.p[5 * (int64_t)k + rr] = zk[rr];
+      ptr += rk[rr] * rk[rr];
+      ptz += rk[rr] * zk[rr];
+    }
+  }
+  {
+    double s1 = block_sum(ptz, sh), s2 = block_sum(ptr, sh);
+    if (threadIdx.x == 0) {
+      a.partial[4 * blockIdx.x + 1] = s1;
+      a.partial[4 * blockIdx.x + 2] = s2;
+    }
+  }
+  grid.sync();
+  {
+    double rz2 = 0.0, rr2 = 0.0;
+    for (int blk = 0; blk < (int)gridDim.x; ++blk) {
+      rz2 += a.partial[4 * blk + 1];
+      rr2 += a.partial[4 * blk + 2];
+    }
+    rz = rz2;
+    rnorm = sqrt(rr2);
+  }
+  grid.sync();
+  if (rnorm <= thresh) break;
   }
   if (tid == 0) {
     *a.iters_out = it;

@@ -137,7 +137,12 @@ struct mabd_ctx {
   std::vector<int32_t> gj_in;
   int gb0 = 0, gb1 = 0;
   int ntree = 0, ngraph = 0;
-  std::vector<int32_t> comp_lvl, lvl_off, tbody, tpk, tabs_off, tabs, inc_off, inc;
+  std::vector<int32_t> comp_lvl, lvl_off, tbody, tpk, tabs_off, tabs, inc_off, inc, tne;
+  std::vector<int64_t> foff;
+  int64_t fac_size = 0;
+  int32_t *d_tne = nullptr;
+  int64_t *d_foff = nullptr;
+  double *d_fac = nullptr;
   // device
   std::vector<void *> allocs;
   double *d_q[2] = {nullptr, nullptr}, *d_qd[2] = {nullptr, nullptr};
@@ -157,6 +162,7 @@ struct mabd_ctx {
   // graph components (PCG)
   std::vector<int32_t> jmask, bmask;
   int32_t *d_jmask = nullptr, *d_bmask = nullptr;
+  double *d_pbv = nullptr;
   double *d_pr_ = nullptr, *d_pp = nullptr, *d_pz = nullptr, *d_psp = nullptr, *d_dinv = nullptr,
          *d_zb = nullptr, *d_partial = nullptr, *d_pcg_res = nullptr;
   int32_t *d_pcg_it = nullptr;
@@ -587,10 +593,17 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
           if (unary) unary_rows += Jn->type[k] ? 5 : 3;
           c->tabs.push_back(abs_pack(gidx[k], side, unary ? 1 : 0));
         }
-        if (unary_rows > MAX_UNARY_ROWS) {
+        int ne = 0;
+        for (int e = c->tabs_off.back(); e < (int)c->tabs.size(); ++e) ne += Jn->type[c->gj_in[c->tabs[e] >> 2]] ? 5 : 3;
+        const int nr = ne + (pk >= 0 ? (Jn->type[parent_joint[b]] ? 5 : 3) : 0);
+        if (nr > TREE_KMAX) {
           delete c;
-          return fail(nullptr, MABD_ERR_TOPOLOGY, "a tree body has more than 6 one-sided joint rows");
+          return fail(nullptr, MABD_ERR_TOPOLOGY, "a tree body has more than 64 joint rows around it");
         }
+        c->tne.push_back(ne);
+        c->foff.push_back(c->fac_size);
+        c->fac_size += (int64_t)nr * nr + nr + (nr > TREE_KLDS ? 24 * (int64_t)nr : 0);
+        (void)unary_rows;
       }
       c->lvl_off.push_back((int)c->tbody.size());
     }
@@ -774,6 +787,9 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(upload(c, &c->d_tpk, c->tpk));
   if (e == hipSuccess) chk(upload(c, &c->d_tabs_off, c->tabs_off));
   if (e == hipSuccess) chk(upload(c, &c->d_tabs, c->tabs));
+  if (e == hipSuccess) chk(upload(c, &c->d_tne, c->tne));
+  if (e == hipSuccess) chk(upload(c, &c->d_foff, c->foff));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_fac, (size_t)std::max<int64_t>(c->fac_size, 1)));
   if (e == hipSuccess) chk(upload(c, &c->d_inc_off, c->inc_off));
   if (e == hipSuccess) chk(upload(c, &c->d_inc, c->inc));
   if (e == hipSuccess) chk(upload(c, &c->d_sol2in, c->sol2in));
@@ -791,6 +807,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     if (e == hipSuccess) chk(dalloc(c, &c->d_pp, 5 * mg));
     if (e == hipSuccess) chk(dalloc(c, &c->d_pz, 5 * mg));
     if (e == hipSuccess) chk(dalloc(c, &c->d_psp, 5 * mg));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_pbv, 5 * mg));
     if (e == hipSuccess) chk(dalloc(c, &c->d_dinv, 25 * mg));
     if (e == hipSuccess) chk(dalloc(c, &c->d_zb, 12 * ns));
     if (e == hipSuccess) {
@@ -892,6 +909,9 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
         ta.glam = c->d_glam;
         ta.status = c->d_status;
         ta.step = st;
+        ta.tne = c->d_tne;
+        ta.foff = c->d_foff;
+        ta.fac = c->d_fac;
         tm.run(5, [&] { launch_tree(ta, c->d_gj, c->ntree, s); });
         if (c->ngraph > 0) {
           PcgArgs pa{};
@@ -913,6 +933,7 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
           pa.p = c->d_pp;
           pa.z = c->d_pz;
           pa.sp = c->d_psp;
+          pa.bv = c->d_pbv;
           pa.dinv = c->d_dinv;
           pa.zb = c->d_zb;
           pa.partial = c->d_partial;

@@ -28,7 +28,29 @@ def ctx_of(asm, **kw):
     return pk.Context(asm, **kw)
 
 
-def teacher_forced(asm, steps, solver=oracle.AUTO, tol=TOL, **kw):
+def reference_step(s, asm, q, qd, solver):
+    """Oracle step.  Trees use the direct dual solve (dense Cholesky, or SuperLU
+    when large): the primal condensation accumulates rounding with depth
+    (~1e-11 relative on 300 bodies against brute-force KKT LU), the dual solve
+    stays at ~5e-12."""
+    if solver == oracle.AUTO and s.classify() == 2:
+        if s.rows <= 4000:
+            return s.step(asm.h, q, qd, solver=oracle.DENSE)
+        if s.s.newton_iters == 1:
+            return s.step_sparse(asm.h, q, qd)
+    return s.step(asm.h, q, qd, solver=solver)
+
+
+# Trees of the tree workload mix 5 cm, 0.125 kg links with k_A = 1e8, so
+# kappa(Hbar) ~ 1e5 and multiplier rounding (the GPU and oracle multipliers
+# agree to ~1e-12 of their largest entry) reaches the velocities of light links
+# at ~2e-10 of the largest velocity.  Velocities of trees are held to 1e-9 and,
+# in addition, the oracle's FP64 KKT residual of the GPU multipliers must be
+# as small as that of its own solution.
+TOL_V_TREE = 1e-9
+
+
+def teacher_forced(asm, steps, solver=oracle.AUTO, tol=TOL, tol_v=None, **kw):
     """Both sides start every step from the oracle's state."""
     s = oracle.System(asm, **{k: v for k, v in kw.items() if k in ("material", "hinge_grad", "newton_iters")})
     ctx = ctx_of(asm, **kw)
@@ -39,14 +61,19 @@ def teacher_forced(asm, steps, solver=oracle.AUTO, tol=TOL, **kw):
         ctx.step(asm.h, 1)
         qg, qdg = ctx.state()
         lam_g = ctx.multipliers()
-        q1, qd1, lam, d = s.step(asm.h, q, qd, solver=solver)
+        q1, qd1, lam, d = reference_step(s, asm, q, qd, solver)
         eq, eqd = state_errors(qg, qdg, q1, qd1)
         # multipliers are forces (N): floor the scale at 1e-6 of the total weight,
         # since a freely falling assembly has lambda ~ 0 up to rounding
         wscale = 1e-6 * float((asm.density * asm.dims.prod(axis=1)).sum()) * 9.8
         el = rel_err(lam_g, lam, wscale) if asm.m else 0.0
         worst = tuple(max(a, b) for a, b in zip(worst, (eq, eqd, el)))
-        assert eq < tol and eqd < tol, (n, eq, eqd)
+        tv = tol if tol_v is None else tol_v
+        if tol_v is not None and asm.m:
+            _, _, dv = s.finish(asm.h, q, qd, lam_g) if s.s.newton_iters == 1 else (0, 0, d)
+            say("  kkt gpu", dv[:3], "oracle", d[:3])
+            assert dv[oracle.KKT] <= max(10 * d[oracle.KKT], 1e-11)
+        assert eq < tol and eqd < tv, (n, eq, eqd)
         assert el < 1e3 * tol, (n, el)
         q, qd = q1, qd1
     ctx.close()
@@ -138,13 +165,13 @@ def test_tree_and_hinge_paths():
     t = mi.tree(300, seed=5)
     t.qd0[1:] = np.random.default_rng(5).normal(0, 0.05, (299, 12))
     say("tree 300")
-    teacher_forced(t, 3)
+    say("worst", teacher_forced(t, 3, tol_v=TOL_V_TREE))
     h = mi.chain(200, seed=6, hinge_frac=0.5)
     say("hinge chain 200")
-    teacher_forced(h, 3)
+    say("worst", teacher_forced(h, 3))
     w = mi.tree(100, seed=7, window=3)
     say("tree frozen hinge gradient")
-    teacher_forced(w, 2, hinge_grad=2)
+    say("worst", teacher_forced(w, 2, hinge_grad=2, tol_v=TOL_V_TREE))
 
 
 def test_tree_with_world_joints_and_lame():
@@ -160,14 +187,14 @@ def test_tree_with_world_joints_and_lame():
     t.poisson = np.full(t.n, 0.3)
     t.k_orth[:] = 1e8
     say("tree with world joints, Lame material")
-    teacher_forced(t, 2)
+    say("worst", teacher_forced(t, 2, tol_v=TOL_V_TREE))
 
 
 def test_newton_iterations():
     t = mi.tree(60, seed=9)
     t.qd0[1:] = np.random.default_rng(9).normal(0, 0.5, (59, 12))
     say("tree newton 3")
-    teacher_forced(t, 2, newton_iters=3)
+    say("worst", teacher_forced(t, 2, newton_iters=3, tol_v=TOL_V_TREE))
 
 
 def test_multi_step_call_equals_single_steps():
@@ -251,7 +278,10 @@ def test_full_size_tree_one_step():
     ctx.step(asm.h, 1)
     qg, qdg = ctx.state()
     s = oracle.System(asm)
-    q1, qd1, lam, d = s.step(asm.h, asm.q0, asm.qd0)
+    q1, qd1, lam, d = s.step_sparse(asm.h, asm.q0, asm.qd0)
     eq, eqd = state_errors(qg, qdg, q1, qd1)
     say("errors", eq, eqd, "oracle kkt", d[:3])
-    assert eq < TOL and eqd < TOL
+    qv, qdv, dv = s.finish(asm.h, asm.q0, asm.qd0, ctx.multipliers())
+    say("kkt of GPU multipliers", dv[:3])
+    assert eq < TOL and eqd < TOL_V_TREE
+    assert dv[oracle.KKT] <= max(10 * d[oracle.KKT], 1e-11)
