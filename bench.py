@@ -41,6 +41,9 @@ def main():
     ap.add_argument("--workload", default="chain1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kkt-check", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
+                    help="only run a plain device-to-device copy of this many MB (5 times), "
+                         "to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -49,6 +52,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration_mb > 0:
+        n = int(args.copy_calibration_mb * (1 << 20)) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 8 * n, "launches": 5}), flush=True)
+        return
 
     import mabd_inputs as mi
     import paper_2603_08079_amd as pk

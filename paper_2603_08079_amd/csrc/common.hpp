@@ -24,9 +24,20 @@ struct ChainDesc {
   int32_t K;      // rows (joints), >= 2
   int32_t hl, hr; // one-sided joint at the start / end
   int32_t tile0;  // first tile
-  int32_t ntile;  // tiles; global reduced rows = ntile + 1
-  int32_t grow0;  // first global reduced row
-  int32_t pad;
+  int32_t ntile;  // tiles; interface rows = ntile + 1
+  int32_t grow0;  // first interface row (global index)
+  int32_t ngroup; // groups of interface rows; top rows = ngroup + 1
+  int32_t group0; // first group (global index; also its record index)
+  int32_t gtop0;  // first top row (global index)
+};
+
+// A group covers chain-local interface rows [g0, g0 + T] (T >= 1), reduced in
+// one workgroup like a tile.
+struct GroupDesc {
+  int32_t chain;
+  int32_t g0;
+  int32_t T;
+  int32_t gidx;   // group index inside its chain
 };
 
 // A tile covers chain-local rows [r0, r0 + T] (T >= 1).  Its rows r0 and r0+T
@@ -41,7 +52,8 @@ struct TileDesc {
 constexpr int CHAIN_TILE = 254;      // rows per tile - 1; a block has 256 threads
 constexpr int CHAIN_THREADS = 256;
 constexpr int TILE_REC = 27;         // doubles per tile record
-constexpr int GROW_REC = 56;         // doubles per global reduced row (scratch)
+constexpr int GROW_REC = 56;         // doubles per top-level row (scratch)
+constexpr int GROUP_T = 255;         // interface rows per group - 1
 
 // per-shape raw constants used by the force: Mbar0..2, m, V, mu, lambda
 constexpr int SHAPE_STRIDE = 8;

@@ -45,6 +45,119 @@ enum { S_WBB = 0, S_VB = 6, S_CB = 9, S_TB = 12, S_WAB = 15, S_N = 24 };
 // reuse for cyclic reduction: PL (9) PU (9) Pb (3) ; back-substitution: x (3)
 enum { S_PL = 0, S_PU = 9, S_PB = 18, S_X = 21 };
 
+// Block cyclic reduction of the rows 1..T-1 of a tile onto its interface
+// rows 0 and T.  Row li (held by one thread, `row_active`) couples to its
+// current left neighbour through L and to its right one through U.  At level
+// d the rows li = d mod 2d are eliminated: each publishes
+// (PL, PU, Pb) = D^{-1} (L, U, b) through LDS and keeps it for the
+// back-substitution; every surviving row folds in its eliminated neighbours.
+DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, double *L, double *D,
+                         double *U, double *b, double *PL, double *PU, double *Pb, int &elim_d,
+                         uint32_t *status, int step) {
+  for (int d = 1; d < T; d *= 2) {
+    const bool active = row_active && (li % d == 0 || li == T);
+    const bool elim = active && li < T && (li % (2 * d) == d);
+    if (elim) {
+      double Df[9], Di[9];
+      full_from_sym(D, Df);
+      if (!spd3_inv(Df, Di)) {
+        raise_flag(status, FLAG_SINGULAR, step);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Di[i] = 0.0;
+      }
+      mat3_mul(Di, L, PL);
+      mat3_mul(Di, U, PU);
+      mat3_vec(Di, b, Pb);
+      elim_d = d;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        lds[(S_PL + i) * CHAIN_THREADS + li] = PL[i];
+        lds[(S_PU + i) * CHAIN_THREADS + li] = PU[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) lds[(S_PB + i) * CHAIN_THREADS + li] = Pb[i];
+    }
+    __syncthreads();
+    if (active && !elim) {
+      const int e = li + d;
+      if (li != T && e < T) {
+        double Xl[9], Xu[9], xb[3], M[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          Xl[i] = lds[(S_PL + i) * CHAIN_THREADS + e];
+          Xu[i] = lds[(S_PU + i) * CHAIN_THREADS + e];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * CHAIN_THREADS + e];
+        mat3_mul(U, Xl, M);
+        double Ms[6];
+        sym_from_full(M, Ms);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) D[i] -= Ms[i];
+        double Ub[3];
+        mat3_vec(U, xb, Ub);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) b[i] -= Ub[i];
+        double Un[9];
+        mat3_mul(U, Xu, Un);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) U[i] = -Un[i];
+      }
+      const int lf = li == T ? d * ((T - 1) / d) : li - d;
+      if (li > 0 && lf > 0 && (lf % (2 * d) == d)) {
+        double Xl[9], Xu[9], xb[3], M[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          Xl[i] = lds[(S_PL + i) * CHAIN_THREADS + lf];
+          Xu[i] = lds[(S_PU + i) * CHAIN_THREADS + lf];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * CHAIN_THREADS + lf];
+        mat3_mul(L, Xu, M);
+        double Ms[6];
+        sym_from_full(M, Ms);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) D[i] -= Ms[i];
+        double Lb[3];
+        mat3_vec(L, xb, Lb);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) b[i] -= Lb[i];
+        double Ln[9];
+        mat3_mul(L, Xl, Ln);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) L[i] = -Ln[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Back-substitution of tile_cr_forward: x of rows 0 and T must already be in
+// LDS (S_X) and visible; on return every row's x is there.
+DEV void tile_cr_backward(double *lds, bool row_active, int li, int T, int elim_d,
+                          const double *PL, const double *PU, const double *Pb) {
+  int dmax = 0;
+  for (int d = 1; d < T; d *= 2) dmax = d;
+  for (int d = dmax; d >= 1; d /= 2) {
+    if (row_active && elim_d == d) {
+      const int lf = li - d;
+      const int rt = li + d < T ? li + d : T;
+      double xl[3], xr[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        xl[i] = lds[(S_X + i) * CHAIN_THREADS + lf];
+        xr[i] = lds[(S_X + i) * CHAIN_THREADS + rt];
+      }
+      double t1[3], t2[3];
+      mat3_vec(PL, xl, t1);
+      mat3_vec(PU, xr, t2);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) lds[(S_X + i) * CHAIN_THREADS + li] = Pb[i] - t1[i] - t2[i];
+    }
+    __syncthreads();
+  }
+}
+
 template <bool APPLY>
 __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) {
   __shared__ double lds[S_N * CHAIN_THREADS];
@@ -205,87 +318,9 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) 
   __syncthreads();
 
   // ---------------------------------------------------------------- phase C
-  // block cyclic reduction of rows 1..T-1 onto the interface rows 0 and T
   double PL[9], PU[9], Pb[3];
   int elim_d = 0;
-  for (int d = 1; d < T; d *= 2) {
-    const bool active = row_active && (li % d == 0 || li == T);
-    const bool elim = active && li < T && (li % (2 * d) == d);
-    if (elim) {
-      double Df[9], Di[9];
-      full_from_sym(D, Df);
-      if (!spd3_inv(Df, Di)) {
-        raise_flag(a.status, FLAG_SINGULAR, a.step);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) Di[i] = 0.0;
-      }
-      mat3_mul(Di, L, PL);
-      mat3_mul(Di, U, PU);
-      mat3_vec(Di, b, Pb);
-      elim_d = d;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        lds[(S_PL + i) * CHAIN_THREADS + li] = PL[i];
-        lds[(S_PU + i) * CHAIN_THREADS + li] = PU[i];
-      }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) lds[(S_PB + i) * CHAIN_THREADS + li] = Pb[i];
-    }
-    __syncthreads();
-    if (active && !elim) {
-      // right neighbour eliminated at this level?
-      const int e = li + d;
-      if (li != T && e < T) {
-        double Xl[9], Xu[9], xb[3], M[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          Xl[i] = lds[(S_PL + i) * CHAIN_THREADS + e];
-          Xu[i] = lds[(S_PU + i) * CHAIN_THREADS + e];
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * CHAIN_THREADS + e];
-        mat3_mul(U, Xl, M);
-        double Ms[6];
-        sym_from_full(M, Ms);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) D[i] -= Ms[i];
-        double Ub[3];
-        mat3_vec(U, xb, Ub);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) b[i] -= Ub[i];
-        double Un[9];
-        mat3_mul(U, Xu, Un);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) U[i] = -Un[i];
-      }
-      // left neighbour eliminated at this level?
-      int lf = li == T ? d * ((T - 1) / d) : li - d;
-      if (li > 0 && lf > 0 && (lf % (2 * d) == d)) {
-        double Xl[9], Xu[9], xb[3], M[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          Xl[i] = lds[(S_PL + i) * CHAIN_THREADS + lf];
-          Xu[i] = lds[(S_PU + i) * CHAIN_THREADS + lf];
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * CHAIN_THREADS + lf];
-        mat3_mul(L, Xu, M);
-        double Ms[6];
-        sym_from_full(M, Ms);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) D[i] -= Ms[i];
-        double Lb[3];
-        mat3_vec(L, xb, Lb);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) b[i] -= Lb[i];
-        double Ln[9];
-        mat3_mul(L, Xl, Ln);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) L[i] = -Ln[i];
-      }
-    }
-    __syncthreads();
-  }
+  tile_cr_forward(lds, row_active, li, T, L, D, U, b, PL, PU, Pb, elim_d, a.status, a.step);
 
   if constexpr (!APPLY) {
     double *rec = a.tilerec + (int64_t)TILE_REC * blockIdx.x;
@@ -310,30 +345,8 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) 
 #pragma unroll
       for (int i = 0; i < 3; ++i) lds[(S_X + i) * CHAIN_THREADS + li] = a.xg[3 * gi + i];
     }
-    int dmax = 0;
-    for (int d = 1; d < T; d *= 2) dmax = d;
     __syncthreads();
-    for (int d = dmax; d >= 1; d /= 2) {
-      if (row_active && elim_d == d) {
-        const int lf = li - d;
-        const int rt = li + d < T ? li + d : T;
-        double xl[3], xr[3], x[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          xl[i] = lds[(S_X + i) * CHAIN_THREADS + lf];
-          xr[i] = lds[(S_X + i) * CHAIN_THREADS + rt];
-        }
-        double t1[3], t2[3];
-        mat3_vec(PL, xl, t1);
-        mat3_vec(PU, xr, t2);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          x[i] = Pb[i] - t1[i] - t2[i];
-          lds[(S_X + i) * CHAIN_THREADS + li] = x[i];
-        }
-      }
-      __syncthreads();
-    }
+    tile_cr_backward(lds, row_active, li, T, elim_d, PL, PU, Pb);
     // multipliers of the tile's rows (interface row T is written by the next tile)
     const bool last_tile = td.tidx == cd.ntile - 1;
     if (row_active && (li < T || last_tile)) {
@@ -396,6 +409,74 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) 
   }
 }
 
+// Interface rows of one chain form again a block-tridiagonal system: row gi
+// gathers D and b from the two tiles that share it and couples to row gi+1
+// through the tile's Schur block U.  Groups of GROUP_T + 1 interface rows are
+// reduced like tiles (reduce variant: Schur record of the group's two end
+// rows) and back-substituted once the top system is solved (apply variant:
+// x of every interface row).
+template <bool APPLY>
+__global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
+    const ChainDesc *chains, const GroupDesc *groups, const double *tilerec, double *grouprec,
+    const double *xtop, double *xg, uint32_t *status, int step) {
+  __shared__ double lds[S_N * CHAIN_THREADS];
+  if (skip_step(status, step)) return;
+  const GroupDesc gd = groups[blockIdx.x];
+  const ChainDesc cd = chains[gd.chain];
+  const int li = threadIdx.x;
+  const int T = gd.T;
+  const int gi = gd.g0 + li;               // chain-local interface row
+  const int n = cd.ntile + 1;
+  const bool row_active = li <= T;
+  const double *TR = tilerec + (int64_t)TILE_REC * cd.tile0;
+  double L[9], D[6], U[9], b[3];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) { L[i] = 0.0; U[i] = 0.0; }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) D[i] = 0.0;
+  b[0] = b[1] = b[2] = 0.0;
+  if (row_active && !(li == T && gi != n - 1)) {
+    if (gi < cd.ntile) {
+      for (int i = 0; i < 6; ++i) D[i] += TR[TILE_REC * gi + i];
+      for (int i = 0; i < 3; ++i) b[i] += TR[TILE_REC * gi + 6 + i];
+    }
+    if (gi > 0) {
+      for (int i = 0; i < 6; ++i) D[i] += TR[TILE_REC * (gi - 1) + 9 + i];
+      for (int i = 0; i < 3; ++i) b[i] += TR[TILE_REC * (gi - 1) + 15 + i];
+    }
+  }
+  if (row_active && li < T)
+    for (int i = 0; i < 9; ++i) U[i] = TR[TILE_REC * gi + 18 + i];
+  if (row_active && li > 0)
+    for (int r2 = 0; r2 < 3; ++r2)
+      for (int c2 = 0; c2 < 3; ++c2) L[3 * r2 + c2] = TR[TILE_REC * (gi - 1) + 18 + 3 * c2 + r2];
+  double PL[9], PU[9], Pb[3];
+  int elim_d = 0;
+  tile_cr_forward(lds, row_active, li, T, L, D, U, b, PL, PU, Pb, elim_d, status, step);
+  if constexpr (!APPLY) {
+    double *rec = grouprec + (int64_t)TILE_REC * (cd.group0 + gd.gidx);
+    if (row_active && li == 0) {
+      for (int i = 0; i < 6; ++i) rec[i] = D[i];
+      for (int i = 0; i < 3; ++i) rec[6 + i] = b[i];
+      for (int i = 0; i < 9; ++i) rec[18 + i] = U[i];
+    }
+    if (row_active && li == T) {
+      for (int i = 0; i < 6; ++i) rec[9 + i] = D[i];
+      for (int i = 0; i < 3; ++i) rec[15 + i] = b[i];
+    }
+  } else {
+    if (row_active && (li == 0 || li == T)) {
+      const int64_t ti = (int64_t)cd.gtop0 + gd.gidx + (li == T ? 1 : 0);
+      for (int i = 0; i < 3; ++i) lds[(S_X + i) * CHAIN_THREADS + li] = xtop[3 * ti + i];
+    }
+    __syncthreads();
+    tile_cr_backward(lds, row_active, li, T, elim_d, PL, PU, Pb);
+    const bool last = gd.gidx == cd.ngroup - 1;
+    if (row_active && (li < T || last))
+      for (int i = 0; i < 3; ++i) xg[3 * ((int64_t)cd.grow0 + gi) + i] = lds[(S_X + i) * CHAIN_THREADS + li];
+  }
+}
+
 // Interface system of each chain: rows gi = 0..ntile, block tridiagonal,
 // solved by block cyclic reduction in global scratch (one workgroup per chain).
 __global__ __launch_bounds__(1024) void chain_global_kernel(const ChainDesc *chains,
@@ -403,15 +484,16 @@ __global__ __launch_bounds__(1024) void chain_global_kernel(const ChainDesc *cha
                                                            double *xg, uint32_t *status, int step) {
   if (skip_step(status, step)) return;
   const ChainDesc cd = chains[blockIdx.x];
-  const int n = cd.ntile + 1;
-  double *S = scr + (int64_t)GROW_REC * cd.grow0;
-  const double *TR = tilerec + (int64_t)TILE_REC * cd.tile0;
+  // top system: the rows that bound the groups (records in tilerec = group records)
+  const int n = cd.ngroup + 1;
+  double *S = scr + (int64_t)GROW_REC * cd.gtop0;
+  const double *TR = tilerec + (int64_t)TILE_REC * cd.group0;
   // record: L 0..8, D 9..17, U 18..26, b 27..29, PL 30..38, PU 39..47, Pb 48..50
   enum { GL = 0, GD = 9, GU = 18, GB = 27, GPL = 30, GPU = 39, GPB = 48 };
   for (int gi = threadIdx.x; gi < n; gi += blockDim.x) {
     double *row = S + (int64_t)GROW_REC * gi;
     double Ds[6] = {0, 0, 0, 0, 0, 0}, bb[3] = {0, 0, 0};
-    if (gi < cd.ntile) {
+    if (gi < cd.ngroup) {
       for (int i = 0; i < 6; ++i) Ds[i] += TR[TILE_REC * gi + i];
       for (int i = 0; i < 3; ++i) bb[i] += TR[TILE_REC * gi + 6 + i];
     }
@@ -424,7 +506,7 @@ __global__ __launch_bounds__(1024) void chain_global_kernel(const ChainDesc *cha
     for (int i = 0; i < 9; ++i) row[GD + i] = Df[i];
     for (int i = 0; i < 3; ++i) row[GB + i] = bb[i];
     for (int i = 0; i < 9; ++i) {
-      row[GU + i] = gi < cd.ntile ? TR[TILE_REC * gi + 18 + i] : 0.0;
+      row[GU + i] = gi < cd.ngroup ? TR[TILE_REC * gi + 18 + i] : 0.0;
       int r2 = i / 3, c2 = i % 3;
       row[GL + i] = gi > 0 ? TR[TILE_REC * (gi - 1) + 18 + 3 * c2 + r2] : 0.0;
     }
@@ -490,7 +572,7 @@ __global__ __launch_bounds__(1024) void chain_global_kernel(const ChainDesc *cha
     }
     __syncthreads();
   }
-  double *X = xg + 3 * (int64_t)cd.grow0;
+  double *X = xg + 3 * (int64_t)cd.gtop0;
   if (threadIdx.x == 0) {
     double Dm[9], Di[9], bv[3], x[3];
     for (int i = 0; i < 9; ++i) Dm[i] = S[GD + i];
@@ -527,6 +609,17 @@ void launch_chain_reduce(const ChainArgs &a, int ntiles, hipStream_t s) {
 void launch_chain_apply(const ChainArgs &a, int ntiles, hipStream_t s) {
   if (ntiles > 0)
     hipLaunchKernelGGL(chain_tile_kernel<true>, dim3(ntiles), dim3(CHAIN_THREADS), 0, s, a);
+}
+void launch_chain_group(bool apply, const ChainDesc *chains, const GroupDesc *groups, int ngroups,
+                        const double *tilerec, double *grouprec, const double *xtop, double *xg,
+                        uint32_t *status, int step, hipStream_t s) {
+  if (ngroups <= 0) return;
+  if (apply)
+    hipLaunchKernelGGL(chain_group_kernel<true>, dim3(ngroups), dim3(CHAIN_THREADS), 0, s, chains,
+                       groups, tilerec, grouprec, xtop, xg, status, step);
+  else
+    hipLaunchKernelGGL(chain_group_kernel<false>, dim3(ngroups), dim3(CHAIN_THREADS), 0, s, chains,
+                       groups, tilerec, grouprec, xtop, xg, status, step);
 }
 void launch_chain_global(const ChainDesc *chains, int nchains, const double *tilerec, double *scr,
                          double *xg, uint32_t *status, int step, hipStream_t s) {

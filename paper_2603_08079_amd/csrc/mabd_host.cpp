@@ -24,6 +24,9 @@ void launch_chain_reduce(const ChainArgs &a, int ntiles, hipStream_t s);
 void launch_chain_apply(const ChainArgs &a, int ntiles, hipStream_t s);
 void launch_chain_global(const ChainDesc *chains, int nchains, const double *tilerec, double *scr,
                          double *xg, uint32_t *status, int step, hipStream_t s);
+void launch_chain_group(bool apply, const ChainDesc *chains, const GroupDesc *groups, int ngroups,
+                        const double *tilerec, double *grouprec, const double *xtop, double *xg,
+                        uint32_t *status, int step, hipStream_t s);
 void launch_prefactor(const double *shape, int nshape, double h, double *hinv, hipStream_t s);
 void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
                   const int32_t *shp, const double *hinv, const double *shape, const double *g,
@@ -130,7 +133,8 @@ struct mabd_ctx {
   // chains
   std::vector<ChainDesc> chains;
   std::vector<TileDesc> tiles;
-  int nchain_rows = 0, nchain_bodies = 0, ngrows = 0;
+  std::vector<GroupDesc> groups;
+  int nchain_rows = 0, nchain_bodies = 0, ngrows = 0, ntop = 0;
   std::vector<int32_t> crow_joint;  // chain row -> input joint
   // generic
   std::vector<GJoint> gj;
@@ -151,6 +155,8 @@ struct mabd_ctx {
   double *d_shape = nullptr, *d_hinv = nullptr;
   ChainDesc *d_chains = nullptr;
   TileDesc *d_tiles = nullptr;
+  GroupDesc *d_groups = nullptr;
+  double *d_grouprec = nullptr, *d_xtop = nullptr;
   double *d_pl = nullptr, *d_pr = nullptr;
   uint8_t *d_flag = nullptr;
   double *d_tilerec = nullptr, *d_grow = nullptr, *d_xg = nullptr, *d_clam = nullptr;
@@ -518,6 +524,18 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       c->tiles.push_back(td);
     }
     c->ngrows += cd.ntile + 1;
+    cd.ngroup = (cd.ntile + GROUP_T - 1) / GROUP_T;  // interface rows - 1 = ntile
+    cd.group0 = (int)c->groups.size();
+    cd.gtop0 = c->ntop;
+    for (int g2 = 0; g2 < cd.ngroup; ++g2) {
+      GroupDesc gd{};
+      gd.chain = (int)c->chains.size();
+      gd.g0 = g2 * GROUP_T;
+      gd.T = std::min(GROUP_T, cd.ntile - gd.g0);
+      gd.gidx = g2;
+      c->groups.push_back(gd);
+    }
+    c->ntop += cd.ngroup + 1;
     c->nchain_rows += K;
     c->chains.push_back(cd);
   }
@@ -771,7 +789,10 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     if (e == hipSuccess) chk(upload(c, &c->d_flag, cflag));
   }
   if (e == hipSuccess) chk(dalloc(c, &c->d_tilerec, (size_t)TILE_REC * c->tiles.size()));
-  if (e == hipSuccess) chk(dalloc(c, &c->d_grow, (size_t)GROW_REC * c->ngrows));
+  if (e == hipSuccess) chk(upload(c, &c->d_groups, c->groups));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_grouprec, (size_t)TILE_REC * c->groups.size()));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_xtop, (size_t)3 * c->ntop));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_grow, (size_t)GROW_REC * c->ntop));
   if (e == hipSuccess) chk(dalloc(c, &c->d_xg, (size_t)3 * c->ngrows));
   if (e == hipSuccess) chk(dalloc(c, &c->d_clam, (size_t)3 * nrs));
   if (e == hipSuccess) chk(upload(c, &c->d_gj, c->gj));
@@ -878,8 +899,12 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
       ca.step = st;
       tm.run(0, [&] { launch_chain_reduce(ca, (int)c->tiles.size(), s); });
       tm.run(1, [&] {
-        launch_chain_global(c->d_chains, (int)c->chains.size(), c->d_tilerec, c->d_grow, c->d_xg,
+        launch_chain_group(false, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
+                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_status, st, s);
+        launch_chain_global(c->d_chains, (int)c->chains.size(), c->d_grouprec, c->d_grow, c->d_xtop,
                             c->d_status, st, s);
+        launch_chain_group(true, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
+                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_status, st, s);
       });
       tm.run(2, [&] { launch_chain_apply(ca, (int)c->tiles.size(), s); });
     }
