@@ -41,6 +41,8 @@ def main():
     ap.add_argument("--workload", default="chain1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kkt-check", action="store_true")
+    ap.add_argument("--kkt-tol", type=float, default=1e-10, help="PCG stopping tolerance")
+    ap.add_argument("--max-iters", type=int, default=200000, help="PCG iteration cap")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many MB (5 times), "
                          "to calibrate HBM byte counters")
@@ -71,20 +73,30 @@ def main():
     stream = torch.cuda.current_stream()
     asm = mi.config(args.workload)
     h = asm.h
-    ctx = pk.Context(asm, stream=stream.cuda_stream, diagnostics=2)
+    ctx = pk.Context(asm, stream=stream.cuda_stream, diagnostics=2, kkt_tol=args.kkt_tol,
+                     max_iters=args.max_iters)
     st0 = ctx.stats()
     n_dyn = st0["n_dyn"]
     print(f"# workload {args.workload}: {asm.n} bodies ({n_dyn} dynamic), {asm.m} joints, "
           f"chains {st0['n_chain']} trees {st0['n_tree']} graphs {st0['n_graph']}",
           file=sys.stderr, flush=True)
+    def run(nsteps):
+        try:
+            ctx.step(h, nsteps)
+            return None
+        except pk.MabdError as e:  # PCG stopped at its iteration cap: report, do not hide
+            if e.status != pk.ERR_NOT_CONVERGED:
+                raise
+            return str(e)
+
     if args.warmup:
-        ctx.step(h, args.warmup)
+        run(args.warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     t0 = time.perf_counter()
-    ctx.step(h, args.steps)
+    notconv = run(args.steps)
     e1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -145,6 +157,10 @@ def main():
                    "joints": asm.m, "h": h, "newton_iters": 1, "form": "plain FP64"},
         "kkt": kkt, "roofline": roof, "cpu_baseline": cpu,
     }
+    if st["n_graph"]:
+        out["pcg"] = {"iters_last_step": st["pcg_iters"], "rel_residual_last_step": st["rho_d"],
+                      "kkt_tol": args.kkt_tol, "max_iters": args.max_iters,
+                      "not_converged": notconv}
     print(json.dumps(out), flush=True)
 
 

@@ -3,9 +3,9 @@
 // back-projection (Eq. recover-dq-explicit).
 //
 // The dual system of a chain is block tridiagonal with 3x3 blocks.  Instead
-// of the serial block Thomas sweep the rows are cut into tiles of
-// CHAIN_TILE + 1 rows that share their first/last (interface) rows with the
-// neighbouring tiles.  One workgroup per tile
+// of the serial block Thomas sweep the rows are cut into tiles of T + 1 rows
+// (T = workgroup size - 2) that share their first/last (interface) rows with
+// the neighbouring tiles.  One workgroup per tile
 //   A) computes the polar rotation, force and local solve of its bodies
 //      (one body per thread, coalesced SoA loads) and the rotated constant
 //      blocks R W(p, p') R^T with W = J(p) Hbar^{-1} J(p')^T;
@@ -51,6 +51,7 @@ enum { S_PL = 0, S_PU = 9, S_PB = 18, S_X = 21 };
 // d the rows li = d mod 2d are eliminated: each publishes
 // (PL, PU, Pb) = D^{-1} (L, U, b) through LDS and keeps it for the
 // back-substitution; every surviving row folds in its eliminated neighbours.
+template <int NT>
 DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, double *L, double *D,
                          double *U, double *b, double *PL, double *PU, double *Pb, int &elim_d,
                          uint32_t *status, int step) {
@@ -71,11 +72,11 @@ DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, double *L,
       elim_d = d;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        lds[(S_PL + i) * CHAIN_THREADS + li] = PL[i];
-        lds[(S_PU + i) * CHAIN_THREADS + li] = PU[i];
+        lds[(S_PL + i) * NT + li] = PL[i];
+        lds[(S_PU + i) * NT + li] = PU[i];
       }
 #pragma unroll
-      for (int i = 0; i < 3; ++i) lds[(S_PB + i) * CHAIN_THREADS + li] = Pb[i];
+      for (int i = 0; i < 3; ++i) lds[(S_PB + i) * NT + li] = Pb[i];
     }
     __syncthreads();
     if (active && !elim) {
@@ -84,11 +85,11 @@ DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, double *L,
         double Xl[9], Xu[9], xb[3], M[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-          Xl[i] = lds[(S_PL + i) * CHAIN_THREADS + e];
-          Xu[i] = lds[(S_PU + i) * CHAIN_THREADS + e];
+          Xl[i] = lds[(S_PL + i) * NT + e];
+          Xu[i] = lds[(S_PU + i) * NT + e];
         }
 #pragma unroll
-        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * CHAIN_THREADS + e];
+        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * NT + e];
         mat3_mul(U, Xl, M);
         double Ms[6];
         sym_from_full(M, Ms);
@@ -108,11 +109,11 @@ DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, double *L,
         double Xl[9], Xu[9], xb[3], M[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-          Xl[i] = lds[(S_PL + i) * CHAIN_THREADS + lf];
-          Xu[i] = lds[(S_PU + i) * CHAIN_THREADS + lf];
+          Xl[i] = lds[(S_PL + i) * NT + lf];
+          Xu[i] = lds[(S_PU + i) * NT + lf];
         }
 #pragma unroll
-        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * CHAIN_THREADS + lf];
+        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * NT + lf];
         mat3_mul(L, Xu, M);
         double Ms[6];
         sym_from_full(M, Ms);
@@ -134,6 +135,7 @@ DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, double *L,
 
 // Back-substitution of tile_cr_forward: x of rows 0 and T must already be in
 // LDS (S_X) and visible; on return every row's x is there.
+template <int NT>
 DEV void tile_cr_backward(double *lds, bool row_active, int li, int T, int elim_d,
                           const double *PL, const double *PU, const double *Pb) {
   int dmax = 0;
@@ -145,22 +147,22 @@ DEV void tile_cr_backward(double *lds, bool row_active, int li, int T, int elim_
       double xl[3], xr[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        xl[i] = lds[(S_X + i) * CHAIN_THREADS + lf];
-        xr[i] = lds[(S_X + i) * CHAIN_THREADS + rt];
+        xl[i] = lds[(S_X + i) * NT + lf];
+        xr[i] = lds[(S_X + i) * NT + rt];
       }
       double t1[3], t2[3];
       mat3_vec(PL, xl, t1);
       mat3_vec(PU, xr, t2);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) lds[(S_X + i) * CHAIN_THREADS + li] = Pb[i] - t1[i] - t2[i];
+      for (int i = 0; i < 3; ++i) lds[(S_X + i) * NT + li] = Pb[i] - t1[i] - t2[i];
     }
     __syncthreads();
   }
 }
 
-template <bool APPLY>
-__global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) {
-  __shared__ double lds[S_N * CHAIN_THREADS];
+template <bool APPLY, int NT>
+__global__ __launch_bounds__(NT) void chain_tile_kernel(ChainArgs a) {
+  __shared__ double lds[S_N * NT];
   if (skip_step(a.status, a.step)) return;
   const TileDesc td = a.tiles[blockIdx.x];
   const ChainDesc cd = a.chains[td.chain];
@@ -265,15 +267,15 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) 
   }
   // publish the part that belongs to row r+1 (left end of that row)
 #pragma unroll
-  for (int i = 0; i < 6; ++i) lds[(S_WBB + i) * CHAIN_THREADS + t] = Wbb[i];
+  for (int i = 0; i < 6; ++i) lds[(S_WBB + i) * NT + t] = Wbb[i];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    lds[(S_VB + i) * CHAIN_THREADS + t] = vb[i];
-    lds[(S_CB + i) * CHAIN_THREADS + t] = cb[i];
-    lds[(S_TB + i) * CHAIN_THREADS + t] = tb[i];
+    lds[(S_VB + i) * NT + t] = vb[i];
+    lds[(S_CB + i) * NT + t] = cb[i];
+    lds[(S_TB + i) * NT + t] = tb[i];
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) lds[(S_WAB + i) * CHAIN_THREADS + t] = Wab[i];
+  for (int i = 0; i < 9; ++i) lds[(S_WAB + i) * NT + t] = Wab[i];
   __syncthreads();
 
   // ---------------------------------------------------------------- phase B
@@ -285,20 +287,20 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) 
   if (row_active) {
     const int tp = t - 1;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) D[i] = Waa[i] + lds[(S_WBB + i) * CHAIN_THREADS + tp];
+    for (int i = 0; i < 6; ++i) D[i] = Waa[i] + lds[(S_WBB + i) * NT + tp];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       // C = (translation difference) + (rotated anchor difference)
-      double C = (lds[(S_TB + i) * CHAIN_THREADS + tp] + ta[i]) +
-                 (lds[(S_CB + i) * CHAIN_THREADS + tp] + ca[i]);
-      b[i] = va[i] + lds[(S_VB + i) * CHAIN_THREADS + tp] + C;
+      double C = (lds[(S_TB + i) * NT + tp] + ta[i]) +
+                 (lds[(S_CB + i) * NT + tp] + ca[i]);
+      b[i] = va[i] + lds[(S_VB + i) * NT + tp] + C;
     }
     // left coupling = (U of the previous row)^T
     if (li >= 1) {
 #pragma unroll
       for (int r2 = 0; r2 < 3; ++r2)
 #pragma unroll
-        for (int c2 = 0; c2 < 3; ++c2) L[3 * r2 + c2] = lds[(S_WAB + 3 * c2 + r2) * CHAIN_THREADS + tp];
+        for (int c2 = 0; c2 < 3; ++c2) L[3 * r2 + c2] = lds[(S_WAB + 3 * c2 + r2) * NT + tp];
     }
     if (li == T && r != cd.K - 1) {
       // interface row owned by the next tile: only Schur updates are summed here
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) 
   // ---------------------------------------------------------------- phase C
   double PL[9], PU[9], Pb[3];
   int elim_d = 0;
-  tile_cr_forward(lds, row_active, li, T, L, D, U, b, PL, PU, Pb, elim_d, a.status, a.step);
+  tile_cr_forward<NT>(lds, row_active, li, T, L, D, U, b, PL, PU, Pb, elim_d, a.status, a.step);
 
   if constexpr (!APPLY) {
     double *rec = a.tilerec + (int64_t)TILE_REC * blockIdx.x;
@@ -343,15 +345,15 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) 
     if (row_active && (li == 0 || li == T)) {
       const int64_t gi = (int64_t)cd.grow0 + td.tidx + (li == T ? 1 : 0);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) lds[(S_X + i) * CHAIN_THREADS + li] = a.xg[3 * gi + i];
+      for (int i = 0; i < 3; ++i) lds[(S_X + i) * NT + li] = a.xg[3 * gi + i];
     }
     __syncthreads();
-    tile_cr_backward(lds, row_active, li, T, elim_d, PL, PU, Pb);
+    tile_cr_backward<NT>(lds, row_active, li, T, elim_d, PL, PU, Pb);
     // multipliers of the tile's rows (interface row T is written by the next tile)
     const bool last_tile = td.tidx == cd.ntile - 1;
     if (row_active && (li < T || last_tile)) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) a.lam[3 * gra + i] = lds[(S_X + i) * CHAIN_THREADS + li];
+      for (int i = 0; i < 3; ++i) a.lam[3 * gra + i] = lds[(S_X + i) * NT + li];
     }
     // -------------------------------------------------- body back-projection
     bool own = has_body && ((t >= 1 && t <= T) || (t == 0 && td.tidx == 0) ||
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) 
       if (has_a) {  // row r is local row t-1
         double lamv[3], w[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) lamv[i] = lds[(S_X + i) * CHAIN_THREADS + (t - 1)];
+        for (int i = 0; i < 3; ++i) lamv[i] = lds[(S_X + i) * NT + (t - 1)];
         mat3t_vec(R, lamv, w);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -377,7 +379,7 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) 
       if (has_b) {  // row r+1 is local row t
         double lamv[3], w[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) lamv[i] = lds[(S_X + i) * CHAIN_THREADS + t];
+        for (int i = 0; i < 3; ++i) lamv[i] = lds[(S_X + i) * NT + t];
         mat3t_vec(R, lamv, w);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -409,6 +411,106 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) 
   }
 }
 
+// Top system of a chain (rows that bound its groups), n = ngroup + 1 <= 256
+// rows, one per thread: cyclic reduction onto rows 0 and n-1, a 6x6 Cholesky
+// solve of those two, back-substitution.  Called by one whole workgroup.
+DEV void top_solve(double *lds, const ChainDesc &cd, const double *grouprec, double *xtop,
+                   uint32_t *status, int step) {
+  const int n = cd.ngroup + 1;
+  const int T = n - 1;
+  const int li = threadIdx.x;
+  const bool row_active = li < n;
+  const double *TR = grouprec + (int64_t)TILE_REC * cd.group0;
+  double L[9], D[6], U[9], b[3];
+  for (int i = 0; i < 9; ++i) { L[i] = 0.0; U[i] = 0.0; }
+  for (int i = 0; i < 6; ++i) D[i] = 0.0;
+  b[0] = b[1] = b[2] = 0.0;
+  if (row_active) {
+    if (li < cd.ngroup) {
+      for (int i = 0; i < 6; ++i) D[i] += TR[TILE_REC * li + i];
+      for (int i = 0; i < 3; ++i) b[i] += TR[TILE_REC * li + 6 + i];
+      for (int i = 0; i < 9; ++i) U[i] = TR[TILE_REC * li + 18 + i];
+    }
+    if (li > 0) {
+      for (int i = 0; i < 6; ++i) D[i] += TR[TILE_REC * (li - 1) + 9 + i];
+      for (int i = 0; i < 3; ++i) b[i] += TR[TILE_REC * (li - 1) + 15 + i];
+      for (int r2 = 0; r2 < 3; ++r2)
+        for (int c2 = 0; c2 < 3; ++c2) L[3 * r2 + c2] = TR[TILE_REC * (li - 1) + 18 + 3 * c2 + r2];
+    }
+  }
+  double PL[9], PU[9], Pb[3];
+  int elim_d = 0;
+  tile_cr_forward<CHAIN_THREADS>(lds, row_active, li, T, L, D, U, b, PL, PU, Pb, elim_d, status, step);
+  // rows 0 and T now form [D0 U0; U0^T DT] [x0; xT] = [b0; bT]
+  if (li == 0) {
+    for (int i = 0; i < 6; ++i) lds[(S_PL + i) * CHAIN_THREADS] = D[i];
+    for (int i = 0; i < 9; ++i) lds[(S_PU + i) * CHAIN_THREADS] = U[i];
+    for (int i = 0; i < 3; ++i) lds[(S_PB + i) * CHAIN_THREADS] = b[i];
+  }
+  if (li == T) {  // column 1 is free once the reduction has finished
+    for (int i = 0; i < 6; ++i) lds[(S_PL + i) * CHAIN_THREADS + 1] = D[i];
+    for (int i = 0; i < 3; ++i) lds[(S_PB + i) * CHAIN_THREADS + 1] = b[i];
+  }
+  __syncthreads();
+  if (li == 0) {
+    double M[36], r[6];
+    double D0[9], DT[9];
+    double s0[6], s1[6];
+    for (int i = 0; i < 6; ++i) { s0[i] = lds[(S_PL + i) * CHAIN_THREADS]; s1[i] = lds[(S_PL + i) * CHAIN_THREADS + 1]; }
+    full_from_sym(s0, D0);
+    full_from_sym(s1, DT);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double u = lds[(S_PU + 3 * i + j) * CHAIN_THREADS];
+        M[6 * i + j] = D0[3 * i + j];
+        M[6 * (i + 3) + j + 3] = DT[3 * i + j];
+        M[6 * i + j + 3] = u;
+        M[6 * (j + 3) + i] = u;
+      }
+    for (int i = 0; i < 3; ++i) {
+      r[i] = lds[(S_PB + i) * CHAIN_THREADS];
+      r[3 + i] = lds[(S_PB + i) * CHAIN_THREADS + 1];
+    }
+    // Cholesky 6x6
+    bool ok = true;
+    for (int j = 0; j < 6 && ok; ++j) {
+      double d = M[6 * j + j];
+      for (int k = 0; k < j; ++k) d -= M[6 * j + k] * M[6 * j + k];
+      if (!(d > 0.0)) { ok = false; break; }
+      d = sqrt(d);
+      M[6 * j + j] = d;
+      for (int i = j + 1; i < 6; ++i) {
+        double v = M[6 * i + j];
+        for (int k = 0; k < j; ++k) v -= M[6 * i + k] * M[6 * j + k];
+        M[6 * i + j] = v / d;
+      }
+    }
+    if (!ok) {
+      raise_flag(status, FLAG_SINGULAR, step);
+      for (int i = 0; i < 6; ++i) r[i] = 0.0;
+    } else {
+      for (int i = 0; i < 6; ++i) {
+        double v = r[i];
+        for (int k = 0; k < i; ++k) v -= M[6 * i + k] * r[k];
+        r[i] = v / M[6 * i + i];
+      }
+      for (int i = 5; i >= 0; --i) {
+        double v = r[i];
+        for (int k = i + 1; k < 6; ++k) v -= M[6 * k + i] * r[k];
+        r[i] = v / M[6 * i + i];
+      }
+    }
+    for (int i = 0; i < 3; ++i) {
+      lds[(S_X + i) * CHAIN_THREADS + 0] = r[i];
+      lds[(S_X + i) * CHAIN_THREADS + T] = r[3 + i];
+    }
+  }
+  __syncthreads();
+  tile_cr_backward<CHAIN_THREADS>(lds, row_active, li, T, elim_d, PL, PU, Pb);
+  if (row_active)
+    for (int i = 0; i < 3; ++i) xtop[3 * ((int64_t)cd.gtop0 + li) + i] = lds[(S_X + i) * CHAIN_THREADS + li];
+}
+
 // Interface rows of one chain form again a block-tridiagonal system: row gi
 // gathers D and b from the two tiles that share it and couples to row gi+1
 // through the tile's Schur block U.  Groups of GROUP_T + 1 interface rows are
@@ -418,7 +520,7 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_tile_kernel(ChainArgs a) 
 template <bool APPLY>
 __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
     const ChainDesc *chains, const GroupDesc *groups, const double *tilerec, double *grouprec,
-    const double *xtop, double *xg, uint32_t *status, int step) {
+    double *xtop, double *xg, int *counters, uint32_t *status, int step) {
   __shared__ double lds[S_N * CHAIN_THREADS];
   if (skip_step(status, step)) return;
   const GroupDesc gd = groups[blockIdx.x];
@@ -452,7 +554,7 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
       for (int c2 = 0; c2 < 3; ++c2) L[3 * r2 + c2] = TR[TILE_REC * (gi - 1) + 18 + 3 * c2 + r2];
   double PL[9], PU[9], Pb[3];
   int elim_d = 0;
-  tile_cr_forward(lds, row_active, li, T, L, D, U, b, PL, PU, Pb, elim_d, status, step);
+  tile_cr_forward<CHAIN_THREADS>(lds, row_active, li, T, L, D, U, b, PL, PU, Pb, elim_d, status, step);
   if constexpr (!APPLY) {
     double *rec = grouprec + (int64_t)TILE_REC * (cd.group0 + gd.gidx);
     if (row_active && li == 0) {
@@ -464,13 +566,30 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
       for (int i = 0; i < 6; ++i) rec[9 + i] = D[i];
       for (int i = 0; i < 3; ++i) rec[15 + i] = b[i];
     }
+    // The last group of the chain to finish solves the top system (its
+    // ngroup + 1 rows fit one workgroup); longer chains use chain_global.
+    if (cd.ngroup + 1 <= CHAIN_THREADS) {
+      __shared__ int is_last;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int prev = atomicAdd(counters + gd.chain, 1);
+        is_last = prev == cd.ngroup - 1;
+      }
+      __syncthreads();
+      if (is_last) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        top_solve(lds, cd, grouprec, xtop, status, step);
+        if (threadIdx.x == 0) counters[gd.chain] = 0;
+      }
+    }
   } else {
     if (row_active && (li == 0 || li == T)) {
       const int64_t ti = (int64_t)cd.gtop0 + gd.gidx + (li == T ? 1 : 0);
       for (int i = 0; i < 3; ++i) lds[(S_X + i) * CHAIN_THREADS + li] = xtop[3 * ti + i];
     }
     __syncthreads();
-    tile_cr_backward(lds, row_active, li, T, elim_d, PL, PU, Pb);
+    tile_cr_backward<CHAIN_THREADS>(lds, row_active, li, T, elim_d, PL, PU, Pb);
     const bool last = gd.gidx == cd.ngroup - 1;
     if (row_active && (li < T || last))
       for (int i = 0; i < 3; ++i) xg[3 * ((int64_t)cd.grow0 + gi) + i] = lds[(S_X + i) * CHAIN_THREADS + li];
@@ -602,24 +721,32 @@ __global__ __launch_bounds__(1024) void chain_global_kernel(const ChainDesc *cha
   }
 }
 
-void launch_chain_reduce(const ChainArgs &a, int ntiles, hipStream_t s) {
-  if (ntiles > 0)
-    hipLaunchKernelGGL(chain_tile_kernel<false>, dim3(ntiles), dim3(CHAIN_THREADS), 0, s, a);
+template <bool APPLY>
+static void launch_tiles(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
+  if (ntiles <= 0) return;
+  if (nt == 64)
+    hipLaunchKernelGGL((chain_tile_kernel<APPLY, 64>), dim3(ntiles), dim3(64), 0, s, a);
+  else if (nt == 128)
+    hipLaunchKernelGGL((chain_tile_kernel<APPLY, 128>), dim3(ntiles), dim3(128), 0, s, a);
+  else
+    hipLaunchKernelGGL((chain_tile_kernel<APPLY, 256>), dim3(ntiles), dim3(256), 0, s, a);
 }
-void launch_chain_apply(const ChainArgs &a, int ntiles, hipStream_t s) {
-  if (ntiles > 0)
-    hipLaunchKernelGGL(chain_tile_kernel<true>, dim3(ntiles), dim3(CHAIN_THREADS), 0, s, a);
+void launch_chain_reduce(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
+  launch_tiles<false>(a, ntiles, nt, s);
+}
+void launch_chain_apply(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
+  launch_tiles<true>(a, ntiles, nt, s);
 }
 void launch_chain_group(bool apply, const ChainDesc *chains, const GroupDesc *groups, int ngroups,
-                        const double *tilerec, double *grouprec, const double *xtop, double *xg,
-                        uint32_t *status, int step, hipStream_t s) {
+                        const double *tilerec, double *grouprec, double *xtop, double *xg,
+                        int *counters, uint32_t *status, int step, hipStream_t s) {
   if (ngroups <= 0) return;
   if (apply)
     hipLaunchKernelGGL(chain_group_kernel<true>, dim3(ngroups), dim3(CHAIN_THREADS), 0, s, chains,
-                       groups, tilerec, grouprec, xtop, xg, status, step);
+                       groups, tilerec, grouprec, xtop, xg, counters, status, step);
   else
     hipLaunchKernelGGL(chain_group_kernel<false>, dim3(ngroups), dim3(CHAIN_THREADS), 0, s, chains,
-                       groups, tilerec, grouprec, xtop, xg, status, step);
+                       groups, tilerec, grouprec, xtop, xg, counters, status, step);
 }
 void launch_chain_global(const ChainDesc *chains, int nchains, const double *tilerec, double *scr,
                          double *xg, uint32_t *status, int step, hipStream_t s) {

@@ -7,6 +7,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -20,13 +21,13 @@
 
 namespace mabd {
 
-void launch_chain_reduce(const ChainArgs &a, int ntiles, hipStream_t s);
-void launch_chain_apply(const ChainArgs &a, int ntiles, hipStream_t s);
+void launch_chain_reduce(const ChainArgs &a, int ntiles, int nt, hipStream_t s);
+void launch_chain_apply(const ChainArgs &a, int ntiles, int nt, hipStream_t s);
 void launch_chain_global(const ChainDesc *chains, int nchains, const double *tilerec, double *scr,
                          double *xg, uint32_t *status, int step, hipStream_t s);
 void launch_chain_group(bool apply, const ChainDesc *chains, const GroupDesc *groups, int ngroups,
-                        const double *tilerec, double *grouprec, const double *xtop, double *xg,
-                        uint32_t *status, int step, hipStream_t s);
+                        const double *tilerec, double *grouprec, double *xtop, double *xg,
+                        int *counters, uint32_t *status, int step, hipStream_t s);
 void launch_prefactor(const double *shape, int nshape, double h, double *hinv, hipStream_t s);
 void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
                   const int32_t *shp, const double *hinv, const double *shape, const double *g,
@@ -157,6 +158,9 @@ struct mabd_ctx {
   TileDesc *d_tiles = nullptr;
   GroupDesc *d_groups = nullptr;
   double *d_grouprec = nullptr, *d_xtop = nullptr;
+  int *d_gcount = nullptr;
+  int tile_threads = 64;     // workgroup size of the chain tile kernels (one wave: fastest measured)
+  bool top_in_group = true;  // every chain's top system fits one workgroup
   double *d_pl = nullptr, *d_pr = nullptr;
   uint8_t *d_flag = nullptr;
   double *d_tilerec = nullptr, *d_grow = nullptr, *d_xg = nullptr, *d_clam = nullptr;
@@ -364,6 +368,10 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
 
   mabd_ctx *c = new mabd_ctx();
   c->opt = opt;
+  if (const char *tt = std::getenv("MABD_CHAIN_TILE_THREADS")) {
+    const int v = std::atoi(tt);
+    if (v == 64 || v == 128 || v == 256) c->tile_threads = v;
+  }
   c->n = n;
   c->m = m;
   c->pinned = pinned;
@@ -512,14 +520,15 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       cflag.push_back((left_is_a ? 1 : 0) | (right_is_a ? 2 : 0));
       c->crow_joint.push_back(k);
     }
-    cd.ntile = (K - 1 + CHAIN_TILE - 1) / CHAIN_TILE;
+    const int TT = c->tile_threads - 2;
+    cd.ntile = (K - 1 + TT - 1) / TT;
     cd.tile0 = (int)c->tiles.size();
     cd.grow0 = c->ngrows;
     for (int t = 0; t < cd.ntile; ++t) {
       TileDesc td{};
       td.chain = (int)c->chains.size();
-      td.r0 = t * CHAIN_TILE;
-      td.T = std::min(CHAIN_TILE, K - 1 - td.r0);
+      td.r0 = t * TT;
+      td.T = std::min(TT, K - 1 - td.r0);
       td.tidx = t;
       c->tiles.push_back(td);
     }
@@ -536,6 +545,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       c->groups.push_back(gd);
     }
     c->ntop += cd.ngroup + 1;
+    if (cd.ngroup + 1 > CHAIN_THREADS) c->top_in_group = false;
     c->nchain_rows += K;
     c->chains.push_back(cd);
   }
@@ -792,6 +802,8 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(upload(c, &c->d_groups, c->groups));
   if (e == hipSuccess) chk(dalloc(c, &c->d_grouprec, (size_t)TILE_REC * c->groups.size()));
   if (e == hipSuccess) chk(dalloc(c, &c->d_xtop, (size_t)3 * c->ntop));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_gcount, std::max<size_t>(c->chains.size(), 1)));
+  if (e == hipSuccess) chk(hipMemset(c->d_gcount, 0, std::max<size_t>(c->chains.size(), 1) * sizeof(int)));
   if (e == hipSuccess) chk(dalloc(c, &c->d_grow, (size_t)GROW_REC * c->ntop));
   if (e == hipSuccess) chk(dalloc(c, &c->d_xg, (size_t)3 * c->ngrows));
   if (e == hipSuccess) chk(dalloc(c, &c->d_clam, (size_t)3 * nrs));
@@ -897,16 +909,17 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
       ca.lam = c->d_clam;
       ca.status = c->d_status;
       ca.step = st;
-      tm.run(0, [&] { launch_chain_reduce(ca, (int)c->tiles.size(), s); });
+      tm.run(0, [&] { launch_chain_reduce(ca, (int)c->tiles.size(), c->tile_threads, s); });
       tm.run(1, [&] {
         launch_chain_group(false, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
-                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_status, st, s);
-        launch_chain_global(c->d_chains, (int)c->chains.size(), c->d_grouprec, c->d_grow, c->d_xtop,
-                            c->d_status, st, s);
+                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, st, s);
+        if (!c->top_in_group)
+          launch_chain_global(c->d_chains, (int)c->chains.size(), c->d_grouprec, c->d_grow,
+                              c->d_xtop, c->d_status, st, s);
         launch_chain_group(true, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
-                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_status, st, s);
+                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, st, s);
       });
-      tm.run(2, [&] { launch_chain_apply(ca, (int)c->tiles.size(), s); });
+      tm.run(2, [&] { launch_chain_apply(ca, (int)c->tiles.size(), c->tile_threads, s); });
     }
     if (c->gb1 > c->gb0) {
       for (int it = 0; it < c->opt.newton_iters; ++it) {
