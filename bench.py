@@ -70,19 +70,20 @@ def main():
     import paper_2603_08079_amd as pk
 
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
+    # a stream of our own (default priority): the step graphs are captured on it
+    stream = torch.cuda.Stream()
     asm = mi.config(args.workload)
     h = asm.h
-    ctx = pk.Context(asm, stream=stream.cuda_stream, diagnostics=2, kkt_tol=args.kkt_tol,
-                     max_iters=args.max_iters)
+    ctx = pk.Context(asm, stream=stream.cuda_stream, kkt_tol=args.kkt_tol, max_iters=args.max_iters)
     st0 = ctx.stats()
     n_dyn = st0["n_dyn"]
     print(f"# workload {args.workload}: {asm.n} bodies ({n_dyn} dynamic), {asm.m} joints, "
           f"chains {st0['n_chain']} trees {st0['n_tree']} graphs {st0['n_graph']}",
           file=sys.stderr, flush=True)
-    def run(nsteps):
+
+    def run(c, nsteps):
         try:
-            ctx.step(h, nsteps)
+            c.step(h, nsteps)
             return None
         except pk.MabdError as e:  # PCG stopped at its iteration cap: report, do not hide
             if e.status != pk.ERR_NOT_CONVERGED:
@@ -90,13 +91,13 @@ def main():
             return str(e)
 
     if args.warmup:
-        run(args.warmup)
+        run(ctx, args.warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     t0 = time.perf_counter()
-    notconv = run(args.steps)
+    notconv = run(ctx, args.steps)
     e1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -104,10 +105,25 @@ def main():
     gpu_ms = e0.elapsed_time(e1)
     st = ctx.stats()
     value = n_dyn * args.steps / wall
+    print(f"# timed: {args.steps} steps in {wall * 1e3:.3f} ms (graph replay {st['graph_replay']}, "
+          f"chain tile threads {st['tile_threads']})", file=sys.stderr, flush=True)
+
+    # Per-kernel durations: the same steps again on a second context whose
+    # kernel groups are bracketed by HIP events on the stream they run on.
+    psteps = min(args.steps, 10)
+    prof = pk.Context(asm, stream=stream.cuda_stream, diagnostics=2, kkt_tol=args.kkt_tol,
+                      max_iters=args.max_iters)
+    run(prof, 1)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    run(prof, psteps)
+    prof_ms = (time.perf_counter() - tp) * 1e3 / psteps
+    sp = prof.stats()
+    prof.close()
     phases = pk.StepStats.PHASES
-    per_launch = {phases[i]: st["phase_ms"][i] / st["phase_calls"][i]
-                  for i in range(8) if st["phase_calls"][i]}
-    dom = max(per_launch, key=lambda k: per_launch[k] * st["phase_calls"][phases.index(k)])
+    per_launch = {phases[i]: sp["phase_ms"][i] / sp["phase_calls"][i]
+                  for i in range(8) if sp["phase_calls"][i]}
+    dom = max(per_launch, key=lambda k: per_launch[k] * sp["phase_calls"][phases.index(k)])
     roof = None
     if dom in ALG_BYTES:
         alg = ALG_BYTES[dom] * n_dyn
@@ -115,7 +131,9 @@ def main():
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
                 "avg_launch_ms": round(per_launch[dom], 4),
-                "alg_bytes_per_launch": alg}
+                "alg_bytes_per_launch": alg,
+                "timing": f"HIP events around each launch, {psteps} steps, eager launches "
+                          f"({prof_ms:.4f} ms/step)"}
     print(f"# per-launch ms: { {k: round(v, 4) for k, v in per_launch.items()} }",
           file=sys.stderr, flush=True)
 
@@ -154,7 +172,8 @@ def main():
         "gpu_ms_per_step": round(gpu_ms / args.steps, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "bodies": asm.n, "dynamic_bodies": n_dyn,
-                   "joints": asm.m, "h": h, "newton_iters": 1, "form": "plain FP64"},
+                   "joints": asm.m, "h": h, "newton_iters": 1, "form": "plain FP64",
+                   "graph_replay": bool(st["graph_replay"]), "chain_tile_threads": st["tile_threads"]},
         "kkt": kkt, "roofline": roof, "cpu_baseline": cpu,
     }
     if st["n_graph"]:

@@ -89,6 +89,10 @@ typedef struct {
   int32_t material;        /* 0: mu = 4 k_A, lambda = 0 (Eq. EA linearised); 1: Lame     */
   int32_t diagnostics;     /* bit 0: evaluate the FP64 KKT residual after every step;
                               bit 1: time every kernel group with HIP events (phase_ms)  */
+  int32_t use_graph;       /* 1 (default): replay each step as a captured hipGraph when
+                              the assembly has no PCG component and bit 1 is off        */
+  int32_t autotune;        /* 1 (default): at the first step, time the chain tile sizes
+                              (64, 128, 256 threads) and keep the fastest               */
   void *stream;            /* hipStream_t, or NULL for a library-owned stream             */
 } mabd_options;
 
@@ -109,6 +113,8 @@ typedef struct {
      5 tree elimination, 6 generic back-projection, 7 PCG. */
   double phase_ms[8];
   int64_t phase_calls[8];
+  int32_t tile_threads;    /* workgroup size of the chain tile kernels in use            */
+  int32_t graph_replay;    /* 1 if the last mabd_step replayed captured step graphs       */
 } mabd_step_stats;
 
 /* Fills *opt with the defaults listed above. */

@@ -61,7 +61,6 @@ constexpr int SHAPE_STRIDE = 8;
 // per-shape structured inverse of Hbar (layout in dmath.hpp)
 constexpr int HINV_STRIDE = 20;
 
-// status words: [0] FLAG_* bits, [1] first failing step of the current call
 constexpr int NO_FAIL = 0x7fffffff;
 
 struct ChainArgs {
@@ -85,15 +84,19 @@ struct ChainArgs {
   int step;                   // step index inside the current call
 };
 
+// status words: [0] FLAG_* bits, [1] first failing step of the current call,
+// [2] index of the running step (set on the device by a one-thread kernel at
+// the start of every step, so that a captured step graph is step-independent)
 #ifdef __HIPCC__
-// record a failure of step `step` (integer atomics only)
-__device__ __forceinline__ void raise_flag(uint32_t *st, uint32_t bits, int step) {
+// record a failure of the running step (integer atomics only)
+__device__ __forceinline__ void raise_flag(uint32_t *st, uint32_t bits, int /*unused*/) {
   atomicOr(st, bits);
-  atomicMin(reinterpret_cast<int *>(st + 1), step);
+  atomicMin(reinterpret_cast<int *>(st + 1), *reinterpret_cast<const volatile int *>(st + 2));
 }
 // a step after a failed one does nothing, so the last good state survives
-__device__ __forceinline__ bool skip_step(const uint32_t *st, int step) {
-  return *reinterpret_cast<const volatile int *>(st + 1) < step;
+__device__ __forceinline__ bool skip_step(const uint32_t *st, int /*unused*/) {
+  return *reinterpret_cast<const volatile int *>(st + 1) <
+         *reinterpret_cast<const volatile int *>(st + 2);
 }
 #endif
 

@@ -477,7 +477,10 @@ __global__ void write_pinned_kernel(int np, const int32_t *idx, const double *q0
 __global__ void reset_status_kernel(uint32_t *st) {
   st[0] = 0u;
   st[1] = (uint32_t)NO_FAIL;
+  st[2] = 0xffffffffu;  // the first begin_step makes it 0
 }
+
+__global__ void begin_step_kernel(uint32_t *st) { st[2] += 1u; }
 
 // launchers ---------------------------------------------------------------
 void launch_scatter_state(int nd, const int32_t *sol2in, const double *qi, const double *qdi,
@@ -494,6 +497,9 @@ void launch_write_pinned(int np, const int32_t *idx, const double *q0, double *q
 }
 void launch_reset_status(uint32_t *st, hipStream_t s) {
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(1), 0, s, st);
+}
+void launch_begin_step(uint32_t *st, hipStream_t s) {
+  hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(1), 0, s, st);
 }
 void launch_prefactor(const double *shape, int nshape, double h, double *hinv, hipStream_t s) {
   if (nshape > 0)

@@ -47,6 +47,7 @@ void launch_scatter_state(int nd, const int32_t *sol2in, const double *qi, const
 void launch_write_pinned(int np, const int32_t *idx, const double *q0, double *qo, double *qdo,
                          hipStream_t s);
 void launch_reset_status(uint32_t *status, hipStream_t s);
+void launch_begin_step(uint32_t *status, hipStream_t s);
 hipError_t launch_pcg(const PcgArgs &a, int nblocks, hipStream_t s);
 int pcg_max_blocks();
 }  // namespace mabd
@@ -159,8 +160,12 @@ struct mabd_ctx {
   GroupDesc *d_groups = nullptr;
   double *d_grouprec = nullptr, *d_xtop = nullptr;
   int *d_gcount = nullptr;
-  int tile_threads = 64;     // workgroup size of the chain tile kernels (one wave: fastest measured)
+  int tile_threads = 64;     // workgroup size of the chain tile kernels (autotuned)
   bool top_in_group = true;  // every chain's top system fits one workgroup
+  bool tuned = false;
+  // captured step graphs, one per state-buffer parity
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  bool graph_failed = false;
   double *d_pl = nullptr, *d_pr = nullptr;
   uint8_t *d_flag = nullptr;
   double *d_tilerec = nullptr, *d_grow = nullptr, *d_xg = nullptr, *d_clam = nullptr;
@@ -266,6 +271,59 @@ struct PhaseTimer {
 };
 }  // namespace
 
+namespace {
+// Tiles of tile_threads - 2 rows and groups of GROUP_T + 1 interface rows for
+// every chain; descriptors go to preallocated device buffers (sized for the
+// smallest tiles), so re-tuning only rewrites them.
+hipError_t build_tiles(mabd_ctx *c, int tt) {
+  c->tile_threads = tt;
+  c->tiles.clear();
+  c->groups.clear();
+  c->ngrows = 0;
+  c->ntop = 0;
+  c->top_in_group = true;
+  const int TT = tt - 2;
+  for (size_t ci = 0; ci < c->chains.size(); ++ci) {
+    ChainDesc &cd = c->chains[ci];
+    const int K = cd.K;
+    cd.ntile = (K - 1 + TT - 1) / TT;
+    cd.tile0 = (int)c->tiles.size();
+    cd.grow0 = c->ngrows;
+    for (int t = 0; t < cd.ntile; ++t) {
+      TileDesc td{};
+      td.chain = (int)ci;
+      td.r0 = t * TT;
+      td.T = std::min(TT, K - 1 - td.r0);
+      td.tidx = t;
+      c->tiles.push_back(td);
+    }
+    c->ngrows += cd.ntile + 1;
+    cd.ngroup = (cd.ntile + GROUP_T - 1) / GROUP_T;
+    cd.group0 = (int)c->groups.size();
+    cd.gtop0 = c->ntop;
+    for (int g2 = 0; g2 < cd.ngroup; ++g2) {
+      GroupDesc gd{};
+      gd.chain = (int)ci;
+      gd.g0 = g2 * GROUP_T;
+      gd.T = std::min(GROUP_T, cd.ntile - gd.g0);
+      gd.gidx = g2;
+      c->groups.push_back(gd);
+    }
+    c->ntop += cd.ngroup + 1;
+    if (cd.ngroup + 1 > CHAIN_THREADS) c->top_in_group = false;
+  }
+  if (!c->d_chains) return hipSuccess;  // not allocated yet (create sizes them first)
+  hipError_t e = hipMemcpy(c->d_chains, c->chains.data(), c->chains.size() * sizeof(ChainDesc),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess && !c->tiles.empty())
+    e = hipMemcpy(c->d_tiles, c->tiles.data(), c->tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !c->groups.empty())
+    e = hipMemcpy(c->d_groups, c->groups.data(), c->groups.size() * sizeof(GroupDesc),
+                  hipMemcpyHostToDevice);
+  return e;
+}
+}  // namespace
+
 extern "C" {
 
 void mabd_options_default(mabd_options *o) {
@@ -280,6 +338,8 @@ void mabd_options_default(mabd_options *o) {
   o->hinge_grad = 0;
   o->material = 0;
   o->diagnostics = 0;
+  o->use_graph = 1;
+  o->autotune = 1;
   o->stream = nullptr;
 }
 
@@ -288,6 +348,8 @@ const char *mabd_last_error(const mabd_ctx *c) { return c ? c->err.c_str() : g_c
 void mabd_destroy(mabd_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (int i = 0; i < 2; ++i)
+    if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
   for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->h_status) (void)hipHostFree(c->h_status);
@@ -368,10 +430,6 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
 
   mabd_ctx *c = new mabd_ctx();
   c->opt = opt;
-  if (const char *tt = std::getenv("MABD_CHAIN_TILE_THREADS")) {
-    const int v = std::atoi(tt);
-    if (v == 64 || v == 128 || v == 256) c->tile_threads = v;
-  }
   c->n = n;
   c->m = m;
   c->pinned = pinned;
@@ -520,36 +578,11 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       cflag.push_back((left_is_a ? 1 : 0) | (right_is_a ? 2 : 0));
       c->crow_joint.push_back(k);
     }
-    const int TT = c->tile_threads - 2;
-    cd.ntile = (K - 1 + TT - 1) / TT;
-    cd.tile0 = (int)c->tiles.size();
-    cd.grow0 = c->ngrows;
-    for (int t = 0; t < cd.ntile; ++t) {
-      TileDesc td{};
-      td.chain = (int)c->chains.size();
-      td.r0 = t * TT;
-      td.T = std::min(TT, K - 1 - td.r0);
-      td.tidx = t;
-      c->tiles.push_back(td);
-    }
-    c->ngrows += cd.ntile + 1;
-    cd.ngroup = (cd.ntile + GROUP_T - 1) / GROUP_T;  // interface rows - 1 = ntile
-    cd.group0 = (int)c->groups.size();
-    cd.gtop0 = c->ntop;
-    for (int g2 = 0; g2 < cd.ngroup; ++g2) {
-      GroupDesc gd{};
-      gd.chain = (int)c->chains.size();
-      gd.g0 = g2 * GROUP_T;
-      gd.T = std::min(GROUP_T, cd.ntile - gd.g0);
-      gd.gidx = g2;
-      c->groups.push_back(gd);
-    }
-    c->ntop += cd.ngroup + 1;
-    if (cd.ngroup + 1 > CHAIN_THREADS) c->top_in_group = false;
     c->nchain_rows += K;
     c->chains.push_back(cd);
   }
   c->nchain_bodies = (int)c->sol2in.size();
+  (void)build_tiles(c, 64);  // sizes every tile buffer for the smallest tiles
   // generic (tree) components
   c->gb0 = c->nchain_bodies;
   std::vector<int> gidx(m, -1);  // input joint -> generic joint
@@ -786,6 +819,13 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(dalloc(c, &c->d_hinv, (size_t)HINV_STRIDE * c->nshape));
   if (e == hipSuccess) chk(upload(c, &c->d_chains, c->chains));
   if (e == hipSuccess) chk(upload(c, &c->d_tiles, c->tiles));
+  if (const char *tt = std::getenv("MABD_CHAIN_TILE_THREADS")) {
+    const int v = std::atoi(tt);
+    if (v == 64 || v == 128 || v == 256) {
+      c->tuned = true;  // fixed by the environment: no autotuning
+      if (e == hipSuccess && v != 64) chk(build_tiles(c, v));
+    }
+  }
   const int64_t nrs = std::max<int64_t>(c->nchain_rows, 1);
   {
     std::vector<double> spl(3 * nrs, 0.0), spr(3 * nrs, 0.0);
@@ -865,11 +905,205 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   c->stats.n_tree = c->ntree;
   c->stats.n_graph = c->ngraph;
   c->stats.n_dyn = c->nd;
+  c->stats.tile_threads = c->tile_threads;
   c->stats.rho_p = c->stats.rho_d = c->stats.kkt = -1.0;
   *out = c;
   return MABD_OK;
 }
 
+
+}  // extern "C"
+
+namespace {
+// Launch sequence of one step reading state buffer a and writing buffer b.
+// The step index lives in device memory (begin_step), so this sequence can
+// be captured once and replayed.
+template <typename Timer>
+hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
+  hipStream_t s = c->stream;
+  const double *g = c->opt.gravity;
+  launch_begin_step(c->d_status, s);
+    if (!c->chains.empty()) {
+    ChainArgs ca{};
+    ca.chains = c->d_chains;
+    ca.tiles = c->d_tiles;
+    ca.q = c->d_q[a];
+    ca.qd = c->d_qd[a];
+    ca.q_out = c->d_q[b];
+    ca.qd_out = c->d_qd[b];
+    ca.ns = c->ns;
+    ca.shp = c->d_shp;
+    ca.hinv = c->d_hinv;
+    ca.shape = c->d_shape;
+    ca.pl = c->d_pl;
+    ca.pr = c->d_pr;
+    ca.flag = c->d_flag;
+    ca.nrs = std::max(c->nchain_rows, 1);
+    ca.g[0] = g[0]; ca.g[1] = g[1]; ca.g[2] = g[2];
+    ca.h = h;
+    ca.tilerec = c->d_tilerec;
+    ca.xg = c->d_xg;
+    ca.lam = c->d_clam;
+    ca.status = c->d_status;
+    ca.step = 0;
+    tm.run(0, [&] { launch_chain_reduce(ca, (int)c->tiles.size(), c->tile_threads, s); });
+    tm.run(1, [&] {
+      launch_chain_group(false, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
+                         c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, 0, s);
+      if (!c->top_in_group)
+        launch_chain_global(c->d_chains, (int)c->chains.size(), c->d_grouprec, c->d_grow,
+                            c->d_xtop, c->d_status, 0, s);
+      launch_chain_group(true, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
+                         c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, 0, s);
+    });
+    tm.run(2, [&] { launch_chain_apply(ca, (int)c->tiles.size(), c->tile_threads, s); });
+  }
+  if (c->gb1 > c->gb0) {
+    for (int it = 0; it < c->opt.newton_iters; ++it) {
+      const double *qcur = it == 0 ? c->d_q[a] : c->d_q[b];
+      tm.run(3, [&] {
+        launch_gbody(c->gb0, c->gb1, qcur, c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv,
+                     c->d_shape, g, h, c->d_Rg, c->d_ug, c->d_status, 0, s);
+      });
+      tm.run(4, [&] {
+        launch_gjoint((int)c->gj.size(), c->d_gj, qcur, c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
+      });
+      TreeArgs ta{};
+      ta.comp_lvl = c->d_comp_lvl;
+      ta.lvl_off = c->d_lvl_off;
+      ta.tbody = c->d_tbody;
+      ta.tpk = c->d_tpk;
+      ta.tabs_off = c->d_tabs_off;
+      ta.tabs = c->d_tabs;
+      ta.gl = c->d_gl;
+      ta.gt = c->d_gt;
+      ta.u = c->d_ug;
+      ta.ns = c->ns;
+      ta.shp = c->d_shp;
+      ta.hinv = c->d_hinv;
+      ta.glam = c->d_glam;
+      ta.status = c->d_status;
+      ta.step = 0;
+      ta.tne = c->d_tne;
+      ta.foff = c->d_foff;
+      ta.fac = c->d_fac;
+      tm.run(5, [&] { launch_tree(ta, c->d_gj, c->ntree, s); });
+      if (c->ngraph > 0) {
+        PcgArgs pa{};
+        pa.nb = c->gb1 - c->gb0;
+        pa.b0 = c->gb0;
+        pa.mj = (int)c->gj.size();
+        pa.jmask = c->d_jmask;
+        pa.bmask = c->d_bmask;
+        pa.J = c->d_gj;
+        pa.gl = c->d_gl;
+        pa.ug = c->d_ug;
+        pa.ns = c->ns;
+        pa.shp = c->d_shp;
+        pa.hinv = c->d_hinv;
+        pa.inc_off = c->d_inc_off;
+        pa.inc = c->d_inc;
+        pa.lam = c->d_glam;
+        pa.r = c->d_pr_;
+        pa.p = c->d_pp;
+        pa.z = c->d_pz;
+        pa.sp = c->d_psp;
+        pa.bv = c->d_pbv;
+        pa.dinv = c->d_dinv;
+        pa.zb = c->d_zb;
+        pa.partial = c->d_partial;
+        pa.tol = c->opt.kkt_tol;
+        pa.max_iters = c->opt.max_iters;
+        pa.warm = (c->opt.warm_start == 1 && c->warm_valid) ? 1 : 0;
+        pa.iters_out = c->d_pcg_it;
+        pa.res_out = c->d_pcg_res;
+        pa.status = c->d_status;
+        pa.step = 0;
+        hipError_t pe = hipSuccess;
+        tm.run(7, [&] { pe = launch_pcg(pa, c->pcg_blocks, s); });
+        if (pe != hipSuccess) return pe;
+      }
+      tm.run(6, [&] {
+        launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_glam, c->d_Rg, c->d_ug,
+                      c->ns, c->d_shp, c->d_hinv, qcur, c->d_q[b], c->d_qd[b], h, it > 0 ? 1 : 0,
+                      c->d_status, c->d_gj, 0, s);
+      });
+    }
+  }
+  return hipGetLastError();
+}
+
+struct NoTimer {
+  template <typename F>
+  void run(int, F &&f) { f(); }
+};
+
+// time the whole step for every chain tile size and keep the fastest
+hipError_t autotune(mabd_ctx *c, double h) {
+  hipStream_t s = c->stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return hipErrorUnknown;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return hipErrorUnknown; }
+  NoTimer nt;
+  int best = c->tile_threads;
+  float best_ms = 1e30f;
+  hipError_t e = hipSuccess;
+  for (int tt : {64, 128, 256}) {
+    e = build_tiles(c, tt);
+    if (e != hipSuccess) break;
+    launch_reset_status(c->d_status, s);
+    e = issue_step(c, h, c->cur, 1 - c->cur, nt);  // writes only the scratch buffer
+    if (e != hipSuccess) break;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < 3; ++r) issue_step(c, h, c->cur, 1 - c->cur, nt);
+    (void)hipEventRecord(e1, s);
+    e = hipEventSynchronize(e1);
+    if (e != hipSuccess) break;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) { best_ms = ms; best = tt; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e == hipSuccess) e = build_tiles(c, best);
+  return e;
+}
+
+void drop_graphs(mabd_ctx *c) {
+  for (int i = 0; i < 2; ++i)
+    if (c->gexec[i]) {
+      (void)hipGraphExecDestroy(c->gexec[i]);
+      c->gexec[i] = nullptr;
+    }
+}
+
+// capture one step per buffer parity; on any failure fall back to launches
+void capture_graphs(mabd_ctx *c, double h) {
+  NoTimer nt;
+  for (int par = 0; par < 2; ++par) {
+    hipGraph_t gr = nullptr;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) break;
+    hipError_t e = issue_step(c, h, par, 1 - par, nt);
+    hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
+    if (e != hipSuccess || e2 != hipSuccess || !gr) {
+      if (gr) (void)hipGraphDestroy(gr);
+      break;
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) break;
+    c->gexec[par] = ex;
+  }
+  if (!c->gexec[0] || !c->gexec[1]) {
+    drop_graphs(c);
+    c->graph_failed = true;
+    (void)hipGetLastError();
+  }
+}
+}  // namespace
+
+extern "C" {
 
 mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
   if (!c) return MABD_ERR_INVALID_ARG;
@@ -879,120 +1113,28 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
   if (h != c->h_last) {
     launch_prefactor(c->d_shape, c->nshape, h, c->d_hinv, s);
     c->h_last = h;
+    drop_graphs(c);
+  }
+  if (c->opt.autotune && !c->tuned && c->nchain_rows >= 20000) {
+    hipError_t te = autotune(c, h);
+    if (te != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(te));
+    c->tuned = true;
+    drop_graphs(c);
   }
   const int start_cur = c->cur;
   PhaseTimer tm(c);
   launch_reset_status(c->d_status, s);
-  const double *g = c->opt.gravity;
+  bool graph = c->opt.use_graph && c->ngraph == 0 && !tm.on && !c->graph_failed;
+  if (graph && !c->gexec[0]) capture_graphs(c, h);
+  graph = graph && c->gexec[0] && c->gexec[1];
+  c->stats.graph_replay = graph ? 1 : 0;
+  c->stats.tile_threads = c->tile_threads;
   for (int st = 0; st < nsteps; ++st) {
     const int a = c->cur, b = 1 - c->cur;
-    if (!c->chains.empty()) {
-      ChainArgs ca{};
-      ca.chains = c->d_chains;
-      ca.tiles = c->d_tiles;
-      ca.q = c->d_q[a];
-      ca.qd = c->d_qd[a];
-      ca.q_out = c->d_q[b];
-      ca.qd_out = c->d_qd[b];
-      ca.ns = c->ns;
-      ca.shp = c->d_shp;
-      ca.hinv = c->d_hinv;
-      ca.shape = c->d_shape;
-      ca.pl = c->d_pl;
-      ca.pr = c->d_pr;
-      ca.flag = c->d_flag;
-      ca.nrs = std::max(c->nchain_rows, 1);
-      ca.g[0] = g[0]; ca.g[1] = g[1]; ca.g[2] = g[2];
-      ca.h = h;
-      ca.tilerec = c->d_tilerec;
-      ca.xg = c->d_xg;
-      ca.lam = c->d_clam;
-      ca.status = c->d_status;
-      ca.step = st;
-      tm.run(0, [&] { launch_chain_reduce(ca, (int)c->tiles.size(), c->tile_threads, s); });
-      tm.run(1, [&] {
-        launch_chain_group(false, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
-                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, st, s);
-        if (!c->top_in_group)
-          launch_chain_global(c->d_chains, (int)c->chains.size(), c->d_grouprec, c->d_grow,
-                              c->d_xtop, c->d_status, st, s);
-        launch_chain_group(true, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
-                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, st, s);
-      });
-      tm.run(2, [&] { launch_chain_apply(ca, (int)c->tiles.size(), c->tile_threads, s); });
-    }
-    if (c->gb1 > c->gb0) {
-      for (int it = 0; it < c->opt.newton_iters; ++it) {
-        const double *qcur = it == 0 ? c->d_q[a] : c->d_q[b];
-        tm.run(3, [&] {
-          launch_gbody(c->gb0, c->gb1, qcur, c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv,
-                       c->d_shape, g, h, c->d_Rg, c->d_ug, c->d_status, st, s);
-        });
-        tm.run(4, [&] {
-          launch_gjoint((int)c->gj.size(), c->d_gj, qcur, c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
-        });
-        TreeArgs ta{};
-        ta.comp_lvl = c->d_comp_lvl;
-        ta.lvl_off = c->d_lvl_off;
-        ta.tbody = c->d_tbody;
-        ta.tpk = c->d_tpk;
-        ta.tabs_off = c->d_tabs_off;
-        ta.tabs = c->d_tabs;
-        ta.gl = c->d_gl;
-        ta.gt = c->d_gt;
-        ta.u = c->d_ug;
-        ta.ns = c->ns;
-        ta.shp = c->d_shp;
-        ta.hinv = c->d_hinv;
-        ta.glam = c->d_glam;
-        ta.status = c->d_status;
-        ta.step = st;
-        ta.tne = c->d_tne;
-        ta.foff = c->d_foff;
-        ta.fac = c->d_fac;
-        tm.run(5, [&] { launch_tree(ta, c->d_gj, c->ntree, s); });
-        if (c->ngraph > 0) {
-          PcgArgs pa{};
-          pa.nb = c->gb1 - c->gb0;
-          pa.b0 = c->gb0;
-          pa.mj = (int)c->gj.size();
-          pa.jmask = c->d_jmask;
-          pa.bmask = c->d_bmask;
-          pa.J = c->d_gj;
-          pa.gl = c->d_gl;
-          pa.ug = c->d_ug;
-          pa.ns = c->ns;
-          pa.shp = c->d_shp;
-          pa.hinv = c->d_hinv;
-          pa.inc_off = c->d_inc_off;
-          pa.inc = c->d_inc;
-          pa.lam = c->d_glam;
-          pa.r = c->d_pr_;
-          pa.p = c->d_pp;
-          pa.z = c->d_pz;
-          pa.sp = c->d_psp;
-          pa.bv = c->d_pbv;
-          pa.dinv = c->d_dinv;
-          pa.zb = c->d_zb;
-          pa.partial = c->d_partial;
-          pa.tol = c->opt.kkt_tol;
-          pa.max_iters = c->opt.max_iters;
-          pa.warm = (c->opt.warm_start == 1 && c->warm_valid) ? 1 : 0;
-          pa.iters_out = c->d_pcg_it;
-          pa.res_out = c->d_pcg_res;
-          pa.status = c->d_status;
-          pa.step = st;
-          hipError_t pe = hipSuccess;
-          tm.run(7, [&] { pe = launch_pcg(pa, c->pcg_blocks, s); });
-          if (pe != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("PCG launch: ") + hipGetErrorString(pe));
-        }
-        tm.run(6, [&] {
-          launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_glam, c->d_Rg, c->d_ug,
-                        c->ns, c->d_shp, c->d_hinv, qcur, c->d_q[b], c->d_qd[b], h, it > 0 ? 1 : 0,
-                        c->d_status, c->d_gj, st, s);
-        });
-      }
-    }
+    hipError_t le;
+    if (graph) le = hipGraphLaunch(c->gexec[a], s);
+    else le = issue_step(c, h, a, b, tm);
+    if (le != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(le));
     c->cur = b;
   }
   hipError_t e = hipMemcpyAsync(c->h_status, c->d_status, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
