@@ -47,7 +47,8 @@ typedef enum {
   MABD_ERR_DEVICE = -3,       /* HIP runtime error                               */
   MABD_ERR_OOM = -4,          /* device allocation failed                        */
   MABD_ERR_NONFINITE = -5,    /* non-finite state or det A <= 0 during a step    */
-  MABD_ERR_NOT_CONVERGED = -6,/* PCG reached max_iters above kkt_tol              */
+  MABD_ERR_NOT_CONVERGED = -6,/* PCG reached max_iters, or precision-1 refinement ran
+                                 out of sweeps, above kkt_tol                        */
   MABD_ERR_SINGULAR = -7      /* a dual pivot block was not positive definite    */
 } mabd_status;
 
@@ -79,9 +80,13 @@ typedef struct {
 
 typedef struct {
   double gravity[3];       /* m/s^2, default (0, 0, -9.8)                                 */
-  int32_t precision;       /* 0 FP64 throughout; 1 FP32 body/assembly + FP64 factor with
-                              FP64 residual refinement                                   */
-  double kkt_tol;          /* PCG stop: |r - S lam| <= kkt_tol |r|, default 1e-10         */
+  int32_t precision;       /* 0 FP64 throughout; 1 on chain components: FP32 body solve and
+                              dual assembly, FP64 dual factor, then FP64 KKT residual
+                              checks and correction sweeps until max(rho_p, rho_d) <=
+                              kkt_tol, or until a sweep no longer halves it (the FP64
+                              rounding floor).  Trees and graphs stay FP64               */
+  double kkt_tol;          /* PCG stop: |r - S lam| <= kkt_tol |r|; precision-1 target of
+                              the chain KKT residual; default 1e-10                      */
   int32_t max_iters;       /* PCG iteration cap, default 200000                           */
   int32_t warm_start;      /* PCG start: 0 zero, 1 previous step's multipliers, 2 GNN     */
   int32_t newton_iters;    /* Newton iterations per step, default 1                       */
@@ -93,8 +98,12 @@ typedef struct {
                               the assembly has no PCG component and bit 1 is off        */
   int32_t autotune;        /* 1 (default): at the first step, time the chain tile sizes
                               (64, 128, 256 threads) and keep the fastest               */
+  int32_t ir_max_sweeps;   /* precision 1: correction sweeps before NOT_CONVERGED, 0..16,
+                              default 4                                                 */
   void *stream;            /* hipStream_t, or NULL for a library-owned stream             */
 } mabd_options;
+
+#define MABD_NPHASES 10
 
 typedef struct {
   int64_t steps_done;      /* steps completed since create                               */
@@ -110,9 +119,10 @@ typedef struct {
   /* With diagnostics bit 1: GPU time of each kernel group summed over the last
      mabd_step call, and its launch count.  Groups: 0 chain tile reduce, 1 chain
      interface solve, 2 chain tile apply, 3 generic bodies, 4 generic joints,
-     5 tree elimination, 6 generic back-projection, 7 PCG. */
-  double phase_ms[8];
-  int64_t phase_calls[8];
+     5 tree elimination, 6 generic back-projection, 7 PCG, 8 chain FP64 KKT
+     residual check (precision 1), 9 chain state update (precision 1). */
+  double phase_ms[MABD_NPHASES];
+  int64_t phase_calls[MABD_NPHASES];
   int32_t tile_threads;    /* workgroup size of the chain tile kernels in use            */
   int32_t graph_replay;    /* 1 if the last mabd_step replayed captured step graphs       */
 } mabd_step_stats;

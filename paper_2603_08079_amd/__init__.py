@@ -51,7 +51,11 @@ class Options(ctypes.Structure):
                 ("warm_start", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
                 ("hinge_grad", ctypes.c_int32), ("material", ctypes.c_int32),
                 ("diagnostics", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("autotune", ctypes.c_int32), ("ir_max_sweeps", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+NPHASES = 10
 
 
 class StepStats(ctypes.Structure):
@@ -62,11 +66,11 @@ class StepStats(ctypes.Structure):
                 ("ir_sweeps", ctypes.c_int32), ("warm_accepted", ctypes.c_int32),
                 ("n_chain", ctypes.c_int32), ("n_tree", ctypes.c_int32),
                 ("n_graph", ctypes.c_int32), ("n_dyn", ctypes.c_int32),
-                ("phase_ms", ctypes.c_double * 8), ("phase_calls", ctypes.c_int64 * 8),
+                ("phase_ms", ctypes.c_double * NPHASES), ("phase_calls", ctypes.c_int64 * NPHASES),
                 ("tile_threads", ctypes.c_int32), ("graph_replay", ctypes.c_int32)]
 
     PHASES = ("chain_reduce", "chain_global", "chain_apply", "body", "joint", "tree", "apply",
-              "pcg")
+              "pcg", "chain_resid", "chain_finish")
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

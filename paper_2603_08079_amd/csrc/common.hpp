@@ -82,6 +82,13 @@ struct ChainArgs {
   double *lam;                // 3 per chain row
   uint32_t *status;
   int step;                   // step index inside the current call
+  // precision form 1 (FP32 body/assembly, FP64 factor, FP64 residual refinement)
+  double *dq;                 // 12 x ns accumulated increment of the current step (SoA)
+  double *rp;                 // 12 x ns FP64 primal residual, world frame (SoA)
+  double *rd;                 // 3 x nrs FP64 dual residual per chain row (SoA)
+  double *part;               // 4 partial sums per tile
+  double *ir;                 // [0] 0 running / 1 converged / 2 stalled, [1] sweeps,
+                              // [2] rho_p, [3] rho_d, [4] kkt, [5] previous kkt
 };
 
 // status words: [0] FLAG_* bits, [1] first failing step of the current call,

@@ -38,42 +38,45 @@ DEV double sym3(const double *S6, int r, int c) {
   return S6[idx];
 }
 
-// y = Hbar^{-1} x for a 12-vector x (structured apply, ~40 flops)
-DEV void hinv_apply(const double *T, const double *x, double *y) {
-  const double ht = T[HI_T];
+// y = Hbar^{-1} x for a 12-vector x (structured apply, ~40 flops), in the
+// precision of x
+template <typename real>
+DEV void hinv_apply(const double *T, const real *x, real *y) {
+  const real ht = real(T[HI_T]);
   y[9] = ht * x[9];
   y[10] = ht * x[10];
   y[11] = ht * x[11];
   const double *D = T + HI_D;
-  double x0 = x[0], x4 = x[4], x8 = x[8];
-  y[0] = D[0] * x0 + D[1] * x4 + D[2] * x8;
-  y[4] = D[1] * x0 + D[3] * x4 + D[4] * x8;
-  y[8] = D[2] * x0 + D[4] * x4 + D[5] * x8;
+  const real x0 = x[0], x4 = x[4], x8 = x[8];
+  y[0] = real(D[0]) * x0 + real(D[1]) * x4 + real(D[2]) * x8;
+  y[4] = real(D[1]) * x0 + real(D[3]) * x4 + real(D[4]) * x8;
+  y[8] = real(D[2]) * x0 + real(D[4]) * x4 + real(D[5]) * x8;
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (r == c) continue;
       const int i1 = 3 * c + r, i2 = 3 * r + c;  // A_rc and its partner A_cr
-      y[i1] = T[HI_PD + 3 * r + c] * x[i1] + T[HI_PX + pair_slot(r, c)] * x[i2];
+      y[i1] = real(T[HI_PD + 3 * r + c]) * x[i1] + real(T[HI_PX + pair_slot(r, c)]) * x[i2];
     }
 }
 
 // W(p, p') = J(p) Hbar^{-1} J(p')^T  (3x3, row-major), J(p) = [p^T (x) I3, I3]
-DEV void wblock(const double *T, const double *p, const double *pp, double *W) {
+template <typename real>
+DEV void wblock(const double *T, const real *p, const real *pp, real *W) {
   const double *D = T + HI_D;
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      double v = p[r] * pp[s] * sym3(D, r, s);
+      real v = p[r] * pp[s] * real(sym3(D, r, s));
       if (r == s) {
-        v += T[HI_T];
+        v += real(T[HI_T]);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          if (c != r) v += p[c] * pp[c] * T[HI_PD + 3 * r + c];
+          if (c != r) v += p[c] * pp[c] * real(T[HI_PD + 3 * r + c]);
       } else {
-        v += p[s] * pp[r] * T[HI_PX + pair_slot(r, s)];
+        v += p[s] * pp[r] * real(T[HI_PX + pair_slot(r, s)]);
       }
       W[3 * r + s] = v;
     }
@@ -81,13 +84,15 @@ DEV void wblock(const double *T, const double *p, const double *pp, double *W) {
 
 // --------------------------------------------------------------- 3x3 algebra
 
-DEV double det3(const double *A) {
+template <typename real>
+DEV real det3(const real *A) {
   return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
          A[2] * (A[3] * A[7] - A[4] * A[6]);
 }
 
 // cofactor matrix: C(r,c) = cofactor of A(r,c); A^{-1} = C^T / det
-DEV void cof3(const double *A, double *C) {
+template <typename real>
+DEV void cof3(const real *A, real *C) {
   C[0] = A[4] * A[8] - A[5] * A[7];
   C[1] = A[5] * A[6] - A[3] * A[8];
   C[2] = A[3] * A[7] - A[4] * A[6];
@@ -103,47 +108,51 @@ DEV void cof3(const double *A, double *C) {
 // X <- (zeta X + X^{-T} / zeta) / 2 with determinant scaling while far from
 // convergence (Higham, Functions of Matrices, Sec. 8.3).  A near-rotation
 // converges in two or three iterations.  Returns false if det A <= 0 or the
-// input is not finite.
-DEV bool polar3(const double *A, double *R) {
-  double X[9];
+// input is not finite.  In FP32 the iteration stops once a step is below
+// 1e-5 (the next error is then below FP32 rounding).
+template <typename real>
+DEV bool polar3(const real *A, real *R) {
+  const real stop = sizeof(real) == 8 ? real(1e-16) : real(1e-10);
+  real X[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) X[i] = A[i];
-  double d0 = det3(X);
+  real d0 = det3(X);
   if (!(d0 > 0.0) || !isfinite(d0)) return false;
   bool done = false;
   for (int it = 0; it < 40 && !done; ++it) {
-    double C[9];
+    real C[9];
     cof3(X, C);
-    double det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
-    if (!(det > 0.0)) return false;
-    double z = 1.0;
-    double diff = 0.0;
+    real det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+    if (!(det > real(0))) return false;
+    real z = real(1);
+    real diff = real(0);
     // X^{-T} = C / det
-    double inv = 1.0 / det;
-    double Y[9];
+    real inv = real(1) / det;
+    real Y[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Y[i] = C[i] * inv;
     // scale only while the iterate is far from orthogonal
-    double s0 = 0.0;
+    real s0 = real(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) s0 += (X[i] - Y[i]) * (X[i] - Y[i]);
-    if (s0 > 1e-4) z = 1.0 / cbrt(det);
+    if (s0 > real(1e-4)) z = real(1) / cbrt(det);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      double xn = 0.5 * (z * X[i] + Y[i] / z);
+      real xn = real(0.5) * (z * X[i] + Y[i] / z);
       diff += (xn - X[i]) * (xn - X[i]);
       X[i] = xn;
     }
-    // quadratic convergence: once the step is below 1e-8 the next error is
-    // below roundoff, so this iterate is final
-    if (diff < 1e-16) done = true;
+    // quadratic convergence: once the step is below 1e-8 (FP64) the next
+    // error is below roundoff, so this iterate is final
+    if (diff < stop) done = true;
   }
 #pragma unroll
   for (int i = 0; i < 9; ++i) R[i] = X[i];
   return done;
 }
 
-DEV void mat3_mul(const double *A, const double *B, double *C) {
+template <typename real>
+DEV void mat3_mul(const real *A, const real *B, real *C) {
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -152,7 +161,8 @@ DEV void mat3_mul(const double *A, const double *B, double *C) {
 }
 
 // C = A B^T
-DEV void mat3_mul_bt(const double *A, const double *B, double *C) {
+template <typename real>
+DEV void mat3_mul_bt(const real *A, const real *B, real *C) {
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -161,7 +171,8 @@ DEV void mat3_mul_bt(const double *A, const double *B, double *C) {
 }
 
 // C = A^T B
-DEV void mat3_mul_at(const double *A, const double *B, double *C) {
+template <typename real>
+DEV void mat3_mul_at(const real *A, const real *B, real *C) {
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -169,21 +180,24 @@ DEV void mat3_mul_at(const double *A, const double *B, double *C) {
       C[3 * r + c] = A[r] * B[c] + A[3 + r] * B[3 + c] + A[6 + r] * B[6 + c];
 }
 
-DEV void mat3_vec(const double *A, const double *x, double *y) {
+template <typename real>
+DEV void mat3_vec(const real *A, const real *x, real *y) {
   y[0] = A[0] * x[0] + A[1] * x[1] + A[2] * x[2];
   y[1] = A[3] * x[0] + A[4] * x[1] + A[5] * x[2];
   y[2] = A[6] * x[0] + A[7] * x[1] + A[8] * x[2];
 }
 
-DEV void mat3t_vec(const double *A, const double *x, double *y) {
+template <typename real>
+DEV void mat3t_vec(const real *A, const real *x, real *y) {
   y[0] = A[0] * x[0] + A[3] * x[1] + A[6] * x[2];
   y[1] = A[1] * x[0] + A[4] * x[1] + A[7] * x[2];
   y[2] = A[2] * x[0] + A[5] * x[1] + A[8] * x[2];
 }
 
 // R W R^T for symmetric or general W (full 3x3 out)
-DEV void rot_congr(const double *R, const double *W, double *out) {
-  double T[9];
+template <typename real>
+DEV void rot_congr(const real *R, const real *W, real *out) {
+  real T[9];
   mat3_mul(R, W, T);
   mat3_mul_bt(T, R, out);
 }
@@ -203,6 +217,23 @@ DEV bool spd3_inv(const double *S, double *I) {
   I[2] = I[6] = b;
   I[5] = I[7] = c;
   return true;
+}
+
+// y = Hbar x with Hbar = M_A / h^2 + Kbar_A (Eq. abd_final), Kbar_A =
+// V (mu (I9 + P9) + lambda vec(I) vec(I)^T) on the nine A entries (P9: the
+// transpose permutation), `sh` = {Mbar0, Mbar1, Mbar2, m, V, mu, lambda}
+DEV void hbar_apply(const double *sh, double h, const double *x, double *y) {
+  const double ih2 = 1.0 / (h * h);
+  const double Vmu = sh[4] * sh[5], Vla = sh[4] * sh[6];
+  const double tr = x[0] + x[4] + x[8];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      y[3 * c + r] = sh[c] * ih2 * x[3 * c + r] + Vmu * (x[3 * c + r] + x[3 * r + c]) +
+                     (r == c ? Vla * tr : 0.0);
+#pragma unroll
+  for (int i = 9; i < 12; ++i) y[i] = sh[3] * ih2 * x[i];
 }
 
 // --------------------------------------------------------------- body force

@@ -18,6 +18,8 @@
 // repeats A-C, back-substitutes the tile, and writes lambda and the new state.
 // Recomputing A-C costs one more read of q, qdot but no HBM traffic for the
 // elimination factors.
+#include <type_traits>
+
 #include "common.hpp"
 #include "dmath.hpp"
 
@@ -160,10 +162,19 @@ DEV void tile_cr_backward(double *lds, bool row_active, int li, int T, int elim_
   }
 }
 
-template <bool APPLY, int NT>
+// MODE 0: plain FP64.  MODE 1 (precision form 1, first solve): phase A in
+// FP32, the factor in FP64, the increment goes to dq.  MODE 2 (form 1
+// correction): the right-hand side is the FP64 KKT residual (rp, rd) of the
+// current iterate and the increment is added to dq and lam; skipped once the
+// residual check has converged.
+template <int MODE, bool APPLY, int NT>
 __global__ __launch_bounds__(NT) void chain_tile_kernel(ChainArgs a) {
+  using breal = typename std::conditional<MODE == 0, double, float>::type;
   __shared__ double lds[S_N * NT];
   if (skip_step(a.status, a.step)) return;
+  if constexpr (MODE == 2) {
+    if (a.ir[0] != 0.0) return;
+  }
   const TileDesc td = a.tiles[blockIdx.x];
   const ChainDesc cd = a.chains[td.chain];
   const int t = threadIdx.x;
@@ -179,7 +190,7 @@ __global__ __launch_bounds__(NT) void chain_tile_kernel(ChainArgs a) {
   const int64_t bg = (int64_t)cd.body0 + p;
 
   // ---------------------------------------------------------------- phase A
-  double R[9], u[12];
+  breal R[9], u[12];
   double pa[3] = {0, 0, 0}, pb[3] = {0, 0, 0};
   double sa = 1.0, sb = 1.0;
   double Waa[6] = {0, 0, 0, 0, 0, 0}, Wab[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -195,12 +206,9 @@ __global__ __launch_bounds__(NT) void chain_tile_kernel(ChainArgs a) {
     sb = (a.flag[grb] & 1) ? 1.0 : -1.0;
   }
   if (has_body) {
-    double q[12], qd[12];
+    double q[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      q[c] = a.q[c * a.ns + bg];
-      qd[c] = a.qd[c * a.ns + bg];
-    }
+    for (int c = 0; c < 12; ++c) q[c] = a.q[c * a.ns + bg];
     const int s = a.shp[bg];
     T_h = a.hinv + (int64_t)HINV_STRIDE * s;
     const double *sh = a.shape + (int64_t)SHAPE_STRIDE * s;
@@ -209,54 +217,90 @@ __global__ __launch_bounds__(NT) void chain_tile_kernel(ChainArgs a) {
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int c = 0; c < 3; ++c) A[3 * i + c] = q[3 * c + i];
-    if (!polar3(A, R)) {
+    breal Ab[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Ab[i] = breal(A[i]);
+    if (!polar3(Ab, R)) {
       raise_flag(a.status, FLAG_NONFINITE, a.step);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+      for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? breal(1) : breal(0);
     }
-    double phi[12];
-    local_force<double>(sh, R, A, q, q, qd, a.g, a.h, phi);
+    breal phi[12];
+    if constexpr (MODE == 2) {
+      // rotated FP64 primal residual of the current iterate
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        breal w[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) w[i] = breal(a.rp[(3 * c + i) * a.ns + bg]);
+        mat3t_vec(R, w, phi + 3 * c);
+      }
+    } else {
+      breal qb[12], qdb[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        qb[c] = breal(q[c]);
+        qdb[c] = breal(a.qd[c * a.ns + bg]);
+      }
+      local_force<breal>(sh, R, Ab, qb, qb, qdb, a.g, a.h, phi);
+    }
     hinv_apply(T_h, phi, u);
+    const breal paf[3] = {breal(pa[0]), breal(pa[1]), breal(pa[2])};
+    const breal pbf[3] = {breal(pb[0]), breal(pb[1]), breal(pb[2])};
     if (has_a) {
-      double W[9], RW[9];
-      wblock(T_h, pa, pa, W);
+      breal W[9], RW[9];
+      wblock(T_h, paf, paf, W);
       rot_congr(R, W, RW);
-      sym_from_full(RW, Waa);
-      double Ju[3], Ap[3];
+      double RWd[9];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) Ju[i] = pa[0] * u[i] + pa[1] * u[3 + i] + pa[2] * u[6 + i] + u[9 + i];
-      mat3_vec(R, Ju, va);
-      mat3_vec(A, pa, Ap);
+      for (int i = 0; i < 9; ++i) RWd[i] = double(RW[i]);
+      sym_from_full(RWd, Waa);
+      breal Ju[3], vv[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        va[i] *= sa;
-        ca[i] = sa * Ap[i];
-        ta[i] = sa * q[9 + i];
+      for (int i = 0; i < 3; ++i) Ju[i] = paf[0] * u[i] + paf[1] * u[3 + i] + paf[2] * u[6 + i] + u[9 + i];
+      mat3_vec(R, Ju, vv);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) va[i] = double(vv[i]) * sa;
+      if constexpr (MODE != 2) {
+        double Ap[3];
+        mat3_vec(A, pa, Ap);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          ca[i] = sa * Ap[i];
+          ta[i] = sa * q[9 + i];
+        }
       }
     }
     if (has_b) {
-      double W[9], RW[9];
-      wblock(T_h, pb, pb, W);
+      breal W[9], RW[9];
+      wblock(T_h, pbf, pbf, W);
       rot_congr(R, W, RW);
-      sym_from_full(RW, Wbb);
-      double Ju[3], Ap[3];
+      double RWd[9];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) Ju[i] = pb[0] * u[i] + pb[1] * u[3 + i] + pb[2] * u[6 + i] + u[9 + i];
-      mat3_vec(R, Ju, vb);
-      mat3_vec(A, pb, Ap);
+      for (int i = 0; i < 9; ++i) RWd[i] = double(RW[i]);
+      sym_from_full(RWd, Wbb);
+      breal Ju[3], vv[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        vb[i] *= sb;
-        cb[i] = sb * Ap[i];
-        tb[i] = sb * q[9 + i];
+      for (int i = 0; i < 3; ++i) Ju[i] = pbf[0] * u[i] + pbf[1] * u[3 + i] + pbf[2] * u[6 + i] + u[9 + i];
+      mat3_vec(R, Ju, vv);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) vb[i] = double(vv[i]) * sb;
+      if constexpr (MODE != 2) {
+        double Ap[3];
+        mat3_vec(A, pb, Ap);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          cb[i] = sb * Ap[i];
+          tb[i] = sb * q[9 + i];
+        }
       }
     }
     if (has_a && has_b) {
-      double W[9];
-      wblock(T_h, pa, pb, W);
-      rot_congr(R, W, Wab);
+      breal W[9], RW[9];
+      wblock(T_h, paf, pbf, W);
+      rot_congr(R, W, RW);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) Wab[i] *= sa * sb;
+      for (int i = 0; i < 9; ++i) Wab[i] = double(RW[i]) * (sa * sb);
     }
   } else {
     // world end: only the constant point enters C
@@ -290,10 +334,14 @@ __global__ __launch_bounds__(NT) void chain_tile_kernel(ChainArgs a) {
     for (int i = 0; i < 6; ++i) D[i] = Waa[i] + lds[(S_WBB + i) * NT + tp];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      // C = (translation difference) + (rotated anchor difference)
-      double C = (lds[(S_TB + i) * NT + tp] + ta[i]) +
-                 (lds[(S_CB + i) * NT + tp] + ca[i]);
-      b[i] = va[i] + lds[(S_VB + i) * NT + tp] + C;
+      if constexpr (MODE == 2) {
+        b[i] = va[i] + lds[(S_VB + i) * NT + tp] - a.rd[i * a.nrs + gra];
+      } else {
+        // C = (translation difference) + (rotated anchor difference)
+        double C = (lds[(S_TB + i) * NT + tp] + ta[i]) +
+                   (lds[(S_CB + i) * NT + tp] + ca[i]);
+        b[i] = va[i] + lds[(S_VB + i) * NT + tp] + C;
+      }
     }
     // left coupling = (U of the previous row)^T
     if (li >= 1) {
@@ -353,58 +401,68 @@ __global__ __launch_bounds__(NT) void chain_tile_kernel(ChainArgs a) {
     const bool last_tile = td.tidx == cd.ntile - 1;
     if (row_active && (li < T || last_tile)) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) a.lam[3 * gra + i] = lds[(S_X + i) * NT + li];
+      for (int i = 0; i < 3; ++i) {
+        if constexpr (MODE == 2) a.lam[3 * gra + i] += lds[(S_X + i) * NT + li];
+        else a.lam[3 * gra + i] = lds[(S_X + i) * NT + li];
+      }
     }
     // -------------------------------------------------- body back-projection
     bool own = has_body && ((t >= 1 && t <= T) || (t == 0 && td.tidx == 0) ||
                             (t == T + 1 && last_tile));
     if (own) {
-      double g12[12];
+      breal g12[12];
 #pragma unroll
-      for (int i = 0; i < 12; ++i) g12[i] = 0.0;
+      for (int i = 0; i < 12; ++i) g12[i] = breal(0);
       if (has_a) {  // row r is local row t-1
-        double lamv[3], w[3];
+        breal lamv[3], w[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) lamv[i] = lds[(S_X + i) * NT + (t - 1)];
+        for (int i = 0; i < 3; ++i) lamv[i] = breal(lds[(S_X + i) * NT + (t - 1)]);
         mat3t_vec(R, lamv, w);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          w[i] *= sa;
-          g12[i] += pa[0] * w[i];
-          g12[3 + i] += pa[1] * w[i];
-          g12[6 + i] += pa[2] * w[i];
+          w[i] *= breal(sa);
+          g12[i] += breal(pa[0]) * w[i];
+          g12[3 + i] += breal(pa[1]) * w[i];
+          g12[6 + i] += breal(pa[2]) * w[i];
           g12[9 + i] += w[i];
         }
       }
       if (has_b) {  // row r+1 is local row t
-        double lamv[3], w[3];
+        breal lamv[3], w[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) lamv[i] = lds[(S_X + i) * NT + t];
+        for (int i = 0; i < 3; ++i) lamv[i] = breal(lds[(S_X + i) * NT + t]);
         mat3t_vec(R, lamv, w);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          w[i] *= sb;
-          g12[i] += pb[0] * w[i];
-          g12[3 + i] += pb[1] * w[i];
-          g12[6 + i] += pb[2] * w[i];
+          w[i] *= breal(sb);
+          g12[i] += breal(pb[0]) * w[i];
+          g12[3 + i] += breal(pb[1]) * w[i];
+          g12[6 + i] += breal(pb[2]) * w[i];
           g12[9 + i] += w[i];
         }
       }
-      double hg[12];
+      breal hg[12];
       hinv_apply(T_h, g12, hg);
       const double ih = 1.0 / a.h;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        double dp[3], dq[3];
+        breal dp[3], dqv[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) dp[i] = u[3 * c + i] - hg[3 * c + i];
-        mat3_vec(R, dp, dq);
+        mat3_vec(R, dp, dqv);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
           const int64_t o = (int64_t)(3 * c + i) * a.ns + bg;
-          a.q_out[o] = a.q[o] + dq[i];
-          a.qd_out[o] = dq[i] * ih;
-          if (!isfinite(dq[i])) raise_flag(a.status, FLAG_NONFINITE, a.step);
+          const double d = double(dqv[i]);
+          if constexpr (MODE == 0) {
+            a.q_out[o] = a.q[o] + d;
+            a.qd_out[o] = d * ih;
+          } else if constexpr (MODE == 1) {
+            a.dq[o] = d;
+          } else {
+            a.dq[o] += d;
+          }
+          if (!isfinite(d)) raise_flag(a.status, FLAG_NONFINITE, a.step);
         }
       }
     }
@@ -520,9 +578,10 @@ DEV void top_solve(double *lds, const ChainDesc &cd, const double *grouprec, dou
 template <bool APPLY>
 __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
     const ChainDesc *chains, const GroupDesc *groups, const double *tilerec, double *grouprec,
-    double *xtop, double *xg, int *counters, uint32_t *status, int step) {
+    double *xtop, double *xg, int *counters, uint32_t *status, int step, const double *ir) {
   __shared__ double lds[S_N * CHAIN_THREADS];
   if (skip_step(status, step)) return;
+  if (ir && ir[0] != 0.0) return;  // form 1 correction after convergence
   const GroupDesc gd = groups[blockIdx.x];
   const ChainDesc cd = chains[gd.chain];
   const int li = threadIdx.x;
@@ -600,8 +659,10 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
 // solved by block cyclic reduction in global scratch (one workgroup per chain).
 __global__ __launch_bounds__(1024) void chain_global_kernel(const ChainDesc *chains,
                                                            const double *tilerec, double *scr,
-                                                           double *xg, uint32_t *status, int step) {
+                                                           double *xg, uint32_t *status, int step,
+                                                           const double *ir) {
   if (skip_step(status, step)) return;
+  if (ir && ir[0] != 0.0) return;
   const ChainDesc cd = chains[blockIdx.x];
   // top system: the rows that bound the groups (records in tilerec = group records)
   const int n = cd.ngroup + 1;
@@ -721,38 +782,300 @@ __global__ __launch_bounds__(1024) void chain_global_kernel(const ChainDesc *cha
   }
 }
 
-template <bool APPLY>
+// ------------------------------------------------------------------ form 1
+// FP64 KKT residual of the current iterate (q + dq, lam) on the chain rows and
+// bodies: r_p = f_A - H dq - G^T lam per body (world frame) and
+// r_d = -(C + G dq) per row, and per tile the sums behind
+// rho_p = |H^{-1} r_p| / |H^{-1} f_A| and rho_d = |r_d| / |G H^{-1} f_A + C|
+// (the KKT residual of Eq. kkt with the -C right-hand side).
+template <int NT>
+__global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
+  enum { L_VB = 0, L_CB = 3, L_TB = 6, L_GB = 9, L_RED = 12 };
+  __shared__ double lds[16 * NT];
+  if (skip_step(a.status, a.step)) return;
+  if (a.ir[0] != 0.0) return;
+  const TileDesc td = a.tiles[blockIdx.x];
+  const ChainDesc cd = a.chains[td.chain];
+  const int t = threadIdx.x;
+  const int T = td.T;
+  const int r = td.r0 + t - 1;
+  const int p = r + 1 - cd.hl;
+  const bool in_tile = t <= T + 1;
+  const bool has_body = in_tile && p >= 0 && p < cd.nb;
+  const bool has_a = in_tile && r >= 0 && r < cd.K;
+  const bool has_b = in_tile && r + 1 < cd.K;
+  const int64_t gra = (int64_t)cd.row0 + r;
+  const int64_t grb = gra + 1;
+  const int64_t bg = (int64_t)cd.body0 + p;
+  const bool last_tile = td.tidx == cd.ntile - 1;
+  const bool own = has_body && ((t >= 1 && t <= T) || (t == 0 && td.tidx == 0) ||
+                                (t == T + 1 && last_tile));
+  double pa[3] = {0, 0, 0}, pb[3] = {0, 0, 0}, la[3] = {0, 0, 0}, lb[3] = {0, 0, 0};
+  double sa = 1.0, sb = 1.0;
+  double va[3] = {0, 0, 0}, ca[3] = {0, 0, 0}, ta[3] = {0, 0, 0}, ga[3] = {0, 0, 0};
+  double vb[3] = {0, 0, 0}, cb[3] = {0, 0, 0}, tb[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
+  double sp = 0.0, sf = 0.0, sr = 0.0, sd = 0.0;
+  if (has_a) {
+    for (int i = 0; i < 3; ++i) {
+      pa[i] = a.pr[i * a.nrs + gra];
+      la[i] = a.lam[3 * gra + i];
+    }
+    sa = (a.flag[gra] & 2) ? 1.0 : -1.0;
+  }
+  if (has_b) {
+    for (int i = 0; i < 3; ++i) {
+      pb[i] = a.pl[i * a.nrs + grb];
+      lb[i] = a.lam[3 * grb + i];
+    }
+    sb = (a.flag[grb] & 1) ? 1.0 : -1.0;
+  }
+  if (has_body) {
+    double q[12], qd[12], dq[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      q[c] = a.q[c * a.ns + bg];
+      qd[c] = a.qd[c * a.ns + bg];
+      dq[c] = a.dq[c * a.ns + bg];
+    }
+    const int s = a.shp[bg];
+    const double *T_h = a.hinv + (int64_t)HINV_STRIDE * s;
+    const double *sh = a.shape + (int64_t)SHAPE_STRIDE * s;
+    double A[9], R[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) A[3 * i + c] = q[3 * c + i];
+    if (!polar3(A, R)) {
+      raise_flag(a.status, FLAG_NONFINITE, a.step);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    }
+    double phi[12], u[12];
+    local_force<double>(sh, R, A, q, q, qd, a.g, a.h, phi);
+    hinv_apply(T_h, phi, u);
+    // r_p = diag4(R) (phi - Hbar diag4(R^T) dq) - G^T lam
+    double dl[12], Hd[12], rw[12];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) mat3t_vec(R, dq + 3 * c, dl + 3 * c);
+    hbar_apply(sh, a.h, dl, Hd);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double e[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) e[i] = phi[3 * c + i] - Hd[3 * c + i];
+      mat3_vec(R, e, rw + 3 * c);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double wa = has_a ? sa * la[i] : 0.0, wb = has_b ? sb * lb[i] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rw[3 * c + i] -= pa[c] * wa + pb[c] * wb;
+      rw[9 + i] -= wa + wb;
+    }
+    if (own) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) a.rp[c * a.ns + bg] = rw[c];
+      double rl[12], y[12];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) mat3t_vec(R, rw + 3 * c, rl + 3 * c);
+      hinv_apply(T_h, rl, y);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        sp += y[k] * y[k];
+        sf += u[k] * u[k];
+      }
+    }
+    if (has_a) {
+      double Ju[3], Ap[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) Ju[i] = pa[0] * u[i] + pa[1] * u[3 + i] + pa[2] * u[6 + i] + u[9 + i];
+      mat3_vec(R, Ju, va);
+      mat3_vec(A, pa, Ap);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        va[i] *= sa;
+        ca[i] = sa * Ap[i];
+        ta[i] = sa * q[9 + i];
+        ga[i] = sa * (pa[0] * dq[i] + pa[1] * dq[3 + i] + pa[2] * dq[6 + i] + dq[9 + i]);
+      }
+    }
+    if (has_b) {
+      double Ju[3], Ap[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) Ju[i] = pb[0] * u[i] + pb[1] * u[3 + i] + pb[2] * u[6 + i] + u[9 + i];
+      mat3_vec(R, Ju, vb);
+      mat3_vec(A, pb, Ap);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        vb[i] *= sb;
+        cb[i] = sb * Ap[i];
+        tb[i] = sb * q[9 + i];
+        gb[i] = sb * (pb[0] * dq[i] + pb[1] * dq[3 + i] + pb[2] * dq[6 + i] + dq[9 + i]);
+      }
+    }
+  } else {
+    // world end: only the constant point enters C
+    if (has_a)
+      for (int i = 0; i < 3; ++i) ca[i] = sa * pa[i];
+    if (has_b)
+      for (int i = 0; i < 3; ++i) cb[i] = sb * pb[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    lds[(L_VB + i) * NT + t] = vb[i];
+    lds[(L_CB + i) * NT + t] = cb[i];
+    lds[(L_TB + i) * NT + t] = tb[i];
+    lds[(L_GB + i) * NT + t] = gb[i];
+  }
+  __syncthreads();
+  const int li = t - 1;
+  if (t >= 1 && t <= T + 1 && (li < T || last_tile)) {
+    const int tp = t - 1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double C = (lds[(L_TB + i) * NT + tp] + ta[i]) + (lds[(L_CB + i) * NT + tp] + ca[i]);
+      const double rk = va[i] + lds[(L_VB + i) * NT + tp] + C;
+      const double rdv = -(C + (ga[i] + lds[(L_GB + i) * NT + tp]));
+      a.rd[i * a.nrs + gra] = rdv;
+      sr += rk * rk;
+      sd += rdv * rdv;
+    }
+  }
+  lds[(L_RED + 0) * NT + t] = sp;
+  lds[(L_RED + 1) * NT + t] = sf;
+  lds[(L_RED + 2) * NT + t] = sr;
+  lds[(L_RED + 3) * NT + t] = sd;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w /= 2) {
+    if (t < w)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) lds[(L_RED + k) * NT + t] += lds[(L_RED + k) * NT + t + w];
+    __syncthreads();
+  }
+  if (t < 4) a.part[4 * (int64_t)blockIdx.x + t] = lds[(L_RED + t) * NT];
+}
+
+// Sums the tile partials in a fixed order and decides: converged (KKT
+// residual <= tol: later corrections and checks of this step do nothing),
+// stalled at the rounding floor (likewise), another correction sweep, or, at
+// the final check, NOT_CONVERGED.
+__global__ __launch_bounds__(256) void chain_ir_check_kernel(const double *part, int nblk, double tol,
+                                                             int final_check, double *ir,
+                                                             uint32_t *status) {
+  __shared__ double red[4 * 256];
+  if (skip_step(status, 0)) return;
+  if (ir[0] != 0.0) return;
+  const int t = threadIdx.x;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = t; b < nblk; b += 256)
+    for (int k = 0; k < 4; ++k) s[k] += part[4 * (int64_t)b + k];
+  for (int k = 0; k < 4; ++k) red[k * 256 + t] = s[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w /= 2) {
+    if (t < w)
+      for (int k = 0; k < 4; ++k) red[k * 256 + t] += red[k * 256 + t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double np = red[0], nf = red[256], nr = red[512], nd = red[768];
+    const double rp = nf > 0.0 ? sqrt(np / nf) : sqrt(np);
+    const double rdd = nr > 0.0 ? sqrt(nd / nr) : sqrt(nd);
+    const double kkt = rp > rdd ? rp : rdd;
+    ir[2] = rp;
+    ir[3] = rdd;
+    ir[4] = kkt;
+    if (!isfinite(rp) || !isfinite(rdd)) raise_flag(status, FLAG_NONFINITE, 0);
+    else if (kkt <= tol) ir[0] = 1.0;
+    // a sweep that no longer halves the residual has reached the FP64
+    // rounding floor of the residual itself: stop there
+    else if (ir[1] > 0.0 && kkt > 0.5 * ir[5]) ir[0] = 2.0;
+    else if (final_check) raise_flag(status, FLAG_NOTCONV, 0);
+    else ir[1] += 1.0;  // a correction sweep follows
+    ir[5] = kkt;
+  }
+}
+
+__global__ void chain_ir_reset_kernel(double *ir) {
+  ir[0] = 0.0;
+  ir[1] = 0.0;
+}
+
+// q_out = q + dq, qdot_out = dq / h for the chain bodies (form 1)
+__global__ void chain_finish_kernel(const double *q, const double *dq, double *q_out, double *qd_out,
+                                    int64_t ns, int nb, double h, uint32_t *status) {
+  if (skip_step(status, 0)) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 12 * (int64_t)nb) return;
+  const int64_t c = i / nb;
+  const int64_t o = c * ns + (i - c * nb);
+  const double d = dq[o];
+  q_out[o] = q[o] + d;
+  qd_out[o] = d * (1.0 / h);
+  if (!isfinite(d)) raise_flag(status, FLAG_NONFINITE, 0);
+}
+
+template <int MODE, bool APPLY>
 static void launch_tiles(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
   if (ntiles <= 0) return;
   if (nt == 64)
-    hipLaunchKernelGGL((chain_tile_kernel<APPLY, 64>), dim3(ntiles), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 64>), dim3(ntiles), dim3(64), 0, s, a);
   else if (nt == 128)
-    hipLaunchKernelGGL((chain_tile_kernel<APPLY, 128>), dim3(ntiles), dim3(128), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 128>), dim3(ntiles), dim3(128), 0, s, a);
   else
-    hipLaunchKernelGGL((chain_tile_kernel<APPLY, 256>), dim3(ntiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 256>), dim3(ntiles), dim3(256), 0, s, a);
 }
-void launch_chain_reduce(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
-  launch_tiles<false>(a, ntiles, nt, s);
+template <bool APPLY>
+static void launch_tiles_mode(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s) {
+  if (mode == 0) launch_tiles<0, APPLY>(a, ntiles, nt, s);
+  else if (mode == 1) launch_tiles<1, APPLY>(a, ntiles, nt, s);
+  else launch_tiles<2, APPLY>(a, ntiles, nt, s);
 }
-void launch_chain_apply(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
-  launch_tiles<true>(a, ntiles, nt, s);
+void launch_chain_reduce(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s) {
+  launch_tiles_mode<false>(a, ntiles, nt, mode, s);
+}
+void launch_chain_apply(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s) {
+  launch_tiles_mode<true>(a, ntiles, nt, mode, s);
 }
 void launch_chain_group(bool apply, const ChainDesc *chains, const GroupDesc *groups, int ngroups,
                         const double *tilerec, double *grouprec, double *xtop, double *xg,
-                        int *counters, uint32_t *status, int step, hipStream_t s) {
+                        int *counters, uint32_t *status, int step, const double *ir, hipStream_t s) {
   if (ngroups <= 0) return;
   if (apply)
     hipLaunchKernelGGL(chain_group_kernel<true>, dim3(ngroups), dim3(CHAIN_THREADS), 0, s, chains,
-                       groups, tilerec, grouprec, xtop, xg, counters, status, step);
+                       groups, tilerec, grouprec, xtop, xg, counters, status, step, ir);
   else
     hipLaunchKernelGGL(chain_group_kernel<false>, dim3(ngroups), dim3(CHAIN_THREADS), 0, s, chains,
-                       groups, tilerec, grouprec, xtop, xg, counters, status, step);
+                       groups, tilerec, grouprec, xtop, xg, counters, status, step, ir);
 }
 void launch_chain_global(const ChainDesc *chains, int nchains, const double *tilerec, double *scr,
-                         double *xg, uint32_t *status, int step, hipStream_t s) {
+                         double *xg, uint32_t *status, int step, const double *ir, hipStream_t s) {
   if (nchains > 0)
     hipLaunchKernelGGL(chain_global_kernel, dim3(nchains), dim3(1024), 0, s, chains, tilerec, scr,
-                       xg, status, step);
+                       xg, status, step, ir);
+}
+void launch_chain_resid(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
+  if (ntiles <= 0) return;
+  if (nt == 64)
+    hipLaunchKernelGGL(chain_resid_kernel<64>, dim3(ntiles), dim3(64), 0, s, a);
+  else if (nt == 128)
+    hipLaunchKernelGGL(chain_resid_kernel<128>, dim3(ntiles), dim3(128), 0, s, a);
+  else
+    hipLaunchKernelGGL(chain_resid_kernel<256>, dim3(ntiles), dim3(256), 0, s, a);
+}
+void launch_chain_ir_check(const double *part, int nblk, double tol, int final_check, double *ir,
+                           uint32_t *status, hipStream_t s) {
+  hipLaunchKernelGGL(chain_ir_check_kernel, dim3(1), dim3(256), 0, s, part, nblk, tol, final_check,
+                     ir, status);
+}
+void launch_chain_ir_reset(double *ir, hipStream_t s) {
+  hipLaunchKernelGGL(chain_ir_reset_kernel, dim3(1), dim3(1), 0, s, ir);
+}
+void launch_chain_finish(const double *q, const double *dq, double *q_out, double *qd_out, int64_t ns,
+                         int nb, double h, uint32_t *status, hipStream_t s) {
+  if (nb <= 0) return;
+  const int64_t n = 12 * (int64_t)nb;
+  hipLaunchKernelGGL(chain_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, q, dq,
+                     q_out, qd_out, ns, nb, h, status);
 }
 
 }  // namespace mabd

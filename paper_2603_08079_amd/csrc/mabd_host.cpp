@@ -21,13 +21,19 @@
 
 namespace mabd {
 
-void launch_chain_reduce(const ChainArgs &a, int ntiles, int nt, hipStream_t s);
-void launch_chain_apply(const ChainArgs &a, int ntiles, int nt, hipStream_t s);
+void launch_chain_reduce(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s);
+void launch_chain_apply(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s);
 void launch_chain_global(const ChainDesc *chains, int nchains, const double *tilerec, double *scr,
-                         double *xg, uint32_t *status, int step, hipStream_t s);
+                         double *xg, uint32_t *status, int step, const double *ir, hipStream_t s);
 void launch_chain_group(bool apply, const ChainDesc *chains, const GroupDesc *groups, int ngroups,
                         const double *tilerec, double *grouprec, double *xtop, double *xg,
-                        int *counters, uint32_t *status, int step, hipStream_t s);
+                        int *counters, uint32_t *status, int step, const double *ir, hipStream_t s);
+void launch_chain_resid(const ChainArgs &a, int ntiles, int nt, hipStream_t s);
+void launch_chain_ir_check(const double *part, int nblk, double tol, int final_check, double *ir,
+                           uint32_t *status, hipStream_t s);
+void launch_chain_ir_reset(double *ir, hipStream_t s);
+void launch_chain_finish(const double *q, const double *dq, double *q_out, double *qd_out, int64_t ns,
+                         int nb, double h, uint32_t *status, hipStream_t s);
 void launch_prefactor(const double *shape, int nshape, double h, double *hinv, hipStream_t s);
 void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
                   const int32_t *shp, const double *hinv, const double *shape, const double *g,
@@ -183,6 +189,9 @@ struct mabd_ctx {
   int32_t *d_pcg_it = nullptr;
   int pcg_blocks = 0;
   double *h_pcg = nullptr;
+  // precision form 1 on the chains
+  double *d_dq = nullptr, *d_rp = nullptr, *d_rd = nullptr, *d_part = nullptr, *d_ir = nullptr;
+  double *h_ir = nullptr;
   double *d_pin_q0 = nullptr, *d_tmp = nullptr;
   uint32_t *d_status = nullptr;
   uint32_t *h_status = nullptr;
@@ -258,7 +267,7 @@ struct PhaseTimer {
     c->ev_marks.emplace_back(phase, (int)used - 2);
   }
   void collect() {
-    for (int i = 0; i < 8; ++i) { c->stats.phase_ms[i] = 0.0; c->stats.phase_calls[i] = 0; }
+    for (int i = 0; i < MABD_NPHASES; ++i) { c->stats.phase_ms[i] = 0.0; c->stats.phase_calls[i] = 0; }
     if (!on) return;
     for (auto &pm : c->ev_marks) {
       float ms = 0.f;
@@ -340,6 +349,7 @@ void mabd_options_default(mabd_options *o) {
   o->diagnostics = 0;
   o->use_graph = 1;
   o->autotune = 1;
+  o->ir_max_sweeps = 4;
   o->stream = nullptr;
 }
 
@@ -354,6 +364,7 @@ void mabd_destroy(mabd_ctx *c) {
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->h_status) (void)hipHostFree(c->h_status);
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
+  if (c->h_ir) (void)hipHostFree(c->h_ir);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -382,7 +393,10 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     return fail(nullptr, MABD_ERR_INVALID_ARG, "material 1 needs poisson");
   if (opt.hinge_grad != 0 && opt.hinge_grad != 2)
     return fail(nullptr, MABD_ERR_INVALID_ARG, "hinge_grad must be 0 or 2");
-  if (opt.precision != 0) return fail(nullptr, MABD_ERR_INVALID_ARG, "precision 1 is not available");
+  if (opt.precision != 0 && opt.precision != 1)
+    return fail(nullptr, MABD_ERR_INVALID_ARG, "precision must be 0 or 1");
+  if (opt.ir_max_sweeps < 0 || opt.ir_max_sweeps > 16)
+    return fail(nullptr, MABD_ERR_INVALID_ARG, "ir_max_sweeps must be in 0..16");
   if (!finite_all(opt.gravity, 3)) return fail(nullptr, MABD_ERR_INVALID_ARG, "gravity not finite");
   // ------------------------------------------------------------ validate
   for (int i = 0; i < n; ++i) {
@@ -819,13 +833,6 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(dalloc(c, &c->d_hinv, (size_t)HINV_STRIDE * c->nshape));
   if (e == hipSuccess) chk(upload(c, &c->d_chains, c->chains));
   if (e == hipSuccess) chk(upload(c, &c->d_tiles, c->tiles));
-  if (const char *tt = std::getenv("MABD_CHAIN_TILE_THREADS")) {
-    const int v = std::atoi(tt);
-    if (v == 64 || v == 128 || v == 256) {
-      c->tuned = true;  // fixed by the environment: no autotuning
-      if (e == hipSuccess && v != 64) chk(build_tiles(c, v));
-    }
-  }
   const int64_t nrs = std::max<int64_t>(c->nchain_rows, 1);
   {
     std::vector<double> spl(3 * nrs, 0.0), spr(3 * nrs, 0.0);
@@ -847,6 +854,15 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(dalloc(c, &c->d_grow, (size_t)GROW_REC * c->ntop));
   if (e == hipSuccess) chk(dalloc(c, &c->d_xg, (size_t)3 * c->ngrows));
   if (e == hipSuccess) chk(dalloc(c, &c->d_clam, (size_t)3 * nrs));
+  if (opt.precision == 1 && !c->chains.empty()) {
+    if (e == hipSuccess) chk(dalloc(c, &c->d_dq, (size_t)12 * ns));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_rp, (size_t)12 * ns));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_rd, (size_t)3 * nrs));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_part, (size_t)4 * c->tiles.size()));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_ir, 8));
+    if (e == hipSuccess) chk(hipMemset(c->d_ir, 0, 8 * sizeof(double)));
+    if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_ir, 8 * sizeof(double)));
+  }
   if (e == hipSuccess) chk(upload(c, &c->d_gj, c->gj));
   const size_t mg = c->gj.size();
   if (e == hipSuccess) chk(dalloc(c, &c->d_gl, GL_STRIDE * mg));
@@ -895,6 +911,14 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess && mg) chk(hipMemset(c->d_glam, 0, 5 * mg * sizeof(double)));
   if (e == hipSuccess) chk(dalloc(c, &c->d_status, 4));
   if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_status, 4 * sizeof(uint32_t)));
+  // after every buffer is sized for the smallest tiles
+  if (const char *tt = std::getenv("MABD_CHAIN_TILE_THREADS")) {
+    const int v = std::atoi(tt);
+    if (v == 64 || v == 128 || v == 256) {
+      c->tuned = true;  // fixed by the environment: no autotuning
+      if (e == hipSuccess && v != 64) chk(build_tiles(c, v));
+    }
+  }
   if (e != hipSuccess) {
     mabd_status st = (e == hipErrorOutOfMemory) ? MABD_ERR_OOM : MABD_ERR_DEVICE;
     std::string msg = std::string("device setup failed: ") + hipGetErrorString(e);
@@ -946,17 +970,49 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
     ca.lam = c->d_clam;
     ca.status = c->d_status;
     ca.step = 0;
-    tm.run(0, [&] { launch_chain_reduce(ca, (int)c->tiles.size(), c->tile_threads, s); });
-    tm.run(1, [&] {
-      launch_chain_group(false, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
-                         c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, 0, s);
-      if (!c->top_in_group)
-        launch_chain_global(c->d_chains, (int)c->chains.size(), c->d_grouprec, c->d_grow,
-                            c->d_xtop, c->d_status, 0, s);
-      launch_chain_group(true, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
-                         c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, 0, s);
-    });
-    tm.run(2, [&] { launch_chain_apply(ca, (int)c->tiles.size(), c->tile_threads, s); });
+    ca.dq = c->d_dq;
+    ca.rp = c->d_rp;
+    ca.rd = c->d_rd;
+    ca.part = c->d_part;
+    ca.ir = c->d_ir;
+    const int ntl = (int)c->tiles.size(), tt = c->tile_threads;
+    // one chain solve: tile reduction, interface solve, tile back-substitution
+    auto solve = [&](int mode) {
+      const double *irs = mode == 2 ? c->d_ir : nullptr;
+      tm.run(0, [&] { launch_chain_reduce(ca, ntl, tt, mode, s); });
+      tm.run(1, [&] {
+        launch_chain_group(false, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
+                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, 0, irs, s);
+        if (!c->top_in_group)
+          launch_chain_global(c->d_chains, (int)c->chains.size(), c->d_grouprec, c->d_grow,
+                              c->d_xtop, c->d_status, 0, irs, s);
+        launch_chain_group(true, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
+                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, 0, irs, s);
+      });
+      tm.run(2, [&] { launch_chain_apply(ca, ntl, tt, mode, s); });
+    };
+    if (c->opt.precision == 0) {
+      solve(0);
+    } else {
+      // form 1: FP32 body/assembly solve, then FP64 KKT residual checks and
+      // correction sweeps (each a solve with the residual as right-hand side)
+      // until the KKT residual is <= kkt_tol
+      launch_chain_ir_reset(c->d_ir, s);
+      solve(1);
+      const int nsw = c->opt.ir_max_sweeps;
+      for (int sw = 0; sw <= nsw; ++sw) {
+        const int final_check = sw == nsw ? 1 : 0;
+        tm.run(8, [&] {
+          launch_chain_resid(ca, ntl, tt, s);
+          launch_chain_ir_check(c->d_part, ntl, c->opt.kkt_tol, final_check, c->d_ir, c->d_status, s);
+        });
+        if (!final_check) solve(2);
+      }
+      tm.run(9, [&] {
+        launch_chain_finish(c->d_q[a], c->d_dq, c->d_q[b], c->d_qd[b], c->ns, c->nchain_bodies, h,
+                            c->d_status, s);
+      });
+    }
   }
   if (c->gb1 > c->gb0) {
     for (int it = 0; it < c->opt.newton_iters; ++it) {
@@ -1138,6 +1194,8 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
     c->cur = b;
   }
   hipError_t e = hipMemcpyAsync(c->h_status, c->d_status, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && c->d_ir)
+    e = hipMemcpyAsync(c->h_ir, c->d_ir, 5 * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess && c->ngraph > 0) {
     e = hipMemcpyAsync(c->h_pcg, c->d_pcg_res, sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
@@ -1151,6 +1209,13 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
     std::memcpy(&its, c->h_pcg + 1, sizeof its);
     c->stats.pcg_iters = its;
     c->stats.rho_d = c->h_pcg[0];
+  }
+  if (c->d_ir) {
+    // FP64 KKT residual of the chains reached by the last step (form 1)
+    c->stats.ir_sweeps = (int32_t)c->h_ir[1];
+    c->stats.rho_p = c->h_ir[2];
+    c->stats.rho_d = c->h_ir[3];
+    c->stats.kkt = c->h_ir[4];
   }
   const uint32_t bits = c->h_status[0];
   if (bits) {

@@ -36,6 +36,7 @@ def test_options_default():
     o = pk.default_options()
     assert tuple(o.gravity) == (0.0, 0.0, -9.8)
     assert o.newton_iters == 1 and o.kkt_tol == 1e-10 and o.material == 0
+    assert o.precision == 0 and o.use_graph == 1 and o.autotune == 1 and o.ir_max_sweeps == 4
 
 
 def _expect(asm, status, **kw):
@@ -69,3 +70,5 @@ def test_invalid_inputs_are_rejected_before_device_work():
     assert "no dynamic side" in _expect(a, pk.ERR_INVALID_ARG)
     _expect(base, pk.ERR_INVALID_ARG, newton_iters=0)
     _expect(base, pk.ERR_INVALID_ARG, hinge_grad=1)
+    assert "precision" in _expect(base, pk.ERR_INVALID_ARG, precision=2)
+    assert "ir_max_sweeps" in _expect(base, pk.ERR_INVALID_ARG, precision=1, ir_max_sweeps=-1)

@@ -116,3 +116,23 @@ def test_autotuned_tiles_match_oracle():
         eq, eqd = state_errors(qg, qdg, q1, qd1)
         say("vs oracle", eq, eqd)
         assert eq < 1e-10 and eqd < 1e-10
+
+
+@pytest.mark.parametrize("tt", [64, 128, 256])
+def test_forced_tile_size(tt, monkeypatch):
+    """MABD_CHAIN_TILE_THREADS fixes the tile size at create (no autotuning)."""
+    import paper_2603_08079_amd as pk
+
+    monkeypatch.setenv("MABD_CHAIN_TILE_THREADS", str(tt))
+    asm = mi.chain(5000, seed=38)
+    ctx = pk.Context(asm)
+    assert ctx.stats()["tile_threads"] == tt
+    ctx.step(asm.h, 2)
+    q, qd = asm.q0, asm.qd0
+    s = oracle.System(asm)
+    for _ in range(2):
+        q, qd, lam, d = s.step(asm.h, q, qd)
+    qg, qdg = ctx.state()
+    eq, eqd = state_errors(qg, qdg, q, qd)
+    say("tile threads", tt, eq, eqd)
+    assert eq < 1e-10 and eqd < 1e-10
