@@ -83,4 +83,37 @@ struct PcgArgs {
   uint32_t *status;
   int step;
 };
+// PCG for graph components whose joints are all ball joints.  A ball row
+// block is s J(p) in world coordinates (s = +1 side a, -1 side b), so the
+// operator needs only the anchors and the body rotations: the body pass forms
+// z = H^{-1} sum s J(p)^T x in world coordinates, the joint pass y = sum s J(p) z.
+struct PcgBallArgs {
+  int nj, nbd;                     // graph joints, graph bodies (compact numbering)
+  const int32_t *jid;              // compact joint -> generic joint (gl, glam)
+  const int32_t *jba, *jbb;        // compact joint -> compact body of side a / b, or -1
+  const double *jp;                // anchors, 8 per compact joint: p_a xyz, p_b xyz, pad
+  const int32_t *bid;              // compact body -> solver body
+  const int32_t *binc_off, *binc;  // compact body -> compact joint << 1 | side
+  const double *gl;                // C at GL_C per generic joint
+  const double *Rg, *ug;           // per solver body, SoA with stride ns
+  int64_t ns;
+  const int32_t *shp;
+  const double *hinv;
+  double *glam;                    // 5 per generic joint: warm start in, solution out
+  double *x, *r, *z, *p0, *p1, *sp, *bv;  // 3 per compact joint
+  double *dinv;                    // 6 per compact joint: S_kk^{-1} (00 01 02 11 12 22)
+  double *zw;                      // 16 per compact body: world-frame H^{-1} G^T v, pad
+  double *partial;                 // 4 per joint block
+  int nblk;                        // joint blocks (ceil(nj / 256))
+  double *sc;                      // scalars of the iteration (8)
+  int32_t *si;                     // flags and counters of the iteration (8)
+  double tol;
+  int max_iters;
+  int warm;
+  int32_t *iters_out;
+  double *res_out;
+  uint32_t *status;
+  int step;
+};
+
 }  // namespace mabd

@@ -55,6 +55,10 @@ void launch_write_pinned(int np, const int32_t *idx, const double *q0, double *q
 void launch_reset_status(uint32_t *status, hipStream_t s);
 void launch_begin_step(uint32_t *status, hipStream_t s);
 hipError_t launch_pcg(const PcgArgs &a, int nblocks, hipStream_t s);
+void launch_pb_setup(const PcgBallArgs &a, hipStream_t s);
+void launch_pb_residual(const PcgBallArgs &a, int use_x, int verify, hipStream_t s);
+void launch_pb_iters(const PcgBallArgs &a, int n, int first, hipStream_t s);
+void launch_pb_finish(const PcgBallArgs &a, hipStream_t s);
 int pcg_max_blocks();
 }  // namespace mabd
 
@@ -188,6 +192,14 @@ struct mabd_ctx {
          *d_zb = nullptr, *d_partial = nullptr, *d_pcg_res = nullptr;
   int32_t *d_pcg_it = nullptr;
   int pcg_blocks = 0;
+  // compact operator when every graph joint is a ball joint
+  bool pcg_ball = false;
+  int pb_nj = 0, pb_nbd = 0, pb_blocks = 0;
+  int32_t *d_pb_jid = nullptr, *d_pb_jba = nullptr, *d_pb_jbb = nullptr, *d_pb_bid = nullptr,
+          *d_pb_boff = nullptr, *d_pb_binc = nullptr;
+  double *d_pb_jp = nullptr, *d_pb_vec = nullptr, *d_pb_dinv = nullptr, *d_pb_zw = nullptr,
+         *d_pb_sc = nullptr;
+  int32_t *d_pb_si = nullptr, *h_pb_si = nullptr;
   double *h_pcg = nullptr;
   // precision form 1 on the chains
   double *d_dq = nullptr, *d_rp = nullptr, *d_rd = nullptr, *d_part = nullptr, *d_ir = nullptr;
@@ -365,6 +377,7 @@ void mabd_destroy(mabd_ctx *c) {
   if (c->h_status) (void)hipHostFree(c->h_status);
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
   if (c->h_ir) (void)hipHostFree(c->h_ir);
+  if (c->h_pb_si) (void)hipHostFree(c->h_pb_si);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -688,9 +701,31 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   c->tabs_off.push_back((int)c->tabs.size());
   // graph components: bodies after the trees, solved by PCG
   std::vector<int32_t> graph_bodies;
+  std::vector<char> gseen(n, 0);
   for (int ci = 0; ci < ncomp; ++ci) {
     if (cls[ci] != CLS_GRAPH) continue;
-    for (int b : cbodies[ci]) {
+    // breadth-first order from a body of least degree (Cuthill-McKee): joint
+    // neighbours get nearby solver indices, so the PCG gathers stay local
+    const auto &bs = cbodies[ci];
+    int start = bs[0];
+    for (int b : bs)
+      if (binc[b].size() < binc[start].size()) start = b;
+    std::vector<int> order;
+    order.reserve(bs.size());
+    order.push_back(start);
+    gseen[start] = 1;
+    for (size_t head = 0; head < order.size(); ++head) {
+      const int b = order[head];
+      for (int k : binc[b]) {
+        const int o = Jn->a[k] == b ? Jn->b[k] : Jn->a[k];
+        if (!dyn(o) || gseen[o]) continue;
+        gseen[o] = 1;
+        order.push_back(o);
+      }
+    }
+    for (int b : bs)  // the component is connected; kept for safety
+      if (!gseen[b]) { gseen[b] = 1; order.push_back(b); }
+    for (int b : order) {
       add_body(b);
       graph_bodies.push_back(c->in2sol[b]);
     }
@@ -903,6 +938,67 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       c->pcg_blocks = std::min(pcg_max_blocks(), (int)std::max<size_t>((mg + 255) / 256, 1));
       if (c->pcg_blocks <= 0) e = hipErrorInvalidConfiguration;
     }
+    // compact ball-joint operator
+    bool allball = true;
+    for (size_t k = 0; k < c->gj.size(); ++k)
+      if (c->jmask[k] && c->gj[k].type != 0) allball = false;
+    if (allball && e == hipSuccess) {
+      std::vector<int32_t> bpos(c->sol2in.size(), -1), bid, jid, jba, jbb;
+      for (int b = c->gb0; b < c->gb1; ++b)
+        if (c->bmask[b]) { bpos[b] = (int)bid.size(); bid.push_back(b); }
+      for (size_t k = 0; k < c->gj.size(); ++k)
+        if (c->jmask[k]) jid.push_back((int)k);
+      // joints in the order of their first dynamic body (locality of gathers)
+      auto key = [&](int k) {
+        const GJoint &g = c->gj[k];
+        const int a = g.sa >= 0 ? bpos[g.sa] : INT32_MAX, b = g.sb >= 0 ? bpos[g.sb] : INT32_MAX;
+        return std::make_pair(std::min(a, b), std::max(a, b));
+      };
+      std::stable_sort(jid.begin(), jid.end(), [&](int x, int y) { return key(x) < key(y); });
+      const int nj = (int)jid.size(), nbd = (int)bid.size();
+      std::vector<double> jp(8 * (size_t)std::max(nj, 1), 0.0);
+      std::vector<int32_t> boff(nbd + 1, 0), binc;
+      jba.resize(nj);
+      jbb.resize(nj);
+      for (int j = 0; j < nj; ++j) {
+        const GJoint &g = c->gj[jid[j]];
+        jba[j] = g.sa >= 0 ? bpos[g.sa] : -1;
+        jbb[j] = g.sb >= 0 ? bpos[g.sb] : -1;
+        for (int q = 0; q < 3; ++q) {
+          jp[8 * (size_t)j + q] = g.p1a[q];
+          jp[8 * (size_t)j + 3 + q] = g.p1b[q];
+        }
+        if (jba[j] >= 0) boff[jba[j] + 1]++;
+        if (jbb[j] >= 0) boff[jbb[j] + 1]++;
+      }
+      for (int i = 0; i < nbd; ++i) boff[i + 1] += boff[i];
+      binc.assign(std::max(boff[nbd], 1), 0);
+      {
+        std::vector<int32_t> fill(boff.begin(), boff.end() - 1);
+        for (int j = 0; j < nj; ++j) {
+          if (jba[j] >= 0) binc[fill[jba[j]]++] = j << 1;
+          if (jbb[j] >= 0) binc[fill[jbb[j]]++] = (j << 1) | 1;
+        }
+      }
+      c->pcg_ball = true;
+      c->pb_nj = nj;
+      c->pb_nbd = nbd;
+      chk(upload(c, &c->d_pb_jid, jid));
+      if (e == hipSuccess) chk(upload(c, &c->d_pb_jba, jba));
+      if (e == hipSuccess) chk(upload(c, &c->d_pb_jbb, jbb));
+      if (e == hipSuccess) chk(upload(c, &c->d_pb_bid, bid));
+      if (e == hipSuccess) chk(upload(c, &c->d_pb_boff, boff));
+      if (e == hipSuccess) chk(upload(c, &c->d_pb_binc, binc));
+      if (e == hipSuccess) chk(upload(c, &c->d_pb_jp, jp));
+      if (e == hipSuccess) chk(dalloc(c, &c->d_pb_vec, (size_t)7 * 3 * std::max(nj, 1)));
+      if (e == hipSuccess) chk(dalloc(c, &c->d_pb_dinv, (size_t)6 * std::max(nj, 1)));
+      if (e == hipSuccess) chk(dalloc(c, &c->d_pb_zw, (size_t)16 * std::max(nbd, 1)));
+      if (e == hipSuccess) chk(dalloc(c, &c->d_pb_sc, 8));
+      if (e == hipSuccess) chk(dalloc(c, &c->d_pb_si, 8));
+      if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_pb_si, 8 * sizeof(int32_t)));
+      c->pb_blocks = std::max(1, (nj + 255) / 256);  // joint blocks: one partial slot set each
+      c->pcg_blocks = std::max(c->pcg_blocks, c->pb_blocks);
+    }
     if (e == hipSuccess) chk(dalloc(c, &c->d_partial, 4 * (size_t)std::max(c->pcg_blocks, 1)));
     if (e == hipSuccess) chk(dalloc(c, &c->d_pcg_res, 2));
     if (e == hipSuccess) chk(dalloc(c, &c->d_pcg_it, 2));
@@ -939,6 +1035,39 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
 }  // extern "C"
 
 namespace {
+// Ball-joint PCG: setup and start on the device, then chunks of iterations
+// with a read of the flags after each chunk (chunk lengths double from 8 to
+// 256, all even, so every chunk starts on an even iteration).  When the
+// recursive residual passes, the true residual decides: done, or a restart
+// from it (at most four).
+hipError_t run_pcg_ball(mabd_ctx *c, const PcgBallArgs &pb, hipStream_t s) {
+  enum { SI_DONE = 0, SI_CONV = 1, SI_ITERS = 2, SI_FINAL = 3, SI_BAD = 4 };
+  launch_pb_setup(pb, s);
+  launch_pb_residual(pb, pb.warm, 0, s);
+  int chunk = 8, restarts = 0;
+  bool first = true;
+  hipError_t e = hipSuccess;
+  for (;;) {
+    e = hipMemcpyAsync(c->h_pb_si, pb.si, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    const int32_t *si = c->h_pb_si;
+    if (si[SI_FINAL] || si[SI_BAD]) break;
+    if (si[SI_DONE]) {
+      if (!si[SI_CONV] || restarts >= 4) break;  // iteration cap, or no restarts left
+      ++restarts;
+      launch_pb_residual(pb, 1, 1, s);  // true residual: ends the solve or restarts it
+      first = true;
+      continue;
+    }
+    launch_pb_iters(pb, chunk, first ? 1 : 0, s);
+    first = false;
+    chunk = std::min(chunk * 2, 256);
+  }
+  launch_pb_finish(pb, s);
+  return hipGetLastError();
+}
+
 // Launch sequence of one step reading state buffer a and writing buffer b.
 // The step index lives in device memory (begin_step), so this sequence can
 // be captured once and replayed.
@@ -1076,7 +1205,49 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
         pa.status = c->d_status;
         pa.step = 0;
         hipError_t pe = hipSuccess;
-        tm.run(7, [&] { pe = launch_pcg(pa, c->pcg_blocks, s); });
+        if (c->pcg_ball) {
+          PcgBallArgs pb{};
+          pb.nj = c->pb_nj;
+          pb.nbd = c->pb_nbd;
+          pb.jid = c->d_pb_jid;
+          pb.jba = c->d_pb_jba;
+          pb.jbb = c->d_pb_jbb;
+          pb.jp = c->d_pb_jp;
+          pb.bid = c->d_pb_bid;
+          pb.binc_off = c->d_pb_boff;
+          pb.binc = c->d_pb_binc;
+          pb.gl = c->d_gl;
+          pb.Rg = c->d_Rg;
+          pb.ug = c->d_ug;
+          pb.ns = c->ns;
+          pb.shp = c->d_shp;
+          pb.hinv = c->d_hinv;
+          pb.glam = c->d_glam;
+          const size_t v3 = (size_t)3 * std::max(c->pb_nj, 1);
+          pb.x = c->d_pb_vec;
+          pb.r = c->d_pb_vec + v3;
+          pb.z = c->d_pb_vec + 2 * v3;
+          pb.p0 = c->d_pb_vec + 3 * v3;
+          pb.p1 = c->d_pb_vec + 4 * v3;
+          pb.sp = c->d_pb_vec + 5 * v3;
+          pb.bv = c->d_pb_vec + 6 * v3;
+          pb.dinv = c->d_pb_dinv;
+          pb.zw = c->d_pb_zw;
+          pb.partial = c->d_partial;
+          pb.nblk = c->pb_blocks;
+          pb.sc = c->d_pb_sc;
+          pb.si = c->d_pb_si;
+          pb.tol = pa.tol;
+          pb.max_iters = pa.max_iters;
+          pb.warm = pa.warm;
+          pb.iters_out = c->d_pcg_it;
+          pb.res_out = c->d_pcg_res;
+          pb.status = c->d_status;
+          pb.step = 0;
+          tm.run(7, [&] { pe = run_pcg_ball(c, pb, s); });
+        } else {
+          tm.run(7, [&] { pe = launch_pcg(pa, c->pcg_blocks, s); });
+        }
         if (pe != hipSuccess) return pe;
       }
       tm.run(6, [&] {

@@ -118,3 +118,15 @@ def test_not_converged_keeps_state():
     assert ei.value.status == pk.ERR_NOT_CONVERGED
     q1, qd1 = ctx.state()
     assert np.array_equal(q0, q1) and np.array_equal(qd0, qd1)
+
+
+def test_hinge_network_uses_general_operator():
+    """A lattice with every third joint a hinge: the 5-row blocks go through
+    the general (stored-gradient) PCG operator."""
+    asm = mi.lattice(6, seed=9)
+    hj = np.arange(0, asm.m, 3)
+    asm.jtype[hj] = 1
+    asm.axis[hj] = np.array([0.0, 0.0, 1.0])
+    asm.cp_len[hj] = 0.1
+    say("hinge lattice 6x6", asm.n, asm.m, "hinges", len(hj))
+    run_pair(asm, 2)
