@@ -37,6 +37,12 @@ ALG_BYTES = {
 # residual kernel is priced: q, qdot, dq read (288 B), anchors, flags and shape
 # index (53 B), multipliers read (24 B), residuals written (96 + 24 B).
 ALG_BYTES_F1 = {"chain_resid": 288 + 53 + 24 + 120}
+# HBM bytes per launch of the dominant kernel measured with rocprofv3 --pmc
+# (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, scales from a plain 512 MiB copy) for
+# the 64-thread chain tile kernels of this build on the 1M chain; reported only
+# for that workload and tile size.
+PMC_TRAFFIC = {("chain1m", "chain_apply", 64): (171531 * 2 + 221390) * 1024,
+               ("chain1m", "chain_reduce", 64): (125814 * 2 + 3569) * 1024}
 
 
 def main():
@@ -167,8 +173,9 @@ def main():
     if dom in ab:
         alg = ab[dom] * n_dyn
         ach = alg / (per_launch[dom] * 1e-3) / 1e9
+        traffic = PMC_TRAFFIC.get((args.workload, dom, st["tile_threads"])) if chosen == 0 else None
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "avg_launch_ms": round(per_launch[dom], 4),
                 "alg_bytes_per_launch": alg,
                 "timing": f"HIP events around each launch, {psteps} steps, eager launches "

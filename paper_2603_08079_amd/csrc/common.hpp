@@ -66,6 +66,7 @@ constexpr int NO_FAIL = 0x7fffffff;
 struct ChainArgs {
   const ChainDesc *chains;
   const TileDesc *tiles;
+  int ntiles;
   const double *q, *qd;       // input state, SoA with stride ns
   double *q_out, *qd_out;     // output state (distinct buffers)
   int64_t ns;

@@ -162,6 +162,18 @@ DEV void tile_cr_backward(double *lds, bool row_active, int li, int T, int elim_
   }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Neighbouring tiles share a row and their body ranges straddle cache
+// lines, so each XCD is given a contiguous range of tiles: the shared lines
+// are then fetched once, into one L2.  Returns -1 for the padding blocks of
+// the last range.
+DEV int xcd_tile(int ntiles) {
+  const int per = (ntiles + 7) / 8;
+  const int ti = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  return ti < ntiles ? ti : -1;
+}
+inline unsigned xcd_grid(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8); }
+
 // MODE 0: plain FP64.  MODE 1 (precision form 1, first solve): phase A in
 // FP32, the factor in FP64, the increment goes to dq.  MODE 2 (form 1
 // correction): the right-hand side is the FP64 KKT residual (rp, rd) of the
@@ -175,7 +187,9 @@ __global__ __launch_bounds__(NT) void chain_tile_kernel(ChainArgs a) {
   if constexpr (MODE == 2) {
     if (a.ir[0] != 0.0) return;
   }
-  const TileDesc td = a.tiles[blockIdx.x];
+  const int ti = xcd_tile(a.ntiles);
+  if (ti < 0) return;
+  const TileDesc td = a.tiles[ti];
   const ChainDesc cd = a.chains[td.chain];
   const int t = threadIdx.x;
   const int T = td.T;
@@ -373,7 +387,7 @@ __global__ __launch_bounds__(NT) void chain_tile_kernel(ChainArgs a) {
   tile_cr_forward<NT>(lds, row_active, li, T, L, D, U, b, PL, PU, Pb, elim_d, a.status, a.step);
 
   if constexpr (!APPLY) {
-    double *rec = a.tilerec + (int64_t)TILE_REC * blockIdx.x;
+    double *rec = a.tilerec + (int64_t)TILE_REC * ti;
     if (row_active && li == 0) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) rec[i] = D[i];
@@ -794,7 +808,9 @@ __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
   __shared__ double lds[16 * NT];
   if (skip_step(a.status, a.step)) return;
   if (a.ir[0] != 0.0) return;
-  const TileDesc td = a.tiles[blockIdx.x];
+  const int ti = xcd_tile(a.ntiles);
+  if (ti < 0) return;
+  const TileDesc td = a.tiles[ti];
   const ChainDesc cd = a.chains[td.chain];
   const int t = threadIdx.x;
   const int T = td.T;
@@ -952,7 +968,7 @@ __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
       for (int k = 0; k < 4; ++k) lds[(L_RED + k) * NT + t] += lds[(L_RED + k) * NT + t + w];
     __syncthreads();
   }
-  if (t < 4) a.part[4 * (int64_t)blockIdx.x + t] = lds[(L_RED + t) * NT];
+  if (t < 4) a.part[4 * (int64_t)ti + t] = lds[(L_RED + t) * NT];
 }
 
 // Sums the tile partials in a fixed order and decides: converged (KKT
@@ -1017,12 +1033,13 @@ __global__ void chain_finish_kernel(const double *q, const double *dq, double *q
 template <int MODE, bool APPLY>
 static void launch_tiles(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
   if (ntiles <= 0) return;
+  const dim3 grid(xcd_grid(ntiles));
   if (nt == 64)
-    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 64>), dim3(ntiles), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 64>), grid, dim3(64), 0, s, a);
   else if (nt == 128)
-    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 128>), dim3(ntiles), dim3(128), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 128>), grid, dim3(128), 0, s, a);
   else
-    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 256>), dim3(ntiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 256>), grid, dim3(256), 0, s, a);
 }
 template <bool APPLY>
 static void launch_tiles_mode(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s) {
@@ -1055,12 +1072,13 @@ void launch_chain_global(const ChainDesc *chains, int nchains, const double *til
 }
 void launch_chain_resid(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
   if (ntiles <= 0) return;
+  const dim3 grid(xcd_grid(ntiles));
   if (nt == 64)
-    hipLaunchKernelGGL(chain_resid_kernel<64>, dim3(ntiles), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(chain_resid_kernel<64>, grid, dim3(64), 0, s, a);
   else if (nt == 128)
-    hipLaunchKernelGGL(chain_resid_kernel<128>, dim3(ntiles), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(chain_resid_kernel<128>, grid, dim3(128), 0, s, a);
   else
-    hipLaunchKernelGGL(chain_resid_kernel<256>, dim3(ntiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(chain_resid_kernel<256>, grid, dim3(256), 0, s, a);
 }
 void launch_chain_ir_check(const double *part, int nblk, double tol, int final_check, double *ir,
                            uint32_t *status, hipStream_t s) {

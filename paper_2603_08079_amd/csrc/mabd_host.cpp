@@ -1080,6 +1080,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
     ChainArgs ca{};
     ca.chains = c->d_chains;
     ca.tiles = c->d_tiles;
+    ca.ntiles = (int)c->tiles.size();
     ca.q = c->d_q[a];
     ca.qd = c->d_qd[a];
     ca.q_out = c->d_q[b];
