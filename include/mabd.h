@@ -88,7 +88,8 @@ typedef struct {
   double kkt_tol;          /* PCG stop: |r - S lam| <= kkt_tol |r|; precision-1 target of
                               the chain KKT residual; default 1e-10                      */
   int32_t max_iters;       /* PCG iteration cap, default 200000                           */
-  int32_t warm_start;      /* PCG start: 0 zero, 1 previous step's multipliers, 2 GNN     */
+  int32_t warm_start;      /* PCG start: 0 zero, 1 previous step's multipliers, 2 learned
+                              (ball networks with weights; otherwise zero)              */
   int32_t newton_iters;    /* Newton iterations per step, default 1                       */
   int32_t hinge_grad;      /* 0 frozen frame + A-linearised rotation term, 2 frozen only  */
   int32_t material;        /* 0: mu = 4 k_A, lambda = 0 (Eq. EA linearised); 1: Lame     */
@@ -170,8 +171,48 @@ int64_t mabd_rows(const mabd_ctx *ctx);
 /* Diagnostics of the last step.  Synchronises the stream. */
 mabd_status mabd_stats(const mabd_ctx *ctx, mabd_step_stats *st);
 
-/* Loads graph-network weights used by warm_start = 2 (binary file written by
-   the package's trainer).  Errors: INVALID_ARG on a bad header. */
+/* ---------------------------------------------------------------------------
+   Learned warm start of the ball-network PCG (warm_start = 2).  Not part of
+   the paper's method: it only supplies the PCG start value, which the solve
+   keeps only if its dual energy 1/2 l^T S l - b^T l is below zero (then its
+   S-norm error is below the cold start's; stats.warm_accepted says which).
+   A message-passing network over the joints (3 layers of width 64, FP32,
+   mabd_gnn_size() parameters) maps per-joint features (block-Jacobi start,
+   previous multipliers, degrees, world sides) to multipliers.  Training
+   minimises that energy, normalised by |b^T D^{-1} b|, over the dual systems
+   of the states the caller steps through; everything runs on the context's
+   stream.  All calls need a ball-joint network component (INVALID_ARG
+   otherwise) and, except init / set, weights (INVALID_ARG otherwise).
+   --------------------------------------------------------------------------- */
+
+/* Number of network parameters (float32). */
+int32_t mabd_gnn_size(void);
+
+/* Allocates the network's device buffers (about 1.6 KB per joint) and draws
+   Glorot-uniform weights from `seed`; resets the Adam state. */
+mabd_status mabd_gnn_init(mabd_ctx *ctx, uint64_t seed);
+
+/* Copies the weights to `get` and/or replaces them from `set` (both host,
+   n = mabd_gnn_size() floats, either may be NULL; `set` resets Adam). */
+mabd_status mabd_gnn_params(mabd_ctx *ctx, float *get, const float *set, int32_t n);
+
+/* Gradient (host, mabd_gnn_size() floats; may be NULL) and loss of the dual
+   system of the current state for time step h; the state is unchanged. */
+mabd_status mabd_gnn_grad(mabd_ctx *ctx, double h, float *grad, double *loss);
+
+/* `iters` Adam steps (learning rate lr) on the dual system of the current
+   state for time step h; the loss before the first and after the last step
+   go to loss_first / loss_last (may be NULL).  The state is unchanged. */
+mabd_status mabd_gnn_train(mabd_ctx *ctx, double h, int32_t iters, float lr, double *loss_first,
+                           double *loss_last);
+
+/* The network's start multipliers for the current state (host, 3 per joint
+   in input order; joints outside ball networks get 0). */
+mabd_status mabd_gnn_predict(mabd_ctx *ctx, double h, double *lam0);
+
+/* Writes / reads the weights (8-byte tag, int32 count, float32 values).
+   Errors: INVALID_ARG on an unreadable file or a wrong tag or count. */
+mabd_status mabd_gnn_save(const mabd_ctx *ctx, const char *path);
 mabd_status mabd_gnn_load(mabd_ctx *ctx, const char *path);
 
 /* Message of the last error on ctx (or of the last failed create if ctx is

@@ -21,8 +21,9 @@ OK, ERR_INVALID_ARG, ERR_TOPOLOGY, ERR_DEVICE, ERR_OOM, ERR_NONFINITE, ERR_NOT_C
     ERR_SINGULAR = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTED = ["mabd_options_default", "mabd_create", "mabd_step", "mabd_state", "mabd_state_device",
-            "mabd_set_state", "mabd_multipliers", "mabd_rows", "mabd_stats", "mabd_gnn_load",
-            "mabd_last_error", "mabd_destroy"]
+            "mabd_set_state", "mabd_multipliers", "mabd_rows", "mabd_stats", "mabd_gnn_size",
+            "mabd_gnn_init", "mabd_gnn_params", "mabd_gnn_grad", "mabd_gnn_train", "mabd_gnn_predict",
+            "mabd_gnn_save", "mabd_gnn_load", "mabd_last_error", "mabd_destroy"]
 
 
 class MabdError(RuntimeError):
@@ -101,6 +102,13 @@ def lib():
         L.mabd_rows.argtypes = [P]; L.mabd_rows.restype = I64
         L.mabd_stats.argtypes = [P, P]; L.mabd_stats.restype = I32
         L.mabd_gnn_load.argtypes = [P, ctypes.c_char_p]; L.mabd_gnn_load.restype = I32
+        L.mabd_gnn_save.argtypes = [P, ctypes.c_char_p]; L.mabd_gnn_save.restype = I32
+        L.mabd_gnn_size.argtypes = []; L.mabd_gnn_size.restype = I32
+        L.mabd_gnn_init.argtypes = [P, ctypes.c_uint64]; L.mabd_gnn_init.restype = I32
+        L.mabd_gnn_params.argtypes = [P, P, P, I32]; L.mabd_gnn_params.restype = I32
+        L.mabd_gnn_grad.argtypes = [P, D, P, P]; L.mabd_gnn_grad.restype = I32
+        L.mabd_gnn_train.argtypes = [P, D, I32, ctypes.c_float, P, P]; L.mabd_gnn_train.restype = I32
+        L.mabd_gnn_predict.argtypes = [P, D, P]; L.mabd_gnn_predict.restype = I32
         L.mabd_last_error.argtypes = [P]; L.mabd_last_error.restype = ctypes.c_char_p
         L.mabd_destroy.argtypes = [P]; L.mabd_destroy.restype = None
         _lib = L
@@ -188,6 +196,43 @@ class Context:
         s = StepStats()
         self._check(lib().mabd_stats(self.h, ctypes.byref(s)))
         return s.as_dict()
+
+    # ---- learned warm start (warm_start = 2)
+    def gnn_init(self, seed: int = 0):
+        self._check(lib().mabd_gnn_init(self.h, ctypes.c_uint64(seed)))
+
+    def gnn_params(self, set_to=None) -> np.ndarray:
+        n = lib().mabd_gnn_size()
+        out = np.zeros(n, np.float32)
+        src = None
+        if set_to is not None:
+            src = np.ascontiguousarray(set_to, np.float32)
+            assert src.shape == (n,)
+        self._check(lib().mabd_gnn_params(self.h, out.ctypes.data,
+                                          None if src is None else src.ctypes.data, n))
+        return out
+
+    def gnn_grad(self, h: float):
+        g = np.zeros(lib().mabd_gnn_size(), np.float32)
+        loss = ctypes.c_double()
+        self._check(lib().mabd_gnn_grad(self.h, h, g.ctypes.data, ctypes.byref(loss)))
+        return g, loss.value
+
+    def gnn_train(self, h: float, iters: int, lr: float):
+        l0, l1 = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().mabd_gnn_train(self.h, h, iters, lr, ctypes.byref(l0), ctypes.byref(l1)))
+        return l0.value, l1.value
+
+    def gnn_predict(self, h: float) -> np.ndarray:
+        lam = np.zeros((max(self.m, 1), 3))
+        self._check(lib().mabd_gnn_predict(self.h, h, lam.ctypes.data))
+        return lam[: self.m]
+
+    def gnn_save(self, path: str):
+        self._check(lib().mabd_gnn_save(self.h, path.encode()))
+
+    def gnn_load(self, path: str):
+        self._check(lib().mabd_gnn_load(self.h, path.encode()))
 
     def close(self):
         if getattr(self, "h", None):

@@ -18,6 +18,7 @@
 #include "../../include/mabd.h"
 #include "common.hpp"
 #include "generic.hpp"
+#include "gnn.hpp"
 
 namespace mabd {
 
@@ -59,6 +60,11 @@ void launch_pb_setup(const PcgBallArgs &a, hipStream_t s);
 void launch_pb_residual(const PcgBallArgs &a, int use_x, int verify, hipStream_t s);
 void launch_pb_iters(const PcgBallArgs &a, int n, int first, hipStream_t s);
 void launch_pb_finish(const PcgBallArgs &a, hipStream_t s);
+void launch_gnn_forward(const PcgBallArgs &a, const GnnBufs &g, int have_prev, hipStream_t s);
+void launch_gnn_loss(const PcgBallArgs &a, const GnnBufs &g, hipStream_t s);
+void launch_gnn_backward(const PcgBallArgs &a, const GnnBufs &g, hipStream_t s);
+void launch_gnn_adam(const GnnBufs &g, float lr, int64_t t, hipStream_t s);
+int gnn_wgrad_blocks(int nj);
 int pcg_max_blocks();
 }  // namespace mabd
 
@@ -200,6 +206,11 @@ struct mabd_ctx {
   double *d_pb_jp = nullptr, *d_pb_vec = nullptr, *d_pb_dinv = nullptr, *d_pb_zw = nullptr,
          *d_pb_sc = nullptr;
   int32_t *d_pb_si = nullptr, *h_pb_si = nullptr;
+  // learned warm start (allocated by mabd_gnn_init / mabd_gnn_load)
+  bool gnn_ready = false;
+  GnnBufs gb{};
+  int64_t gnn_t = 0;       // Adam steps taken
+  double *h_gsc = nullptr;  // pinned copies of loss / energy
   double *h_pcg = nullptr;
   // precision form 1 on the chains
   double *d_dq = nullptr, *d_rp = nullptr, *d_rd = nullptr, *d_part = nullptr, *d_ir = nullptr;
@@ -378,6 +389,7 @@ void mabd_destroy(mabd_ctx *c) {
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
   if (c->h_ir) (void)hipHostFree(c->h_ir);
   if (c->h_pb_si) (void)hipHostFree(c->h_pb_si);
+  if (c->h_gsc) (void)hipHostFree(c->h_gsc);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -406,6 +418,8 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     return fail(nullptr, MABD_ERR_INVALID_ARG, "material 1 needs poisson");
   if (opt.hinge_grad != 0 && opt.hinge_grad != 2)
     return fail(nullptr, MABD_ERR_INVALID_ARG, "hinge_grad must be 0 or 2");
+  if (opt.warm_start < 0 || opt.warm_start > 2)
+    return fail(nullptr, MABD_ERR_INVALID_ARG, "warm_start must be 0, 1 or 2");
   if (opt.precision != 0 && opt.precision != 1)
     return fail(nullptr, MABD_ERR_INVALID_ARG, "precision must be 0 or 1");
   if (opt.ir_max_sweeps < 0 || opt.ir_max_sweeps > 16)
@@ -1035,6 +1049,152 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
 }  // extern "C"
 
 namespace {
+// arguments of the ball-network operator and PCG
+PcgBallArgs make_ball_args(mabd_ctx *c, double tol, int max_iters, int warm) {
+  PcgBallArgs pb{};
+  pb.nj = c->pb_nj;
+  pb.nbd = c->pb_nbd;
+  pb.jid = c->d_pb_jid;
+  pb.jba = c->d_pb_jba;
+  pb.jbb = c->d_pb_jbb;
+  pb.jp = c->d_pb_jp;
+  pb.bid = c->d_pb_bid;
+  pb.binc_off = c->d_pb_boff;
+  pb.binc = c->d_pb_binc;
+  pb.gl = c->d_gl;
+  pb.Rg = c->d_Rg;
+  pb.ug = c->d_ug;
+  pb.ns = c->ns;
+  pb.shp = c->d_shp;
+  pb.hinv = c->d_hinv;
+  pb.glam = c->d_glam;
+  const size_t v3 = (size_t)3 * std::max(c->pb_nj, 1);
+  pb.x = c->d_pb_vec;
+  pb.r = c->d_pb_vec + v3;
+  pb.z = c->d_pb_vec + 2 * v3;
+  pb.p0 = c->d_pb_vec + 3 * v3;
+  pb.p1 = c->d_pb_vec + 4 * v3;
+  pb.sp = c->d_pb_vec + 5 * v3;
+  pb.bv = c->d_pb_vec + 6 * v3;
+  pb.dinv = c->d_pb_dinv;
+  pb.zw = c->d_pb_zw;
+  pb.partial = c->d_partial;
+  pb.nblk = c->pb_blocks;
+  pb.sc = c->d_pb_sc;
+  pb.si = c->d_pb_si;
+  pb.tol = tol;
+  pb.max_iters = max_iters;
+  pb.warm = warm;
+  pb.iters_out = c->d_pcg_it;
+  pb.res_out = c->d_pcg_res;
+  pb.status = c->d_status;
+  pb.step = 0;
+  return pb;
+}
+}  // namespace
+
+namespace {
+void drop_graphs(mabd_ctx *c);
+
+// ------------------------------------------------------ learned warm start
+hipError_t gnn_alloc(mabd_ctx *c) {
+  if (c->gnn_ready) return hipSuccess;
+  const size_t nj = (size_t)std::max(c->pb_nj, 1), nbd = (size_t)std::max(c->pb_nbd, 1);
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  GnnBufs &g = c->gb;
+  chk(dalloc(c, &g.x0, GNN_FIN * nj));
+  for (int l = 0; l < GNN_L; ++l) chk(dalloc(c, &g.X[l], 2 * GNN_W * nj));
+  for (int l = 0; l <= GNN_L; ++l) chk(dalloc(c, &g.H[l], GNN_W * nj));
+  chk(dalloc(c, &g.y, 3 * nj));
+  chk(dalloc(c, &g.m, GNN_W * nbd));
+  chk(dalloc(c, &g.dX, 2 * GNN_W * nj));
+  chk(dalloc(c, &g.dZ, GNN_W * nj));
+  chk(dalloc(c, &g.dY, 3 * nj));
+  chk(dalloc(c, &g.params, (size_t)GNN_NPARAM));
+  chk(dalloc(c, &g.grad, (size_t)GNN_NPARAM));
+  chk(dalloc(c, &g.adam_m, (size_t)GNN_NPARAM));
+  chk(dalloc(c, &g.adam_v, (size_t)GNN_NPARAM));
+  chk(dalloc(c, &g.wpart, (size_t)gnn_wgrad_blocks((int)nj) * (2 * GNN_W + 1) * GNN_W));
+  chk(dalloc(c, &g.red, 4 * ((nj + 255) / 256)));
+  chk(dalloc(c, &g.sc, 8));
+  if (e == hipSuccess && !c->h_gsc) e = hipHostMalloc((void **)&c->h_gsc, 4 * sizeof(double));
+  return e;
+}
+
+hipError_t gnn_set_params(mabd_ctx *c, const float *P) {
+  hipError_t e = hipMemcpy(c->gb.params, P, GNN_NPARAM * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(c->gb.adam_m, 0, GNN_NPARAM * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(c->gb.adam_v, 0, GNN_NPARAM * sizeof(float));
+  c->gnn_t = 0;
+  if (e == hipSuccess) c->gnn_ready = true;
+  return e;
+}
+
+// Glorot-uniform weights from a splitmix64 stream, zero biases; the decoder is
+// scaled by 0.1 so that an untrained network starts near zero
+void gnn_init_params(std::vector<float> &P, uint64_t seed) {
+  P.assign(GNN_NPARAM, 0.0f);
+  uint64_t st = seed;
+  auto uni = [&]() {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  };
+  auto glorot = [&](int off, int fin, int fout, double gain) {
+    const double a = gain * std::sqrt(6.0 / (fin + fout));
+    for (int i = 0; i < fin * fout; ++i) P[off + i] = (float)((2.0 * uni() - 1.0) * a);
+  };
+  glorot(GNN_P_WE, GNN_FIN, GNN_W, 1.0);
+  for (int l = 0; l < GNN_L; ++l) glorot(GNN_P_L0 + l * GNN_P_LSTRIDE, 2 * GNN_W, GNN_W, 1.0);
+  glorot(GNN_P_WD, GNN_W, 3, 0.1);
+}
+
+// The dual system of the current state (per-body solve, joint rows, PCG
+// diagonal blocks and right-hand side) without advancing the state.
+hipError_t gnn_prepare(mabd_ctx *c, double h, PcgBallArgs &pb) {
+  hipStream_t s = c->stream;
+  if (h != c->h_last) {
+    launch_prefactor(c->d_shape, c->nshape, h, c->d_hinv, s);
+    c->h_last = h;
+    drop_graphs(c);
+  }
+  launch_reset_status(c->d_status, s);
+  launch_begin_step(c->d_status, s);
+  const int a = c->cur;
+  launch_gbody(c->gb0, c->gb1, c->d_q[a], c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv, c->d_shape,
+               c->opt.gravity, h, c->d_Rg, c->d_ug, c->d_status, 0, s);
+  launch_gjoint((int)c->gj.size(), c->d_gj, c->d_q[a], c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
+  pb = make_ball_args(c, c->opt.kkt_tol, c->opt.max_iters, 0);
+  launch_pb_setup(pb, s);
+  return hipGetLastError();
+}
+
+mabd_status gnn_check(mabd_ctx *c, bool need_ready) {
+  if (!c) return MABD_ERR_INVALID_ARG;
+  if (!c->pcg_ball || c->pb_nj == 0)
+    return fail(c, MABD_ERR_INVALID_ARG, "the learned warm start needs a ball-joint network component");
+  if (need_ready && !c->gnn_ready)
+    return fail(c, MABD_ERR_INVALID_ARG, "no network weights: call mabd_gnn_init or mabd_gnn_load");
+  return MABD_OK;
+}
+
+mabd_status gnn_finish(mabd_ctx *c, const char *what) {
+  hipError_t e = hipMemcpyAsync(c->h_status, c->d_status, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  if (c->h_status[0] & FLAG_NONFINITE) return fail(c, MABD_ERR_NONFINITE, std::string(what) + ": non-finite state");
+  if (c->h_status[0] & FLAG_SINGULAR) return fail(c, MABD_ERR_SINGULAR, std::string(what) + ": singular block");
+  return MABD_OK;
+}
+}  // namespace
+
+
+namespace {
 // Ball-joint PCG: setup and start on the device, then chunks of iterations
 // with a read of the flags after each chunk (chunk lengths double from 8 to
 // 256, all even, so every chunk starts on an even iteration).  When the
@@ -1043,7 +1203,25 @@ namespace {
 hipError_t run_pcg_ball(mabd_ctx *c, const PcgBallArgs &pb, hipStream_t s) {
   enum { SI_DONE = 0, SI_CONV = 1, SI_ITERS = 2, SI_FINAL = 3, SI_BAD = 4 };
   launch_pb_setup(pb, s);
-  launch_pb_residual(pb, pb.warm, 0, s);
+  c->stats.warm_accepted = 0;
+  if (c->opt.warm_start == 2 && c->gnn_ready) {
+    // learned start, kept only if its dual energy is below that of zero
+    // (then its S-norm error is smaller than the cold start's)
+    launch_gnn_forward(pb, c->gb, c->warm_valid ? 1 : 0, s);
+    launch_gnn_loss(pb, c->gb, s);
+    hipError_t e = hipMemcpyAsync(c->h_gsc, c->gb.sc + 3, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (c->h_gsc[0] < 0.0) {
+      c->stats.warm_accepted = 1;
+      launch_pb_residual(pb, 1, 0, s);
+    } else {
+      launch_pb_setup(pb, s);  // x = 0 again (pb.warm is 0 here)
+      launch_pb_residual(pb, 0, 0, s);
+    }
+  } else {
+    launch_pb_residual(pb, pb.warm, 0, s);
+  }
   int chunk = 8, restarts = 0;
   bool first = true;
   hipError_t e = hipSuccess;
@@ -1207,44 +1385,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
         pa.step = 0;
         hipError_t pe = hipSuccess;
         if (c->pcg_ball) {
-          PcgBallArgs pb{};
-          pb.nj = c->pb_nj;
-          pb.nbd = c->pb_nbd;
-          pb.jid = c->d_pb_jid;
-          pb.jba = c->d_pb_jba;
-          pb.jbb = c->d_pb_jbb;
-          pb.jp = c->d_pb_jp;
-          pb.bid = c->d_pb_bid;
-          pb.binc_off = c->d_pb_boff;
-          pb.binc = c->d_pb_binc;
-          pb.gl = c->d_gl;
-          pb.Rg = c->d_Rg;
-          pb.ug = c->d_ug;
-          pb.ns = c->ns;
-          pb.shp = c->d_shp;
-          pb.hinv = c->d_hinv;
-          pb.glam = c->d_glam;
-          const size_t v3 = (size_t)3 * std::max(c->pb_nj, 1);
-          pb.x = c->d_pb_vec;
-          pb.r = c->d_pb_vec + v3;
-          pb.z = c->d_pb_vec + 2 * v3;
-          pb.p0 = c->d_pb_vec + 3 * v3;
-          pb.p1 = c->d_pb_vec + 4 * v3;
-          pb.sp = c->d_pb_vec + 5 * v3;
-          pb.bv = c->d_pb_vec + 6 * v3;
-          pb.dinv = c->d_pb_dinv;
-          pb.zw = c->d_pb_zw;
-          pb.partial = c->d_partial;
-          pb.nblk = c->pb_blocks;
-          pb.sc = c->d_pb_sc;
-          pb.si = c->d_pb_si;
-          pb.tol = pa.tol;
-          pb.max_iters = pa.max_iters;
-          pb.warm = pa.warm;
-          pb.iters_out = c->d_pcg_it;
-          pb.res_out = c->d_pcg_res;
-          pb.status = c->d_status;
-          pb.step = 0;
+          PcgBallArgs pb = make_ball_args(c, pa.tol, pa.max_iters, pa.warm);
           tm.run(7, [&] { pe = run_pcg_ball(c, pb, s); });
         } else {
           tm.run(7, [&] { pe = launch_pcg(pa, c->pcg_blocks, s); });
@@ -1489,9 +1630,151 @@ mabd_status mabd_stats(const mabd_ctx *c, mabd_step_stats *st) {
   return MABD_OK;
 }
 
+int32_t mabd_gnn_size(void) { return GNN_NPARAM; }
+
+mabd_status mabd_gnn_init(mabd_ctx *c, uint64_t seed) {
+  mabd_status st = gnn_check(c, false);
+  if (st != MABD_OK) return st;
+  hipError_t e = gnn_alloc(c);
+  if (e != hipSuccess) return fail(c, e == hipErrorOutOfMemory ? MABD_ERR_OOM : MABD_ERR_DEVICE, hipGetErrorString(e));
+  std::vector<float> P;
+  gnn_init_params(P, seed);
+  e = gnn_set_params(c, P.data());
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  return MABD_OK;
+}
+
+mabd_status mabd_gnn_params(mabd_ctx *c, float *get, const float *set, int32_t n) {
+  mabd_status st = gnn_check(c, set == nullptr);
+  if (st != MABD_OK) return st;
+  if (n != GNN_NPARAM) return fail(c, MABD_ERR_INVALID_ARG, "n must equal mabd_gnn_size()");
+  hipError_t e = hipSuccess;
+  if (set) {
+    e = gnn_alloc(c);
+    if (e == hipSuccess) e = gnn_set_params(c, set);
+  }
+  if (e == hipSuccess && get)
+    e = hipMemcpy(get, c->gb.params, GNN_NPARAM * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  return MABD_OK;
+}
+
+mabd_status mabd_gnn_grad(mabd_ctx *c, double h, float *grad, double *loss) {
+  mabd_status st = gnn_check(c, true);
+  if (st != MABD_OK) return st;
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(c, MABD_ERR_INVALID_ARG, "h must be > 0");
+  PcgBallArgs pb;
+  hipError_t e = gnn_prepare(c, h, pb);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  hipStream_t s = c->stream;
+  launch_gnn_forward(pb, c->gb, c->warm_valid ? 1 : 0, s);
+  launch_gnn_loss(pb, c->gb, s);
+  launch_gnn_backward(pb, c->gb, s);
+  e = hipMemcpyAsync(c->h_gsc, c->gb.sc + 2, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && grad)
+    e = hipMemcpyAsync(grad, c->gb.grad, GNN_NPARAM * sizeof(float), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  st = gnn_finish(c, "gnn_grad");
+  if (st == MABD_OK && loss) *loss = c->h_gsc[0];
+  return st;
+}
+
+mabd_status mabd_gnn_train(mabd_ctx *c, double h, int32_t iters, float lr, double *loss_first,
+                           double *loss_last) {
+  mabd_status st = gnn_check(c, true);
+  if (st != MABD_OK) return st;
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(c, MABD_ERR_INVALID_ARG, "h must be > 0");
+  if (iters < 0 || !(lr >= 0.0f) || !std::isfinite(lr)) return fail(c, MABD_ERR_INVALID_ARG, "iters, lr");
+  PcgBallArgs pb;
+  hipError_t e = gnn_prepare(c, h, pb);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  hipStream_t s = c->stream;
+  const int prev = c->warm_valid ? 1 : 0;
+  for (int it = 0; it <= iters; ++it) {
+    launch_gnn_forward(pb, c->gb, prev, s);
+    launch_gnn_loss(pb, c->gb, s);
+    if (it == 0) e = hipMemcpyAsync(c->h_gsc, c->gb.sc + 2, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (it == iters) {
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(c->h_gsc + 1, c->gb.sc + 2, sizeof(double), hipMemcpyDeviceToHost, s);
+      break;
+    }
+    launch_gnn_backward(pb, c->gb, s);
+    launch_gnn_adam(c->gb, lr, ++c->gnn_t, s);
+  }
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  st = gnn_finish(c, "gnn_train");
+  if (st == MABD_OK) {
+    if (loss_first) *loss_first = c->h_gsc[0];
+    if (loss_last) *loss_last = c->h_gsc[1];
+  }
+  return st;
+}
+
+mabd_status mabd_gnn_predict(mabd_ctx *c, double h, double *lam0) {
+  mabd_status st = gnn_check(c, true);
+  if (st != MABD_OK) return st;
+  if (!(h > 0.0) || !std::isfinite(h) || !lam0) return fail(c, MABD_ERR_INVALID_ARG, "h, lam0");
+  PcgBallArgs pb;
+  hipError_t e = gnn_prepare(c, h, pb);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  launch_gnn_forward(pb, c->gb, c->warm_valid ? 1 : 0, c->stream);
+  std::vector<double> x(3 * (size_t)c->pb_nj);
+  std::vector<int32_t> jid(c->pb_nj);
+  e = hipMemcpyAsync(x.data(), pb.x, x.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(jid.data(), c->d_pb_jid, jid.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  st = gnn_finish(c, "gnn_predict");
+  if (st != MABD_OK) return st;
+  std::fill(lam0, lam0 + 3 * (size_t)c->m, 0.0);
+  for (int j = 0; j < c->pb_nj; ++j) {
+    const int k = c->gj_in[jid[j]];
+    for (int r = 0; r < 3; ++r) lam0[3 * (size_t)k + r] = x[3 * (size_t)j + r];
+  }
+  return MABD_OK;
+}
+
+static const char GNN_MAGIC[8] = {'M', 'A', 'B', 'D', 'G', 'N', 'N', '1'};
+
+mabd_status mabd_gnn_save(const mabd_ctx *cc, const char *path) {
+  mabd_ctx *c = const_cast<mabd_ctx *>(cc);
+  mabd_status st = gnn_check(c, true);
+  if (st != MABD_OK) return st;
+  if (!path) return fail(c, MABD_ERR_INVALID_ARG, "path");
+  std::vector<float> P(GNN_NPARAM);
+  hipError_t e = hipMemcpy(P.data(), c->gb.params, P.size() * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(c, MABD_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  const int32_t n = GNN_NPARAM;
+  bool ok = std::fwrite(GNN_MAGIC, 1, 8, f) == 8 && std::fwrite(&n, sizeof n, 1, f) == 1 &&
+            std::fwrite(P.data(), sizeof(float), P.size(), f) == P.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(c, MABD_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  return MABD_OK;
+}
+
 mabd_status mabd_gnn_load(mabd_ctx *c, const char *path) {
-  if (!c || !path) return MABD_ERR_INVALID_ARG;
-  return fail(c, MABD_ERR_INVALID_ARG, "graph-network warm start is not available in this build");
+  mabd_status st = gnn_check(c, false);
+  if (st != MABD_OK) return st;
+  if (!path) return fail(c, MABD_ERR_INVALID_ARG, "path");
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(c, MABD_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t n = 0;
+  std::vector<float> P(GNN_NPARAM);
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, GNN_MAGIC, 8) == 0 &&
+            std::fread(&n, sizeof n, 1, f) == 1 && n == GNN_NPARAM &&
+            std::fread(P.data(), sizeof(float), P.size(), f) == P.size();
+  std::fclose(f);
+  if (!ok) return fail(c, MABD_ERR_INVALID_ARG, std::string("not a weight file of this network: ") + path);
+  for (float v : P)
+    if (!std::isfinite(v)) return fail(c, MABD_ERR_INVALID_ARG, "weights not finite");
+  hipError_t e = gnn_alloc(c);
+  if (e == hipSuccess) e = gnn_set_params(c, P.data());
+  if (e != hipSuccess) return fail(c, e == hipErrorOutOfMemory ? MABD_ERR_OOM : MABD_ERR_DEVICE, hipGetErrorString(e));
+  return MABD_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,75 @@
+"""Pins of the reference network of the learned warm start (CPU).
+
+The network is not part of the paper, so it is pinned by properties that any
+correct implementation of its definition has: the energy loss equals the
+S-norm error identity of the dual quadratic, the message passing is
+equivariant under a renumbering of joints and bodies, and a hand-computed
+two-joint case."""
+import numpy as np
+
+import mabd_inputs as mi
+import oracle
+from oracle import gnn_ref as G
+
+
+def _params(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, scale, G.NPARAM)
+
+
+def _net(asm, lam_prev=None):
+    s = oracle.System(asm)
+    S, r = s.dual(asm.h, asm.q0, asm.qd0)
+    return G.Network(asm, S, r, lam_prev), S, r
+
+
+def test_energy_identity():
+    """E(l) - E(l*) = 1/2 |l - l*|_S^2 with l* = S^{-1} r (the loss is the
+    quadratic whose minimiser is the dual solution)."""
+    asm = mi.lattice(5, seed=1)
+    net, S, r = _net(asm)
+    p = _params(2)
+    lam = net.forward(p).ravel()
+    Sd = S.toarray()
+    ls = np.linalg.solve(Sd, r)
+    e_min = -0.5 * r @ ls
+    lhs = net.loss(p) * net.eref - e_min
+    rhs = 0.5 * (lam - ls) @ Sd @ (lam - ls)
+    assert abs(lhs - rhs) <= 1e-9 * max(abs(rhs), abs(e_min))
+
+
+def test_permutation_equivariance():
+    asm = mi.lattice(5, seed=3)
+    lam_prev = np.random.default_rng(4).normal(size=3 * asm.m)
+    net, _, _ = _net(asm, lam_prev)
+    p = _params(5)
+    y = net.forward(p)
+    perm = np.random.default_rng(6).permutation(asm.m)
+    b = asm.copy()
+    for f in ("jtype", "ja", "jb", "pa", "pb", "axis", "cp_len"):
+        setattr(b, f, getattr(b, f)[perm])
+    netp, _, _ = _net(b, lam_prev.reshape(-1, 3)[perm].ravel())
+    yp = netp.forward(p)
+    assert np.allclose(yp, y[perm], rtol=1e-10, atol=1e-12 * np.abs(y).max())
+
+
+def test_two_joint_message_by_hand():
+    """Chain of 3 bodies, body 0 pinned: joint 0 (world, body 1), joint 1
+    (body 1, body 2); deg(1) = 2, deg(2) = 1.  Weights chosen so that h0 =
+    deg_b (4 x feature 7), layer 1 copies the neighbour channel, layers 2-3
+    and the decoder copy channel 0: the output is the normalised neighbour sum
+    n_k = (m_a + m_b) / (deg_a + deg_b) with m_1 = 2 + 1, m_2 = 1, i.e.
+    n_0 = 3 / 2 and n_1 = (3 + 1) / 3."""
+    asm = mi.chain(3, seed=7)
+    net, _, _ = _net(asm)
+    assert list(net.ja) == [-1, 1] and list(net.jb) == [1, 2]
+    assert np.allclose(net.x[:, 6:10], [[0.0, 0.5, 1.0, 0.0], [0.5, 0.25, 0.0, 0.0]])
+    p = np.zeros(G.NPARAM)
+    p[G.P_WE + 7 * G.W + 0] = 4.0
+    p[G.P_L0 + 64 * G.W + 0] = 1.0
+    for l in (1, 2):
+        p[G.P_L0 + l * G.P_LS + 0] = 1.0
+    p[G.P_WD + 0] = 1.0
+    y = net.forward(p) / net.s
+    assert np.allclose(y[:, 0], [1.5, 4.0 / 3.0], rtol=1e-14)
+    assert np.all(y[:, 1:] == 0.0)

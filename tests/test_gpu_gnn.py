@@ -1,0 +1,149 @@
+"""Learned PCG warm start on the GPU against the FP64 reference network.
+
+The GPU network runs in FP32 and must reproduce the reference's start
+multipliers and loss to FP32 rounding; its analytic gradient must match
+central finite differences of the FP64 reference loss; training must lower
+the loss; and a learned start must leave the converged PCG solution where a
+cold start puts it (the KKT residual is the only judge of a warm start).
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import mabd_inputs as mi
+import oracle
+from oracle import gnn_ref as G
+from gpu_util import say, state_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(asm, steps_before=1, seed=11):
+    """Context stepped `steps_before` times (so the previous-multiplier
+    feature is live), and the reference network of its current state."""
+    import paper_2603_08079_amd as pk
+
+    ctx = pk.Context(asm, kkt_tol=1e-10)
+    st = ctx.stats()
+    assert st["n_graph"] == 1 and st["n_tree"] == 0 and st["n_chain"] == 0
+    for _ in range(steps_before):
+        ctx.step(asm.h, 1)
+    q, qd = ctx.state()
+    lam_prev = ctx.multipliers() if steps_before else None
+    s = oracle.System(asm)
+    S, r = s.dual(asm.h, q, qd)
+    net = G.Network(asm, S, r, lam_prev)
+    ctx.gnn_init(seed)
+    return ctx, net
+
+
+def test_forward_and_loss_match_reference():
+    asm = mi.lattice(7, seed=21)
+    ctx, net = _setup(asm)
+    p = ctx.gnn_params().astype(np.float64)
+    lam_gpu = ctx.gnn_predict(asm.h)
+    lam_ref = net.forward(p)
+    err = np.abs(lam_gpu - lam_ref).max() / np.abs(lam_ref).max()
+    _, loss_gpu = ctx.gnn_grad(asm.h)
+    loss_ref = net.loss(p)
+    say("forward rel err", err, "loss gpu", loss_gpu, "ref", loss_ref)
+    assert err < 1e-4
+    assert abs(loss_gpu - loss_ref) <= 1e-4 * max(abs(loss_ref), 1e-3)
+
+
+@pytest.mark.parametrize("kind", ["lattice", "rgg"])
+def test_gradient_matches_finite_differences(kind):
+    """GPU FP32 backpropagation against central differences of the FP64
+    reference loss, on parameters of every layer (weights and biases)."""
+    asm = mi.lattice(6, seed=22) if kind == "lattice" else mi.rgg(60, seed=5, pin_frac=0.1)
+    import paper_2603_08079_amd as pk
+
+    st = pk.Context(asm).stats()
+    if st["n_tree"] or st["n_chain"] or st["n_graph"] != 1:
+        pytest.skip("generator produced more than one component for this seed")
+    ctx, net = _setup(asm, seed=12)
+    p32 = ctx.gnn_params()
+    p = p32.astype(np.float64)
+    g_gpu, _ = ctx.gnn_grad(asm.h)
+    rng = np.random.default_rng(13)
+    blocks = [(G.P_WE, G.P_CE), (G.P_CE, G.P_L0)]
+    for l in range(G.L):
+        o = G.P_L0 + l * G.P_LS
+        blocks += [(o, o + 2 * G.W * G.W), (o + 2 * G.W * G.W, o + G.P_LS)]
+    blocks += [(G.P_WD, G.P_CD), (G.P_CD, G.NPARAM)]
+    gmax = np.abs(g_gpu).max()
+    worst = 0.0
+    for lo, hi in blocks:
+        # the parameters of this block with the largest gradients, plus random ones
+        idx = list(lo + np.argsort(-np.abs(g_gpu[lo:hi]))[:3]) + list(rng.integers(lo, hi, 2))
+        for i in idx:
+            d = 1e-4 * max(abs(p[i]), 1e-2)
+            pp, pm = p.copy(), p.copy()
+            pp[i] += d
+            pm[i] -= d
+            fd = (net.loss(pp) - net.loss(pm)) / (2 * d)
+            e = abs(g_gpu[i] - fd) / max(abs(fd), 1e-3 * gmax)
+            worst = max(worst, e)
+            assert e < 2e-3, (i, g_gpu[i], fd)
+    say(kind, "worst relative gradient error", worst, "max |g|", gmax)
+
+
+def test_training_lowers_loss_and_keeps_the_solution():
+    import paper_2603_08079_amd as pk
+
+    asm = mi.lattice(10, seed=23)
+    ctx, _ = _setup(asm, seed=14)
+    l0, l1 = ctx.gnn_train(asm.h, 60, 3e-3)
+    say("loss before", l0, "after 60 Adam steps", l1)
+    assert l1 < l0
+    # PCG with the learned start: same converged solution as a cold start
+    tol = 1e-10
+    q, qd = ctx.state()
+    cold = pk.Context(asm, kkt_tol=tol, warm_start=0)
+    cold.set_state(q, qd)
+    cold.step(asm.h, 1)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "w.bin")
+        ctx.gnn_save(path)
+        warm = pk.Context(asm, kkt_tol=tol, warm_start=2)
+        warm.gnn_load(path)
+        assert np.array_equal(warm.gnn_params(), ctx.gnn_params())
+    warm.set_state(q, qd)
+    warm.step(asm.h, 1)
+    sw = warm.stats()
+    qc, qdc = cold.state()
+    qw, qdw = warm.state()
+    eq, eqd = state_errors(qw, qdw, qc, qdc)
+    s = oracle.System(asm)
+    _, _, dv = s.finish(asm.h, q, qd, warm.multipliers())
+    say("accepted", sw["warm_accepted"], "iters warm", sw["pcg_iters"], "cold", cold.stats()["pcg_iters"],
+        "state diff", eq, eqd, "oracle rho_d", dv[oracle.RHO_D])
+    assert dv[oracle.RHO_D] <= 2 * tol
+    assert eq < 1e-10 and eqd < 1e-5
+
+
+def test_rejected_start_falls_back_to_zero():
+    """Weights scaled up until the start's energy is above zero's: the solve
+    must drop it and still converge."""
+    import paper_2603_08079_amd as pk
+
+    asm = mi.lattice(6, seed=24)
+    ctx = pk.Context(asm, kkt_tol=1e-10, warm_start=2)
+    ctx.gnn_init(15)
+    p = ctx.gnn_params()
+    p[G.P_CD:] = 1e3  # a large constant start
+    ctx.gnn_params(set_to=p)
+    ctx.step(asm.h, 1)
+    st = ctx.stats()
+    assert st["warm_accepted"] == 0 and st["rho_d"] <= 1e-10
+
+
+def test_gnn_needs_a_ball_network():
+    import paper_2603_08079_amd as pk
+
+    ctx = pk.Context(mi.chain(50, seed=25))
+    with pytest.raises(pk.MabdError) as ei:
+        ctx.gnn_init(0)
+    assert ei.value.status == pk.ERR_INVALID_ARG
