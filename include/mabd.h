@@ -173,16 +173,19 @@ mabd_status mabd_stats(const mabd_ctx *ctx, mabd_step_stats *st);
 
 /* ---------------------------------------------------------------------------
    Learned warm start of the ball-network PCG (warm_start = 2).  Not part of
-   the paper's method: it only supplies the PCG start value, which the solve
-   keeps only if its dual energy 1/2 l^T S l - b^T l is below zero (then its
-   S-norm error is below the cold start's; stats.warm_accepted says which).
-   A message-passing network over the joints (3 layers of width 64, FP32,
-   mabd_gnn_size() parameters) maps per-joint features (block-Jacobi start,
-   previous multipliers, degrees, world sides) to multipliers.  Training
-   minimises that energy, normalised by |b^T D^{-1} b|, over the dual systems
-   of the states the caller steps through; everything runs on the context's
-   stream.  All calls need a ball-joint network component (INVALID_ARG
-   otherwise) and, except init / set, weights (INVALID_ARG otherwise).
+   the paper's method: it only supplies the PCG start value.  A
+   message-passing network over the joints (3 layers of width 64, FP32,
+   mabd_gnn_size() parameters) predicts a correction of the base start (the
+   previous step's multipliers, or zero on a first step) from per-joint
+   features (block-Jacobi step of the base residual, base multipliers,
+   degrees, world sides).  The solve keeps the corrected start only if it
+   lowers the dual energy 1/2 l^T S l - b^T l below the base start's (then its
+   S-norm error is smaller; stats.warm_accepted says which start was used).
+   Training minimises that energy decrease, normalised by the energy of a
+   block-Jacobi step, over the dual systems of the states the caller steps
+   through; everything runs on the context's stream.  All calls need a
+   ball-joint network component (INVALID_ARG otherwise) and, except init and
+   set, weights (INVALID_ARG otherwise).
    --------------------------------------------------------------------------- */
 
 /* Number of network parameters (float32). */

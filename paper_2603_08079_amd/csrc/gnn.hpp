@@ -1,28 +1,32 @@
 // Learned warm start for the ball-network PCG (not part of the paper's
 // method; it only supplies the start value of the dual solve).
 //
-// Nodes are the joints of the network; two joints exchange messages through
-// every dynamic body they share.  Per joint j:
-//   x_j   = [D_j^{-1} b_j / s, lambda_prev_j / s, deg_a / 4, deg_b / 4,
-//            world_a, world_b, 0...]                       (16 features)
+// The network refines a base start lambda_b (the previous step's multipliers,
+// or zero) by a correction delta = s y.  Nodes are the joints of the network;
+// two joints exchange messages through every dynamic body they share.  Per
+// joint j, with r_b = b - S lambda_b the base residual and D_j the diagonal
+// block of the dual S:
+//   x_j   = [D_j^{-1} r_bj / s, lambda_bj / s_l, deg_a / 4, deg_b / 4,
+//            world_a, world_b, have_base, 0...]             (16 features)
 //   h^0   = relu(x W_e + c_e)                               (width 64)
 //   m_b   = sum of h^{l-1} over the joints of body b
 //   n_j   = (m_a + m_b) / max(1, deg_a + deg_b)            (world side: 0)
 //   h^l   = relu([h^{l-1}, n] W_l + c_l),  l = 1..3
-//   y_j   = h^3 W_d + c_d,  lambda0_j = s y_j
-// with D_j the diagonal block of the dual S, b the dual right-hand side,
-// s = sqrt(mean_j |D_j^{-1} b_j|^2).  The loss of one system is the energy of
-// the dual quadratic, E(lambda0) = 1/2 lambda0^T S lambda0 - b^T lambda0,
-// divided by E_ref = |b^T D^{-1} b|: its minimiser is the solution and
-// E - E_min = 1/2 |lambda0 - lambda*|_S^2, the error that bounds conjugate
-// gradients; E < 0 means the start is better than zero in that norm.
+//   y_j   = h^3 W_d + c_d,  lambda0_j = lambda_bj + s y_j
+// s = sqrt(mean_j |D_j^{-1} r_bj|^2), s_l = sqrt(mean_j |lambda_bj|^2) (1 if
+// zero).  The loss of one system is the decrease of the dual energy
+// E(l) = 1/2 l^T S l - b^T l from the base start,
+//   E(lambda0) - E(lambda_b) = 1/2 delta^T S delta - delta^T r_b,
+// divided by E_ref = |r_b^T D^{-1} r_b|.  Since E(l) - E_min is half the
+// squared S-norm error, the error that bounds conjugate gradients, a negative
+// loss means the learned start is better than the base start.
 #pragma once
 #include <cstdint>
 
 namespace mabd {
 
 constexpr int GNN_W = 64;       // width
-constexpr int GNN_FIN = 16;     // input features (10 used)
+constexpr int GNN_FIN = 16;     // input features (11 used)
 constexpr int GNN_L = 3;        // message-passing layers
 // parameter layout (float32, weights row-major [in][out], each followed by
 // its bias)
@@ -45,8 +49,9 @@ struct GnnBufs {
   float *dY;                // nj x 3
   float *params, *grad, *adam_m, *adam_v;
   float *wpart;             // weight-gradient partials
+  double *lb, *rb;          // 3 x nj: base start and its residual b - S lambda_b
   double *red;              // reduction partials (4 per joint block)
-  double *sc;               // [0] s, [1] E_ref, [2] loss, [3] energy
+  double *sc;               // [0] s, [1] E_ref, [2] loss, [3] energy decrease, [4] s_l
 };
 
 }  // namespace mabd

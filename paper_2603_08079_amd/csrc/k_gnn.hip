@@ -33,61 +33,84 @@ DEV float joint_norm(const PcgBallArgs &a, int j) {
 }
 
 // ---------------------------------------------------------------- features
-// partials of |D^{-1} b|^2 and b^T D^{-1} b
-__global__ __launch_bounds__(GT) void gnn_feat_a_kernel(PcgBallArgs a, GnnBufs g) {
-  __shared__ double sh[GT];
+// base start lambda_b (previous multipliers or zero) into g.lb and a.x, so
+// that a body pass can form S lambda_b
+__global__ __launch_bounds__(GT) void gnn_base_kernel(PcgBallArgs a, GnnBufs g, int have_prev) {
   const int j = blockIdx.x * GT + threadIdx.x;
-  double zz = 0.0, bz = 0.0;
-  if (j < a.nj) {
-    double b[3], z[3];
-    for (int r = 0; r < 3; ++r) b[r] = a.bv[3 * (int64_t)j + r];
-    precond(a.dinv + 6 * (int64_t)j, b, z);
-    for (int r = 0; r < 3; ++r) {
-      zz += z[r] * z[r];
-      bz += b[r] * z[r];
-    }
-  }
-  const double s0 = gnn_block_sum(zz, sh), s1 = gnn_block_sum(bz, sh);
-  if (threadIdx.x == 0) {
-    g.red[4 * (int64_t)blockIdx.x + 0] = s0;
-    g.red[4 * (int64_t)blockIdx.x + 1] = s1;
+  if (j >= a.nj) return;
+  const int k = a.jid[j];
+  for (int r = 0; r < 3; ++r) {
+    const double v = have_prev ? a.glam[5 * (int64_t)k + r] : 0.0;
+    g.lb[3 * (int64_t)j + r] = v;
+    a.x[3 * (int64_t)j + r] = v;
   }
 }
 
-// one block: s and E_ref from the partials
+// r_b = b - S lambda_b (S lambda_b from the body pass on a.x when have_prev);
+// partials of |D^{-1} r_b|^2, r_b^T D^{-1} r_b and |lambda_b|^2
+__global__ __launch_bounds__(GT) void gnn_feat_a_kernel(PcgBallArgs a, GnnBufs g, int have_prev) {
+  __shared__ double sh[GT];
+  const int j = blockIdx.x * GT + threadIdx.x;
+  double zz = 0.0, rz = 0.0, ll = 0.0;
+  if (j < a.nj) {
+    double y[3] = {0.0, 0.0, 0.0}, rb[3], z[3];
+    if (have_prev) joint_one(a, j, y);
+    for (int r = 0; r < 3; ++r) {
+      rb[r] = a.bv[3 * (int64_t)j + r] - y[r];
+      g.rb[3 * (int64_t)j + r] = rb[r];
+      const double l = g.lb[3 * (int64_t)j + r];
+      ll += l * l;
+    }
+    precond(a.dinv + 6 * (int64_t)j, rb, z);
+    for (int r = 0; r < 3; ++r) {
+      zz += z[r] * z[r];
+      rz += rb[r] * z[r];
+    }
+  }
+  const double s0 = gnn_block_sum(zz, sh), s1 = gnn_block_sum(rz, sh), s2 = gnn_block_sum(ll, sh);
+  if (threadIdx.x == 0) {
+    g.red[4 * (int64_t)blockIdx.x + 0] = s0;
+    g.red[4 * (int64_t)blockIdx.x + 1] = s1;
+    g.red[4 * (int64_t)blockIdx.x + 3] = s2;
+  }
+}
+
+// one block: s, E_ref and s_l from the partials
 __global__ __launch_bounds__(GT) void gnn_feat_reduce_kernel(int nj, int nblk, GnnBufs g) {
   __shared__ double sh[GT];
-  double a0 = 0.0, a1 = 0.0;
+  double a0 = 0.0, a1 = 0.0, a3 = 0.0;
   for (int b = threadIdx.x; b < nblk; b += GT) {
     a0 += g.red[4 * (int64_t)b + 0];
     a1 += g.red[4 * (int64_t)b + 1];
+    a3 += g.red[4 * (int64_t)b + 3];
   }
-  const double zz = gnn_block_sum(a0, sh), bz = gnn_block_sum(a1, sh);
+  const double zz = gnn_block_sum(a0, sh), rz = gnn_block_sum(a1, sh), ll = gnn_block_sum(a3, sh);
   if (threadIdx.x == 0) {
-    const double s = sqrt(zz / (double)max(nj, 1));
+    const double s = sqrt(zz / (double)max(nj, 1)), sl = sqrt(ll / (double)max(nj, 1));
     g.sc[0] = s > 0.0 ? s : 1.0;
-    g.sc[1] = fabs(bz) > 0.0 ? fabs(bz) : 1.0;
+    g.sc[1] = fabs(rz) > 0.0 ? fabs(rz) : 1.0;
+    g.sc[4] = sl > 0.0 ? sl : 1.0;
   }
 }
 
 __global__ __launch_bounds__(GT) void gnn_feat_b_kernel(PcgBallArgs a, GnnBufs g, int have_prev) {
   const int j = blockIdx.x * GT + threadIdx.x;
   if (j >= a.nj) return;
-  const double is = 1.0 / g.sc[0];
-  double b[3], z[3];
-  for (int r = 0; r < 3; ++r) b[r] = a.bv[3 * (int64_t)j + r];
-  precond(a.dinv + 6 * (int64_t)j, b, z);
+  const double is = 1.0 / g.sc[0], isl = 1.0 / g.sc[4];
+  double rb[3], z[3];
+  for (int r = 0; r < 3; ++r) rb[r] = g.rb[3 * (int64_t)j + r];
+  precond(a.dinv + 6 * (int64_t)j, rb, z);
   float *x = g.x0 + (int64_t)GNN_FIN * j;
-  const int k = a.jid[j];
   for (int r = 0; r < 3; ++r) {
     x[r] = (float)(z[r] * is);
-    x[3 + r] = have_prev ? (float)(a.glam[5 * (int64_t)k + r] * is) : 0.0f;
+    x[3 + r] = (float)(g.lb[3 * (int64_t)j + r] * isl);
   }
   x[6] = 0.25f * (float)body_deg(a, a.jba[j]);
   x[7] = 0.25f * (float)body_deg(a, a.jbb[j]);
   x[8] = a.jba[j] < 0 ? 1.0f : 0.0f;
   x[9] = a.jbb[j] < 0 ? 1.0f : 0.0f;
-  for (int r = 10; r < GNN_FIN; ++r) x[r] = 0.0f;
+  x[10] = have_prev ? 1.0f : 0.0f;
+  for (int r = 11; r < GNN_FIN; ++r) x[r] = 0.0f;
 }
 
 // ----------------------------------------------------------- dense layers
@@ -264,7 +287,7 @@ __global__ __launch_bounds__(GT) void gnn_aggbwd_kernel(PcgBallArgs a, const flo
 }
 
 // ------------------------------------------------------------------- loss
-// lambda0 = s y (FP64, into a.x)
+// delta = s y (FP64, into a.x)
 __global__ __launch_bounds__(GT) void gnn_lam_kernel(PcgBallArgs a, GnnBufs g) {
   const int j = blockIdx.x * GT + threadIdx.x;
   if (j >= a.nj) return;
@@ -272,12 +295,20 @@ __global__ __launch_bounds__(GT) void gnn_lam_kernel(PcgBallArgs a, GnnBufs g) {
   for (int r = 0; r < 3; ++r) a.x[3 * (int64_t)j + r] = s * (double)g.y[3 * (int64_t)j + r];
 }
 
+// lambda0 = lambda_b + delta (a.x holds delta)
+__global__ __launch_bounds__(GT) void gnn_add_base_kernel(PcgBallArgs a, GnnBufs g) {
+  const int j = blockIdx.x * GT + threadIdx.x;
+  if (j >= a.nj) return;
+  for (int r = 0; r < 3; ++r) a.x[3 * (int64_t)j + r] += g.lb[3 * (int64_t)j + r];
+}
+
 __global__ __launch_bounds__(GT) void gnn_body_kernel(PcgBallArgs a) {
   const int i = blockIdx.x * GT + threadIdx.x;
   if (i < a.nbd) body_one(a, i, a.x, nullptr, 0.0);
 }
 
-// energy partials and dL/dy = s (S lambda0 - b) / E_ref
+// partials of the energy decrease 1/2 delta^T S delta - delta^T r_b and
+// dL/dy = s (S delta - r_b) / E_ref (a.x holds delta, zw its body pass)
 __global__ __launch_bounds__(GT) void gnn_loss_kernel(PcgBallArgs a, GnnBufs g) {
   __shared__ double sh[GT];
   const int j = blockIdx.x * GT + threadIdx.x;
@@ -287,9 +318,9 @@ __global__ __launch_bounds__(GT) void gnn_loss_kernel(PcgBallArgs a, GnnBufs g) 
     joint_one(a, j, y);
     const double f = g.sc[0] / g.sc[1];
     for (int r = 0; r < 3; ++r) {
-      const double l = a.x[3 * (int64_t)j + r], b = a.bv[3 * (int64_t)j + r];
-      e += 0.5 * l * y[r] - b * l;
-      g.dY[3 * (int64_t)j + r] = (float)(f * (y[r] - b));
+      const double d = a.x[3 * (int64_t)j + r], rb = g.rb[3 * (int64_t)j + r];
+      e += 0.5 * d * y[r] - rb * d;
+      g.dY[3 * (int64_t)j + r] = (float)(f * (y[r] - rb));
     }
   }
   const double s = gnn_block_sum(e, sh);
@@ -326,11 +357,13 @@ constexpr int WROWS = 1024;  // rows per weight-gradient block
 
 int gnn_wgrad_blocks(int nj) { return std::max(1, (nj + WROWS - 1) / WROWS); }
 
-// features, layers, decoder, lambda0 into a.x
+// base start and residual, features, layers, decoder; delta = s y into a.x
 void launch_gnn_forward(const PcgBallArgs &a, const GnnBufs &g, int have_prev, hipStream_t s) {
   const int nj = a.nj;
   const unsigned jb = blocks_of(nj);
-  hipLaunchKernelGGL(gnn_feat_a_kernel, dim3(jb), dim3(GT), 0, s, a, g);
+  hipLaunchKernelGGL(gnn_base_kernel, dim3(jb), dim3(GT), 0, s, a, g, have_prev);
+  if (have_prev) hipLaunchKernelGGL(gnn_body_kernel, dim3(blocks_of(a.nbd)), dim3(GT), 0, s, a);
+  hipLaunchKernelGGL(gnn_feat_a_kernel, dim3(jb), dim3(GT), 0, s, a, g, have_prev);
   hipLaunchKernelGGL(gnn_feat_reduce_kernel, dim3(1), dim3(GT), 0, s, nj, (int)jb, g);
   hipLaunchKernelGGL(gnn_feat_b_kernel, dim3(jb), dim3(GT), 0, s, a, g, have_prev);
   gemm<GNN_FIN, GNN_W, true, false, false>(g.x0, g.params + GNN_P_WE, g.params + GNN_P_CE, nullptr, g.H[0],
@@ -348,7 +381,7 @@ void launch_gnn_forward(const PcgBallArgs &a, const GnnBufs &g, int have_prev, h
   hipLaunchKernelGGL(gnn_lam_kernel, dim3(jb), dim3(GT), 0, s, a, g);
 }
 
-// energy of a.x (loss in g.sc[2], energy in g.sc[3]) and dL/dy
+// energy decrease of delta = a.x (loss in g.sc[2], decrease in g.sc[3]) and dL/dy
 void launch_gnn_loss(const PcgBallArgs &a, const GnnBufs &g, hipStream_t s) {
   const unsigned jb = blocks_of(a.nj);
   hipLaunchKernelGGL(gnn_body_kernel, dim3(blocks_of(a.nbd)), dim3(GT), 0, s, a);
@@ -380,6 +413,10 @@ void launch_gnn_backward(const PcgBallArgs &a, const GnnBufs &g, hipStream_t s) 
                        g.m, g.H[l], g.dZ);
   }
   wgrad<GNN_FIN, GNN_W>(g.x0, g.dZ, nj, g.wpart, g.grad + GNN_P_WE, s);
+}
+
+void launch_gnn_add_base(const PcgBallArgs &a, const GnnBufs &g, hipStream_t s) {
+  hipLaunchKernelGGL(gnn_add_base_kernel, dim3(blocks_of(a.nj)), dim3(GT), 0, s, a, g);
 }
 
 void launch_gnn_adam(const GnnBufs &g, float lr, int64_t t, hipStream_t s) {

@@ -64,6 +64,7 @@ void launch_gnn_forward(const PcgBallArgs &a, const GnnBufs &g, int have_prev, h
 void launch_gnn_loss(const PcgBallArgs &a, const GnnBufs &g, hipStream_t s);
 void launch_gnn_backward(const PcgBallArgs &a, const GnnBufs &g, hipStream_t s);
 void launch_gnn_adam(const GnnBufs &g, float lr, int64_t t, hipStream_t s);
+void launch_gnn_add_base(const PcgBallArgs &a, const GnnBufs &g, hipStream_t s);
 int gnn_wgrad_blocks(int nj);
 int pcg_max_blocks();
 }  // namespace mabd
@@ -1116,6 +1117,8 @@ hipError_t gnn_alloc(mabd_ctx *c) {
   chk(dalloc(c, &g.adam_m, (size_t)GNN_NPARAM));
   chk(dalloc(c, &g.adam_v, (size_t)GNN_NPARAM));
   chk(dalloc(c, &g.wpart, (size_t)gnn_wgrad_blocks((int)nj) * (2 * GNN_W + 1) * GNN_W));
+  chk(dalloc(c, &g.lb, 3 * nj));
+  chk(dalloc(c, &g.rb, 3 * nj));
   chk(dalloc(c, &g.red, 4 * ((nj + 255) / 256)));
   chk(dalloc(c, &g.sc, 8));
   if (e == hipSuccess && !c->h_gsc) e = hipHostMalloc((void **)&c->h_gsc, 4 * sizeof(double));
@@ -1205,19 +1208,23 @@ hipError_t run_pcg_ball(mabd_ctx *c, const PcgBallArgs &pb, hipStream_t s) {
   launch_pb_setup(pb, s);
   c->stats.warm_accepted = 0;
   if (c->opt.warm_start == 2 && c->gnn_ready) {
-    // learned start, kept only if its dual energy is below that of zero
-    // (then its S-norm error is smaller than the cold start's)
-    launch_gnn_forward(pb, c->gb, c->warm_valid ? 1 : 0, s);
+    // learned correction of the base start (previous multipliers, or zero),
+    // kept only if it lowers the dual energy, i.e. the S-norm error
+    const int prev = c->warm_valid ? 1 : 0;
+    launch_gnn_forward(pb, c->gb, prev, s);
     launch_gnn_loss(pb, c->gb, s);
     hipError_t e = hipMemcpyAsync(c->h_gsc, c->gb.sc + 3, sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
     if (c->h_gsc[0] < 0.0) {
       c->stats.warm_accepted = 1;
+      launch_gnn_add_base(pb, c->gb, s);
       launch_pb_residual(pb, 1, 0, s);
     } else {
-      launch_pb_setup(pb, s);  // x = 0 again (pb.warm is 0 here)
-      launch_pb_residual(pb, 0, 0, s);
+      PcgBallArgs base = pb;
+      base.warm = prev;
+      launch_pb_setup(base, s);  // x = the base start again
+      launch_pb_residual(base, prev, 0, s);
     }
   } else {
     launch_pb_residual(pb, pb.warm, 0, s);
@@ -1719,6 +1726,7 @@ mabd_status mabd_gnn_predict(mabd_ctx *c, double h, double *lam0) {
   hipError_t e = gnn_prepare(c, h, pb);
   if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
   launch_gnn_forward(pb, c->gb, c->warm_valid ? 1 : 0, c->stream);
+  launch_gnn_add_base(pb, c->gb, c->stream);
   std::vector<double> x(3 * (size_t)c->pb_nj);
   std::vector<int32_t> jid(c->pb_nj);
   e = hipMemcpyAsync(x.data(), pb.x, x.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);

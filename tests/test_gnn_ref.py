@@ -24,18 +24,20 @@ def _net(asm, lam_prev=None):
 
 
 def test_energy_identity():
-    """E(l) - E(l*) = 1/2 |l - l*|_S^2 with l* = S^{-1} r (the loss is the
-    quadratic whose minimiser is the dual solution)."""
+    """The loss is the decrease of the dual energy E(l) = 1/2 l^T S l - r^T l
+    from the base start, and E(l) - E(l*) = 1/2 |l - l*|_S^2 with
+    l* = S^{-1} r: checked against the plain energy, with and without a base."""
     asm = mi.lattice(5, seed=1)
-    net, S, r = _net(asm)
-    p = _params(2)
-    lam = net.forward(p).ravel()
-    Sd = S.toarray()
-    ls = np.linalg.solve(Sd, r)
-    e_min = -0.5 * r @ ls
-    lhs = net.loss(p) * net.eref - e_min
-    rhs = 0.5 * (lam - ls) @ Sd @ (lam - ls)
-    assert abs(lhs - rhs) <= 1e-9 * max(abs(rhs), abs(e_min))
+    for base in (None, np.random.default_rng(8).normal(0.0, 5.0, 3 * asm.m)):
+        net, S, r = _net(asm, base)
+        p = _params(2)
+        lam = net.forward(p).ravel()
+        Sd = S.toarray()
+        E = lambda l: 0.5 * l @ Sd @ l - r @ l
+        lb = np.zeros_like(lam) if base is None else base
+        assert abs(net.loss(p) * net.eref - (E(lam) - E(lb))) <= 1e-9 * abs(E(lb) - E(lam)) + 1e-12 * abs(E(lb))
+        ls = np.linalg.solve(Sd, r)
+        assert abs((E(lam) - E(ls)) - 0.5 * (lam - ls) @ Sd @ (lam - ls)) <= 1e-9 * abs(E(ls))
 
 
 def test_permutation_equivariance():
@@ -63,7 +65,7 @@ def test_two_joint_message_by_hand():
     asm = mi.chain(3, seed=7)
     net, _, _ = _net(asm)
     assert list(net.ja) == [-1, 1] and list(net.jb) == [1, 2]
-    assert np.allclose(net.x[:, 6:10], [[0.0, 0.5, 1.0, 0.0], [0.5, 0.25, 0.0, 0.0]])
+    assert np.allclose(net.x[:, 6:11], [[0.0, 0.5, 1.0, 0.0, 0.0], [0.5, 0.25, 0.0, 0.0, 0.0]])
     p = np.zeros(G.NPARAM)
     p[G.P_WE + 7 * G.W + 0] = 4.0
     p[G.P_L0 + 64 * G.W + 0] = 1.0
