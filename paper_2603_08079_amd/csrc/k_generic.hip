@@ -217,6 +217,97 @@ DEV void team_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Clique matrix of one body without its children's condensed far sides:
+// K0 = L Hbar^{-1} L^T (lower triangle) and y0 = L u + C (C of one-sided and
+// parent joints), written to the body's factor slot.  Independent of every
+// other body, so all bodies of all components run in one parallel pre-pass;
+// the level-ordered elimination then only adds the children's Sigma, rho and
+// factors.
+__global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const GJoint *J, int nslots) {
+  __shared__ TeamLds team_lds[TEAMS];
+  const int tm = threadIdx.x / TEAM, ln = threadIdx.x % TEAM;
+  TeamLds &S = team_lds[tm];
+  if (skip_step(a.status, a.step)) return;
+  const int slot = blockIdx.x * TEAMS + tm;
+  if (slot >= nslots) return;  // whole teams only: team_sync is wave-local
+  const int64_t b = a.tbody[slot];
+  const double *Th = a.hinv + (int64_t)HINV_STRIDE * a.shp[b];
+  const int pk = a.tpk[slot];
+  const int kpar = pk >= 0 ? (pk >> 1) : -1;
+  const int ck = kpar >= 0 ? (J[kpar].type ? 5 : 3) : 0;
+  const int e0 = a.tabs_off[slot], e1 = a.tabs_off[slot + 1];
+  const int ne = a.tne[slot];
+  const int nr = ne + ck;
+  if (nr == 0) return;
+  double *fac = a.fac + a.foff[slot];  // nr*nr K, nr y, then (big cliques) L, Y
+  const bool big = nr > TREE_KLDS;
+  double *Lm = big ? fac + nr * nr + nr : S.L;
+  double *Ym = big ? fac + nr * nr + nr + 12 * nr : S.Y;
+  // 1) clique rows: absorbed joints in list order, then the parent joint
+  {
+    int r0 = 0;
+    for (int e = e0; e <= e1; ++e) {
+      int k, side;
+      if (e < e1) {
+        k = a.tabs[e] >> 2;
+        side = (a.tabs[e] >> 1) & 1;
+      } else {
+        if (kpar < 0) break;
+        k = kpar;
+        side = pk & 1;
+      }
+      const int c = J[k].type ? 5 : 3;
+      const double *Lsrc = a.gl + (int64_t)GL_STRIDE * k + (side ? GL_LB : GL_LA);
+      for (int i = ln; i < c * 12; i += TEAM) Lm[r0 * 12 + i] = Lsrc[i];
+      r0 += c;
+    }
+  }
+  team_sync();
+  // 2) Y = Hbar^{-1} L^T, one clique row per lane
+  for (int col = ln; col < nr; col += TEAM) {
+    double yv[12];
+    hinv_apply(Th, Lm + 12 * col, yv);
+    for (int s = 0; s < 12; ++s) Ym[s * nr + col] = yv[s];
+  }
+  team_sync();
+  // 3) K0 = L Y (lower triangle), y0 = L u + C of one-sided and parent rows
+  for (int idx = ln; idx < nr * nr; idx += TEAM) {
+    const int i = idx / nr, jj = idx % nr;
+    double v = 0.0;
+    if (jj <= i)
+      for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * Ym[s * nr + jj];
+    fac[idx] = v;
+  }
+  for (int i = ln; i < nr; i += TEAM) {
+    double v = 0.0;
+    for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * a.u[s * a.ns + b];
+    fac[nr * nr + i] = v;
+  }
+  team_sync();
+  {
+    int r0 = 0;
+    for (int e = e0; e <= e1; ++e) {
+      int k, unary;
+      if (e < e1) {
+        k = a.tabs[e] >> 2;
+        unary = a.tabs[e] & 1;
+      } else {
+        if (kpar < 0) break;
+        k = kpar;
+        unary = 1;  // parent rows take C_k only
+      }
+      const int c = J[k].type ? 5 : 3;
+      if (e == e1 || unary)
+        for (int i = ln; i < c; i += TEAM) fac[nr * nr + r0 + i] += a.gl[(int64_t)GL_STRIDE * k + GL_C + i];
+      r0 += c;
+    }
+  }
+}
+
+// Leaves first, per level: add the condensed far sides (Sigma, rho) of the
+// child joints to K0, y0, factor the absorbed rows (partial Cholesky) and
+// pass the Schur complement on the parent joint up.  One workgroup per
+// component; a 16-lane team per body of the level.
 __global__ __launch_bounds__(TREE_BLOCK) void tree_forward_kernel(TreeArgs a, const GJoint *J) {
   __shared__ TeamLds team_lds[TEAMS];
   const int tm = threadIdx.x / TEAM, ln = threadIdx.x % TEAM;
@@ -226,93 +317,41 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_forward_kernel(TreeArgs a, co
   for (int lv = l0; lv < l1; ++lv) {
     const int s0 = a.lvl_off[lv], s1 = a.lvl_off[lv + 1];
     for (int slot = s0 + tm; slot < s1; slot += TEAMS) {
-      const int64_t b = a.tbody[slot];
-      const double *Th = a.hinv + (int64_t)HINV_STRIDE * a.shp[b];
       const int pk = a.tpk[slot];
       const int kpar = pk >= 0 ? (pk >> 1) : -1;
       const int ck = kpar >= 0 ? (J[kpar].type ? 5 : 3) : 0;
       const int e0 = a.tabs_off[slot], e1 = a.tabs_off[slot + 1];
       const int ne = a.tne[slot];
       const int nr = ne + ck;
-      double *fac = a.fac + a.foff[slot];  // nr*nr K, nr y, then (big cliques) L, Y
+      if (nr == 0) continue;
+      double *fac = a.fac + a.foff[slot];
       const bool big = nr > TREE_KLDS;
-      double *Lm = big ? fac + nr * nr + nr : S.L;
-      double *Ym = big ? fac + nr * nr + nr + 12 * nr : S.Y;
       double *Km = big ? fac : S.K;
       double *ym = big ? fac + nr * nr : S.y;
-      // 1) clique rows: absorbed joints in list order, then the parent joint
+      if (!big) {
+        for (int idx = ln; idx < nr * nr; idx += TEAM) Km[idx] = fac[idx];
+        for (int i = ln; i < nr; i += TEAM) ym[i] = fac[nr * nr + i];
+      }
+      team_sync();
+      // condensed far sides of the child joints
       {
         int r0 = 0;
-        for (int e = e0; e <= e1; ++e) {
-          int k, side;
-          if (e < e1) {
-            k = a.tabs[e] >> 2;
-            side = (a.tabs[e] >> 1) & 1;
-          } else {
-            if (kpar < 0) break;
-            k = kpar;
-            side = pk & 1;
-          }
+        for (int e = e0; e < e1; ++e) {
+          const int k = a.tabs[e] >> 2;
           const int c = J[k].type ? 5 : 3;
-          const double *Lsrc = a.gl + (int64_t)GL_STRIDE * k + (side ? GL_LB : GL_LA);
-          for (int i = ln; i < c * 12; i += TEAM) Lm[r0 * 12 + i] = Lsrc[i];
-          if (!big && ln < c) {
-            S.rowk[r0 + ln] = k;
-            S.rowi[r0 + ln] = ln;
-          }
-          r0 += c;
-        }
-      }
-      team_sync();
-      // 2) Y = Hbar^{-1} L^T, one clique row per lane
-      for (int col = ln; col < nr; col += TEAM) {
-        double yv[12];
-        hinv_apply(Th, Lm + 12 * col, yv);
-        for (int s = 0; s < 12; ++s) Ym[s * nr + col] = yv[s];
-      }
-      team_sync();
-      // 3) K = L Y (lower triangle), y = L u + constants
-      for (int idx = ln; idx < nr * nr; idx += TEAM) {
-        const int i = idx / nr, jj = idx % nr;
-        if (jj > i) continue;
-        double v = 0.0;
-        for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * Ym[s * nr + jj];
-        Km[i * nr + jj] = v;
-      }
-      for (int i = ln; i < nr; i += TEAM) {
-        double v = 0.0;
-        for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * a.u[s * a.ns + b];
-        ym[i] = v;
-      }
-      team_sync();
-      // far-side terms: Sigma and rho of child joints, C of one-sided and parent joints
-      if (ln == 0) {
-        int r0 = 0;
-        for (int e = e0; e <= e1; ++e) {
-          int k, unary;
-          if (e < e1) {
-            k = a.tabs[e] >> 2;
-            unary = a.tabs[e] & 1;
-          } else {
-            if (kpar < 0) break;
-            k = kpar;
-            unary = 1;  // parent rows take C_k only
-          }
-          const int c = J[k].type ? 5 : 3;
-          if (e < e1 && !unary) {
+          if (!(a.tabs[e] & 1)) {
             const double *gtk = a.gt + (int64_t)GT_STRIDE * k;
-            for (int i = 0; i < c; ++i) {
-              for (int jj = 0; jj <= i; ++jj) Km[(r0 + i) * nr + r0 + jj] += gtk[GT_SIG + 5 * i + jj];
-              ym[r0 + i] += gtk[GT_RHO + i];
+            for (int idx = ln; idx < c * c; idx += TEAM) {
+              const int i = idx / c, jj = idx % c;
+              if (jj <= i) Km[(r0 + i) * nr + r0 + jj] += gtk[GT_SIG + 5 * i + jj];
             }
-          } else {
-            for (int i = 0; i < c; ++i) ym[r0 + i] += a.gl[(int64_t)GL_STRIDE * k + GL_C + i];
+            for (int i = ln; i < c; i += TEAM) ym[r0 + i] += gtk[GT_RHO + i];
           }
           r0 += c;
         }
       }
       team_sync();
-      // 4) partial Cholesky over the ne absorbed rows (lower triangle, in place)
+      // partial Cholesky over the ne absorbed rows (lower triangle, in place)
       for (int p = 0; p < ne; ++p) {
         if (ln == 0) {
           double d = Km[p * nr + p];
@@ -335,7 +374,7 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_forward_kernel(TreeArgs a, co
         }
         team_sync();
       }
-      // 5) Schur complement on the parent joint; factor to the body's slot
+      // Schur complement on the parent joint; factor to the body's slot
       if (kpar >= 0) {
         double *gtk = a.gt + (int64_t)GT_STRIDE * kpar;
         for (int idx = ln; idx < 25; idx += TEAM) {
@@ -518,8 +557,10 @@ void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, in
   if (m > 0)
     hipLaunchKernelGGL(gjoint_kernel, dim3((m + 127) / 128), dim3(128), 0, s, m, J, q, Rg, ns, hg, gl);
 }
-void launch_tree(const TreeArgs &a, const GJoint *J, int ncomp, hipStream_t s) {
+void launch_tree(const TreeArgs &a, const GJoint *J, int ncomp, int nslots, hipStream_t s) {
   if (ncomp > 0) {
+    hipLaunchKernelGGL(tree_prep_kernel, dim3((nslots + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
+                       nslots);
     hipLaunchKernelGGL(tree_forward_kernel, dim3(ncomp), dim3(TREE_BLOCK), 0, s, a, J);
     hipLaunchKernelGGL(tree_backward_kernel, dim3(ncomp), dim3(256), 0, s, a, J);
   }

@@ -41,7 +41,7 @@ void launch_gbody(int b0, int b1, const double *q, const double *qn, const doubl
                   double h, double *Rg, double *ug, uint32_t *status, int step, hipStream_t s);
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
                    double *gl, hipStream_t s);
-void launch_tree(const TreeArgs &a, const GJoint *J, int ncomp, hipStream_t s);
+void launch_tree(const TreeArgs &a, const GJoint *J, int ncomp, int nslots, hipStream_t s);
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
@@ -1358,7 +1358,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       ta.tne = c->d_tne;
       ta.foff = c->d_foff;
       ta.fac = c->d_fac;
-      tm.run(5, [&] { launch_tree(ta, c->d_gj, c->ntree, s); });
+      tm.run(5, [&] { launch_tree(ta, c->d_gj, c->ntree, (int)c->tbody.size(), s); });
       if (c->ngraph > 0) {
         PcgArgs pa{};
         pa.nb = c->gb1 - c->gb0;
