@@ -126,6 +126,7 @@ typedef struct {
   int64_t phase_calls[MABD_NPHASES];
   int32_t tile_threads;    /* workgroup size of the chain tile kernels in use            */
   int32_t graph_replay;    /* 1 if the last mabd_step replayed captured step graphs       */
+  int32_t tree_rounds;     /* rounds of the tree contraction (rake + compress)          */
 } mabd_step_stats;
 
 /* Fills *opt with the defaults listed above. */

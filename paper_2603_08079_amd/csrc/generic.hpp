@@ -53,7 +53,24 @@ struct TreeArgs {
   int step;
   const int32_t *tne;       // slot -> absorbed rows
   const int64_t *foff;      // slot -> offset of its factor in fac
-  double *fac;
+  double *fac;              // per slot: K (LD x LD, LD = absorbed rows + 5), y (LD), scratch
+  const struct TcOp *ops;   // contraction schedule
+  double *crec;             // compress records
+};
+
+// One operation of the tree contraction.  rake: eliminate the private rows of
+// slot v (absorbed joints: condensed children and one-sided joints) and pass
+// the Schur complement on its current parent joint kcur up (none at a root).
+// compress: v has exactly one uncondensed child c, joined by joint e (the
+// last absorbed entry of v); eliminate v's private rows, then joint e, which
+// merges v into c: c's parent rows become kcur.
+struct TcOp {
+  int32_t v, c;      // slot eliminated; compress: slot merged into (else -1)
+  int32_t kcur, ck;  // current parent joint of v (generic index, -1 at a root) and its rows
+  int32_t e, ce;     // compress: joint v-c and its rows
+  int32_t nv;        // current rows of v's clique (absorbed + ck)
+  int32_t pad;
+  int64_t rec;       // compress: offset of (Lp 5x5, X_o ce x a_c, X_k 5x5, z 5) in crec
 };
 
 struct PcgArgs {

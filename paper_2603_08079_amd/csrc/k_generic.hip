@@ -239,10 +239,11 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   const int ne = a.tne[slot];
   const int nr = ne + ck;
   if (nr == 0) return;
-  double *fac = a.fac + a.foff[slot];  // nr*nr K, nr y, then (big cliques) L, Y
+  const int LD = ne + 5;
+  double *fac = a.fac + a.foff[slot];  // LD*LD K, LD y, then (big cliques) L, Y
   const bool big = nr > TREE_KLDS;
-  double *Lm = big ? fac + nr * nr + nr : S.L;
-  double *Ym = big ? fac + nr * nr + nr + 12 * nr : S.Y;
+  double *Lm = big ? fac + LD * LD + LD : S.L;
+  double *Ym = big ? fac + LD * LD + LD + 12 * nr : S.Y;
   // 1) clique rows: absorbed joints in list order, then the parent joint
   {
     int r0 = 0;
@@ -276,12 +277,12 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
     double v = 0.0;
     if (jj <= i)
       for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * Ym[s * nr + jj];
-    fac[idx] = v;
+    fac[i * LD + jj] = v;
   }
   for (int i = ln; i < nr; i += TEAM) {
     double v = 0.0;
     for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * a.u[s * a.ns + b];
-    fac[nr * nr + i] = v;
+    fac[LD * LD + i] = v;
   }
   team_sync();
   {
@@ -298,143 +299,278 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
       }
       const int c = J[k].type ? 5 : 3;
       if (e == e1 || unary)
-        for (int i = ln; i < c; i += TEAM) fac[nr * nr + r0 + i] += a.gl[(int64_t)GL_STRIDE * k + GL_C + i];
+        for (int i = ln; i < c; i += TEAM) fac[LD * LD + r0 + i] += a.gl[(int64_t)GL_STRIDE * k + GL_C + i];
       r0 += c;
     }
   }
 }
 
-// Leaves first, per level: add the condensed far sides (Sigma, rho) of the
-// child joints to K0, y0, factor the absorbed rows (partial Cholesky) and
-// pass the Schur complement on the parent joint up.  One workgroup per
-// component; a 16-lane team per body of the level.
-__global__ __launch_bounds__(TREE_BLOCK) void tree_forward_kernel(TreeArgs a, const GJoint *J) {
-  __shared__ TeamLds team_lds[TEAMS];
-  const int tm = threadIdx.x / TEAM, ln = threadIdx.x % TEAM;
-  TeamLds &S = team_lds[tm];
-  if (skip_step(a.status, a.step)) return;
-  const int l0 = a.comp_lvl[blockIdx.x], l1 = a.comp_lvl[blockIdx.x + 1];
-  for (int lv = l0; lv < l1; ++lv) {
-    const int s0 = a.lvl_off[lv], s1 = a.lvl_off[lv + 1];
-    for (int slot = s0 + tm; slot < s1; slot += TEAMS) {
-      const int pk = a.tpk[slot];
-      const int kpar = pk >= 0 ? (pk >> 1) : -1;
-      const int ck = kpar >= 0 ? (J[kpar].type ? 5 : 3) : 0;
-      const int e0 = a.tabs_off[slot], e1 = a.tabs_off[slot + 1];
-      const int ne = a.tne[slot];
-      const int nr = ne + ck;
-      if (nr == 0) continue;
-      double *fac = a.fac + a.foff[slot];
-      const bool big = nr > TREE_KLDS;
-      double *Km = big ? fac : S.K;
-      double *ym = big ? fac + nr * nr : S.y;
-      if (!big) {
-        for (int idx = ln; idx < nr * nr; idx += TEAM) Km[idx] = fac[idx];
-        for (int i = ln; i < nr; i += TEAM) ym[i] = fac[nr * nr + i];
+// Tree contraction (rake and compress rounds, planned on the host).  Every
+// round's operations touch disjoint slots, so each round is one launch per
+// kind; a 16-lane team per operation, matrices in the slots' global storage.
+
+// add the condensed far sides (Sigma, rho) of v's child joints, entries
+// [e0, e1) of its absorbed list
+DEV void tc_add_children(const TreeArgs &a, const GJoint *J, int e0, int e1, double *K, double *y, int LD,
+                         int ln) {
+  int r0 = 0;
+  for (int e = e0; e < e1; ++e) {
+    const int k = a.tabs[e] >> 2;
+    const int c = J[k].type ? 5 : 3;
+    if (!(a.tabs[e] & 1)) {
+      const double *gtk = a.gt + (int64_t)GT_STRIDE * k;
+      for (int idx = ln; idx < c * c; idx += TEAM) {
+        const int i = idx / c, jj = idx % c;
+        if (jj <= i) K[(r0 + i) * LD + r0 + jj] += gtk[GT_SIG + 5 * i + jj];
       }
-      team_sync();
-      // condensed far sides of the child joints
-      {
-        int r0 = 0;
-        for (int e = e0; e < e1; ++e) {
-          const int k = a.tabs[e] >> 2;
-          const int c = J[k].type ? 5 : 3;
-          if (!(a.tabs[e] & 1)) {
-            const double *gtk = a.gt + (int64_t)GT_STRIDE * k;
-            for (int idx = ln; idx < c * c; idx += TEAM) {
-              const int i = idx / c, jj = idx % c;
-              if (jj <= i) Km[(r0 + i) * nr + r0 + jj] += gtk[GT_SIG + 5 * i + jj];
-            }
-            for (int i = ln; i < c; i += TEAM) ym[r0 + i] += gtk[GT_RHO + i];
-          }
-          r0 += c;
-        }
-      }
-      team_sync();
-      // partial Cholesky over the ne absorbed rows (lower triangle, in place)
-      for (int p = 0; p < ne; ++p) {
-        if (ln == 0) {
-          double d = Km[p * nr + p];
-          if (!(d > 0.0)) {
-            raise_flag(a.status, FLAG_SINGULAR, a.step);
-            d = 1.0;
-          }
-          d = sqrt(d);
-          Km[p * nr + p] = d;
-          ym[p] /= d;
-        }
-        team_sync();
-        const double d = Km[p * nr + p];
-        for (int i = p + 1 + ln; i < nr; i += TEAM) Km[i * nr + p] /= d;
-        team_sync();
-        for (int i = p + 1 + ln; i < nr; i += TEAM) {
-          const double lip = Km[i * nr + p];
-          for (int jj = p + 1; jj <= i; ++jj) Km[i * nr + jj] -= lip * Km[jj * nr + p];
-          ym[i] -= lip * ym[p];
-        }
-        team_sync();
-      }
-      // Schur complement on the parent joint; factor to the body's slot
-      if (kpar >= 0) {
-        double *gtk = a.gt + (int64_t)GT_STRIDE * kpar;
-        for (int idx = ln; idx < 25; idx += TEAM) {
-          const int i = idx / 5, jj = idx % 5;
-          double v = 0.0;
-          if (i < ck && jj < ck) v = jj <= i ? Km[(ne + i) * nr + ne + jj] : Km[(ne + jj) * nr + ne + i];
-          gtk[GT_SIG + idx] = v;
-        }
-        if (ln < 5) gtk[GT_RHO + ln] = ln < ck ? ym[ne + ln] : 0.0;
-      }
-      if (!big) {
-        for (int idx = ln; idx < nr * nr; idx += TEAM) fac[idx] = Km[idx];
-        for (int i = ln; i < nr; i += TEAM) fac[nr * nr + i] = ym[i];
-      }
-      team_sync();
+      for (int i = ln; i < c; i += TEAM) y[r0 + i] += gtk[GT_RHO + i];
     }
-    __syncthreads();
+    r0 += c;
   }
 }
 
-// root to leaf: lambda_e = Lc^{-T} (z - X lambda_k), one thread per body
-__global__ __launch_bounds__(256) void tree_backward_kernel(TreeArgs a, const GJoint *J) {
+// partial Cholesky of the first np of nr rows (lower triangle, in place):
+// K_pp = Lc Lc^T, X = Lc^{-1} K_pb, z = Lc^{-1} y_p; the trailing block
+// becomes the Schur complement K_bb - X^T X, y_b - X^T z
+DEV void tc_partial_cholesky(const TreeArgs &a, double *K, double *y, int LD, int nr, int np, int ln) {
+  for (int p = 0; p < np; ++p) {
+    if (ln == 0) {
+      double d = K[p * LD + p];
+      if (!(d > 0.0)) {
+        raise_flag(a.status, FLAG_SINGULAR, a.step);
+        d = 1.0;
+      }
+      d = sqrt(d);
+      K[p * LD + p] = d;
+      y[p] /= d;
+    }
+    team_sync();
+    const double d = K[p * LD + p];
+    for (int i = p + 1 + ln; i < nr; i += TEAM) K[i * LD + p] /= d;
+    team_sync();
+    for (int i = p + 1 + ln; i < nr; i += TEAM) {
+      const double lip = K[i * LD + p];
+      for (int jj = p + 1; jj <= i; ++jj) K[i * LD + jj] -= lip * K[jj * LD + p];
+      y[i] -= lip * y[p];
+    }
+    team_sync();
+  }
+}
+
+__global__ __launch_bounds__(TREE_BLOCK) void tc_rake_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
+  const int tm = threadIdx.x / TEAM, ln = threadIdx.x % TEAM;
   if (skip_step(a.status, a.step)) return;
-  const int l0 = a.comp_lvl[blockIdx.x], l1 = a.comp_lvl[blockIdx.x + 1];
-  for (int lv = l1 - 1; lv >= l0; --lv) {
-    const int s0 = a.lvl_off[lv], s1 = a.lvl_off[lv + 1];
-    for (int slot = s0 + threadIdx.x; slot < s1; slot += blockDim.x) {
-      const int pk = a.tpk[slot];
-      const int kpar = pk >= 0 ? (pk >> 1) : -1;
-      const int ck = kpar >= 0 ? (J[kpar].type ? 5 : 3) : 0;
-      const int ne = a.tne[slot];
-      const int nr = ne + ck;
-      if (ne == 0) continue;
-      const double *K = a.fac + a.foff[slot];
-      const double *y = K + nr * nr;
-      double lk[5] = {0, 0, 0, 0, 0};
-      for (int i = 0; i < ck; ++i) lk[i] = a.glam[5 * (int64_t)kpar + i];
-      // t = z - X lambda_k, X^T stored in rows ne.. of the factor
-      double t[TREE_KMAX];
-      for (int i = 0; i < ne; ++i) {
-        double v = y[i];
-        for (int f = 0; f < ck; ++f) v -= K[(ne + f) * nr + i] * lk[f];
-        t[i] = v;
+  const int i = op0 + blockIdx.x * TEAMS + tm;
+  if (i >= op1) return;
+  const TcOp op = a.ops[i];
+  const int v = op.v;
+  const int ne = a.tne[v], LD = ne + 5;
+  double *K = a.fac + a.foff[v];
+  double *y = K + LD * LD;
+  tc_add_children(a, J, a.tabs_off[v], a.tabs_off[v + 1], K, y, LD, ln);
+  team_sync();
+  tc_partial_cholesky(a, K, y, LD, op.nv, ne, ln);
+  if (op.kcur >= 0) {
+    double *gtk = a.gt + (int64_t)GT_STRIDE * op.kcur;
+    for (int idx = ln; idx < 25; idx += TEAM) {
+      const int r = idx / 5, s = idx % 5;
+      double val = 0.0;
+      if (r < op.ck && s < op.ck) val = s <= r ? K[(ne + r) * LD + ne + s] : K[(ne + s) * LD + ne + r];
+      gtk[GT_SIG + idx] = val;
+    }
+    if (ln < 5) gtk[GT_RHO + ln] = ln < op.ck ? y[ne + ln] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(TREE_BLOCK) void tc_compress_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
+  __shared__ double scratch[TEAMS][160];
+  const int tm = threadIdx.x / TEAM, ln = threadIdx.x % TEAM;
+  if (skip_step(a.status, a.step)) return;
+  const int i = op0 + blockIdx.x * TEAMS + tm;
+  if (i >= op1) return;
+  double *M = scratch[tm];  // boundary Schur complement of v, 10 x 10
+  double *m = M + 100;      // its right-hand side
+  double *Lp = M + 110;     // Cholesky factor of the pivot block of e, 5 x 5
+  double *zp = M + 135;     // Lp^{-1} rhs_e
+  const TcOp op = a.ops[i];
+  const int v = op.v, cs = op.c, ce = op.ce, ck = op.ck;
+  // 1) v: add condensed children except the live child (last entry), factor
+  //    the private rows, boundary rows [e; kcur] remain
+  const int av = a.tne[v], LDv = av + 5, pv = av - ce, nb = ce + ck;
+  double *Kv = a.fac + a.foff[v];
+  double *yv = Kv + LDv * LDv;
+  tc_add_children(a, J, a.tabs_off[v], a.tabs_off[v + 1] - 1, Kv, yv, LDv, ln);
+  team_sync();
+  tc_partial_cholesky(a, Kv, yv, LDv, op.nv, pv, ln);
+  for (int idx = ln; idx < nb * nb; idx += TEAM) {
+    const int r = idx / nb, s = idx % nb;
+    M[idx] = s <= r ? Kv[(pv + r) * LDv + pv + s] : Kv[(pv + s) * LDv + pv + r];
+  }
+  for (int r = ln; r < nb; r += TEAM) m[r] = yv[pv + r];
+  team_sync();
+  // 2) c: rows [absorbed (ac); e (ce)]; pivot P = K_c[e,e] + M[e,e]
+  const int ac = a.tne[cs], LDc = ac + 5;
+  double *Kc = a.fac + a.foff[cs];
+  double *yc = Kc + LDc * LDc;
+  double *rec = a.crec + op.rec;
+  double *Xo = rec + 25, *Xk = rec + 25 + 5 * ac, *zr = Xk + 25;
+  if (ln == 0) {
+    double P[25], r[5];
+    for (int p = 0; p < ce; ++p) {
+      for (int q = 0; q <= p; ++q) P[5 * p + q] = Kc[(ac + p) * LDc + ac + q] + M[p * nb + q];
+      r[p] = yc[ac + p] + m[p];
+    }
+    for (int p = 0; p < ce; ++p) {  // Cholesky, lower triangle
+      double d = P[5 * p + p];
+      for (int t = 0; t < p; ++t) d -= P[5 * p + t] * P[5 * p + t];
+      if (!(d > 0.0)) {
+        raise_flag(a.status, FLAG_SINGULAR, a.step);
+        d = 1.0;
       }
-      for (int i = ne - 1; i >= 0; --i) {
-        double v = t[i];
-        for (int l = i + 1; l < ne; ++l) v -= K[l * nr + i] * t[l];
-        t[i] = v / K[i * nr + i];
-      }
-      int r0 = 0;
-      for (int e = a.tabs_off[slot]; e < a.tabs_off[slot + 1]; ++e) {
-        const int k = a.tabs[e] >> 2;
-        const int c = J[k].type ? 5 : 3;
-        for (int i = 0; i < c; ++i) a.glam[5 * (int64_t)k + i] = t[r0 + i];
-        for (int i = c; i < 5; ++i) a.glam[5 * (int64_t)k + i] = 0.0;
-        r0 += c;
+      d = sqrt(d);
+      P[5 * p + p] = d;
+      for (int q = p + 1; q < ce; ++q) {
+        double s = P[5 * q + p];
+        for (int t = 0; t < p; ++t) s -= P[5 * q + t] * P[5 * p + t];
+        P[5 * q + p] = s / d;
       }
     }
-    __syncthreads();
+    for (int p = 0; p < ce; ++p) {  // z = Lp^{-1} rhs_e
+      double s = r[p];
+      for (int t = 0; t < p; ++t) s -= P[5 * p + t] * zp[t];
+      zp[p] = s / P[5 * p + p];
+    }
+    for (int q = 0; q < 25; ++q) Lp[q] = (q / 5 < ce && q % 5 <= q / 5) ? P[q] : 0.0;
   }
+  team_sync();
+  // X_o = Lp^{-1} K_c[e, o] (ce x ac), X_k = Lp^{-1} M[e, k] (ce x ck)
+  for (int col = ln; col < ac + ck; col += TEAM) {
+    double x[5];
+    for (int p = 0; p < ce; ++p) {
+      double s = col < ac ? Kc[(ac + p) * LDc + col] : M[(ce + col - ac) * nb + p];
+      for (int t = 0; t < p; ++t) s -= Lp[5 * p + t] * x[t];
+      x[p] = s / Lp[5 * p + p];
+    }
+    for (int p = 0; p < ce; ++p) {
+      if (col < ac) Xo[p * ac + col] = x[p];
+      else Xk[p * 5 + (col - ac)] = x[p];
+    }
+  }
+  team_sync();
+  // K_c[o, o] -= X_o^T X_o ; rows of kcur replace the rows of e
+  for (int idx = ln; idx < ac * ac; idx += TEAM) {
+    const int r = idx / ac, s = idx % ac;
+    if (s > r) continue;
+    double t = 0.0;
+    for (int p = 0; p < ce; ++p) t += Xo[p * ac + r] * Xo[p * ac + s];
+    Kc[r * LDc + s] -= t;
+  }
+  for (int r = ln; r < ac; r += TEAM) {
+    double t = 0.0;
+    for (int p = 0; p < ce; ++p) t += Xo[p * ac + r] * zp[p];
+    yc[r] -= t;
+  }
+  for (int idx = ln; idx < ck * (ac + ck); idx += TEAM) {
+    const int r = idx / (ac + ck), s = idx % (ac + ck);
+    double t = 0.0;
+    if (s < ac) {
+      for (int p = 0; p < ce; ++p) t -= Xk[p * 5 + r] * Xo[p * ac + s];
+      Kc[(ac + r) * LDc + s] = t;
+    } else if (s - ac <= r) {
+      const int q = s - ac;
+      t = M[(ce + r) * nb + ce + q];
+      for (int p = 0; p < ce; ++p) t -= Xk[p * 5 + r] * Xk[p * 5 + q];
+      Kc[(ac + r) * LDc + ac + q] = t;
+    }
+  }
+  for (int r = ln; r < ck; r += TEAM) {
+    double t = m[ce + r];
+    for (int p = 0; p < ce; ++p) t -= Xk[p * 5 + r] * zp[p];
+    yc[ac + r] = t;
+  }
+  for (int q = ln; q < 25; q += TEAM) rec[q] = Lp[q];
+  for (int p = ln; p < 5; p += TEAM) zr[p] = p < ce ? zp[p] : 0.0;
+}
+
+// lambda of v's private rows: Lc^{-T} (z - X lambda_b), with lambda_b the
+// multipliers of the boundary rows (nb values), and their write-out
+DEV void tc_private_back(const TreeArgs &a, const GJoint *J, int v, int np, int nr, const double *lb,
+                         int e_end) {
+  const int LD = a.tne[v] + 5;
+  const double *K = a.fac + a.foff[v];
+  const double *y = K + LD * LD;
+  const int nb = nr - np;
+  double t[TREE_KMAX];
+  for (int i = 0; i < np; ++i) {
+    double s = y[i];
+    for (int f = 0; f < nb; ++f) s -= K[(np + f) * LD + i] * lb[f];
+    t[i] = s;
+  }
+  for (int i = np - 1; i >= 0; --i) {
+    double s = t[i];
+    for (int l = i + 1; l < np; ++l) s -= K[l * LD + i] * t[l];
+    t[i] = s / K[i * LD + i];
+  }
+  int r0 = 0;
+  for (int e = a.tabs_off[v]; e < e_end; ++e) {
+    const int k = a.tabs[e] >> 2;
+    const int c = J[k].type ? 5 : 3;
+    for (int i = 0; i < c; ++i) a.glam[5 * (int64_t)k + i] = t[r0 + i];
+    for (int i = c; i < 5; ++i) a.glam[5 * (int64_t)k + i] = 0.0;
+    r0 += c;
+  }
+}
+
+__global__ __launch_bounds__(256) void tc_rake_back_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
+  if (skip_step(a.status, a.step)) return;
+  const int i = op0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= op1) return;
+  const TcOp op = a.ops[i];
+  double lb[5] = {0, 0, 0, 0, 0};
+  for (int r = 0; r < op.ck; ++r) lb[r] = a.glam[5 * (int64_t)op.kcur + r];
+  tc_private_back(a, J, op.v, a.tne[op.v], op.nv, lb, a.tabs_off[op.v + 1]);
+}
+
+__global__ __launch_bounds__(256) void tc_compress_back_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
+  if (skip_step(a.status, a.step)) return;
+  const int i = op0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= op1) return;
+  const TcOp op = a.ops[i];
+  const int ce = op.ce, ck = op.ck, cs = op.c;
+  const int ac = a.tne[cs];
+  const double *rec = a.crec + op.rec;
+  const double *Lp = rec, *Xo = rec + 25, *Xk = rec + 25 + 5 * ac, *zr = Xk + 25;
+  // lambda of c's absorbed joints (solved later in the forward order) and of kcur
+  double lo[TREE_KMAX], lk[5] = {0, 0, 0, 0, 0};
+  {
+    int r0 = 0;
+    for (int e = a.tabs_off[cs]; e < a.tabs_off[cs + 1]; ++e) {
+      const int k = a.tabs[e] >> 2;
+      const int c = J[k].type ? 5 : 3;
+      for (int r = 0; r < c; ++r) lo[r0 + r] = a.glam[5 * (int64_t)k + r];
+      r0 += c;
+    }
+  }
+  for (int r = 0; r < ck; ++r) lk[r] = a.glam[5 * (int64_t)op.kcur + r];
+  // lambda_e = Lp^{-T} (z - X_o lambda_o - X_k lambda_k)
+  double le[5];
+  for (int p = 0; p < ce; ++p) {
+    double s = zr[p];
+    for (int q = 0; q < ac; ++q) s -= Xo[p * ac + q] * lo[q];
+    for (int q = 0; q < ck; ++q) s -= Xk[p * 5 + q] * lk[q];
+    le[p] = s;
+  }
+  for (int p = ce - 1; p >= 0; --p) {
+    double s = le[p];
+    for (int q = p + 1; q < ce; ++q) s -= Lp[5 * q + p] * le[q];
+    le[p] = s / Lp[5 * p + p];
+  }
+  for (int r = 0; r < 5; ++r) a.glam[5 * (int64_t)op.e + r] = r < ce ? le[r] : 0.0;
+  // v's private rows, boundary [e; kcur]
+  double lb[10];
+  for (int r = 0; r < ce; ++r) lb[r] = le[r];
+  for (int r = 0; r < ck; ++r) lb[ce + r] = lk[r];
+  tc_private_back(a, J, op.v, a.tne[op.v] - ce, op.nv, lb, a.tabs_off[op.v + 1] - 1);
 }
 
 // ------------------------------------------------------ (d) back-projection
@@ -557,12 +693,25 @@ void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, in
   if (m > 0)
     hipLaunchKernelGGL(gjoint_kernel, dim3((m + 127) / 128), dim3(128), 0, s, m, J, q, Rg, ns, hg, gl);
 }
-void launch_tree(const TreeArgs &a, const GJoint *J, int ncomp, int nslots, hipStream_t s) {
-  if (ncomp > 0) {
-    hipLaunchKernelGGL(tree_prep_kernel, dim3((nslots + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
-                       nslots);
-    hipLaunchKernelGGL(tree_forward_kernel, dim3(ncomp), dim3(TREE_BLOCK), 0, s, a, J);
-    hipLaunchKernelGGL(tree_backward_kernel, dim3(ncomp), dim3(256), 0, s, a, J);
+void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
+                 hipStream_t s) {
+  if (nslots <= 0) return;
+  hipLaunchKernelGGL(tree_prep_kernel, dim3((nslots + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J, nslots);
+  // rounds[2r] .. rounds[2r+1]: rakes of round r; rounds[2r+1] .. rounds[2r+2]: compresses
+  for (int r = 0; r < nround; ++r) {
+    const int r0 = rounds[2 * r], r1 = rounds[2 * r + 1], r2 = rounds[2 * r + 2];
+    if (r1 > r0)
+      hipLaunchKernelGGL(tc_rake_kernel, dim3((r1 - r0 + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J, r0, r1);
+    if (r2 > r1)
+      hipLaunchKernelGGL(tc_compress_kernel, dim3((r2 - r1 + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
+                         r1, r2);
+  }
+  for (int r = nround - 1; r >= 0; --r) {
+    const int r0 = rounds[2 * r], r1 = rounds[2 * r + 1], r2 = rounds[2 * r + 2];
+    if (r2 > r1)
+      hipLaunchKernelGGL(tc_compress_back_kernel, dim3((r2 - r1 + 255) / 256), dim3(256), 0, s, a, J, r1, r2);
+    if (r1 > r0)
+      hipLaunchKernelGGL(tc_rake_back_kernel, dim3((r1 - r0 + 255) / 256), dim3(256), 0, s, a, J, r0, r1);
   }
 }
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,

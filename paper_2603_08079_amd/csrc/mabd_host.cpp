@@ -41,7 +41,8 @@ void launch_gbody(int b0, int b1, const double *q, const double *qn, const doubl
                   double h, double *Rg, double *ug, uint32_t *status, int step, hipStream_t s);
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
                    double *gl, hipStream_t s);
-void launch_tree(const TreeArgs &a, const GJoint *J, int ncomp, int nslots, hipStream_t s);
+void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
+                 hipStream_t s);
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
@@ -163,6 +164,12 @@ struct mabd_ctx {
   std::vector<int32_t> comp_lvl, lvl_off, tbody, tpk, tabs_off, tabs, inc_off, inc, tne;
   std::vector<int64_t> foff;
   int64_t fac_size = 0;
+  // tree contraction schedule
+  std::vector<TcOp> tc_ops;
+  std::vector<int32_t> tc_rounds;  // 2 * rounds + 1 offsets into tc_ops
+  int64_t crec_size = 0;
+  TcOp *d_tc_ops = nullptr;
+  double *d_crec = nullptr;
   int32_t *d_tne = nullptr;
   int64_t *d_foff = nullptr;
   double *d_fac = nullptr;
@@ -714,6 +721,101 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     c->ntree++;
   }
   c->tabs_off.push_back((int)c->tabs.size());
+  // ---- tree contraction schedule: rounds of rakes (slots with no live
+  // child) and compresses (slots with exactly one live child, an independent
+  // set chosen top-down), until every slot is eliminated
+  {
+    const int nsl = (int)c->tbody.size();
+    std::vector<int> slot_of(c->sol2in.size(), -1);
+    for (int s = 0; s < nsl; ++s) slot_of[c->tbody[s]] = s;
+    std::vector<int> par(nsl, -1), kcur(nsl, -1), ckcur(nsl, 0), depth(nsl, 0);
+    std::vector<std::vector<int>> kids(nsl);
+    for (int s = 0; s < nsl; ++s) {
+      const int pk = c->tpk[s];
+      if (pk < 0) continue;
+      const int kin = c->gj_in[pk >> 1];
+      const int me = c->sol2in[c->tbody[s]];
+      const int other = Jn->a[kin] == me ? Jn->b[kin] : Jn->a[kin];
+      par[s] = slot_of[c->in2sol[other]];
+      kcur[s] = pk >> 1;
+      ckcur[s] = Jn->type[kin] ? 5 : 3;
+      kids[par[s]].push_back(s);
+    }
+    // slots are stored leaves first (by height): parents come after children
+    for (int s = nsl - 1; s >= 0; --s)
+      if (par[s] >= 0) depth[s] = depth[par[s]] + 1;
+    std::vector<int> topdown(nsl);
+    for (int s = 0; s < nsl; ++s) topdown[s] = s;
+    std::stable_sort(topdown.begin(), topdown.end(), [&](int x, int y) { return depth[x] < depth[y]; });
+    std::vector<int> nalive(nsl), alive(nsl, 1), sel(nsl, 0), live_child(nsl, -1);
+    for (int s = 0; s < nsl; ++s) nalive[s] = (int)kids[s].size();
+    int remaining = nsl;
+    std::vector<int> chosen;
+    while (remaining > 0) {
+      c->tc_rounds.push_back((int)c->tc_ops.size());
+      for (int s : topdown) {
+        if (!alive[s] || nalive[s] != 0) continue;
+        TcOp op{};
+        op.v = s; op.c = -1; op.kcur = kcur[s]; op.ck = ckcur[s]; op.e = -1; op.ce = 0;
+        op.nv = c->tne[s] + ckcur[s];
+        c->tc_ops.push_back(op);
+      }
+      for (int i = c->tc_rounds.back(); i < (int)c->tc_ops.size(); ++i) {
+        const int s = c->tc_ops[i].v;
+        alive[s] = 0;
+        --remaining;
+        if (par[s] >= 0) --nalive[par[s]];
+      }
+      c->tc_rounds.push_back((int)c->tc_ops.size());
+      chosen.clear();
+      for (int s : topdown) {
+        if (!alive[s] || par[s] < 0 || nalive[s] != 1 || sel[par[s]]) continue;
+        int cs = -1;
+        for (int k2 : kids[s])
+          if (alive[k2]) cs = k2;
+        sel[s] = 1;
+        chosen.push_back(s);
+        live_child[s] = cs;
+      }
+      for (int s : chosen) {
+        const int cs = live_child[s];
+        TcOp op{};
+        op.v = s; op.c = cs; op.kcur = kcur[s]; op.ck = ckcur[s]; op.e = kcur[cs]; op.ce = ckcur[cs];
+        op.nv = c->tne[s] + ckcur[s];
+        op.rec = c->crec_size;
+        c->crec_size += 55 + 5 * (int64_t)c->tne[cs];
+        c->tc_ops.push_back(op);
+        // the live child's joint goes last in v's absorbed list
+        int e0 = c->tabs_off[s], e1 = c->tabs_off[s + 1];
+        for (int e = e0; e < e1; ++e)
+          if ((c->tabs[e] >> 2) == op.e && !(c->tabs[e] & 1)) {
+            std::swap(c->tabs[e], c->tabs[e1 - 1]);
+            break;
+          }
+        // merge: c takes v's parent and parent joint
+        par[cs] = par[s];
+        kcur[cs] = kcur[s];
+        ckcur[cs] = ckcur[s];
+        for (int &k2 : kids[par[s]])
+          if (k2 == s) k2 = cs;
+        alive[s] = 0;
+        sel[s] = 0;
+        --remaining;
+      }
+    }
+    c->tc_rounds.push_back((int)c->tc_ops.size());
+    // factor slots: K and y with leading dimension absorbed rows + 5, plus
+    // the pre-pass scratch of large cliques
+    c->foff.clear();
+    c->fac_size = 0;
+    for (int s = 0; s < nsl; ++s) {
+      const int LD = c->tne[s] + 5;
+      const int pk = c->tpk[s];
+      const int nr0 = c->tne[s] + (pk >= 0 ? (Jn->type[c->gj_in[pk >> 1]] ? 5 : 3) : 0);
+      c->foff.push_back(c->fac_size);
+      c->fac_size += (int64_t)LD * LD + LD + (nr0 > TREE_KLDS ? 24 * (int64_t)nr0 : 0);
+    }
+  }
   // graph components: bodies after the trees, solved by PCG
   std::vector<int32_t> graph_bodies;
   std::vector<char> gseen(n, 0);
@@ -929,6 +1031,8 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(upload(c, &c->d_tne, c->tne));
   if (e == hipSuccess) chk(upload(c, &c->d_foff, c->foff));
   if (e == hipSuccess) chk(dalloc(c, &c->d_fac, (size_t)std::max<int64_t>(c->fac_size, 1)));
+  if (e == hipSuccess) chk(upload(c, &c->d_tc_ops, c->tc_ops));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_crec, (size_t)std::max<int64_t>(c->crec_size, 1)));
   if (e == hipSuccess) chk(upload(c, &c->d_inc_off, c->inc_off));
   if (e == hipSuccess) chk(upload(c, &c->d_inc, c->inc));
   if (e == hipSuccess) chk(upload(c, &c->d_sol2in, c->sol2in));
@@ -1041,6 +1145,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   c->stats.n_graph = c->ngraph;
   c->stats.n_dyn = c->nd;
   c->stats.tile_threads = c->tile_threads;
+  c->stats.tree_rounds = ((int)c->tc_rounds.size() - 1) / 2;
   c->stats.rho_p = c->stats.rho_d = c->stats.kkt = -1.0;
   *out = c;
   return MABD_OK;
@@ -1358,7 +1463,12 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       ta.tne = c->d_tne;
       ta.foff = c->d_foff;
       ta.fac = c->d_fac;
-      tm.run(5, [&] { launch_tree(ta, c->d_gj, c->ntree, (int)c->tbody.size(), s); });
+      ta.ops = c->d_tc_ops;
+      ta.crec = c->d_crec;
+      tm.run(5, [&] {
+        launch_tree(ta, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
+                    ((int)c->tc_rounds.size() - 1) / 2, s);
+      });
       if (c->ngraph > 0) {
         PcgArgs pa{};
         pa.nb = c->gb1 - c->gb0;
