@@ -203,14 +203,6 @@ __global__ void gjoint_kernel(int m, const GJoint *J, const double *q, const dou
 constexpr int TEAMS = 16;
 constexpr int TREE_BLOCK = TEAMS * TEAM;
 
-struct TeamLds {
-  double L[TREE_KLDS * 12];
-  double Y[12 * TREE_KLDS];
-  double K[TREE_KLDS * TREE_KLDS];
-  double y[TREE_KLDS];
-  int32_t rowk[TREE_KLDS];   // joint of each clique row
-  int32_t rowi[TREE_KLDS];   // row index inside that joint
-};
 
 DEV void team_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -223,10 +215,15 @@ DEV void team_sync() {
 // other body, so all bodies of all components run in one parallel pre-pass;
 // the level-ordered elimination then only adds the children's Sigma, rho and
 // factors.
+struct PrepLds {
+  double L[TREE_KLDS * 12];
+  double Y[12 * TREE_KLDS];
+};
+
 __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const GJoint *J, int nslots) {
-  __shared__ TeamLds team_lds[TEAMS];
+  __shared__ PrepLds team_lds[TEAMS];
   const int tm = threadIdx.x / TEAM, ln = threadIdx.x % TEAM;
-  TeamLds &S = team_lds[tm];
+  PrepLds &S = team_lds[tm];
   if (skip_step(a.status, a.step)) return;
   const int slot = blockIdx.x * TEAMS + tm;
   if (slot >= nslots) return;  // whole teams only: team_sync is wave-local
@@ -272,11 +269,14 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   }
   team_sync();
   // 3) K0 = L Y (lower triangle), y0 = L u + C of one-sided and parent rows
-  for (int idx = ln; idx < nr * nr; idx += TEAM) {
-    const int i = idx / nr, jj = idx % nr;
+  for (int idx = ln; idx < nr * (nr + 1) / 2; idx += TEAM) {
+    // lower-triangle entry idx -> (i, jj), jj <= i (only the lower triangle is ever read)
+    int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > idx) --i;
+    while ((i + 1) * (i + 2) / 2 <= idx) ++i;
+    const int jj = idx - i * (i + 1) / 2;
     double v = 0.0;
-    if (jj <= i)
-      for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * Ym[s * nr + jj];
+    for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * Ym[s * nr + jj];
     fac[i * LD + jj] = v;
   }
   for (int i = ln; i < nr; i += TEAM) {
