@@ -21,6 +21,9 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-variable", "-Wno-unused-function",
+    # extra defines, e.g. -DMABD_TILE_WAVES_REDUCE=3 (minimum waves per SIMD
+    # the chain tile kernels are compiled for)
+    *os.environ.get("MABD_HIPCC_DEFINES", "").split(),
 ]
 
 

@@ -180,7 +180,14 @@ inline unsigned xcd_grid(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8);
 // current iterate and the increment is added to dq and lam; skipped once the
 // residual check has converged.
 template <int MODE, bool APPLY, int NT>
-__global__ __launch_bounds__(NT) void chain_tile_kernel(ChainArgs a) {
+#ifndef MABD_TILE_WAVES_REDUCE
+#define MABD_TILE_WAVES_REDUCE 2
+#endif
+#ifndef MABD_TILE_WAVES_APPLY
+#define MABD_TILE_WAVES_APPLY 2
+#endif
+__global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES_REDUCE) void chain_tile_kernel(
+    ChainArgs a) {
   using breal = typename std::conditional<MODE == 0, double, float>::type;
   __shared__ double lds[S_N * NT];
   if (skip_step(a.status, a.step)) return;
