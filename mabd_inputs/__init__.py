@@ -145,11 +145,11 @@ def chain(n: int, seed: int = 0, sigma: float = 1e-3, hinge_frac: float = 0.0,
 def tree(n: int, seed: int = 0, window: int = 64, sigma: float = 1e-3,
          hinge_frac: float = 0.5, dim_range=(0.05, 0.5), density: float = 1000.0,
          k_orth: float = 1e8, h: float = 1e-2, steps: int = 100,
-         origin=(0.0, 0.0, 0.0)) -> Assembly:
-    """Random tree: parent of body i > 0 uniform over [max(0, i - window), i - 1];
-    A = I; the child's -x end centre meets the parent's +x end centre; body 0
-    pinned; joint type Bernoulli(hinge_frac) hinge, else ball; hinge axes
-    uniform on the sphere."""
+         origin=(0.0, 0.0, 0.0), parents=None) -> Assembly:
+    """Random tree: parent of body i > 0 uniform over [max(0, i - window), i - 1]
+    (or the given `parents` array, parents[i] < i); A = I; the child's -x end
+    centre meets the parent's +x end centre; body 0 pinned; joint type
+    Bernoulli(hinge_frac) hinge, else ball; hinge axes uniform on the sphere."""
     rng = np.random.default_rng(seed)
     dims = rng.uniform(dim_range[0], dim_range[1], size=(n, 3))
     parent = np.full(n, -1, np.int64)
@@ -158,6 +158,9 @@ def tree(n: int, seed: int = 0, window: int = 64, sigma: float = 1e-3,
         span = np.arange(1, n) - lo
         parent[1:] = lo + np.floor(rng.random(n - 1) * span).astype(np.int64)
         parent[1:] = np.minimum(parent[1:], np.arange(1, n) - 1)
+        if parents is not None:
+            parent[1:] = np.asarray(parents, np.int64)[1:]
+            assert np.all(parent[1:] < np.arange(1, n)) and np.all(parent[1:] >= 0)
     centres = np.zeros((n, 3))
     centres[0] = origin
     for i in range(1, n):

@@ -174,6 +174,38 @@ def test_tree_and_hinge_paths():
     say("worst", teacher_forced(w, 2, hinge_grad=2, tol_v=TOL_V_TREE))
 
 
+def test_deep_hinge_chain_contraction():
+    """3,000 hinge-jointed links: a path of 5-row blocks, eliminated almost
+    entirely by compress rounds of the tree contraction."""
+    asm = mi.chain(3000, seed=41, hinge_frac=1.0)
+    asm.qd0[1:] = np.random.default_rng(41).normal(0, 0.05, (asm.n - 1, 12))
+    say("all-hinge chain 3000")
+    say("worst", teacher_forced(asm, 2, tol_v=TOL_V_TREE))
+
+
+def test_wide_tree_contraction():
+    """8-ary tree: every interior body absorbs 8 child joints (cliques of up
+    to 45 rows), so rakes dominate and the large-clique storage is used."""
+    n = 600
+    parents = np.array([0] + [(i - 1) // 8 for i in range(1, n)])
+    asm = mi.tree(n, seed=42, parents=parents)
+    asm.qd0[1:] = np.random.default_rng(42).normal(0, 0.05, (n - 1, 12))
+    say("8-ary tree", n)
+    say("worst", teacher_forced(asm, 2, tol_v=TOL_V_TREE))
+
+
+def test_many_tree_components():
+    """Trees and hinge chains of different depths in one context: their
+    contraction rounds run in the same launches."""
+    parts = [mi.tree(700, seed=43), mi.chain(400, seed=44, hinge_frac=0.5, origin=(0.0, 15.0, 0.0)),
+             mi.tree(40, seed=45, window=2, origin=(0.0, 30.0, 0.0)),
+             mi.chain(5, seed=46, hinge_frac=1.0, origin=(0.0, 45.0, 0.0)),
+             mi.tree(1500, seed=47, window=4, origin=(0.0, 60.0, 0.0))]
+    asm = mi.concat(parts, h=1e-2, steps=2)
+    say("mixed trees", asm.n)
+    say("worst", teacher_forced(asm, 2, tol_v=TOL_V_TREE))
+
+
 def test_tree_with_world_joints_and_lame():
     t = mi.tree(120, seed=8, window=8)
     t.jtype = np.append(t.jtype, [0, 1]).astype(np.uint8)
