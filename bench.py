@@ -193,14 +193,15 @@ def main():
     if not args.no_kkt_check:
         # one more GPU step from the current (moving) state, verified by the
         # oracle's FP64 back-projection of the GPU multipliers
-        ctx.step(h, 1)
+        kkt_notconv = run(ctx, 1)
         lam = ctx.multipliers()
         q1, qd1 = ctx.state()
         qo, qdo, diag = s.finish(h, q_n, qd_n, lam)
         kkt = {"rho_p": float(diag[oracle.RHO_P]), "rho_d": float(diag[oracle.RHO_D]),
                "kkt": float(diag[oracle.KKT]),
                "state_rel_err": float(np.abs(q1 - qo).max() / max(1.0, np.abs(qo).max())),
-               "vel_rel_err": float(np.abs(qd1 - qdo).max() / max(1e-300, np.abs(qdo).max()))}
+               "vel_rel_err": float(np.abs(qd1 - qdo).max() / max(1e-300, np.abs(qdo).max())),
+               "pcg_not_converged": kkt_notconv}
     if not args.no_cpu_baseline:
         # the oracle's own step from the same state: CPU baseline, and the KKT
         # residual its direct FP64 solve reaches there
