@@ -104,27 +104,58 @@ DEV void cof3(const real *A, real *C) {
   C[8] = A[0] * A[4] - A[1] * A[3];
 }
 
-// Polar factor R = A (A^T A)^{-1/2} (Eq. polar) by Newton's iteration
-// X <- (zeta X + X^{-T} / zeta) / 2 with determinant scaling while far from
-// convergence (Higham, Functions of Matrices, Sec. 8.3).  A near-rotation
-// converges in two or three iterations.  Returns false if det A <= 0 or the
-// input is not finite.  In FP32 the iteration stops once a step is below
-// 1e-5 (the next error is then below FP32 rounding).
+// Polar factor R = A (A^T A)^{-1/2} (Eq. polar).  A stiff body keeps A close
+// to a rotation, and there the Newton-Schulz iteration X <- X (3I - X^T X)/2
+// converges quadratically using only products (about 65 flops a step, no
+// division): with E = X^T X - I each step maps |E| to about 1.5 |E|^2, so
+// once |E|_F < 1e-8 (FP64; 1e-5 in FP32) the step just taken leaves an error
+// below rounding and the iterate is final.  Farther from orthogonality
+// (|E|_F >= 0.5, where Newton-Schulz may not converge) Newton's iteration
+// X <- (zeta X + X^{-T} / zeta) / 2 with determinant scaling takes over
+// (Higham, Functions of Matrices, Sec. 8.3).  Returns false if det A <= 0 or
+// the input is not finite.
 template <typename real>
 DEV bool polar3(const real *A, real *R) {
-  const real stop = sizeof(real) == 8 ? real(1e-16) : real(1e-10);
+  const real ns_stop = sizeof(real) == 8 ? real(1e-16) : real(1e-10);
   real X[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) X[i] = A[i];
   real d0 = det3(X);
-  if (!(d0 > 0.0) || !isfinite(d0)) return false;
+  if (!(d0 > real(0)) || !isfinite(d0)) return false;
   bool done = false;
+  for (int it = 0; it < 8 && !done; ++it) {
+    // E = X^T X - I (symmetric)
+    real E[6];
+    E[0] = X[0] * X[0] + X[3] * X[3] + X[6] * X[6] - real(1);
+    E[1] = X[0] * X[1] + X[3] * X[4] + X[6] * X[7];
+    E[2] = X[0] * X[2] + X[3] * X[5] + X[6] * X[8];
+    E[3] = X[1] * X[1] + X[4] * X[4] + X[7] * X[7] - real(1);
+    E[4] = X[1] * X[2] + X[4] * X[5] + X[7] * X[8];
+    E[5] = X[2] * X[2] + X[5] * X[5] + X[8] * X[8] - real(1);
+    const real e2 = E[0] * E[0] + E[3] * E[3] + E[5] * E[5] +
+                    real(2) * (E[1] * E[1] + E[2] * E[2] + E[4] * E[4]);
+    if (!(e2 < real(0.25))) break;  // far from orthogonal: Newton below
+    // X <- X (I - E / 2)
+    const real N[9] = {real(1) - real(0.5) * E[0], -real(0.5) * E[1], -real(0.5) * E[2],
+                       -real(0.5) * E[1], real(1) - real(0.5) * E[3], -real(0.5) * E[4],
+                       -real(0.5) * E[2], -real(0.5) * E[4], real(1) - real(0.5) * E[5]};
+    real Y[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        Y[3 * r + c] = X[3 * r] * N[c] + X[3 * r + 1] * N[3 + c] + X[3 * r + 2] * N[6 + c];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) X[i] = Y[i];
+    if (e2 < ns_stop) done = true;
+  }
+  const real stop = sizeof(real) == 8 ? real(1e-16) : real(1e-10);
   for (int it = 0; it < 40 && !done; ++it) {
     real C[9];
     cof3(X, C);
     real det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
     if (!(det > real(0))) return false;
-    real z = real(1);
+    real z = real(1), iz = real(1);
     real diff = real(0);
     // X^{-T} = C / det
     real inv = real(1) / det;
@@ -135,10 +166,13 @@ DEV bool polar3(const real *A, real *R) {
     real s0 = real(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) s0 += (X[i] - Y[i]) * (X[i] - Y[i]);
-    if (s0 > real(1e-4)) z = real(1) / cbrt(det);
+    if (s0 > real(1e-4)) {
+      z = real(1) / cbrt(det);
+      iz = cbrt(det);
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      real xn = real(0.5) * (z * X[i] + Y[i] / z);
+      real xn = real(0.5) * (z * X[i] + Y[i] * iz);
       diff += (xn - X[i]) * (xn - X[i]);
       X[i] = xn;
     }

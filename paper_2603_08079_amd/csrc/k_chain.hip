@@ -42,17 +42,27 @@ DEV void full_from_sym(const double *S6, double *F) {
   F[6] = S6[2]; F[7] = S6[4]; F[8] = S6[5];
 }
 
-// LDS layout (doubles): 24 arrays of CHAIN_THREADS entries
-enum { S_WBB = 0, S_VB = 6, S_CB = 9, S_TB = 12, S_WAB = 15, S_N = 24 };
-// reuse for cyclic reduction: PL (9) PU (9) Pb (3) ; back-substitution: x (3)
-enum { S_PL = 0, S_PU = 9, S_PB = 18, S_X = 21 };
+// LDS layout (doubles): S_N arrays of CHAIN_THREADS entries
+enum { S_WBB = 0, S_VB = 6, S_CB = 9, S_TB = 12, S_WAB = 15, S_N = 27 };
+// cyclic reduction: what an eliminated row hands to its left neighbour
+// (dD 6, db 3, new coupling 9) and to its right one (dD 6, db 3);
+// back-substitution: x (3).  S_PL / S_PU / S_PB name the same slots for the
+// two-row exchange of the top solve.
+enum { S_DL = 0, S_BL = 6, S_UN = 9, S_DR = 18, S_BR = 24, S_X = 21 };
+enum { S_PL = 0, S_PU = 9, S_PB = 18 };
 
 // Block cyclic reduction of the rows 1..T-1 of a tile onto its interface
 // rows 0 and T.  Row li (held by one thread, `row_active`) couples to its
-// current left neighbour through L and to its right one through U.  At level
-// d the rows li = d mod 2d are eliminated: each publishes
-// (PL, PU, Pb) = D^{-1} (L, U, b) through LDS and keeps it for the
-// back-substitution; every surviving row folds in its eliminated neighbours.
+// current left neighbour through L and to its right one through U; the
+// system is symmetric, so a row's L is the transpose of its left
+// neighbour's U.  At level d the rows li = d mod 2d are eliminated.  Each
+// keeps (PL, PU, Pb) = D^{-1} (L, U, b) for the back-substitution and, since
+// the left neighbour's coupling to it is L^T and the right one's is U^T,
+// computes every Schur update itself:
+//   left:  D -= L^T PL,  b -= L^T Pb,  U <- -L^T PU
+//   right: D -= U^T PU,  b -= U^T Pb,  L <- (-L^T PU)^T
+// The surviving rows then only add what their eliminated neighbours
+// published, so the costly branch runs on one set of lanes per level.
 template <int NT>
 DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, double *L, double *D,
                          double *U, double *b, double *PL, double *PU, double *Pb, int &elim_d,
@@ -72,63 +82,54 @@ DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, double *L,
       mat3_mul(Di, U, PU);
       mat3_vec(Di, b, Pb);
       elim_d = d;
+      double M[9], v[3];
+      // left neighbour
+      mat3_mul_at(L, PL, M);
+      lds[(S_DL + 0) * NT + li] = M[0];
+      lds[(S_DL + 1) * NT + li] = 0.5 * (M[1] + M[3]);
+      lds[(S_DL + 2) * NT + li] = 0.5 * (M[2] + M[6]);
+      lds[(S_DL + 3) * NT + li] = M[4];
+      lds[(S_DL + 4) * NT + li] = 0.5 * (M[5] + M[7]);
+      lds[(S_DL + 5) * NT + li] = M[8];
+      mat3t_vec(L, Pb, v);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        lds[(S_PL + i) * NT + li] = PL[i];
-        lds[(S_PU + i) * NT + li] = PU[i];
-      }
+      for (int i = 0; i < 3; ++i) lds[(S_BL + i) * NT + li] = v[i];
+      mat3_mul_at(L, PU, M);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) lds[(S_PB + i) * NT + li] = Pb[i];
+      for (int i = 0; i < 9; ++i) lds[(S_UN + i) * NT + li] = -M[i];
+      // right neighbour
+      mat3_mul_at(U, PU, M);
+      lds[(S_DR + 0) * NT + li] = M[0];
+      lds[(S_DR + 1) * NT + li] = 0.5 * (M[1] + M[3]);
+      lds[(S_DR + 2) * NT + li] = 0.5 * (M[2] + M[6]);
+      lds[(S_DR + 3) * NT + li] = M[4];
+      lds[(S_DR + 4) * NT + li] = 0.5 * (M[5] + M[7]);
+      lds[(S_DR + 5) * NT + li] = M[8];
+      mat3t_vec(U, Pb, v);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) lds[(S_BR + i) * NT + li] = v[i];
     }
     __syncthreads();
     if (active && !elim) {
       const int e = li + d;
       if (li != T && e < T) {
-        double Xl[9], Xu[9], xb[3], M[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          Xl[i] = lds[(S_PL + i) * NT + e];
-          Xu[i] = lds[(S_PU + i) * NT + e];
-        }
+        for (int i = 0; i < 6; ++i) D[i] -= lds[(S_DL + i) * NT + e];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * NT + e];
-        mat3_mul(U, Xl, M);
-        double Ms[6];
-        sym_from_full(M, Ms);
+        for (int i = 0; i < 3; ++i) b[i] -= lds[(S_BL + i) * NT + e];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) D[i] -= Ms[i];
-        double Ub[3];
-        mat3_vec(U, xb, Ub);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) b[i] -= Ub[i];
-        double Un[9];
-        mat3_mul(U, Xu, Un);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) U[i] = -Un[i];
+        for (int i = 0; i < 9; ++i) U[i] = lds[(S_UN + i) * NT + e];
       }
       const int lf = li == T ? d * ((T - 1) / d) : li - d;
       if (li > 0 && lf > 0 && (lf % (2 * d) == d)) {
-        double Xl[9], Xu[9], xb[3], M[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          Xl[i] = lds[(S_PL + i) * NT + lf];
-          Xu[i] = lds[(S_PU + i) * NT + lf];
-        }
+        for (int i = 0; i < 6; ++i) D[i] -= lds[(S_DR + i) * NT + lf];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) xb[i] = lds[(S_PB + i) * NT + lf];
-        mat3_mul(L, Xu, M);
-        double Ms[6];
-        sym_from_full(M, Ms);
+        for (int i = 0; i < 3; ++i) b[i] -= lds[(S_BR + i) * NT + lf];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) D[i] -= Ms[i];
-        double Lb[3];
-        mat3_vec(L, xb, Lb);
+        for (int r2 = 0; r2 < 3; ++r2)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) b[i] -= Lb[i];
-        double Ln[9];
-        mat3_mul(L, Xl, Ln);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) L[i] = -Ln[i];
+          for (int c2 = 0; c2 < 3; ++c2) L[3 * r2 + c2] = lds[(S_UN + 3 * c2 + r2) * NT + lf];
       }
     }
     __syncthreads();
