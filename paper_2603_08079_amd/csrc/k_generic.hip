@@ -573,6 +573,455 @@ __global__ __launch_bounds__(256) void tc_compress_back_kernel(TreeArgs a, const
   tc_private_back(a, J, op.v, a.tne[op.v] - ce, op.nv, lb, a.tabs_off[op.v + 1] - 1);
 }
 
+// ------------------------------------------- wave-per-operation contraction
+// The rounds are bound by the latency of their slowest operations, not by
+// bandwidth: a clique's partial Cholesky is a chain of dependent steps.  So
+// each operation gets a whole wave (one 64-lane workgroup), its cliques are
+// staged in LDS (rows padded to R + 1 doubles), every copy issues all of its
+// loads before the first wait, and the rank-1 updates run column-parallel.
+// Two sizes: R = 16 (most operations) and R = 48 / 64; compresses with
+// larger cliques use the team kernels above on the global slots.
+constexpr int TCW = 64;
+
+template <int R>
+struct TcwMat {
+  double K[R * (R + 1)];
+  double y[R];
+};
+template <int R>
+struct TcwComp {
+  TcwMat<R> v, c;
+  double M[110];  // boundary Schur complement of v (nb x nb) and its rhs
+  double Lp[25];  // Cholesky factor of the pivot block of e
+  double zp[5];   // Lp^{-1} rhs_e
+  double Xo[5 * R];
+  double Xk[25];
+};
+
+DEV int lane() { return (int)threadIdx.x; }
+
+// lower triangle of rows [0, nr) of a global clique (leading dimension ls)
+// into LDS; loads are issued eight at a time before their stores
+template <int R>
+DEV void tcw_load_lower(const double *src, int ls, double *dst, int nr) {
+  constexpr int LD = R + 1;
+  const int n = nr * R;
+  for (int base = 0; base < n; base += 8 * TCW) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * TCW + lane();
+      const int i = idx / R, j = idx - (idx / R) * R;
+      v[u] = src[(idx < n && j <= i) ? i * ls + j : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * TCW + lane();
+      const int i = idx / R, j = idx - (idx / R) * R;
+      if (idx < n && j <= i) dst[i * LD + j] = v[u];
+    }
+  }
+}
+
+// LDS clique rows [0, nr), columns j <= i and j < ncol, back to global
+template <int R>
+DEV void tcw_store_lower(const double *src, double *dst, int ld, int nr, int ncol) {
+  constexpr int LD = R + 1;
+  for (int idx = lane(); idx < nr * R; idx += TCW) {
+    const int i = idx / R, j = idx - (idx / R) * R;
+    if (j <= i && j < ncol) dst[i * ld + j] = src[i * LD + j];
+  }
+}
+
+// Entries [e0, e1) of an absorbed list, one per lane: joint, rows, first
+// row in the clique, and whether the joint is one-sided (no condensed side).
+struct TcwEnt {
+  int k, c, r0, unary;
+};
+DEV TcwEnt tcw_entry(const TreeArgs &a, const GJoint *J, int e0, int e1) {
+  TcwEnt t{0, 0, 0, 1};
+  const int ln = lane();
+  if (ln < e1 - e0) {
+    const int tab = a.tabs[e0 + ln];
+    t.k = tab >> 2;
+    t.unary = tab & 1;
+    t.c = J[t.k].type ? 5 : 3;
+  }
+  int x = t.c;  // inclusive prefix over lanes
+  for (int o = 1; o < TCW; o <<= 1) {
+    const int u = __shfl_up(x, o);
+    if (ln >= o) x += u;
+  }
+  t.r0 = x - t.c;
+  return t;
+}
+
+// add the condensed far sides of the list's non-unary joints; each lane
+// adds its own entry's diagonal block (all loads in flight at once)
+template <int R>
+DEV void tcw_add_children(const TreeArgs &a, const GJoint *J, int e0, int e1, double *K, double *y) {
+  constexpr int LD = R + 1;
+  const TcwEnt t = tcw_entry(a, J, e0, e1);
+  if (lane() < e1 - e0 && !t.unary) {
+    const double *g = a.gt + (int64_t)GT_STRIDE * t.k;
+    double sg[25], rh[5];
+#pragma unroll
+    for (int q = 0; q < 25; ++q) sg[q] = g[GT_SIG + q];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) rh[q] = g[GT_RHO + q];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      if (r < t.c) {
+#pragma unroll
+        for (int s = 0; s <= r; ++s) K[(t.r0 + r) * LD + t.r0 + s] += sg[5 * r + s];
+        y[t.r0 + r] += rh[r];
+      }
+    }
+  }
+}
+
+// partial Cholesky of the first np of nr rows of an LDS clique (same
+// arithmetic as tc_partial_cholesky): lane i scales row p + 1 + i of the
+// pivot column, then updates column p + 1 + i of the trailing triangle
+template <int R>
+DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, int np) {
+  constexpr int LD = R + 1;
+  const int ln = lane();
+  for (int p = 0; p < np; ++p) {
+    double d = K[p * LD + p];
+    if (!(d > 0.0)) {
+      if (ln == 0) raise_flag(a.status, FLAG_SINGULAR, a.step);
+      d = 1.0;
+    }
+    d = sqrt(d);
+    const double yp = y[p] / d;
+    const int i = p + 1 + ln;
+    double lip = 0.0;
+    if (i < nr) lip = K[i * LD + p] / d;
+    __syncthreads();
+    if (ln == 0) {
+      K[p * LD + p] = d;
+      y[p] = yp;
+    }
+    if (i < nr) {
+      K[i * LD + p] = lip;
+      y[i] -= lip * yp;
+    }
+    __syncthreads();
+    if (i < nr) {  // column j = i, rows r >= j: K[r][j] -= l_rp l_jp
+      for (int r = i; r < nr; r += 8) {
+        double kv[8], lr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int rr = r + u < nr ? r + u : nr - 1;
+          kv[u] = K[rr * LD + i];
+          lr[u] = K[rr * LD + p];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (r + u < nr) K[(r + u) * LD + i] = kv[u] - lr[u] * lip;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(TCW) void tcw_rake_kernel(TreeArgs a, const GJoint *J, int op0) {
+  constexpr int LD = R + 1;
+  __shared__ TcwMat<R> sm;
+  if (skip_step(a.status, a.step)) return;
+  const int ln = lane();
+  const TcOp op = a.ops[op0 + blockIdx.x];
+  const int v = op.v;
+  const int ne = a.tne[v], LDg = ne + 5, nr = op.nv;
+  double *Kg = a.fac + a.foff[v];
+  double *yg = Kg + LDg * LDg;
+  tcw_load_lower<R>(Kg, LDg, sm.K, nr);
+  if (ln < nr) sm.y[ln] = yg[ln];
+  __syncthreads();
+  tcw_add_children<R>(a, J, a.tabs_off[v], a.tabs_off[v + 1], sm.K, sm.y);
+  __syncthreads();
+  tcw_partial_cholesky<R>(a, sm.K, sm.y, nr, ne);
+  if (op.kcur >= 0) {
+    double *gtk = a.gt + (int64_t)GT_STRIDE * op.kcur;
+    if (ln < 25) {
+      const int r = ln / 5, s = ln % 5;
+      double val = 0.0;
+      if (r < op.ck && s < op.ck) val = s <= r ? sm.K[(ne + r) * LD + ne + s] : sm.K[(ne + s) * LD + ne + r];
+      gtk[GT_SIG + ln] = val;
+    } else if (ln < 30) {
+      const int r = ln - 25;
+      gtk[GT_RHO + r] = r < op.ck ? sm.y[ne + r] : 0.0;
+    }
+  }
+  // factor columns and z of the private rows, for the back-substitution
+  tcw_store_lower<R>(sm.K, Kg, LDg, nr, ne);
+  if (ln < ne) yg[ln] = sm.y[ln];
+}
+
+template <int R>
+__global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJoint *J, int op0) {
+  constexpr int LD = R + 1;
+  __shared__ TcwComp<R> sm;
+  if (skip_step(a.status, a.step)) return;
+  const int ln = lane();
+  const TcOp op = a.ops[op0 + blockIdx.x];
+  const int v = op.v, cs = op.c, ce = op.ce, ck = op.ck;
+  const int av = a.tne[v], LDvg = av + 5, pv = av - ce, nb = ce + ck, nv = op.nv;
+  const int ac = a.tne[cs], LDcg = ac + 5;
+  double *Kvg = a.fac + a.foff[v];
+  double *yvg = Kvg + LDvg * LDvg;
+  double *Kcg = a.fac + a.foff[cs];
+  double *ycg = Kcg + LDcg * LDcg;
+  double *Kv = sm.v.K, *yv = sm.v.y, *Kc = sm.c.K, *yc = sm.c.y;
+  double *M = sm.M, *m = sm.M + 100;
+  // 1) v: condensed children except the live child (last entry), private
+  //    rows factored; boundary rows [e; kcur] remain
+  tcw_load_lower<R>(Kvg, LDvg, Kv, nv);
+  tcw_load_lower<R>(Kcg, LDcg, Kc, ac + ce);
+  if (ln < nv) yv[ln] = yvg[ln];
+  if (ln < ac + ce) yc[ln] = ycg[ln];
+  __syncthreads();
+  tcw_add_children<R>(a, J, a.tabs_off[v], a.tabs_off[v + 1] - 1, Kv, yv);
+  __syncthreads();
+  tcw_partial_cholesky<R>(a, Kv, yv, nv, pv);
+  for (int idx = ln; idx < nb * nb; idx += TCW) {
+    const int r = idx / nb, s = idx % nb;
+    M[idx] = s <= r ? Kv[(pv + r) * LD + pv + s] : Kv[(pv + s) * LD + pv + r];
+  }
+  if (ln < nb) m[ln] = yv[pv + ln];
+  tcw_store_lower<R>(Kv, Kvg, LDvg, nv, pv);
+  if (ln < pv) yvg[ln] = yv[ln];
+  __syncthreads();
+  // 2) c: rows [absorbed (ac); e (ce)]; pivot P = K_c[e,e] + M[e,e]
+  if (ln == 0) {  // ce <= 5: fixed trip counts keep P, r, z in registers
+    double P[25], r[5], z[5];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+        P[5 * p + q] = (p < ce && q <= p) ? Kc[(ac + p) * LD + ac + q] + M[p * nb + q] : 0.0;
+      r[p] = p < ce ? yc[ac + p] + m[p] : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {  // Cholesky, lower triangle
+      if (p < ce) {
+        double d = P[5 * p + p];
+#pragma unroll
+        for (int t = 0; t < p; ++t) d -= P[5 * p + t] * P[5 * p + t];
+        if (!(d > 0.0)) {
+          raise_flag(a.status, FLAG_SINGULAR, a.step);
+          d = 1.0;
+        }
+        d = sqrt(d);
+        P[5 * p + p] = d;
+#pragma unroll
+        for (int q = p + 1; q < 5; ++q) {
+          double s = P[5 * q + p];
+#pragma unroll
+          for (int t = 0; t < p; ++t) s -= P[5 * q + t] * P[5 * p + t];
+          P[5 * q + p] = s / d;
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {  // z = Lp^{-1} rhs_e
+      double s = r[p];
+#pragma unroll
+      for (int t = 0; t < p; ++t) s -= P[5 * p + t] * z[t];
+      z[p] = p < ce ? s / P[5 * p + p] : 0.0;
+      sm.zp[p] = z[p];
+    }
+#pragma unroll
+    for (int q = 0; q < 25; ++q) sm.Lp[q] = (q / 5 < ce && q % 5 <= q / 5) ? P[q] : 0.0;
+  }
+  __syncthreads();
+  const double *Lp = sm.Lp, *zp = sm.zp;
+  double *Xo = sm.Xo, *Xk = sm.Xk;
+  // X_o = Lp^{-1} K_c[e, o] (ce x ac), X_k = Lp^{-1} M[e, k] (ce x ck)
+  for (int col = ln; col < ac + ck; col += TCW) {
+    double x[5];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      x[p] = 0.0;
+      if (p < ce) {
+        double s = col < ac ? Kc[(ac + p) * LD + col] : M[(ce + col - ac) * nb + p];
+#pragma unroll
+        for (int t = 0; t < p; ++t) s -= Lp[5 * p + t] * x[t];
+        x[p] = s / Lp[5 * p + p];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      if (p < ce) {
+        if (col < ac) Xo[p * ac + col] = x[p];
+        else Xk[p * 5 + (col - ac)] = x[p];
+      }
+    }
+  }
+  __syncthreads();
+  // K_c[o, o] -= X_o^T X_o ; rows of kcur replace the rows of e
+  for (int idx = ln; idx < ac * ac; idx += TCW) {
+    const int r = idx / ac, s = idx % ac;
+    if (s > r) continue;
+    double t = 0.0;
+    for (int p = 0; p < ce; ++p) t += Xo[p * ac + r] * Xo[p * ac + s];
+    Kc[r * LD + s] -= t;
+  }
+  for (int r = ln; r < ac; r += TCW) {
+    double t = 0.0;
+    for (int p = 0; p < ce; ++p) t += Xo[p * ac + r] * zp[p];
+    yc[r] -= t;
+  }
+  // (kcur rows may overwrite e rows: e rows were read into X_o before the sync)
+  for (int idx = ln; idx < ck * (ac + ck); idx += TCW) {
+    const int r = idx / (ac + ck), s = idx % (ac + ck);
+    double t = 0.0;
+    if (s < ac) {
+      for (int p = 0; p < ce; ++p) t -= Xk[p * 5 + r] * Xo[p * ac + s];
+      Kc[(ac + r) * LD + s] = t;
+    } else if (s - ac <= r) {
+      const int q = s - ac;
+      t = M[(ce + r) * nb + ce + q];
+      for (int p = 0; p < ce; ++p) t -= Xk[p * 5 + r] * Xk[p * 5 + q];
+      Kc[(ac + r) * LD + ac + q] = t;
+    }
+  }
+  if (ln < ck) {
+    double t = m[ce + ln];
+    for (int p = 0; p < ce; ++p) t -= Xk[p * 5 + ln] * zp[p];
+    yc[ac + ln] = t;
+  }
+  // compress record: Lp 5x5, X_o (ce x ac), X_k 5x5, z 5
+  double *rec = a.crec + op.rec;
+  if (ln < 25) {
+    rec[ln] = Lp[ln];
+    rec[25 + 5 * ac + ln] = (ln / 5 < ce && ln % 5 < ck) ? Xk[ln] : 0.0;
+  }
+  if (ln < 5) rec[25 + 5 * ac + 25 + ln] = ln < ce ? zp[ln] : 0.0;
+  for (int idx = ln; idx < ce * ac; idx += TCW) rec[25 + idx] = Xo[idx];
+  __syncthreads();
+  // c's clique now has rows [absorbed; kcur]
+  tcw_store_lower<R>(Kc, Kcg, LDcg, ac + ck, ac + ck);
+  if (ln < ac + ck) ycg[ln] = yc[ln];
+}
+
+// Back-substitution of one clique's private rows: lambda = Lc^{-T} (z - X
+// lambda_b) (lambda_b: nb <= 10 boundary multipliers, the same in every
+// lane), with lane i holding row i, then written to the absorbed joints.
+template <int R>
+DEV void tcw_private_back(const TreeArgs &a, const GJoint *J, int v, int np, int nr,
+                          const double *lb, int e_end, double *Ks) {
+  constexpr int LD = R + 1;
+  const int ln = lane();
+  const int LDg = a.tne[v] + 5;
+  const double *Kg = a.fac + a.foff[v];
+  const double *yg = Kg + LDg * LDg;
+  const int nb = nr - np;
+  tcw_load_lower<R>(Kg, LDg, Ks, nr);
+  double t = 0.0;
+  if (ln < np) t = yg[ln];
+  __syncthreads();
+  if (ln < np) {
+#pragma unroll
+    for (int f = 0; f < 10; ++f)
+      if (f < nb) t -= Ks[(np + f) * LD + ln] * lb[f];
+  }
+  for (int l = np - 1; l >= 0; --l) {
+    if (ln == l) t /= Ks[l * LD + l];
+    const double tl = __shfl(t, l);
+    if (ln < l) t -= Ks[l * LD + ln] * tl;
+  }
+  // write-out: lane e owns absorbed entry e
+  const TcwEnt en = tcw_entry(a, J, a.tabs_off[v], e_end);
+  double w[5];
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    const double tv = __shfl(t, en.r0 + r < TCW ? en.r0 + r : 0);
+    w[r] = r < en.c ? tv : 0.0;
+  }
+  if (ln < e_end - a.tabs_off[v]) {
+#pragma unroll
+    for (int r = 0; r < 5; ++r) a.glam[5 * (int64_t)en.k + r] = w[r];
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(TCW) void tcw_rake_back_kernel(TreeArgs a, const GJoint *J, int op0) {
+  __shared__ double Ks[R * (R + 1)];
+  if (skip_step(a.status, a.step)) return;
+  const TcOp op = a.ops[op0 + blockIdx.x];
+  double lb[10];
+#pragma unroll
+  for (int r = 0; r < 10; ++r) lb[r] = (r < op.ck) ? a.glam[5 * (int64_t)op.kcur + (r < 5 ? r : 0)] : 0.0;
+  tcw_private_back<R>(a, J, op.v, a.tne[op.v], op.nv, lb, a.tabs_off[op.v + 1], Ks);
+}
+
+template <int R>
+__global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, const GJoint *J, int op0) {
+  __shared__ double Ks[R * (R + 1)];
+  if (skip_step(a.status, a.step)) return;
+  const int ln = lane();
+  const TcOp op = a.ops[op0 + blockIdx.x];
+  const int ce = op.ce, ck = op.ck, cs = op.c;
+  const int ac = a.tne[cs];
+  const double *rec = a.crec + op.rec;
+  const double *Lp = rec, *Xo = rec + 25, *Xk = rec + 25 + 5 * ac, *zr = Xk + 25;
+  double lk[5];
+#pragma unroll
+  for (int r = 0; r < 5; ++r) lk[r] = r < ck ? a.glam[5 * (int64_t)op.kcur + r] : 0.0;
+  // lambda_o of c's absorbed rows (solved later in the forward order): lane q
+  // finds the entry that holds row q
+  const TcwEnt en = tcw_entry(a, J, a.tabs_off[cs], a.tabs_off[cs + 1]);
+  const int nent = a.tabs_off[cs + 1] - a.tabs_off[cs];
+  int myk = 0, myw = 0;
+  for (int e = 0; e < nent; ++e) {
+    const int r0 = __shfl(en.r0, e), c = __shfl(en.c, e), k = __shfl(en.k, e);
+    if (ln >= r0 && ln < r0 + c) {
+      myk = k;
+      myw = ln - r0;
+    }
+  }
+  const double lo = ln < ac ? a.glam[5 * (int64_t)myk + myw] : 0.0;
+  // lambda_e = Lp^{-T} (z - X_o lambda_o - X_k lambda_k)
+  double le[5];
+#pragma unroll
+  for (int p = 0; p < 5; ++p) {
+    double s = (p < ce && ln < ac) ? Xo[p * ac + ln] * lo : 0.0;
+    for (int o = TCW / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    double v = 0.0;
+    if (p < ce) {
+      v = zr[p] - s;
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+        if (q < ck) v -= Xk[p * 5 + q] * lk[q];
+    }
+    le[p] = v;
+  }
+#pragma unroll
+  for (int p = 4; p >= 0; --p) {
+    if (p < ce) {
+      double s = le[p];
+#pragma unroll
+      for (int q = p + 1; q < 5; ++q)
+        if (q < ce) s -= Lp[5 * q + p] * le[q];
+      le[p] = s / Lp[5 * p + p];
+    }
+  }
+  if (ln < 5) a.glam[5 * (int64_t)op.e + ln] = ln < ce ? le[ln] : 0.0;
+  // v's private rows, boundary [e; kcur]
+  double lb[10];  // [lambda_e; lambda_kcur], e has 3 or 5 rows
+  if (ce == 3) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) lb[r] = r < 3 ? le[r] : (r < 8 ? lk[r - 3] : 0.0);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) lb[r] = r < 5 ? le[r] : lk[r - 5];
+  }
+  tcw_private_back<R>(a, J, op.v, a.tne[op.v] - ce, op.nv, lb, a.tabs_off[op.v + 1] - 1, Ks);
+}
+
 // ------------------------------------------------------ (d) back-projection
 // dq = diag4(R) (u - Hbar^{-1} sum_k L_k^T lambda_k)  (Eq. primal), then
 // q_out = q_cur + dq and qd_out = (accumulate ? qd_out : 0) + dq / h.
@@ -697,21 +1146,32 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
                  hipStream_t s) {
   if (nslots <= 0) return;
   hipLaunchKernelGGL(tree_prep_kernel, dim3((nslots + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J, nslots);
-  // rounds[2r] .. rounds[2r+1]: rakes of round r; rounds[2r+1] .. rounds[2r+2]: compresses
+  // per round, 6 segments of the operation list: rakes with cliques of <= 16
+  // rows, <= 64 rows, (none), then compresses with cliques of <= 16 rows,
+  // <= 48 rows, and larger (team kernels on the global slots)
   for (int r = 0; r < nround; ++r) {
-    const int r0 = rounds[2 * r], r1 = rounds[2 * r + 1], r2 = rounds[2 * r + 2];
-    if (r1 > r0)
-      hipLaunchKernelGGL(tc_rake_kernel, dim3((r1 - r0 + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J, r0, r1);
-    if (r2 > r1)
-      hipLaunchKernelGGL(tc_compress_kernel, dim3((r2 - r1 + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
-                         r1, r2);
+    const int32_t *o = rounds + 6 * r;
+    if (o[1] > o[0]) hipLaunchKernelGGL(tcw_rake_kernel<16>, dim3(o[1] - o[0]), dim3(TCW), 0, s, a, J, o[0]);
+    if (o[2] > o[1]) hipLaunchKernelGGL(tcw_rake_kernel<64>, dim3(o[2] - o[1]), dim3(TCW), 0, s, a, J, o[1]);
+    if (o[3] > o[2])
+      hipLaunchKernelGGL(tc_rake_kernel, dim3((o[3] - o[2] + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
+                         o[2], o[3]);
+    if (o[4] > o[3]) hipLaunchKernelGGL(tcw_compress_kernel<16>, dim3(o[4] - o[3]), dim3(TCW), 0, s, a, J, o[3]);
+    if (o[5] > o[4]) hipLaunchKernelGGL(tcw_compress_kernel<48>, dim3(o[5] - o[4]), dim3(TCW), 0, s, a, J, o[4]);
+    if (o[6] > o[5])
+      hipLaunchKernelGGL(tc_compress_kernel, dim3((o[6] - o[5] + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
+                         o[5], o[6]);
   }
   for (int r = nround - 1; r >= 0; --r) {
-    const int r0 = rounds[2 * r], r1 = rounds[2 * r + 1], r2 = rounds[2 * r + 2];
-    if (r2 > r1)
-      hipLaunchKernelGGL(tc_compress_back_kernel, dim3((r2 - r1 + 255) / 256), dim3(256), 0, s, a, J, r1, r2);
-    if (r1 > r0)
-      hipLaunchKernelGGL(tc_rake_back_kernel, dim3((r1 - r0 + 255) / 256), dim3(256), 0, s, a, J, r0, r1);
+    const int32_t *o = rounds + 6 * r;
+    if (o[6] > o[5])
+      hipLaunchKernelGGL(tc_compress_back_kernel, dim3((o[6] - o[5] + 255) / 256), dim3(256), 0, s, a, J, o[5], o[6]);
+    if (o[5] > o[4]) hipLaunchKernelGGL(tcw_compress_back_kernel<48>, dim3(o[5] - o[4]), dim3(TCW), 0, s, a, J, o[4]);
+    if (o[4] > o[3]) hipLaunchKernelGGL(tcw_compress_back_kernel<16>, dim3(o[4] - o[3]), dim3(TCW), 0, s, a, J, o[3]);
+    if (o[3] > o[2])
+      hipLaunchKernelGGL(tc_rake_back_kernel, dim3((o[3] - o[2] + 255) / 256), dim3(256), 0, s, a, J, o[2], o[3]);
+    if (o[2] > o[1]) hipLaunchKernelGGL(tcw_rake_back_kernel<64>, dim3(o[2] - o[1]), dim3(TCW), 0, s, a, J, o[1]);
+    if (o[1] > o[0]) hipLaunchKernelGGL(tcw_rake_back_kernel<16>, dim3(o[1] - o[0]), dim3(TCW), 0, s, a, J, o[0]);
   }
 }
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,

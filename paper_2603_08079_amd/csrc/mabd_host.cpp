@@ -166,7 +166,7 @@ struct mabd_ctx {
   int64_t fac_size = 0;
   // tree contraction schedule
   std::vector<TcOp> tc_ops;
-  std::vector<int32_t> tc_rounds;  // 2 * rounds + 1 offsets into tc_ops
+  std::vector<int32_t> tc_rounds;  // 6 * rounds + 1 offsets into tc_ops (segments by kind and size)
   int64_t crec_size = 0;
   TcOp *d_tc_ops = nullptr;
   double *d_crec = nullptr;
@@ -766,7 +766,13 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
         --remaining;
         if (par[s] >= 0) --nalive[par[s]];
       }
-      c->tc_rounds.push_back((int)c->tc_ops.size());
+      {  // rakes by clique size: <= 16 rows, then <= 64 (TREE_KMAX)
+        auto b = c->tc_ops.begin() + c->tc_rounds.back();
+        auto m = std::stable_partition(b, c->tc_ops.end(), [](const TcOp &o) { return o.nv <= 16; });
+        c->tc_rounds.push_back((int)(m - c->tc_ops.begin()));
+        c->tc_rounds.push_back((int)c->tc_ops.size());
+        c->tc_rounds.push_back((int)c->tc_ops.size());
+      }
       chosen.clear();
       for (int s : topdown) {
         if (!alive[s] || par[s] < 0 || nalive[s] != 1 || sel[par[s]]) continue;
@@ -801,6 +807,18 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
         alive[s] = 0;
         sel[s] = 0;
         --remaining;
+      }
+      {  // compresses by the larger of v's and c's staged cliques: <= 16, <= 48, more
+        auto cls = [&](const TcOp &o) {
+          const int cc = c->tne[o.c] + std::max(o.ce, o.ck);
+          const int r = std::max(o.nv, cc);
+          return r <= 16 ? 0 : (r <= 48 ? 1 : 2);
+        };
+        auto b = c->tc_ops.begin() + c->tc_rounds.back();
+        auto m1 = std::stable_partition(b, c->tc_ops.end(), [&](const TcOp &o) { return cls(o) == 0; });
+        auto m2 = std::stable_partition(m1, c->tc_ops.end(), [&](const TcOp &o) { return cls(o) == 1; });
+        c->tc_rounds.push_back((int)(m1 - c->tc_ops.begin()));
+        c->tc_rounds.push_back((int)(m2 - c->tc_ops.begin()));
       }
     }
     c->tc_rounds.push_back((int)c->tc_ops.size());
@@ -1145,7 +1163,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   c->stats.n_graph = c->ngraph;
   c->stats.n_dyn = c->nd;
   c->stats.tile_threads = c->tile_threads;
-  c->stats.tree_rounds = ((int)c->tc_rounds.size() - 1) / 2;
+  c->stats.tree_rounds = ((int)c->tc_rounds.size() - 1) / 6;
   c->stats.rho_p = c->stats.rho_d = c->stats.kkt = -1.0;
   *out = c;
   return MABD_OK;
@@ -1467,7 +1485,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       ta.crec = c->d_crec;
       tm.run(5, [&] {
         launch_tree(ta, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
-                    ((int)c->tc_rounds.size() - 1) / 2, s);
+                    ((int)c->tc_rounds.size() - 1) / 6, s);
       });
       if (c->ngraph > 0) {
         PcgArgs pa{};
