@@ -46,7 +46,7 @@ __global__ void prefactor_kernel(const double *shape, int nshape, double h, doub
 // R and the local unconstrained increment u = Hbar^{-1} diag4(R^T) f_A for
 // bodies [b0, b1) (Eqs. polar, abd_final).  q is the current iterate, qn/qdn
 // the state at the start of the step.
-__global__ void gbody_kernel(int b0, int b1, const double *q, const double *qn, const double *qdn,
+__global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double *q, const double *qn, const double *qdn,
                              int64_t ns, const int32_t *shp, const double *hinv,
                              const double *shape, double g0, double g1, double g2, double h,
                              double *Rg, double *ug, uint32_t *status, int step) {
@@ -86,7 +86,7 @@ __global__ void gbody_kernel(int b0, int b1, const double *q, const double *qn, 
 // end L = s R J(p); for the hinge frame owner L = S_H diag2(dR_H)[J(p1); J(p2)]
 // plus the A-linearised rotation term (rbar_c (x) R_a^T d_m) on the A columns;
 // for the other side L = -S_H diag2(R_H R_b)[J(p1); J(p2)].
-__global__ void gjoint_kernel(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns,
+__global__ __launch_bounds__(128) void gjoint_kernel(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns,
                               int hinge_grad, double *gl) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
@@ -108,7 +108,6 @@ __global__ void gjoint_kernel(int m, const GJoint *J, const double *q, const dou
       t[0] = t[1] = t[2] = 0.0;
     }
   }
-  for (int i = 0; i < GL_STRIDE; ++i) out[i] = 0.0;
   auto point_diff = [&](const double *pa_, const double *pb_, double *d) {
     double wa[3], wb[3];
     mat3_vec(Aa, pa_, wa);
@@ -218,6 +217,9 @@ DEV void team_sync() {
 struct PrepLds {
   double L[TREE_KLDS * 12];
   double Y[12 * TREE_KLDS];
+  int ek[24];               // clique entries: joint,
+  int ei[24];               // first row << 8 | rows << 4 | unary << 1 | side
+  uint8_t rowent[TREE_KMAX];  // clique row -> entry
 };
 
 __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const GJoint *J, int nslots) {
@@ -231,9 +233,38 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   const double *Th = a.hinv + (int64_t)HINV_STRIDE * a.shp[b];
   const int pk = a.tpk[slot];
   const int kpar = pk >= 0 ? (pk >> 1) : -1;
-  const int ck = kpar >= 0 ? (J[kpar].type ? 5 : 3) : 0;
   const int e0 = a.tabs_off[slot], e1 = a.tabs_off[slot + 1];
   const int ne = a.tne[slot];
+  const int nent = e1 - e0 + (kpar >= 0 ? 1 : 0);
+  // 1) clique entries (absorbed joints in list order, then the parent joint),
+  //    fetched in parallel; their rows and the row -> entry map
+  for (int e = ln; e < nent; e += TEAM) {
+    int k, side, un;
+    if (e < e1 - e0) {
+      const int t = a.tabs[e0 + e];
+      k = t >> 2;
+      side = (t >> 1) & 1;
+      un = t & 1;
+    } else {
+      k = kpar;
+      side = pk & 1;
+      un = 1;  // parent rows take C_k only
+    }
+    S.ek[e] = k;
+    S.ei[e] = ((J[k].type ? 5 : 3) << 4) | (un << 1) | side;
+  }
+  team_sync();
+  if (ln == 0) {
+    int r = 0;
+    for (int e = 0; e < nent; ++e) {
+      const int c = (S.ei[e] >> 4) & 15;
+      S.ei[e] |= r << 8;
+      for (int i = 0; i < c; ++i) S.rowent[r + i] = (uint8_t)e;
+      r += c;
+    }
+  }
+  team_sync();
+  const int ck = kpar >= 0 ? (S.ei[nent - 1] >> 4) & 15 : 0;
   const int nr = ne + ck;
   if (nr == 0) return;
   const int LD = ne + 5;
@@ -241,23 +272,20 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   const bool big = nr > TREE_KLDS;
   double *Lm = big ? fac + LD * LD + LD : S.L;
   double *Ym = big ? fac + LD * LD + LD + 12 * nr : S.Y;
-  // 1) clique rows: absorbed joints in list order, then the parent joint
-  {
-    int r0 = 0;
-    for (int e = e0; e <= e1; ++e) {
-      int k, side;
-      if (e < e1) {
-        k = a.tabs[e] >> 2;
-        side = (a.tabs[e] >> 1) & 1;
-      } else {
-        if (kpar < 0) break;
-        k = kpar;
-        side = pk & 1;
-      }
-      const int c = J[k].type ? 5 : 3;
-      const double *Lsrc = a.gl + (int64_t)GL_STRIDE * k + (side ? GL_LB : GL_LA);
-      for (int i = ln; i < c * 12; i += TEAM) Lm[r0 * 12 + i] = Lsrc[i];
-      r0 += c;
+  //    clique rows L (nr x 12), four independent loads per lane in flight
+  for (int base = 0; base < nr * 12; base += 4 * TEAM) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * TEAM + ln;
+      const int r = idx < nr * 12 ? idx / 12 : 0, sc = idx < nr * 12 ? idx % 12 : 0;
+      const int e = S.rowent[r], ei = S.ei[e];
+      v[u] = a.gl[(int64_t)GL_STRIDE * S.ek[e] + ((ei & 1) ? GL_LB : GL_LA) + 12 * (r - (ei >> 8)) + sc];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * TEAM + ln;
+      if (idx < nr * 12) Lm[idx] = v[u];
     }
   }
   team_sync();
@@ -271,7 +299,7 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   // 3) K0 = L Y (lower triangle), y0 = L u + C of one-sided and parent rows
   for (int idx = ln; idx < nr * (nr + 1) / 2; idx += TEAM) {
     // lower-triangle entry idx -> (i, jj), jj <= i (only the lower triangle is ever read)
-    int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    int i = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
     while (i * (i + 1) / 2 > idx) --i;
     while ((i + 1) * (i + 2) / 2 <= idx) ++i;
     const int jj = idx - i * (i + 1) / 2;
@@ -282,26 +310,9 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   for (int i = ln; i < nr; i += TEAM) {
     double v = 0.0;
     for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * a.u[s * a.ns + b];
+    const int e = S.rowent[i], ei = S.ei[e];
+    if (ei & 2) v += a.gl[(int64_t)GL_STRIDE * S.ek[e] + GL_C + (i - (ei >> 8))];
     fac[LD * LD + i] = v;
-  }
-  team_sync();
-  {
-    int r0 = 0;
-    for (int e = e0; e <= e1; ++e) {
-      int k, unary;
-      if (e < e1) {
-        k = a.tabs[e] >> 2;
-        unary = a.tabs[e] & 1;
-      } else {
-        if (kpar < 0) break;
-        k = kpar;
-        unary = 1;  // parent rows take C_k only
-      }
-      const int c = J[k].type ? 5 : 3;
-      if (e == e1 || unary)
-        for (int i = ln; i < c; i += TEAM) fac[LD * LD + r0 + i] += a.gl[(int64_t)GL_STRIDE * k + GL_C + i];
-      r0 += c;
-    }
   }
 }
 
@@ -1025,7 +1036,7 @@ __global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, cons
 // ------------------------------------------------------ (d) back-projection
 // dq = diag4(R) (u - Hbar^{-1} sum_k L_k^T lambda_k)  (Eq. primal), then
 // q_out = q_cur + dq and qd_out = (accumulate ? qd_out : 0) + dq / h.
-__global__ void gapply_kernel(int b0, int b1, const int32_t *inc_off, const int32_t *inc,
+__global__ __launch_bounds__(256) void gapply_kernel(int b0, int b1, const int32_t *inc_off, const int32_t *inc,
                               const double *gl, const double *glam, const double *Rg,
                               const double *ug, int64_t ns, const int32_t *shp, const double *hinv,
                               const double *q_cur, double *q_out, double *qd_out, double h,
