@@ -11,6 +11,7 @@ enum : uint32_t {
   FLAG_NONFINITE = 1u,  // det A <= 0, polar did not converge, or a non-finite value
   FLAG_SINGULAR = 2u,   // a pivot block of an elimination was not positive definite
   FLAG_NOTCONV = 4u,    // an iterative dual solve stopped above its tolerance
+  FLAG_GUARD = 8u,      // a kernel was handed work beyond its static sizes (internal error)
 };
 
 // Chain of ball joints in "row space".  Rows r = 0..K-1 are the joints in

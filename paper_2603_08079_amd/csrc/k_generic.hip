@@ -590,8 +590,9 @@ __global__ __launch_bounds__(256) void tc_compress_back_kernel(TreeArgs a, const
 // each operation gets a whole wave (one 64-lane workgroup), its cliques are
 // staged in LDS (rows padded to R + 1 doubles), every copy issues all of its
 // loads before the first wait, and the rank-1 updates run column-parallel.
-// Two sizes: R = 16 (most operations) and R = 48 / 64; compresses with
-// larger cliques use the team kernels above on the global slots.
+// Sizes R = 16 (most operations), 32 and 48 (compress) / 64 (rake);
+// compresses with larger cliques use the team kernels above on the global
+// slots.
 constexpr int TCW = 64;
 
 template <int R>
@@ -744,6 +745,10 @@ __global__ __launch_bounds__(TCW) void tcw_rake_kernel(TreeArgs a, const GJoint 
   if (skip_step(a.status, a.step)) return;
   const int ln = lane();
   const TcOp op = a.ops[op0 + blockIdx.x];
+  if (op.nv > R) {  // the host sorts operations by clique size
+    if (ln == 0) raise_flag(a.status, FLAG_GUARD, a.step);
+    return;
+  }
   const int v = op.v;
   const int ne = a.tne[v], LDg = ne + 5, nr = op.nv;
   double *Kg = a.fac + a.foff[v];
@@ -781,6 +786,10 @@ __global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJo
   const int v = op.v, cs = op.c, ce = op.ce, ck = op.ck;
   const int av = a.tne[v], LDvg = av + 5, pv = av - ce, nb = ce + ck, nv = op.nv;
   const int ac = a.tne[cs], LDcg = ac + 5;
+  if (nv > R || ac + (ce > ck ? ce : ck) > R) {  // the host sorts operations by clique size
+    if (ln == 0) raise_flag(a.status, FLAG_GUARD, a.step);
+    return;
+  }
   double *Kvg = a.fac + a.foff[v];
   double *yvg = Kvg + LDvg * LDvg;
   double *Kcg = a.fac + a.foff[cs];
@@ -963,6 +972,10 @@ __global__ __launch_bounds__(TCW) void tcw_rake_back_kernel(TreeArgs a, const GJ
   __shared__ double Ks[R * (R + 1)];
   if (skip_step(a.status, a.step)) return;
   const TcOp op = a.ops[op0 + blockIdx.x];
+  if (op.nv > R) {
+    if (threadIdx.x == 0) raise_flag(a.status, FLAG_GUARD, a.step);
+    return;
+  }
   double lb[10];
 #pragma unroll
   for (int r = 0; r < 10; ++r) lb[r] = (r < op.ck) ? a.glam[5 * (int64_t)op.kcur + (r < 5 ? r : 0)] : 0.0;
@@ -977,6 +990,10 @@ __global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, cons
   const TcOp op = a.ops[op0 + blockIdx.x];
   const int ce = op.ce, ck = op.ck, cs = op.c;
   const int ac = a.tne[cs];
+  if (op.nv > R || ac > TCW) {
+    if (ln == 0) raise_flag(a.status, FLAG_GUARD, a.step);
+    return;
+  }
   const double *rec = a.crec + op.rec;
   const double *Lp = rec, *Xo = rec + 25, *Xk = rec + 25 + 5 * ac, *zr = Xk + 25;
   double lk[5];
@@ -1157,31 +1174,30 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
                  hipStream_t s) {
   if (nslots <= 0) return;
   hipLaunchKernelGGL(tree_prep_kernel, dim3((nslots + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J, nslots);
-  // per round, 6 segments of the operation list: rakes with cliques of <= 16
-  // rows, <= 64 rows, (none), then compresses with cliques of <= 16 rows,
-  // <= 48 rows, and larger (team kernels on the global slots)
+  // per round, 7 segments of the operation list (o[7] starts the next round): rakes with cliques of <= 16,
+  // <= 32, <= 64 rows, then compresses with cliques of <= 16, <= 32, <= 48
+  // rows and larger (team kernels on the global slots)
   for (int r = 0; r < nround; ++r) {
-    const int32_t *o = rounds + 6 * r;
+    const int32_t *o = rounds + 7 * r;
     if (o[1] > o[0]) hipLaunchKernelGGL(tcw_rake_kernel<16>, dim3(o[1] - o[0]), dim3(TCW), 0, s, a, J, o[0]);
-    if (o[2] > o[1]) hipLaunchKernelGGL(tcw_rake_kernel<64>, dim3(o[2] - o[1]), dim3(TCW), 0, s, a, J, o[1]);
-    if (o[3] > o[2])
-      hipLaunchKernelGGL(tc_rake_kernel, dim3((o[3] - o[2] + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
-                         o[2], o[3]);
+    if (o[2] > o[1]) hipLaunchKernelGGL(tcw_rake_kernel<32>, dim3(o[2] - o[1]), dim3(TCW), 0, s, a, J, o[1]);
+    if (o[3] > o[2]) hipLaunchKernelGGL(tcw_rake_kernel<64>, dim3(o[3] - o[2]), dim3(TCW), 0, s, a, J, o[2]);
     if (o[4] > o[3]) hipLaunchKernelGGL(tcw_compress_kernel<16>, dim3(o[4] - o[3]), dim3(TCW), 0, s, a, J, o[3]);
-    if (o[5] > o[4]) hipLaunchKernelGGL(tcw_compress_kernel<48>, dim3(o[5] - o[4]), dim3(TCW), 0, s, a, J, o[4]);
-    if (o[6] > o[5])
-      hipLaunchKernelGGL(tc_compress_kernel, dim3((o[6] - o[5] + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
-                         o[5], o[6]);
+    if (o[5] > o[4]) hipLaunchKernelGGL(tcw_compress_kernel<32>, dim3(o[5] - o[4]), dim3(TCW), 0, s, a, J, o[4]);
+    if (o[6] > o[5]) hipLaunchKernelGGL(tcw_compress_kernel<48>, dim3(o[6] - o[5]), dim3(TCW), 0, s, a, J, o[5]);
+    if (o[7] > o[6])
+      hipLaunchKernelGGL(tc_compress_kernel, dim3((o[7] - o[6] + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
+                         o[6], o[7]);
   }
   for (int r = nround - 1; r >= 0; --r) {
-    const int32_t *o = rounds + 6 * r;
-    if (o[6] > o[5])
-      hipLaunchKernelGGL(tc_compress_back_kernel, dim3((o[6] - o[5] + 255) / 256), dim3(256), 0, s, a, J, o[5], o[6]);
-    if (o[5] > o[4]) hipLaunchKernelGGL(tcw_compress_back_kernel<48>, dim3(o[5] - o[4]), dim3(TCW), 0, s, a, J, o[4]);
+    const int32_t *o = rounds + 7 * r;
+    if (o[7] > o[6])
+      hipLaunchKernelGGL(tc_compress_back_kernel, dim3((o[7] - o[6] + 255) / 256), dim3(256), 0, s, a, J, o[6], o[7]);
+    if (o[6] > o[5]) hipLaunchKernelGGL(tcw_compress_back_kernel<48>, dim3(o[6] - o[5]), dim3(TCW), 0, s, a, J, o[5]);
+    if (o[5] > o[4]) hipLaunchKernelGGL(tcw_compress_back_kernel<32>, dim3(o[5] - o[4]), dim3(TCW), 0, s, a, J, o[4]);
     if (o[4] > o[3]) hipLaunchKernelGGL(tcw_compress_back_kernel<16>, dim3(o[4] - o[3]), dim3(TCW), 0, s, a, J, o[3]);
-    if (o[3] > o[2])
-      hipLaunchKernelGGL(tc_rake_back_kernel, dim3((o[3] - o[2] + 255) / 256), dim3(256), 0, s, a, J, o[2], o[3]);
-    if (o[2] > o[1]) hipLaunchKernelGGL(tcw_rake_back_kernel<64>, dim3(o[2] - o[1]), dim3(TCW), 0, s, a, J, o[1]);
+    if (o[3] > o[2]) hipLaunchKernelGGL(tcw_rake_back_kernel<64>, dim3(o[3] - o[2]), dim3(TCW), 0, s, a, J, o[2]);
+    if (o[2] > o[1]) hipLaunchKernelGGL(tcw_rake_back_kernel<32>, dim3(o[2] - o[1]), dim3(TCW), 0, s, a, J, o[1]);
     if (o[1] > o[0]) hipLaunchKernelGGL(tcw_rake_back_kernel<16>, dim3(o[1] - o[0]), dim3(TCW), 0, s, a, J, o[0]);
   }
 }

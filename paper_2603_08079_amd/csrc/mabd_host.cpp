@@ -166,7 +166,7 @@ struct mabd_ctx {
   int64_t fac_size = 0;
   // tree contraction schedule
   std::vector<TcOp> tc_ops;
-  std::vector<int32_t> tc_rounds;  // 6 * rounds + 1 offsets into tc_ops (segments by kind and size)
+  std::vector<int32_t> tc_rounds;  // 7 * rounds + 1 offsets into tc_ops (segments by kind and size)
   int64_t crec_size = 0;
   TcOp *d_tc_ops = nullptr;
   double *d_crec = nullptr;
@@ -254,6 +254,38 @@ hipError_t dalloc(mabd_ctx *c, T **p, size_t count) {
     *p = static_cast<T *>(q);
   }
   return e;
+}
+
+// Sorts the operations of one round and kind, from ops[rounds.back()] to the
+// end, into size classes (clique rows <= rows[k]) and appends the class ends
+// to rounds (nclass values; larger cliques form a last class ending at
+// ops.end(), the start of the next segment).  A class whose operations all fit at once into
+// the next class's kernel (count <= cap[k + 1]) joins that class: one launch
+// fewer on the critical path of a small round.
+template <class Size>
+void segment_ops(std::vector<TcOp> &ops, std::vector<int32_t> &rounds, Size size, const int *rows,
+                 const int *cap, int nclass) {
+  auto b = ops.begin() + rounds.back();
+  auto cls = [&](const TcOp &o) {
+    const int r = size(o);
+    for (int k = 0; k < nclass; ++k)
+      if (r <= rows[k]) return k;
+    return nclass;
+  };
+  std::vector<int> cnt(nclass + 1, 0), up(nclass + 1);
+  for (auto it = b; it != ops.end(); ++it) ++cnt[cls(*it)];
+  for (int k = 0; k <= nclass; ++k) up[k] = k;
+  for (int k = 0; k + 1 < nclass; ++k)
+    if (cnt[k] > 0 && cnt[k] + cnt[k + 1] <= cap[k + 1]) {
+      cnt[k + 1] += cnt[k];
+      cnt[k] = 0;
+      for (int q = 0; q <= k; ++q)
+        if (up[q] == k) up[q] = k + 1;
+    }
+  std::stable_sort(b, ops.end(), [&](const TcOp &x, const TcOp &y) { return up[cls(x)] < up[cls(y)]; });
+  for (int k = 0; k < nclass; ++k)
+    rounds.push_back((int)(std::partition_point(b, ops.end(), [&](const TcOp &o) { return up[cls(o)] <= k; }) -
+                           ops.begin()));
 }
 
 template <typename T>
@@ -766,12 +798,10 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
         --remaining;
         if (par[s] >= 0) --nalive[par[s]];
       }
-      {  // rakes by clique size: <= 16 rows, then <= 64 (TREE_KMAX)
-        auto b = c->tc_ops.begin() + c->tc_rounds.back();
-        auto m = std::stable_partition(b, c->tc_ops.end(), [](const TcOp &o) { return o.nv <= 16; });
-        c->tc_rounds.push_back((int)(m - c->tc_ops.begin()));
-        c->tc_rounds.push_back((int)c->tc_ops.size());
-        c->tc_rounds.push_back((int)c->tc_ops.size());
+      {  // rakes by clique size: <= 16, <= 32, <= 64 rows (TREE_KMAX)
+        const int rows[3] = {16, 32, 64};
+        const int cap[3] = {1 << 30, 4096, 1024};  // operations the kernel runs at once
+        segment_ops(c->tc_ops, c->tc_rounds, [](const TcOp &o) { return o.nv; }, rows, cap, 3);
       }
       chosen.clear();
       for (int s : topdown) {
@@ -808,17 +838,13 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
         sel[s] = 0;
         --remaining;
       }
-      {  // compresses by the larger of v's and c's staged cliques: <= 16, <= 48, more
-        auto cls = [&](const TcOp &o) {
-          const int cc = c->tne[o.c] + std::max(o.ce, o.ck);
-          const int r = std::max(o.nv, cc);
-          return r <= 16 ? 0 : (r <= 48 ? 1 : 2);
-        };
-        auto b = c->tc_ops.begin() + c->tc_rounds.back();
-        auto m1 = std::stable_partition(b, c->tc_ops.end(), [&](const TcOp &o) { return cls(o) == 0; });
-        auto m2 = std::stable_partition(m1, c->tc_ops.end(), [&](const TcOp &o) { return cls(o) == 1; });
-        c->tc_rounds.push_back((int)(m1 - c->tc_ops.begin()));
-        c->tc_rounds.push_back((int)(m2 - c->tc_ops.begin()));
+      {  // compresses by the larger of v's and c's staged cliques: <= 16, <= 32,
+         // <= 48 rows, more (team kernels on the global slots)
+        const int rows[3] = {16, 32, 48};
+        const int cap[3] = {1 << 30, 2048, 768};
+        segment_ops(c->tc_ops, c->tc_rounds,
+                    [&](const TcOp &o) { return std::max(o.nv, c->tne[o.c] + std::max(o.ce, o.ck)); }, rows,
+                    cap, 3);
       }
     }
     c->tc_rounds.push_back((int)c->tc_ops.size());
@@ -1163,7 +1189,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   c->stats.n_graph = c->ngraph;
   c->stats.n_dyn = c->nd;
   c->stats.tile_threads = c->tile_threads;
-  c->stats.tree_rounds = ((int)c->tc_rounds.size() - 1) / 6;
+  c->stats.tree_rounds = ((int)c->tc_rounds.size() - 1) / 7;
   c->stats.rho_p = c->stats.rho_d = c->stats.kkt = -1.0;
   *out = c;
   return MABD_OK;
@@ -1485,7 +1511,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       ta.crec = c->d_crec;
       tm.run(5, [&] {
         launch_tree(ta, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
-                    ((int)c->tc_rounds.size() - 1) / 6, s);
+                    ((int)c->tc_rounds.size() - 1) / 7, s);
       });
       if (c->ngraph > 0) {
         PcgArgs pa{};
@@ -1672,13 +1698,15 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
     const int f = (int)c->h_status[1];
     c->cur = (start_cur + f) % 2;
     c->stats.steps_done += f;
-    c->stats.last_status = (bits & FLAG_NONFINITE) ? MABD_ERR_NONFINITE
-                           : (bits & FLAG_SINGULAR) ? MABD_ERR_SINGULAR
-                                                    : MABD_ERR_NOT_CONVERGED;
+    c->stats.last_status = (bits & FLAG_GUARD)       ? MABD_ERR_DEVICE
+                           : (bits & FLAG_NONFINITE) ? MABD_ERR_NONFINITE
+                           : (bits & FLAG_SINGULAR)  ? MABD_ERR_SINGULAR
+                                                     : MABD_ERR_NOT_CONVERGED;
     return fail(c, (mabd_status)c->stats.last_status,
-                (bits & FLAG_NONFINITE) ? "non-finite value or det A <= 0 during the step"
-                : (bits & FLAG_SINGULAR) ? "dual pivot block not positive definite"
-                                         : "PCG reached max_iters above kkt_tol");
+                (bits & FLAG_GUARD)       ? "internal error: a tree operation exceeded its kernel's clique size"
+                : (bits & FLAG_NONFINITE) ? "non-finite value or det A <= 0 during the step"
+                : (bits & FLAG_SINGULAR)  ? "dual pivot block not positive definite"
+                                          : "PCG reached max_iters above kkt_tol");
   }
   c->stats.steps_done += nsteps;
   c->stats.last_status = MABD_OK;
