@@ -27,7 +27,7 @@ FORMS = {0: "plain FP64", 1: "FP32 bulk + FP64 factor + FP64 refinement"}
 # Algorithmic HBM bytes per body (or joint) that each kernel must move at
 # minimum (FP64): state q, qdot read (192 B) and written (192 B), per-row
 # anchors of both ends and the side flags (49 B), shape index (4 B),
-# multipliers written (24 B).  See DESIGN.md, "Measurement".
+# multipliers written (24 B).
 ALG_BYTES = {
     "chain_reduce": 192 + 49 + 4,
     "chain_apply": 192 + 49 + 4 + 192 + 24,
@@ -39,9 +39,9 @@ ALG_BYTES = {
 ALG_BYTES_F1 = {"chain_resid": 288 + 53 + 24 + 120}
 # HBM bytes per launch of the dominant kernel measured with rocprofv3 --pmc
 # (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, scales from a plain 512 MiB copy) for
-# the 64-thread chain tile kernels of this build on the 1M chain; reported only
+# the 64-thread chain tile kernels as they stand, on the 1M chain; reported only
 # for that workload and tile size.
-PMC_TRAFFIC = {("chain1m", "chain_apply", 64): (171531 * 2 + 221390) * 1024,
+PMC_TRAFFIC = {("chain1m", "chain_apply", 64): (171525 * 2 + 221386) * 1024,
                ("chain1m", "chain_reduce", 64): (125814 * 2 + 3569) * 1024}
 
 
@@ -65,8 +65,8 @@ def main():
                          "to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
+              "run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
