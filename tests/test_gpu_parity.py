@@ -194,6 +194,18 @@ def test_wide_tree_contraction():
     say("worst", teacher_forced(asm, 2, tol_v=TOL_V_TREE))
 
 
+def test_large_clique_compress():
+    """A body with ten hinge leaves and one hinge child chain, under a short
+    chain: after the leaves are raked it has a single live child, so it is
+    compressed with a 60-row clique, larger than the LDS-staged kernels take
+    (the team kernels on the global slots run it)."""
+    parents = np.array([0, 0, 1, 2, 3, 4] + [5] * 10 + [5] + list(range(16, 60)))
+    asm = mi.tree(len(parents), seed=48, parents=parents, hinge_frac=1.0)
+    asm.qd0[1:] = np.random.default_rng(48).normal(0, 0.05, (asm.n - 1, 12))
+    say("60-row clique compress, bodies", asm.n)
+    say("worst", teacher_forced(asm, 2, tol_v=TOL_V_TREE))
+
+
 def test_many_tree_components():
     """Trees and hinge chains of different depths in one context: their
     contraction rounds run in the same launches."""
