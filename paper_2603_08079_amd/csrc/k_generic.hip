@@ -584,84 +584,87 @@ __global__ __launch_bounds__(256) void tc_compress_back_kernel(TreeArgs a, const
   tc_private_back(a, J, op.v, a.tne[op.v] - ce, op.nv, lb, a.tabs_off[op.v + 1] - 1);
 }
 
-// ------------------------------------------- wave-per-operation contraction
+// ------------------------------------------- team-per-operation contraction
 // The rounds are bound by the latency of their slowest operations, not by
 // bandwidth: a clique's partial Cholesky is a chain of dependent steps.  So
-// each operation gets a whole wave (one 64-lane workgroup), its cliques are
-// staged in LDS (rows padded to R + 1 doubles), every copy issues all of its
-// loads before the first wait, and the rank-1 updates run column-parallel.
-// Sizes R = 16 (most operations), 32 and 48 (compress) / 64 (rake);
-// compresses with larger cliques use the team kernels above on the global
-// slots.
-constexpr int TCW = 64;
+// each operation gets a team of TW lanes within one wave (TW = 16: four
+// operations per wave, for cliques of up to 16 rows; TW = 64 for larger
+// ones), its cliques are staged in LDS as packed lower triangles (row i at
+// i (i + 1) / 2), every copy issues all of its loads before the first wait,
+// and the rank-1 updates run column-parallel.  Clique sizes R = 16, 32 and
+// 48 (compress) / 64 (rake); compresses with larger cliques use the team
+// kernels above on the global slots.  Workgroups are one wave, so a team
+// synchronises with a wave barrier.
+constexpr int TCW = 64;  // lanes per workgroup
+
+DEV int tri(int i) { return (i * (i + 1)) >> 1; }
 
 template <int R>
 struct TcwMat {
-  double K[R * (R + 1)];
+  double K[R * (R + 1) / 2];
   double y[R];
 };
 template <int R>
 struct TcwComp {
   TcwMat<R> v, c;
-  double M[110];  // boundary Schur complement of v (nb x nb) and its rhs
   double Lp[25];  // Cholesky factor of the pivot block of e
   double zp[5];   // Lp^{-1} rhs_e
   double Xo[5 * R];
   double Xk[25];
 };
 
-DEV int lane() { return (int)threadIdx.x; }
+template <int TW>
+DEV int tlane() { return (int)threadIdx.x % TW; }
 
 // lower triangle of rows [0, nr) of a global clique (leading dimension ls)
-// into LDS; loads are issued eight at a time before their stores
-template <int R>
+// into a packed LDS triangle; loads are issued eight at a time
+template <int R, int TW>
 DEV void tcw_load_lower(const double *src, int ls, double *dst, int nr) {
-  constexpr int LD = R + 1;
   const int n = nr * R;
-  for (int base = 0; base < n; base += 8 * TCW) {
+  for (int base = 0; base < n; base += 8 * TW) {
     double v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int idx = base + u * TCW + lane();
+      const int idx = base + u * TW + tlane<TW>();
       const int i = idx / R, j = idx - (idx / R) * R;
       v[u] = src[(idx < n && j <= i) ? i * ls + j : 0];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int idx = base + u * TCW + lane();
+      const int idx = base + u * TW + tlane<TW>();
       const int i = idx / R, j = idx - (idx / R) * R;
-      if (idx < n && j <= i) dst[i * LD + j] = v[u];
+      if (idx < n && j <= i) dst[tri(i) + j] = v[u];
     }
   }
 }
 
-// LDS clique rows [0, nr), columns j <= i and j < ncol, back to global
-template <int R>
+// packed LDS clique rows [0, nr), columns j <= i and j < ncol, back to global
+template <int R, int TW>
 DEV void tcw_store_lower(const double *src, double *dst, int ld, int nr, int ncol) {
-  constexpr int LD = R + 1;
-  for (int idx = lane(); idx < nr * R; idx += TCW) {
+  for (int idx = tlane<TW>(); idx < nr * R; idx += TW) {
     const int i = idx / R, j = idx - (idx / R) * R;
-    if (j <= i && j < ncol) dst[i * ld + j] = src[i * LD + j];
+    if (j <= i && j < ncol) dst[i * ld + j] = src[tri(i) + j];
   }
 }
 
-// Entries [e0, e1) of an absorbed list, one per lane: joint, rows, first
-// row in the clique, and whether the joint is one-sided (no condensed side).
+// Entries [e0, e1) of an absorbed list, one per lane (e1 - e0 <= TW): joint,
+// rows, first row in the clique, and whether the joint is one-sided.
 struct TcwEnt {
   int k, c, r0, unary;
 };
+template <int TW>
 DEV TcwEnt tcw_entry(const TreeArgs &a, const GJoint *J, int e0, int e1) {
   TcwEnt t{0, 0, 0, 1};
-  const int ln = lane();
+  const int ln = tlane<TW>();
   if (ln < e1 - e0) {
     const int tab = a.tabs[e0 + ln];
     t.k = tab >> 2;
     t.unary = tab & 1;
     t.c = J[t.k].type ? 5 : 3;
   }
-  int x = t.c;  // inclusive prefix over lanes
-  for (int o = 1; o < TCW; o <<= 1) {
-    const int u = __shfl_up(x, o);
+  int x = t.c;  // inclusive prefix over the team
+  for (int o = 1; o < TW; o <<= 1) {
+    const int u = __shfl_up(x, o, TW);
     if (ln >= o) x += u;
   }
   t.r0 = x - t.c;
@@ -670,11 +673,10 @@ DEV TcwEnt tcw_entry(const TreeArgs &a, const GJoint *J, int e0, int e1) {
 
 // add the condensed far sides of the list's non-unary joints; each lane
 // adds its own entry's diagonal block (all loads in flight at once)
-template <int R>
+template <int R, int TW>
 DEV void tcw_add_children(const TreeArgs &a, const GJoint *J, int e0, int e1, double *K, double *y) {
-  constexpr int LD = R + 1;
-  const TcwEnt t = tcw_entry(a, J, e0, e1);
-  if (lane() < e1 - e0 && !t.unary) {
+  const TcwEnt t = tcw_entry<TW>(a, J, e0, e1);
+  if (tlane<TW>() < e1 - e0 && !t.unary) {
     const double *g = a.gt + (int64_t)GT_STRIDE * t.k;
     double sg[25], rh[5];
 #pragma unroll
@@ -685,22 +687,22 @@ DEV void tcw_add_children(const TreeArgs &a, const GJoint *J, int e0, int e1, do
     for (int r = 0; r < 5; ++r) {
       if (r < t.c) {
 #pragma unroll
-        for (int s = 0; s <= r; ++s) K[(t.r0 + r) * LD + t.r0 + s] += sg[5 * r + s];
+        for (int s = 0; s <= r; ++s) K[tri(t.r0 + r) + t.r0 + s] += sg[5 * r + s];
         y[t.r0 + r] += rh[r];
       }
     }
   }
 }
 
-// partial Cholesky of the first np of nr rows of an LDS clique (same
-// arithmetic as tc_partial_cholesky): lane i scales row p + 1 + i of the
-// pivot column, then updates column p + 1 + i of the trailing triangle
-template <int R>
+// partial Cholesky of the first np of nr (<= TW + 1) rows of a packed LDS
+// clique (same arithmetic as tc_partial_cholesky): lane i scales row
+// p + 1 + i of the pivot column, then updates column p + 1 + i of the
+// trailing triangle in batches of eight independent rows
+template <int R, int TW>
 DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, int np) {
-  constexpr int LD = R + 1;
-  const int ln = lane();
+  const int ln = tlane<TW>();
   for (int p = 0; p < np; ++p) {
-    double d = K[p * LD + p];
+    double d = K[tri(p) + p];
     if (!(d > 0.0)) {
       if (ln == 0) raise_flag(a.status, FLAG_SINGULAR, a.step);
       d = 1.0;
@@ -709,42 +711,44 @@ DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, i
     const double yp = y[p] / d;
     const int i = p + 1 + ln;
     double lip = 0.0;
-    if (i < nr) lip = K[i * LD + p] / d;
-    __syncthreads();
+    if (i < nr) lip = K[tri(i) + p] / d;
+    team_sync();
     if (ln == 0) {
-      K[p * LD + p] = d;
+      K[tri(p) + p] = d;
       y[p] = yp;
     }
     if (i < nr) {
-      K[i * LD + p] = lip;
+      K[tri(i) + p] = lip;
       y[i] -= lip * yp;
     }
-    __syncthreads();
+    team_sync();
     if (i < nr) {  // column j = i, rows r >= j: K[r][j] -= l_rp l_jp
       for (int r = i; r < nr; r += 8) {
         double kv[8], lr[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int rr = r + u < nr ? r + u : nr - 1;
-          kv[u] = K[rr * LD + i];
-          lr[u] = K[rr * LD + p];
+          kv[u] = K[tri(rr) + i];
+          lr[u] = K[tri(rr) + p];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          if (r + u < nr) K[(r + u) * LD + i] = kv[u] - lr[u] * lip;
+          if (r + u < nr) K[tri(r + u) + i] = kv[u] - lr[u] * lip;
       }
     }
-    __syncthreads();
+    team_sync();
   }
 }
 
-template <int R>
-__global__ __launch_bounds__(TCW) void tcw_rake_kernel(TreeArgs a, const GJoint *J, int op0) {
-  constexpr int LD = R + 1;
-  __shared__ TcwMat<R> sm;
+template <int R, int TW>
+__global__ __launch_bounds__(TCW) void tcw_rake_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
+  __shared__ TcwMat<R> team_sm[TCW / TW];
   if (skip_step(a.status, a.step)) return;
-  const int ln = lane();
-  const TcOp op = a.ops[op0 + blockIdx.x];
+  const int ln = tlane<TW>(), tm = (int)threadIdx.x / TW;
+  const int oi = op0 + (int)blockIdx.x * (TCW / TW) + tm;
+  if (oi >= op1) return;
+  TcwMat<R> &sm = team_sm[tm];
+  const TcOp op = a.ops[oi];
   if (op.nv > R) {  // the host sorts operations by clique size
     if (ln == 0) raise_flag(a.status, FLAG_GUARD, a.step);
     return;
@@ -753,36 +757,40 @@ __global__ __launch_bounds__(TCW) void tcw_rake_kernel(TreeArgs a, const GJoint 
   const int ne = a.tne[v], LDg = ne + 5, nr = op.nv;
   double *Kg = a.fac + a.foff[v];
   double *yg = Kg + LDg * LDg;
-  tcw_load_lower<R>(Kg, LDg, sm.K, nr);
-  if (ln < nr) sm.y[ln] = yg[ln];
-  __syncthreads();
-  tcw_add_children<R>(a, J, a.tabs_off[v], a.tabs_off[v + 1], sm.K, sm.y);
-  __syncthreads();
-  tcw_partial_cholesky<R>(a, sm.K, sm.y, nr, ne);
+  tcw_load_lower<R, TW>(Kg, LDg, sm.K, nr);
+  for (int r = ln; r < nr; r += TW) sm.y[r] = yg[r];
+  team_sync();
+  tcw_add_children<R, TW>(a, J, a.tabs_off[v], a.tabs_off[v + 1], sm.K, sm.y);
+  team_sync();
+  tcw_partial_cholesky<R, TW>(a, sm.K, sm.y, nr, ne);
   if (op.kcur >= 0) {
     double *gtk = a.gt + (int64_t)GT_STRIDE * op.kcur;
-    if (ln < 25) {
-      const int r = ln / 5, s = ln % 5;
-      double val = 0.0;
-      if (r < op.ck && s < op.ck) val = s <= r ? sm.K[(ne + r) * LD + ne + s] : sm.K[(ne + s) * LD + ne + r];
-      gtk[GT_SIG + ln] = val;
-    } else if (ln < 30) {
-      const int r = ln - 25;
-      gtk[GT_RHO + r] = r < op.ck ? sm.y[ne + r] : 0.0;
+    for (int q = ln; q < 30; q += TW) {
+      if (q < 25) {
+        const int r = q / 5, s = q % 5;
+        double val = 0.0;
+        if (r < op.ck && s < op.ck) val = s <= r ? sm.K[tri(ne + r) + ne + s] : sm.K[tri(ne + s) + ne + r];
+        gtk[GT_SIG + q] = val;
+      } else {
+        const int r = q - 25;
+        gtk[GT_RHO + r] = r < op.ck ? sm.y[ne + r] : 0.0;
+      }
     }
   }
   // factor columns and z of the private rows, for the back-substitution
-  tcw_store_lower<R>(sm.K, Kg, LDg, nr, ne);
-  if (ln < ne) yg[ln] = sm.y[ln];
+  tcw_store_lower<R, TW>(sm.K, Kg, LDg, nr, ne);
+  for (int r = ln; r < ne; r += TW) yg[r] = sm.y[r];
 }
 
-template <int R>
-__global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJoint *J, int op0) {
-  constexpr int LD = R + 1;
-  __shared__ TcwComp<R> sm;
+template <int R, int TW>
+__global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
+  __shared__ TcwComp<R> team_sm[TCW / TW];
   if (skip_step(a.status, a.step)) return;
-  const int ln = lane();
-  const TcOp op = a.ops[op0 + blockIdx.x];
+  const int ln = tlane<TW>(), tm = (int)threadIdx.x / TW;
+  const int oi = op0 + (int)blockIdx.x * (TCW / TW) + tm;
+  if (oi >= op1) return;
+  TcwComp<R> &sm = team_sm[tm];
+  const TcOp op = a.ops[oi];
   const int v = op.v, cs = op.c, ce = op.ce, ck = op.ck;
   const int av = a.tne[v], LDvg = av + 5, pv = av - ce, nb = ce + ck, nv = op.nv;
   const int ac = a.tne[cs], LDcg = ac + 5;
@@ -795,25 +803,20 @@ __global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJo
   double *Kcg = a.fac + a.foff[cs];
   double *ycg = Kcg + LDcg * LDcg;
   double *Kv = sm.v.K, *yv = sm.v.y, *Kc = sm.c.K, *yc = sm.c.y;
-  double *M = sm.M, *m = sm.M + 100;
+  // boundary Schur complement of v on [e; kcur] (read in place, symmetric)
+  auto Mv = [&](int r, int s) { return r >= s ? Kv[tri(pv + r) + pv + s] : Kv[tri(pv + s) + pv + r]; };
   // 1) v: condensed children except the live child (last entry), private
   //    rows factored; boundary rows [e; kcur] remain
-  tcw_load_lower<R>(Kvg, LDvg, Kv, nv);
-  tcw_load_lower<R>(Kcg, LDcg, Kc, ac + ce);
-  if (ln < nv) yv[ln] = yvg[ln];
-  if (ln < ac + ce) yc[ln] = ycg[ln];
-  __syncthreads();
-  tcw_add_children<R>(a, J, a.tabs_off[v], a.tabs_off[v + 1] - 1, Kv, yv);
-  __syncthreads();
-  tcw_partial_cholesky<R>(a, Kv, yv, nv, pv);
-  for (int idx = ln; idx < nb * nb; idx += TCW) {
-    const int r = idx / nb, s = idx % nb;
-    M[idx] = s <= r ? Kv[(pv + r) * LD + pv + s] : Kv[(pv + s) * LD + pv + r];
-  }
-  if (ln < nb) m[ln] = yv[pv + ln];
-  tcw_store_lower<R>(Kv, Kvg, LDvg, nv, pv);
-  if (ln < pv) yvg[ln] = yv[ln];
-  __syncthreads();
+  tcw_load_lower<R, TW>(Kvg, LDvg, Kv, nv);
+  tcw_load_lower<R, TW>(Kcg, LDcg, Kc, ac + ce);
+  for (int r = ln; r < nv; r += TW) yv[r] = yvg[r];
+  for (int r = ln; r < ac + ce; r += TW) yc[r] = ycg[r];
+  team_sync();
+  tcw_add_children<R, TW>(a, J, a.tabs_off[v], a.tabs_off[v + 1] - 1, Kv, yv);
+  team_sync();
+  tcw_partial_cholesky<R, TW>(a, Kv, yv, nv, pv);
+  tcw_store_lower<R, TW>(Kv, Kvg, LDvg, nv, pv);
+  for (int r = ln; r < pv; r += TW) yvg[r] = yv[r];
   // 2) c: rows [absorbed (ac); e (ce)]; pivot P = K_c[e,e] + M[e,e]
   if (ln == 0) {  // ce <= 5: fixed trip counts keep P, r, z in registers
     double P[25], r[5], z[5];
@@ -821,8 +824,8 @@ __global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJo
     for (int p = 0; p < 5; ++p) {
 #pragma unroll
       for (int q = 0; q < 5; ++q)
-        P[5 * p + q] = (p < ce && q <= p) ? Kc[(ac + p) * LD + ac + q] + M[p * nb + q] : 0.0;
-      r[p] = p < ce ? yc[ac + p] + m[p] : 0.0;
+        P[5 * p + q] = (p < ce && q <= p) ? Kc[tri(ac + p) + ac + q] + Mv(p, q) : 0.0;
+      r[p] = p < ce ? yc[ac + p] + yv[pv + p] : 0.0;
     }
 #pragma unroll
     for (int p = 0; p < 5; ++p) {  // Cholesky, lower triangle
@@ -856,17 +859,17 @@ __global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJo
 #pragma unroll
     for (int q = 0; q < 25; ++q) sm.Lp[q] = (q / 5 < ce && q % 5 <= q / 5) ? P[q] : 0.0;
   }
-  __syncthreads();
+  team_sync();
   const double *Lp = sm.Lp, *zp = sm.zp;
   double *Xo = sm.Xo, *Xk = sm.Xk;
   // X_o = Lp^{-1} K_c[e, o] (ce x ac), X_k = Lp^{-1} M[e, k] (ce x ck)
-  for (int col = ln; col < ac + ck; col += TCW) {
+  for (int col = ln; col < ac + ck; col += TW) {
     double x[5];
 #pragma unroll
     for (int p = 0; p < 5; ++p) {
       x[p] = 0.0;
       if (p < ce) {
-        double s = col < ac ? Kc[(ac + p) * LD + col] : M[(ce + col - ac) * nb + p];
+        double s = col < ac ? Kc[tri(ac + p) + col] : Mv(ce + col - ac, p);
 #pragma unroll
         for (int t = 0; t < p; ++t) s -= Lp[5 * p + t] * x[t];
         x[p] = s / Lp[5 * p + p];
@@ -880,85 +883,85 @@ __global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJo
       }
     }
   }
-  __syncthreads();
-  // K_c[o, o] -= X_o^T X_o ; rows of kcur replace the rows of e
-  for (int idx = ln; idx < ac * ac; idx += TCW) {
+  team_sync();
+  // K_c[o, o] -= X_o^T X_o ; rows of kcur replace the rows of e (the e rows
+  // were read into X_o before the barrier)
+  for (int idx = ln; idx < ac * ac; idx += TW) {
     const int r = idx / ac, s = idx % ac;
     if (s > r) continue;
     double t = 0.0;
     for (int p = 0; p < ce; ++p) t += Xo[p * ac + r] * Xo[p * ac + s];
-    Kc[r * LD + s] -= t;
+    Kc[tri(r) + s] -= t;
   }
-  for (int r = ln; r < ac; r += TCW) {
+  for (int r = ln; r < ac; r += TW) {
     double t = 0.0;
     for (int p = 0; p < ce; ++p) t += Xo[p * ac + r] * zp[p];
     yc[r] -= t;
   }
-  // (kcur rows may overwrite e rows: e rows were read into X_o before the sync)
-  for (int idx = ln; idx < ck * (ac + ck); idx += TCW) {
+  for (int idx = ln; idx < ck * (ac + ck); idx += TW) {
     const int r = idx / (ac + ck), s = idx % (ac + ck);
     double t = 0.0;
     if (s < ac) {
       for (int p = 0; p < ce; ++p) t -= Xk[p * 5 + r] * Xo[p * ac + s];
-      Kc[(ac + r) * LD + s] = t;
+      Kc[tri(ac + r) + s] = t;
     } else if (s - ac <= r) {
       const int q = s - ac;
-      t = M[(ce + r) * nb + ce + q];
+      t = Mv(ce + r, ce + q);
       for (int p = 0; p < ce; ++p) t -= Xk[p * 5 + r] * Xk[p * 5 + q];
-      Kc[(ac + r) * LD + ac + q] = t;
+      Kc[tri(ac + r) + ac + q] = t;
     }
   }
-  if (ln < ck) {
-    double t = m[ce + ln];
-    for (int p = 0; p < ce; ++p) t -= Xk[p * 5 + ln] * zp[p];
-    yc[ac + ln] = t;
+  for (int r = ln; r < ck; r += TW) {
+    double t = yv[pv + ce + r];
+    for (int p = 0; p < ce; ++p) t -= Xk[p * 5 + r] * zp[p];
+    yc[ac + r] = t;
   }
   // compress record: Lp 5x5, X_o (ce x ac), X_k 5x5, z 5
   double *rec = a.crec + op.rec;
-  if (ln < 25) {
-    rec[ln] = Lp[ln];
-    rec[25 + 5 * ac + ln] = (ln / 5 < ce && ln % 5 < ck) ? Xk[ln] : 0.0;
+  for (int q = ln; q < 25; q += TW) {
+    rec[q] = Lp[q];
+    rec[25 + 5 * ac + q] = (q / 5 < ce && q % 5 < ck) ? Xk[q] : 0.0;
   }
   if (ln < 5) rec[25 + 5 * ac + 25 + ln] = ln < ce ? zp[ln] : 0.0;
-  for (int idx = ln; idx < ce * ac; idx += TCW) rec[25 + idx] = Xo[idx];
-  __syncthreads();
+  for (int idx = ln; idx < ce * ac; idx += TW) rec[25 + idx] = Xo[idx];
+  team_sync();
   // c's clique now has rows [absorbed; kcur]
-  tcw_store_lower<R>(Kc, Kcg, LDcg, ac + ck, ac + ck);
-  if (ln < ac + ck) ycg[ln] = yc[ln];
+  tcw_store_lower<R, TW>(Kc, Kcg, LDcg, ac + ck, ac + ck);
+  for (int r = ln; r < ac + ck; r += TW) ycg[r] = yc[r];
 }
 
 // Back-substitution of one clique's private rows: lambda = Lc^{-T} (z - X
 // lambda_b) (lambda_b: nb <= 10 boundary multipliers, the same in every
-// lane), with lane i holding row i, then written to the absorbed joints.
-template <int R>
+// lane), with lane i holding row i (np <= TW), then written to the absorbed
+// joints.
+template <int R, int TW>
 DEV void tcw_private_back(const TreeArgs &a, const GJoint *J, int v, int np, int nr,
                           const double *lb, int e_end, double *Ks) {
-  constexpr int LD = R + 1;
-  const int ln = lane();
+  const int ln = tlane<TW>();
   const int LDg = a.tne[v] + 5;
   const double *Kg = a.fac + a.foff[v];
   const double *yg = Kg + LDg * LDg;
   const int nb = nr - np;
-  tcw_load_lower<R>(Kg, LDg, Ks, nr);
+  tcw_load_lower<R, TW>(Kg, LDg, Ks, nr);
   double t = 0.0;
   if (ln < np) t = yg[ln];
-  __syncthreads();
+  team_sync();
   if (ln < np) {
 #pragma unroll
     for (int f = 0; f < 10; ++f)
-      if (f < nb) t -= Ks[(np + f) * LD + ln] * lb[f];
+      if (f < nb) t -= Ks[tri(np + f) + ln] * lb[f];
   }
   for (int l = np - 1; l >= 0; --l) {
-    if (ln == l) t /= Ks[l * LD + l];
-    const double tl = __shfl(t, l);
-    if (ln < l) t -= Ks[l * LD + ln] * tl;
+    if (ln == l) t /= Ks[tri(l) + l];
+    const double tl = __shfl(t, l, TW);
+    if (ln < l) t -= Ks[tri(l) + ln] * tl;
   }
   // write-out: lane e owns absorbed entry e
-  const TcwEnt en = tcw_entry(a, J, a.tabs_off[v], e_end);
+  const TcwEnt en = tcw_entry<TW>(a, J, a.tabs_off[v], e_end);
   double w[5];
 #pragma unroll
   for (int r = 0; r < 5; ++r) {
-    const double tv = __shfl(t, en.r0 + r < TCW ? en.r0 + r : 0);
+    const double tv = __shfl(t, en.r0 + r < TW ? en.r0 + r : 0, TW);
     w[r] = r < en.c ? tv : 0.0;
   }
   if (ln < e_end - a.tabs_off[v]) {
@@ -967,30 +970,36 @@ DEV void tcw_private_back(const TreeArgs &a, const GJoint *J, int v, int np, int
   }
 }
 
-template <int R>
-__global__ __launch_bounds__(TCW) void tcw_rake_back_kernel(TreeArgs a, const GJoint *J, int op0) {
-  __shared__ double Ks[R * (R + 1)];
+template <int R, int TW>
+__global__ __launch_bounds__(TCW) void tcw_rake_back_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
+  __shared__ double team_ks[TCW / TW][R * (R + 1) / 2];
   if (skip_step(a.status, a.step)) return;
-  const TcOp op = a.ops[op0 + blockIdx.x];
+  const int tm = (int)threadIdx.x / TW;
+  const int oi = op0 + (int)blockIdx.x * (TCW / TW) + tm;
+  if (oi >= op1) return;
+  const TcOp op = a.ops[oi];
   if (op.nv > R) {
-    if (threadIdx.x == 0) raise_flag(a.status, FLAG_GUARD, a.step);
+    if (tlane<TW>() == 0) raise_flag(a.status, FLAG_GUARD, a.step);
     return;
   }
   double lb[10];
 #pragma unroll
   for (int r = 0; r < 10; ++r) lb[r] = (r < op.ck) ? a.glam[5 * (int64_t)op.kcur + (r < 5 ? r : 0)] : 0.0;
-  tcw_private_back<R>(a, J, op.v, a.tne[op.v], op.nv, lb, a.tabs_off[op.v + 1], Ks);
+  tcw_private_back<R, TW>(a, J, op.v, a.tne[op.v], op.nv, lb, a.tabs_off[op.v + 1], team_ks[tm]);
 }
 
-template <int R>
-__global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, const GJoint *J, int op0) {
-  __shared__ double Ks[R * (R + 1)];
+template <int R, int TW>
+__global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, const GJoint *J, int op0,
+                                                               int op1) {
+  __shared__ double team_ks[TCW / TW][R * (R + 1) / 2];
   if (skip_step(a.status, a.step)) return;
-  const int ln = lane();
-  const TcOp op = a.ops[op0 + blockIdx.x];
+  const int ln = tlane<TW>(), tm = (int)threadIdx.x / TW;
+  const int oi = op0 + (int)blockIdx.x * (TCW / TW) + tm;
+  if (oi >= op1) return;
+  const TcOp op = a.ops[oi];
   const int ce = op.ce, ck = op.ck, cs = op.c;
   const int ac = a.tne[cs];
-  if (op.nv > R || ac > TCW) {
+  if (op.nv > R || ac > TW) {
     if (ln == 0) raise_flag(a.status, FLAG_GUARD, a.step);
     return;
   }
@@ -1001,11 +1010,11 @@ __global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, cons
   for (int r = 0; r < 5; ++r) lk[r] = r < ck ? a.glam[5 * (int64_t)op.kcur + r] : 0.0;
   // lambda_o of c's absorbed rows (solved later in the forward order): lane q
   // finds the entry that holds row q
-  const TcwEnt en = tcw_entry(a, J, a.tabs_off[cs], a.tabs_off[cs + 1]);
+  const TcwEnt en = tcw_entry<TW>(a, J, a.tabs_off[cs], a.tabs_off[cs + 1]);
   const int nent = a.tabs_off[cs + 1] - a.tabs_off[cs];
   int myk = 0, myw = 0;
   for (int e = 0; e < nent; ++e) {
-    const int r0 = __shfl(en.r0, e), c = __shfl(en.c, e), k = __shfl(en.k, e);
+    const int r0 = __shfl(en.r0, e, TW), c = __shfl(en.c, e, TW), k = __shfl(en.k, e, TW);
     if (ln >= r0 && ln < r0 + c) {
       myk = k;
       myw = ln - r0;
@@ -1017,7 +1026,7 @@ __global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, cons
 #pragma unroll
   for (int p = 0; p < 5; ++p) {
     double s = (p < ce && ln < ac) ? Xo[p * ac + ln] * lo : 0.0;
-    for (int o = TCW / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    for (int o = TW / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, TW);
     double v = 0.0;
     if (p < ce) {
       v = zr[p] - s;
@@ -1047,7 +1056,7 @@ __global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, cons
 #pragma unroll
     for (int r = 0; r < 10; ++r) lb[r] = r < 5 ? le[r] : lk[r - 5];
   }
-  tcw_private_back<R>(a, J, op.v, a.tne[op.v] - ce, op.nv, lb, a.tabs_off[op.v + 1] - 1, Ks);
+  tcw_private_back<R, TW>(a, J, op.v, a.tne[op.v] - ce, op.nv, lb, a.tabs_off[op.v + 1] - 1, team_ks[tm]);
 }
 
 // ------------------------------------------------------ (d) back-projection
@@ -1170,21 +1179,34 @@ void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, in
   if (m > 0)
     hipLaunchKernelGGL(gjoint_kernel, dim3((m + 127) / 128), dim3(128), 0, s, m, J, q, Rg, ns, hg, gl);
 }
+// operations of [o0, o1) with TW-lane teams, TCW / TW per workgroup
+static dim3 tcw_grid(int o0, int o1, int tw) { return dim3((unsigned)((o1 - o0 + TCW / tw - 1) / (TCW / tw))); }
+
 void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
                  hipStream_t s) {
   if (nslots <= 0) return;
   hipLaunchKernelGGL(tree_prep_kernel, dim3((nslots + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J, nslots);
-  // per round, 7 segments of the operation list (o[7] starts the next round): rakes with cliques of <= 16,
-  // <= 32, <= 64 rows, then compresses with cliques of <= 16, <= 32, <= 48
-  // rows and larger (team kernels on the global slots)
+  // per round, 7 segments of the operation list (o[7] starts the next round):
+  // rakes with cliques of <= 16, <= 32, <= 64 rows, then compresses with
+  // cliques of <= 16, <= 32, <= 48 rows and larger (team kernels on the
+  // global slots)
   for (int r = 0; r < nround; ++r) {
     const int32_t *o = rounds + 7 * r;
-    if (o[1] > o[0]) hipLaunchKernelGGL(tcw_rake_kernel<16>, dim3(o[1] - o[0]), dim3(TCW), 0, s, a, J, o[0]);
-    if (o[2] > o[1]) hipLaunchKernelGGL(tcw_rake_kernel<32>, dim3(o[2] - o[1]), dim3(TCW), 0, s, a, J, o[1]);
-    if (o[3] > o[2]) hipLaunchKernelGGL(tcw_rake_kernel<64>, dim3(o[3] - o[2]), dim3(TCW), 0, s, a, J, o[2]);
-    if (o[4] > o[3]) hipLaunchKernelGGL(tcw_compress_kernel<16>, dim3(o[4] - o[3]), dim3(TCW), 0, s, a, J, o[3]);
-    if (o[5] > o[4]) hipLaunchKernelGGL(tcw_compress_kernel<32>, dim3(o[5] - o[4]), dim3(TCW), 0, s, a, J, o[4]);
-    if (o[6] > o[5]) hipLaunchKernelGGL(tcw_compress_kernel<48>, dim3(o[6] - o[5]), dim3(TCW), 0, s, a, J, o[5]);
+    if (o[1] > o[0])
+      hipLaunchKernelGGL((tcw_rake_kernel<16, 16>), tcw_grid(o[0], o[1], 16), dim3(TCW), 0, s, a, J, o[0], o[1]);
+    if (o[2] > o[1])
+      hipLaunchKernelGGL((tcw_rake_kernel<32, 64>), tcw_grid(o[1], o[2], 64), dim3(TCW), 0, s, a, J, o[1], o[2]);
+    if (o[3] > o[2])
+      hipLaunchKernelGGL((tcw_rake_kernel<64, 64>), tcw_grid(o[2], o[3], 64), dim3(TCW), 0, s, a, J, o[2], o[3]);
+    if (o[4] > o[3])
+      hipLaunchKernelGGL((tcw_compress_kernel<16, 16>), tcw_grid(o[3], o[4], 16), dim3(TCW), 0, s, a, J, o[3],
+                         o[4]);
+    if (o[5] > o[4])
+      hipLaunchKernelGGL((tcw_compress_kernel<32, 64>), tcw_grid(o[4], o[5], 64), dim3(TCW), 0, s, a, J, o[4],
+                         o[5]);
+    if (o[6] > o[5])
+      hipLaunchKernelGGL((tcw_compress_kernel<48, 64>), tcw_grid(o[5], o[6], 64), dim3(TCW), 0, s, a, J, o[5],
+                         o[6]);
     if (o[7] > o[6])
       hipLaunchKernelGGL(tc_compress_kernel, dim3((o[7] - o[6] + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
                          o[6], o[7]);
@@ -1193,12 +1215,24 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
     const int32_t *o = rounds + 7 * r;
     if (o[7] > o[6])
       hipLaunchKernelGGL(tc_compress_back_kernel, dim3((o[7] - o[6] + 255) / 256), dim3(256), 0, s, a, J, o[6], o[7]);
-    if (o[6] > o[5]) hipLaunchKernelGGL(tcw_compress_back_kernel<48>, dim3(o[6] - o[5]), dim3(TCW), 0, s, a, J, o[5]);
-    if (o[5] > o[4]) hipLaunchKernelGGL(tcw_compress_back_kernel<32>, dim3(o[5] - o[4]), dim3(TCW), 0, s, a, J, o[4]);
-    if (o[4] > o[3]) hipLaunchKernelGGL(tcw_compress_back_kernel<16>, dim3(o[4] - o[3]), dim3(TCW), 0, s, a, J, o[3]);
-    if (o[3] > o[2]) hipLaunchKernelGGL(tcw_rake_back_kernel<64>, dim3(o[3] - o[2]), dim3(TCW), 0, s, a, J, o[2]);
-    if (o[2] > o[1]) hipLaunchKernelGGL(tcw_rake_back_kernel<32>, dim3(o[2] - o[1]), dim3(TCW), 0, s, a, J, o[1]);
-    if (o[1] > o[0]) hipLaunchKernelGGL(tcw_rake_back_kernel<16>, dim3(o[1] - o[0]), dim3(TCW), 0, s, a, J, o[0]);
+    if (o[6] > o[5])
+      hipLaunchKernelGGL((tcw_compress_back_kernel<48, 64>), tcw_grid(o[5], o[6], 64), dim3(TCW), 0, s, a, J,
+                         o[5], o[6]);
+    if (o[5] > o[4])
+      hipLaunchKernelGGL((tcw_compress_back_kernel<32, 64>), tcw_grid(o[4], o[5], 64), dim3(TCW), 0, s, a, J,
+                         o[4], o[5]);
+    if (o[4] > o[3])
+      hipLaunchKernelGGL((tcw_compress_back_kernel<16, 16>), tcw_grid(o[3], o[4], 16), dim3(TCW), 0, s, a, J,
+                         o[3], o[4]);
+    if (o[3] > o[2])
+      hipLaunchKernelGGL((tcw_rake_back_kernel<64, 64>), tcw_grid(o[2], o[3], 64), dim3(TCW), 0, s, a, J, o[2],
+                         o[3]);
+    if (o[2] > o[1])
+      hipLaunchKernelGGL((tcw_rake_back_kernel<32, 64>), tcw_grid(o[1], o[2], 64), dim3(TCW), 0, s, a, J, o[1],
+                         o[2]);
+    if (o[1] > o[0])
+      hipLaunchKernelGGL((tcw_rake_back_kernel<16, 16>), tcw_grid(o[0], o[1], 16), dim3(TCW), 0, s, a, J, o[0],
+                         o[1]);
   }
 }
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,
