@@ -216,7 +216,6 @@ DEV void team_sync() {
 // factors.
 struct PrepLds {
   double L[TREE_KLDS * 12];
-  double Y[12 * TREE_KLDS];
   int ek[24];               // clique entries: joint,
   int ei[24];               // first row << 8 | rows << 4 | unary << 1 | side
   uint8_t rowent[TREE_KMAX];  // clique row -> entry
@@ -271,7 +270,7 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   double *fac = a.fac + a.foff[slot];  // LD*LD K, LD y, then (big cliques) L, Y
   const bool big = nr > TREE_KLDS;
   double *Lm = big ? fac + LD * LD + LD : S.L;
-  double *Ym = big ? fac + LD * LD + LD + 12 * nr : S.Y;
+  double *Ym = fac + LD * LD + LD + 12 * nr;  // large cliques only
   //    clique rows L (nr x 12), four independent loads per lane in flight
   for (int base = 0; base < nr * 12; base += 4 * TEAM) {
     double v[4];
@@ -289,24 +288,40 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
     }
   }
   team_sync();
-  // 2) Y = Hbar^{-1} L^T, one clique row per lane
-  for (int col = ln; col < nr; col += TEAM) {
-    double yv[12];
-    hinv_apply(Th, Lm + 12 * col, yv);
-    for (int s = 0; s < 12; ++s) Ym[s * nr + col] = yv[s];
+  if (!big) {
+    // 2-3) K0 = L Hbar^{-1} L^T (lower triangle): lane j holds
+    //      y_j = Hbar^{-1} L_j^T in registers and forms column j
+    if (ln < nr) {
+      double yv[12];
+      hinv_apply(Th, Lm + 12 * ln, yv);
+      for (int i = ln; i < nr; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * yv[s];
+        fac[i * LD + ln] = v;
+      }
+    }
+  } else {
+    // 2) Y = Hbar^{-1} L^T, one clique row per lane
+    for (int col = ln; col < nr; col += TEAM) {
+      double yv[12];
+      hinv_apply(Th, Lm + 12 * col, yv);
+      for (int s = 0; s < 12; ++s) Ym[s * nr + col] = yv[s];
+    }
+    team_sync();
+    // 3) K0 = L Y (lower triangle)
+    for (int idx = ln; idx < nr * (nr + 1) / 2; idx += TEAM) {
+      // lower-triangle entry idx -> (i, jj), jj <= i (only the lower triangle is ever read)
+      int i = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+      while (i * (i + 1) / 2 > idx) --i;
+      while ((i + 1) * (i + 2) / 2 <= idx) ++i;
+      const int jj = idx - i * (i + 1) / 2;
+      double v = 0.0;
+      for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * Ym[s * nr + jj];
+      fac[i * LD + jj] = v;
+    }
   }
-  team_sync();
-  // 3) K0 = L Y (lower triangle), y0 = L u + C of one-sided and parent rows
-  for (int idx = ln; idx < nr * (nr + 1) / 2; idx += TEAM) {
-    // lower-triangle entry idx -> (i, jj), jj <= i (only the lower triangle is ever read)
-    int i = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
-    while (i * (i + 1) / 2 > idx) --i;
-    while ((i + 1) * (i + 2) / 2 <= idx) ++i;
-    const int jj = idx - i * (i + 1) / 2;
-    double v = 0.0;
-    for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * Ym[s * nr + jj];
-    fac[i * LD + jj] = v;
-  }
+  //    y0 = L u + C of one-sided and parent rows
   for (int i = ln; i < nr; i += TEAM) {
     double v = 0.0;
     for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * a.u[s * a.ns + b];
