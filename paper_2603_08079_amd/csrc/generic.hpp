@@ -26,8 +26,13 @@ enum { GL_C = 0, GL_LA = 8, GL_LB = 68 };
 constexpr int GT_STRIDE = 64;
 enum { GT_SIG = 0, GT_RHO = 25, GT_A = 30, GT_E = 35 };
 
-// absorbed-joint entry of a tree body: joint index << 2 | side << 1 | unary
-inline int32_t abs_pack(int32_t k, int side, int unary) { return (k << 2) | (side << 1) | unary; }
+// absorbed-joint entry of a tree body: joint index << 3 | hinge << 2 | side << 1
+// | unary (the hinge bit gives the joint's rows, 5 or 3, without a lookup)
+inline int32_t abs_pack(int32_t k, int hinge, int side, int unary) {
+  return (k << 3) | (hinge << 2) | (side << 1) | unary;
+}
+__host__ __device__ inline int abs_joint(int32_t t) { return t >> 3; }
+__host__ __device__ inline int abs_rows(int32_t t) { return (t & 4) ? 5 : 3; }
 
 constexpr int TEAM = 16;              // lanes per body in the tree elimination
 constexpr int TREE_KLDS = 16;         // cliques up to this many rows are factored in LDS
@@ -69,7 +74,11 @@ struct TcOp {
   int32_t kcur, ck;  // current parent joint of v (generic index, -1 at a root) and its rows
   int32_t e, ce;     // compress: joint v-c and its rows
   int32_t nv;        // current rows of v's clique (absorbed + ck)
+  int32_t av, ac;    // absorbed rows of v and (compress) of c
+  int32_t ev0, ev1;  // v's absorbed list [ev0, ev1) in tabs
+  int32_t ec0, ec1;  // compress: c's absorbed list
   int32_t pad;
+  int64_t fv, fc;    // factor slot offsets of v and (compress) c
   int64_t rec;       // compress: offset of (Lp 5x5, X_o ce x a_c, X_k 5x5, z 5) in crec
 };
 

@@ -239,18 +239,21 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   //    fetched in parallel; their rows and the row -> entry map
   for (int e = ln; e < nent; e += TEAM) {
     int k, side, un;
+    int rows;
     if (e < e1 - e0) {
       const int t = a.tabs[e0 + e];
-      k = t >> 2;
+      k = abs_joint(t);
+      rows = abs_rows(t);
       side = (t >> 1) & 1;
       un = t & 1;
     } else {
       k = kpar;
+      rows = J[k].type ? 5 : 3;
       side = pk & 1;
       un = 1;  // parent rows take C_k only
     }
     S.ek[e] = k;
-    S.ei[e] = ((J[k].type ? 5 : 3) << 4) | (un << 1) | side;
+    S.ei[e] = (rows << 4) | (un << 1) | side;
   }
   team_sync();
   if (ln == 0) {
@@ -341,8 +344,8 @@ DEV void tc_add_children(const TreeArgs &a, const GJoint *J, int e0, int e1, dou
                          int ln) {
   int r0 = 0;
   for (int e = e0; e < e1; ++e) {
-    const int k = a.tabs[e] >> 2;
-    const int c = J[k].type ? 5 : 3;
+    const int k = abs_joint(a.tabs[e]);
+    const int c = abs_rows(a.tabs[e]);
     if (!(a.tabs[e] & 1)) {
       const double *gtk = a.gt + (int64_t)GT_STRIDE * k;
       for (int idx = ln; idx < c * c; idx += TEAM) {
@@ -539,8 +542,8 @@ DEV void tc_private_back(const TreeArgs &a, const GJoint *J, int v, int np, int 
   }
   int r0 = 0;
   for (int e = a.tabs_off[v]; e < e_end; ++e) {
-    const int k = a.tabs[e] >> 2;
-    const int c = J[k].type ? 5 : 3;
+    const int k = abs_joint(a.tabs[e]);
+    const int c = abs_rows(a.tabs[e]);
     for (int i = 0; i < c; ++i) a.glam[5 * (int64_t)k + i] = t[r0 + i];
     for (int i = c; i < 5; ++i) a.glam[5 * (int64_t)k + i] = 0.0;
     r0 += c;
@@ -571,8 +574,8 @@ __global__ __launch_bounds__(256) void tc_compress_back_kernel(TreeArgs a, const
   {
     int r0 = 0;
     for (int e = a.tabs_off[cs]; e < a.tabs_off[cs + 1]; ++e) {
-      const int k = a.tabs[e] >> 2;
-      const int c = J[k].type ? 5 : 3;
+      const int k = abs_joint(a.tabs[e]);
+      const int c = abs_rows(a.tabs[e]);
       for (int r = 0; r < c; ++r) lo[r0 + r] = a.glam[5 * (int64_t)k + r];
       r0 += c;
     }
@@ -673,9 +676,9 @@ DEV TcwEnt tcw_entry(const TreeArgs &a, const GJoint *J, int e0, int e1) {
   const int ln = tlane<TW>();
   if (ln < e1 - e0) {
     const int tab = a.tabs[e0 + ln];
-    t.k = tab >> 2;
+    t.k = abs_joint(tab);
     t.unary = tab & 1;
-    t.c = J[t.k].type ? 5 : 3;
+    t.c = abs_rows(tab);
   }
   int x = t.c;  // inclusive prefix over the team
   for (int o = 1; o < TW; o <<= 1) {
@@ -768,14 +771,13 @@ __global__ __launch_bounds__(TCW) void tcw_rake_kernel(TreeArgs a, const GJoint 
     if (ln == 0) raise_flag(a.status, FLAG_GUARD, a.step);
     return;
   }
-  const int v = op.v;
-  const int ne = a.tne[v], LDg = ne + 5, nr = op.nv;
-  double *Kg = a.fac + a.foff[v];
+  const int ne = op.av, LDg = ne + 5, nr = op.nv;
+  double *Kg = a.fac + op.fv;
   double *yg = Kg + LDg * LDg;
   tcw_load_lower<R, TW>(Kg, LDg, sm.K, nr);
   for (int r = ln; r < nr; r += TW) sm.y[r] = yg[r];
   team_sync();
-  tcw_add_children<R, TW>(a, J, a.tabs_off[v], a.tabs_off[v + 1], sm.K, sm.y);
+  tcw_add_children<R, TW>(a, J, op.ev0, op.ev1, sm.K, sm.y);
   team_sync();
   tcw_partial_cholesky<R, TW>(a, sm.K, sm.y, nr, ne);
   if (op.kcur >= 0) {
@@ -806,16 +808,16 @@ __global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJo
   if (oi >= op1) return;
   TcwComp<R> &sm = team_sm[tm];
   const TcOp op = a.ops[oi];
-  const int v = op.v, cs = op.c, ce = op.ce, ck = op.ck;
-  const int av = a.tne[v], LDvg = av + 5, pv = av - ce, nb = ce + ck, nv = op.nv;
-  const int ac = a.tne[cs], LDcg = ac + 5;
+  const int ce = op.ce, ck = op.ck;
+  const int av = op.av, LDvg = av + 5, pv = av - ce, nv = op.nv;
+  const int ac = op.ac, LDcg = ac + 5;
   if (nv > R || ac + (ce > ck ? ce : ck) > R) {  // the host sorts operations by clique size
     if (ln == 0) raise_flag(a.status, FLAG_GUARD, a.step);
     return;
   }
-  double *Kvg = a.fac + a.foff[v];
+  double *Kvg = a.fac + op.fv;
   double *yvg = Kvg + LDvg * LDvg;
-  double *Kcg = a.fac + a.foff[cs];
+  double *Kcg = a.fac + op.fc;
   double *ycg = Kcg + LDcg * LDcg;
   double *Kv = sm.v.K, *yv = sm.v.y, *Kc = sm.c.K, *yc = sm.c.y;
   // boundary Schur complement of v on [e; kcur] (read in place, symmetric)
@@ -827,7 +829,7 @@ __global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJo
   for (int r = ln; r < nv; r += TW) yv[r] = yvg[r];
   for (int r = ln; r < ac + ce; r += TW) yc[r] = ycg[r];
   team_sync();
-  tcw_add_children<R, TW>(a, J, a.tabs_off[v], a.tabs_off[v + 1] - 1, Kv, yv);
+  tcw_add_children<R, TW>(a, J, op.ev0, op.ev1 - 1, Kv, yv);
   team_sync();
   tcw_partial_cholesky<R, TW>(a, Kv, yv, nv, pv);
   tcw_store_lower<R, TW>(Kv, Kvg, LDvg, nv, pv);
@@ -950,11 +952,12 @@ __global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJo
 // lane), with lane i holding row i (np <= TW), then written to the absorbed
 // joints.
 template <int R, int TW>
-DEV void tcw_private_back(const TreeArgs &a, const GJoint *J, int v, int np, int nr,
-                          const double *lb, int e_end, double *Ks) {
+DEV void tcw_private_back(const TreeArgs &a, const GJoint *J, const TcOp &op, int np, const double *lb,
+                          int e_end, double *Ks) {
   const int ln = tlane<TW>();
-  const int LDg = a.tne[v] + 5;
-  const double *Kg = a.fac + a.foff[v];
+  const int nr = op.nv, e_beg = op.ev0;
+  const int LDg = op.av + 5;
+  const double *Kg = a.fac + op.fv;
   const double *yg = Kg + LDg * LDg;
   const int nb = nr - np;
   tcw_load_lower<R, TW>(Kg, LDg, Ks, nr);
@@ -972,14 +975,14 @@ DEV void tcw_private_back(const TreeArgs &a, const GJoint *J, int v, int np, int
     if (ln < l) t -= Ks[tri(l) + ln] * tl;
   }
   // write-out: lane e owns absorbed entry e
-  const TcwEnt en = tcw_entry<TW>(a, J, a.tabs_off[v], e_end);
+  const TcwEnt en = tcw_entry<TW>(a, J, e_beg, e_end);
   double w[5];
 #pragma unroll
   for (int r = 0; r < 5; ++r) {
     const double tv = __shfl(t, en.r0 + r < TW ? en.r0 + r : 0, TW);
     w[r] = r < en.c ? tv : 0.0;
   }
-  if (ln < e_end - a.tabs_off[v]) {
+  if (ln < e_end - e_beg) {
 #pragma unroll
     for (int r = 0; r < 5; ++r) a.glam[5 * (int64_t)en.k + r] = w[r];
   }
@@ -1000,7 +1003,7 @@ __global__ __launch_bounds__(TCW) void tcw_rake_back_kernel(TreeArgs a, const GJ
   double lb[10];
 #pragma unroll
   for (int r = 0; r < 10; ++r) lb[r] = (r < op.ck) ? a.glam[5 * (int64_t)op.kcur + (r < 5 ? r : 0)] : 0.0;
-  tcw_private_back<R, TW>(a, J, op.v, a.tne[op.v], op.nv, lb, a.tabs_off[op.v + 1], team_ks[tm]);
+  tcw_private_back<R, TW>(a, J, op, op.av, lb, op.ev1, team_ks[tm]);
 }
 
 template <int R, int TW>
@@ -1012,8 +1015,8 @@ __global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, cons
   const int oi = op0 + (int)blockIdx.x * (TCW / TW) + tm;
   if (oi >= op1) return;
   const TcOp op = a.ops[oi];
-  const int ce = op.ce, ck = op.ck, cs = op.c;
-  const int ac = a.tne[cs];
+  const int ce = op.ce, ck = op.ck;
+  const int ac = op.ac;
   if (op.nv > R || ac > TW) {
     if (ln == 0) raise_flag(a.status, FLAG_GUARD, a.step);
     return;
@@ -1025,8 +1028,8 @@ __global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, cons
   for (int r = 0; r < 5; ++r) lk[r] = r < ck ? a.glam[5 * (int64_t)op.kcur + r] : 0.0;
   // lambda_o of c's absorbed rows (solved later in the forward order): lane q
   // finds the entry that holds row q
-  const TcwEnt en = tcw_entry<TW>(a, J, a.tabs_off[cs], a.tabs_off[cs + 1]);
-  const int nent = a.tabs_off[cs + 1] - a.tabs_off[cs];
+  const TcwEnt en = tcw_entry<TW>(a, J, op.ec0, op.ec1);
+  const int nent = op.ec1 - op.ec0;
   int myk = 0, myw = 0;
   for (int e = 0; e < nent; ++e) {
     const int r0 = __shfl(en.r0, e, TW), c = __shfl(en.c, e, TW), k = __shfl(en.k, e, TW);
@@ -1071,7 +1074,7 @@ __global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, cons
 #pragma unroll
     for (int r = 0; r < 10; ++r) lb[r] = r < 5 ? le[r] : lk[r - 5];
   }
-  tcw_private_back<R, TW>(a, J, op.v, a.tne[op.v] - ce, op.nv, lb, a.tabs_off[op.v + 1] - 1, team_ks[tm]);
+  tcw_private_back<R, TW>(a, J, op, op.av - ce, lb, op.ev1 - 1, team_ks[tm]);
 }
 
 // ------------------------------------------------------ (d) back-projection

@@ -733,10 +733,10 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
           const int side = Jn->a[k] == b ? 0 : 1;
           const bool unary = !dyn(Jn->a[k]) || !dyn(Jn->b[k]);
           if (unary) unary_rows += Jn->type[k] ? 5 : 3;
-          c->tabs.push_back(abs_pack(gidx[k], side, unary ? 1 : 0));
+          c->tabs.push_back(abs_pack(gidx[k], Jn->type[k] ? 1 : 0, side, unary ? 1 : 0));
         }
         int ne = 0;
-        for (int e = c->tabs_off.back(); e < (int)c->tabs.size(); ++e) ne += Jn->type[c->gj_in[c->tabs[e] >> 2]] ? 5 : 3;
+        for (int e = c->tabs_off.back(); e < (int)c->tabs.size(); ++e) ne += abs_rows(c->tabs[e]);
         const int nr = ne + (pk >= 0 ? (Jn->type[parent_joint[b]] ? 5 : 3) : 0);
         if (nr > TREE_KMAX) {
           delete c;
@@ -824,7 +824,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
         // the live child's joint goes last in v's absorbed list
         int e0 = c->tabs_off[s], e1 = c->tabs_off[s + 1];
         for (int e = e0; e < e1; ++e)
-          if ((c->tabs[e] >> 2) == op.e && !(c->tabs[e] & 1)) {
+          if (abs_joint(c->tabs[e]) == op.e && !(c->tabs[e] & 1)) {
             std::swap(c->tabs[e], c->tabs[e1 - 1]);
             break;
           }
@@ -858,6 +858,19 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       const int nr0 = c->tne[s] + (pk >= 0 ? (Jn->type[c->gj_in[pk >> 1]] ? 5 : 3) : 0);
       c->foff.push_back(c->fac_size);
       c->fac_size += (int64_t)LD * LD + LD + (nr0 > TREE_KLDS ? 24 * (int64_t)nr0 : 0);
+    }
+    // what the kernels would otherwise look up per operation
+    for (TcOp &op : c->tc_ops) {
+      op.av = c->tne[op.v];
+      op.ev0 = c->tabs_off[op.v];
+      op.ev1 = c->tabs_off[op.v + 1];
+      op.fv = c->foff[op.v];
+      if (op.c >= 0) {
+        op.ac = c->tne[op.c];
+        op.ec0 = c->tabs_off[op.c];
+        op.ec1 = c->tabs_off[op.c + 1];
+        op.fc = c->foff[op.c];
+      }
     }
   }
   // graph components: bodies after the trees, solved by PCG
