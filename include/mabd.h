@@ -44,7 +44,7 @@ typedef enum {
   MABD_OK = 0,
   MABD_ERR_INVALID_ARG = -1,  /* bad index, size, non-finite input, bad option   */
   MABD_ERR_TOPOLOGY = -2,     /* joint graph the library cannot solve            */
-  MABD_ERR_DEVICE = -3,       /* HIP runtime error                               */
+  MABD_ERR_DEVICE = -3,       /* HIP runtime error, or a kernel's internal size check   */
   MABD_ERR_OOM = -4,          /* device allocation failed                        */
   MABD_ERR_NONFINITE = -5,    /* non-finite state or det A <= 0 during a step    */
   MABD_ERR_NOT_CONVERGED = -6,/* PCG reached max_iters, or precision-1 refinement ran

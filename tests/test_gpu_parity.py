@@ -329,3 +329,72 @@ def test_full_size_tree_one_step():
     say("kkt of GPU multipliers", dv[:3])
     assert eq < TOL and eqd < TOL_V_TREE
     assert dv[oracle.KKT] <= max(10 * d[oracle.KKT], 1e-11)
+
+
+def part_of(asm, b0, b1):
+    """Bodies [b0, b1) of an assembly of independent parts, with their joints
+    (indices shifted), as an assembly of its own."""
+    import dataclasses
+
+    jm = ((asm.ja >= b0) & (asm.ja < b1)) | ((asm.jb >= b0) & (asm.jb < b1))
+    shift = lambda x: np.where(x >= 0, x - b0, -1).astype(np.int32)
+    return dataclasses.replace(
+        asm, name=f"{asm.name}[{b0}:{b1}]", dims=asm.dims[b0:b1], density=asm.density[b0:b1],
+        k_orth=asm.k_orth[b0:b1], pinned=asm.pinned[b0:b1], q0=asm.q0[b0:b1], qd0=asm.qd0[b0:b1],
+        poisson=None if asm.poisson is None else asm.poisson[b0:b1], jtype=asm.jtype[jm],
+        ja=shift(asm.ja[jm]), jb=shift(asm.jb[jm]), pa=asm.pa[jm], pb=asm.pb[jm], axis=asm.axis[jm],
+        cp_len=asm.cp_len[jm], meta={})
+
+
+def test_full_size_batch_one_step():
+    """The 4,096-assembly batch (2.95M bodies, chains and trees, ball/hinge
+    50/50) at full size, in the launch configuration the benchmark times (one
+    context, graph replay): the FP64 KKT residual of the GPU multipliers over
+    the whole batch, and nine assemblies (the smallest, the largest, the
+    largest tree, the first four and two drawn at random) body by body against
+    the oracle's own step of that assembly alone."""
+    asm = mi.config("batch4096")
+    say("batch4096 full size", asm.n, asm.m)
+    ctx = ctx_of(asm)
+    ctx.step(asm.h, 1)
+    assert ctx.stats()["graph_replay"] == 1
+    qg, qdg = ctx.state()
+    lam_g = ctx.multipliers()
+    ctx.close()
+    s = oracle.System(asm)
+    _, _, dv = s.finish(asm.h, asm.q0, asm.qd0, lam_g)
+    say("kkt of GPU multipliers over the batch", dv[:3])
+    sizes = np.asarray(asm.meta["sizes"])
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    tree_sizes = np.where(np.asarray(asm.meta["chain"]), -1, sizes)
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), int(np.argmax(tree_sizes)), 0, 1, 2, 3,
+                    *np.random.default_rng(49).choice(len(sizes), 2, replace=False).tolist()})
+    worst_kkt = 0.0
+    for i in picks:
+        sub = part_of(asm, off[i], off[i + 1])
+        sp = oracle.System(sub)
+        q1, qd1, lam, d = reference_step(sp, sub, sub.q0, sub.qd0, oracle.AUTO)
+        eq, eqd = state_errors(qg[off[i]:off[i + 1]], qdg[off[i]:off[i + 1]], q1, qd1)
+        worst_kkt = max(worst_kkt, d[oracle.KKT])
+        say(f"  part {i} ({'chain' if asm.meta['chain'][i] else 'tree'}, {sub.n} bodies): errors", eq, eqd,
+            "oracle kkt", d[oracle.KKT])
+        assert eq < TOL and eqd < TOL_V_TREE, (i, eq, eqd)
+    assert dv[oracle.KKT] <= max(10 * worst_kkt, 1e-11)
+
+
+def test_full_size_lattice_one_step():
+    """The 512 x 512 lattice (522,753 ball joints closing loops) at full size:
+    one cold-start PCG step to 1e-10; the oracle's FP64 dual residual of the
+    GPU multipliers must be at that tolerance (a direct factorisation of this
+    system is too large to serve as the reference state)."""
+    asm = mi.config("lattice512")
+    say("lattice512 full size", asm.n, asm.m)
+    ctx = ctx_of(asm, kkt_tol=1e-10, warm_start=0)
+    ctx.step(asm.h, 1)
+    st = ctx.stats()
+    lam_g = ctx.multipliers()
+    ctx.close()
+    s = oracle.System(asm)
+    _, _, dv = s.finish(asm.h, asm.q0, asm.qd0, lam_g)
+    say("pcg iterations", st["pcg_iters"], "kkt of GPU multipliers", dv[:3])
+    assert dv[oracle.RHO_D] <= 2e-10 and dv[oracle.RHO_P] <= 1e-12
