@@ -670,12 +670,17 @@ DEV void tcw_store_lower(const double *src, double *dst, int ld, int nr, int nco
 struct TcwEnt {
   int k, c, r0, unary;
 };
+// the lane's entry word (issued early: nothing waits on it until used)
 template <int TW>
-DEV TcwEnt tcw_entry(const TreeArgs &a, const GJoint *J, int e0, int e1) {
+DEV int tcw_tab(const TreeArgs &a, int e0, int e1) {
+  const int ln = tlane<TW>();
+  return ln < e1 - e0 ? a.tabs[e0 + ln] : 0;
+}
+template <int TW>
+DEV TcwEnt tcw_entry_of(int tab, int nent) {
   TcwEnt t{0, 0, 0, 1};
   const int ln = tlane<TW>();
-  if (ln < e1 - e0) {
-    const int tab = a.tabs[e0 + ln];
+  if (ln < nent) {
     t.k = abs_joint(tab);
     t.unary = tab & 1;
     t.c = abs_rows(tab);
@@ -688,13 +693,17 @@ DEV TcwEnt tcw_entry(const TreeArgs &a, const GJoint *J, int e0, int e1) {
   t.r0 = x - t.c;
   return t;
 }
+template <int TW>
+DEV TcwEnt tcw_entry(const TreeArgs &a, const GJoint *J, int e0, int e1) {
+  return tcw_entry_of<TW>(tcw_tab<TW>(a, e0, e1), e1 - e0);
+}
 
 // add the condensed far sides of the list's non-unary joints; each lane
 // adds its own entry's diagonal block (all loads in flight at once)
 template <int R, int TW>
-DEV void tcw_add_children(const TreeArgs &a, const GJoint *J, int e0, int e1, double *K, double *y) {
-  const TcwEnt t = tcw_entry<TW>(a, J, e0, e1);
-  if (tlane<TW>() < e1 - e0 && !t.unary) {
+DEV void tcw_add_children(const TreeArgs &a, int tab, int nent, double *K, double *y) {
+  const TcwEnt t = tcw_entry_of<TW>(tab, nent);
+  if (tlane<TW>() < nent && !t.unary) {
     const double *g = a.gt + (int64_t)GT_STRIDE * t.k;
     double sg[25], rh[5];
 #pragma unroll
@@ -774,10 +783,11 @@ __global__ __launch_bounds__(TCW) void tcw_rake_kernel(TreeArgs a, const GJoint 
   const int ne = op.av, LDg = ne + 5, nr = op.nv;
   double *Kg = a.fac + op.fv;
   double *yg = Kg + LDg * LDg;
+  const int tab = tcw_tab<TW>(a, op.ev0, op.ev1);
   tcw_load_lower<R, TW>(Kg, LDg, sm.K, nr);
   for (int r = ln; r < nr; r += TW) sm.y[r] = yg[r];
   team_sync();
-  tcw_add_children<R, TW>(a, J, op.ev0, op.ev1, sm.K, sm.y);
+  tcw_add_children<R, TW>(a, tab, op.ev1 - op.ev0, sm.K, sm.y);
   team_sync();
   tcw_partial_cholesky<R, TW>(a, sm.K, sm.y, nr, ne);
   if (op.kcur >= 0) {
@@ -824,12 +834,13 @@ __global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJo
   auto Mv = [&](int r, int s) { return r >= s ? Kv[tri(pv + r) + pv + s] : Kv[tri(pv + s) + pv + r]; };
   // 1) v: condensed children except the live child (last entry), private
   //    rows factored; boundary rows [e; kcur] remain
+  const int tab = tcw_tab<TW>(a, op.ev0, op.ev1 - 1);
   tcw_load_lower<R, TW>(Kvg, LDvg, Kv, nv);
   tcw_load_lower<R, TW>(Kcg, LDcg, Kc, ac + ce);
   for (int r = ln; r < nv; r += TW) yv[r] = yvg[r];
   for (int r = ln; r < ac + ce; r += TW) yc[r] = ycg[r];
   team_sync();
-  tcw_add_children<R, TW>(a, J, op.ev0, op.ev1 - 1, Kv, yv);
+  tcw_add_children<R, TW>(a, tab, op.ev1 - 1 - op.ev0, Kv, yv);
   team_sync();
   tcw_partial_cholesky<R, TW>(a, Kv, yv, nv, pv);
   tcw_store_lower<R, TW>(Kv, Kvg, LDvg, nv, pv);
@@ -960,6 +971,7 @@ DEV void tcw_private_back(const TreeArgs &a, const GJoint *J, const TcOp &op, in
   const double *Kg = a.fac + op.fv;
   const double *yg = Kg + LDg * LDg;
   const int nb = nr - np;
+  const int tab = tcw_tab<TW>(a, e_beg, e_end);
   tcw_load_lower<R, TW>(Kg, LDg, Ks, nr);
   double t = 0.0;
   if (ln < np) t = yg[ln];
@@ -975,7 +987,7 @@ DEV void tcw_private_back(const TreeArgs &a, const GJoint *J, const TcOp &op, in
     if (ln < l) t -= Ks[tri(l) + ln] * tl;
   }
   // write-out: lane e owns absorbed entry e
-  const TcwEnt en = tcw_entry<TW>(a, J, e_beg, e_end);
+  const TcwEnt en = tcw_entry_of<TW>(tab, e_end - e_beg);
   double w[5];
 #pragma unroll
   for (int r = 0; r < 5; ++r) {
