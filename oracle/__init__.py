@@ -55,6 +55,7 @@ class _Sys(ctypes.Structure):
         ("gravity", ctypes.c_double * 3),
         ("material", ctypes.c_int32), ("hinge_grad", ctypes.c_int32),
         ("newton_iters", ctypes.c_int32),
+        ("wrench", ctypes.c_void_p),
     ]
 
 
@@ -101,7 +102,7 @@ class System:
     """Holds contiguous copies of an assembly's arrays and the C struct."""
 
     def __init__(self, asm, material: Optional[int] = None, hinge_grad: int = 0,
-                 newton_iters: int = 1, gravity=None):
+                 newton_iters: int = 1, gravity=None, wrench=None):
         c = np.ascontiguousarray
         self.n, self.m = asm.n, asm.m
         self.dims = c(asm.dims, np.float64)
@@ -117,10 +118,12 @@ class System:
         self.pb = c(asm.pb, np.float64)
         self.axis = c(asm.axis, np.float64)
         self.cp_len = c(asm.cp_len, np.float64)
+        # external wrench per body [tau; f] (world frame, about the COM), or None
+        self.wrench = None if wrench is None else c(np.asarray(wrench, np.float64).reshape(self.n, 6))
         s = _Sys()
         s.n, s.m = self.n, self.m
         for f in ("dims", "density", "k_orth", "poisson", "pinned", "q0", "jtype", "ja", "jb",
-                  "pa", "pb", "axis", "cp_len"):
+                  "pa", "pb", "axis", "cp_len", "wrench"):
             setattr(s, f, _p(getattr(self, f)))
         g = asm.gravity if gravity is None else gravity
         s.gravity[0], s.gravity[1], s.gravity[2] = g
@@ -214,7 +217,7 @@ def polar(A):
 def run(asm, steps=None, solver=AUTO, **kw):
     """Integrate `steps` steps from the assembly's initial state."""
     sysm = System(asm, **{k: v for k, v in kw.items() if k in ("material", "hinge_grad",
-                                                                "newton_iters", "gravity")})
+                                                                "newton_iters", "gravity", "wrench")})
     q, qd = asm.q0.copy(), asm.qd0.copy()
     diags = []
     for _ in range(asm.steps if steps is None else steps):

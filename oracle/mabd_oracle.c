@@ -12,7 +12,8 @@
  *     decomposition of A^T A, the co-rotated Hessian H = diag4(R) Hbar diag4(R^T)
  *     (Eq. reduced_newton), and the force f_A = -grad E at the current iterate
  *     (Eq. variation_energy with implicit Euler), elastic part evaluated in the
- *     rotated frame (Eq. reduced_K);
+ *     rotated frame (Eq. reduced_K), plus external wrenches mapped by
+ *     f_A,ext = G(A)^T W (Eqs. module1-G-twist, module1-wrench-map);
  *   per joint (Sec. 4): ball rows (Eq. ball) and 5-row hinge rows (Eq. hinge)
  *     with the gradient of Eqs. constraint_gradient, pcpq, pcpr, r_gradient
  *     (R approximated by A in the rotation term);
@@ -269,11 +270,27 @@ static int body_terms_at(const ora_system *s, double h, const double *qi, const 
     for (int c = 0; c < 3; ++c)
       P[r * 3 + c] = mu * (Sym[r * 3 + c] + Sym[c * 3 + r] - 2.0 * (r == c)) + lam * tr * (r == c);
   mm(3, 3, 3, R, P, F);
+  /* external wrench W = [tau; f] at the current iterate: G(A) maps qdot to the
+     twist [omega; v] with omega = 1/2 sum_c q_c x qdot_c and v = tdot (Eq.
+     module1-G-twist), so G(A)^T W puts 1/2 [q_c]_x^T tau = 1/2 tau x q_c on
+     column c of A and f on the translation */
+  double gw[12];
+  memset(gw, 0, sizeof gw);
+  if (s->wrench) {
+    const double *tau = s->wrench + 6 * i, *fw = tau + 3;
+    for (int c = 0; c < 3; ++c) {
+      const double *qc = qi + 3 * c;
+      gw[3 * c + 0] = 0.5 * (tau[1] * qc[2] - tau[2] * qc[1]);
+      gw[3 * c + 1] = 0.5 * (tau[2] * qc[0] - tau[0] * qc[2]);
+      gw[3 * c + 2] = 0.5 * (tau[0] * qc[1] - tau[1] * qc[0]);
+    }
+    for (int r = 0; r < 3; ++r) gw[9 + r] = fw[r];
+  }
   for (int a = 0; a < 12; ++a) {
     int c = a / 3, r = a % 3;
     double M = Mbar[c];
     double fel = (c < 3) ? -V * F[r * 3 + c] : 0.0;
-    double fext = (c == 3) ? m * s->gravity[r] : 0.0;
+    double fext = ((c == 3) ? m * s->gravity[r] : 0.0) + gw[a];
     f[a] = M * qdn[a] / h - M * (qi[a] - qn[a]) / (h * h) + fext + fel;
   }
   for (int a = 0; a < 144; ++a)

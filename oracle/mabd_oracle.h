@@ -33,6 +33,9 @@ typedef struct {
   int32_t material;        /* 0: mu = 4 k_A, lambda = 0 ; 1: Lame from (E, nu)     */
   int32_t hinge_grad;      /* 0: frozen frame + A-linearized rotation term; 2: frozen only */
   int32_t newton_iters;    /* >= 1                                                 */
+  const double *wrench;    /* n*6 external spatial wrench [tau; f] per body, world
+                              frame, about the COM (Eq. module1-wrench-map); NULL:
+                              none                                                 */
 } ora_system;
 
 /* diag[] slots written by ora_step / ora_finish */

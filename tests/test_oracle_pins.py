@@ -48,6 +48,71 @@ def test_free_fall_closed_form():
         assert np.allclose(qdd[0, :9], 0.0, atol=1e-12)
 
 
+def test_wrench_force_closed_form():
+    """A force f at the COM of an unjointed box (wrench [0; f], Eq.
+    module1-wrench-map) adds f / m to gravity in the implicit Euler closed form
+    of test_free_fall_closed_form, and turns nothing."""
+    A0 = rot([2, -1, 1], 0.4)
+    v0 = np.array([0.5, 0.2, -0.3])
+    qd = np.zeros(12); qd[9:] = v0
+    dims = (0.3, 0.2, 0.1)
+    body = mi.free_body(dims=dims, A=A0, t=(0.0, 1.0, 2.0), qd=qd)
+    f = np.array([3.0, -7.0, 11.0])
+    m = 1000.0 * np.prod(dims)
+    s = oracle.System(body, wrench=np.concatenate([np.zeros(3), f])[None, :])
+    q, qdd = body.q0.copy(), body.qd0.copy()
+    acc = np.array(mi.GRAVITY) + f / m
+    for n in range(1, 21):
+        q, qdd, _, _ = s.step(H, q, qdd)
+        assert np.allclose(q[0, 9:], np.array([0.0, 1.0, 2.0]) + n * H * v0 + 0.5 * n * (n + 1) * H * H * acc,
+                           rtol=0, atol=1e-13)
+        assert np.allclose(qdd[0, 9:], v0 + n * H * acc, rtol=0, atol=1e-12)
+        assert np.allclose(A_of(q[0]), A0, rtol=0, atol=1e-14)
+
+
+def test_wrench_torque_spins_cube_rigidly():
+    """A torque tau on a cube at rest (any orientation R0, no gravity): the
+    affine increment is R0-skew, so the stiff stretch modes stay idle and one
+    implicit Euler step gives the rigid answer omega = h tau / I with
+    I = m a^2 / 6, read through the twist map omega = 1/2 sum_c q_c x qdot_c
+    (Eq. module1-omega-v)."""
+    a = 0.2
+    for R0 in (np.eye(3), rot([1, 1, 0], 0.9)):
+        body = mi.free_body(dims=(a, a, a), A=R0, t=(0.0, 0.0, 1.0))
+        tau = np.array([0.4, -1.2, 2.5])
+        s = oracle.System(body, gravity=(0.0, 0.0, 0.0), wrench=np.concatenate([tau, np.zeros(3)])[None, :])
+        q1, qd1, _, _ = s.step(H, body.q0, body.qd0)
+        A1, Ad = A_of(q1[0]), qd1[0, 0:9].reshape(3, 3).T
+        omega = 0.5 * sum(np.cross(A1[:, c] - H * Ad[:, c], Ad[:, c]) for c in range(3))
+        inertia = 1000.0 * a ** 3 * a * a / 6.0
+        # the 12x12 solve mixes the skew direction (inertia only) with the
+        # stiff stretch modes: kappa(Hbar) ~ 1e4, so ~1e-12 of rounding
+        assert np.allclose(omega, H * tau / inertia, rtol=1e-10, atol=0)
+        assert np.allclose(qd1[0, 9:], 0.0, atol=1e-15)
+
+
+def test_wrench_map_is_power_consistent():
+    """Virtual work: the affine force of a wrench satisfies f_A,ext . qdot =
+    tau . omega + f . v for every velocity, with omega, v from the twist map
+    (Eqs. module1-G-twist, module1-omega-v).  f_A,ext is read from the oracle
+    as the difference of its forces with and without the wrench, at a
+    deformed, rotated configuration (a soft body at rest, so that the other
+    force terms are small and the difference is exact to rounding)."""
+    rng = np.random.default_rng(3)
+    A0 = rot([0.3, 1, -2], 1.1) @ (np.eye(3) + 0.05 * rng.normal(size=(3, 3)))
+    body = mi.free_body(dims=(0.3, 0.25, 0.15), A=A0, t=(1.0, -2.0, 0.5), k_orth=1.0)
+    W = rng.normal(size=6)
+    q = body.q0.copy()
+    qd0 = np.zeros((1, 12))
+    _, f0, _ = oracle.System(body).body_terms(H, q, qd0, 0)
+    _, fw, _ = oracle.System(body, wrench=W[None, :]).body_terms(H, q, qd0, 0)
+    fext = fw - f0
+    for _ in range(5):
+        v = rng.normal(size=12)
+        omega = 0.5 * sum(np.cross(q[0, 3 * c:3 * c + 3], v[3 * c:3 * c + 3]) for c in range(3))
+        assert abs(fext @ v - (W[:3] @ omega + W[3:] @ v[9:])) <= 1e-12 * (1 + abs(fext @ v))
+
+
 @pytest.mark.parametrize("material,E,nu", [(0, 1e6, 0.0), (1, 1e6, 0.3)])
 def test_stretch_mode_is_implicit_euler_oscillator(material, E, nu):
     """A box stretched along its own x axis keeps R = I (polar of a symmetric
