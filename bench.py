@@ -60,6 +60,9 @@ def main():
                          "auto: time both on chain workloads and report the faster")
     ap.add_argument("--ir-tol", type=float, default=1e-12,
                     help="precision 1: target KKT residual of the refinement")
+    ap.add_argument("--wrenches", action="store_true",
+                    help="apply a seeded wind-like load at every step: force 0.2 m g along +x with "
+                         "2 %% noise, torques of 1 %% of m g times the body size")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many MB (5 times), "
                          "to calibrate HBM byte counters")
@@ -92,10 +95,22 @@ def main():
     asm = mi.config(args.workload)
     h = asm.h
 
+    wrench = None
+    if args.wrenches:
+        rng = np.random.default_rng(7)
+        mg = 9.8 * asm.density * asm.dims.prod(axis=1)
+        wrench = np.zeros((asm.n, 6))
+        wrench[:, :3] = 0.01 * rng.normal(size=(asm.n, 3)) * (mg * asm.dims.max(axis=1))[:, None]
+        wrench[:, 3:] = 0.02 * rng.normal(size=(asm.n, 3)) * mg[:, None]
+        wrench[:, 3] += 0.2 * mg
+
     def make(precision, **kw):
         tol = args.ir_tol if precision == 1 else args.kkt_tol
-        return pk.Context(asm, stream=stream.cuda_stream, precision=precision, kkt_tol=tol,
-                          max_iters=args.max_iters, **kw)
+        c = pk.Context(asm, stream=stream.cuda_stream, precision=precision, kkt_tol=tol,
+                       max_iters=args.max_iters, **kw)
+        if wrench is not None:
+            c.set_wrenches(wrench)
+        return c
 
     def run(c, nsteps):
         try:
@@ -188,7 +203,7 @@ def main():
     if not args.no_kkt_check or not args.no_cpu_baseline:
         import oracle
 
-        s = oracle.System(asm)
+        s = oracle.System(asm, wrench=wrench)
         q_n, qd_n = ctx.state()
     if not args.no_kkt_check:
         # one more GPU step from the current (moving) state, verified by the
@@ -228,7 +243,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if chosen == 0 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "bodies": asm.n, "dynamic_bodies": n_dyn,
-                   "joints": asm.m, "h": h, "newton_iters": 1,
+                   "joints": asm.m, "h": h, "newton_iters": 1, "wrenches": bool(args.wrenches),
                    "form": FORMS[chosen], "graph_replay": bool(st["graph_replay"]),
                    "chain_tile_threads": st["tile_threads"]},
         "forms": {FORMS[k]: {"ms_per_step": round(v["wall"] * 1e3 / args.steps, 4),

@@ -163,6 +163,16 @@ mabd_status mabd_state_device(const mabd_ctx *ctx, void *q_dev, void *qd_dev);
    bodies keep q0.  Bitwise continuation: set_state(state()) changes nothing. */
 mabd_status mabd_set_state(mabd_ctx *ctx, const double *q, const double *qd);
 
+/* External spatial wrenches W = [tau; f] per body (host, n*6 doubles in input
+   body order: torque then force, world frame, about the body's centre of
+   mass), applied at every following step until replaced; w = NULL removes
+   them.  Each enters the body force as f_A,ext = G(A)^T W (Eqs.
+   module1-G-twist, module1-wrench-map): 1/2 tau x a_c on column c of A and f
+   on the translation, evaluated at the current Newton iterate.  Entries of
+   pinned bodies are ignored.  Synchronises the stream.  Errors: INVALID_ARG
+   (NULL ctx, non-finite entries), OOM, DEVICE. */
+mabd_status mabd_set_wrenches(mabd_ctx *ctx, const double *w);
+
 /* Multipliers dlambda of the last step's dual solve (Eq. dual) in input joint
    order, 3 doubles per ball joint and 5 per hinge, concatenated.  lam must hold
    mabd_rows(ctx) doubles.  Synchronises the stream. */

@@ -21,7 +21,8 @@ OK, ERR_INVALID_ARG, ERR_TOPOLOGY, ERR_DEVICE, ERR_OOM, ERR_NONFINITE, ERR_NOT_C
     ERR_SINGULAR = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTED = ["mabd_options_default", "mabd_create", "mabd_step", "mabd_state", "mabd_state_device",
-            "mabd_set_state", "mabd_multipliers", "mabd_rows", "mabd_stats", "mabd_gnn_size",
+            "mabd_set_state", "mabd_set_wrenches", "mabd_multipliers", "mabd_rows", "mabd_stats",
+            "mabd_gnn_size",
             "mabd_gnn_init", "mabd_gnn_params", "mabd_gnn_grad", "mabd_gnn_train", "mabd_gnn_predict",
             "mabd_gnn_save", "mabd_gnn_load", "mabd_last_error", "mabd_destroy"]
 
@@ -99,6 +100,7 @@ def lib():
         L.mabd_state.argtypes = [P, P, P]; L.mabd_state.restype = I32
         L.mabd_state_device.argtypes = [P, P, P]; L.mabd_state_device.restype = I32
         L.mabd_set_state.argtypes = [P, P, P]; L.mabd_set_state.restype = I32
+        L.mabd_set_wrenches.argtypes = [P, P]; L.mabd_set_wrenches.restype = I32
         L.mabd_multipliers.argtypes = [P, P]; L.mabd_multipliers.restype = I32
         L.mabd_rows.argtypes = [P]; L.mabd_rows.restype = I64
         L.mabd_stats.argtypes = [P, P]; L.mabd_stats.restype = I32
@@ -187,6 +189,17 @@ class Context:
     def set_state(self, q, qd):
         q = np.ascontiguousarray(q, np.float64); qd = np.ascontiguousarray(qd, np.float64)
         self._check(lib().mabd_set_state(self.h, q.ctypes.data, qd.ctypes.data))
+
+    def set_wrenches(self, w):
+        """External wrenches [tau; f] per body (n x 6, world frame, about the
+        COM), applied from the next step on; None removes them."""
+        if w is None:
+            self._check(lib().mabd_set_wrenches(self.h, None))
+            return
+        w = np.ascontiguousarray(w, np.float64).reshape(-1, 6)
+        if w.shape[0] != self.n:
+            raise ValueError(f"wrench array has {w.shape[0]} rows, the assembly {self.n} bodies")
+        self._check(lib().mabd_set_wrenches(self.h, w.ctypes.data))
 
     def multipliers(self):
         lam = np.zeros(max(self.rows, 1))

@@ -91,6 +91,7 @@ struct ChainArgs {
   double *part;               // 4 partial sums per tile
   double *ir;                 // [0] 0 running / 1 converged / 2 stalled, [1] sweeps,
                               // [2] rho_p, [3] rho_d, [4] kkt, [5] previous kkt
+  const double *wr;           // 6 x ns external wrench [tau; f] per body (SoA), or null
 };
 
 // status words: [0] FLAG_* bits, [1] first failing step of the current call,

@@ -273,13 +273,20 @@ DEV void hbar_apply(const double *sh, double h, const double *x, double *y) {
 // --------------------------------------------------------------- body force
 
 // Local (rotated) right-hand side phi = diag4(R^T) f_A of one body, with
-//   f_A = Mbar qd / h - Mbar (q - qn) / h^2 + [0; m g] + f_el      (Eq. variation_energy)
-// and the co-rotated linear elastic force f_el = -V vec(R P(R^T A))
-// (Eq. reduced_K with dPsi/dA of Sec. 3.3), so that the rotated elastic part
-// is simply -V P.  `sh` = {Mbar0, Mbar1, Mbar2, m, V, mu, lambda}.
+//   f_A = Mbar qd / h - Mbar (q - qn) / h^2 + [0; m g] + f_el + G(A)^T W
+// (Eq. variation_energy; Eq. module1-wrench-map) and the co-rotated linear
+// elastic force f_el = -V vec(R P(R^T A)) (Eq. reduced_K with dPsi/dA of
+// Sec. 3.3), so that the rotated elastic part is simply -V P.  W = [tau; f]
+// is the body's external wrench (world frame, about the COM; `wr` its 6
+// values or null): G(A) maps qdot to the twist (omega = 1/2 sum_c q_c x
+// qdot_c, v = tdot; Eq. module1-G-twist), so G(A)^T W adds 1/2 tau x q_c to
+// column c of A and f to the translation.  `wr` is the SoA wrench array (six
+// streams of stride `ws`) and `wb` this body's index in it, or wr is null.
+// `sh` = {Mbar0, Mbar1, Mbar2, m, V, mu, lambda}.
 template <typename real>
 DEV void local_force(const double *sh, const real *R, const real *A, const real *q,
-                     const real *qn, const real *qd, const double *g, double h, real *phi) {
+                     const real *qn, const real *qd, const double *g, double h, real *phi,
+                     const double *wr = nullptr, int64_t ws = 0, int64_t wb = 0) {
   const real ih = real(1.0 / h), ih2 = real(1.0 / (h * h));
   real Sym[9];
 #pragma unroll
@@ -299,6 +306,18 @@ DEV void local_force(const double *sh, const real *R, const real *A, const real 
     if (c == 3) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) w[i] += real(sh[3] * g[i]);
+    }
+    if (wr) {
+      if (c < 3) {
+        const real t0 = real(wr[wb]), t1 = real(wr[ws + wb]), t2 = real(wr[2 * ws + wb]);
+        const real *qc = q + 3 * c;
+        w[0] += real(0.5) * (t1 * qc[2] - t2 * qc[1]);
+        w[1] += real(0.5) * (t2 * qc[0] - t0 * qc[2]);
+        w[2] += real(0.5) * (t0 * qc[1] - t1 * qc[0]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) w[i] += real(wr[(3 + i) * ws + wb]);
+      }
     }
     // R^T w
 #pragma unroll

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
         qb[c] = breal(q[c]);
         qdb[c] = breal(a.qd[c * a.ns + bg]);
       }
-      local_force<breal>(sh, R, Ab, qb, qb, qdb, a.g, a.h, phi);
+      local_force<breal>(sh, R, Ab, qb, qb, qdb, a.g, a.h, phi, a.wr, a.ns, bg);
     }
     hinv_apply(T_h, phi, u);
     const breal paf[3] = {breal(pa[0]), breal(pa[1]), breal(pa[2])};
@@ -875,7 +875,7 @@ __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
       for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
     }
     double phi[12], u[12];
-    local_force<double>(sh, R, A, q, q, qd, a.g, a.h, phi);
+    local_force<double>(sh, R, A, q, q, qd, a.g, a.h, phi, a.wr, a.ns, bg);
     hinv_apply(T_h, phi, u);
     // r_p = diag4(R) (phi - Hbar diag4(R^T) dq) - G^T lam
     double dl[12], Hd[12], rw[12];

@@ -49,7 +49,7 @@ __global__ void prefactor_kernel(const double *shape, int nshape, double h, doub
 __global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double *q, const double *qn, const double *qdn,
                              int64_t ns, const int32_t *shp, const double *hinv,
                              const double *shape, double g0, double g1, double g2, double h,
-                             double *Rg, double *ug, uint32_t *status, int step) {
+                             double *Rg, double *ug, uint32_t *status, int step, const double *wr) {
   int64_t b = (int64_t)b0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= b1 || skip_step(status, step)) return;
   double qq[12], qnn[12], qd[12];
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double
   const int s = shp[b];
   const double g[3] = {g0, g1, g2};
   double phi[12], u[12];
-  local_force<double>(shape + (int64_t)SHAPE_STRIDE * s, R, A, qq, qnn, qd, g, h, phi);
+  local_force<double>(shape + (int64_t)SHAPE_STRIDE * s, R, A, qq, qnn, qd, g, h, phi, wr, ns, b);
   hinv_apply(hinv + (int64_t)HINV_STRIDE * s, phi, u);
 #pragma unroll
   for (int i = 0; i < 9; ++i) Rg[i * ns + b] = R[i];
@@ -1199,10 +1199,11 @@ void launch_prefactor(const double *shape, int nshape, double h, double *hinv, h
 }
 void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
                   const int32_t *shp, const double *hinv, const double *shape, const double *g,
-                  double h, double *Rg, double *ug, uint32_t *status, int step, hipStream_t s) {
+                  double h, double *Rg, double *ug, uint32_t *status, int step, const double *wr,
+                  hipStream_t s) {
   if (b1 > b0)
     hipLaunchKernelGGL(gbody_kernel, dim3((b1 - b0 + 255) / 256), dim3(256), 0, s, b0, b1, q, qn, qdn,
-                       ns, shp, hinv, shape, g[0], g[1], g[2], h, Rg, ug, status, step);
+                       ns, shp, hinv, shape, g[0], g[1], g[2], h, Rg, ug, status, step, wr);
 }
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
                    double *gl, hipStream_t s) {

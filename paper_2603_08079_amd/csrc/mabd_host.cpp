@@ -38,7 +38,8 @@ void launch_chain_finish(const double *q, const double *dq, double *q_out, doubl
 void launch_prefactor(const double *shape, int nshape, double h, double *hinv, hipStream_t s);
 void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
                   const int32_t *shp, const double *hinv, const double *shape, const double *g,
-                  double h, double *Rg, double *ug, uint32_t *status, int step, hipStream_t s);
+                  double h, double *Rg, double *ug, uint32_t *status, int step, const double *wr,
+                  hipStream_t s);
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
                    double *gl, hipStream_t s);
 void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
@@ -189,6 +190,9 @@ struct mabd_ctx {
   bool tuned = false;
   // captured step graphs, one per state-buffer parity
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // external wrenches: 6 x ns doubles (solver order, SoA), used while wr_on
+  double *d_wr = nullptr;
+  bool wr_on = false;
   bool graph_failed = false;
   double *d_pl = nullptr, *d_pr = nullptr;
   uint8_t *d_flag = nullptr;
@@ -1331,7 +1335,7 @@ hipError_t gnn_prepare(mabd_ctx *c, double h, PcgBallArgs &pb) {
   launch_begin_step(c->d_status, s);
   const int a = c->cur;
   launch_gbody(c->gb0, c->gb1, c->d_q[a], c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv, c->d_shape,
-               c->opt.gravity, h, c->d_Rg, c->d_ug, c->d_status, 0, s);
+               c->opt.gravity, h, c->d_Rg, c->d_ug, c->d_status, 0, c->wr_on ? c->d_wr : nullptr, s);
   launch_gjoint((int)c->gj.size(), c->d_gj, c->d_q[a], c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
   pb = make_ball_args(c, c->opt.kkt_tol, c->opt.max_iters, 0);
   launch_pb_setup(pb, s);
@@ -1452,6 +1456,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
     ca.rd = c->d_rd;
     ca.part = c->d_part;
     ca.ir = c->d_ir;
+    ca.wr = c->wr_on ? c->d_wr : nullptr;
     const int ntl = (int)c->tiles.size(), tt = c->tile_threads;
     // one chain solve: tile reduction, interface solve, tile back-substitution
     auto solve = [&](int mode) {
@@ -1496,7 +1501,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       const double *qcur = it == 0 ? c->d_q[a] : c->d_q[b];
       tm.run(3, [&] {
         launch_gbody(c->gb0, c->gb1, qcur, c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv,
-                     c->d_shape, g, h, c->d_Rg, c->d_ug, c->d_status, 0, s);
+                     c->d_shape, g, h, c->d_Rg, c->d_ug, c->d_status, 0, c->wr_on ? c->d_wr : nullptr, s);
       });
       tm.run(4, [&] {
         launch_gjoint((int)c->gj.size(), c->d_gj, qcur, c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
@@ -1775,6 +1780,31 @@ mabd_status mabd_set_state(mabd_ctx *c, const double *q, const double *qd) {
     e = hipStreamSynchronize(c->stream);
   }
   if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  return MABD_OK;
+}
+
+mabd_status mabd_set_wrenches(mabd_ctx *c, const double *w) {
+  if (!c) return MABD_ERR_INVALID_ARG;
+  if (!w) {
+    if (c->wr_on) drop_graphs(c);  // the step launches change
+    c->wr_on = false;
+    return MABD_OK;
+  }
+  const size_t n6 = (size_t)6 * c->n;
+  if (!finite_all(w, n6)) return fail(c, MABD_ERR_INVALID_ARG, "wrench not finite");
+  if (!c->d_wr) {
+    hipError_t e = dalloc(c, &c->d_wr, 6 * (size_t)c->ns);
+    if (e != hipSuccess) return fail(c, MABD_ERR_OOM, "wrench buffer");
+  }
+  // solver order, SoA; pinned bodies are not in the solver order
+  std::vector<double> hw(6 * (size_t)c->ns, 0.0);
+  for (int s = 0; s < c->nd; ++s)
+    for (int k = 0; k < 6; ++k) hw[(size_t)k * c->ns + s] = w[6 * (size_t)c->sol2in[s] + k];
+  hipError_t e = hipMemcpyAsync(c->d_wr, hw.data(), hw.size() * 8, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
+  if (!c->wr_on) drop_graphs(c);
+  c->wr_on = true;
   return MABD_OK;
 }
 
