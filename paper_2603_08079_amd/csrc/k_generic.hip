@@ -336,7 +336,9 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
 
 // Tree contraction (rake and compress rounds, planned on the host).  Every
 // round's operations touch disjoint slots, so each round is one launch per
-// kind; a 16-lane team per operation, matrices in the slots' global storage.
+// kind and clique size.  The team kernels below (a 16-lane team per
+// operation, matrices in the slots' global storage) take the compresses whose
+// cliques exceed the LDS-staged kernels further down.
 
 // add the condensed far sides (Sigma, rho) of v's child joints, entries
 // [e0, e1) of its absorbed list
@@ -383,31 +385,6 @@ DEV void tc_partial_cholesky(const TreeArgs &a, double *K, double *y, int LD, in
       y[i] -= lip * y[p];
     }
     team_sync();
-  }
-}
-
-__global__ __launch_bounds__(TREE_BLOCK) void tc_rake_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
-  const int tm = threadIdx.x / TEAM, ln = threadIdx.x % TEAM;
-  if (skip_step(a.status, a.step)) return;
-  const int i = op0 + blockIdx.x * TEAMS + tm;
-  if (i >= op1) return;
-  const TcOp op = a.ops[i];
-  const int v = op.v;
-  const int ne = a.tne[v], LD = ne + 5;
-  double *K = a.fac + a.foff[v];
-  double *y = K + LD * LD;
-  tc_add_children(a, J, a.tabs_off[v], a.tabs_off[v + 1], K, y, LD, ln);
-  team_sync();
-  tc_partial_cholesky(a, K, y, LD, op.nv, ne, ln);
-  if (op.kcur >= 0) {
-    double *gtk = a.gt + (int64_t)GT_STRIDE * op.kcur;
-    for (int idx = ln; idx < 25; idx += TEAM) {
-      const int r = idx / 5, s = idx % 5;
-      double val = 0.0;
-      if (r < op.ck && s < op.ck) val = s <= r ? K[(ne + r) * LD + ne + s] : K[(ne + s) * LD + ne + r];
-      gtk[GT_SIG + idx] = val;
-    }
-    if (ln < 5) gtk[GT_RHO + ln] = ln < op.ck ? y[ne + ln] : 0.0;
   }
 }
 
@@ -548,16 +525,6 @@ DEV void tc_private_back(const TreeArgs &a, const GJoint *J, int v, int np, int 
     for (int i = c; i < 5; ++i) a.glam[5 * (int64_t)k + i] = 0.0;
     r0 += c;
   }
-}
-
-__global__ __launch_bounds__(256) void tc_rake_back_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
-  if (skip_step(a.status, a.step)) return;
-  const int i = op0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= op1) return;
-  const TcOp op = a.ops[i];
-  double lb[5] = {0, 0, 0, 0, 0};
-  for (int r = 0; r < op.ck; ++r) lb[r] = a.glam[5 * (int64_t)op.kcur + r];
-  tc_private_back(a, J, op.v, a.tne[op.v], op.nv, lb, a.tabs_off[op.v + 1]);
 }
 
 __global__ __launch_bounds__(256) void tc_compress_back_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
@@ -722,45 +689,63 @@ DEV void tcw_add_children(const TreeArgs &a, int tab, int nent, double *K, doubl
 }
 
 // partial Cholesky of the first np of nr (<= TW + 1) rows of a packed LDS
-// clique (same arithmetic as tc_partial_cholesky): lane i scales row
-// p + 1 + i of the pivot column, then updates column p + 1 + i of the
-// trailing triangle in batches of eight independent rows
+// clique (the factorisation of tc_partial_cholesky, blocked): pivots are
+// taken in panels of four columns.  Within a panel, lane i scales row
+// p + 1 + i of the pivot column and updates its row in the panel's later
+// columns; then the trailing triangle gets one rank-four update, lane i
+// owning column p0 + 4 + i, in batches of eight independent rows.
 template <int R, int TW>
 DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, int np) {
+  constexpr int PB = 4;
   const int ln = tlane<TW>();
-  for (int p = 0; p < np; ++p) {
-    double d = K[tri(p) + p];
-    if (!(d > 0.0)) {
-      if (ln == 0) raise_flag(a.status, FLAG_SINGULAR, a.step);
-      d = 1.0;
+  for (int p0 = 0; p0 < np; p0 += PB) {
+    const int pe = p0 + PB < np ? p0 + PB : np;  // panel columns [p0, pe)
+    for (int p = p0; p < pe; ++p) {
+      double d = K[tri(p) + p];
+      if (!(d > 0.0)) {
+        if (ln == 0) raise_flag(a.status, FLAG_SINGULAR, a.step);
+        d = 1.0;
+      }
+      d = sqrt(d);
+      const double yp = y[p] / d;
+      const int i = p + 1 + ln;
+      double lip = 0.0;
+      if (i < nr) lip = K[tri(i) + p] / d;
+      team_sync();
+      if (ln == 0) {
+        K[tri(p) + p] = d;
+        y[p] = yp;
+      }
+      if (i < nr) {
+        K[tri(i) + p] = lip;
+        y[i] -= lip * yp;
+      }
+      team_sync();
+      if (i < nr) {  // row i, panel columns j in (p, pe), j <= i
+        for (int j = p + 1; j < pe && j <= i; ++j) K[tri(i) + j] -= lip * K[tri(j) + p];
+      }
+      team_sync();
     }
-    d = sqrt(d);
-    const double yp = y[p] / d;
-    const int i = p + 1 + ln;
-    double lip = 0.0;
-    if (i < nr) lip = K[tri(i) + p] / d;
-    team_sync();
-    if (ln == 0) {
-      K[tri(p) + p] = d;
-      y[p] = yp;
-    }
-    if (i < nr) {
-      K[tri(i) + p] = lip;
-      y[i] -= lip * yp;
-    }
-    team_sync();
-    if (i < nr) {  // column j = i, rows r >= j: K[r][j] -= l_rp l_jp
-      for (int r = i; r < nr; r += 8) {
-        double kv[8], lr[8];
+    const int j = pe + ln;  // trailing column of this lane: rows r >= j
+    if (pe < nr && j < nr) {
+      double lj[PB];
+#pragma unroll
+      for (int q = 0; q < PB; ++q) lj[q] = p0 + q < pe ? K[tri(j) + p0 + q] : 0.0;
+      for (int r = j; r < nr; r += 8) {
+        double kv[8], upd[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int rr = r + u < nr ? r + u : nr - 1;
-          kv[u] = K[tri(rr) + i];
-          lr[u] = K[tri(rr) + p];
+          const double *row = K + tri(rr);
+          kv[u] = row[j];
+          double t = 0.0;
+#pragma unroll
+          for (int q = 0; q < PB; ++q) t += (p0 + q < pe ? row[p0 + q] : 0.0) * lj[q];
+          upd[u] = t;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          if (r + u < nr) K[tri(r + u) + i] = kv[u] - lr[u] * lip;
+          if (r + u < nr) K[tri(r + u) + j] = kv[u] - upd[u];
       }
     }
     team_sync();
