@@ -690,13 +690,14 @@ DEV void tcw_add_children(const TreeArgs &a, int tab, int nent, double *K, doubl
 
 // partial Cholesky of the first np of nr (<= TW + 1) rows of a packed LDS
 // clique (the factorisation of tc_partial_cholesky, blocked): pivots are
-// taken in panels of four columns.  Within a panel, lane i scales row
+// taken in panels of PB columns.  Within a panel, lane i scales row
 // p + 1 + i of the pivot column and updates its row in the panel's later
-// columns; then the trailing triangle gets one rank-four update, lane i
-// owning column p0 + 4 + i, in batches of eight independent rows.
+// columns; then the trailing triangle gets one rank-PB update, lane i owning
+// column p0 + PB + i, in batches of RB independent rows.
 template <int R, int TW>
 DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, int np) {
-  constexpr int PB = 4;
+  constexpr int PB = R >= 32 ? 8 : 4;  // panel width
+  constexpr int RB = R >= 32 ? 4 : 8;  // rows per batch of the trailing update
   const int ln = tlane<TW>();
   for (int p0 = 0; p0 < np; p0 += PB) {
     const int pe = p0 + PB < np ? p0 + PB : np;  // panel columns [p0, pe)
@@ -731,10 +732,10 @@ DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, i
       double lj[PB];
 #pragma unroll
       for (int q = 0; q < PB; ++q) lj[q] = p0 + q < pe ? K[tri(j) + p0 + q] : 0.0;
-      for (int r = j; r < nr; r += 8) {
-        double kv[8], upd[8];
+      for (int r = j; r < nr; r += RB) {
+        double kv[RB], upd[RB];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < RB; ++u) {
           const int rr = r + u < nr ? r + u : nr - 1;
           const double *row = K + tri(rr);
           kv[u] = row[j];
@@ -744,7 +745,7 @@ DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, i
           upd[u] = t;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < RB; ++u)
           if (r + u < nr) K[tri(r + u) + j] = kv[u] - upd[u];
       }
     }
