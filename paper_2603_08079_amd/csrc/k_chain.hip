@@ -179,8 +179,9 @@ inline unsigned xcd_grid(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8);
 // FP32, the factor in FP64, the increment goes to dq.  MODE 2 (form 1
 // correction): the right-hand side is the FP64 KKT residual (rp, rd) of the
 // current iterate and the increment is added to dq and lam; skipped once the
-// residual check has converged.
-template <int MODE, bool APPLY, int NT>
+// residual check has converged.  WR: the bodies carry external wrenches (a
+// separate instantiation, so that the plain path holds none of that code).
+template <int MODE, bool APPLY, int NT, bool WR>
 #ifndef MABD_TILE_WAVES_REDUCE
 #define MABD_TILE_WAVES_REDUCE 2
 #endif
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
         qb[c] = breal(q[c]);
         qdb[c] = breal(a.qd[c * a.ns + bg]);
       }
-      local_force<breal>(sh, R, Ab, qb, qb, qdb, a.g, a.h, phi, a.wr, a.ns, bg);
+      local_force<breal>(sh, R, Ab, qb, qb, qdb, a.g, a.h, phi, WR ? a.wr : nullptr, a.ns, bg);
     }
     hinv_apply(T_h, phi, u);
     const breal paf[3] = {breal(pa[0]), breal(pa[1]), breal(pa[2])};
@@ -810,7 +811,7 @@ __global__ __launch_bounds__(1024) void chain_global_kernel(const ChainDesc *cha
 // r_d = -(C + G dq) per row, and per tile the sums behind
 // rho_p = |H^{-1} r_p| / |H^{-1} f_A| and rho_d = |r_d| / |G H^{-1} f_A + C|
 // (the KKT residual of Eq. kkt with the -C right-hand side).
-template <int NT>
+template <int NT, bool WR>
 __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
   enum { L_VB = 0, L_CB = 3, L_TB = 6, L_GB = 9, L_RED = 12 };
   __shared__ double lds[16 * NT];
@@ -875,7 +876,7 @@ __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
       for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
     }
     double phi[12], u[12];
-    local_force<double>(sh, R, A, q, q, qd, a.g, a.h, phi, a.wr, a.ns, bg);
+    local_force<double>(sh, R, A, q, q, qd, a.g, a.h, phi, WR ? a.wr : nullptr, a.ns, bg);
     hinv_apply(T_h, phi, u);
     // r_p = diag4(R) (phi - Hbar diag4(R^T) dq) - G^T lam
     double dl[12], Hd[12], rw[12];
@@ -1038,22 +1039,29 @@ __global__ void chain_finish_kernel(const double *q, const double *dq, double *q
   if (!isfinite(d)) raise_flag(status, FLAG_NONFINITE, 0);
 }
 
-template <int MODE, bool APPLY>
+template <int MODE, bool APPLY, bool WR>
 static void launch_tiles(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
   if (ntiles <= 0) return;
   const dim3 grid(xcd_grid(ntiles));
   if (nt == 64)
-    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 64>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 64, WR>), grid, dim3(64), 0, s, a);
   else if (nt == 128)
-    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 128>), grid, dim3(128), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 128, WR>), grid, dim3(128), 0, s, a);
   else
-    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 256>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 256, WR>), grid, dim3(256), 0, s, a);
 }
 template <bool APPLY>
 static void launch_tiles_mode(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s) {
-  if (mode == 0) launch_tiles<0, APPLY>(a, ntiles, nt, s);
-  else if (mode == 1) launch_tiles<1, APPLY>(a, ntiles, nt, s);
-  else launch_tiles<2, APPLY>(a, ntiles, nt, s);
+  // the correction sweeps (mode 2) take the force from the FP64 residual
+  if (mode == 0) {
+    if (a.wr) launch_tiles<0, APPLY, true>(a, ntiles, nt, s);
+    else launch_tiles<0, APPLY, false>(a, ntiles, nt, s);
+  } else if (mode == 1) {
+    if (a.wr) launch_tiles<1, APPLY, true>(a, ntiles, nt, s);
+    else launch_tiles<1, APPLY, false>(a, ntiles, nt, s);
+  } else {
+    launch_tiles<2, APPLY, false>(a, ntiles, nt, s);
+  }
 }
 void launch_chain_reduce(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s) {
   launch_tiles_mode<false>(a, ntiles, nt, mode, s);
@@ -1081,12 +1089,21 @@ void launch_chain_global(const ChainDesc *chains, int nchains, const double *til
 void launch_chain_resid(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
   if (ntiles <= 0) return;
   const dim3 grid(xcd_grid(ntiles));
-  if (nt == 64)
-    hipLaunchKernelGGL(chain_resid_kernel<64>, grid, dim3(64), 0, s, a);
-  else if (nt == 128)
-    hipLaunchKernelGGL(chain_resid_kernel<128>, grid, dim3(128), 0, s, a);
-  else
-    hipLaunchKernelGGL(chain_resid_kernel<256>, grid, dim3(256), 0, s, a);
+  if (a.wr) {
+    if (nt == 64)
+      hipLaunchKernelGGL((chain_resid_kernel<64, true>), grid, dim3(64), 0, s, a);
+    else if (nt == 128)
+      hipLaunchKernelGGL((chain_resid_kernel<128, true>), grid, dim3(128), 0, s, a);
+    else
+      hipLaunchKernelGGL((chain_resid_kernel<256, true>), grid, dim3(256), 0, s, a);
+  } else {
+    if (nt == 64)
+      hipLaunchKernelGGL((chain_resid_kernel<64, false>), grid, dim3(64), 0, s, a);
+    else if (nt == 128)
+      hipLaunchKernelGGL((chain_resid_kernel<128, false>), grid, dim3(128), 0, s, a);
+    else
+      hipLaunchKernelGGL((chain_resid_kernel<256, false>), grid, dim3(256), 0, s, a);
+  }
 }
 void launch_chain_ir_check(const double *part, int nblk, double tol, int final_check, double *ir,
                            uint32_t *status, hipStream_t s) {
