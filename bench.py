@@ -39,10 +39,10 @@ ALG_BYTES = {
 ALG_BYTES_F1 = {"chain_resid": 288 + 53 + 24 + 120}
 # HBM bytes per launch of the dominant kernel measured with rocprofv3 --pmc
 # (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, scales from a plain 512 MiB copy) for
-# the 64-thread chain tile kernels as they stand, on the 1M chain; reported only
-# for that workload and tile size.
-PMC_TRAFFIC = {("chain1m", "chain_apply", 64): (171525 * 2 + 221386) * 1024,
-               ("chain1m", "chain_reduce", 64): (125814 * 2 + 3569) * 1024}
+# the chain tile kernels as they stand, on the 1M chain; keyed by workload,
+# kernel, tile threads and tile packing, and reported only for those.
+PMC_TRAFFIC = {("chain1m", "chain_apply", 64, 0): (171525 * 2 + 221386) * 1024,
+               ("chain1m", "chain_reduce", 64, 0): (125814 * 2 + 3569) * 1024}
 
 
 def main():
@@ -156,6 +156,7 @@ def main():
         s_ = r_["stats"]
         print(f"# precision {p_}: {args.steps} steps in {r_['wall'] * 1e3:.3f} ms (graph replay "
               f"{s_['graph_replay']}, chain tile threads {s_['tile_threads']}"
+              + (" packed" if s_['tile_packed'] else "")
               + (f", sweeps {s_['ir_sweeps']}, device kkt {s_['kkt']:.3e})" if p_ == 1 else ")"),
               file=sys.stderr, flush=True)
     # the chosen form: the faster one (both reach the FP64 KKT residual)
@@ -188,7 +189,8 @@ def main():
     if dom in ab:
         alg = ab[dom] * n_dyn
         ach = alg / (per_launch[dom] * 1e-3) / 1e9
-        traffic = PMC_TRAFFIC.get((args.workload, dom, st["tile_threads"])) if chosen == 0 else None
+        traffic = (PMC_TRAFFIC.get((args.workload, dom, st["tile_threads"], st["tile_packed"]))
+                   if chosen == 0 else None)
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "avg_launch_ms": round(per_launch[dom], 4),
@@ -245,7 +247,8 @@ def main():
         "config": {"workload": args.workload, "bodies": asm.n, "dynamic_bodies": n_dyn,
                    "joints": asm.m, "h": h, "newton_iters": 1, "wrenches": bool(args.wrenches),
                    "form": FORMS[chosen], "graph_replay": bool(st["graph_replay"]),
-                   "chain_tile_threads": st["tile_threads"]},
+                   "chain_tile_threads": st["tile_threads"],
+                   "chain_tiles_packed": bool(st["tile_packed"])},
         "forms": {FORMS[k]: {"ms_per_step": round(v["wall"] * 1e3 / args.steps, 4),
                              "body_steps_per_s": round(n_dyn * args.steps / v["wall"], 1),
                              **({"ir_sweeps_last_step": v["stats"]["ir_sweeps"],

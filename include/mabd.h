@@ -127,6 +127,8 @@ typedef struct {
   int32_t tile_threads;    /* workgroup size of the chain tile kernels in use            */
   int32_t graph_replay;    /* 1 if the last mabd_step replayed captured step graphs       */
   int32_t tree_rounds;     /* rounds of the tree contraction (rake + compress)          */
+  int32_t tile_packed;     /* 1 if the chain tiles are packed: 60-row tiles whose last
+                              four cyclic-reduction levels run four tiles to a wave     */
 } mabd_step_stats;
 
 /* Fills *opt with the defaults listed above. */

@@ -70,7 +70,7 @@ class StepStats(ctypes.Structure):
                 ("n_graph", ctypes.c_int32), ("n_dyn", ctypes.c_int32),
                 ("phase_ms", ctypes.c_double * NPHASES), ("phase_calls", ctypes.c_int64 * NPHASES),
                 ("tile_threads", ctypes.c_int32), ("graph_replay", ctypes.c_int32),
-                ("tree_rounds", ctypes.c_int32)]
+                ("tree_rounds", ctypes.c_int32), ("tile_packed", ctypes.c_int32)]
 
     PHASES = ("chain_reduce", "chain_global", "chain_apply", "body", "joint", "tree", "apply",
               "pcg", "chain_resid", "chain_finish")

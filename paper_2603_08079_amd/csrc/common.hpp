@@ -56,6 +56,12 @@ constexpr int CHAIN_THREADS = 256;
 constexpr int TILE_REC = 27;         // doubles per tile record
 constexpr int GROW_REC = 56;         // doubles per top-level row (scratch)
 constexpr int GROUP_T = 255;         // interface rows per group - 1
+// packed tiles: 64-thread tiles of PACK_T rows; after two levels of cyclic
+// reduction at most 16 rows of a tile survive, and four tiles' survivors are
+// reduced together in one wave (rows of tile ti: lanes 16 (ti mod 4) + j)
+constexpr int PACK_T = 60;
+constexpr int PACK_SV = 18;          // doubles per surviving row: D 6, b 3, U 9
+constexpr int PACK_CF = 21;          // doubles per packed eliminated row: PL 9, PU 9, Pb 3
 
 // per-shape raw constants used by the force: Mbar0..2, m, V, mu, lambda
 constexpr int SHAPE_STRIDE = 8;
@@ -92,6 +98,11 @@ struct ChainArgs {
   double *ir;                 // [0] 0 running / 1 converged / 2 stalled, [1] sweeps,
                               // [2] rho_p, [3] rho_d, [4] kkt, [5] previous kkt
   const double *wr;           // 6 x ns external wrench [tau; f] per body (SoA), or null
+  // packed tiles (per group of four tiles, 64 lanes each): surviving rows
+  // [PACK_SV][64] and factors of the rows eliminated in the packed levels
+  // [PACK_CF][64]
+  double *psv;
+  double *pcf;
 };
 
 // status words: [0] FLAG_* bits, [1] first failing step of the current call,

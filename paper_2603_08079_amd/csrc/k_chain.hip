@@ -63,11 +63,14 @@ enum { S_PL = 0, S_PU = 9, S_PB = 18 };
 //   right: D -= U^T PU,  b -= U^T Pb,  L <- (-L^T PU)^T
 // The surviving rows then only add what their eliminated neighbours
 // published, so the costly branch runs on one set of lanes per level.
+// Levels d < dend run; dend must be the same in the whole workgroup (it
+// brackets barriers), and a level with d >= T changes nothing, so rows of
+// systems of different sizes can share one call.
 template <int NT>
-DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, double *L, double *D,
-                         double *U, double *b, double *PL, double *PU, double *Pb, int &elim_d,
-                         uint32_t *status, int step) {
-  for (int d = 1; d < T; d *= 2) {
+DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, int dend, double *L,
+                         double *D, double *U, double *b, double *PL, double *PU, double *Pb,
+                         int &elim_d, uint32_t *status, int step) {
+  for (int d = 1; d < dend; d *= 2) {
     const bool active = row_active && (li % d == 0 || li == T);
     const bool elim = active && li < T && (li % (2 * d) == d);
     if (elim) {
@@ -174,6 +177,94 @@ DEV int xcd_tile(int ntiles) {
   return ti < ntiles ? ti : -1;
 }
 inline unsigned xcd_grid(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8); }
+// The same with ranges of a multiple of four tiles, so that the four tiles of
+// a packed group share an XCD (and its L2).
+DEV int xcd_tile4(int ntiles) {
+  const int per = 4 * ((ntiles + 31) / 32);
+  const int ti = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  return ti < ntiles ? ti : -1;
+}
+inline unsigned xcd_grid4(int ntiles) { return 32u * (unsigned)((ntiles + 31) / 32); }
+
+// Packed tiles.  A tile of T <= PACK_T rows runs the first two levels of its
+// cyclic reduction alone; its surviving rows are li = 4j (li < T) and li = T,
+// at most 16, numbered j = 0..T' with T' = ceil(T/4).  Levels d = 4, 8, 16,
+// 32 of the tile eliminate exactly the rows that levels 1, 2, 4, 8 of the
+// survivors' own cyclic reduction (rows j, T') eliminate, with the same
+// neighbours, so the survivors of four tiles are reduced as four 16-row
+// systems side by side in one wave (chain_pack_kernel, launched after the
+// tiles: handing the survivors over inside one launch would need device-scope
+// cache maintenance per workgroup).  That wave writes the tiles' Schur
+// records and the factors (PL, PU, Pb) of the rows it eliminated; the apply
+// pass reads those factors instead of repeating the four sparse levels.
+DEV void pack_reduce_group(const ChainArgs &a, int grp, double *lds) {
+  const int t = threadIdx.x;
+  const int q = t >> 4, j = t & 15;
+  const int nq = min(4, a.ntiles - 4 * grp);
+  const int tq = 4 * grp + q;
+  // every slot of a present tile is read together with the tile size (slots
+  // past the tile's survivors hold stale values and are discarded below)
+  int Tp = 0;
+  double L[9], D[6], U[9], b[3];
+  if (q < nq) {
+    const double *sv = a.psv + (int64_t)grp * (PACK_SV * 64) + t;
+    Tp = (a.tiles[tq].T + 3) >> 2;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) D[i] = sv[i * 64];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) b[i] = sv[(6 + i) * 64];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) U[i] = sv[(9 + i) * 64];
+    // left coupling = (U of the previous survivor)^T
+    const double *svl = sv - (j > 0 ? 1 : 0);
+#pragma unroll
+    for (int r2 = 0; r2 < 3; ++r2)
+#pragma unroll
+      for (int c2 = 0; c2 < 3; ++c2) L[3 * r2 + c2] = svl[(9 + 3 * c2 + r2) * 64];
+  }
+  const bool act = q < nq && j <= Tp;
+  if (!act || j == 0) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) L[i] = 0.0;
+  }
+  if (!act) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) U[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) D[i] = 0.0;
+    b[0] = b[1] = b[2] = 0.0;
+  }
+  double PL[9], PU[9], Pb[3];
+  int elim_d = 0;
+  tile_cr_forward<64>(lds + 16 * q, act, j, Tp, 16, L, D, U, b, PL, PU, Pb, elim_d, a.status,
+                      a.step);
+  if (act && (j == 0 || j == Tp)) {
+    double *rec = a.tilerec + (int64_t)TILE_REC * tq;
+    if (j == 0) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) rec[i] = D[i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) rec[6 + i] = b[i];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) rec[18 + i] = U[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) rec[9 + i] = D[i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) rec[15 + i] = b[i];
+    }
+  }
+  if (elim_d > 0) {
+    double *cf = a.pcf + (int64_t)grp * (PACK_CF * 64) + t;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      cf[i * 64] = PL[i];
+      cf[(9 + i) * 64] = PU[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) cf[(18 + i) * 64] = Pb[i];
+  }
+}
 
 // MODE 0: plain FP64.  MODE 1 (precision form 1, first solve): phase A in
 // FP32, the factor in FP64, the increment goes to dq.  MODE 2 (form 1
@@ -181,7 +272,8 @@ inline unsigned xcd_grid(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8);
 // current iterate and the increment is added to dq and lam; skipped once the
 // residual check has converged.  WR: the bodies carry external wrenches (a
 // separate instantiation, so that the plain path holds none of that code).
-template <int MODE, bool APPLY, int NT, bool WR>
+// PACK: packed 64-thread tiles (pack_reduce_group).
+template <int MODE, bool APPLY, int NT, bool WR, bool PACK>
 #ifndef MABD_TILE_WAVES_REDUCE
 #define MABD_TILE_WAVES_REDUCE 2
 #endif
@@ -196,7 +288,8 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
   if constexpr (MODE == 2) {
     if (a.ir[0] != 0.0) return;
   }
-  const int ti = xcd_tile(a.ntiles);
+  static_assert(!PACK || NT == 64, "packed tiles are 64-thread tiles");
+  const int ti = PACK ? xcd_tile4(a.ntiles) : xcd_tile(a.ntiles);
   if (ti < 0) return;
   const TileDesc td = a.tiles[ti];
   const ChainDesc cd = a.chains[td.chain];
@@ -220,6 +313,7 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
   double va[3] = {0, 0, 0}, ca[3] = {0, 0, 0}, ta[3] = {0, 0, 0};
   double Wbb[6] = {0, 0, 0, 0, 0, 0}, vb[3] = {0, 0, 0}, cb[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
   const double *T_h = nullptr;
+  double q[12];  // kept for the state update of the apply pass
   if (has_a) {
     for (int i = 0; i < 3; ++i) pa[i] = a.pr[i * a.nrs + gra];
     sa = (a.flag[gra] & 2) ? 1.0 : -1.0;
@@ -229,7 +323,6 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
     sb = (a.flag[grb] & 1) ? 1.0 : -1.0;
   }
   if (has_body) {
-    double q[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) q[c] = a.q[c * a.ns + bg];
     const int s = a.shp[bg];
@@ -393,9 +486,23 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
   // ---------------------------------------------------------------- phase C
   double PL[9], PU[9], Pb[3];
   int elim_d = 0;
-  tile_cr_forward<NT>(lds, row_active, li, T, L, D, U, b, PL, PU, Pb, elim_d, a.status, a.step);
+  tile_cr_forward<NT>(lds, row_active, li, T, PACK ? 4 : T, L, D, U, b, PL, PU, Pb, elim_d,
+                      a.status, a.step);
 
-  if constexpr (!APPLY) {
+  if constexpr (!APPLY && PACK) {
+    // survivors to the group's slots (reduced by chain_pack_kernel)
+    const int grp = ti >> 2, Tp = (T + 3) >> 2;
+    if (row_active && (li == T || (li & 3) == 0)) {
+      const int j = li == T ? Tp : li >> 2;
+      double *sv = a.psv + (int64_t)grp * (PACK_SV * 64) + 16 * (ti & 3) + j;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) sv[i * 64] = D[i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) sv[(6 + i) * 64] = b[i];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) sv[(9 + i) * 64] = U[i];
+    }
+  } else if constexpr (!APPLY) {
     double *rec = a.tilerec + (int64_t)TILE_REC * ti;
     if (row_active && li == 0) {
 #pragma unroll
@@ -413,6 +520,22 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
     }
   } else {
     // -------------------------------------------------- back-substitution
+    if constexpr (PACK) {
+      // rows eliminated in the packed levels take their factors from the
+      // reduce pass
+      const int j = li >> 2, Tp = (T + 3) >> 2;
+      if (row_active && (li & 3) == 0 && j > 0 && j < Tp) {
+        elim_d = 4 * (j & -j);
+        const double *cf = a.pcf + (int64_t)(ti >> 2) * (PACK_CF * 64) + 16 * (ti & 3) + j;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          PL[i] = cf[i * 64];
+          PU[i] = cf[(9 + i) * 64];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Pb[i] = cf[(18 + i) * 64];
+      }
+    }
     if (row_active && (li == 0 || li == T)) {
       const int64_t gi = (int64_t)cd.grow0 + td.tidx + (li == T ? 1 : 0);
 #pragma unroll
@@ -478,7 +601,7 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
           const int64_t o = (int64_t)(3 * c + i) * a.ns + bg;
           const double d = double(dqv[i]);
           if constexpr (MODE == 0) {
-            a.q_out[o] = a.q[o] + d;
+            a.q_out[o] = q[3 * c + i] + d;
             a.qd_out[o] = d * ih;
           } else if constexpr (MODE == 1) {
             a.dq[o] = d;
@@ -490,6 +613,22 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
       }
     }
   }
+}
+
+// One wave per group of four packed tiles.  Groups are ordered like the tiles
+// (xcd_tile4), so a group runs on the XCD whose L2 holds its survivors.
+template <int MODE>
+__global__ __launch_bounds__(64) void chain_pack_kernel(ChainArgs a) {
+  __shared__ double lds[S_N * 64];
+  if (skip_step(a.status, a.step)) return;
+  if constexpr (MODE == 2) {
+    if (a.ir[0] != 0.0) return;
+  }
+  const int ngrp = (a.ntiles + 3) / 4;
+  const int per = (a.ntiles + 31) / 32;  // groups per XCD range
+  const int grp = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (grp >= ngrp) return;
+  pack_reduce_group(a, grp, lds);
 }
 
 // Top system of a chain (rows that bound its groups), n = ngroup + 1 <= 256
@@ -521,7 +660,7 @@ DEV void top_solve(double *lds, const ChainDesc &cd, const double *grouprec, dou
   }
   double PL[9], PU[9], Pb[3];
   int elim_d = 0;
-  tile_cr_forward<CHAIN_THREADS>(lds, row_active, li, T, L, D, U, b, PL, PU, Pb, elim_d, status, step);
+  tile_cr_forward<CHAIN_THREADS>(lds, row_active, li, T, T, L, D, U, b, PL, PU, Pb, elim_d, status, step);
   // rows 0 and T now form [D0 U0; U0^T DT] [x0; xT] = [b0; bT]
   if (li == 0) {
     for (int i = 0; i < 6; ++i) lds[(S_PL + i) * CHAIN_THREADS] = D[i];
@@ -636,7 +775,7 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
       for (int c2 = 0; c2 < 3; ++c2) L[3 * r2 + c2] = TR[TILE_REC * (gi - 1) + 18 + 3 * c2 + r2];
   double PL[9], PU[9], Pb[3];
   int elim_d = 0;
-  tile_cr_forward<CHAIN_THREADS>(lds, row_active, li, T, L, D, U, b, PL, PU, Pb, elim_d, status, step);
+  tile_cr_forward<CHAIN_THREADS>(lds, row_active, li, T, T, L, D, U, b, PL, PU, Pb, elim_d, status, step);
   if constexpr (!APPLY) {
     double *rec = grouprec + (int64_t)TILE_REC * (cd.group0 + gd.gidx);
     if (row_active && li == 0) {
@@ -1039,35 +1178,47 @@ __global__ void chain_finish_kernel(const double *q, const double *dq, double *q
   if (!isfinite(d)) raise_flag(status, FLAG_NONFINITE, 0);
 }
 
+// nt: 64, 128 or 256 threads per tile; pack: packed 64-thread tiles
 template <int MODE, bool APPLY, bool WR>
-static void launch_tiles(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {
+static void launch_tiles(const ChainArgs &a, int ntiles, int nt, bool pack, hipStream_t s) {
   if (ntiles <= 0) return;
+  if (pack) {
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 64, WR, true>), dim3(xcd_grid4(ntiles)),
+                       dim3(64), 0, s, a);
+    if (!APPLY)  // one workgroup per group of four tiles, XCD ranges as the tiles'
+      hipLaunchKernelGGL((chain_pack_kernel<MODE>), dim3(8u * (unsigned)((ntiles + 31) / 32)),
+                         dim3(64), 0, s, a);
+    return;
+  }
   const dim3 grid(xcd_grid(ntiles));
   if (nt == 64)
-    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 64, WR>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 64, WR, false>), grid, dim3(64), 0, s, a);
   else if (nt == 128)
-    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 128, WR>), grid, dim3(128), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 128, WR, false>), grid, dim3(128), 0, s, a);
   else
-    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 256, WR>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((chain_tile_kernel<MODE, APPLY, 256, WR, false>), grid, dim3(256), 0, s, a);
 }
 template <bool APPLY>
-static void launch_tiles_mode(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s) {
+static void launch_tiles_mode(const ChainArgs &a, int ntiles, int nt, bool pack, int mode,
+                              hipStream_t s) {
   // the correction sweeps (mode 2) take the force from the FP64 residual
   if (mode == 0) {
-    if (a.wr) launch_tiles<0, APPLY, true>(a, ntiles, nt, s);
-    else launch_tiles<0, APPLY, false>(a, ntiles, nt, s);
+    if (a.wr) launch_tiles<0, APPLY, true>(a, ntiles, nt, pack, s);
+    else launch_tiles<0, APPLY, false>(a, ntiles, nt, pack, s);
   } else if (mode == 1) {
-    if (a.wr) launch_tiles<1, APPLY, true>(a, ntiles, nt, s);
-    else launch_tiles<1, APPLY, false>(a, ntiles, nt, s);
+    if (a.wr) launch_tiles<1, APPLY, true>(a, ntiles, nt, pack, s);
+    else launch_tiles<1, APPLY, false>(a, ntiles, nt, pack, s);
   } else {
-    launch_tiles<2, APPLY, false>(a, ntiles, nt, s);
+    launch_tiles<2, APPLY, false>(a, ntiles, nt, pack, s);
   }
 }
-void launch_chain_reduce(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s) {
-  launch_tiles_mode<false>(a, ntiles, nt, mode, s);
+void launch_chain_reduce(const ChainArgs &a, int ntiles, int nt, bool pack, int mode,
+                         hipStream_t s) {
+  launch_tiles_mode<false>(a, ntiles, nt, pack, mode, s);
 }
-void launch_chain_apply(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s) {
-  launch_tiles_mode<true>(a, ntiles, nt, mode, s);
+void launch_chain_apply(const ChainArgs &a, int ntiles, int nt, bool pack, int mode,
+                        hipStream_t s) {
+  launch_tiles_mode<true>(a, ntiles, nt, pack, mode, s);
 }
 void launch_chain_group(bool apply, const ChainDesc *chains, const GroupDesc *groups, int ngroups,
                         const double *tilerec, double *grouprec, double *xtop, double *xg,

@@ -22,8 +22,10 @@
 
 namespace mabd {
 
-void launch_chain_reduce(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s);
-void launch_chain_apply(const ChainArgs &a, int ntiles, int nt, int mode, hipStream_t s);
+void launch_chain_reduce(const ChainArgs &a, int ntiles, int nt, bool pack, int mode,
+                         hipStream_t s);
+void launch_chain_apply(const ChainArgs &a, int ntiles, int nt, bool pack, int mode,
+                        hipStream_t s);
 void launch_chain_global(const ChainDesc *chains, int nchains, const double *tilerec, double *scr,
                          double *xg, uint32_t *status, int step, const double *ir, hipStream_t s);
 void launch_chain_group(bool apply, const ChainDesc *chains, const GroupDesc *groups, int ngroups,
@@ -186,6 +188,9 @@ struct mabd_ctx {
   double *d_grouprec = nullptr, *d_xtop = nullptr;
   int *d_gcount = nullptr;
   int tile_threads = 64;     // workgroup size of the chain tile kernels (autotuned)
+  bool tile_pack = true;     // packed 64-thread tiles (autotuned)
+  // packed tiles, per group of four tiles: survivors and factors
+  double *d_psv = nullptr, *d_pcf = nullptr;
   bool top_in_group = true;  // every chain's top system fits one workgroup
   bool tuned = false;
   // captured step graphs, one per state-buffer parity
@@ -348,17 +353,20 @@ struct PhaseTimer {
 }  // namespace
 
 namespace {
-// Tiles of tile_threads - 2 rows and groups of GROUP_T + 1 interface rows for
-// every chain; descriptors go to preallocated device buffers (sized for the
-// smallest tiles), so re-tuning only rewrites them.
-hipError_t build_tiles(mabd_ctx *c, int tt) {
+// Tiles of tile_threads - 2 rows (PACK_T rows for packed tiles) and groups of
+// GROUP_T + 1 interface rows for every chain; descriptors go to preallocated
+// device buffers (sized for the smallest tiles), so re-tuning only rewrites
+// them.
+hipError_t build_tiles(mabd_ctx *c, int tt, bool pack) {
+  if (pack) tt = 64;
   c->tile_threads = tt;
+  c->tile_pack = pack;
   c->tiles.clear();
   c->groups.clear();
   c->ngrows = 0;
   c->ntop = 0;
   c->top_in_group = true;
-  const int TT = tt - 2;
+  const int TT = pack ? PACK_T : tt - 2;
   for (size_t ci = 0; ci < c->chains.size(); ++ci) {
     ChainDesc &cd = c->chains[ci];
     const int K = cd.K;
@@ -667,7 +675,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     c->chains.push_back(cd);
   }
   c->nchain_bodies = (int)c->sol2in.size();
-  (void)build_tiles(c, 64);  // sizes every tile buffer for the smallest tiles
+  (void)build_tiles(c, 64, true);  // sizes every tile buffer for the smallest tiles
   // generic (tree) components
   c->gb0 = c->nchain_bodies;
   std::vector<int> gidx(m, -1);  // input joint -> generic joint
@@ -1063,6 +1071,11 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(dalloc(c, &c->d_grouprec, (size_t)TILE_REC * c->groups.size()));
   if (e == hipSuccess) chk(dalloc(c, &c->d_xtop, (size_t)3 * c->ntop));
   if (e == hipSuccess) chk(dalloc(c, &c->d_gcount, std::max<size_t>(c->chains.size(), 1)));
+  {
+    const size_t ngrp = (c->tiles.size() + 3) / 4;
+    if (e == hipSuccess) chk(dalloc(c, &c->d_psv, (size_t)PACK_SV * 64 * ngrp));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_pcf, (size_t)PACK_CF * 64 * ngrp));
+  }
   if (e == hipSuccess) chk(hipMemset(c->d_gcount, 0, std::max<size_t>(c->chains.size(), 1) * sizeof(int)));
   if (e == hipSuccess) chk(dalloc(c, &c->d_grow, (size_t)GROW_REC * c->ntop));
   if (e == hipSuccess) chk(dalloc(c, &c->d_xg, (size_t)3 * c->ngrows));
@@ -1188,11 +1201,14 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(dalloc(c, &c->d_status, 4));
   if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_status, 4 * sizeof(uint32_t)));
   // after every buffer is sized for the smallest tiles
+  // "64p" (packed), 64, 128 or 256: fixed by the environment, no autotuning
   if (const char *tt = std::getenv("MABD_CHAIN_TILE_THREADS")) {
-    const int v = std::atoi(tt);
-    if (v == 64 || v == 128 || v == 256) {
-      c->tuned = true;  // fixed by the environment: no autotuning
-      if (e == hipSuccess && v != 64) chk(build_tiles(c, v));
+    const std::string v(tt);
+    const bool pack = v == "64p";
+    const int n = pack ? 64 : std::atoi(tt);
+    if (pack || v == "64" || v == "128" || v == "256") {
+      c->tuned = true;
+      if (e == hipSuccess) chk(build_tiles(c, n, pack));
     }
   }
   if (e != hipSuccess) {
@@ -1206,6 +1222,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   c->stats.n_graph = c->ngraph;
   c->stats.n_dyn = c->nd;
   c->stats.tile_threads = c->tile_threads;
+  c->stats.tile_packed = c->tile_pack ? 1 : 0;
   c->stats.tree_rounds = ((int)c->tc_rounds.size() - 1) / 7;
   c->stats.rho_p = c->stats.rho_d = c->stats.kkt = -1.0;
   *out = c;
@@ -1457,11 +1474,14 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
     ca.part = c->d_part;
     ca.ir = c->d_ir;
     ca.wr = c->wr_on ? c->d_wr : nullptr;
+    ca.psv = c->d_psv;
+    ca.pcf = c->d_pcf;
     const int ntl = (int)c->tiles.size(), tt = c->tile_threads;
+    const bool pk = c->tile_pack;
     // one chain solve: tile reduction, interface solve, tile back-substitution
     auto solve = [&](int mode) {
       const double *irs = mode == 2 ? c->d_ir : nullptr;
-      tm.run(0, [&] { launch_chain_reduce(ca, ntl, tt, mode, s); });
+      tm.run(0, [&] { launch_chain_reduce(ca, ntl, tt, pk, mode, s); });
       tm.run(1, [&] {
         launch_chain_group(false, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
                            c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, 0, irs, s);
@@ -1471,7 +1491,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
         launch_chain_group(true, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
                            c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, 0, irs, s);
       });
-      tm.run(2, [&] { launch_chain_apply(ca, ntl, tt, mode, s); });
+      tm.run(2, [&] { launch_chain_apply(ca, ntl, tt, pk, mode, s); });
     };
     if (c->opt.precision == 0) {
       solve(0);
@@ -1594,10 +1614,13 @@ hipError_t autotune(mabd_ctx *c, double h) {
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return hipErrorUnknown; }
   NoTimer nt;
   int best = c->tile_threads;
+  bool best_pack = c->tile_pack;
   float best_ms = 1e30f;
   hipError_t e = hipSuccess;
-  for (int tt : {64, 128, 256}) {
-    e = build_tiles(c, tt);
+  const std::pair<int, bool> cand[] = {{64, true}, {64, false}, {128, false}, {256, false}};
+  for (const auto &cv : cand) {
+    const int tt = cv.first;
+    e = build_tiles(c, tt, cv.second);
     if (e != hipSuccess) break;
     launch_reset_status(c->d_status, s);
     e = issue_step(c, h, c->cur, 1 - c->cur, nt);  // writes only the scratch buffer
@@ -1609,11 +1632,11 @@ hipError_t autotune(mabd_ctx *c, double h) {
     if (e != hipSuccess) break;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_ms) { best_ms = ms; best = tt; }
+    if (ms < best_ms) { best_ms = ms; best = tt; best_pack = cv.second; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (e == hipSuccess) e = build_tiles(c, best);
+  if (e == hipSuccess) e = build_tiles(c, best, best_pack);
   return e;
 }
 
@@ -1677,6 +1700,7 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
   graph = graph && c->gexec[0] && c->gexec[1];
   c->stats.graph_replay = graph ? 1 : 0;
   c->stats.tile_threads = c->tile_threads;
+  c->stats.tile_packed = c->tile_pack ? 1 : 0;
   for (int st = 0; st < nsteps; ++st) {
     const int a = c->cur, b = 1 - c->cur;
     hipError_t le;

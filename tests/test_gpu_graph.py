@@ -118,15 +118,18 @@ def test_autotuned_tiles_match_oracle():
         assert eq < 1e-10 and eqd < 1e-10
 
 
-@pytest.mark.parametrize("tt", [64, 128, 256])
+@pytest.mark.parametrize("tt", ["64p", "64", "128", "256"])
 def test_forced_tile_size(tt, monkeypatch):
-    """MABD_CHAIN_TILE_THREADS fixes the tile size at create (no autotuning)."""
+    """MABD_CHAIN_TILE_THREADS fixes the tile size at create (no autotuning);
+    "64p" selects the packed 60-row tiles."""
     import paper_2603_08079_amd as pk
 
-    monkeypatch.setenv("MABD_CHAIN_TILE_THREADS", str(tt))
+    monkeypatch.setenv("MABD_CHAIN_TILE_THREADS", tt)
     asm = mi.chain(5000, seed=38)
     ctx = pk.Context(asm)
-    assert ctx.stats()["tile_threads"] == tt
+    st = ctx.stats()
+    assert st["tile_threads"] == int(tt.rstrip("p"))
+    assert st["tile_packed"] == (1 if tt.endswith("p") else 0)
     ctx.step(asm.h, 2)
     q, qd = asm.q0, asm.qd0
     s = oracle.System(asm)

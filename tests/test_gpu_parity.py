@@ -132,6 +132,19 @@ def test_chain_tile_edges(n):
     say("worst", teacher_forced(asm, 2))
 
 
+@pytest.mark.parametrize("tt", ["64p", "64"])
+def test_chain_tails_in_one_context(tt, monkeypatch):
+    """Many chains in one context whose last tiles take every row count from
+    1 to 62, so that groups of four packed tiles mix chains, full and ragged
+    tiles, and the last group is partial."""
+    monkeypatch.setenv("MABD_CHAIN_TILE_THREADS", tt)
+    parts = [mi.chain(n, seed=1000 + n) for n in range(3, 130)]
+    asm = mi.concat(parts, name="tails")
+    asm.qd0 = asm.qd0 + np.random.default_rng(41).normal(0, 0.05, asm.qd0.shape) * (asm.pinned == 0)[:, None]
+    say("chain tails", tt, "bodies", asm.n)
+    say("worst", teacher_forced(asm, 2))
+
+
 def test_chain_variants():
     """No pinned body (free chain), a world joint at the far end, and joints
     listed with reversed sides (flags of the row ends)."""
