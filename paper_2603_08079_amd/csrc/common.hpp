@@ -115,9 +115,12 @@ __device__ __forceinline__ void raise_flag(uint32_t *st, uint32_t bits, int /*un
   atomicMin(reinterpret_cast<int *>(st + 1), *reinterpret_cast<const volatile int *>(st + 2));
 }
 // a step after a failed one does nothing, so the last good state survives
+// (two relaxed device-scope reads, issued together)
 __device__ __forceinline__ bool skip_step(const uint32_t *st, int /*unused*/) {
-  return *reinterpret_cast<const volatile int *>(st + 1) <
-         *reinterpret_cast<const volatile int *>(st + 2);
+  int *s = const_cast<int *>(reinterpret_cast<const int *>(st));
+  const int fail = __hip_atomic_load(s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int cur = __hip_atomic_load(s + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return fail < cur;
 }
 #endif
 

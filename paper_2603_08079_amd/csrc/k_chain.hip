@@ -283,7 +283,10 @@ template <int MODE, bool APPLY, int NT, bool WR, bool PACK>
 __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES_REDUCE) void chain_tile_kernel(
     ChainArgs a) {
   using breal = typename std::conditional<MODE == 0, double, float>::type;
-  __shared__ double lds[S_N * NT];
+  // packed apply pass: the packed factors and the interface x are staged
+  // after the exchange slots (read with phase A's loads, used after phase C)
+  constexpr int STG = S_N * NT, STG_X = STG + PACK_CF * 16;
+  __shared__ double lds[S_N * NT + (PACK && APPLY ? PACK_CF * 16 + 6 : 0)];
   if (skip_step(a.status, a.step)) return;
   if constexpr (MODE == 2) {
     if (a.ir[0] != 0.0) return;
@@ -312,22 +315,61 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
   double Waa[6] = {0, 0, 0, 0, 0, 0}, Wab[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   double va[3] = {0, 0, 0}, ca[3] = {0, 0, 0}, ta[3] = {0, 0, 0};
   double Wbb[6] = {0, 0, 0, 0, 0, 0}, vb[3] = {0, 0, 0}, cb[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
-  const double *T_h = nullptr;
-  double q[12];  // kept for the state update of the apply pass
-  if (has_a) {
-    for (int i = 0; i < 3; ++i) pa[i] = a.pr[i * a.nrs + gra];
-    sa = (a.flag[gra] & 2) ? 1.0 : -1.0;
-  }
-  if (has_b) {
-    for (int i = 0; i < 3; ++i) pb[i] = a.pl[i * a.nrs + grb];
-    sb = (a.flag[grb] & 1) ? 1.0 : -1.0;
+  const double *T_h = nullptr, *shc = nullptr;
+  double sh[7], hv[HINV_STRIDE];  // shape constants and Hbar^{-1}, read during the polar
+  // Every independent read of phase A is issued before the first use, with
+  // indices clamped in bounds for lanes without the row or the body: the
+  // kernel is bound by memory latency, and reads issued under branches or
+  // after the polar would each cost a round trip of their own.
+  double q[12];    // kept for the state update of the apply pass
+  double qd0[12];  // qdot (MODE 2: the FP64 primal residual)
+  {
+    const int64_t ia = has_a ? gra : 0, ib = has_b ? grb : 0, ibg = has_body ? bg : 0;
+    const uint8_t fa = a.flag[ia], fb = a.flag[ib];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      pa[i] = a.pr[i * a.nrs + ia];
+      pb[i] = a.pl[i * a.nrs + ib];
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) q[c] = a.q[c * a.ns + ibg];
+    const double *src = MODE == 2 ? a.rp : a.qd;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) qd0[c] = src[c * a.ns + ibg];
+    const int s = a.shp[ibg];
+    T_h = a.hinv + (int64_t)HINV_STRIDE * s;
+    shc = a.shape + (int64_t)SHAPE_STRIDE * s;
+    if constexpr (PACK && APPLY) {
+      const int li = t - 1, j = li >> 2, Tp = (T + 3) >> 2;
+      if (t >= 1 && t <= T + 1 && (li & 3) == 0 && j > 0 && j < Tp) {
+        const double *cf = a.pcf + (int64_t)(ti >> 2) * (PACK_CF * 64) + 16 * (ti & 3) + j;
+        double v[PACK_CF];
+#pragma unroll
+        for (int k = 0; k < PACK_CF; ++k) v[k] = cf[k * 64];
+#pragma unroll
+        for (int k = 0; k < PACK_CF; ++k) lds[STG + k * 16 + j] = v[k];
+      }
+      if (t == 1 || t == T + 1) {
+        const int64_t gi = (int64_t)cd.grow0 + td.tidx + (t == T + 1 ? 1 : 0);
+        double v[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) v[i] = a.xg[3 * gi + i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) lds[STG_X + (t == 1 ? 0 : 3) + i] = v[i];
+      }
+    }
+    if (has_a) sa = (fa & 2) ? 1.0 : -1.0;
+    else pa[0] = pa[1] = pa[2] = 0.0;
+    if (has_b) sb = (fb & 1) ? 1.0 : -1.0;
+    else pb[0] = pb[1] = pb[2] = 0.0;
   }
   if (has_body) {
+    {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) q[c] = a.q[c * a.ns + bg];
-    const int s = a.shp[bg];
-    T_h = a.hinv + (int64_t)HINV_STRIDE * s;
-    const double *sh = a.shape + (int64_t)SHAPE_STRIDE * s;
+      for (int i = 0; i < 7; ++i) sh[i] = shc[i];
+#pragma unroll
+      for (int i = 0; i < HINV_STRIDE; ++i) hv[i] = T_h[i];
+    }
     double A[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -348,7 +390,7 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
       for (int c = 0; c < 4; ++c) {
         breal w[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) w[i] = breal(a.rp[(3 * c + i) * a.ns + bg]);
+        for (int i = 0; i < 3; ++i) w[i] = breal(qd0[3 * c + i]);
         mat3t_vec(R, w, phi + 3 * c);
       }
     } else {
@@ -356,16 +398,16 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         qb[c] = breal(q[c]);
-        qdb[c] = breal(a.qd[c * a.ns + bg]);
+        qdb[c] = breal(qd0[c]);
       }
       local_force<breal>(sh, R, Ab, qb, qb, qdb, a.g, a.h, phi, WR ? a.wr : nullptr, a.ns, bg);
     }
-    hinv_apply(T_h, phi, u);
+    hinv_apply(hv, phi, u);
     const breal paf[3] = {breal(pa[0]), breal(pa[1]), breal(pa[2])};
     const breal pbf[3] = {breal(pb[0]), breal(pb[1]), breal(pb[2])};
     if (has_a) {
       breal W[9], RW[9];
-      wblock(T_h, paf, paf, W);
+      wblock(hv, paf, paf, W);
       rot_congr(R, W, RW);
       double RWd[9];
 #pragma unroll
@@ -389,7 +431,7 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
     }
     if (has_b) {
       breal W[9], RW[9];
-      wblock(T_h, pbf, pbf, W);
+      wblock(hv, pbf, pbf, W);
       rot_congr(R, W, RW);
       double RWd[9];
 #pragma unroll
@@ -413,7 +455,7 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
     }
     if (has_a && has_b) {
       breal W[9], RW[9];
-      wblock(T_h, paf, pbf, W);
+      wblock(hv, paf, pbf, W);
       rot_congr(R, W, RW);
 #pragma unroll
       for (int i = 0; i < 9; ++i) Wab[i] = double(RW[i]) * (sa * sb);
@@ -526,20 +568,24 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
       const int j = li >> 2, Tp = (T + 3) >> 2;
       if (row_active && (li & 3) == 0 && j > 0 && j < Tp) {
         elim_d = 4 * (j & -j);
-        const double *cf = a.pcf + (int64_t)(ti >> 2) * (PACK_CF * 64) + 16 * (ti & 3) + j;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-          PL[i] = cf[i * 64];
-          PU[i] = cf[(9 + i) * 64];
+          PL[i] = lds[STG + i * 16 + j];
+          PU[i] = lds[STG + (9 + i) * 16 + j];
         }
 #pragma unroll
-        for (int i = 0; i < 3; ++i) Pb[i] = cf[(18 + i) * 64];
+        for (int i = 0; i < 3; ++i) Pb[i] = lds[STG + (18 + i) * 16 + j];
       }
     }
     if (row_active && (li == 0 || li == T)) {
-      const int64_t gi = (int64_t)cd.grow0 + td.tidx + (li == T ? 1 : 0);
+      if constexpr (PACK) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) lds[(S_X + i) * NT + li] = a.xg[3 * gi + i];
+        for (int i = 0; i < 3; ++i) lds[(S_X + i) * NT + li] = lds[STG_X + (li == T ? 3 : 0) + i];
+      } else {
+        const int64_t gi = (int64_t)cd.grow0 + td.tidx + (li == T ? 1 : 0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) lds[(S_X + i) * NT + li] = a.xg[3 * gi + i];
+      }
     }
     __syncthreads();
     tile_cr_backward<NT>(lds, row_active, li, T, elim_d, PL, PU, Pb);
