@@ -636,6 +636,7 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
       breal hg[12];
       hinv_apply(T_h, g12, hg);
       const double ih = 1.0 / a.h;
+      bool finite = true;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         breal dp[3], dqv[3];
@@ -654,9 +655,10 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
           } else {
             a.dq[o] += d;
           }
-          if (!isfinite(d)) raise_flag(a.status, FLAG_NONFINITE, a.step);
+          finite = finite && isfinite(d);
         }
       }
+      if (!finite) raise_flag(a.status, FLAG_NONFINITE, a.step);
     }
   }
 }
