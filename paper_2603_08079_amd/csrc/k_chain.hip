@@ -784,11 +784,15 @@ DEV void top_solve(double *lds, const ChainDesc &cd, const double *grouprec, dou
 // through the tile's Schur block U.  Groups of GROUP_T + 1 interface rows are
 // reduced like tiles (reduce variant: Schur record of the group's two end
 // rows) and back-substituted once the top system is solved (apply variant:
-// x of every interface row).
+// x of every interface row).  The reduce variant keeps the factors
+// (PL, PU, Pb) of the rows it eliminates in gfac ([PACK_CF][CHAIN_THREADS]
+// per group); the apply variant reads them back instead of repeating the
+// elimination (every interior row li is eliminated at level lowbit(li)).
 template <bool APPLY>
 __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
     const ChainDesc *chains, const GroupDesc *groups, const double *tilerec, double *grouprec,
-    double *xtop, double *xg, int *counters, uint32_t *status, int step, const double *ir) {
+    double *xtop, double *xg, double *gfac, int *counters, uint32_t *status, int step,
+    const double *ir) {
   __shared__ double lds[S_N * CHAIN_THREADS];
   if (skip_step(status, step)) return;
   if (ir && ir[0] != 0.0) return;  // form 1 correction after convergence
@@ -799,6 +803,31 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
   const int gi = gd.g0 + li;               // chain-local interface row
   const int n = cd.ntile + 1;
   const bool row_active = li <= T;
+  double *fac = gfac + (int64_t)blockIdx.x * (PACK_CF * CHAIN_THREADS) + li;
+  if constexpr (APPLY) {
+    double PL[9], PU[9], Pb[3];
+    int elim_d = 0;
+    if (row_active && li > 0 && li < T) {
+      elim_d = li & -li;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        PL[i] = fac[i * CHAIN_THREADS];
+        PU[i] = fac[(9 + i) * CHAIN_THREADS];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) Pb[i] = fac[(18 + i) * CHAIN_THREADS];
+    }
+    if (row_active && (li == 0 || li == T)) {
+      const int64_t ti = (int64_t)cd.gtop0 + gd.gidx + (li == T ? 1 : 0);
+      for (int i = 0; i < 3; ++i) lds[(S_X + i) * CHAIN_THREADS + li] = xtop[3 * ti + i];
+    }
+    __syncthreads();
+    tile_cr_backward<CHAIN_THREADS>(lds, row_active, li, T, elim_d, PL, PU, Pb);
+    const bool last = gd.gidx == cd.ngroup - 1;
+    if (row_active && (li < T || last))
+      for (int i = 0; i < 3; ++i) xg[3 * ((int64_t)cd.grow0 + gi) + i] = lds[(S_X + i) * CHAIN_THREADS + li];
+    return;
+  }
   const double *TR = tilerec + (int64_t)TILE_REC * cd.tile0;
   double L[9], D[6], U[9], b[3];
 #pragma unroll
@@ -824,7 +853,16 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
   double PL[9], PU[9], Pb[3];
   int elim_d = 0;
   tile_cr_forward<CHAIN_THREADS>(lds, row_active, li, T, T, L, D, U, b, PL, PU, Pb, elim_d, status, step);
-  if constexpr (!APPLY) {
+  if (elim_d > 0) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      fac[i * CHAIN_THREADS] = PL[i];
+      fac[(9 + i) * CHAIN_THREADS] = PU[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) fac[(18 + i) * CHAIN_THREADS] = Pb[i];
+  }
+  {
     double *rec = grouprec + (int64_t)TILE_REC * (cd.group0 + gd.gidx);
     if (row_active && li == 0) {
       for (int i = 0; i < 6; ++i) rec[i] = D[i];
@@ -852,16 +890,6 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
         if (threadIdx.x == 0) counters[gd.chain] = 0;
       }
     }
-  } else {
-    if (row_active && (li == 0 || li == T)) {
-      const int64_t ti = (int64_t)cd.gtop0 + gd.gidx + (li == T ? 1 : 0);
-      for (int i = 0; i < 3; ++i) lds[(S_X + i) * CHAIN_THREADS + li] = xtop[3 * ti + i];
-    }
-    __syncthreads();
-    tile_cr_backward<CHAIN_THREADS>(lds, row_active, li, T, elim_d, PL, PU, Pb);
-    const bool last = gd.gidx == cd.ngroup - 1;
-    if (row_active && (li < T || last))
-      for (int i = 0; i < 3; ++i) xg[3 * ((int64_t)cd.grow0 + gi) + i] = lds[(S_X + i) * CHAIN_THREADS + li];
   }
 }
 
@@ -1270,14 +1298,15 @@ void launch_chain_apply(const ChainArgs &a, int ntiles, int nt, bool pack, int m
 }
 void launch_chain_group(bool apply, const ChainDesc *chains, const GroupDesc *groups, int ngroups,
                         const double *tilerec, double *grouprec, double *xtop, double *xg,
-                        int *counters, uint32_t *status, int step, const double *ir, hipStream_t s) {
+                        double *gfac, int *counters, uint32_t *status, int step, const double *ir,
+                        hipStream_t s) {
   if (ngroups <= 0) return;
   if (apply)
     hipLaunchKernelGGL(chain_group_kernel<true>, dim3(ngroups), dim3(CHAIN_THREADS), 0, s, chains,
-                       groups, tilerec, grouprec, xtop, xg, counters, status, step, ir);
+                       groups, tilerec, grouprec, xtop, xg, gfac, counters, status, step, ir);
   else
     hipLaunchKernelGGL(chain_group_kernel<false>, dim3(ngroups), dim3(CHAIN_THREADS), 0, s, chains,
-                       groups, tilerec, grouprec, xtop, xg, counters, status, step, ir);
+                       groups, tilerec, grouprec, xtop, xg, gfac, counters, status, step, ir);
 }
 void launch_chain_global(const ChainDesc *chains, int nchains, const double *tilerec, double *scr,
                          double *xg, uint32_t *status, int step, const double *ir, hipStream_t s) {

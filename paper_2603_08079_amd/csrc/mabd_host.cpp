@@ -30,7 +30,8 @@ void launch_chain_global(const ChainDesc *chains, int nchains, const double *til
                          double *xg, uint32_t *status, int step, const double *ir, hipStream_t s);
 void launch_chain_group(bool apply, const ChainDesc *chains, const GroupDesc *groups, int ngroups,
                         const double *tilerec, double *grouprec, double *xtop, double *xg,
-                        int *counters, uint32_t *status, int step, const double *ir, hipStream_t s);
+                        double *gfac, int *counters, uint32_t *status, int step, const double *ir,
+                        hipStream_t s);
 void launch_chain_resid(const ChainArgs &a, int ntiles, int nt, hipStream_t s);
 void launch_chain_ir_check(const double *part, int nblk, double tol, int final_check, double *ir,
                            uint32_t *status, hipStream_t s);
@@ -186,6 +187,7 @@ struct mabd_ctx {
   TileDesc *d_tiles = nullptr;
   GroupDesc *d_groups = nullptr;
   double *d_grouprec = nullptr, *d_xtop = nullptr;
+  double *d_gfac = nullptr;  // factors of the group reductions, PACK_CF x CHAIN_THREADS per group
   int *d_gcount = nullptr;
   int tile_threads = 64;     // workgroup size of the chain tile kernels (autotuned)
   bool tile_pack = true;     // packed 64-thread tiles (autotuned)
@@ -1069,6 +1071,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(dalloc(c, &c->d_tilerec, (size_t)TILE_REC * c->tiles.size()));
   if (e == hipSuccess) chk(upload(c, &c->d_groups, c->groups));
   if (e == hipSuccess) chk(dalloc(c, &c->d_grouprec, (size_t)TILE_REC * c->groups.size()));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_gfac, (size_t)PACK_CF * CHAIN_THREADS * c->groups.size()));
   if (e == hipSuccess) chk(dalloc(c, &c->d_xtop, (size_t)3 * c->ntop));
   if (e == hipSuccess) chk(dalloc(c, &c->d_gcount, std::max<size_t>(c->chains.size(), 1)));
   {
@@ -1484,12 +1487,14 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       tm.run(0, [&] { launch_chain_reduce(ca, ntl, tt, pk, mode, s); });
       tm.run(1, [&] {
         launch_chain_group(false, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
-                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, 0, irs, s);
+                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_gfac, c->d_gcount, c->d_status, 0,
+                           irs, s);
         if (!c->top_in_group)
           launch_chain_global(c->d_chains, (int)c->chains.size(), c->d_grouprec, c->d_grow,
                               c->d_xtop, c->d_status, 0, irs, s);
         launch_chain_group(true, c->d_chains, c->d_groups, (int)c->groups.size(), c->d_tilerec,
-                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_gcount, c->d_status, 0, irs, s);
+                           c->d_grouprec, c->d_xtop, c->d_xg, c->d_gfac, c->d_gcount, c->d_status, 0,
+                           irs, s);
       });
       tm.run(2, [&] { launch_chain_apply(ca, ntl, tt, pk, mode, s); });
     };
