@@ -70,9 +70,9 @@ template <int NT>
 DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, int dend, double *L,
                          double *D, double *U, double *b, double *PL, double *PU, double *Pb,
                          int &elim_d, uint32_t *status, int step) {
-  for (int d = 1; d < dend; d *= 2) {
-    const bool active = row_active && (li % d == 0 || li == T);
-    const bool elim = active && li < T && (li % (2 * d) == d);
+  for (int d = 1; d < dend; d *= 2) {  // d is a power of two: masks for mod and div
+    const bool active = row_active && ((li & (d - 1)) == 0 || li == T);
+    const bool elim = active && li < T && ((li & (2 * d - 1)) == d);
     if (elim) {
       double Df[9], Di[9];
       full_from_sym(D, Df);
@@ -123,8 +123,8 @@ DEV void tile_cr_forward(double *lds, bool row_active, int li, int T, int dend, 
 #pragma unroll
         for (int i = 0; i < 9; ++i) U[i] = lds[(S_UN + i) * NT + e];
       }
-      const int lf = li == T ? d * ((T - 1) / d) : li - d;
-      if (li > 0 && lf > 0 && (lf % (2 * d) == d)) {
+      const int lf = li == T ? ((T - 1) & ~(d - 1)) : li - d;
+      if (li > 0 && lf > 0 && ((lf & (2 * d - 1)) == d)) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) D[i] -= lds[(S_DR + i) * NT + lf];
 #pragma unroll
@@ -724,10 +724,13 @@ DEV void top_solve(double *lds, const ChainDesc &cd, const double *grouprec, dou
     double M[36], r[6];
     double D0[9], DT[9];
     double s0[6], s1[6];
+#pragma unroll
     for (int i = 0; i < 6; ++i) { s0[i] = lds[(S_PL + i) * CHAIN_THREADS]; s1[i] = lds[(S_PL + i) * CHAIN_THREADS + 1]; }
     full_from_sym(s0, D0);
     full_from_sym(s1, DT);
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
       for (int j = 0; j < 3; ++j) {
         const double u = lds[(S_PU + 3 * i + j) * CHAIN_THREADS];
         M[6 * i + j] = D0[3 * i + j];
@@ -735,38 +738,49 @@ DEV void top_solve(double *lds, const ChainDesc &cd, const double *grouprec, dou
         M[6 * i + j + 3] = u;
         M[6 * (j + 3) + i] = u;
       }
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
       r[i] = lds[(S_PB + i) * CHAIN_THREADS];
       r[3 + i] = lds[(S_PB + i) * CHAIN_THREADS + 1];
     }
-    // Cholesky 6x6
+    // Cholesky 6x6, fully unrolled (constant indices keep M and r in
+    // registers); a non-positive pivot is replaced by 1 and reported
     bool ok = true;
-    for (int j = 0; j < 6 && ok; ++j) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
       double d = M[6 * j + j];
+#pragma unroll
       for (int k = 0; k < j; ++k) d -= M[6 * j + k] * M[6 * j + k];
-      if (!(d > 0.0)) { ok = false; break; }
-      d = sqrt(d);
+      ok = ok && d > 0.0;
+      d = d > 0.0 ? sqrt(d) : 1.0;
       M[6 * j + j] = d;
+      const double id = 1.0 / d;
+#pragma unroll
       for (int i = j + 1; i < 6; ++i) {
         double v = M[6 * i + j];
+#pragma unroll
         for (int k = 0; k < j; ++k) v -= M[6 * i + k] * M[6 * j + k];
-        M[6 * i + j] = v / d;
+        M[6 * i + j] = v * id;
       }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double v = r[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) v -= M[6 * i + k] * r[k];
+      r[i] = v / M[6 * i + i];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+      double v = r[i];
+#pragma unroll
+      for (int k = i + 1; k < 6; ++k) v -= M[6 * k + i] * r[k];
+      r[i] = v / M[6 * i + i];
     }
     if (!ok) {
       raise_flag(status, FLAG_SINGULAR, step);
+#pragma unroll
       for (int i = 0; i < 6; ++i) r[i] = 0.0;
-    } else {
-      for (int i = 0; i < 6; ++i) {
-        double v = r[i];
-        for (int k = 0; k < i; ++k) v -= M[6 * i + k] * r[k];
-        r[i] = v / M[6 * i + i];
-      }
-      for (int i = 5; i >= 0; --i) {
-        double v = r[i];
-        for (int k = i + 1; k < 6; ++k) v -= M[6 * k + i] * r[k];
-        r[i] = v / M[6 * i + i];
-      }
     }
     for (int i = 0; i < 3; ++i) {
       lds[(S_X + i) * CHAIN_THREADS + 0] = r[i];
