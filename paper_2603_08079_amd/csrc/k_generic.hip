@@ -216,6 +216,8 @@ DEV void team_sync() {
 // factors.
 struct PrepLds {
   double L[TREE_KLDS * 12];
+  double th[HINV_STRIDE];   // Hbar^{-1} of the body
+  double uu[12];            // its local solve u
   int ek[24];               // clique entries: joint,
   int ei[24];               // first row << 8 | rows << 4 | unary << 1 | side
   uint8_t rowent[TREE_KMAX];  // clique row -> entry
@@ -235,8 +237,16 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   const int e0 = a.tabs_off[slot], e1 = a.tabs_off[slot + 1];
   const int ne = a.tne[slot];
   const int nent = e1 - e0 + (kpar >= 0 ? 1 : 0);
-  // 1) clique entries (absorbed joints in list order, then the parent joint),
-  //    fetched in parallel; their rows and the row -> entry map
+  // 1) Hbar^{-1} and u of the body and the clique entries (absorbed joints
+  //    in list order, then the parent joint), fetched together (every read
+  //    issued before the first store); their rows and the row -> entry map
+  {
+    const double t0 = Th[ln], t1 = ln + TEAM < HINV_STRIDE ? Th[ln + TEAM] : 0.0;
+    const double u0 = ln < 12 ? a.u[(int64_t)ln * a.ns + b] : 0.0;
+    S.th[ln] = t0;
+    if (ln + TEAM < HINV_STRIDE) S.th[ln + TEAM] = t1;
+    if (ln < 12) S.uu[ln] = u0;
+  }
   for (int e = ln; e < nent; e += TEAM) {
     int k, side, un;
     int rows;
@@ -274,6 +284,17 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   const bool big = nr > TREE_KLDS;
   double *Lm = big ? fac + LD * LD + LD : S.L;
   double *Ym = fac + LD * LD + LD + 12 * nr;  // large cliques only
+  //    C of the unary rows this lane sums into y0 below, read with the rows
+  double cv[TREE_KMAX / TEAM];
+#pragma unroll
+  for (int k = 0; k < TREE_KMAX / TEAM; ++k) {
+    const int i = ln + k * TEAM;
+    cv[k] = 0.0;
+    if (i < nr) {
+      const int e = S.rowent[i], ei = S.ei[e];
+      if (ei & 2) cv[k] = a.gl[(int64_t)GL_STRIDE * S.ek[e] + GL_C + (i - (ei >> 8))];
+    }
+  }
   //    clique rows L (nr x 12), four independent loads per lane in flight
   for (int base = 0; base < nr * 12; base += 4 * TEAM) {
     double v[4];
@@ -296,7 +317,7 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
     //      y_j = Hbar^{-1} L_j^T in registers and forms column j
     if (ln < nr) {
       double yv[12];
-      hinv_apply(Th, Lm + 12 * ln, yv);
+      hinv_apply(S.th, Lm + 12 * ln, yv);
       for (int i = ln; i < nr; ++i) {
         double v = 0.0;
 #pragma unroll
@@ -308,7 +329,7 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
     // 2) Y = Hbar^{-1} L^T, one clique row per lane
     for (int col = ln; col < nr; col += TEAM) {
       double yv[12];
-      hinv_apply(Th, Lm + 12 * col, yv);
+      hinv_apply(S.th, Lm + 12 * col, yv);
       for (int s = 0; s < 12; ++s) Ym[s * nr + col] = yv[s];
     }
     team_sync();
@@ -325,12 +346,15 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
     }
   }
   //    y0 = L u + C of one-sided and parent rows
-  for (int i = ln; i < nr; i += TEAM) {
-    double v = 0.0;
-    for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * a.u[s * a.ns + b];
-    const int e = S.rowent[i], ei = S.ei[e];
-    if (ei & 2) v += a.gl[(int64_t)GL_STRIDE * S.ek[e] + GL_C + (i - (ei >> 8))];
-    fac[LD * LD + i] = v;
+#pragma unroll
+  for (int k = 0; k < TREE_KMAX / TEAM; ++k) {
+    const int i = ln + k * TEAM;
+    if (i < nr) {
+      double v = 0.0;
+#pragma unroll
+      for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * S.uu[s];
+      fac[LD * LD + i] = v + cv[k];
+    }
   }
 }
 
