@@ -30,6 +30,8 @@ struct ChainDesc {
   int32_t ngroup; // groups of interface rows; top rows = ngroup + 1
   int32_t group0; // first group (global index; also its record index)
   int32_t gtop0;  // first top row (global index)
+  int32_t top_global;  // 1: the top system is reduced by chain_global_kernel
+                       // (more than CHAIN_THREADS rows), 0: by the last group
 };
 
 // A group covers chain-local interface rows [g0, g0 + T] (T >= 1), reduced in

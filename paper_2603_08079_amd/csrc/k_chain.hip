@@ -889,7 +889,7 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
     }
     // The last group of the chain to finish solves the top system (its
     // ngroup + 1 rows fit one workgroup); longer chains use chain_global.
-    if (cd.ngroup + 1 <= CHAIN_THREADS) {
+    if (!cd.top_global) {
       __shared__ int is_last;
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -909,13 +909,14 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
 
 // Interface system of each chain: rows gi = 0..ntile, block tridiagonal,
 // solved by block cyclic reduction in global scratch (one workgroup per chain).
-__global__ __launch_bounds__(1024) void chain_global_kernel(const ChainDesc *chains,
+__global__ __launch_bounds__(256) void chain_global_kernel(const ChainDesc *chains,
                                                            const double *tilerec, double *scr,
                                                            double *xg, uint32_t *status, int step,
                                                            const double *ir) {
   if (skip_step(status, step)) return;
   if (ir && ir[0] != 0.0) return;
   const ChainDesc cd = chains[blockIdx.x];
+  if (!cd.top_global) return;  // solved by the last group workgroup
   // top system: the rows that bound the groups (records in tilerec = group records)
   const int n = cd.ngroup + 1;
   double *S = scr + (int64_t)GROW_REC * cd.gtop0;
@@ -1325,7 +1326,7 @@ void launch_chain_group(bool apply, const ChainDesc *chains, const GroupDesc *gr
 void launch_chain_global(const ChainDesc *chains, int nchains, const double *tilerec, double *scr,
                          double *xg, uint32_t *status, int step, const double *ir, hipStream_t s) {
   if (nchains > 0)
-    hipLaunchKernelGGL(chain_global_kernel, dim3(nchains), dim3(1024), 0, s, chains, tilerec, scr,
+    hipLaunchKernelGGL(chain_global_kernel, dim3(nchains), dim3(256), 0, s, chains, tilerec, scr,
                        xg, status, step, ir);
 }
 void launch_chain_resid(const ChainArgs &a, int ntiles, int nt, hipStream_t s) {

@@ -194,6 +194,9 @@ struct mabd_ctx {
   // packed tiles, per group of four tiles: survivors and factors
   double *d_psv = nullptr, *d_pcf = nullptr;
   bool top_in_group = true;  // every chain's top system fits one workgroup
+  // MABD_CHAIN_TOP_GLOBAL=1: every chain's top system goes through
+  // chain_global_kernel (the path of chains beyond ~3.9M rows), for testing
+  bool force_top_global = false;
   bool tuned = false;
   // captured step graphs, one per state-buffer parity
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -396,7 +399,8 @@ hipError_t build_tiles(mabd_ctx *c, int tt, bool pack) {
       c->groups.push_back(gd);
     }
     c->ntop += cd.ngroup + 1;
-    if (cd.ngroup + 1 > CHAIN_THREADS) c->top_in_group = false;
+    cd.top_global = (cd.ngroup + 1 > CHAIN_THREADS || c->force_top_global) ? 1 : 0;
+    if (cd.top_global) c->top_in_group = false;
   }
   if (!c->d_chains) return hipSuccess;  // not allocated yet (create sizes them first)
   hipError_t e = hipMemcpy(c->d_chains, c->chains.data(), c->chains.size() * sizeof(ChainDesc),
@@ -677,6 +681,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     c->chains.push_back(cd);
   }
   c->nchain_bodies = (int)c->sol2in.size();
+  if (const char *tg = std::getenv("MABD_CHAIN_TOP_GLOBAL")) c->force_top_global = std::atoi(tg) != 0;
   (void)build_tiles(c, 64, true);  // sizes every tile buffer for the smallest tiles
   // generic (tree) components
   c->gb0 = c->nchain_bodies;

@@ -145,6 +145,21 @@ def test_chain_tails_in_one_context(tt, monkeypatch):
     say("worst", teacher_forced(asm, 2))
 
 
+@pytest.mark.parametrize("tt", ["64p", "64", "256"])
+def test_chain_top_system_in_global_memory(tt, monkeypatch):
+    """MABD_CHAIN_TOP_GLOBAL=1 sends every chain's top system (the rows that
+    bound the groups of interface rows) through chain_global_kernel, the path
+    that chains of more than ~3.9M rows take; several chains of different
+    group counts in one context, two steps against the oracle."""
+    monkeypatch.setenv("MABD_CHAIN_TOP_GLOBAL", "1")
+    monkeypatch.setenv("MABD_CHAIN_TILE_THREADS", tt)
+    parts = [mi.chain(n, seed=n) for n in (40, 20_000, 70_000, 160_000)]
+    asm = mi.concat(parts, name="top_global")
+    asm.qd0 = asm.qd0 + np.random.default_rng(43).normal(0, 0.05, asm.qd0.shape) * (asm.pinned == 0)[:, None]
+    say("top system in global memory", tt, "bodies", asm.n)
+    say("worst", teacher_forced(asm, 2))
+
+
 def test_chain_variants():
     """No pinned body (free chain), a world joint at the far end, and joints
     listed with reversed sides (flags of the row ends)."""
