@@ -97,8 +97,15 @@ typedef struct {
                               bit 1: time every kernel group with HIP events (phase_ms)  */
   int32_t use_graph;       /* 1 (default): replay each step as a captured hipGraph when
                               the assembly has no PCG component and bit 1 is off        */
-  int32_t autotune;        /* 1 (default): at the first step, time the chain tile sizes
-                              (64, 128, 256 threads) and keep the fastest               */
+  int32_t autotune;        /* 1 (default): at the first step of a context with at least
+                              20,000 chain rows, time the chain tile forms (packed
+                              60-row tiles; 64, 128, 256 threads) and keep the fastest;
+                              without it packed tiles are used.  The environment
+                              variable MABD_CHAIN_TILE_THREADS = 64p, 64, 128 or 256
+                              fixes the form at mabd_create instead, and
+                              MABD_CHAIN_TOP_GLOBAL=1 sends every chain's top system
+                              through the global-memory reduction that chains beyond
+                              ~3.9M rows need (both for testing)                         */
   int32_t ir_max_sweeps;   /* precision 1: correction sweeps before NOT_CONVERGED, 0..16,
                               default 4                                                 */
   void *stream;            /* hipStream_t, or NULL for a library-owned stream             */

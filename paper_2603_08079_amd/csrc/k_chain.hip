@@ -4,20 +4,25 @@
 //
 // The dual system of a chain is block tridiagonal with 3x3 blocks.  Instead
 // of the serial block Thomas sweep the rows are cut into tiles of T + 1 rows
-// (T = workgroup size - 2) that share their first/last (interface) rows with
-// the neighbouring tiles.  One workgroup per tile
+// (T = workgroup size - 2, or PACK_T for packed tiles) that share their
+// first/last (interface) rows with the neighbouring tiles.  One workgroup per
+// tile
 //   A) computes the polar rotation, force and local solve of its bodies
 //      (one body per thread, coalesced SoA loads) and the rotated constant
 //      blocks R W(p, p') R^T with W = J(p) Hbar^{-1} J(p')^T;
 //   B) assembles its rows D, U, b (Eqs. chain-Schur-blocks, chain-b, with +C);
 //   C) runs block cyclic reduction on the tile interior (log2 levels, one
 //      row per thread, neighbours exchanged through LDS), which leaves the
-//      Schur complement on the two interface rows.
-// chain_global solves the block-tridiagonal system of interface rows (one
-// workgroup per chain, cyclic reduction in global memory), and chain_apply
-// repeats A-C, back-substitutes the tile, and writes lambda and the new state.
-// Recomputing A-C costs one more read of q, qdot but no HBM traffic for the
-// elimination factors.
+//      Schur complement on the two interface rows.  Packed tiles run the
+//      first two levels here and the rest in chain_pack_kernel, four tiles
+//      to a wave.
+// The interface rows form a block-tridiagonal system again, reduced in groups
+// of 256 rows (chain_group_kernel) whose end rows form the top system (solved
+// by the last group to finish, or by chain_global_kernel when it exceeds one
+// workgroup).  The apply pass repeats A-C, back-substitutes the tile, and
+// writes lambda and the new state.  Recomputing A-C costs one more read of
+// q, qdot but moves no dense elimination factors through HBM (packed tiles
+// read only the factors of the rows eliminated four tiles to a wave).
 #include <type_traits>
 
 #include "common.hpp"
