@@ -1,5 +1,7 @@
 // Generic-topology kernels of libmabd: per-shape factors, per-body co-rotated
 // solve, per-joint rows, tree elimination, back-projection, state gather.
+#include <algorithm>
+
 #include "common.hpp"
 #include "dmath.hpp"
 #include "generic.hpp"
@@ -778,11 +780,10 @@ DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, i
 }
 
 template <int R, int TW>
-__global__ __launch_bounds__(TCW) void tcw_rake_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
-  __shared__ TcwMat<R> team_sm[TCW / TW];
-  if (skip_step(a.status, a.step)) return;
+DEV void tcw_rake_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int blk, double *smem) {
+  TcwMat<R> *team_sm = reinterpret_cast<TcwMat<R> *>(smem);
   const int ln = tlane<TW>(), tm = (int)threadIdx.x / TW;
-  const int oi = op0 + (int)blockIdx.x * (TCW / TW) + tm;
+  const int oi = op0 + blk * (TCW / TW) + tm;
   if (oi >= op1) return;
   TcwMat<R> &sm = team_sm[tm];
   const TcOp op = a.ops[oi];
@@ -820,11 +821,10 @@ __global__ __launch_bounds__(TCW) void tcw_rake_kernel(TreeArgs a, const GJoint 
 }
 
 template <int R, int TW>
-__global__ __launch_bounds__(TCW) void tcw_compress_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
-  __shared__ TcwComp<R> team_sm[TCW / TW];
-  if (skip_step(a.status, a.step)) return;
+DEV void tcw_compress_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int blk, double *smem) {
+  TcwComp<R> *team_sm = reinterpret_cast<TcwComp<R> *>(smem);
   const int ln = tlane<TW>(), tm = (int)threadIdx.x / TW;
-  const int oi = op0 + (int)blockIdx.x * (TCW / TW) + tm;
+  const int oi = op0 + blk * (TCW / TW) + tm;
   if (oi >= op1) return;
   TcwComp<R> &sm = team_sm[tm];
   const TcOp op = a.ops[oi];
@@ -1011,11 +1011,10 @@ DEV void tcw_private_back(const TreeArgs &a, const GJoint *J, const TcOp &op, in
 }
 
 template <int R, int TW>
-__global__ __launch_bounds__(TCW) void tcw_rake_back_kernel(TreeArgs a, const GJoint *J, int op0, int op1) {
-  __shared__ double team_ks[TCW / TW][R * (R + 1) / 2];
-  if (skip_step(a.status, a.step)) return;
+DEV void tcw_rake_back_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int blk, double *smem) {
+  double(*team_ks)[R * (R + 1) / 2] = reinterpret_cast<double(*)[R * (R + 1) / 2]>(smem);
   const int tm = (int)threadIdx.x / TW;
-  const int oi = op0 + (int)blockIdx.x * (TCW / TW) + tm;
+  const int oi = op0 + blk * (TCW / TW) + tm;
   if (oi >= op1) return;
   const TcOp op = a.ops[oi];
   if (op.nv > R) {
@@ -1029,12 +1028,11 @@ __global__ __launch_bounds__(TCW) void tcw_rake_back_kernel(TreeArgs a, const GJ
 }
 
 template <int R, int TW>
-__global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, const GJoint *J, int op0,
-                                                               int op1) {
-  __shared__ double team_ks[TCW / TW][R * (R + 1) / 2];
-  if (skip_step(a.status, a.step)) return;
+DEV void tcw_compress_back_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int blk,
+                                double *smem) {
+  double(*team_ks)[R * (R + 1) / 2] = reinterpret_cast<double(*)[R * (R + 1) / 2]>(smem);
   const int ln = tlane<TW>(), tm = (int)threadIdx.x / TW;
-  const int oi = op0 + (int)blockIdx.x * (TCW / TW) + tm;
+  const int oi = op0 + blk * (TCW / TW) + tm;
   if (oi >= op1) return;
   const TcOp op = a.ops[oi];
   const int ce = op.ce, ck = op.ck;
@@ -1097,6 +1095,59 @@ __global__ __launch_bounds__(TCW) void tcw_compress_back_kernel(TreeArgs a, cons
     for (int r = 0; r < 10; ++r) lb[r] = r < 5 ? le[r] : lk[r - 5];
   }
   tcw_private_back<R, TW>(a, J, op, op.av - ce, lb, op.ev1 - 1, team_ks[tm]);
+}
+
+// One launch for several LDS-staged clique-size classes of one kind (rake or
+// compress) in a round.  Operations of one kind in a round touch disjoint
+// slots and read nothing the others write, so the classes need no ordering
+// among themselves: launched together they cost the latency of the slowest
+// operation instead of the sum over the classes.  Block b belongs to the
+// last segment whose first block is <= b; the dynamic LDS is sized by the
+// host for the largest class in the launch.
+enum { TC_RAKE16, TC_RAKE32, TC_RAKE64, TC_COMP16, TC_COMP32, TC_COMP48, TC_NCLASS };
+struct TcwSeg {
+  int32_t cls, op0, op1, blk0;
+};
+struct TcwLaunch {
+  TcwSeg seg[TC_NCLASS];
+  int32_t nseg;
+};
+
+template <bool BACK>
+__global__ __launch_bounds__(TCW) void tcw_round_kernel(TreeArgs a, const GJoint *J, TcwLaunch L) {
+  extern __shared__ double tcw_smem[];
+  if (skip_step(a.status, a.step)) return;
+  // fixed indices only (the launch record stays in kernel-argument memory)
+  int cls = L.seg[0].cls, op0 = L.seg[0].op0, op1 = L.seg[0].op1, blk0 = L.seg[0].blk0;
+#pragma unroll
+  for (int k = 1; k < TC_NCLASS; ++k) {
+    if (k < L.nseg && (int)blockIdx.x >= L.seg[k].blk0) {
+      cls = L.seg[k].cls;
+      op0 = L.seg[k].op0;
+      op1 = L.seg[k].op1;
+      blk0 = L.seg[k].blk0;
+    }
+  }
+  const int blk = (int)blockIdx.x - blk0;
+  if constexpr (!BACK) {
+    switch (cls) {
+      case TC_RAKE16: tcw_rake_body<16, 16>(a, J, op0, op1, blk, tcw_smem); break;
+      case TC_RAKE32: tcw_rake_body<32, 64>(a, J, op0, op1, blk, tcw_smem); break;
+      case TC_RAKE64: tcw_rake_body<64, 64>(a, J, op0, op1, blk, tcw_smem); break;
+      case TC_COMP16: tcw_compress_body<16, 16>(a, J, op0, op1, blk, tcw_smem); break;
+      case TC_COMP32: tcw_compress_body<32, 64>(a, J, op0, op1, blk, tcw_smem); break;
+      default: tcw_compress_body<48, 64>(a, J, op0, op1, blk, tcw_smem); break;
+    }
+  } else {
+    switch (cls) {
+      case TC_RAKE16: tcw_rake_back_body<16, 16>(a, J, op0, op1, blk, tcw_smem); break;
+      case TC_RAKE32: tcw_rake_back_body<32, 64>(a, J, op0, op1, blk, tcw_smem); break;
+      case TC_RAKE64: tcw_rake_back_body<64, 64>(a, J, op0, op1, blk, tcw_smem); break;
+      case TC_COMP16: tcw_compress_back_body<16, 16>(a, J, op0, op1, blk, tcw_smem); break;
+      case TC_COMP32: tcw_compress_back_body<32, 64>(a, J, op0, op1, blk, tcw_smem); break;
+      default: tcw_compress_back_body<48, 64>(a, J, op0, op1, blk, tcw_smem); break;
+    }
+  }
 }
 
 // ------------------------------------------------------ (d) back-projection
@@ -1221,7 +1272,6 @@ void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, in
     hipLaunchKernelGGL(gjoint_kernel, dim3((m + 127) / 128), dim3(128), 0, s, m, J, q, Rg, ns, hg, gl);
 }
 // operations of [o0, o1) with TW-lane teams, TCW / TW per workgroup
-static dim3 tcw_grid(int o0, int o1, int tw) { return dim3((unsigned)((o1 - o0 + TCW / tw - 1) / (TCW / tw))); }
 
 void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
                  hipStream_t s) {
@@ -1230,24 +1280,51 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
   // per round, 7 segments of the operation list (o[7] starts the next round):
   // rakes with cliques of <= 16, <= 32, <= 64 rows, then compresses with
   // cliques of <= 16, <= 32, <= 48 rows and larger (team kernels on the
-  // global slots)
+  // global slots).  A round's compresses are chosen after its rakes and add
+  // the condensed sides of children raked in the same round, and a leaf's
+  // back-substitution reads the multiplier of its parent joint, which a
+  // compress of the same round may solve: so rakes run before compresses,
+  // compress back-substitutions before rake back-substitutions, and the size
+  // classes of one kind share a launch.  When the 16-row class holds many
+  // operations (throughput-bound: its small LDS footprint keeps more of them
+  // resident) it gets a launch of its own.
+  static const int tw[TC_NCLASS] = {16, 64, 64, 16, 64, 64};
+  static const size_t lds_fwd[TC_NCLASS] = {4 * sizeof(TcwMat<16>),  sizeof(TcwMat<32>),
+                                            sizeof(TcwMat<64>),      4 * sizeof(TcwComp<16>),
+                                            sizeof(TcwComp<32>),     sizeof(TcwComp<48>)};
+  static const size_t lds_back[TC_NCLASS] = {4 * 136 * 8, 528 * 8, 2080 * 8, 4 * 136 * 8, 528 * 8, 1176 * 8};
+  constexpr int SPLIT_OPS = 6000;
+  auto launch_classes = [&](const int32_t *o, int c0, int c1, bool back) {
+    TcwLaunch L{};
+    int nb = 0;
+    size_t lds = 0;
+    for (int c = c0; c < c1; ++c) {
+      const int n = o[c + 1] - o[c];
+      if (n <= 0) continue;
+      const int per = TCW / tw[c];
+      L.seg[L.nseg++] = TcwSeg{c, o[c], o[c + 1], nb};
+      nb += (n + per - 1) / per;
+      lds = std::max(lds, back ? lds_back[c] : lds_fwd[c]);
+    }
+    if (nb == 0) return;
+    if (back)
+      hipLaunchKernelGGL(tcw_round_kernel<true>, dim3(nb), dim3(TCW), lds, s, a, J, L);
+    else
+      hipLaunchKernelGGL(tcw_round_kernel<false>, dim3(nb), dim3(TCW), lds, s, a, J, L);
+  };
+  // the three classes of one kind, c16 = its 16-row class
+  auto launch_kind = [&](const int32_t *o, int c16, bool back) {
+    if (o[c16 + 1] - o[c16] > SPLIT_OPS) {
+      launch_classes(o, c16, c16 + 1, back);
+      launch_classes(o, c16 + 1, c16 + 3, back);
+    } else {
+      launch_classes(o, c16, c16 + 3, back);
+    }
+  };
   for (int r = 0; r < nround; ++r) {
     const int32_t *o = rounds + 7 * r;
-    if (o[1] > o[0])
-      hipLaunchKernelGGL((tcw_rake_kernel<16, 16>), tcw_grid(o[0], o[1], 16), dim3(TCW), 0, s, a, J, o[0], o[1]);
-    if (o[2] > o[1])
-      hipLaunchKernelGGL((tcw_rake_kernel<32, 64>), tcw_grid(o[1], o[2], 64), dim3(TCW), 0, s, a, J, o[1], o[2]);
-    if (o[3] > o[2])
-      hipLaunchKernelGGL((tcw_rake_kernel<64, 64>), tcw_grid(o[2], o[3], 64), dim3(TCW), 0, s, a, J, o[2], o[3]);
-    if (o[4] > o[3])
-      hipLaunchKernelGGL((tcw_compress_kernel<16, 16>), tcw_grid(o[3], o[4], 16), dim3(TCW), 0, s, a, J, o[3],
-                         o[4]);
-    if (o[5] > o[4])
-      hipLaunchKernelGGL((tcw_compress_kernel<32, 64>), tcw_grid(o[4], o[5], 64), dim3(TCW), 0, s, a, J, o[4],
-                         o[5]);
-    if (o[6] > o[5])
-      hipLaunchKernelGGL((tcw_compress_kernel<48, 64>), tcw_grid(o[5], o[6], 64), dim3(TCW), 0, s, a, J, o[5],
-                         o[6]);
+    launch_kind(o, TC_RAKE16, false);
+    launch_kind(o, TC_COMP16, false);
     if (o[7] > o[6])
       hipLaunchKernelGGL(tc_compress_kernel, dim3((o[7] - o[6] + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
                          o[6], o[7]);
@@ -1256,24 +1333,8 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
     const int32_t *o = rounds + 7 * r;
     if (o[7] > o[6])
       hipLaunchKernelGGL(tc_compress_back_kernel, dim3((o[7] - o[6] + 255) / 256), dim3(256), 0, s, a, J, o[6], o[7]);
-    if (o[6] > o[5])
-      hipLaunchKernelGGL((tcw_compress_back_kernel<48, 64>), tcw_grid(o[5], o[6], 64), dim3(TCW), 0, s, a, J,
-                         o[5], o[6]);
-    if (o[5] > o[4])
-      hipLaunchKernelGGL((tcw_compress_back_kernel<32, 64>), tcw_grid(o[4], o[5], 64), dim3(TCW), 0, s, a, J,
-                         o[4], o[5]);
-    if (o[4] > o[3])
-      hipLaunchKernelGGL((tcw_compress_back_kernel<16, 16>), tcw_grid(o[3], o[4], 16), dim3(TCW), 0, s, a, J,
-                         o[3], o[4]);
-    if (o[3] > o[2])
-      hipLaunchKernelGGL((tcw_rake_back_kernel<64, 64>), tcw_grid(o[2], o[3], 64), dim3(TCW), 0, s, a, J, o[2],
-                         o[3]);
-    if (o[2] > o[1])
-      hipLaunchKernelGGL((tcw_rake_back_kernel<32, 64>), tcw_grid(o[1], o[2], 64), dim3(TCW), 0, s, a, J, o[1],
-                         o[2]);
-    if (o[1] > o[0])
-      hipLaunchKernelGGL((tcw_rake_back_kernel<16, 16>), tcw_grid(o[0], o[1], 16), dim3(TCW), 0, s, a, J, o[0],
-                         o[1]);
+    launch_kind(o, TC_COMP16, true);
+    launch_kind(o, TC_RAKE16, true);
   }
 }
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,
