@@ -1097,13 +1097,13 @@ DEV void tcw_compress_back_body(const TreeArgs &a, const GJoint *J, int op0, int
   tcw_private_back<R, TW>(a, J, op, op.av - ce, lb, op.ev1 - 1, team_ks[tm]);
 }
 
-// One launch for several LDS-staged clique-size classes of one kind (rake or
-// compress) in a round.  Operations of one kind in a round touch disjoint
-// slots and read nothing the others write, so the classes need no ordering
-// among themselves: launched together they cost the latency of the slowest
-// operation instead of the sum over the classes.  Block b belongs to the
-// last segment whose first block is <= b; the dynamic LDS is sized by the
-// host for the largest class in the launch.
+// One launch for several LDS-staged operation classes (rake or compress, by
+// clique size) of a round.  A round's operations touch disjoint slots, and
+// the planner keeps its rakes and compresses independent, so the classes
+// need no ordering among themselves: launched together they cost the latency
+// of the slowest operation instead of the sum over the classes.  Block b
+// belongs to the last segment whose first block is <= b; the dynamic LDS is
+// sized by the host for the largest class in the launch.
 enum { TC_RAKE16, TC_RAKE32, TC_RAKE64, TC_COMP16, TC_COMP32, TC_COMP48, TC_NCLASS };
 struct TcwSeg {
   int32_t cls, op0, op1, blk0;
@@ -1280,26 +1280,26 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
   // per round, 7 segments of the operation list (o[7] starts the next round):
   // rakes with cliques of <= 16, <= 32, <= 64 rows, then compresses with
   // cliques of <= 16, <= 32, <= 48 rows and larger (team kernels on the
-  // global slots).  A round's compresses are chosen after its rakes and add
-  // the condensed sides of children raked in the same round, and a leaf's
-  // back-substitution reads the multiplier of its parent joint, which a
-  // compress of the same round may solve: so rakes run before compresses,
-  // compress back-substitutions before rake back-substitutions, and the size
-  // classes of one kind share a launch.  When the 16-row class holds many
-  // operations (throughput-bound: its small LDS footprint keeps more of them
-  // resident) it gets a launch of its own.
+  // global slots).  The planner keeps a round's rakes and compresses
+  // independent (a node with a child raked in the round is compressed in a
+  // later one), so every LDS-staged class of a round shares one launch, in
+  // both directions.  When the 16-row classes hold many operations
+  // (throughput-bound: their small LDS footprint keeps more of them
+  // resident) they get a launch of their own.
   static const int tw[TC_NCLASS] = {16, 64, 64, 16, 64, 64};
   static const size_t lds_fwd[TC_NCLASS] = {4 * sizeof(TcwMat<16>),  sizeof(TcwMat<32>),
                                             sizeof(TcwMat<64>),      4 * sizeof(TcwComp<16>),
                                             sizeof(TcwComp<32>),     sizeof(TcwComp<48>)};
   static const size_t lds_back[TC_NCLASS] = {4 * 136 * 8, 528 * 8, 2080 * 8, 4 * 136 * 8, 528 * 8, 1176 * 8};
+  static const int all[TC_NCLASS] = {TC_RAKE16, TC_COMP16, TC_RAKE32, TC_RAKE64, TC_COMP32, TC_COMP48};
+  static const int *small = all, *large = all + 2;
   constexpr int SPLIT_OPS = 6000;
-  auto launch_classes = [&](const int32_t *o, int c0, int c1, bool back) {
+  auto launch_classes = [&](const int32_t *o, const int *cl, int ncl, bool back) {
     TcwLaunch L{};
     int nb = 0;
     size_t lds = 0;
-    for (int c = c0; c < c1; ++c) {
-      const int n = o[c + 1] - o[c];
+    for (int i = 0; i < ncl; ++i) {
+      const int c = cl[i], n = o[c + 1] - o[c];
       if (n <= 0) continue;
       const int per = TCW / tw[c];
       L.seg[L.nseg++] = TcwSeg{c, o[c], o[c + 1], nb};
@@ -1312,19 +1312,17 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
     else
       hipLaunchKernelGGL(tcw_round_kernel<false>, dim3(nb), dim3(TCW), lds, s, a, J, L);
   };
-  // the three classes of one kind, c16 = its 16-row class
-  auto launch_kind = [&](const int32_t *o, int c16, bool back) {
-    if (o[c16 + 1] - o[c16] > SPLIT_OPS) {
-      launch_classes(o, c16, c16 + 1, back);
-      launch_classes(o, c16 + 1, c16 + 3, back);
+  auto launch_round = [&](const int32_t *o, bool back) {
+    if ((o[TC_RAKE16 + 1] - o[TC_RAKE16]) + (o[TC_COMP16 + 1] - o[TC_COMP16]) > SPLIT_OPS) {
+      launch_classes(o, small, 2, back);
+      launch_classes(o, large, 4, back);
     } else {
-      launch_classes(o, c16, c16 + 3, back);
+      launch_classes(o, all, TC_NCLASS, back);
     }
   };
   for (int r = 0; r < nround; ++r) {
     const int32_t *o = rounds + 7 * r;
-    launch_kind(o, TC_RAKE16, false);
-    launch_kind(o, TC_COMP16, false);
+    launch_round(o, false);
     if (o[7] > o[6])
       hipLaunchKernelGGL(tc_compress_kernel, dim3((o[7] - o[6] + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
                          o[6], o[7]);
@@ -1333,8 +1331,7 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
     const int32_t *o = rounds + 7 * r;
     if (o[7] > o[6])
       hipLaunchKernelGGL(tc_compress_back_kernel, dim3((o[7] - o[6] + 255) / 256), dim3(256), 0, s, a, J, o[6], o[7]);
-    launch_kind(o, TC_COMP16, true);
-    launch_kind(o, TC_RAKE16, true);
+    launch_round(o, true);
   }
 }
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,

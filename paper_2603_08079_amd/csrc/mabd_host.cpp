@@ -798,12 +798,13 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     std::vector<int> topdown(nsl);
     for (int s = 0; s < nsl; ++s) topdown[s] = s;
     std::stable_sort(topdown.begin(), topdown.end(), [&](int x, int y) { return depth[x] < depth[y]; });
-    std::vector<int> nalive(nsl), alive(nsl, 1), sel(nsl, 0), live_child(nsl, -1);
+    std::vector<int> nalive(nsl), alive(nsl, 1), sel(nsl, 0), live_child(nsl, -1), raked_child(nsl, 0);
     for (int s = 0; s < nsl; ++s) nalive[s] = (int)kids[s].size();
     int remaining = nsl;
     std::vector<int> chosen;
     while (remaining > 0) {
-      c->tc_rounds.push_back((int)c->tc_ops.size());
+      const int round0 = (int)c->tc_ops.size();
+      c->tc_rounds.push_back(round0);
       for (int s : topdown) {
         if (!alive[s] || nalive[s] != 0) continue;
         TcOp op{};
@@ -815,16 +816,23 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
         const int s = c->tc_ops[i].v;
         alive[s] = 0;
         --remaining;
-        if (par[s] >= 0) --nalive[par[s]];
+        if (par[s] >= 0) {
+          --nalive[par[s]];
+          raked_child[par[s]] = 1;
+        }
       }
       {  // rakes by clique size: <= 16, <= 32, <= 64 rows (TREE_KMAX)
         const int rows[3] = {16, 32, 64};
         const int cap[3] = {1 << 30, 4096, 1024};  // operations the kernel runs at once
         segment_ops(c->tc_ops, c->tc_rounds, [](const TcOp &o) { return o.nv; }, rows, cap, 3);
       }
+      // a compress of v adds the condensed sides of v's other children, and a
+      // child raked in this round writes its side in this round: such v wait
+      // a round, so that a round's rakes and compresses are independent and
+      // share a launch
       chosen.clear();
       for (int s : topdown) {
-        if (!alive[s] || par[s] < 0 || nalive[s] != 1 || sel[par[s]]) continue;
+        if (!alive[s] || par[s] < 0 || nalive[s] != 1 || sel[par[s]] || raked_child[s]) continue;
         int cs = -1;
         for (int k2 : kids[s])
           if (alive[k2]) cs = k2;
@@ -857,6 +865,8 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
         sel[s] = 0;
         --remaining;
       }
+      for (int i = round0; i < (int)c->tc_ops.size(); ++i)
+        if (c->tc_ops[i].c < 0 && par[c->tc_ops[i].v] >= 0) raked_child[par[c->tc_ops[i].v]] = 0;
       {  // compresses by the larger of v's and c's staged cliques: <= 16, <= 32,
          // <= 48 rows, more (team kernels on the global slots)
         const int rows[3] = {16, 32, 48};
