@@ -53,7 +53,8 @@ struct TileDesc {
 };
 
 // a tile of a chain has T + 1 rows with T = tile threads - 2 (64, 128 or 256
-// threads); groups of interface rows use CHAIN_THREADS threads
+// threads), or T = PACK_T for packed tiles (64 threads); groups of interface
+// rows use CHAIN_THREADS threads
 constexpr int CHAIN_THREADS = 256;
 constexpr int TILE_REC = 27;         // doubles per tile record
 constexpr int GROW_REC = 56;         // doubles per top-level row (scratch)
