@@ -119,11 +119,17 @@ __device__ __forceinline__ void raise_flag(uint32_t *st, uint32_t bits, int /*un
 }
 // a step after a failed one does nothing, so the last good state survives
 // (two relaxed device-scope reads, issued together)
-__device__ __forceinline__ bool skip_step(const uint32_t *st, int /*unused*/) {
+struct StepGate {
+  int fail, cur;
+  __device__ __forceinline__ bool skip() const { return fail < cur; }
+};
+__device__ __forceinline__ StepGate step_gate(const uint32_t *st) {
   int *s = const_cast<int *>(reinterpret_cast<const int *>(st));
-  const int fail = __hip_atomic_load(s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int cur = __hip_atomic_load(s + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return fail < cur;
+  return StepGate{__hip_atomic_load(s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                  __hip_atomic_load(s + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+}
+__device__ __forceinline__ bool skip_step(const uint32_t *st, int /*unused*/) {
+  return step_gate(st).skip();
 }
 #endif
 

@@ -202,7 +202,7 @@ inline unsigned xcd_grid4(int ntiles) { return 32u * (unsigned)((ntiles + 31) / 
 // cache maintenance per workgroup).  That wave writes the tiles' Schur
 // records and the factors (PL, PU, Pb) of the rows it eliminated; the apply
 // pass reads those factors instead of repeating the four sparse levels.
-DEV void pack_reduce_group(const ChainArgs &a, int grp, double *lds) {
+DEV void pack_reduce_group(const ChainArgs &a, int grp, double *lds, StepGate gate, double ir0) {
   const int t = threadIdx.x;
   const int q = t >> 4, j = t & 15;
   const int nq = min(4, a.ntiles - 4 * grp);
@@ -227,6 +227,7 @@ DEV void pack_reduce_group(const ChainArgs &a, int grp, double *lds) {
 #pragma unroll
       for (int c2 = 0; c2 < 3; ++c2) L[3 * r2 + c2] = svl[(9 + 3 * c2 + r2) * 64];
   }
+  if (gate.skip() || ir0 != 0.0) return;  // uniform, tested with the reads in flight
   const bool act = q < nq && j <= Tp;
   if (!act || j == 0) {
 #pragma unroll
@@ -292,10 +293,11 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
   // after the exchange slots (read with phase A's loads, used after phase C)
   constexpr int STG = S_N * NT, STG_X = STG + PACK_CF * 16;
   __shared__ double lds[S_N * NT + (PACK && APPLY ? PACK_CF * 16 + 6 : 0)];
-  if (skip_step(a.status, a.step)) return;
-  if constexpr (MODE == 2) {
-    if (a.ir[0] != 0.0) return;
-  }
+  // the step gate (and, for corrections, the convergence flag) is read first
+  // and tested once phase A's reads are in flight: nothing before the test
+  // writes global memory or raises a flag
+  const StepGate gate = step_gate(a.status);
+  const double ir0 = MODE == 2 ? a.ir[0] : 0.0;
   static_assert(!PACK || NT == 64, "packed tiles are 64-thread tiles");
   const int ti = PACK ? xcd_tile4(a.ntiles) : xcd_tile(a.ntiles);
   if (ti < 0) return;
@@ -368,6 +370,7 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
     if (has_b) sb = (fb & 1) ? 1.0 : -1.0;
     else pb[0] = pb[1] = pb[2] = 0.0;
   }
+  if (gate.skip() || ir0 != 0.0) return;  // uniform: before any barrier
   if (has_body) {
     {
 #pragma unroll
@@ -673,15 +676,13 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
 template <int MODE>
 __global__ __launch_bounds__(64) void chain_pack_kernel(ChainArgs a) {
   __shared__ double lds[S_N * 64];
-  if (skip_step(a.status, a.step)) return;
-  if constexpr (MODE == 2) {
-    if (a.ir[0] != 0.0) return;
-  }
+  const StepGate gate = step_gate(a.status);
+  const double ir0 = MODE == 2 ? a.ir[0] : 0.0;
   const int ngrp = (a.ntiles + 3) / 4;
   const int per = (a.ntiles + 31) / 32;  // groups per XCD range
   const int grp = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (grp >= ngrp) return;
-  pack_reduce_group(a, grp, lds);
+  pack_reduce_group(a, grp, lds, gate, ir0);
 }
 
 // Top system of a chain (rows that bound its groups), n = ngroup + 1 <= 256
@@ -813,8 +814,10 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
     double *xtop, double *xg, double *gfac, int *counters, uint32_t *status, int step,
     const double *ir) {
   __shared__ double lds[S_N * CHAIN_THREADS];
-  if (skip_step(status, step)) return;
-  if (ir && ir[0] != 0.0) return;  // form 1 correction after convergence
+  // step gate and convergence flag (form 1 corrections) read first, tested
+  // once the group's reads are in flight (before any barrier or store)
+  const StepGate gate = step_gate(status);
+  const double ir0 = ir ? ir[0] : 0.0;
   const GroupDesc gd = groups[blockIdx.x];
   const ChainDesc cd = chains[gd.chain];
   const int li = threadIdx.x;
@@ -836,6 +839,7 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
 #pragma unroll
       for (int i = 0; i < 3; ++i) Pb[i] = fac[(18 + i) * CHAIN_THREADS];
     }
+    if (gate.skip() || ir0 != 0.0) return;
     if (row_active && (li == 0 || li == T)) {
       const int64_t ti = (int64_t)cd.gtop0 + gd.gidx + (li == T ? 1 : 0);
       for (int i = 0; i < 3; ++i) lds[(S_X + i) * CHAIN_THREADS + li] = xtop[3 * ti + i];
@@ -869,6 +873,7 @@ __global__ __launch_bounds__(CHAIN_THREADS) void chain_group_kernel(
   if (row_active && li > 0)
     for (int r2 = 0; r2 < 3; ++r2)
       for (int c2 = 0; c2 < 3; ++c2) L[3 * r2 + c2] = TR[TILE_REC * (gi - 1) + 18 + 3 * c2 + r2];
+  if (gate.skip() || ir0 != 0.0) return;
   double PL[9], PU[9], Pb[3];
   int elim_d = 0;
   tile_cr_forward<CHAIN_THREADS>(lds, row_active, li, T, T, L, D, U, b, PL, PU, Pb, elim_d, status, step);
