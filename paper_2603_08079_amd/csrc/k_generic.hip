@@ -780,13 +780,15 @@ DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, i
 }
 
 template <int R, int TW>
-DEV void tcw_rake_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int blk, double *smem) {
+DEV void tcw_rake_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int blk, double *smem,
+                       StepGate gate) {
   TcwMat<R> *team_sm = reinterpret_cast<TcwMat<R> *>(smem);
   const int ln = tlane<TW>(), tm = (int)threadIdx.x / TW;
   const int oi = op0 + blk * (TCW / TW) + tm;
   if (oi >= op1) return;
   TcwMat<R> &sm = team_sm[tm];
   const TcOp op = a.ops[oi];
+  if (gate.skip()) return;  // tested with the operation record in flight
   if (op.nv > R) {  // the host sorts operations by clique size
     if (ln == 0) raise_flag(a.status, FLAG_GUARD, a.step);
     return;
@@ -821,13 +823,15 @@ DEV void tcw_rake_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int
 }
 
 template <int R, int TW>
-DEV void tcw_compress_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int blk, double *smem) {
+DEV void tcw_compress_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int blk, double *smem,
+                           StepGate gate) {
   TcwComp<R> *team_sm = reinterpret_cast<TcwComp<R> *>(smem);
   const int ln = tlane<TW>(), tm = (int)threadIdx.x / TW;
   const int oi = op0 + blk * (TCW / TW) + tm;
   if (oi >= op1) return;
   TcwComp<R> &sm = team_sm[tm];
   const TcOp op = a.ops[oi];
+  if (gate.skip()) return;  // tested with the operation record in flight
   const int ce = op.ce, ck = op.ck;
   const int av = op.av, LDvg = av + 5, pv = av - ce, nv = op.nv;
   const int ac = op.ac, LDcg = ac + 5;
@@ -1011,12 +1015,14 @@ DEV void tcw_private_back(const TreeArgs &a, const GJoint *J, const TcOp &op, in
 }
 
 template <int R, int TW>
-DEV void tcw_rake_back_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int blk, double *smem) {
+DEV void tcw_rake_back_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int blk, double *smem,
+                            StepGate gate) {
   double(*team_ks)[R * (R + 1) / 2] = reinterpret_cast<double(*)[R * (R + 1) / 2]>(smem);
   const int tm = (int)threadIdx.x / TW;
   const int oi = op0 + blk * (TCW / TW) + tm;
   if (oi >= op1) return;
   const TcOp op = a.ops[oi];
+  if (gate.skip()) return;  // tested with the operation record in flight
   if (op.nv > R) {
     if (tlane<TW>() == 0) raise_flag(a.status, FLAG_GUARD, a.step);
     return;
@@ -1029,12 +1035,13 @@ DEV void tcw_rake_back_body(const TreeArgs &a, const GJoint *J, int op0, int op1
 
 template <int R, int TW>
 DEV void tcw_compress_back_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int blk,
-                                double *smem) {
+                                double *smem, StepGate gate) {
   double(*team_ks)[R * (R + 1) / 2] = reinterpret_cast<double(*)[R * (R + 1) / 2]>(smem);
   const int ln = tlane<TW>(), tm = (int)threadIdx.x / TW;
   const int oi = op0 + blk * (TCW / TW) + tm;
   if (oi >= op1) return;
   const TcOp op = a.ops[oi];
+  if (gate.skip()) return;  // tested with the operation record in flight
   const int ce = op.ce, ck = op.ck;
   const int ac = op.ac;
   if (op.nv > R || ac > TW) {
@@ -1116,7 +1123,7 @@ struct TcwLaunch {
 template <bool BACK>
 __global__ __launch_bounds__(TCW) void tcw_round_kernel(TreeArgs a, const GJoint *J, TcwLaunch L) {
   extern __shared__ double tcw_smem[];
-  if (skip_step(a.status, a.step)) return;
+  const StepGate gate = step_gate(a.status);  // tested by each operation with its first read
   // fixed indices only (the launch record stays in kernel-argument memory)
   int cls = L.seg[0].cls, op0 = L.seg[0].op0, op1 = L.seg[0].op1, blk0 = L.seg[0].blk0;
 #pragma unroll
@@ -1131,21 +1138,21 @@ __global__ __launch_bounds__(TCW) void tcw_round_kernel(TreeArgs a, const GJoint
   const int blk = (int)blockIdx.x - blk0;
   if constexpr (!BACK) {
     switch (cls) {
-      case TC_RAKE16: tcw_rake_body<16, 16>(a, J, op0, op1, blk, tcw_smem); break;
-      case TC_RAKE32: tcw_rake_body<32, 64>(a, J, op0, op1, blk, tcw_smem); break;
-      case TC_RAKE64: tcw_rake_body<64, 64>(a, J, op0, op1, blk, tcw_smem); break;
-      case TC_COMP16: tcw_compress_body<16, 16>(a, J, op0, op1, blk, tcw_smem); break;
-      case TC_COMP32: tcw_compress_body<32, 64>(a, J, op0, op1, blk, tcw_smem); break;
-      default: tcw_compress_body<48, 64>(a, J, op0, op1, blk, tcw_smem); break;
+      case TC_RAKE16: tcw_rake_body<16, 16>(a, J, op0, op1, blk, tcw_smem, gate); break;
+      case TC_RAKE32: tcw_rake_body<32, 64>(a, J, op0, op1, blk, tcw_smem, gate); break;
+      case TC_RAKE64: tcw_rake_body<64, 64>(a, J, op0, op1, blk, tcw_smem, gate); break;
+      case TC_COMP16: tcw_compress_body<16, 16>(a, J, op0, op1, blk, tcw_smem, gate); break;
+      case TC_COMP32: tcw_compress_body<32, 64>(a, J, op0, op1, blk, tcw_smem, gate); break;
+      default: tcw_compress_body<48, 64>(a, J, op0, op1, blk, tcw_smem, gate); break;
     }
   } else {
     switch (cls) {
-      case TC_RAKE16: tcw_rake_back_body<16, 16>(a, J, op0, op1, blk, tcw_smem); break;
-      case TC_RAKE32: tcw_rake_back_body<32, 64>(a, J, op0, op1, blk, tcw_smem); break;
-      case TC_RAKE64: tcw_rake_back_body<64, 64>(a, J, op0, op1, blk, tcw_smem); break;
-      case TC_COMP16: tcw_compress_back_body<16, 16>(a, J, op0, op1, blk, tcw_smem); break;
-      case TC_COMP32: tcw_compress_back_body<32, 64>(a, J, op0, op1, blk, tcw_smem); break;
-      default: tcw_compress_back_body<48, 64>(a, J, op0, op1, blk, tcw_smem); break;
+      case TC_RAKE16: tcw_rake_back_body<16, 16>(a, J, op0, op1, blk, tcw_smem, gate); break;
+      case TC_RAKE32: tcw_rake_back_body<32, 64>(a, J, op0, op1, blk, tcw_smem, gate); break;
+      case TC_RAKE64: tcw_rake_back_body<64, 64>(a, J, op0, op1, blk, tcw_smem, gate); break;
+      case TC_COMP16: tcw_compress_back_body<16, 16>(a, J, op0, op1, blk, tcw_smem, gate); break;
+      case TC_COMP32: tcw_compress_back_body<32, 64>(a, J, op0, op1, blk, tcw_smem, gate); break;
+      default: tcw_compress_back_body<48, 64>(a, J, op0, op1, blk, tcw_smem, gate); break;
     }
   }
 }
