@@ -50,11 +50,15 @@ DEV double block_reduce(double v, double *sh) {
 }
 
 // fixed-order sum of one partial slot over all joint blocks (every thread
-// gets the result)
-DEV double sum_partials(const PcgBallArgs &a, int slot, double *sh) {
+// gets the result); thread_partials is the per-thread part, so that its
+// reads can be issued before a test that must precede the first barrier
+DEV double thread_partials(const PcgBallArgs &a, int slot) {
   double v = 0.0;
   for (int b = threadIdx.x; b < a.nblk; b += PB_THREADS) v += a.partial[4 * (int64_t)b + slot];
-  return block_reduce(v, sh);
+  return v;
+}
+DEV double sum_partials(const PcgBallArgs &a, int slot, double *sh) {
+  return block_reduce(thread_partials(a, slot), sh);
 }
 
 DEV void write_partial(const PcgBallArgs &a, int slot, double v, double *sh) {
@@ -179,13 +183,18 @@ __global__ __launch_bounds__(PB_THREADS) void pb_start_kernel(PcgBallArgs a, int
 // A: beta and the convergence test, then the body pass on p = z + beta p_prev
 __global__ __launch_bounds__(PB_THREADS) void pb_iter_a_kernel(PcgBallArgs a, int par, int first) {
   __shared__ double sh[PB_THREADS];
-  if (skip_step(a.status, a.step) || a.si[SI_DONE]) return;
+  // the step gate, the done flag, the partials and the scalars go out
+  // together; the flags are tested before the first barrier
+  const StepGate gate = step_gate(a.status);
+  const int done = a.si[SI_DONE];
+  const double t1 = first ? 0.0 : thread_partials(a, 1), t2 = first ? 0.0 : thread_partials(a, 2);
+  const double rzprev = a.sc[SC_RZ + (par ^ 1)], th = a.sc[SC_THRESH];
+  if (gate.skip() || done) return;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   double beta = 0.0;
   if (!first) {
-    const double rz = sum_partials(a, 1, sh), rr = sum_partials(a, 2, sh);
-    beta = rz / a.sc[SC_RZ + (par ^ 1)];
-    const double th = a.sc[SC_THRESH];
+    const double rz = block_reduce(t1, sh), rr = block_reduce(t2, sh);
+    beta = rz / rzprev;
     const bool bad = !isfinite(rz) || !isfinite(rr) || !isfinite(beta);
     const bool conv = !bad && rr <= th * th;
     if (lead) {
@@ -217,8 +226,10 @@ __global__ __launch_bounds__(PB_THREADS) void pb_iter_a_kernel(PcgBallArgs a, in
 // B: p = z + beta p_prev (stored), S p, partials of p.Sp
 __global__ __launch_bounds__(PB_THREADS) void pb_iter_b_kernel(PcgBallArgs a, int par) {
   __shared__ double sh[PB_THREADS];
-  if (skip_step(a.status, a.step) || a.si[SI_DONE]) return;
+  const StepGate gate = step_gate(a.status);  // read together with the flag and beta
+  const int done = a.si[SI_DONE];
   const double beta = a.sc[SC_BETA];
+  if (gate.skip() || done) return;
   const double *pprev = par ? a.p1 : a.p0;
   double *pnext = par ? a.p0 : a.p1;
   const int j = blockIdx.x * PB_THREADS + threadIdx.x;
@@ -241,21 +252,38 @@ __global__ __launch_bounds__(PB_THREADS) void pb_iter_b_kernel(PcgBallArgs a, in
 // C: alpha, x and r updates, z = M^{-1} r, partials of r.z and r.r
 __global__ __launch_bounds__(PB_THREADS) void pb_iter_c_kernel(PcgBallArgs a, int par) {
   __shared__ double sh[PB_THREADS];
-  if (skip_step(a.status, a.step) || a.si[SI_DONE]) return;
-  const double alpha = a.sc[SC_RZ + par] / sum_partials(a, 3, sh);
+  // the step gate, the done flag, the partials and this joint's vectors go
+  // out together (none of them depends on alpha)
+  const StepGate gate = step_gate(a.status);
+  const int done = a.si[SI_DONE];
+  const double rz = a.sc[SC_RZ + par], tp = thread_partials(a, 3);
   const double *pnext = par ? a.p0 : a.p1;
   const int j = blockIdx.x * PB_THREADS + threadIdx.x;
+  const int64_t jc = j < a.nj ? j : 0;
+  double pn[3], xo[3], ro[3], so[3], dv[6];
+#pragma unroll
+  for (int rr = 0; rr < 3; ++rr) {
+    const int64_t o = 3 * jc + rr;
+    pn[rr] = pnext[o];
+    xo[rr] = a.x[o];
+    ro[rr] = a.r[o];
+    so[rr] = a.sp[o];
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) dv[q] = a.dinv[6 * jc + q];
+  if (gate.skip() || done) return;
+  const double alpha = rz / block_reduce(tp, sh);
   double prz = 0.0, prr = 0.0;
   if (j < a.nj) {
     double rk[3], zk[3];
 #pragma unroll
     for (int rr = 0; rr < 3; ++rr) {
       const int64_t o = 3 * (int64_t)j + rr;
-      a.x[o] += alpha * pnext[o];
-      rk[rr] = a.r[o] - alpha * a.sp[o];
+      a.x[o] = xo[rr] + alpha * pn[rr];
+      rk[rr] = ro[rr] - alpha * so[rr];
       a.r[o] = rk[rr];
     }
-    precond(a.dinv + 6 * (int64_t)j, rk, zk);
+    precond(dv, rk, zk);
 #pragma unroll
     for (int rr = 0; rr < 3; ++rr) {
       a.z[3 * (int64_t)j + rr] = zk[rr];
