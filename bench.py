@@ -43,9 +43,9 @@ ALG_BYTES_F1 = {"chain_resid": 288 + 53 + 24 + 120}
 # (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, scales from a plain 512 MiB copy) for
 # the chain tile kernels as they stand, on the 1M chain; keyed by workload,
 # kernel, tile threads and tile packing, and reported only for those.
-PMC_TRAFFIC = {("chain1m", "chain_apply", 64, 1): (149036 * 2 + 221479) * 1024,
-               ("chain1m", "chain_reduce", 64, 1): ((125861 + 19900) * 2 + 39322 + 49569) * 1024,
-               ("chain1m", "chain_apply", 64, 0): (126028 * 2 + 221398) * 1024,
+PMC_TRAFFIC = {("chain1m", "chain_apply", 64, 1): (149035 * 2 + 221771) * 1024,
+               ("chain1m", "chain_reduce", 64, 1): ((125865 + 19889) * 2 + 39322 + 49566) * 1024,
+               ("chain1m", "chain_apply", 64, 0): (126031 * 2 + 221418) * 1024,
                ("chain1m", "chain_reduce", 64, 0): (125815 * 2 + 3571) * 1024}
 
 
