@@ -57,7 +57,8 @@ def test_forward_and_loss_match_reference():
 def test_gradient_matches_finite_differences(kind):
     """GPU FP32 backpropagation against central differences of the FP64
     reference loss, on parameters of every layer (weights and biases)."""
-    asm = mi.lattice(6, seed=22) if kind == "lattice" else mi.rgg(60, seed=5, pin_frac=0.1)
+    # rgg seed 1: one network component of 54 dynamic bodies and 138 joints
+    asm = mi.lattice(6, seed=22) if kind == "lattice" else mi.rgg(60, seed=1, pin_frac=0.1)
     import paper_2603_08079_amd as pk
 
     st = pk.Context(asm).stats()
