@@ -229,15 +229,16 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   __shared__ PrepLds team_lds[TEAMS];
   const int tm = threadIdx.x / TEAM, ln = threadIdx.x % TEAM;
   PrepLds &S = team_lds[tm];
-  if (skip_step(a.status, a.step)) return;
+  const StepGate gate = step_gate(a.status);  // tested with the slot's records
   const int slot = blockIdx.x * TEAMS + tm;
   if (slot >= nslots) return;  // whole teams only: team_sync is wave-local
   const int64_t b = a.tbody[slot];
-  const double *Th = a.hinv + (int64_t)HINV_STRIDE * a.shp[b];
   const int pk = a.tpk[slot];
-  const int kpar = pk >= 0 ? (pk >> 1) : -1;
   const int e0 = a.tabs_off[slot], e1 = a.tabs_off[slot + 1];
   const int ne = a.tne[slot];
+  if (gate.skip()) return;
+  const double *Th = a.hinv + (int64_t)HINV_STRIDE * a.shp[b];
+  const int kpar = pk >= 0 ? (pk >> 1) : -1;
   const int nent = e1 - e0 + (kpar >= 0 ? 1 : 0);
   // 1) Hbar^{-1} and u of the body and the clique entries (absorbed joints
   //    in list order, then the parent joint), fetched together (every read
@@ -268,7 +269,20 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
     S.ei[e] = (rows << 4) | (un << 1) | side;
   }
   team_sync();
-  if (ln == 0) {
+  if (nent <= TEAM) {
+    // first rows by a prefix sum over the team; each lane maps its own rows
+    const int c = ln < nent ? (S.ei[ln] >> 4) & 15 : 0;
+    int x = c;
+    for (int o = 1; o < TEAM; o <<= 1) {
+      const int y = __shfl_up(x, o, TEAM);
+      if (ln >= o) x += y;
+    }
+    const int r0 = x - c;
+    if (ln < nent) {
+      S.ei[ln] |= r0 << 8;
+      for (int i = 0; i < c; ++i) S.rowent[r0 + i] = (uint8_t)ln;
+    }
+  } else if (ln == 0) {
     int r = 0;
     for (int e = 0; e < nent; ++e) {
       const int c = (S.ei[e] >> 4) & 15;
