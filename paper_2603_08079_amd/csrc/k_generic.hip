@@ -642,20 +642,23 @@ template <int TW>
 DEV int tlane() { return (int)threadIdx.x % TW; }
 
 // lower triangle of rows [0, nr) of a global clique (leading dimension ls)
-// into a packed LDS triangle; loads are issued eight at a time
-template <int R, int TW>
+// into a packed LDS triangle; every lane issues U loads before the first
+// wait (the factorisations stage with U = 16: half the round trips of
+// batches of eight at no occupancy cost; the back-substitutions keep 8,
+// where 16 would cost them occupancy)
+template <int R, int TW, int U = 8>
 DEV void tcw_load_lower(const double *src, int ls, double *dst, int nr) {
   const int n = nr * R;
-  for (int base = 0; base < n; base += 8 * TW) {
-    double v[8];
+  for (int base = 0; base < n; base += U * TW) {
+    double v[U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int idx = base + u * TW + tlane<TW>();
       const int i = idx / R, j = idx - (idx / R) * R;
       v[u] = src[(idx < n && j <= i) ? i * ls + j : 0];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int idx = base + u * TW + tlane<TW>();
       const int i = idx / R, j = idx - (idx / R) * R;
       if (idx < n && j <= i) dst[tri(i) + j] = v[u];
@@ -811,7 +814,7 @@ DEV void tcw_rake_body(const TreeArgs &a, const GJoint *J, int op0, int op1, int
   double *Kg = a.fac + op.fv;
   double *yg = Kg + LDg * LDg;
   const int tab = tcw_tab<TW>(a, op.ev0, op.ev1);
-  tcw_load_lower<R, TW>(Kg, LDg, sm.K, nr);
+  tcw_load_lower<R, TW, 16>(Kg, LDg, sm.K, nr);
   for (int r = ln; r < nr; r += TW) sm.y[r] = yg[r];
   team_sync();
   tcw_add_children<R, TW>(a, tab, op.ev1 - op.ev0, sm.K, sm.y);
@@ -863,8 +866,8 @@ DEV void tcw_compress_body(const TreeArgs &a, const GJoint *J, int op0, int op1,
   // 1) v: condensed children except the live child (last entry), private
   //    rows factored; boundary rows [e; kcur] remain
   const int tab = tcw_tab<TW>(a, op.ev0, op.ev1 - 1);
-  tcw_load_lower<R, TW>(Kvg, LDvg, Kv, nv);
-  tcw_load_lower<R, TW>(Kcg, LDcg, Kc, ac + ce);
+  tcw_load_lower<R, TW, 16>(Kvg, LDvg, Kv, nv);
+  tcw_load_lower<R, TW, 16>(Kcg, LDcg, Kc, ac + ce);
   for (int r = ln; r < nv; r += TW) yv[r] = yvg[r];
   for (int r = ln; r < ac + ce; r += TW) yc[r] = ycg[r];
   team_sync();
