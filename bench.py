@@ -83,11 +83,19 @@ def main():
         n = int(args.copy_calibration_mb * (1 << 20)) // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
+        b.copy_(a)
         torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(5):
             b.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_per_launch": 8 * n, "launches": 5}), flush=True)
+        ms = e0.elapsed_time(e1) / 5
+        # achieved HBM rate of a plain copy (bytes read + written): the
+        # practical ceiling next to the 8 TB/s of the specification
+        print(json.dumps({"copy_bytes_per_launch": 8 * n, "launches": 6, "ms_per_copy": round(ms, 4),
+                          "read_plus_write_GBps": round(2 * 8 * n / (ms * 1e-3) / 1e9, 1)}), flush=True)
         return
 
     import mabd_inputs as mi
