@@ -226,21 +226,43 @@ __global__ __launch_bounds__(PB_THREADS) void pb_iter_a_kernel(PcgBallArgs a, in
 // B: p = z + beta p_prev (stored), S p, partials of p.Sp
 __global__ __launch_bounds__(PB_THREADS) void pb_iter_b_kernel(PcgBallArgs a, int par) {
   __shared__ double sh[PB_THREADS];
-  const StepGate gate = step_gate(a.status);  // read together with the flag and beta
+  // the step gate, flag and beta go out with the joint's own reads (end
+  // bodies, anchors, z, p_prev); only the end bodies' zw wait for them
+  const StepGate gate = step_gate(a.status);
   const int done = a.si[SI_DONE];
   const double beta = a.sc[SC_BETA];
-  if (gate.skip() || done) return;
   const double *pprev = par ? a.p1 : a.p0;
   double *pnext = par ? a.p0 : a.p1;
   const int j = blockIdx.x * PB_THREADS + threadIdx.x;
+  const int64_t jc = j < a.nj ? j : 0;
+  const int ba = a.jba[jc], bb = a.jbb[jc];
+  double pj[6], zk[3], pk[3];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) pj[c] = a.jp[8 * jc + c];
+#pragma unroll
+  for (int rr = 0; rr < 3; ++rr) {
+    zk[rr] = a.z[3 * jc + rr];
+    pk[rr] = pprev[3 * jc + rr];
+  }
+  if (gate.skip() || done) return;
   double ppap = 0.0;
   if (j < a.nj) {
-    double y[3];
-    joint_one(a, j, y);
+    double y[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int b = side ? bb : ba;
+      if (b < 0) continue;
+      const double sg = side ? -1.0 : 1.0;
+      const double *p = pj + 3 * side;
+      const double *zb = a.zw + 16 * (int64_t)b;
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr)
+        y[rr] += sg * (p[0] * zb[rr] + p[1] * zb[3 + rr] + p[2] * zb[6 + rr] + zb[9 + rr]);
+    }
 #pragma unroll
     for (int rr = 0; rr < 3; ++rr) {
       const int64_t o = 3 * (int64_t)j + rr;
-      const double pv = a.z[o] + beta * pprev[o];
+      const double pv = zk[rr] + beta * pk[rr];
       pnext[o] = pv;
       a.sp[o] = y[rr];
       ppap += pv * y[rr];
