@@ -9,12 +9,31 @@
 
 namespace mabd {
 
+// The body's own reads (incidence range, solver index, rotation, shape),
+// which a caller may issue early, e.g. ahead of a reduction.
+struct BodyRefs {
+  int e0, e1, shp;
+  int64_t B;
+  double R[9];
+};
+DEV BodyRefs body_refs(const PcgBallArgs &a, int i) {
+  BodyRefs r;
+  r.e0 = a.binc_off[i];
+  r.e1 = a.binc_off[i + 1];
+  r.B = a.bid[i];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) r.R[k] = a.Rg[k * a.ns + r.B];
+  r.shp = a.shp[r.B];
+  return r;
+}
+
 // zw_i = diag4(R) Hbar^{-1} diag4(R^T) sum_k s J(p_k)^T (va_k + coef vb_k)
-DEV void body_one(const PcgBallArgs &a, int i, const double *va, const double *vb, double coef) {
+DEV void body_one(const PcgBallArgs &a, int i, const BodyRefs &br, const double *va, const double *vb,
+                  double coef) {
   double g[12];
 #pragma unroll
   for (int s = 0; s < 12; ++s) g[s] = 0.0;
-  for (int e = a.binc_off[i]; e < a.binc_off[i + 1]; ++e) {
+  for (int e = br.e0; e < br.e1; ++e) {
     const int ent = a.binc[e];
     const int j = ent >> 1, side = ent & 1;
     const double sg = side ? -1.0 : 1.0;
@@ -33,17 +52,18 @@ DEV void body_one(const PcgBallArgs &a, int i, const double *va, const double *v
 #pragma unroll
     for (int rr = 0; rr < 3; ++rr) g[9 + rr] += v[rr];
   }
-  const int64_t B = a.bid[i];
-  double R[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) R[k] = a.Rg[k * a.ns + B];
+  const double *R = br.R;
   double gl_[12], zl[12];
 #pragma unroll
   for (int c = 0; c < 4; ++c) mat3t_vec(R, g + 3 * c, gl_ + 3 * c);
-  hinv_apply(a.hinv + (int64_t)HINV_STRIDE * a.shp[B], gl_, zl);
+  hinv_apply(a.hinv + (int64_t)HINV_STRIDE * br.shp, gl_, zl);
   double *zo = a.zw + 16 * (int64_t)i;
 #pragma unroll
   for (int c = 0; c < 4; ++c) mat3_vec(R, zl + 3 * c, zo + 3 * c);
+}
+
+DEV void body_one(const PcgBallArgs &a, int i, const double *va, const double *vb, double coef) {
+  body_one(a, i, body_refs(a, i), va, vb, coef);
 }
 
 // y = sum_sides s J(p) zw_b

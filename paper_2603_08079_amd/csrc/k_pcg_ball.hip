@@ -189,6 +189,9 @@ __global__ __launch_bounds__(PB_THREADS) void pb_iter_a_kernel(PcgBallArgs a, in
   const int done = a.si[SI_DONE];
   const double t1 = first ? 0.0 : thread_partials(a, 1), t2 = first ? 0.0 : thread_partials(a, 2);
   const double rzprev = a.sc[SC_RZ + (par ^ 1)], th = a.sc[SC_THRESH];
+  const int i = blockIdx.x * PB_THREADS + threadIdx.x;
+  BodyRefs br{};  // the body's own reads, independent of beta
+  if (a.nbd > 0) br = body_refs(a, i < a.nbd ? i : 0);
   if (gate.skip() || done) return;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   double beta = 0.0;
@@ -219,8 +222,7 @@ __global__ __launch_bounds__(PB_THREADS) void pb_iter_a_kernel(PcgBallArgs a, in
     if (a.si[SI_ITERS] >= a.max_iters) a.si[SI_DONE] = 1;
     else a.si[SI_ITERS] += 1;
   }
-  const int i = blockIdx.x * PB_THREADS + threadIdx.x;
-  if (i < a.nbd) body_one(a, i, a.z, par ? a.p1 : a.p0, beta);
+  if (i < a.nbd) body_one(a, i, br, a.z, par ? a.p1 : a.p0, beta);
 }
 
 // B: p = z + beta p_prev (stored), S p, partials of p.Sp
