@@ -11,10 +11,12 @@ namespace mabd {
 
 // The body's own reads (incidence range, solver index, rotation, shape),
 // which a caller may issue early, e.g. ahead of a reduction.
+constexpr int BODY_ENT = 4;  // incidence entries read ahead (a lattice body has up to four joints)
 struct BodyRefs {
   int e0, e1, shp;
   int64_t B;
   double R[9];
+  int ent[BODY_ENT];
 };
 DEV BodyRefs body_refs(const PcgBallArgs &a, int i) {
   BodyRefs r;
@@ -24,6 +26,8 @@ DEV BodyRefs body_refs(const PcgBallArgs &a, int i) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) r.R[k] = a.Rg[k * a.ns + r.B];
   r.shp = a.shp[r.B];
+#pragma unroll
+  for (int u = 0; u < BODY_ENT; ++u) r.ent[u] = r.e0 + u < r.e1 ? a.binc[r.e0 + u] : 0;
   return r;
 }
 
@@ -34,7 +38,11 @@ DEV void body_one(const PcgBallArgs &a, int i, const BodyRefs &br, const double 
 #pragma unroll
   for (int s = 0; s < 12; ++s) g[s] = 0.0;
   for (int e = br.e0; e < br.e1; ++e) {
-    const int ent = a.binc[e];
+    int ent = 0;
+#pragma unroll
+    for (int u = 0; u < BODY_ENT; ++u)
+      if (e - br.e0 == u) ent = br.ent[u];
+    if (e - br.e0 >= BODY_ENT) ent = a.binc[e];
     const int j = ent >> 1, side = ent & 1;
     const double sg = side ? -1.0 : 1.0;
     double v[3];
