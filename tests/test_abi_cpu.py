@@ -72,3 +72,21 @@ def test_invalid_inputs_are_rejected_before_device_work():
     _expect(base, pk.ERR_INVALID_ARG, hinge_grad=1)
     assert "precision" in _expect(base, pk.ERR_INVALID_ARG, precision=2)
     assert "ir_max_sweeps" in _expect(base, pk.ERR_INVALID_ARG, precision=1, ir_max_sweeps=-1)
+
+
+def test_missing_library_fails_loudly():
+    """Without libmabd.so the binding raises at the first call: no fallback."""
+    import subprocess
+    import sys
+
+    code = ("import paper_2603_08079_amd as pk\n"
+            "pk.LIB_PATH = '/nonexistent/libmabd.so'\n"
+            "pk._lib = None\n"
+            "try:\n"
+            "    pk.lib()\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120, cwd=root)
+    assert r.returncode == 0, r.stderr
+    assert "raised:" in r.stdout and "no CPU fallback" in r.stdout
