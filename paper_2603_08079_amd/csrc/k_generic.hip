@@ -237,36 +237,43 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   const int e0 = a.tabs_off[slot], e1 = a.tabs_off[slot + 1];
   const int ne = a.tne[slot];
   if (gate.skip()) return;
-  const double *Th = a.hinv + (int64_t)HINV_STRIDE * a.shp[b];
   const int kpar = pk >= 0 ? (pk >> 1) : -1;
-  const int nent = e1 - e0 + (kpar >= 0 ? 1 : 0);
-  // 1) Hbar^{-1} and u of the body and the clique entries (absorbed joints
-  //    in list order, then the parent joint), fetched together (every read
-  //    issued before the first store); their rows and the row -> entry map
-  {
-    const double t0 = Th[ln], t1 = ln + TEAM < HINV_STRIDE ? Th[ln + TEAM] : 0.0;
-    const double u0 = ln < 12 ? a.u[(int64_t)ln * a.ns + b] : 0.0;
-    S.th[ln] = t0;
-    if (ln + TEAM < HINV_STRIDE) S.th[ln + TEAM] = t1;
-    if (ln < 12) S.uu[ln] = u0;
-  }
-  for (int e = ln; e < nent; e += TEAM) {
-    int k, side, un;
-    int rows;
-    if (e < e1 - e0) {
-      const int t = a.tabs[e0 + e];
-      k = abs_joint(t);
-      rows = abs_rows(t);
-      side = (t >> 1) & 1;
-      un = t & 1;
-    } else {
-      k = kpar;
-      rows = J[k].type ? 5 : 3;
-      side = pk & 1;
-      un = 1;  // parent rows take C_k only
+  const int nabs = e1 - e0;
+  const int nent = nabs + (kpar >= 0 ? 1 : 0);  // <= 21: cliques hold <= TREE_KMAX rows
+  // 1) what depends only on the slot's records, fetched in one batch: the
+  //    body's shape index and local solve u, its absorbed-joint entries (two
+  //    per lane) and the parent joint's type; then Hbar^{-1}, which waits
+  //    only for the shape index and lands while the entries are decoded
+  const int shp = a.shp[b];
+  const double u0 = ln < 12 ? a.u[(int64_t)ln * a.ns + b] : 0.0;
+  const int ta = ln < nabs ? a.tabs[e0 + ln] : 0;
+  const int tb = ln + TEAM < nabs ? a.tabs[e0 + ln + TEAM] : 0;
+  const int ptype = kpar >= 0 ? J[kpar].type : 0;
+  const double *Th = a.hinv + (int64_t)HINV_STRIDE * shp;
+  const double t0 = Th[ln], t1 = ln + TEAM < HINV_STRIDE ? Th[ln + TEAM] : 0.0;
+  //    clique entries (absorbed joints in list order, then the parent joint),
+  //    their rows and the row -> entry map
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = ln + h * TEAM;
+    if (e < nent) {
+      int k, side, un;
+      int rows;
+      if (e < nabs) {
+        const int t = h ? tb : ta;
+        k = abs_joint(t);
+        rows = abs_rows(t);
+        side = (t >> 1) & 1;
+        un = t & 1;
+      } else {
+        k = kpar;
+        rows = ptype ? 5 : 3;
+        side = pk & 1;
+        un = 1;  // parent rows take C_k only
+      }
+      S.ek[e] = k;
+      S.ei[e] = (rows << 4) | (un << 1) | side;
     }
-    S.ek[e] = k;
-    S.ei[e] = (rows << 4) | (un << 1) | side;
   }
   team_sync();
   if (nent <= TEAM) {
@@ -311,22 +318,26 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
       if (ei & 2) cv[k] = a.gl[(int64_t)GL_STRIDE * S.ek[e] + GL_C + (i - (ei >> 8))];
     }
   }
-  //    clique rows L (nr x 12), four independent loads per lane in flight
-  for (int base = 0; base < nr * 12; base += 4 * TEAM) {
-    double v[4];
+  //    clique rows L (nr x 12), eight independent loads per lane in flight
+  //    (one pass for cliques of up to 10 rows); lanes past the end read row 0
+  for (int base = 0; base < nr * 12; base += 8 * TEAM) {
+    double v[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int idx = base + u * TEAM + ln;
       const int r = idx < nr * 12 ? idx / 12 : 0, sc = idx < nr * 12 ? idx % 12 : 0;
       const int e = S.rowent[r], ei = S.ei[e];
       v[u] = a.gl[(int64_t)GL_STRIDE * S.ek[e] + ((ei & 1) ? GL_LB : GL_LA) + 12 * (r - (ei >> 8)) + sc];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int idx = base + u * TEAM + ln;
       if (idx < nr * 12) Lm[idx] = v[u];
     }
   }
+  S.th[ln] = t0;
+  if (ln + TEAM < HINV_STRIDE) S.th[ln + TEAM] = t1;
+  if (ln < 12) S.uu[ln] = u0;
   team_sync();
   if (!big) {
     // 2-3) K0 = L Hbar^{-1} L^T (lower triangle): lane j holds
