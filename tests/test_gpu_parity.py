@@ -426,3 +426,30 @@ def test_full_size_lattice_one_step():
     _, _, dv = s.finish(asm.h, asm.q0, asm.qd0, lam_g)
     say("pcg iterations", st["pcg_iters"], "kkt of GPU multipliers", dv[:3])
     assert dv[oracle.RHO_D] <= 2e-10 and dv[oracle.RHO_P] <= 1e-12
+
+
+def test_full_size_rgg_one_step():
+    """The 100,000-body random geometric network (244,291 ball joints, six
+    network components and twelve trees) at full size: one cold-start PCG
+    step to relative residual 1e-2, a tolerance block-Jacobi PCG reaches on
+    this over-constrained graph within a few thousand iterations (1e-10 is
+    out of its reach).  The oracle back-projects the GPU multipliers in FP64
+    and must find the dual residual at that tolerance and the primal one at
+    rounding level."""
+    tol = 1e-2
+    asm = mi.config("rgg100k")
+    say("rgg100k full size", asm.n, asm.m)
+    ctx = ctx_of(asm, kkt_tol=tol, max_iters=100000, warm_start=0)
+    ctx.step(asm.h, 1)
+    st = ctx.stats()
+    lam_g = ctx.multipliers()
+    ctx.close()
+    assert st["n_graph"] == 6 and st["last_status"] == 0
+    assert 0 < st["pcg_iters"] < 100000 and st["rho_d"] <= tol
+    s = oracle.System(asm)
+    _, _, dv = s.finish(asm.h, asm.q0, asm.qd0, lam_g)
+    say("pcg iterations", st["pcg_iters"], "GPU residual", st["rho_d"], "kkt of GPU multipliers", dv[:3])
+    assert dv[oracle.RHO_D] <= 2 * tol and dv[oracle.RHO_P] <= 1e-12
+    # the GPU's own true residual of the networks and the oracle's over all
+    # rows (the trees' rows are solved exactly) are the same number
+    assert abs(dv[oracle.RHO_D] - st["rho_d"]) <= 1e-4 * st["rho_d"]
