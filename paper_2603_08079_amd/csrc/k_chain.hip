@@ -293,11 +293,17 @@ __global__ __launch_bounds__(NT, APPLY ? MABD_TILE_WAVES_APPLY : MABD_TILE_WAVES
   // after the exchange slots (read with phase A's loads, used after phase C)
   constexpr int STG = S_N * NT, STG_X = STG + PACK_CF * 16;
   __shared__ double lds[S_N * NT + (PACK && APPLY ? PACK_CF * 16 + 6 : 0)];
-  // the step gate (and, for corrections, the convergence flag) is read first
-  // and tested once phase A's reads are in flight: nothing before the test
-  // writes global memory or raises a flag
+  // the step gate is read first and tested once phase A's reads are in
+  // flight (nothing before the test writes global memory or raises a flag);
+  // a correction sweep's convergence flag is tested as soon as it arrives
   const StepGate gate = step_gate(a.status);
   const double ir0 = MODE == 2 ? a.ir[0] : 0.0;
+  // a correction sweep after convergence ends before reading its tile: the
+  // flag's round trip costs the sweep that runs less than phase A's reads
+  // cost every sweep that is skipped
+  if constexpr (MODE == 2) {
+    if (ir0 != 0.0) return;
+  }
   static_assert(!PACK || NT == 64, "packed tiles are 64-thread tiles");
   const int ti = PACK ? xcd_tile4(a.ntiles) : xcd_tile(a.ntiles);
   if (ti < 0) return;
@@ -678,6 +684,9 @@ __global__ __launch_bounds__(64) void chain_pack_kernel(ChainArgs a) {
   __shared__ double lds[S_N * 64];
   const StepGate gate = step_gate(a.status);
   const double ir0 = MODE == 2 ? a.ir[0] : 0.0;
+  if constexpr (MODE == 2) {
+    if (ir0 != 0.0) return;  // converged: skip before the survivors' reads
+  }
   const int ngrp = (a.ntiles + 3) / 4;
   const int per = (a.ntiles + 31) / 32;  // groups per XCD range
   const int grp = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
