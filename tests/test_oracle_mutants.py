@@ -1,0 +1,99 @@
+"""Planted mistakes in the oracle are caught by its pins.
+
+Each case copies the oracle's C source, plants one mistake of the kind a
+transcription of the paper's equations makes (a flipped sign, a dropped term,
+a transposed index), compiles the copy with gcc into a temporary directory and
+runs, against that copy, the pin that must catch it.  The oracle itself is
+never modified; a control case runs the same pins on an unmodified copy built
+the same way.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+ORACLE_DIR = os.path.dirname(os.path.abspath(oracle.__file__))
+SRC = os.path.join(ORACLE_DIR, "mabd_oracle.c")
+
+
+def chain_lu():
+    pins.test_solvers_match_dense_kkt_lu(*pins.small_assemblies()[0])
+
+
+def tree_lu():
+    pins.test_solvers_match_dense_kkt_lu(*pins.small_assemblies()[1])
+
+
+def stretch_modes():
+    pins.test_stretch_mode_is_implicit_euler_oscillator(0, 1e6, 0.0)
+    pins.test_stretch_mode_is_implicit_euler_oscillator(1, 1e6, 0.3)
+
+
+def hinge_pins():
+    pins.test_hinge_blocks_off_axis_rotation()
+    pins.test_pendulum_converges_to_elliptic_solution(True)
+    pins.test_hinge_second_point_rows_are_normal_to_the_axis()
+
+
+# (name, text in the oracle, planted replacement, pin that must fail)
+MUTANTS = [
+    # Eq. variation_energy: gravity enters the force with its own sign
+    ("gravity_sign", "m * s->gravity[r] : 0.0", "-m * s->gravity[r] : 0.0",
+     pins.test_free_fall_closed_form),
+    # implicit Euler: the momentum term M qdot_n / h dropped
+    ("velocity_term_dropped", "f[a] = M * qdn[a] / h - M", "f[a] = 0.0 * qdn[a] / h - M",
+     pins.test_free_fall_closed_form),
+    # the elastic force is minus the energy gradient
+    ("elastic_force_sign", "? -V * F[r * 3 + c] : 0.0", "? V * F[r * 3 + c] : 0.0", stretch_modes),
+    # Eq. polar: (A^T A)^{-1/2}, not (A^T A)^{-1}
+    ("polar_sqrt_dropped", "/ sqrt(w[k]);", "/ w[k];", pins.test_polar_against_svd),
+    # Eq. abd_dof: J(p) = [p^T (x) I3, I3], not [I3 (x) p^T, I3]
+    ("jacobian_transposed", "J[r * 12 + 3 * c + r] = p[c];", "J[r * 12 + 3 * r + c] = p[c];",
+     pins.test_ball_constraints_exact_every_step),
+    # Eq. chain-btd, forward elimination: D_i - B^T D^{-1} B
+    ("thomas_schur_sign", "Dh[25 * i + e] -= Y[e];", "Dh[25 * i + e] += Y[e];", chain_lu),
+    # back-substitution with the coupling block transposed
+    ("thomas_back_transposed", "x[a] -= Bm[25 * i + a * rk[i + 1] + c] * xn[c];",
+     "x[a] -= Bm[25 * i + c * r0 + a] * xn[c];", chain_lu),
+    # tree condensation: the child's G^T S^{-1} G update dropped
+    ("tree_condensed_block_dropped", "Hh[144 * p + e] += U[e];", "Hh[144 * p + e] += 0.0 * U[e];",
+     tree_lu),
+    # tree condensation: the condensed right-hand side with the wrong sign
+    ("tree_condensed_rhs_sign", "fh[12 * p + i] -= acc;", "fh[12 * p + i] += acc;", tree_lu),
+    # Sec. 4.3 hinge frame: the second-order Rodrigues term with the wrong sign
+    ("hinge_frame_sign", "+ K2[i] / (1.0 + a[1]);", "- K2[i] / (1.0 + a[1]);", hinge_pins),
+]
+
+
+def build_copy(tmp_path, old=None, new=None):
+    src = open(SRC).read()
+    if old is not None:
+        assert src.count(old) == 1, f"mutation site not unique: {old!r}"
+        src = src.replace(old, new)
+    path = tmp_path / "mabd_oracle.c"
+    path.write_text(src)
+    lib = tmp_path / "libmabd_oracle_copy.so"
+    subprocess.check_call(["gcc", "-O2", "-march=x86-64-v3", "-std=c99", "-fPIC", "-shared",
+                           "-I", ORACLE_DIR, "-o", str(lib), str(path), "-lm"])
+    return str(lib)
+
+
+def use_library(monkeypatch, path):
+    monkeypatch.setattr(oracle, "LIB_PATH", path)
+    monkeypatch.setattr(oracle, "_lib", None)
+
+
+def test_unmodified_copy_passes_every_pin(tmp_path, monkeypatch):
+    use_library(monkeypatch, build_copy(tmp_path))
+    for pin in {id(m[3]): m[3] for m in MUTANTS}.values():
+        pin()
+
+
+@pytest.mark.parametrize("name,old,new,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(name, old, new, pin, tmp_path, monkeypatch):
+    use_library(monkeypatch, build_copy(tmp_path, old, new))
+    with pytest.raises((AssertionError, oracle.OracleError)):
+        pin()

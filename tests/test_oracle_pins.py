@@ -435,6 +435,43 @@ def test_hinge_gradient_finite_difference_at_rest():
                 assert np.allclose(G[:, j], fd, atol=1e-8)
 
 
+def test_hinge_second_point_rows_are_normal_to_the_axis():
+    """The hinge's two rows on the second control-point pair constrain only
+    the directions normal to the hinge axis (Sec. 4.3: the frame maps the axis
+    onto one coordinate and keeps the other two).  Stretching the hinged body
+    along the axis about the first control point moves the second one along
+    the axis only: no row of C may change.  A shear that moves the second
+    point normal to the axis must change those two rows (the check is not
+    vacuous)."""
+    asm = pins_world_hinge()
+    s = oracle.System(asm)
+    k, b = asm.m - 1, 0
+    a = asm.axis[k] / np.linalg.norm(asm.axis[k])
+    q = asm.q0.copy()
+    cp1 = A_of(q[b]) @ asm.pb[k] + q[b, 9:]
+
+    def stretched(direction, eps):
+        # x -> cp1 + (I + eps direction a^T)(x - cp1): cp1 stays, the second
+        # control point (on the axis through cp1) moves along `direction`
+        S = np.eye(3) + eps * np.outer(direction, a)
+        qs = q.copy()
+        qs[b, :9] = (S @ A_of(q[b])).T.reshape(9)
+        qs[b, 9:] = cp1 + S @ (q[b, 9:] - cp1)
+        return s.joint_terms(qs, k)[0]
+
+    e = 1e-6
+    dC = (stretched(a, e) - stretched(a, -e)) / (2 * e)
+    assert np.abs(dC).max() < 1e-8 * asm.cp_len[k]
+    n = np.cross(a, [1.0, 0.0, 0.0]); n /= np.linalg.norm(n)
+    dCn = (stretched(n, e) - stretched(n, -e)) / (2 * e)
+    assert np.abs(dCn[3:]).max() > 0.1 * asm.cp_len[k]
+
+
+def pins_world_hinge():
+    """The world-owned oblique hinge of small_assemblies()."""
+    return small_assemblies()[3][1]
+
+
 # ---------------------------------------------------------------- pendulum
 
 def pendulum_run(h, T, hinge=False):
