@@ -16,10 +16,15 @@ Parity status per function (pins live in tests/test_oracle_pins.py):
   * ball joints, chain/tree/dense solvers .. pinned (dense KKT LU, exact constraint
                                               residual, pendulum convergence)
   * hinge joints ........................... pinned (finite differences of the
-                                              constraint, hinge pendulum); the
+                                              constraint, hinge pendulum, rows of
+                                              the second point normal to the
+                                              axis); the
                                               A-linearised rotation term itself is a
                                               reading of Eq. r_gradient
   * PCG .................................... pinned against the dense solve
+
+tests/test_oracle_mutants.py plants mistakes in copies of the C source and
+checks that these pins catch them.
 """
 from __future__ import annotations
 
