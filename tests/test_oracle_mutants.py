@@ -53,6 +53,9 @@ MUTANTS = [
     # Eq. abd_dof: J(p) = [p^T (x) I3, I3], not [I3 (x) p^T, I3]
     ("jacobian_transposed", "J[r * 12 + 3 * c + r] = p[c];", "J[r * 12 + 3 * r + c] = p[c];",
      pins.test_ball_constraints_exact_every_step),
+    # footnote of Eq. kkt: the dual right-hand side carries the constraint value C
+    ("dual_rhs_constraint_dropped", "r[i] = d->C[5 * k + i];", "r[i] = 0.0 * d->C[5 * k + i];",
+     pins.test_ball_constraints_exact_every_step),
     # Eq. chain-btd, forward elimination: D_i - B^T D^{-1} B
     ("thomas_schur_sign", "Dh[25 * i + e] -= Y[e];", "Dh[25 * i + e] += Y[e];", chain_lu),
     # back-substitution with the coupling block transposed
