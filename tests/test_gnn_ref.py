@@ -61,7 +61,11 @@ def test_two_joint_message_by_hand():
     deg_b (4 x feature 7), layer 1 copies the neighbour channel, layers 2-3
     and the decoder copy channel 0: the output is the normalised neighbour sum
     n_k = (m_a + m_b) / (deg_a + deg_b) with m_1 = 2 + 1, m_2 = 1, i.e.
-    n_0 = 3 / 2 and n_1 = (3 + 1) / 3."""
+    n_0 = 3 / 2 and n_1 = (3 + 1) / 3.  Two more channels check the
+    rectifiers: channel 1 of the last layer has bias -1 and feeds output 1;
+    channel 2 of the encoder has bias -1 and reaches output 2 through a -1
+    weight in layer 1 and unit weights after it.  Both outputs are 0 only if
+    every layer clips its negative values."""
     asm = mi.chain(3, seed=7)
     net, _, _ = _net(asm)
     assert list(net.ja) == [-1, 1] and list(net.jb) == [1, 2]
@@ -72,6 +76,13 @@ def test_two_joint_message_by_hand():
     for l in (1, 2):
         p[G.P_L0 + l * G.P_LS + 0] = 1.0
     p[G.P_WD + 0] = 1.0
+    p[G.P_L0 + 2 * G.P_LS + 2 * G.W * G.W + 1] = -1.0  # last layer, bias of channel 1
+    p[G.P_WD + 1 * 3 + 1] = 1.0
+    p[G.P_CE + 2] = -1.0                                 # encoder, bias of channel 2
+    p[G.P_L0 + 0 * G.P_LS + 2 * G.W + 2] = -1.0          # layer 1: channel 2 <- -channel 2
+    for l in (1, 2):
+        p[G.P_L0 + l * G.P_LS + 2 * G.W + 2] = 1.0
+    p[G.P_WD + 2 * 3 + 2] = 1.0
     y = net.forward(p) / net.s
     assert np.allclose(y[:, 0], [1.5, 4.0 / 3.0], rtol=1e-14)
     assert np.all(y[:, 1:] == 0.0)

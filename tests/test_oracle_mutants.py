@@ -3,20 +3,24 @@
 Each case copies the oracle's C source, plants one mistake of the kind a
 transcription of the paper's equations makes (a flipped sign, a dropped term,
 a transposed index), compiles the copy with gcc into a temporary directory and
-runs, against that copy, the pin that must catch it.  The oracle itself is
-never modified; a control case runs the same pins on an unmodified copy built
-the same way.
+runs, against that copy, the pin that must catch it.  The reference network
+of the learned warm start (numpy) is treated the same way: a mutated copy of
+its source is loaded as a module of its own.  The oracle itself is never
+modified; control cases run the same pins on unmodified copies.
 """
+import importlib.util
 import os
 import subprocess
 
 import pytest
 
 import oracle
+import test_gnn_ref as gnn_pins
 import test_oracle_pins as pins
 
 ORACLE_DIR = os.path.dirname(os.path.abspath(oracle.__file__))
 SRC = os.path.join(ORACLE_DIR, "mabd_oracle.c")
+GNN_SRC = os.path.join(ORACLE_DIR, "gnn_ref.py")
 
 
 def chain_lu():
@@ -100,3 +104,48 @@ def test_planted_mistake_is_caught(name, old, new, pin, tmp_path, monkeypatch):
     use_library(monkeypatch, build_copy(tmp_path, old, new))
     with pytest.raises((AssertionError, oracle.OracleError)):
         pin()
+
+
+def gnn_all_pins():
+    gnn_pins.test_energy_identity()
+    gnn_pins.test_permutation_equivariance()
+    gnn_pins.test_two_joint_message_by_hand()
+
+
+# (name, text in the reference network, planted replacement)
+GNN_MUTANTS = [
+    ("encoder_relu_dropped", "h = np.maximum(self.x @ We + ce, 0.0)", "h = self.x @ We + ce"),
+    ("layer_relu_dropped", "h = np.maximum(np.concatenate([h, n], axis=1) @ Wl + cl, 0.0)",
+     "h = np.concatenate([h, n], axis=1) @ Wl + cl"),
+    ("degree_norm_one_side", "self.norm = 1.0 / np.maximum(1.0, dga + dgb)",
+     "self.norm = 1.0 / np.maximum(1.0, dga)"),
+    ("message_own_state", "n[k] += m[b]", "n[k] += h[k]"),
+    ("loss_linear_term_sign", "return (0.5 * d @ (self.S @ d) - self.rb @ d) / self.eref",
+     "return (0.5 * d @ (self.S @ d) + self.rb @ d) / self.eref"),
+    ("base_residual_sign", "self.rb = self.r - S @ self.lb", "self.rb = self.r + S @ self.lb"),
+]
+
+
+def load_gnn_copy(tmp_path, old=None, new=None):
+    src = open(GNN_SRC).read()
+    if old is not None:
+        assert src.count(old) == 1, f"mutation site not unique: {old!r}"
+        src = src.replace(old, new)
+    path = tmp_path / "gnn_ref_copy.py"
+    path.write_text(src)
+    spec = importlib.util.spec_from_file_location("gnn_ref_copy", str(path))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_unmodified_network_copy_passes_every_pin(tmp_path, monkeypatch):
+    monkeypatch.setattr(gnn_pins, "G", load_gnn_copy(tmp_path))
+    gnn_all_pins()
+
+
+@pytest.mark.parametrize("name,old,new", GNN_MUTANTS, ids=[m[0] for m in GNN_MUTANTS])
+def test_planted_network_mistake_is_caught(name, old, new, tmp_path, monkeypatch):
+    monkeypatch.setattr(gnn_pins, "G", load_gnn_copy(tmp_path, old, new))
+    with pytest.raises(AssertionError):
+        gnn_all_pins()
