@@ -70,6 +70,12 @@ MUTANTS = [
      tree_lu),
     # tree condensation: the condensed right-hand side with the wrong sign
     ("tree_condensed_rhs_sign", "fh[12 * p + i] -= acc;", "fh[12 * p + i] += acc;", tree_lu),
+    # PCG on the dual (closed loops): the recursive residual r - alpha S p
+    ("pcg_residual_update_sign", "res[i] -= alpha * Ap[i];", "res[i] += alpha * Ap[i];",
+     pins.test_pcg_matches_direct_on_small_lattice),
+    # PCG: the iterate moves along +alpha p
+    ("pcg_iterate_update_sign", "lam[i] += alpha * p[i];", "lam[i] -= alpha * p[i];",
+     pins.test_pcg_matches_direct_on_small_lattice),
     # Sec. 4.3 hinge frame: the second-order Rodrigues term with the wrong sign
     ("hinge_frame_sign", "+ K2[i] / (1.0 + a[1]);", "- K2[i] / (1.0 + a[1]);", hinge_pins),
 ]
