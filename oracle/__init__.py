@@ -9,19 +9,25 @@ numpy arrays into it and adds one step that is a library call: solving the
 assembled sparse dual system with SciPy's SuperLU for graphs too large for the
 dense Cholesky path (Sec. 5.1 allows "any linear solver").
 
-Parity status per function (pins live in tests/test_oracle_pins.py):
+Parity status per function (pins live in tests/test_oracle_pins.py and
+tests/test_oracle_verifier.py):
   * single-body step, free flight .......... pinned (closed-form implicit Euler)
   * co-rotated elastic step ................ pinned (closed-form linear oscillator,
                                               rotation equivariance)
   * ball joints, chain/tree/dense solvers .. pinned (dense KKT LU, exact constraint
                                               residual, pendulum convergence)
   * hinge joints ........................... pinned (finite differences of the
-                                              constraint, hinge pendulum, rows of
-                                              the second point normal to the
-                                              axis); the
-                                              A-linearised rotation term itself is a
-                                              reading of Eq. r_gradient
+                                              constraint at rest and, away from
+                                              rest, along rigid motions; hinge
+                                              pendulum; rows of the second point
+                                              normal to the axis); the
+                                              A-linearised rotation term along
+                                              stretch directions is a reading of
+                                              Eq. r_gradient
   * PCG .................................... pinned against the dense solve
+  * verifier (residual) .................... pinned (closed-form rho_d of scaled
+                                              multipliers, brute-force KKT
+                                              residuals, anchor distances)
 
 tests/test_oracle_mutants.py plants mistakes in copies of the C source and
 checks that these pins catch them.
@@ -80,23 +86,47 @@ def build(force: bool = False) -> str:
     return LIB_PATH
 
 
+def build_native(path: str, openmp: bool) -> str:
+    """Compile a copy of the oracle for the machine it runs on (-O3
+    -march=native, with or without OpenMP over the per-body phases) at `path`;
+    the arithmetic is the same source.  Used for the CPU baseline timing."""
+    import subprocess
+
+    src = os.path.join(_HERE, "mabd_oracle.c")
+    cmd = ["gcc", "-O3", "-march=native", "-std=c99", "-fPIC", "-shared"]
+    if openmp:
+        cmd.append("-fopenmp")
+    subprocess.check_call(cmd + ["-o", path, src, "-lm"])
+    return path
+
+
+def load(path: str):
+    """Load an oracle library built by build_native (CPU baseline only)."""
+    return _declare(ctypes.CDLL(path))
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
-        P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-        L.ora_polar.argtypes = [P, P]; L.ora_polar.restype = I32
-        L.ora_rows.argtypes = [P]; L.ora_rows.restype = I32
-        L.ora_classify.argtypes = [P]; L.ora_classify.restype = I32
-        L.ora_step.argtypes = [P, D, P, P, I32, D, I32, P, P]; L.ora_step.restype = I32
-        L.ora_body_terms.argtypes = [P, D, P, P, I32, P, P, P]; L.ora_body_terms.restype = I32
-        L.ora_joint_terms.argtypes = [P, P, I32, P, P, P]; L.ora_joint_terms.restype = I32
-        L.ora_dual_coo.argtypes = [P, D, P, P, I64, P, P, P, P]; L.ora_dual_coo.restype = I64
-        L.ora_finish.argtypes = [P, D, P, P, P, P, P, P]; L.ora_finish.restype = I32
-        _lib = L
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+def _declare(L):
+    """Argument and result types of the exported oracle calls."""
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.ora_polar.argtypes = [P, P]; L.ora_polar.restype = I32
+    L.ora_rows.argtypes = [P]; L.ora_rows.restype = I32
+    L.ora_classify.argtypes = [P]; L.ora_classify.restype = I32
+    L.ora_step.argtypes = [P, D, P, P, I32, D, I32, P, P]; L.ora_step.restype = I32
+    L.ora_body_terms.argtypes = [P, D, P, P, I32, P, P, P]; L.ora_body_terms.restype = I32
+    L.ora_joint_terms.argtypes = [P, P, I32, P, P, P]; L.ora_joint_terms.restype = I32
+    L.ora_dual_coo.argtypes = [P, D, P, P, I64, P, P, P, P]; L.ora_dual_coo.restype = I64
+    L.ora_finish.argtypes = [P, D, P, P, P, P, P, P]; L.ora_finish.restype = I32
+    L.ora_residual.argtypes = [P, D, P, P, P, P, P, P]; L.ora_residual.restype = I32
+    return L
 
 
 def _p(a):
@@ -197,6 +227,21 @@ class System:
         if st != 0:
             raise OracleError(st, "finish")
         return q1, qd1, diag
+
+    def residual(self, h, q, qd, dq, lam, q_new=None):
+        """Verifier of a step computed elsewhere: the KKT residuals (rho_p,
+        rho_d, max of both) of the increment dq and multipliers lam for the
+        state (q, qd), and the post-step constraint values at q_new (q + dq if
+        None).  Nothing is solved.  Returns the diag vector."""
+        c = np.ascontiguousarray
+        q = c(q, np.float64); qd = c(qd, np.float64); dq = c(dq, np.float64)
+        lam = c(lam, np.float64)
+        qn = None if q_new is None else c(q_new, np.float64)
+        diag = np.zeros(NDIAG)
+        st = lib().ora_residual(self.ref, h, _p(q), _p(qd), _p(dq), _p(lam), _p(qn), _p(diag))
+        if st != 0:
+            raise OracleError(st, "residual")
+        return diag
 
     def step_sparse(self, h, q, qd):
         """One step with the dual solved by SciPy SuperLU (graphs at reduced sizes)."""

@@ -589,18 +589,30 @@ static int build_sd(const ora_system *s, double h, const double *qi, const doubl
   d->Ga = calloc(60 * (m ? m : 1), sizeof(double));
   d->Gb = calloc(60 * (m ? m : 1), sizeof(double));
   build_incid(s, &d->inc);
-  int st = ORA_OK;
-  for (int i = 0; i < s->n && !st; ++i) {
+  /* bodies and joints are independent of each other: with -fopenmp these
+     loops run on all host cores (the result does not depend on it); the
+     reported status is that of the first failing body, then joint */
+  int *bst = calloc(n + 1, sizeof(int)), *jst = calloc(m + 1, sizeof(int));
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < s->n; ++i) {
     if (!is_dyn(s, i)) continue;
     double R[9];
-    st = body_terms_at(s, h, qi + 12 * i, qn + 12 * i, qdn + 12 * i, i, d->H + 144 * i,
-                       d->f + 12 * i, R);
-    if (st) break;
+    bst[i] = body_terms_at(s, h, qi + 12 * i, qn + 12 * i, qdn + 12 * i, i, d->H + 144 * i,
+                           d->f + 12 * i, R);
+    if (bst[i]) continue;
     memcpy(d->L + 144 * i, d->H + 144 * i, sizeof(double) * 144);
-    if (chol(12, d->L + 144 * i)) st = ORA_ESINGULAR;
+    if (chol(12, d->L + 144 * i)) bst[i] = ORA_ESINGULAR;
   }
-  for (int k = 0; k < s->m && !st; ++k)
-    st = joint_terms(s, qi, k, d->C + 5 * k, d->Ga + 60 * k, d->Gb + 60 * k);
+  int st = ORA_OK;
+  for (int i = 0; i < s->n && !st; ++i) st = bst[i];
+  if (!st) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < s->m; ++k)
+      jst[k] = joint_terms(s, qi, k, d->C + 5 * k, d->Ga + 60 * k, d->Gb + 60 * k);
+    for (int k = 0; k < s->m && !st; ++k) st = jst[k];
+  }
+  free(bst);
+  free(jst);
   return st;
 }
 
@@ -1063,6 +1075,7 @@ static int solve_pcg(const ora_system *s, const stepdata *d, double tol, int max
 
 /* dq_b = H_b^{-1} (f_b - sum_k G_kb^T lam_k)  (Eq. primal) */
 static void back_project(const ora_system *s, const stepdata *d, const double *lam, double *dq) {
+#pragma omp parallel for schedule(static)
   for (int b = 0; b < s->n; ++b) {
     double *x = dq + 12 * b;
     memset(x, 0, sizeof(double) * 12);
@@ -1266,6 +1279,39 @@ int32_t ora_finish(const ora_system *s, double h, const double *q, const double 
     post_constraints(s, q_out, &diag[ORA_CBALL], &diag[ORA_CHINGE]);
   }
   free(dq);
+  free_sd(&d);
+  return ORA_OK;
+}
+
+/* The verifier: KKT residuals (oracle diagnostics, Eq. kkt) of a step given
+   from outside as an increment dq and multipliers lam for the state (q, qd),
+   one Newton iteration; post-step constraint values at q_new (at q + dq when
+   q_new is NULL).  Nothing is solved here. */
+int32_t ora_residual(const ora_system *s, double h, const double *q, const double *qd,
+                     const double *dq, const double *lam, const double *q_new, double *diag) {
+  if (validate(s)) return ORA_EINVAL;
+  stepdata d;
+  int st = build_sd(s, h, q, q, qd, &d);
+  if (st) { free_sd(&d); return st; }
+  size_t n = s->n;
+  double *dqd = malloc(sizeof(double) * 12 * (n + 1));
+  double *qe = malloc(sizeof(double) * 12 * (n + 1));
+  for (size_t b = 0; b < n; ++b)
+    for (int c = 0; c < 12; ++c) {
+      dqd[12 * b + c] = is_dyn(s, (int)b) ? dq[12 * b + c] : 0.0;
+      qe[12 * b + c] = q_new ? q_new[12 * b + c] : q[12 * b + c] + dqd[12 * b + c];
+    }
+  double rp, rd;
+  kkt_residual(s, &d, lam, dqd, &rp, &rd);
+  if (diag) {
+    for (int i = 0; i < ORA_NDIAG; ++i) diag[i] = 0.0;
+    diag[ORA_RHO_P] = rp;
+    diag[ORA_RHO_D] = rd;
+    diag[ORA_KKT] = rp > rd ? rp : rd;
+    post_constraints(s, qe, &diag[ORA_CBALL], &diag[ORA_CHINGE]);
+  }
+  free(dqd);
+  free(qe);
   free_sd(&d);
   return ORA_OK;
 }

@@ -62,4 +62,6 @@ int64_t ora_dual_coo(const ora_system *s, double h, const double *q, const doubl
                      int64_t cap, int64_t *I, int64_t *J, double *V, double *r);
 int32_t ora_finish(const ora_system *s, double h, const double *q, const double *qd,
                    const double *lam, double *q_out, double *qd_out, double *diag);
+int32_t ora_residual(const ora_system *s, double h, const double *q, const double *qd,
+                     const double *dq, const double *lam, const double *q_new, double *diag);
 #endif

@@ -17,6 +17,7 @@ import pytest
 import oracle
 import test_gnn_ref as gnn_pins
 import test_oracle_pins as pins
+import test_oracle_verifier as vpins
 
 ORACLE_DIR = os.path.dirname(os.path.abspath(oracle.__file__))
 SRC = os.path.join(ORACLE_DIR, "mabd_oracle.c")
@@ -40,6 +41,15 @@ def hinge_pins():
     pins.test_hinge_blocks_off_axis_rotation()
     pins.test_pendulum_converges_to_elliptic_solution(True)
     pins.test_hinge_second_point_rows_are_normal_to_the_axis()
+
+
+def verifier_pins():
+    vpins.test_exact_solution_has_zero_residual()
+    for sc in (0.0, 0.5, 2.0, -1.0):
+        vpins.test_scaled_multipliers_give_closed_form_dual_residual(sc)
+    vpins.test_perturbed_step_matches_brute_force_residual()
+    vpins.test_primal_residual_is_relative_to_the_free_increment()
+    vpins.test_post_step_constraints()
 
 
 # (name, text in the oracle, planted replacement, pin that must fail)
@@ -78,6 +88,25 @@ MUTANTS = [
      pins.test_pcg_matches_direct_on_small_lattice),
     # Sec. 4.3 hinge frame: the second-order Rodrigues term with the wrong sign
     ("hinge_frame_sign", "+ K2[i] / (1.0 + a[1]);", "- K2[i] / (1.0 + a[1]);", hinge_pins),
+    # Eq. r_gradient, A-linearised: the rotation term with A's indices transposed
+    ("hinge_rotation_term_transposed", "G[i * 12 + 3 * l + kk] += dRh[comp[i] * 3 + l] * dm[kk];",
+     "G[i * 12 + 3 * kk + l] += dRh[comp[i] * 3 + l] * dm[kk];",
+     vpins.test_hinge_gradient_along_rigid_motions_away_from_rest),
+    # the verifier: a dual residual that reads zero
+    ("verifier_rho_d_zeroed", "*rho_d = nr > 0.0 ? sqrt(nd / nr) : sqrt(nd);",
+     "*rho_d = 0.0 * (nr > 0.0 ? sqrt(nd / nr) : sqrt(nd));", verifier_pins),
+    # the verifier: a primal residual that reads zero
+    ("verifier_rho_p_zeroed", "*rho_p = nf > 0.0 ? sqrt(np / nf) : sqrt(np);",
+     "*rho_p = 0.0 * (nf > 0.0 ? sqrt(np / nf) : sqrt(np));", verifier_pins),
+    # the verifier: C dropped from the dual residual G dq + C
+    ("verifier_constraint_dropped", "for (int a = 0; a < rk; ++a) rd[a] = d->C[5 * k + a];",
+     "for (int a = 0; a < rk; ++a) rd[a] = 0.0 * d->C[5 * k + a];", verifier_pins),
+    # the verifier: r_p not mapped through H^{-1}
+    ("verifier_rp_unscaled", "    chol_solve(12, d->L + 144 * b, rp);\n    memcpy(hf",
+     "    memcpy(hf", verifier_pins),
+    # the verifier: the ball joints' post-step value reads zero
+    ("verifier_cball_zeroed", "if (s->jtype[k] == 0) { if (v > *cball) *cball = v; }",
+     "if (s->jtype[k] == 0) { if (v > *cball) *cball = 0.0 * v; }", verifier_pins),
 ]
 
 

@@ -278,9 +278,11 @@ def test_polar_against_svd():
 
 # ------------------------------------------------------------ joint systems
 
-def brute_force_kkt(asm, s, q, qd, h):
-    """Assemble the full KKT of Eq. kkt (with -C on the right) from the oracle's
-    per-body H, f and per-joint C, G, and solve it with LAPACK."""
+def kkt_matrix(asm, s, q, qd, h):
+    """The full KKT matrix of Eq. kkt and its right-hand side [f; -C] (the
+    footnote's -C), assembled from the oracle's per-body H, f and per-joint
+    C, G.  Returns (K, rhs, col, nq): col maps a dynamic body to its first
+    column, nq is the number of primal unknowns."""
     dyn = [i for i in range(asm.n) if not asm.pinned[i]]
     col = {b: 12 * k for k, b in enumerate(dyn)}
     nq = 12 * len(dyn)
@@ -301,10 +303,16 @@ def brute_force_kkt(asm, s, q, qd, h):
                 K[col[side]:col[side] + 12, r0:r0 + rk] = G.T
         rhs[r0:r0 + rk] = -C
         r0 += rk
+    return K, rhs, col, nq
+
+
+def brute_force_kkt(asm, s, q, qd, h):
+    """Solve the full KKT of Eq. kkt (with -C on the right) with LAPACK."""
+    K, rhs, col, nq = kkt_matrix(asm, s, q, qd, h)
     x = np.linalg.solve(K, rhs)
     dq = np.zeros((asm.n, 12))
-    for b in dyn:
-        dq[b] = x[col[b]:col[b] + 12]
+    for b, c in col.items():
+        dq[b] = x[c:c + 12]
     return dq, x[nq:]
 
 
