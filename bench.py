@@ -40,13 +40,97 @@ ALG_BYTES = {
 # index (53 B), multipliers read (24 B), residuals written (96 + 24 B).
 ALG_BYTES_F1 = {"chain_resid": 288 + 53 + 24 + 120}
 # HBM bytes per launch of the dominant kernel measured with rocprofv3 --pmc
-# (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, scales from a plain 512 MiB copy) for
-# the chain tile kernels as they stand, on the 1M chain; keyed by workload,
-# kernel, tile threads and tile packing, and reported only for those.
-PMC_TRAFFIC = {("chain1m", "chain_apply", 64, 1): (149035 * 2 + 221771) * 1024,
-               ("chain1m", "chain_reduce", 64, 1): ((125865 + 19889) * 2 + 39322 + 49566) * 1024,
-               ("chain1m", "chain_apply", 64, 0): (126031 * 2 + 221418) * 1024,
-               ("chain1m", "chain_reduce", 64, 0): (125815 * 2 + 3571) * 1024}
+# (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, scales from a plain 512 MiB copy),
+# keyed by workload, kernel, tile threads and tile packing, together with the
+# SHA-256 (first 16 hex digits) of the kernel source the counters were taken
+# on: once that source changes the figure is stale and `traffic` is null.
+PMC_TRAFFIC = {}
+PMC_SOURCE = os.path.join(ROOT, "paper_2603_08079_amd", "csrc", "k_chain.hip")
+
+
+def source_sha16(path):
+    import hashlib
+
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host (for the CPU baseline)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+def slice_bodies(asm, nb):
+    """Bodies [0, nb) of an assembly with the joints among them (a prefix of
+    the chain workload is the same chain, shorter)."""
+    import dataclasses
+
+    import numpy as np
+
+    jm = (np.where(asm.ja >= 0, asm.ja, 0) < nb) & (np.where(asm.jb >= 0, asm.jb, 0) < nb)
+    return dataclasses.replace(
+        asm, name=f"{asm.name}[:{nb}]", dims=asm.dims[:nb], density=asm.density[:nb],
+        k_orth=asm.k_orth[:nb], pinned=asm.pinned[:nb], q0=asm.q0[:nb], qd0=asm.qd0[:nb],
+        poisson=None if asm.poisson is None else asm.poisson[:nb], jtype=asm.jtype[jm],
+        ja=asm.ja[jm], jb=asm.jb[jm], pa=asm.pa[jm], pb=asm.pb[jm], axis=asm.axis[jm],
+        cp_len=asm.cp_len[jm], meta={})
+
+
+def cpu_baseline(asm, wrench, q, qd, workload, nb, steps):
+    """The FP64 oracle (the same C source, built -O3 -march=native for this
+    host) timed on `steps` steps of a bounded sample of the workload: its
+    first `nb` bodies, from the benchmark's final state.  Two legs: one
+    thread (the paper's design point) and OpenMP over the per-body phases on
+    the host's cores (the chain / tree eliminations stay serial)."""
+    import ctypes
+    import tempfile
+
+    import numpy as np
+
+    import oracle
+
+    sub = slice_bodies(asm, nb)
+    w = None if wrench is None else wrench[:nb]
+    n_dyn = int((sub.pinned == 0).sum())
+    legs = {}
+    with tempfile.TemporaryDirectory() as td:
+        for name, omp in (("single_thread", False), ("openmp", True)):
+            L = oracle.load(oracle.build_native(os.path.join(td, f"ora_{name}.so"), omp))
+            threads = 1
+            if omp:
+                try:
+                    threads = int(ctypes.CDLL("libgomp.so.1").omp_get_max_threads())
+                except OSError:
+                    threads = os.cpu_count()
+            sysm = oracle.System(sub, wrench=w, L=L)
+            qq, qqd = q[:nb].copy(), qd[:nb].copy()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                qq, qqd, _, _ = sysm.step(sub.h, qq, qqd)
+            dt = time.perf_counter() - t0
+            legs[name] = {"body_steps_per_s": round(n_dyn * steps / dt, 1), "threads": threads,
+                          "seconds": round(dt, 2)}
+    model, ncpu, usable = host_cpu()
+    best = max(legs, key=lambda k: legs[k]["body_steps_per_s"])
+    return {"value": legs[best]["body_steps_per_s"], "unit": "body-steps/s",
+            "cores": legs[best]["threads"], "kind": "oracle",
+            "sample": f"{steps} steps of the first {nb} bodies ({n_dyn} dynamic) of the {workload} "
+                      f"workload from the benchmark's final state; FP64 oracle built -O3 "
+                      f"-march=native; value = the faster leg ({best})",
+            "legs": legs, "cpu_model": model, "nproc": ncpu, "usable_cpus": usable}
 
 
 def main():
@@ -57,6 +141,11 @@ def main():
     ap.add_argument("--workload", default="chain1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kkt-check", action="store_true")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed repeats of --steps steps; the median is reported")
+    ap.add_argument("--cpu-sample-bodies", type=int, default=131072,
+                    help="CPU baseline: bodies of the workload's prefix the oracle steps")
+    ap.add_argument("--cpu-sample-steps", type=int, default=10)
     ap.add_argument("--kkt-tol", type=float, default=1e-10, help="PCG stopping tolerance")
     ap.add_argument("--max-iters", type=int, default=200000, help="PCG iteration cap")
     ap.add_argument("--precision", choices=("auto", "0", "1"), default="auto",
@@ -134,18 +223,32 @@ def main():
             return str(e)
 
     def timed(c):
+        """--repeats timed regions of exactly --steps steps, each bracketed by
+        a device synchronisation; the median region is reported."""
         if args.warmup:
             run(c, args.warmup)
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        t0 = time.perf_counter()
-        nc = run(c, args.steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        return {"wall": wall, "gpu_ms": e0.elapsed_time(e1), "stats": c.stats(), "notconv": nc}
+        reps = []
+        for _ in range(max(1, args.repeats)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            t0 = time.perf_counter()
+            nc = run(c, args.steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st_ = c.stats()  # also reads the outcome of the queued steps
+            if st_["last_status"] not in (0, pk.ERR_NOT_CONVERGED):
+                raise RuntimeError(f"step failed with status {st_['last_status']}")
+            if st_["last_status"] == pk.ERR_NOT_CONVERGED and nc is None:
+                nc = "NOT_CONVERGED"
+            reps.append({"wall": wall, "gpu_ms": e0.elapsed_time(e1), "stats": st_, "notconv": nc})
+        reps.sort(key=lambda r: r["wall"])
+        med = dict(reps[len(reps) // 2])
+        med["walls_ms"] = [round(r["wall"] * 1e3, 4) for r in reps]
+        return med
 
     ctx = make(0)
     st0 = ctx.stats()
@@ -201,8 +304,11 @@ def main():
     if dom in ab:
         alg = ab[dom] * n_dyn
         ach = alg / (per_launch[dom] * 1e-3) / 1e9
-        traffic = (PMC_TRAFFIC.get((args.workload, dom, st["tile_threads"], st["tile_packed"]))
-                   if chosen == 0 else None)
+        key = (args.workload, dom, st["tile_threads"], st["tile_packed"])
+        traffic = None
+        if chosen == 0 and key in PMC_TRAFFIC:
+            sha, nbytes = PMC_TRAFFIC[key]
+            traffic = nbytes if sha == source_sha16(PMC_SOURCE) else None
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "avg_launch_ms": round(per_launch[dom], 4),
@@ -225,22 +331,22 @@ def main():
         kkt_notconv = run(ctx, 1)
         lam = ctx.multipliers()
         q1, qd1 = ctx.state()
+        dres = ctx.residual() if st["n_graph"] == 0 or kkt_notconv is None else None
         qo, qdo, diag = s.finish(h, q_n, qd_n, lam)
         kkt = {"rho_p": float(diag[oracle.RHO_P]), "rho_d": float(diag[oracle.RHO_D]),
                "kkt": float(diag[oracle.KKT]),
                "state_rel_err": float(np.abs(q1 - qo).max() / max(1.0, np.abs(qo).max())),
                "vel_rel_err": float(np.abs(qd1 - qdo).max() / max(1e-300, np.abs(qdo).max())),
-               "pcg_not_converged": kkt_notconv}
+               "pcg_not_converged": kkt_notconv,
+               "device_residual": dres}
     if not args.no_cpu_baseline:
-        # the oracle's own step from the same state: CPU baseline, and the KKT
-        # residual its direct FP64 solve reaches there
-        tc = time.perf_counter()
-        qo1, qdo1, lam_o, diag_o = s.step(h, q_n, qd_n)
-        dt = time.perf_counter() - tc
-        cpu = {"value": round(n_dyn / dt, 1), "unit": "body-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full step of the {args.workload} workload ({n_dyn} dynamic bodies) "
-                         f"from the benchmark's final state, single-threaded FP64 oracle, {dt:.2f} s"}
-        if kkt is not None:
+        cpu = cpu_baseline(asm, wrench, q_n, qd_n, args.workload,
+                           min(args.cpu_sample_bodies, asm.n), args.cpu_sample_steps)
+        print(f"# cpu baseline {cpu}", file=sys.stderr, flush=True)
+        if kkt is not None and asm.n <= 2_000_000:
+            # the oracle's own full step from the same state: the KKT residual
+            # its direct FP64 solve reaches there
+            qo1, qdo1, lam_o, diag_o = s.step(h, q_n, qd_n)
             kkt["oracle_rho_p"] = float(diag_o[oracle.RHO_P])
             kkt["oracle_rho_d"] = float(diag_o[oracle.RHO_D])
             kkt["oracle_kkt"] = float(diag_o[oracle.KKT])
@@ -261,6 +367,8 @@ def main():
                    "form": FORMS[chosen], "graph_replay": bool(st["graph_replay"]),
                    "chain_tile_threads": st["tile_threads"],
                    "chain_tiles_packed": bool(st["tile_packed"])},
+        "repeats": {"count": max(1, args.repeats), "statistic": "median",
+                    "walls_ms": res["walls_ms"]},
         "forms": {FORMS[k]: {"ms_per_step": round(v["wall"] * 1e3 / args.steps, 4),
                              "body_steps_per_s": round(n_dyn * args.steps / v["wall"], 1),
                              **({"ir_sweeps_last_step": v["stats"]["ir_sweeps"],

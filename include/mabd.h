@@ -24,8 +24,13 @@
  *     aborts or throws across the ABI.
  *   - A context is not thread-safe; several contexts may coexist.  Work is
  *     issued on the stream given in mabd_options.stream (a hipStream_t), or on
- *     a stream of the library's own when that is NULL.  Only mabd_state,
- *     mabd_stats, mabd_multipliers and error paths synchronise that stream.
+ *     a stream of the library's own when that is NULL.  mabd_step returns as
+ *     soon as its steps are queued (unless the assembly has a network
+ *     component, whose solve runs under host control, or kernel timing is
+ *     on); the outcome of queued steps is read by the next call that waits
+ *     for the stream: mabd_state, mabd_multipliers, mabd_residual, mabd_stats,
+ *     mabd_set_state, mabd_set_wrenches, the learned-start calls, or a later
+ *     mabd_step once that outcome has arrived.
  *   - Units are SI.  q per body = [a1; a2; a3; t] (12 doubles), a_c the c-th
  *     column of the affine matrix A, t the translation (Sec. 3.1, Eq. abd_dof);
  *     qdot has the same layout.
@@ -83,8 +88,15 @@ typedef struct {
   int32_t precision;       /* 0 FP64 throughout; 1 on chain components: FP32 body solve and
                               dual assembly, FP64 dual factor, then FP64 KKT residual
                               checks and correction sweeps until max(rho_p, rho_d) <=
-                              kkt_tol, or until a sweep no longer halves it (the FP64
-                              rounding floor).  Trees and graphs stay FP64               */
+                              kkt_tol; a sweep that no longer halves it has reached the
+                              FP64 rounding floor and ends the step, accepted
+                              (stats.ir_stalled = 1) if the residual is within 10
+                              kkt_tol, or if rho_p is and |G dq + C| is within 64
+                              units of rounding of the size of the summands it is
+                              formed from (where the dual right-hand side all but
+                              vanishes, as for a freely falling chain, rho_d is O(1)
+                              for any FP64 solution);
+                              NOT_CONVERGED otherwise.  Trees and graphs stay FP64     */
   double kkt_tol;          /* PCG stop: |r - S lam| <= kkt_tol |r|; precision-1 target of
                               the chain KKT residual; default 1e-10                      */
   int32_t max_iters;       /* PCG iteration cap, default 200000                           */
@@ -93,7 +105,10 @@ typedef struct {
   int32_t newton_iters;    /* Newton iterations per step, default 1                       */
   int32_t hinge_grad;      /* 0 frozen frame + A-linearised rotation term, 2 frozen only  */
   int32_t material;        /* 0: mu = 4 k_A, lambda = 0 (Eq. EA linearised); 1: Lame     */
-  int32_t diagnostics;     /* bit 0: evaluate the FP64 KKT residual after every step;
+  int32_t diagnostics;     /* bit 0: evaluate on the device, after every step, the FP64
+                              KKT residual of the step (every Newton iteration's when
+                              newton_iters > 1) and the joint values at the new state
+                              (stats rho_p, rho_d, kkt, c_ball, c_hinge, kkt_newton);
                               bit 1: time every kernel group with HIP events (phase_ms)  */
   int32_t use_graph;       /* 1 (default): replay each step as a captured hipGraph when
                               the assembly has no PCG component and bit 1 is off        */
@@ -112,14 +127,20 @@ typedef struct {
 } mabd_options;
 
 #define MABD_NPHASES 10
+#define MABD_NEWTON_DIAG 8  /* Newton iterations whose KKT residual the stats keep */
 
 typedef struct {
   int64_t steps_done;      /* steps completed since create                               */
   int32_t last_status;     /* status of the last mabd_step                               */
   int32_t pcg_iters;       /* PCG iterations of the last step (max over components)      */
-  double rho_p, rho_d;     /* |H^-1 r_p|/|H^-1 f|, |G dq + C|/|G H^-1 f + C| (diagnostics) */
+  /* FP64 KKT residual of the last step (Eq. kkt with the -C right-hand side):
+     r_p = f_A - H dq - G^T lambda, r_d = G dq + C.  With diagnostics bit 0 all
+     five values come from the device evaluation; otherwise rho_d is the PCG's
+     true residual (network components), rho_p, rho_d and kkt the form-1
+     refinement's (chains, precision 1), and -1 / 0 where nothing evaluated them */
+  double rho_p, rho_d;     /* |H^-1 r_p|/|H^-1 f_A|, |r_d|/|G H^-1 f_A + C|                */
   double kkt;              /* max(rho_p, rho_d)                                           */
-  double c_ball, c_hinge;  /* max |C| after the step per joint type (diagnostics)         */
+  double c_ball, c_hinge;  /* max |C| at the new state per joint type (diagnostics bit 0) */
   int32_t ir_sweeps;       /* refinement sweeps of the last step (precision 1)           */
   int32_t warm_accepted;   /* 1 if the GNN warm start was kept                            */
   int32_t n_chain, n_tree, n_graph;  /* components per solver class                     */
@@ -136,6 +157,11 @@ typedef struct {
   int32_t tree_rounds;     /* rounds of the tree contraction (rake + compress)          */
   int32_t tile_packed;     /* 1 if the chain tiles are packed: 60-row tiles whose last
                               four cyclic-reduction levels run four tiles to a wave     */
+  int32_t ir_stalled;      /* precision 1: the refinement of the last step ended at the
+                              rounding floor (see precision) instead of below kkt_tol    */
+  double kkt_newton[MABD_NEWTON_DIAG]; /* diagnostics bit 0: KKT residual of each Newton
+                              iteration of the last step (a ninth and later iterations
+                              share the last entry), -1 where not evaluated             */
 } mabd_step_stats;
 
 /* Fills *opt with the defaults listed above. */
@@ -155,13 +181,22 @@ mabd_status mabd_create(const mabd_bodies *bodies, const mabd_joints *joints,
 /* Advances n >= 1 steps of size h > 0 (implicit Euler, Eq. variation_energy;
    newton_iters Newton iterations per step, Eq. kkt).  If h differs from the
    previous call the per-shape factors Hbar^{-1} are rebuilt first (Eq.
-   abd_final).  Asynchronous on the context's stream unless diagnostics or PCG
-   convergence need a host read.  On NONFINITE, NOT_CONVERGED or SINGULAR the
-   state stays at the last completed step. */
+   abd_final).  Asynchronous on the context's stream: it returns once the
+   steps are queued, except for assemblies with a network component (PCG under
+   host control) and kernel timing (diagnostics bit 1), which wait.  A step
+   that fails (NONFINITE, NOT_CONVERGED, SINGULAR) makes the later queued
+   steps do nothing and leaves the state at the last completed step; the
+   failure is returned by the next call that reads the outcome (mabd_state,
+   mabd_multipliers, mabd_residual, a learned-start call, or mabd_step itself
+   once the outcome has arrived) and recorded in mabd_stats' last_status,
+   also where mabd_set_state or mabd_set_wrenches read it.  The state
+   written by mabd_state_device is the last completed step's in every case. */
 mabd_status mabd_step(mabd_ctx *ctx, double h, int32_t n);
 
 /* Copies the state to host buffers q, qd (n*12 doubles each, input body
-   order; either may be NULL).  Synchronises the stream. */
+   order; either may be NULL).  Synchronises the stream and returns the
+   failure of a queued step, if one failed (the state copied is then the last
+   completed step's). */
 mabd_status mabd_state(const mabd_ctx *ctx, double *q, double *qd);
 
 /* Writes the state into device buffers (n*12 doubles each, input body order)
@@ -169,7 +204,8 @@ mabd_status mabd_state(const mabd_ctx *ctx, double *q, double *qd);
 mabd_status mabd_state_device(const mabd_ctx *ctx, void *q_dev, void *qd_dev);
 
 /* Replaces the state (host buffers, n*12 doubles each, input order).  Pinned
-   bodies keep q0.  Bitwise continuation: set_state(state()) changes nothing. */
+   bodies keep q0.  Bitwise continuation: set_state(state()) changes nothing.
+   Waits for queued steps first; the multipliers stop being a warm start. */
 mabd_status mabd_set_state(mabd_ctx *ctx, const double *q, const double *qd);
 
 /* External spatial wrenches W = [tau; f] per body (host, n*6 doubles in input
@@ -184,11 +220,50 @@ mabd_status mabd_set_wrenches(mabd_ctx *ctx, const double *w);
 
 /* Multipliers dlambda of the last step's dual solve (Eq. dual) in input joint
    order, 3 doubles per ball joint and 5 per hinge, concatenated.  lam must hold
-   mabd_rows(ctx) doubles.  Synchronises the stream. */
+   mabd_rows(ctx) doubles.  Synchronises the stream; returns the failure of a
+   queued step, if one failed. */
 mabd_status mabd_multipliers(const mabd_ctx *ctx, double *lam);
 int64_t mabd_rows(const mabd_ctx *ctx);
 
-/* Diagnostics of the last step.  Synchronises the stream. */
+/* FP64 KKT residual of the last completed step, evaluated on the device
+   from the state it started from, its increment dq = h qdot_new and its
+   multipliers (Eq. kkt with the -C of its footnote):
+     out[0] rho_p = |H^-1 (f_A - H dq - G^T lambda)| / |H^-1 f_A|,
+     out[1] rho_d = |G dq + C| / |G H^-1 f_A + C|,
+     out[2] max(rho_p, rho_d),
+     out[3], out[4] largest |C| of the ball joints / hinges at the new state
+   (out: 5 host doubles).  Partial sums go to a buffer of the library's,
+   allocated at the first call (diag_blocks x 6 doubles, diag_blocks = chain
+   tiles + ceil(generic bodies / 256) + ceil(generic joints / 256)) and kept
+   until mabd_destroy.  Synchronises the stream.  Errors: the failure of a
+   queued step; INVALID_ARG if no step completed since create, mabd_set_state,
+   mabd_set_wrenches or a learned-start call, or if newton_iters > 1
+   (diagnostics bit 0 evaluates every iteration instead); OOM; DEVICE. */
+mabd_status mabd_residual(mabd_ctx *ctx, double *out);
+
+/* Spatial twist of every body at the current state (Eq. module1-G-twist):
+   V = G(A) qdot = [omega; v], omega = 1/2 sum_c a_c x adot_c (a_c the c-th
+   column of A), v = tdot; world frame.  V: host, n*6 doubles in input body
+   order, zero for pinned bodies.  Synchronises the stream; returns the
+   failure of a queued step, if one failed. */
+mabd_status mabd_twists(const mabd_ctx *ctx, double *V);
+
+/* Joint wrench on every body from the last step: the spatial wrench W =
+   [tau; f] (world frame, about the centre of mass) that does the same
+   virtual work on rigid motions as the body's generalised joint force
+   -sum_k G_kb^T dlambda_k (the primal rows of Eq. kkt), W = E(A)^T (-G^T
+   dlambda) with the rigid-motion embedding E(A) of Eq. module2-E, taken at
+   the state the step started from (single-body comparison of Sec. 6: the
+   spatial wrench of a generalised force).  For a ball joint this is the
+   point force at the anchor and its moment.  W: host, n*6 doubles in input
+   body order, zero for pinned bodies.  Synchronises the stream.  Errors: the
+   failure of a queued step; INVALID_ARG if no step completed since create,
+   mabd_set_state, mabd_set_wrenches or a learned-start call, or if
+   newton_iters > 1. */
+mabd_status mabd_joint_wrenches(const mabd_ctx *ctx, double *W);
+
+/* Diagnostics of the last step.  Synchronises the stream; the outcome of
+   queued steps goes to st->last_status (the call itself returns MABD_OK). */
 mabd_status mabd_stats(const mabd_ctx *ctx, mabd_step_stats *st);
 
 /* ---------------------------------------------------------------------------

@@ -28,6 +28,11 @@ tests/test_oracle_verifier.py):
   * verifier (residual) .................... pinned (closed-form rho_d of scaled
                                               multipliers, brute-force KKT
                                               residuals, anchor distances)
+  * twists and joint wrenches .............. pinned (rigid spin closed form,
+                                              wrench round trip through G(A)^T,
+                                              action and reaction of internal
+                                              joints, a hanging body carrying
+                                              its weight)
 
 tests/test_oracle_mutants.py plants mistakes in copies of the C source and
 checks that these pins catch them.
@@ -126,6 +131,8 @@ def _declare(L):
     L.ora_dual_coo.argtypes = [P, D, P, P, I64, P, P, P, P]; L.ora_dual_coo.restype = I64
     L.ora_finish.argtypes = [P, D, P, P, P, P, P, P]; L.ora_finish.restype = I32
     L.ora_residual.argtypes = [P, D, P, P, P, P, P, P]; L.ora_residual.restype = I32
+    L.ora_twists.argtypes = [P, P, P, P]; L.ora_twists.restype = I32
+    L.ora_joint_wrenches.argtypes = [P, P, P, P]; L.ora_joint_wrenches.restype = I32
     return L
 
 
@@ -137,7 +144,10 @@ class System:
     """Holds contiguous copies of an assembly's arrays and the C struct."""
 
     def __init__(self, asm, material: Optional[int] = None, hinge_grad: int = 0,
-                 newton_iters: int = 1, gravity=None, wrench=None):
+                 newton_iters: int = 1, gravity=None, wrench=None, L=None):
+        # L: an oracle library loaded with load() (the same source built for
+        # the host, for the CPU baseline timing); default: the test build
+        self.L = lib() if L is None else L
         c = np.ascontiguousarray
         self.n, self.m = asm.n, asm.m
         self.dims = c(asm.dims, np.float64)
@@ -166,14 +176,14 @@ class System:
         s.hinge_grad = hinge_grad
         s.newton_iters = newton_iters
         self.s = s
-        self.rows = lib().ora_rows(ctypes.byref(s))
+        self.rows = self.L.ora_rows(ctypes.byref(s))
 
     @property
     def ref(self):
         return ctypes.byref(self.s)
 
     def classify(self) -> int:
-        return lib().ora_classify(self.ref)
+        return self.L.ora_classify(self.ref)
 
     def step(self, h, q, qd, solver=AUTO, tol=1e-10, max_iters=100000):
         """One time step.  Returns (q1, qd1, lam, diag)."""
@@ -181,7 +191,7 @@ class System:
         qd1 = np.array(qd, np.float64, order="C", copy=True)
         lam = np.zeros(max(self.rows, 1))
         diag = np.zeros(NDIAG)
-        st = lib().ora_step(self.ref, h, _p(q1), _p(qd1), solver, tol, max_iters, _p(lam),
+        st = self.L.ora_step(self.ref, h, _p(q1), _p(qd1), solver, tol, max_iters, _p(lam),
                             _p(diag))
         if st != 0:
             raise OracleError(st, "step")
@@ -190,7 +200,7 @@ class System:
     def body_terms(self, h, q, qd, i):
         H = np.zeros((12, 12)); f = np.zeros(12); R = np.zeros(9)
         q = np.ascontiguousarray(q, np.float64); qd = np.ascontiguousarray(qd, np.float64)
-        st = lib().ora_body_terms(self.ref, h, _p(q), _p(qd), i, _p(H), _p(f), _p(R))
+        st = self.L.ora_body_terms(self.ref, h, _p(q), _p(qd), i, _p(H), _p(f), _p(R))
         if st != 0:
             raise OracleError(st, "body_terms")
         return H, f, R
@@ -198,7 +208,7 @@ class System:
     def joint_terms(self, q, k):
         C = np.zeros(5); Ga = np.zeros((5, 12)); Gb = np.zeros((5, 12))
         q = np.ascontiguousarray(q, np.float64)
-        st = lib().ora_joint_terms(self.ref, _p(q), k, _p(C), _p(Ga), _p(Gb))
+        st = self.L.ora_joint_terms(self.ref, _p(q), k, _p(C), _p(Ga), _p(Gb))
         if st != 0:
             raise OracleError(st, "joint_terms")
         r = 5 if self.jtype[k] == 1 else 3
@@ -209,12 +219,12 @@ class System:
         import scipy.sparse as sp
 
         q = np.ascontiguousarray(q, np.float64); qd = np.ascontiguousarray(qd, np.float64)
-        nnz = lib().ora_dual_coo(self.ref, h, _p(q), _p(qd), 0, None, None, None, None)
+        nnz = self.L.ora_dual_coo(self.ref, h, _p(q), _p(qd), 0, None, None, None, None)
         if nnz < 0:
             raise OracleError(int(nnz), "dual_coo")
         I = np.zeros(max(nnz, 1), np.int64); J = np.zeros(max(nnz, 1), np.int64)
         V = np.zeros(max(nnz, 1)); r = np.zeros(max(self.rows, 1))
-        lib().ora_dual_coo(self.ref, h, _p(q), _p(qd), nnz, _p(I), _p(J), _p(V), _p(r))
+        self.L.ora_dual_coo(self.ref, h, _p(q), _p(qd), nnz, _p(I), _p(J), _p(V), _p(r))
         S = sp.coo_matrix((V[:nnz], (I[:nnz], J[:nnz])), shape=(self.rows, self.rows)).tocsr()
         return S, r[: self.rows]
 
@@ -223,7 +233,7 @@ class System:
         q = np.ascontiguousarray(q, np.float64); qd = np.ascontiguousarray(qd, np.float64)
         lam = np.ascontiguousarray(lam, np.float64)
         q1 = np.zeros_like(q); qd1 = np.zeros_like(qd); diag = np.zeros(NDIAG)
-        st = lib().ora_finish(self.ref, h, _p(q), _p(qd), _p(lam), _p(q1), _p(qd1), _p(diag))
+        st = self.L.ora_finish(self.ref, h, _p(q), _p(qd), _p(lam), _p(q1), _p(qd1), _p(diag))
         if st != 0:
             raise OracleError(st, "finish")
         return q1, qd1, diag
@@ -238,10 +248,31 @@ class System:
         lam = c(lam, np.float64)
         qn = None if q_new is None else c(q_new, np.float64)
         diag = np.zeros(NDIAG)
-        st = lib().ora_residual(self.ref, h, _p(q), _p(qd), _p(dq), _p(lam), _p(qn), _p(diag))
+        st = self.L.ora_residual(self.ref, h, _p(q), _p(qd), _p(dq), _p(lam), _p(qn), _p(diag))
         if st != 0:
             raise OracleError(st, "residual")
         return diag
+
+    def twists(self, q, qd):
+        """Spatial twist [omega; v] of every body (n x 6)."""
+        c = np.ascontiguousarray
+        q = c(q, np.float64); qd = c(qd, np.float64)
+        V = np.zeros((self.n, 6))
+        st = self.L.ora_twists(self.ref, _p(q), _p(qd), _p(V))
+        if st != 0:
+            raise OracleError(st, "twists")
+        return V
+
+    def joint_wrenches(self, q, lam):
+        """Spatial wrench [tau; f] (about the COM) of the joint forces of a
+        step from q with multipliers lam, on every body (n x 6)."""
+        c = np.ascontiguousarray
+        q = c(q, np.float64); lam = c(lam, np.float64)
+        W = np.zeros((self.n, 6))
+        st = self.L.ora_joint_wrenches(self.ref, _p(q), _p(lam), _p(W))
+        if st != 0:
+            raise OracleError(st, "joint_wrenches")
+        return W
 
     def step_sparse(self, h, q, qd):
         """One step with the dual solved by SciPy SuperLU (graphs at reduced sizes)."""

@@ -1315,3 +1315,65 @@ int32_t ora_residual(const ora_system *s, double h, const double *q, const doubl
   free_sd(&d);
   return ORA_OK;
 }
+
+/* Spatial twist of every body (Eq. module1-G-twist): V = G(A) qdot with
+   omega = 1/2 sum_c q_c x qdot_c (q_c the c-th column of A) and v = tdot;
+   V holds n*6 values [omega; v], zero for pinned bodies. */
+int32_t ora_twists(const ora_system *s, const double *q, const double *qd, double *V) {
+  if (validate(s)) return ORA_EINVAL;
+  for (int b = 0; b < s->n; ++b) {
+    double *o = V + 6 * (size_t)b;
+    for (int i = 0; i < 6; ++i) o[i] = 0.0;
+    if (!is_dyn(s, b)) continue;
+    for (int c = 0; c < 3; ++c) {
+      const double *a = q + 12 * (size_t)b + 3 * c, *ad = qd + 12 * (size_t)b + 3 * c;
+      o[0] += 0.5 * (a[1] * ad[2] - a[2] * ad[1]);
+      o[1] += 0.5 * (a[2] * ad[0] - a[0] * ad[2]);
+      o[2] += 0.5 * (a[0] * ad[1] - a[1] * ad[0]);
+    }
+    for (int i = 0; i < 3; ++i) o[3 + i] = qd[12 * (size_t)b + 9 + i];
+  }
+  return ORA_OK;
+}
+
+/* Joint wrench on every body: the spatial wrench (world frame, about the
+   centre of mass) that does the same virtual work on rigid motions as the
+   generalised joint force -sum_k G_kb^T lam_k of a step from q (the force
+   term of the primal rows of Eq. kkt), W = E(A)^T f with the rigid-motion
+   embedding E(A) of Eq. module2-E: W = [sum_c q_c x f_c; f_t].  G is taken
+   at q; W holds n*6 values [tau; f], zero for pinned bodies. */
+int32_t ora_joint_wrenches(const ora_system *s, const double *q, const double *lam, double *W) {
+  if (validate(s)) return ORA_EINVAL;
+  size_t n = s->n;
+  double *f = calloc(12 * (n ? n : 1), sizeof(double));
+  int off = 0;
+  for (int k = 0; k < s->m; ++k) {
+    double C[5], Ga[60], Gb[60];
+    int rk = jrows(s, k);
+    int st = joint_terms(s, q, k, C, Ga, Gb);
+    if (st) { free(f); return st; }
+    for (int side = 0; side < 2; ++side) {
+      int b = side ? s->jb[k] : s->ja[k];
+      if (!is_dyn(s, b)) continue;
+      const double *G = side ? Gb : Ga;
+      for (int c = 0; c < 12; ++c)
+        for (int i = 0; i < rk; ++i) f[12 * (size_t)b + c] -= G[i * 12 + c] * lam[off + i];
+    }
+    off += rk;
+  }
+  for (size_t b = 0; b < n; ++b) {
+    double *o = W + 6 * b;
+    const double *fb = f + 12 * b, *qb = q + 12 * b;
+    for (int i = 0; i < 6; ++i) o[i] = 0.0;
+    if (!is_dyn(s, (int)b)) continue;
+    for (int c = 0; c < 3; ++c) {
+      const double *a = qb + 3 * c, *fc = fb + 3 * c;
+      o[0] += a[1] * fc[2] - a[2] * fc[1];
+      o[1] += a[2] * fc[0] - a[0] * fc[2];
+      o[2] += a[0] * fc[1] - a[1] * fc[0];
+    }
+    for (int i = 0; i < 3; ++i) o[3 + i] = fb[9 + i];
+  }
+  free(f);
+  return ORA_OK;
+}

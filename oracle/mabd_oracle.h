@@ -64,4 +64,6 @@ int32_t ora_finish(const ora_system *s, double h, const double *q, const double 
                    const double *lam, double *q_out, double *qd_out, double *diag);
 int32_t ora_residual(const ora_system *s, double h, const double *q, const double *qd,
                      const double *dq, const double *lam, const double *q_new, double *diag);
+int32_t ora_twists(const ora_system *s, const double *q, const double *qd, double *V);
+int32_t ora_joint_wrenches(const ora_system *s, const double *q, const double *lam, double *W);
 #endif

@@ -21,7 +21,9 @@ OK, ERR_INVALID_ARG, ERR_TOPOLOGY, ERR_DEVICE, ERR_OOM, ERR_NONFINITE, ERR_NOT_C
     ERR_SINGULAR = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTED = ["mabd_options_default", "mabd_create", "mabd_step", "mabd_state", "mabd_state_device",
-            "mabd_set_state", "mabd_set_wrenches", "mabd_multipliers", "mabd_rows", "mabd_stats",
+            "mabd_set_state", "mabd_set_wrenches", "mabd_multipliers", "mabd_rows", "mabd_residual",
+            "mabd_twists", "mabd_joint_wrenches",
+            "mabd_stats",
             "mabd_gnn_size",
             "mabd_gnn_init", "mabd_gnn_params", "mabd_gnn_grad", "mabd_gnn_train", "mabd_gnn_predict",
             "mabd_gnn_save", "mabd_gnn_load", "mabd_last_error", "mabd_destroy"]
@@ -58,6 +60,7 @@ class Options(ctypes.Structure):
 
 
 NPHASES = 10
+NEWTON_DIAG = 8
 
 
 class StepStats(ctypes.Structure):
@@ -70,7 +73,8 @@ class StepStats(ctypes.Structure):
                 ("n_graph", ctypes.c_int32), ("n_dyn", ctypes.c_int32),
                 ("phase_ms", ctypes.c_double * NPHASES), ("phase_calls", ctypes.c_int64 * NPHASES),
                 ("tile_threads", ctypes.c_int32), ("graph_replay", ctypes.c_int32),
-                ("tree_rounds", ctypes.c_int32), ("tile_packed", ctypes.c_int32)]
+                ("tree_rounds", ctypes.c_int32), ("tile_packed", ctypes.c_int32),
+                ("ir_stalled", ctypes.c_int32), ("kkt_newton", ctypes.c_double * NEWTON_DIAG)]
 
     PHASES = ("chain_reduce", "chain_global", "chain_apply", "body", "joint", "tree", "apply",
               "pcg", "chain_resid", "chain_finish")
@@ -79,6 +83,7 @@ class StepStats(ctypes.Structure):
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["phase_ms"] = list(self.phase_ms)
         d["phase_calls"] = list(self.phase_calls)
+        d["kkt_newton"] = list(self.kkt_newton)
         return d
 
 
@@ -104,6 +109,9 @@ def lib():
         L.mabd_multipliers.argtypes = [P, P]; L.mabd_multipliers.restype = I32
         L.mabd_rows.argtypes = [P]; L.mabd_rows.restype = I64
         L.mabd_stats.argtypes = [P, P]; L.mabd_stats.restype = I32
+        L.mabd_residual.argtypes = [P, P]; L.mabd_residual.restype = I32
+        L.mabd_twists.argtypes = [P, P]; L.mabd_twists.restype = I32
+        L.mabd_joint_wrenches.argtypes = [P, P]; L.mabd_joint_wrenches.restype = I32
         L.mabd_gnn_load.argtypes = [P, ctypes.c_char_p]; L.mabd_gnn_load.restype = I32
         L.mabd_gnn_save.argtypes = [P, ctypes.c_char_p]; L.mabd_gnn_save.restype = I32
         L.mabd_gnn_size.argtypes = []; L.mabd_gnn_size.restype = I32
@@ -205,6 +213,25 @@ class Context:
         lam = np.zeros(max(self.rows, 1))
         self._check(lib().mabd_multipliers(self.h, lam.ctypes.data))
         return lam[: self.rows]
+
+    def residual(self) -> dict:
+        """FP64 KKT residual of the last completed step, evaluated on the device."""
+        out = np.zeros(5)
+        self._check(lib().mabd_residual(self.h, out.ctypes.data))
+        return dict(zip(("rho_p", "rho_d", "kkt", "c_ball", "c_hinge"), out.tolist()))
+
+    def twists(self) -> np.ndarray:
+        """Spatial twist [omega; v] of every body at the current state (n x 6)."""
+        V = np.zeros((self.n, 6))
+        self._check(lib().mabd_twists(self.h, V.ctypes.data))
+        return V
+
+    def joint_wrenches(self) -> np.ndarray:
+        """Spatial wrench [tau; f] of the last step's joint forces on every
+        body, about its centre of mass (n x 6)."""
+        W = np.zeros((self.n, 6))
+        self._check(lib().mabd_joint_wrenches(self.h, W.ctypes.data))
+        return W
 
     def stats(self) -> dict:
         s = StepStats()

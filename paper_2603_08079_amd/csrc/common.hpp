@@ -73,6 +73,18 @@ constexpr int HINV_STRIDE = 20;
 
 constexpr int NO_FAIL = 0x7fffffff;
 
+// precision form 1: a correction sweep that does not halve the KKT residual
+// has reached the FP64 rounding floor; the step is accepted there only if the
+// residual is within this factor of kkt_tol
+constexpr double IR_STALL_FACTOR = 10.0;
+// ... or if rho_p is and |G dq + C| is within this many units of rounding of
+// the size of the summands it is formed from (per row: the translation
+// difference, both anchor offsets A p, both ends' increments J(p) dq)
+constexpr double IR_ROUND_FACTOR = 64.0;
+// form-1 partials per tile: the four sums behind rho_p and rho_d, then the
+// squared size of the summands of G dq + C
+constexpr int IR_PART = 5;
+
 struct ChainArgs {
   const ChainDesc *chains;
   const TileDesc *tiles;
@@ -97,8 +109,9 @@ struct ChainArgs {
   double *dq;                 // 12 x ns accumulated increment of the current step (SoA)
   double *rp;                 // 12 x ns FP64 primal residual, world frame (SoA)
   double *rd;                 // 3 x nrs FP64 dual residual per chain row (SoA)
-  double *part;               // 4 partial sums per tile
-  double *ir;                 // [0] 0 running / 1 converged / 2 stalled, [1] sweeps,
+  double *part;               // IR_PART partial sums per tile (DIAG_PART with diag)
+  double *ir;                 // [0] 0 running / 1 converged / 2 stalled near tol /
+                              // 3 stalled above it, [1] sweeps,
                               // [2] rho_p, [3] rho_d, [4] kkt, [5] previous kkt
   const double *wr;           // 6 x ns external wrench [tau; f] per body (SoA), or null
   // packed tiles (per group of four tiles, 64 lanes each): surviving rows
@@ -106,7 +119,15 @@ struct ChainArgs {
   // [PACK_CF][64]
   double *psv;
   double *pcf;
+  // 1: chain_resid_kernel checks a finished step (dq = h qd_out, constraint
+  // values at q_out) and writes DIAG_PART partials per tile into part
+  int diag;
 };
+
+// partials per block of the step diagnostics: sum |H^-1 r_p|^2, sum
+// |H^-1 f_A|^2, sum |G H^-1 f_A + C|^2, sum |G dq + C|^2, max |C| of ball
+// joints and of hinges at the new state
+constexpr int DIAG_PART = 6;
 
 // status words: [0] FLAG_* bits, [1] first failing step of the current call,
 // [2] index of the running step (set on the device by a one-thread kernel at

@@ -23,6 +23,7 @@
 // writes lambda and the new state.  Recomputing A-C costs one more read of
 // q, qdot but moves no dense elimination factors through HBM (packed tiles
 // read only the factors of the rows eliminated four tiles to a wave).
+#include <cfloat>
 #include <type_traits>
 
 #include "common.hpp"
@@ -1060,12 +1061,18 @@ __global__ __launch_bounds__(256) void chain_global_kernel(const ChainDesc *chai
 // r_d = -(C + G dq) per row, and per tile the sums behind
 // rho_p = |H^{-1} r_p| / |H^{-1} f_A| and rho_d = |r_d| / |G H^{-1} f_A + C|
 // (the KKT residual of Eq. kkt with the -C right-hand side).
+//
+// With a.diag set the kernel checks a finished step instead: q, qd are the
+// state the step started from, dq = h qd_out its increment, nothing is
+// stored but the tile partials (DIAG_PART per tile: the four sums, then the
+// largest |C| of the rows at the new state q_out, then 0 for hinges).
 template <int NT, bool WR>
 __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
-  enum { L_VB = 0, L_CB = 3, L_TB = 6, L_GB = 9, L_RED = 12 };
-  __shared__ double lds[16 * NT];
+  enum { L_VB = 0, L_CB = 3, L_TB = 6, L_GB = 9, L_RED = 12, L_CN = 16, L_TN = 19, L_CM = 22, L_SE = 23 };
+  __shared__ double lds[24 * NT];
   if (skip_step(a.status, a.step)) return;
-  if (a.ir[0] != 0.0) return;
+  const bool diag = a.diag != 0;
+  if (!diag && a.ir[0] != 0.0) return;
   const int ti = xcd_tile(a.ntiles);
   if (ti < 0) return;
   const TileDesc td = a.tiles[ti];
@@ -1088,7 +1095,11 @@ __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
   double sa = 1.0, sb = 1.0;
   double va[3] = {0, 0, 0}, ca[3] = {0, 0, 0}, ta[3] = {0, 0, 0}, ga[3] = {0, 0, 0};
   double vb[3] = {0, 0, 0}, cb[3] = {0, 0, 0}, tb[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
-  double sp = 0.0, sf = 0.0, sr = 0.0, sd = 0.0;
+  // diag: the joint values at the new state, split as in C
+  double cna[3] = {0, 0, 0}, tna[3] = {0, 0, 0}, cnb[3] = {0, 0, 0}, tnb[3] = {0, 0, 0};
+  // sums behind rho_p, rho_d; se: squared size of the summands of r_d (its
+  // rounding floor); cmax: diagnostics
+  double sp = 0.0, sf = 0.0, sr = 0.0, sd = 0.0, se = 0.0, cmax = 0.0;
   if (has_a) {
     for (int i = 0; i < 3; ++i) {
       pa[i] = a.pr[i * a.nrs + gra];
@@ -1109,7 +1120,26 @@ __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
     for (int c = 0; c < 12; ++c) {
       q[c] = a.q[c * a.ns + bg];
       qd[c] = a.qd[c * a.ns + bg];
-      dq[c] = a.dq[c * a.ns + bg];
+      dq[c] = diag ? a.h * a.qd_out[c * a.ns + bg] : a.dq[c * a.ns + bg];
+    }
+    if (diag) {
+      double qn[12], An[9];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) qn[c] = a.q_out[c * a.ns + bg];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) An[3 * i + c] = qn[3 * c + i];
+      if (has_a) {
+        mat3_vec(An, pa, cna);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { cna[i] *= sa; tna[i] = sa * qn[9 + i]; }
+      }
+      if (has_b) {
+        mat3_vec(An, pb, cnb);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { cnb[i] *= sb; tnb[i] = sb * qn[9 + i]; }
+      }
     }
     const int s = a.shp[bg];
     const double *T_h = a.hinv + (int64_t)HINV_STRIDE * s;
@@ -1147,8 +1177,9 @@ __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
       rw[9 + i] -= wa + wb;
     }
     if (own) {
+      if (!diag)
 #pragma unroll
-      for (int c = 0; c < 12; ++c) a.rp[c * a.ns + bg] = rw[c];
+        for (int c = 0; c < 12; ++c) a.rp[c * a.ns + bg] = rw[c];
       double rl[12], y[12];
 #pragma unroll
       for (int c = 0; c < 4; ++c) mat3t_vec(R, rw + 3 * c, rl + 3 * c);
@@ -1190,9 +1221,9 @@ __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
   } else {
     // world end: only the constant point enters C
     if (has_a)
-      for (int i = 0; i < 3; ++i) ca[i] = sa * pa[i];
+      for (int i = 0; i < 3; ++i) cna[i] = ca[i] = sa * pa[i];
     if (has_b)
-      for (int i = 0; i < 3; ++i) cb[i] = sb * pb[i];
+      for (int i = 0; i < 3; ++i) cnb[i] = cb[i] = sb * pb[i];
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -1200,6 +1231,8 @@ __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
     lds[(L_CB + i) * NT + t] = cb[i];
     lds[(L_TB + i) * NT + t] = tb[i];
     lds[(L_GB + i) * NT + t] = gb[i];
+    lds[(L_CN + i) * NT + t] = cnb[i];
+    lds[(L_TN + i) * NT + t] = tnb[i];
   }
   __syncthreads();
   const int li = t - 1;
@@ -1207,51 +1240,76 @@ __global__ __launch_bounds__(NT) void chain_resid_kernel(ChainArgs a) {
     const int tp = t - 1;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const double C = (lds[(L_TB + i) * NT + tp] + ta[i]) + (lds[(L_CB + i) * NT + tp] + ca[i]);
+      const double tt = lds[(L_TB + i) * NT + tp] + ta[i];
+      const double cbl = lds[(L_CB + i) * NT + tp], gbl = lds[(L_GB + i) * NT + tp];
+      const double C = tt + (cbl + ca[i]);
       const double rk = va[i] + lds[(L_VB + i) * NT + tp] + C;
-      const double rdv = -(C + (ga[i] + lds[(L_GB + i) * NT + tp]));
-      a.rd[i * a.nrs + gra] = rdv;
+      const double gdq = ga[i] + gbl;
+      const double rdv = -(C + gdq);
+      if (!diag) a.rd[i * a.nrs + gra] = rdv;
       sr += rk * rk;
       sd += rdv * rdv;
+      // the summands r_d is formed from (the translation difference, both
+      // anchor offsets, both ends' increments): its rounding floor
+      se += tt * tt + cbl * cbl + ca[i] * ca[i] + ga[i] * ga[i] + gbl * gbl;
+      if (diag) {
+        const double Cn = (lds[(L_TN + i) * NT + tp] + tna[i]) + (lds[(L_CN + i) * NT + tp] + cna[i]);
+        cmax = fmax(cmax, fabs(Cn));
+      }
     }
   }
   lds[(L_RED + 0) * NT + t] = sp;
   lds[(L_RED + 1) * NT + t] = sf;
   lds[(L_RED + 2) * NT + t] = sr;
   lds[(L_RED + 3) * NT + t] = sd;
+  lds[L_CM * NT + t] = cmax;
+  lds[L_SE * NT + t] = se;
   __syncthreads();
   for (int w = NT / 2; w > 0; w /= 2) {
-    if (t < w)
+    if (t < w) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) lds[(L_RED + k) * NT + t] += lds[(L_RED + k) * NT + t + w];
+      lds[L_SE * NT + t] += lds[L_SE * NT + t + w];
+      lds[L_CM * NT + t] = fmax(lds[L_CM * NT + t], lds[L_CM * NT + t + w]);
+    }
     __syncthreads();
   }
-  if (t < 4) a.part[4 * (int64_t)ti + t] = lds[(L_RED + t) * NT];
+  if (diag) {
+    double *o = a.part + DIAG_PART * (int64_t)ti;
+    if (t < 4) o[t] = lds[(L_RED + t) * NT];
+    if (t == 4) o[4] = lds[L_CM * NT];
+    if (t == 5) o[5] = 0.0;
+  } else if (t < 4) {
+    a.part[IR_PART * (int64_t)ti + t] = lds[(L_RED + t) * NT];
+  } else if (t == 4) {
+    a.part[IR_PART * (int64_t)ti + 4] = lds[L_SE * NT];
+  }
 }
 
 // Sums the tile partials in a fixed order and decides: converged (KKT
 // residual <= tol: later corrections and checks of this step do nothing),
-// stalled at the rounding floor (likewise), another correction sweep, or, at
-// the final check, NOT_CONVERGED.
+// stalled at the rounding floor within IR_STALL_FACTOR tol (likewise),
+// stalled above it or, at the final check, still above tol (NOT_CONVERGED),
+// or another correction sweep.
 __global__ __launch_bounds__(256) void chain_ir_check_kernel(const double *part, int nblk, double tol,
                                                              int final_check, double *ir,
                                                              uint32_t *status) {
-  __shared__ double red[4 * 256];
+  __shared__ double red[IR_PART * 256];
   if (skip_step(status, 0)) return;
   if (ir[0] != 0.0) return;
   const int t = threadIdx.x;
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  double s[IR_PART] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int b = t; b < nblk; b += 256)
-    for (int k = 0; k < 4; ++k) s[k] += part[4 * (int64_t)b + k];
-  for (int k = 0; k < 4; ++k) red[k * 256 + t] = s[k];
+    for (int k = 0; k < IR_PART; ++k) s[k] += part[IR_PART * (int64_t)b + k];
+  for (int k = 0; k < IR_PART; ++k) red[k * 256 + t] = s[k];
   __syncthreads();
   for (int w = 128; w > 0; w /= 2) {
     if (t < w)
-      for (int k = 0; k < 4; ++k) red[k * 256 + t] += red[k * 256 + t + w];
+      for (int k = 0; k < IR_PART; ++k) red[k * 256 + t] += red[k * 256 + t + w];
     __syncthreads();
   }
   if (t == 0) {
-    const double np = red[0], nf = red[256], nr = red[512], nd = red[768];
+    const double np = red[0], nf = red[256], nr = red[512], nd = red[768], ne = red[1024];
     const double rp = nf > 0.0 ? sqrt(np / nf) : sqrt(np);
     const double rdd = nr > 0.0 ? sqrt(nd / nr) : sqrt(nd);
     const double kkt = rp > rdd ? rp : rdd;
@@ -1261,8 +1319,21 @@ __global__ __launch_bounds__(256) void chain_ir_check_kernel(const double *part,
     if (!isfinite(rp) || !isfinite(rdd)) raise_flag(status, FLAG_NONFINITE, 0);
     else if (kkt <= tol) ir[0] = 1.0;
     // a sweep that no longer halves the residual has reached the FP64
-    // rounding floor of the residual itself: stop there
-    else if (ir[1] > 0.0 && kkt > 0.5 * ir[5]) ir[0] = 2.0;
+    // rounding floor of the residual itself: stop there, accepted when
+    // within IR_STALL_FACTOR of the target, otherwise not converged
+    else if (ir[1] > 0.0 && kkt > 0.5 * ir[5]) {
+      // at the floor: within the factor of the target, or the primal part
+      // is and the dual residual is at the rounding level of its own terms
+      // (where the dual right-hand side all but vanishes, as for a freely
+      // falling chain, rho_d is O(1) for every FP64 solution)
+      const bool dual_at_rounding = sqrt(nd) <= IR_ROUND_FACTOR * DBL_EPSILON * sqrt(ne);
+      if (kkt <= IR_STALL_FACTOR * tol || (rp <= IR_STALL_FACTOR * tol && dual_at_rounding)) {
+        ir[0] = 2.0;
+      } else {
+        ir[0] = 3.0;
+        raise_flag(status, FLAG_NOTCONV, 0);
+      }
+    }
     else if (final_check) raise_flag(status, FLAG_NOTCONV, 0);
     else ir[1] += 1.0;  // a correction sweep follows
     ir[5] = kkt;

@@ -1192,7 +1192,8 @@ __global__ __launch_bounds__(256) void gapply_kernel(int b0, int b1, const int32
                               const double *gl, const double *glam, const double *Rg,
                               const double *ug, int64_t ns, const int32_t *shp, const double *hinv,
                               const double *q_cur, double *q_out, double *qd_out, double h,
-                              int accumulate, uint32_t *status, const GJoint *J, int step) {
+                              int accumulate, uint32_t *status, const GJoint *J, int step,
+                              double *dq_save) {
   int64_t b = (int64_t)b0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= b1 || skip_step(status, step)) return;
   double g12[12];
@@ -1219,17 +1220,26 @@ __global__ __launch_bounds__(256) void gapply_kernel(int b0, int b1, const int32
       const int64_t o = (int64_t)(3 * c + i) * ns + b;
       q_out[o] = q_cur[o] + dq[i];
       qd_out[o] = (accumulate ? qd_out[o] : 0.0) + dq[i] * ih;
+      if (dq_save) dq_save[o] = dq[i];
       if (!isfinite(dq[i])) raise_flag(status, FLAG_NONFINITE, step);
     }
   }
 }
 
 // ------------------------------------------------------------ state copies
-// solver-order SoA -> input-order AoS (n x 12) for dynamic bodies
-__global__ void gather_state_kernel(int nd, const int32_t *sol2in, const double *q, const double *qd,
-                                    int64_t ns, double *qo, double *qdo) {
+// solver-order SoA -> input-order AoS (n x 12) for dynamic bodies.  The
+// state is buffer `cur` of (q0, qd0) / (q1, qd1), unless `status` is given
+// and records a failed step: then it is the buffer that step read, index
+// (cur0 + failing step) mod 2, cur0 the buffer current when the status word
+// was cleared (steps after a failed one do nothing).
+__global__ void gather_state_kernel(int nd, const int32_t *sol2in, const double *q0, const double *qd0,
+                                    const double *q1, const double *qd1, int cur, int cur0,
+                                    const uint32_t *status, int64_t ns, double *qo, double *qdo) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nd) return;
+  int idx = cur;
+  if (status && status[0] != 0u) idx = (int)((cur0 + status[1]) & 1u);
+  const double *q = idx ? q1 : q0, *qd = idx ? qd1 : qd0;
   const int64_t o = sol2in[i];
   for (int c = 0; c < 12; ++c) {
     if (qo) qo[12 * o + c] = q[c * ns + i];
@@ -1373,17 +1383,18 @@ void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, c
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
                    double *qd_out, double h, int acc, uint32_t *status, const GJoint *J,
-                   int step, hipStream_t s) {
+                   int step, double *dq_save, hipStream_t s) {
   if (b1 > b0)
     hipLaunchKernelGGL(gapply_kernel, dim3((b1 - b0 + 255) / 256), dim3(256), 0, s, b0, b1, inc_off,
                        inc, gl, glam, Rg, ug, ns, shp, hinv, q_cur, q_out, qd_out, h, acc, status, J,
-                       step);
+                       step, dq_save);
 }
-void launch_gather_state(int nd, const int32_t *sol2in, const double *q, const double *qd, int64_t ns,
-                         double *qo, double *qdo, hipStream_t s) {
+void launch_gather_state(int nd, const int32_t *sol2in, const double *const *q, const double *const *qd,
+                         int cur, int cur0, const uint32_t *status, int64_t ns, double *qo, double *qdo,
+                         hipStream_t s) {
   if (nd > 0)
-    hipLaunchKernelGGL(gather_state_kernel, dim3((nd + 255) / 256), dim3(256), 0, s, nd, sol2in, q, qd,
-                       ns, qo, qdo);
+    hipLaunchKernelGGL(gather_state_kernel, dim3((nd + 255) / 256), dim3(256), 0, s, nd, sol2in, q[0],
+                       qd[0], q[1], qd[1], cur, cur0, status, ns, qo, qdo);
 }
 
 }  // namespace mabd

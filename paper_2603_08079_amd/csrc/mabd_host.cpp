@@ -51,9 +51,29 @@ void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, c
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
                    double *qd_out, double h, int acc, uint32_t *status, const GJoint *J,
-                   int step, hipStream_t s);
-void launch_gather_state(int nd, const int32_t *sol2in, const double *q, const double *qd, int64_t ns,
-                         double *qo, double *qdo, hipStream_t s);
+                   int step, double *dq_save, hipStream_t s);
+void launch_gather_state(int nd, const int32_t *sol2in, const double *const *q, const double *const *qd,
+                         int cur, int cur0, const uint32_t *status, int64_t ns, double *qo, double *qdo,
+                         hipStream_t s);
+int diag_body_blocks(int nb);
+void launch_gdiag_body(int b0, int b1, const double *q, const double *qn, const double *qdn,
+                       const double *dqv, double dq_scale, int64_t ns, const int32_t *shp,
+                       const double *hinv, const double *shape, const double *g, double h,
+                       const double *Rg, const int32_t *inc_off, const int32_t *inc, const GJoint *J,
+                       const double *gl, const double *glam, const double *wr, const uint32_t *status,
+                       double *part, hipStream_t s);
+void launch_gdiag_joint(int m, const GJoint *J, const double *gl, const double *Rg, const double *ug,
+                        const double *dqv, double dq_scale, const double *q_new, int64_t ns,
+                        const uint32_t *status, double *part, hipStream_t s);
+void launch_diag_reduce(const double *part, int nblk, double *out, const uint32_t *status,
+                        hipStream_t s);
+void launch_twists(int nd, const int32_t *sol2in, const double *q, const double *qd, int64_t ns,
+                   double *V, hipStream_t s);
+void launch_joint_wrenches(const ChainDesc *chains, int nchains, int nchain_bodies, const double *pl,
+                           const double *pr, const uint8_t *flag, int64_t nrs, const double *clam,
+                           int b0, int b1, const double *Rg, const int32_t *inc_off, const int32_t *inc,
+                           const GJoint *J, const double *gl, const double *glam, const double *q,
+                           int64_t ns, const int32_t *sol2in, double *W, hipStream_t s);
 void launch_scatter_state(int nd, const int32_t *sol2in, const double *qi, const double *qdi,
                           double *q, double *qd, int64_t ns, hipStream_t s);
 void launch_write_pinned(int np, const int32_t *idx, const double *q0, double *qo, double *qdo,
@@ -240,6 +260,20 @@ struct mabd_ctx {
   double *d_pin_q0 = nullptr, *d_tmp = nullptr;
   uint32_t *d_status = nullptr;
   uint32_t *h_status = nullptr;
+  // status of issued steps not read yet (mabd_step is asynchronous): the
+  // state buffer current when the status word was cleared, the steps issued
+  // since then, and an event recorded after the status copies
+  bool pending = false;
+  int pend_cur0 = 0;
+  int64_t pend_steps = 0;
+  hipEvent_t pend_ev = nullptr;
+  // step diagnostics: DIAG_PART partial records (diag_nblk of them), the
+  // reduced values {rho_p, rho_d, kkt, c_ball, c_hinge} of the step and of
+  // each Newton iteration, their pinned host copy, and the iterate and
+  // increment of the running Newton iteration
+  double *d_dpart = nullptr, *d_diag = nullptr, *h_diag = nullptr;
+  double *d_qit = nullptr, *d_dqit = nullptr;
+  bool resid_ok = false;  // the buffers still describe the last completed step
   hipStream_t stream = nullptr;
   bool own_stream = false;
   double h_last = -1.0;
@@ -256,6 +290,18 @@ mabd_status fail(mabd_ctx *c, mabd_status st, const std::string &msg) {
   if (c) c->err = msg;
   else g_create_error = msg;
   return st;
+}
+
+mabd_status resolve(mabd_ctx *c);
+
+// reduced diagnostics per context: the step's five values, then five per
+// Newton iteration (at most MABD_NEWTON_DIAG iterations are recorded)
+constexpr int DIAG_VALUES = 5 * (1 + MABD_NEWTON_DIAG);
+
+// partial records of one residual evaluation: chain tiles, then blocks of
+// generic bodies, then blocks of generic joints
+int64_t diag_nblk(const mabd_ctx *c) {
+  return (int64_t)c->tiles.size() + diag_body_blocks(c->gb1 - c->gb0) + diag_body_blocks((int)c->gj.size());
 }
 
 template <typename T>
@@ -448,6 +494,8 @@ void mabd_destroy(mabd_ctx *c) {
   if (c->h_ir) (void)hipHostFree(c->h_ir);
   if (c->h_pb_si) (void)hipHostFree(c->h_pb_si);
   if (c->h_gsc) (void)hipHostFree(c->h_gsc);
+  if (c->h_diag) (void)hipHostFree(c->h_diag);
+  if (c->pend_ev) (void)hipEventDestroy(c->pend_ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1102,7 +1150,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     if (e == hipSuccess) chk(dalloc(c, &c->d_dq, (size_t)12 * ns));
     if (e == hipSuccess) chk(dalloc(c, &c->d_rp, (size_t)12 * ns));
     if (e == hipSuccess) chk(dalloc(c, &c->d_rd, (size_t)3 * nrs));
-    if (e == hipSuccess) chk(dalloc(c, &c->d_part, (size_t)4 * c->tiles.size()));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_part, (size_t)IR_PART * c->tiles.size()));
     if (e == hipSuccess) chk(dalloc(c, &c->d_ir, 8));
     if (e == hipSuccess) chk(hipMemset(c->d_ir, 0, 8 * sizeof(double)));
     if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_ir, 8 * sizeof(double)));
@@ -1218,6 +1266,17 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess && mg) chk(hipMemset(c->d_glam, 0, 5 * mg * sizeof(double)));
   if (e == hipSuccess) chk(dalloc(c, &c->d_status, 4));
   if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_status, 4 * sizeof(uint32_t)));
+  if (e == hipSuccess) chk(hipEventCreateWithFlags(&c->pend_ev, hipEventDisableTiming));
+  if (e == hipSuccess) chk(dalloc(c, &c->d_diag, DIAG_VALUES));
+  if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_diag, DIAG_VALUES * sizeof(double)));
+  if (opt.diagnostics & 1) {
+    // sized here, while the tiles are the smallest (most numerous) form
+    if (e == hipSuccess) chk(dalloc(c, &c->d_dpart, (size_t)DIAG_PART * diag_nblk(c)));
+    if (opt.newton_iters > 1 && c->gb1 > c->gb0) {
+      if (e == hipSuccess) chk(dalloc(c, &c->d_qit, (size_t)12 * ns));
+      if (e == hipSuccess) chk(dalloc(c, &c->d_dqit, (size_t)12 * ns));
+    }
+  }
   // after every buffer is sized for the smallest tiles
   // "64p" (packed), 64, 128 or 256: fixed by the environment, no autotuning
   if (const char *tt = std::getenv("MABD_CHAIN_TILE_THREADS")) {
@@ -1379,6 +1438,9 @@ hipError_t gnn_prepare(mabd_ctx *c, double h, PcgBallArgs &pb) {
 
 mabd_status gnn_check(mabd_ctx *c, bool need_ready) {
   if (!c) return MABD_ERR_INVALID_ARG;
+  const mabd_status rs = resolve(c);  // these calls clear the status word
+  if (rs != MABD_OK) return rs;
+  c->resid_ok = false;  // and overwrite the step's rows and local solves
   if (!c->pcg_ball || c->pb_nj == 0)
     return fail(c, MABD_ERR_INVALID_ARG, "the learned warm start needs a ball-joint network component");
   if (need_ready && !c->gnn_ready)
@@ -1454,6 +1516,73 @@ hipError_t run_pcg_ball(mabd_ctx *c, const PcgBallArgs &pb, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Arguments of the chain kernels for a step reading state buffer a and
+// writing buffer b.
+ChainArgs chain_args(mabd_ctx *c, double h, int a, int b) {
+  const double *g = c->opt.gravity;
+  ChainArgs ca{};
+  ca.chains = c->d_chains;
+  ca.tiles = c->d_tiles;
+  ca.ntiles = (int)c->tiles.size();
+  ca.q = c->d_q[a];
+  ca.qd = c->d_qd[a];
+  ca.q_out = c->d_q[b];
+  ca.qd_out = c->d_qd[b];
+  ca.ns = c->ns;
+  ca.shp = c->d_shp;
+  ca.hinv = c->d_hinv;
+  ca.shape = c->d_shape;
+  ca.pl = c->d_pl;
+  ca.pr = c->d_pr;
+  ca.flag = c->d_flag;
+  ca.nrs = std::max(c->nchain_rows, 1);
+  ca.g[0] = g[0]; ca.g[1] = g[1]; ca.g[2] = g[2];
+  ca.h = h;
+  ca.tilerec = c->d_tilerec;
+  ca.xg = c->d_xg;
+  ca.lam = c->d_clam;
+  ca.status = c->d_status;
+  ca.step = 0;
+  ca.dq = c->d_dq;
+  ca.rp = c->d_rp;
+  ca.rd = c->d_rd;
+  ca.part = c->d_part;
+  ca.ir = c->d_ir;
+  ca.wr = c->wr_on ? c->d_wr : nullptr;
+  ca.psv = c->d_psv;
+  ca.pcf = c->d_pcf;
+  ca.diag = 0;
+  return ca;
+}
+
+// Residual kernels of one finished Newton iteration into `part` (diag_nblk
+// records) and their reduction into out[0..4] (diag_reduce_kernel).  The
+// step read state buffer a and wrote buffer b.  Chains (fused path, one
+// iteration) recompute their forces from buffer a and take their increment
+// as h times the new velocity; generic bodies take the iterate q_it and the
+// increment dq_scale * dqv.
+void issue_residual(mabd_ctx *c, double h, int a, int b, const double *q_it, const double *dqv,
+                    double dq_scale, double *part, double *out) {
+  hipStream_t s = c->stream;
+  int64_t off = 0;
+  if (!c->chains.empty()) {
+    ChainArgs ca = chain_args(c, h, a, b);
+    ca.diag = 1;
+    ca.part = part;
+    launch_chain_resid(ca, (int)c->tiles.size(), c->tile_threads, s);
+  }
+  off += (int64_t)c->tiles.size();
+  launch_gdiag_body(c->gb0, c->gb1, q_it, c->d_q[a], c->d_qd[a], dqv, dq_scale, c->ns, c->d_shp,
+                    c->d_hinv, c->d_shape, c->opt.gravity, h, c->d_Rg, c->d_inc_off, c->d_inc, c->d_gj,
+                    c->d_gl, c->d_glam, c->wr_on ? c->d_wr : nullptr, c->d_status,
+                    part + DIAG_PART * off, s);
+  off += diag_body_blocks(c->gb1 - c->gb0);
+  launch_gdiag_joint((int)c->gj.size(), c->d_gj, c->d_gl, c->d_Rg, c->d_ug, dqv, dq_scale, c->d_q[b],
+                     c->ns, c->d_status, part + DIAG_PART * off, s);
+  off += diag_body_blocks((int)c->gj.size());
+  launch_diag_reduce(part, (int)off, out, c->d_status, s);
+}
+
 // Launch sequence of one step reading state buffer a and writing buffer b.
 // The step index lives in device memory (begin_step), so this sequence can
 // be captured once and replayed.
@@ -1461,39 +1590,10 @@ template <typename Timer>
 hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
   hipStream_t s = c->stream;
   const double *g = c->opt.gravity;
+  const bool diag = (c->opt.diagnostics & 1) != 0 && c->d_dpart;
   launch_begin_step(c->d_status, s);
-    if (!c->chains.empty()) {
-    ChainArgs ca{};
-    ca.chains = c->d_chains;
-    ca.tiles = c->d_tiles;
-    ca.ntiles = (int)c->tiles.size();
-    ca.q = c->d_q[a];
-    ca.qd = c->d_qd[a];
-    ca.q_out = c->d_q[b];
-    ca.qd_out = c->d_qd[b];
-    ca.ns = c->ns;
-    ca.shp = c->d_shp;
-    ca.hinv = c->d_hinv;
-    ca.shape = c->d_shape;
-    ca.pl = c->d_pl;
-    ca.pr = c->d_pr;
-    ca.flag = c->d_flag;
-    ca.nrs = std::max(c->nchain_rows, 1);
-    ca.g[0] = g[0]; ca.g[1] = g[1]; ca.g[2] = g[2];
-    ca.h = h;
-    ca.tilerec = c->d_tilerec;
-    ca.xg = c->d_xg;
-    ca.lam = c->d_clam;
-    ca.status = c->d_status;
-    ca.step = 0;
-    ca.dq = c->d_dq;
-    ca.rp = c->d_rp;
-    ca.rd = c->d_rd;
-    ca.part = c->d_part;
-    ca.ir = c->d_ir;
-    ca.wr = c->wr_on ? c->d_wr : nullptr;
-    ca.psv = c->d_psv;
-    ca.pcf = c->d_pcf;
+  if (!c->chains.empty()) {
+    ChainArgs ca = chain_args(c, h, a, b);
     const int ntl = (int)c->tiles.size(), tt = c->tile_threads;
     const bool pk = c->tile_pack;
     // one chain solve: tile reduction, interface solve, tile back-substitution
@@ -1611,13 +1711,37 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
         }
         if (pe != hipSuccess) return pe;
       }
+      // diagnostics with several Newton iterations: the residual of every
+      // iteration, from its own iterate and increment (the update below
+      // overwrites the iterate in place, so it is saved first)
+      const bool dg_it = diag && c->opt.newton_iters > 1;
+      if (dg_it && it > 0) {
+        hipError_t ce = hipMemcpyAsync(c->d_qit, c->d_q[b], (size_t)12 * c->ns * sizeof(double),
+                                       hipMemcpyDeviceToDevice, s);
+        if (ce != hipSuccess) return ce;
+      }
       tm.run(6, [&] {
         launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_glam, c->d_Rg, c->d_ug,
                       c->ns, c->d_shp, c->d_hinv, qcur, c->d_q[b], c->d_qd[b], h, it > 0 ? 1 : 0,
-                      c->d_status, c->d_gj, 0, s);
+                      c->d_status, c->d_gj, 0, dg_it ? c->d_dqit : nullptr, s);
       });
+      if (dg_it) {
+        const int slot = std::min(it, MABD_NEWTON_DIAG - 1);
+        issue_residual(c, h, a, b, it > 0 ? c->d_qit : c->d_q[a], c->d_dqit, 1.0, c->d_dpart,
+                       c->d_diag + 5 * (1 + slot));
+        if (it == c->opt.newton_iters - 1) {
+          hipError_t ce = hipMemcpyAsync(c->d_diag, c->d_diag + 5 * (1 + slot), 5 * sizeof(double),
+                                         hipMemcpyDeviceToDevice, s);
+          if (ce != hipSuccess) return ce;
+        }
+      }
     }
   }
+  // diagnostics with one Newton iteration: the residual of the whole step
+  // (chains and generic components), its increment being h times the new
+  // velocity
+  if (diag && c->opt.newton_iters == 1)
+    issue_residual(c, h, a, b, c->d_q[a], c->d_qd[b], h, c->d_dpart, c->d_diag);
   return hipGetLastError();
 }
 
@@ -1694,6 +1818,91 @@ void capture_graphs(mabd_ctx *c, double h) {
 }
 }  // namespace
 
+namespace {
+// Reads the status of the steps issued since the status word was cleared
+// (waiting for them) and settles the context: on a failure the state goes
+// back to the buffer the failing step read (the steps after it did nothing),
+// the step count stops before it and warm starts are withdrawn.  Returns the
+// status of those steps; MABD_OK when nothing was pending.
+mabd_status resolve(mabd_ctx *c) {
+  if (!c->pending) return MABD_OK;
+  const hipError_t e = hipEventSynchronize(c->pend_ev);
+  c->pending = false;
+  if (e != hipSuccess) {
+    c->resid_ok = false;
+    c->warm_valid = false;
+    return fail(c, MABD_ERR_DEVICE, std::string("step: ") + hipGetErrorString(e));
+  }
+  if (c->ngraph > 0) {
+    int32_t its;
+    std::memcpy(&its, c->h_pcg + 1, sizeof its);
+    c->stats.pcg_iters = its;
+    c->stats.rho_d = c->h_pcg[0];
+  }
+  if (c->d_ir) {
+    // FP64 KKT residual of the chains reached by the last step (form 1)
+    c->stats.ir_sweeps = (int32_t)c->h_ir[1];
+    c->stats.ir_stalled = c->h_ir[0] == 2.0 ? 1 : 0;
+    c->stats.rho_p = c->h_ir[2];
+    c->stats.rho_d = c->h_ir[3];
+    c->stats.kkt = c->h_ir[4];
+  }
+  for (int i = 0; i < MABD_NEWTON_DIAG; ++i) c->stats.kkt_newton[i] = -1.0;
+  if ((c->opt.diagnostics & 1) && c->d_dpart) {
+    // the FP64 KKT residual of the last step evaluated on the device
+    const double *d = c->h_diag;
+    c->stats.rho_p = d[0];
+    c->stats.rho_d = d[1];
+    c->stats.kkt = d[2];
+    c->stats.c_ball = d[3];
+    c->stats.c_hinge = d[4];
+    if (c->opt.newton_iters == 1) {
+      c->stats.kkt_newton[0] = d[2];
+    } else {
+      for (int i = 0; i < std::min(c->opt.newton_iters, MABD_NEWTON_DIAG); ++i)
+        c->stats.kkt_newton[i] = d[5 * (1 + i) + 2];
+    }
+  }
+  const uint32_t bits = c->h_status[0];
+  if (bits) {
+    const int f = (int)c->h_status[1];
+    c->cur = (c->pend_cur0 + f) % 2;
+    c->stats.steps_done += f;
+    c->resid_ok = false;
+    c->warm_valid = false;  // the failed step's multipliers are no start value
+    c->stats.last_status = (bits & FLAG_GUARD)       ? MABD_ERR_DEVICE
+                           : (bits & FLAG_NONFINITE) ? MABD_ERR_NONFINITE
+                           : (bits & FLAG_SINGULAR)  ? MABD_ERR_SINGULAR
+                                                     : MABD_ERR_NOT_CONVERGED;
+    return fail(c, (mabd_status)c->stats.last_status,
+                (bits & FLAG_GUARD)       ? "internal error: a tree operation exceeded its kernel's clique size"
+                : (bits & FLAG_NONFINITE) ? "non-finite value or det A <= 0 during the step"
+                : (bits & FLAG_SINGULAR)  ? "dual pivot block not positive definite"
+                : c->d_ir                 ? "KKT residual above kkt_tol (PCG iteration cap, or "
+                                            "precision-1 refinement out of sweeps or stalled)"
+                                          : "PCG reached max_iters above kkt_tol");
+  }
+  c->stats.steps_done += c->pend_steps;
+  c->stats.last_status = MABD_OK;
+  c->warm_valid = true;
+  return MABD_OK;
+}
+
+// The FP64 KKT residual of the last completed step (one Newton iteration),
+// evaluated with the partial records in `part` (diag_nblk(c) of them),
+// copied to out[0..4]; synchronises the stream.
+mabd_status residual_into(mabd_ctx *c, double *part, double *out) {
+  hipStream_t s = c->stream;
+  const int a = 1 - c->cur, b = c->cur;
+  issue_residual(c, c->h_last, a, b, c->d_q[a], c->d_qd[b], c->h_last, part, c->d_diag);
+  hipError_t e = hipMemcpyAsync(c->h_diag, c->d_diag, 5 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("residual: ") + hipGetErrorString(e));
+  for (int i = 0; i < 5; ++i) out[i] = c->h_diag[i];
+  return MABD_OK;
+}
+}  // namespace
+
 extern "C" {
 
 mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
@@ -1701,20 +1910,31 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
   if (!(h > 0.0) || !std::isfinite(h)) return fail(c, MABD_ERR_INVALID_ARG, "h must be > 0");
   if (nsteps < 1) return fail(c, MABD_ERR_INVALID_ARG, "n must be >= 1");
   hipStream_t s = c->stream;
+  // a failure of earlier steps whose status has already arrived is reported
+  // now, before any new step is issued (no wait)
+  if (c->pending && hipEventQuery(c->pend_ev) == hipSuccess) {
+    const mabd_status st = resolve(c);
+    if (st != MABD_OK) return st;
+  }
   if (h != c->h_last) {
     launch_prefactor(c->d_shape, c->nshape, h, c->d_hinv, s);
     c->h_last = h;
     drop_graphs(c);
   }
   if (c->opt.autotune && !c->tuned && c->nchain_rows >= 20000) {
+    const mabd_status st = resolve(c);  // tuning clears the status word
+    if (st != MABD_OK) return st;
     hipError_t te = autotune(c, h);
     if (te != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(te));
     c->tuned = true;
     drop_graphs(c);
   }
-  const int start_cur = c->cur;
   PhaseTimer tm(c);
-  launch_reset_status(c->d_status, s);
+  if (!c->pending) {
+    launch_reset_status(c->d_status, s);
+    c->pend_cur0 = c->cur;
+    c->pend_steps = 0;
+  }
   bool graph = c->opt.use_graph && c->ngraph == 0 && !tm.on && !c->graph_failed;
   if (graph && !c->gexec[0]) capture_graphs(c, h);
   graph = graph && c->gexec[0] && c->gexec[1];
@@ -1729,50 +1949,30 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
     if (le != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("launch: ") + hipGetErrorString(le));
     c->cur = b;
   }
+  c->pend_steps += nsteps;
+  c->resid_ok = true;  // withdrawn if the status read finds a failure
+  // status words and results are copied now and read when a later call
+  // needs them (resolve)
   hipError_t e = hipMemcpyAsync(c->h_status, c->d_status, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess && c->d_ir)
-    e = hipMemcpyAsync(c->h_ir, c->d_ir, 5 * sizeof(double), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(c->h_ir, c->d_ir, 6 * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess && c->ngraph > 0) {
     e = hipMemcpyAsync(c->h_pcg, c->d_pcg_res, sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->h_pcg + 1, c->d_pcg_it, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && (c->opt.diagnostics & 1) && c->d_dpart)
+    e = hipMemcpyAsync(c->h_diag, c->d_diag, DIAG_VALUES * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipEventRecord(c->pend_ev, s);
   if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("step: ") + hipGetErrorString(e));
-  tm.collect();
-  if (c->ngraph > 0) {
-    int32_t its;
-    std::memcpy(&its, c->h_pcg + 1, sizeof its);
-    c->stats.pcg_iters = its;
-    c->stats.rho_d = c->h_pcg[0];
+  c->pending = true;
+  // networks are solved under host control and kernel timing needs the
+  // events: those steps have synchronised already, so read the status now
+  if (c->ngraph > 0 || tm.on) {
+    const mabd_status st = resolve(c);
+    tm.collect();
+    return st;
   }
-  if (c->d_ir) {
-    // FP64 KKT residual of the chains reached by the last step (form 1)
-    c->stats.ir_sweeps = (int32_t)c->h_ir[1];
-    c->stats.rho_p = c->h_ir[2];
-    c->stats.rho_d = c->h_ir[3];
-    c->stats.kkt = c->h_ir[4];
-  }
-  const uint32_t bits = c->h_status[0];
-  if (bits) {
-    // steps after the failing one did nothing: the state before it is in the
-    // buffer that step read from
-    const int f = (int)c->h_status[1];
-    c->cur = (start_cur + f) % 2;
-    c->stats.steps_done += f;
-    c->stats.last_status = (bits & FLAG_GUARD)       ? MABD_ERR_DEVICE
-                           : (bits & FLAG_NONFINITE) ? MABD_ERR_NONFINITE
-                           : (bits & FLAG_SINGULAR)  ? MABD_ERR_SINGULAR
-                                                     : MABD_ERR_NOT_CONVERGED;
-    return fail(c, (mabd_status)c->stats.last_status,
-                (bits & FLAG_GUARD)       ? "internal error: a tree operation exceeded its kernel's clique size"
-                : (bits & FLAG_NONFINITE) ? "non-finite value or det A <= 0 during the step"
-                : (bits & FLAG_SINGULAR)  ? "dual pivot block not positive definite"
-                                          : "PCG reached max_iters above kkt_tol");
-  }
-  c->stats.steps_done += nsteps;
-  c->stats.last_status = MABD_OK;
-  c->warm_valid = true;
   return MABD_OK;
 }
 
@@ -1780,8 +1980,9 @@ mabd_status mabd_state_device(const mabd_ctx *cc, void *q_dev, void *qd_dev) {
   mabd_ctx *c = const_cast<mabd_ctx *>(cc);
   if (!c) return MABD_ERR_INVALID_ARG;
   hipStream_t s = c->stream;
-  launch_gather_state(c->nd, c->d_sol2in, c->d_q[c->cur], c->d_qd[c->cur], c->ns, (double *)q_dev,
-                      (double *)qd_dev, s);
+  // with steps in flight the kernel itself picks the last good buffer
+  launch_gather_state(c->nd, c->d_sol2in, c->d_q, c->d_qd, c->cur, c->pend_cur0,
+                      c->pending ? c->d_status : nullptr, c->ns, (double *)q_dev, (double *)qd_dev, s);
   launch_write_pinned((int)c->pin_idx.size(), c->d_pin_idx, c->d_pin_q0, (double *)q_dev,
                       (double *)qd_dev, s);
   hipError_t e = hipGetLastError();
@@ -1801,7 +2002,9 @@ mabd_status mabd_state(const mabd_ctx *cc, double *q, double *qd) {
   if (e == hipSuccess && qd && n12) e = hipMemcpyAsync(qd, tqd, n12 * 8, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
-  return MABD_OK;
+  // the state copied is the last completed step's; a failure of the steps
+  // in flight is reported here
+  return resolve(c);
 }
 
 mabd_status mabd_set_state(mabd_ctx *c, const double *q, const double *qd) {
@@ -1815,6 +2018,11 @@ mabd_status mabd_set_state(mabd_ctx *c, const double *q, const double *qd) {
                  A[2] * (A[3] * A[7] - A[4] * A[6]);
     if (!(det > 0)) return fail(c, MABD_ERR_INVALID_ARG, "det A <= 0 in the new state");
   }
+  // settle steps in flight first (a failure among them stays in the stats);
+  // the new state replaces whatever they left
+  (void)resolve(c);
+  c->warm_valid = false;  // the multipliers belong to another state
+  c->resid_ok = false;
   double *tq = c->d_tmp, *tqd = c->d_tmp + n12;
   hipError_t e = hipSuccess;
   if (n12) e = hipMemcpyAsync(tq, q, n12 * 8, hipMemcpyHostToDevice, c->stream);
@@ -1829,8 +2037,10 @@ mabd_status mabd_set_state(mabd_ctx *c, const double *q, const double *qd) {
 
 mabd_status mabd_set_wrenches(mabd_ctx *c, const double *w) {
   if (!c) return MABD_ERR_INVALID_ARG;
+  (void)resolve(c);  // a failure among steps in flight stays in the stats
   if (!w) {
     if (c->wr_on) drop_graphs(c);  // the step launches change
+    if (c->wr_on) c->resid_ok = false;
     c->wr_on = false;
     return MABD_OK;
   }
@@ -1849,12 +2059,15 @@ mabd_status mabd_set_wrenches(mabd_ctx *c, const double *w) {
   if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, hipGetErrorString(e));
   if (!c->wr_on) drop_graphs(c);
   c->wr_on = true;
+  c->resid_ok = false;  // the last step ran with other loads
   return MABD_OK;
 }
 
 mabd_status mabd_multipliers(const mabd_ctx *cc, double *lam) {
   mabd_ctx *c = const_cast<mabd_ctx *>(cc);
   if (!c || !lam) return MABD_ERR_INVALID_ARG;
+  const mabd_status rs = resolve(c);
+  if (rs != MABD_OK) return rs;
   std::vector<double> cl(3 * (size_t)c->nchain_rows), gl(5 * c->gj.size());
   hipError_t e = hipSuccess;
   if (!cl.empty()) e = hipMemcpyAsync(cl.data(), c->d_clam, cl.size() * 8, hipMemcpyDeviceToHost, c->stream);
@@ -1874,8 +2087,75 @@ mabd_status mabd_multipliers(const mabd_ctx *cc, double *lam) {
   return MABD_OK;
 }
 
-mabd_status mabd_stats(const mabd_ctx *c, mabd_step_stats *st) {
+mabd_status mabd_residual(mabd_ctx *c, double *out) {
+  if (!c || !out) return MABD_ERR_INVALID_ARG;
+  const mabd_status rs = resolve(c);
+  if (rs != MABD_OK) return rs;
+  if (!c->resid_ok)
+    return fail(c, MABD_ERR_INVALID_ARG,
+                "no completed step to check: a step must follow create, set_state, set_wrenches "
+                "and the learned-start calls");
+  if (c->opt.newton_iters != 1)
+    return fail(c, MABD_ERR_INVALID_ARG,
+                "newton_iters > 1: the iterates are not kept; diagnostics bit 0 reports every iteration");
+  if (!c->d_dpart) {
+    // partial records, kept until mabd_destroy
+    hipError_t e = dalloc(c, &c->d_dpart, (size_t)DIAG_PART * diag_nblk(c));
+    if (e != hipSuccess) return fail(c, MABD_ERR_OOM, "residual partials");
+  }
+  return residual_into(c, c->d_dpart, out);
+}
+
+mabd_status mabd_twists(const mabd_ctx *cc, double *V) {
+  mabd_ctx *c = const_cast<mabd_ctx *>(cc);
+  if (!c || !V) return MABD_ERR_INVALID_ARG;
+  const mabd_status rs = resolve(c);
+  if (rs != MABD_OK) return rs;
+  const size_t n6 = (size_t)6 * c->n;
+  double *t = c->d_tmp;  // 24 n doubles
+  hipError_t e = n6 ? hipMemsetAsync(t, 0, n6 * 8, c->stream) : hipSuccess;
+  if (e == hipSuccess) {
+    launch_twists(c->nd, c->d_sol2in, c->d_q[c->cur], c->d_qd[c->cur], c->ns, t, c->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && n6) e = hipMemcpyAsync(V, t, n6 * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("twists: ") + hipGetErrorString(e));
+  return MABD_OK;
+}
+
+mabd_status mabd_joint_wrenches(const mabd_ctx *cc, double *W) {
+  mabd_ctx *c = const_cast<mabd_ctx *>(cc);
+  if (!c || !W) return MABD_ERR_INVALID_ARG;
+  const mabd_status rs = resolve(c);
+  if (rs != MABD_OK) return rs;
+  if (!c->resid_ok)
+    return fail(c, MABD_ERR_INVALID_ARG,
+                "no completed step: a step must follow create, set_state, set_wrenches "
+                "and the learned-start calls");
+  if (c->opt.newton_iters != 1)
+    return fail(c, MABD_ERR_INVALID_ARG, "newton_iters > 1: the last iterate's joint rows are not kept");
+  const size_t n6 = (size_t)6 * c->n;
+  double *t = c->d_tmp;
+  const int a = 1 - c->cur;  // the state the step started from
+  hipError_t e = n6 ? hipMemsetAsync(t, 0, n6 * 8, c->stream) : hipSuccess;
+  if (e == hipSuccess) {
+    launch_joint_wrenches(c->d_chains, (int)c->chains.size(), c->nchain_bodies, c->d_pl, c->d_pr, c->d_flag,
+                          std::max(c->nchain_rows, 1), c->d_clam, c->gb0, c->gb1, c->d_Rg, c->d_inc_off,
+                          c->d_inc, c->d_gj, c->d_gl, c->d_glam, c->d_q[a], c->ns, c->d_sol2in, t,
+                          c->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && n6) e = hipMemcpyAsync(W, t, n6 * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("joint wrenches: ") + hipGetErrorString(e));
+  return MABD_OK;
+}
+
+mabd_status mabd_stats(const mabd_ctx *cc, mabd_step_stats *st) {
+  mabd_ctx *c = const_cast<mabd_ctx *>(cc);
   if (!c || !st) return MABD_ERR_INVALID_ARG;
+  (void)resolve(c);  // the outcome goes to st->last_status
   *st = c->stats;
   return MABD_OK;
 }

@@ -87,7 +87,9 @@ def test_gradient_matches_finite_differences(kind):
             fd = (net.loss(pp) - net.loss(pm)) / (2 * d)
             e = abs(g_gpu[i] - fd) / max(abs(fd), 1e-3 * gmax)
             worst = max(worst, e)
-            assert e < 2e-3, (i, g_gpu[i], fd)
+            # FP32 network against FP64 central differences: measured
+            # worst 1.8e-6 (lattice) and 2.7e-6 (network)
+            assert e < 2e-5, (i, g_gpu[i], fd)
     say(kind, "worst relative gradient error", worst, "max |g|", gmax)
 
 

@@ -79,10 +79,9 @@ def test_graph_nonfinite_rollback():
     bad = qd.copy()
     bad[50, 10] = 1e308  # finite input whose step overflows
     ctx.set_state(q, bad)
-    with pytest.raises(pk.MabdError) as ei:
-        ctx.step(asm.h, 4)
-    assert ei.value.status == pk.ERR_NONFINITE
-    assert ctx.stats()["graph_replay"] == 1
+    ctx.step(asm.h, 4)  # queued: the outcome is read by the next call
+    st = ctx.stats()
+    assert st["last_status"] == pk.ERR_NONFINITE and st["graph_replay"] == 1
     q1, qd1 = ctx.state()
     assert np.array_equal(q1, q) and np.array_equal(qd1, bad)
     # the context keeps working after the failure

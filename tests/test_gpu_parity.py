@@ -41,13 +41,13 @@ def reference_step(s, asm, q, qd, solver):
     return s.step(asm.h, q, qd, solver=solver)
 
 
-# Trees of the tree workload mix 5 cm, 0.125 kg links with k_A = 1e8, so
-# kappa(Hbar) ~ 1e5 and multiplier rounding (the GPU and oracle multipliers
-# agree to ~1e-12 of their largest entry) reaches the velocities of light links
-# at ~2e-10 of the largest velocity.  Velocities of trees are held to 1e-9 and,
-# in addition, the oracle's FP64 KKT residual of the GPU multipliers must be
-# as small as that of its own solution.
-TOL_V_TREE = 1e-9
+# Trees are held to the same bar as every other assembly.  The oracle's exact
+# FP64 solvers (dense Cholesky and SuperLU of the dual, primal leaf-to-root
+# condensation, LU of the full KKT matrix) agree among themselves on tree
+# velocities to 6e-12 of the largest velocity on the tree test cases, and the
+# GPU's tree contraction to 5e-12; in addition, the oracle's FP64 KKT residual
+# of the GPU multipliers must be as small as that of its own solution.
+TOL_V_TREE = TOL
 
 
 def teacher_forced(asm, steps, solver=oracle.AUTO, tol=TOL, tol_v=None, **kw):
@@ -74,7 +74,7 @@ def teacher_forced(asm, steps, solver=oracle.AUTO, tol=TOL, tol_v=None, **kw):
             say("  kkt gpu", dv[:3], "oracle", d[:3])
             assert dv[oracle.KKT] <= max(10 * d[oracle.KKT], 1e-11)
         assert eq < tol and eqd < tv, (n, eq, eqd)
-        assert el < 1e3 * tol, (n, el)
+        assert el < tol, (n, el)
         q, qd = q1, qd1
     ctx.close()
     return worst
@@ -311,8 +311,9 @@ def test_nonfinite_step_keeps_last_state():
     bad = qd.copy()
     bad[5, 9] = 1e308
     ctx.set_state(q, bad)
+    ctx.step(asm.h, 3)  # queued: mabd_state reads the outcome
     with pytest.raises(pk.MabdError) as ei:
-        ctx.step(asm.h, 3)
+        ctx.state()
     assert ei.value.status == pk.ERR_NONFINITE
     q1, qd1 = ctx.state()
     assert np.array_equal(q1, q) and np.array_equal(qd1, bad)
@@ -421,11 +422,16 @@ def test_full_size_lattice_one_step():
     ctx.step(asm.h, 1)
     st = ctx.stats()
     lam_g = ctx.multipliers()
+    qg, qdg = ctx.state()
     ctx.close()
     s = oracle.System(asm)
-    _, _, dv = s.finish(asm.h, asm.q0, asm.qd0, lam_g)
+    qv, qdv, dv = s.finish(asm.h, asm.q0, asm.qd0, lam_g)
     say("pcg iterations", st["pcg_iters"], "kkt of GPU multipliers", dv[:3])
     assert dv[oracle.RHO_D] <= 2e-10 and dv[oracle.RHO_P] <= 1e-12
+    # the GPU's back-projection of its multipliers is the oracle's
+    eq, eqd = state_errors(qg, qdg, qv, qdv)
+    say("state vs the oracle's back-projection of the GPU multipliers", eq, eqd)
+    assert eq < TOL and eqd < TOL
 
 
 def test_full_size_rgg_one_step():
@@ -443,13 +449,18 @@ def test_full_size_rgg_one_step():
     ctx.step(asm.h, 1)
     st = ctx.stats()
     lam_g = ctx.multipliers()
+    qg, qdg = ctx.state()
     ctx.close()
     assert st["n_graph"] == 6 and st["last_status"] == 0
     assert 0 < st["pcg_iters"] < 100000 and st["rho_d"] <= tol
     s = oracle.System(asm)
-    _, _, dv = s.finish(asm.h, asm.q0, asm.qd0, lam_g)
+    qv, qdv, dv = s.finish(asm.h, asm.q0, asm.qd0, lam_g)
     say("pcg iterations", st["pcg_iters"], "GPU residual", st["rho_d"], "kkt of GPU multipliers", dv[:3])
     assert dv[oracle.RHO_D] <= 2 * tol and dv[oracle.RHO_P] <= 1e-12
+    # the GPU's back-projection of its multipliers is the oracle's
+    eq, eqd = state_errors(qg, qdg, qv, qdv)
+    say("state vs the oracle's back-projection of the GPU multipliers", eq, eqd)
+    assert eq < TOL and eqd < TOL
     # the GPU's own true residual of the networks and the oracle's over all
     # rows (the trees' rows are solved exactly) are the same number
     assert abs(dv[oracle.RHO_D] - st["rho_d"]) <= 1e-4 * st["rho_d"]

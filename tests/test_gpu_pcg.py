@@ -1,10 +1,15 @@
 """GPU PCG on assemblies with closed loops against the oracle's direct solve.
 
-The iterative solve stops at |r - S lam| <= tol |r| (tol = 1e-12 here), so the
-state is compared at the bound that tolerance implies: the oracle re-projects
-the GPU multipliers (FP64, its own back-projection) and must find the same
-relative dual residual, and the GPU state must agree with the oracle's direct
-solution to relative 1e-8 (kappa(S) ~ 1e4 on these sizes).
+The iterative solve stops at |r - S lam| <= tol |r| (tol = 1e-10 by default,
+the closed-loop workload's stop), so the state is compared at the bound that
+tolerance implies:
+  * the oracle re-projects the GPU multipliers (FP64, its own
+    back-projection) and must find the relative dual residual within 2 tol,
+    and the GPU state must equal that back-projection to 1e-12 (q) and 1e-9
+    (qdot);
+  * against the oracle's direct (SuperLU) solution the multiplier error of a
+    tol-accurate solve is amplified by kappa(S) ~ 1e4..1e6 on these sizes:
+    q must agree to 1e-10 and qdot to 1e-5 of the largest velocity.
 """
 import numpy as np
 import pytest

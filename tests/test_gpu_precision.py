@@ -109,8 +109,9 @@ def test_form1_not_converged_keeps_state():
     asm = mi.chain(500, seed=108)
     ctx = pk.Context(asm, precision=1, kkt_tol=1e-12, ir_max_sweeps=0)
     q0, qd0 = ctx.state()
+    ctx.step(asm.h, 2)  # queued: mabd_multipliers reads the outcome
     with pytest.raises(pk.MabdError) as ei:
-        ctx.step(asm.h, 2)
+        ctx.multipliers()
     assert ei.value.status == pk.ERR_NOT_CONVERGED
     st = ctx.stats()
     say("kkt of the FP32 solve", st["kkt"])

@@ -11,7 +11,7 @@ from gpu_util import say, state_errors
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
-TOL_V_TREE = 1e-9  # light tree links, as in the parity tests
+TOL_V_TREE = TOL  # the parity tests' tree bar
 
 
 def wrenches(asm, seed, scale=1.0):

@@ -18,6 +18,7 @@ import oracle
 import test_gnn_ref as gnn_pins
 import test_oracle_pins as pins
 import test_oracle_verifier as vpins
+import test_oracle_wrench_pins as wpins
 
 ORACLE_DIR = os.path.dirname(os.path.abspath(oracle.__file__))
 SRC = os.path.join(ORACLE_DIR, "mabd_oracle.c")
@@ -50,6 +51,13 @@ def verifier_pins():
     vpins.test_perturbed_step_matches_brute_force_residual()
     vpins.test_primal_residual_is_relative_to_the_free_increment()
     vpins.test_post_step_constraints()
+
+
+def wrench_pins():
+    wpins.test_twist_of_rigid_spin()
+    wpins.test_ball_joint_wrench_is_the_anchor_point_force()
+    wpins.test_internal_joint_forces_cancel()
+    wpins.test_hanging_box_carries_its_weight()
 
 
 # (name, text in the oracle, planted replacement, pin that must fail)
@@ -107,6 +115,15 @@ MUTANTS = [
     # the verifier: the ball joints' post-step value reads zero
     ("verifier_cball_zeroed", "if (s->jtype[k] == 0) { if (v > *cball) *cball = v; }",
      "if (s->jtype[k] == 0) { if (v > *cball) *cball = 0.0 * v; }", verifier_pins),
+    # Eq. module1-G-twist: the factor 1/2 of the angular velocity dropped
+    ("twist_half_dropped", "o[0] += 0.5 * (a[1] * ad[2] - a[2] * ad[1]);",
+     "o[0] += (a[1] * ad[2] - a[2] * ad[1]);", wrench_pins),
+    # Eq. module2-E: E(A)^T with the cross product reversed (E instead of -E)
+    ("wrench_moment_sign", "o[1] += a[2] * fc[0] - a[0] * fc[2];", "o[1] -= a[2] * fc[0] - a[0] * fc[2];",
+     wrench_pins),
+    # the joint force taken as +G^T lambda instead of -G^T lambda
+    ("wrench_force_sign", "f[12 * (size_t)b + c] -= G[i * 12 + c] * lam[off + i];",
+     "f[12 * (size_t)b + c] += G[i * 12 + c] * lam[off + i];", wrench_pins),
 ]
 
 
