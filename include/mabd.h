@@ -241,6 +241,25 @@ int64_t mabd_rows(const mabd_ctx *ctx);
    (diagnostics bit 0 evaluates every iteration instead); OOM; DEVICE. */
 mabd_status mabd_residual(mabd_ctx *ctx, double *out);
 
+/* mabd_residual for callers that cannot allocate device memory or wait for
+   the stream: code under HIP graph capture, serving loops that forbid
+   allocation.  The five values (as mabd_residual's out) are written to
+   out_dev, a DEVICE buffer of 5 doubles, by kernels queued on the context's
+   stream; the call returns without waiting.  The partial sums go to a fixed
+   device array of the library's instead of a buffer allocated at the first
+   call: 65,536 records of 6 doubles (3 MiB), one copy on every device the
+   library runs on, held until the process ends; nothing is allocated.  Every
+   call on one device shares that array and its records are rewritten by
+   each call: calls that overlap on one device (other host threads, or
+   streams not ordered with this context's) race.  Errors (host-side, nothing
+   queued): INVALID_ARG if the assembly needs more than 65,536 records (chain
+   tiles of 60 rows + ceil(generic bodies / 256) + ceil(generic joints /
+   256)), if no step completed since create, mabd_set_state, mabd_set_wrenches
+   or a learned-start call, or if newton_iters > 1; DEVICE.  If a queued step
+   fails, out_dev is not meaningful (it may be left unchanged); the failure is
+   reported by the next call that reads the outcome. */
+mabd_status mabd_residual_noalloc(mabd_ctx *ctx, double *out_dev);
+
 /* Spatial twist of every body at the current state (Eq. module1-G-twist):
    V = G(A) qdot = [omega; v], omega = 1/2 sum_c a_c x adot_c (a_c the c-th
    column of A), v = tdot; world frame.  V: host, n*6 doubles in input body

@@ -21,7 +21,7 @@ OK, ERR_INVALID_ARG, ERR_TOPOLOGY, ERR_DEVICE, ERR_OOM, ERR_NONFINITE, ERR_NOT_C
     ERR_SINGULAR = 0, -1, -2, -3, -4, -5, -6, -7
 
 EXPORTED = ["mabd_options_default", "mabd_create", "mabd_step", "mabd_state", "mabd_state_device",
-            "mabd_set_state", "mabd_set_wrenches", "mabd_multipliers", "mabd_rows", "mabd_residual",
+            "mabd_set_state", "mabd_set_wrenches", "mabd_multipliers", "mabd_rows", "mabd_residual", "mabd_residual_noalloc",
             "mabd_twists", "mabd_joint_wrenches",
             "mabd_stats",
             "mabd_gnn_size",
@@ -110,6 +110,7 @@ def lib():
         L.mabd_rows.argtypes = [P]; L.mabd_rows.restype = I64
         L.mabd_stats.argtypes = [P, P]; L.mabd_stats.restype = I32
         L.mabd_residual.argtypes = [P, P]; L.mabd_residual.restype = I32
+        L.mabd_residual_noalloc.argtypes = [P, P]; L.mabd_residual_noalloc.restype = I32
         L.mabd_twists.argtypes = [P, P]; L.mabd_twists.restype = I32
         L.mabd_joint_wrenches.argtypes = [P, P]; L.mabd_joint_wrenches.restype = I32
         L.mabd_gnn_load.argtypes = [P, ctypes.c_char_p]; L.mabd_gnn_load.restype = I32
@@ -219,6 +220,15 @@ class Context:
         out = np.zeros(5)
         self._check(lib().mabd_residual(self.h, out.ctypes.data))
         return dict(zip(("rho_p", "rho_d", "kkt", "c_ball", "c_hinge"), out.tolist()))
+
+    def residual_noalloc(self, out_dev):
+        """The same five values written into a device tensor of 5 float64
+        (contiguous) on the context's stream, with the library's fixed
+        scratch; returns without waiting."""
+        if not out_dev.is_cuda or out_dev.dtype.itemsize != 8 or out_dev.numel() < 5 \
+                or not out_dev.is_contiguous():
+            raise ValueError("residual_noalloc needs a contiguous float64 device tensor of 5")
+        self._check(lib().mabd_residual_noalloc(self.h, out_dev.data_ptr()))
 
     def twists(self) -> np.ndarray:
         """Spatial twist [omega; v] of every body at the current state (n x 6)."""

@@ -9,6 +9,8 @@
 // block writes DIAG_PART partials (four sums, two maxima); diag_reduce_kernel
 // combines them in a fixed order.  The chain rows' partials come from
 // chain_resid_kernel in its diagnostics mode.
+#include <mutex>
+
 #include "common.hpp"
 #include "dmath.hpp"
 #include "generic.hpp"
@@ -375,5 +377,34 @@ void launch_joint_wrenches(const ChainDesc *chains, int nchains, int nchain_bodi
                        Rg, inc_off, inc, J, gl, glam, sol2in, W);
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of mabd_residual_noalloc: RESID_STATIC_BLOCKS partial
+// records of DIAG_PART doubles (3 MiB), one copy on every device the library
+// runs on, held until the process ends.  In host code the name `scratch` is a
+// host-side stand-in, not a device address: the address of a device's copy
+// comes from hipGetSymbolAddress, looked up once per device with that device
+// current (resid_scratch), and only that address is passed to kernels.
+constexpr int RESID_STATIC_BLOCKS = 65536;
+constexpr int RESID_MAX_DEVICES = 64;
+static __device__ __align__(256) double scratch[(size_t)RESID_STATIC_BLOCKS * DIAG_PART];
+
+int resid_static_blocks() { return RESID_STATIC_BLOCKS; }
+
+// Device address of the current device's copy of `scratch` (device index
+// `device`, which must be current).
+hipError_t resid_scratch(int device, double **out) {
+  static std::mutex mu;
+  static double *ptr[RESID_MAX_DEVICES] = {};
+  if (device < 0 || device >= RESID_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[device] = static_cast<double *>(p);
+  }
+  *out = ptr[device];
+  return hipSuccess;
+}
 
 }  // namespace mabd

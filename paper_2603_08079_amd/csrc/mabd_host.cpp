@@ -67,6 +67,8 @@ void launch_gdiag_joint(int m, const GJoint *J, const double *gl, const double *
                         const uint32_t *status, double *part, hipStream_t s);
 void launch_diag_reduce(const double *part, int nblk, double *out, const uint32_t *status,
                         hipStream_t s);
+int resid_static_blocks();
+hipError_t resid_scratch(int device, double **out);
 void launch_twists(int nd, const int32_t *sol2in, const double *q, const double *qd, int64_t ns,
                    double *V, hipStream_t s);
 void launch_joint_wrenches(const ChainDesc *chains, int nchains, int nchain_bodies, const double *pl,
@@ -274,6 +276,8 @@ struct mabd_ctx {
   double *d_dpart = nullptr, *d_diag = nullptr, *h_diag = nullptr;
   double *d_qit = nullptr, *d_dqit = nullptr;
   bool resid_ok = false;  // the buffers still describe the last completed step
+  // this device's copy of the library's fixed residual scratch (not owned)
+  double *d_rscratch = nullptr;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   double h_last = -1.0;
@@ -1267,6 +1271,12 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(dalloc(c, &c->d_status, 4));
   if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_status, 4 * sizeof(uint32_t)));
   if (e == hipSuccess) chk(hipEventCreateWithFlags(&c->pend_ev, hipEventDisableTiming));
+  {
+    // the fixed scratch of mabd_residual_noalloc on this (current) device
+    int dev = 0;
+    if (e == hipSuccess) chk(hipGetDevice(&dev));
+    if (e == hipSuccess) chk(resid_scratch(dev, &c->d_rscratch));
+  }
   if (e == hipSuccess) chk(dalloc(c, &c->d_diag, DIAG_VALUES));
   if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_diag, DIAG_VALUES * sizeof(double)));
   if (opt.diagnostics & 1) {
@@ -2104,6 +2114,27 @@ mabd_status mabd_residual(mabd_ctx *c, double *out) {
     if (e != hipSuccess) return fail(c, MABD_ERR_OOM, "residual partials");
   }
   return residual_into(c, c->d_dpart, out);
+}
+
+mabd_status mabd_residual_noalloc(mabd_ctx *c, double *out_dev) {
+  if (!c || !out_dev) return MABD_ERR_INVALID_ARG;
+  const int64_t nb = diag_nblk(c);
+  if (nb > resid_static_blocks())
+    return fail(c, MABD_ERR_INVALID_ARG,
+                "the assembly needs " + std::to_string(nb) + " partial records, the fixed scratch holds " +
+                    std::to_string(resid_static_blocks()) + ": use mabd_residual");
+  if (!c->resid_ok)
+    return fail(c, MABD_ERR_INVALID_ARG,
+                "no completed step to check: a step must follow create, set_state, set_wrenches "
+                "and the learned-start calls");
+  if (c->opt.newton_iters != 1)
+    return fail(c, MABD_ERR_INVALID_ARG, "newton_iters > 1: the iterates are not kept");
+  if (!c->d_rscratch) return fail(c, MABD_ERR_DEVICE, "fixed residual scratch unavailable");
+  const int a = 1 - c->cur, b = c->cur;
+  issue_residual(c, c->h_last, a, b, c->d_q[a], c->d_qd[b], c->h_last, c->d_rscratch, out_dev);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("residual: ") + hipGetErrorString(e));
+  return MABD_OK;
 }
 
 mabd_status mabd_twists(const mabd_ctx *cc, double *V) {
