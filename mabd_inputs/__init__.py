@@ -7,10 +7,13 @@ one piece shared by the FP64 oracle and the GPU library's tests/benchmarks.
 
 Layout conventions (paper Sec. 3.1 and Sec. 4.1):
   * q per body = [a1; a2; a3; t] (12 doubles), a_c the c-th column of A;
-  * a joint is (type, a, b, pa, pb, axis, cp_len): type 0 ball (Eq. ball),
-    1 five-row hinge (Eq. hinge); a/b body indices (-1 = world); pa/pb the
-    first control point in each body's rest frame; axis the hinge axis in a's
-    rest frame; cp_len the spacing of the second control point along the axis.
+  * a joint is (type, a, b, pa, pb, axis, cp_len, axis2): type 0 ball (Eq.
+    ball), 1 five-row hinge (Eq. hinge), 2 four-row universal (Eq. universal),
+    3 five-row prismatic (Eq. prismatic); a/b body indices (-1 = world); pa/pb
+    the first control point in each body's rest frame; axis the hinge or
+    prismatic axis, or the universal joint's first axis, in a's rest frame;
+    axis2 the universal joint's second axis (orthogonal to the first, a's
+    rest frame); cp_len the spacing of the further control points.
 
 Workloads (the paper's scenes are not reproducible: their geometry is not
 published, so these stand in for them at the configurations' sizes):
@@ -34,6 +37,8 @@ from typing import Optional
 import numpy as np
 
 GRAVITY = (0.0, 0.0, -9.8)
+BALL, HINGE, UNIVERSAL, PRISMATIC = 0, 1, 2, 3
+JOINT_ROWS = (3, 5, 4, 5)   # constraint rows per joint type
 
 
 @dataclasses.dataclass
@@ -53,6 +58,7 @@ class Assembly:
     axis: np.ndarray          # (m, 3)
     cp_len: np.ndarray        # (m,)
     poisson: Optional[np.ndarray] = None
+    axis2: Optional[np.ndarray] = None  # (m, 3) universal joints' second axis
     gravity: tuple = GRAVITY
     material: int = 0         # 0 orthogonality stiffness k_A, 1 Lame from (E, nu)
     h: float = 1e-2
@@ -68,7 +74,7 @@ class Assembly:
         return int(self.jtype.shape[0])
 
     def rows(self) -> int:
-        return int(np.where(self.jtype == 1, 5, 3).sum())
+        return int(np.asarray(JOINT_ROWS)[self.jtype].sum())
 
     def copy(self) -> "Assembly":
         return dataclasses.replace(self, **{f.name: (getattr(self, f.name).copy()
@@ -190,13 +196,43 @@ def tree(n: int, seed: int = 0, window: int = 64, sigma: float = 1e-3,
         meta=dict(kind="tree", seed=seed, parent=parent))
 
 
+def perpendicular(axis):
+    """A unit vector orthogonal to each row of `axis` (m x 3)."""
+    axis = np.asarray(axis, float).reshape(-1, 3)
+    e = np.where(np.abs(axis[:, :1]) < 0.9, [[1.0, 0.0, 0.0]], [[0.0, 1.0, 0.0]])
+    v = np.cross(axis, e)
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def axis2_of(asm) -> np.ndarray:
+    """The assembly's second axes, or perpendiculars of its axes if unset."""
+    return perpendicular(asm.axis) if asm.axis2 is None else asm.axis2
+
+
+def mix_joint_types(asm: Assembly, seed: int, probs=(0.25, 0.25, 0.25, 0.25)) -> Assembly:
+    """The assembly with each joint's type redrawn (ball, hinge, universal,
+    prismatic with the given probabilities), axes uniform on the sphere and
+    second axes uniform on the circle orthogonal to them; anchors unchanged."""
+    rng = np.random.default_rng(seed)
+    out = asm.copy()
+    m = out.m
+    out.jtype = rng.choice(4, size=m, p=np.asarray(probs, float) / np.sum(probs)).astype(np.uint8)
+    out.axis = _unit_sphere(rng, m)
+    u = perpendicular(out.axis)
+    w = np.cross(out.axis, u)
+    phi = rng.uniform(0.0, 2.0 * np.pi, m)[:, None]
+    out.axis2 = np.cos(phi) * u + np.sin(phi) * w
+    return out
+
+
 def concat(parts, name="batch", h=1e-2, steps=100) -> Assembly:
     """One assembly holding independent sub-assemblies (indices shifted)."""
     off = 0
     cols = {k: [] for k in ("dims", "density", "k_orth", "pinned", "q0", "qd0", "jtype",
-                             "ja", "jb", "pa", "pb", "axis", "cp_len")}
+                             "ja", "jb", "pa", "pb", "axis", "cp_len", "axis2")}
     sizes = []
     for p in parts:
+        cols["axis2"].append(axis2_of(p))
         for k in ("dims", "density", "k_orth", "pinned", "q0", "qd0", "jtype", "pa", "pb",
                   "axis", "cp_len"):
             cols[k].append(getattr(p, k))

@@ -72,6 +72,7 @@ class _Sys(ctypes.Structure):
         ("material", ctypes.c_int32), ("hinge_grad", ctypes.c_int32),
         ("newton_iters", ctypes.c_int32),
         ("wrench", ctypes.c_void_p),
+        ("axis2", ctypes.c_void_p),
     ]
 
 
@@ -163,12 +164,14 @@ class System:
         self.pb = c(asm.pb, np.float64)
         self.axis = c(asm.axis, np.float64)
         self.cp_len = c(asm.cp_len, np.float64)
+        a2 = getattr(asm, "axis2", None)
+        self.axis2 = None if a2 is None else c(a2, np.float64)
         # external wrench per body [tau; f] (world frame, about the COM), or None
         self.wrench = None if wrench is None else c(np.asarray(wrench, np.float64).reshape(self.n, 6))
         s = _Sys()
         s.n, s.m = self.n, self.m
         for f in ("dims", "density", "k_orth", "poisson", "pinned", "q0", "jtype", "ja", "jb",
-                  "pa", "pb", "axis", "cp_len", "wrench"):
+                  "pa", "pb", "axis", "cp_len", "wrench", "axis2"):
             setattr(s, f, _p(getattr(self, f)))
         g = asm.gravity if gravity is None else gravity
         s.gravity[0], s.gravity[1], s.gravity[2] = g
@@ -211,7 +214,7 @@ class System:
         st = self.L.ora_joint_terms(self.ref, _p(q), k, _p(C), _p(Ga), _p(Gb))
         if st != 0:
             raise OracleError(st, "joint_terms")
-        r = 5 if self.jtype[k] == 1 else 3
+        r = (3, 5, 4, 5)[int(self.jtype[k])]  # rows per joint type
         return C[:r], Ga[:r], Gb[:r]
 
     def dual(self, h, q, qd):

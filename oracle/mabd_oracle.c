@@ -362,7 +362,20 @@ static int side_rot0(const ora_system *s, int b, double *R) {
   return polar_rm(A, R);
 }
 
-static int jrows(const ora_system *s, int k) { return s->jtype[k] == 1 ? 5 : 3; }
+/* rows per joint: ball 3 (Eq. ball), hinge 5 (Eq. hinge), universal 4
+   (Eq. universal), prismatic 5 (Eq. prismatic) */
+static int jrows(const ora_system *s, int k) {
+  static const int rows[4] = {3, 5, 4, 5};
+  return rows[s->jtype[k]];
+}
+
+/* u = v / |v|; nonzero status if v is zero or not finite */
+static int unit3(const double *v, double *u) {
+  double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  if (!(n > 0.0) || !isfinite(n)) return ORA_EINVAL;
+  for (int r = 0; r < 3; ++r) u[r] = v[r] / n;
+  return ORA_OK;
+}
 
 /* difference of two attached points, translation difference first so that
    rounding stays at the scale of the bodies rather than the world position */
@@ -400,65 +413,113 @@ static int joint_terms(const ora_system *s, const double *q, int k, double *C, d
     }
     return ORA_OK;
   }
-  /* hinge */
-  double ax[3], nrm;
-  memcpy(ax, s->axis + 3 * k, sizeof ax);
-  nrm = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
-  if (!(nrm > 0.0)) return ORA_EINVAL;
-  for (int r = 0; r < 3; ++r) ax[r] /= nrm;
-  double Ra0[9], Rb0[9], wax[3], axb[3];
+  /* Joints expressed in a rotated frame (Secs. 4.3-4.5).  Body a owns the
+     frame R_J = dR R_a^T, dR the joint's frame at rest (R_a the polar
+     rotation of a, Eq. polar): hinge and prismatic use the Rodrigues frame of
+     their axis (rows r_x, axis, r_z), the universal joint the rows
+     (a1 x a2, a1, a2).  Control points (rest frames of their bodies): P1 of
+     either side at the anchor; hinge: P2 = P1 + ell * axis on both sides;
+     universal: b's P2 = P1 + ell * a2; prismatic: b's P2 = P1 + ell * axis and
+     P3 = P1 + ell * n, n the frame's local z axis at rest.  A direction fixed
+     in a's rest frame enters b's rest frame as the same world direction at
+     creation.  Each row is one local component of R_J (y_X - y_Y):
+       hinge      x, y, z of (P1a - P1b); x, z of (P2a - P2b)        (5 rows)
+       universal  x, y, z of (P1a - P1b); y of (P2b - P1b)            (4 rows)
+       prismatic  x, z of (P1a - P1b); x, z of (P2b - P1b); x of (P3b - P1b)
+     Gradient (default hinge_grad): the frozen-frame part R_J J(p) on each
+     point's body, plus on body a the rotation term of Eq. r_gradient with
+     R_a ~ A_a (Eq. pcpr), d(rbar^T A_a^T d)/dvec(A_a). */
+  const int type = s->jtype[k];
+  double ax[3];
+  if (unit3(s->axis + 3 * k, ax)) return ORA_EINVAL;
+  double Ra0[9], Rb0[9];
   int st = side_rot0(s, a, Ra0);
   if (st) return st;
   st = side_rot0(s, b, Rb0);
   if (st) return st;
-  mm(3, 3, 1, Ra0, ax, wax);  /* axis in the world at creation */
-  mtm(3, 3, 1, Rb0, wax, axb); /* same axis in b's rest frame */
-  double ell = s->cp_len[k];
-  double pa2[3], pb2[3];
-  for (int r = 0; r < 3; ++r) {
-    pa2[r] = pa[r] + ell * ax[r];
-    pb2[r] = pb[r] + ell * axb[r];
+  double dRh[9];
+  if (type == 2) {
+    double a2[3];
+    if (!s->axis2 || unit3(s->axis2 + 3 * k, a2)) return ORA_EINVAL;
+    double dt = ax[0] * a2[0] + ax[1] * a2[1] + ax[2] * a2[2];
+    for (int r = 0; r < 3; ++r) a2[r] -= dt * ax[r];
+    if (unit3(a2, a2)) return ORA_EINVAL;
+    double x[3] = {ax[1] * a2[2] - ax[2] * a2[1], ax[2] * a2[0] - ax[0] * a2[2],
+                   ax[0] * a2[1] - ax[1] * a2[0]};
+    for (int r = 0; r < 3; ++r) {
+      dRh[r] = x[r];
+      dRh[3 + r] = ax[r];
+      dRh[6 + r] = a2[r];
+    }
+  } else {
+    hinge_frame(ax, dRh);
   }
-  double d1[3], d2[3];
-  point_diff(Aa, ta, pa, Ab, tb, pb, d1);
-  point_diff(Aa, ta, pa2, Ab, tb, pb2, d2);
-  double Ra[9], dRh[9], Rh[9];
+  double ell = s->cp_len[k];
+  /* directions of b's second and third points, in a's rest frame, then in b's */
+  double da2[3], da3[3] = {0.0, 0.0, 0.0}, wd[3], db2[3], db3[3];
+  if (type == 2) memcpy(da2, dRh + 6, sizeof da2);
+  else memcpy(da2, ax, sizeof da2);
+  if (type == 3) memcpy(da3, dRh + 6, sizeof da3);
+  mm(3, 3, 1, Ra0, da2, wd);
+  mtm(3, 3, 1, Rb0, wd, db2);
+  mm(3, 3, 1, Ra0, da3, wd);
+  mtm(3, 3, 1, Rb0, wd, db3);
+  /* points: 0 P1 of a, 1 P2 of a, 2 P1 of b, 3 P2 of b, 4 P3 of b */
+  double P[5][3];
+  for (int r = 0; r < 3; ++r) {
+    P[0][r] = pa[r];
+    P[1][r] = pa[r] + ell * ax[r];
+    P[2][r] = pb[r];
+    P[3][r] = pb[r] + ell * db2[r];
+    P[4][r] = pb[r] + ell * db3[r];
+  }
+  const int pside[5] = {0, 0, 1, 1, 1};
+  /* rows: local component, point X, point Y */
+  static const int spec[4][5][3] = {
+      {{0, 0, 2}, {1, 0, 2}, {2, 0, 2}, {0, 0, 2}, {0, 0, 2}},  /* (ball: unused) */
+      {{0, 0, 2}, {1, 0, 2}, {2, 0, 2}, {0, 1, 3}, {2, 1, 3}},  /* hinge */
+      {{0, 0, 2}, {1, 0, 2}, {2, 0, 2}, {1, 3, 2}, {0, 0, 2}},  /* universal */
+      {{0, 0, 2}, {2, 0, 2}, {0, 3, 2}, {2, 3, 2}, {0, 4, 2}}}; /* prismatic */
+  double Ra[9], Rh[9];
   if (a >= 0) {
     st = polar_rm(Aa, Ra);
     if (st) return st;
   } else {
     for (int i = 0; i < 9; ++i) Ra[i] = (i % 4 == 0) ? 1.0 : 0.0;
   }
-  hinge_frame(ax, dRh);
-  mmt(3, 3, 3, dRh, Ra, Rh); /* R_H = dR_H R_a^T */
-  double e1[3], e2[3];
-  mm(3, 3, 1, Rh, d1, e1);
-  mm(3, 3, 1, Rh, d2, e2);
-  C[0] = e1[0]; C[1] = e1[1]; C[2] = e1[2]; C[3] = e2[0]; C[4] = e2[2];
-  /* rows: (CP index, local component) */
-  const int cp[5] = {1, 1, 1, 2, 2};
-  const int comp[5] = {0, 1, 2, 0, 2};
-  for (int side = 0; side < 2; ++side) {
-    int body = side == 0 ? a : b;
-    if (!is_dyn(s, body)) continue;
-    double *G = side == 0 ? Ga : Gb;
-    double J1[36], J2[36];
-    jmat(side == 0 ? pa : pb, J1);
-    jmat(side == 0 ? pa2 : pb2, J2);
-    double sg = side == 0 ? 1.0 : -1.0;
-    for (int i = 0; i < 5; ++i) {
-      const double *Jm = cp[i] == 1 ? J1 : J2;
+  mmt(3, 3, 3, dRh, Ra, Rh); /* R_J = dR R_a^T */
+  for (int i = 0; i < rows; ++i) {
+    const int comp = spec[type][i][0], X = spec[type][i][1], Y = spec[type][i][2];
+    /* y_X - y_Y: across the joint the translation difference first; on one
+       body its affine block times the difference of the rest points */
+    double dm[3];
+    if (pside[X] != pside[Y]) {
+      point_diff(Aa, ta, P[X], Ab, tb, P[Y], dm);
+    } else {
+      double dp[3] = {P[X][0] - P[Y][0], P[X][1] - P[Y][1], P[X][2] - P[Y][2]};
+      mm(3, 3, 1, pside[X] ? Ab : Aa, dp, dm);
+    }
+    double e[3];
+    mm(3, 3, 1, Rh, dm, e);
+    C[i] = e[comp];
+    for (int pt = 0; pt < 2; ++pt) {
+      const int id = pt == 0 ? X : Y;
+      const int body = pside[id] ? b : a;
+      if (!is_dyn(s, body)) continue;
+      double *G = pside[id] ? Gb : Ga;
+      const double sg = pt == 0 ? 1.0 : -1.0;
+      double Jm[36];
+      jmat(P[id], Jm);
       for (int col = 0; col < 12; ++col) {
         double v = 0.0;
-        for (int r = 0; r < 3; ++r) v += Rh[comp[i] * 3 + r] * Jm[r * 12 + col];
-        G[i * 12 + col] = sg * v;
+        for (int r = 0; r < 3; ++r) v += Rh[comp * 3 + r] * Jm[r * 12 + col];
+        G[i * 12 + col] += sg * v;
       }
-      if (side == 0 && s->hinge_grad == 0) {
-        /* d(rbar_c^T A^T d_m)/dvec(A): entry 3l + kk is rbar_c[l] d_m[kk] */
-        const double *dm = cp[i] == 1 ? d1 : d2;
-        for (int l = 0; l < 3; ++l)
-          for (int kk = 0; kk < 3; ++kk) G[i * 12 + 3 * l + kk] += dRh[comp[i] * 3 + l] * dm[kk];
-      }
+    }
+    if (is_dyn(s, a) && s->hinge_grad == 0) {
+      /* d(rbar_c^T A^T d_m)/dvec(A): entry 3l + kk is rbar_c[l] d_m[kk] */
+      for (int l = 0; l < 3; ++l)
+        for (int kk = 0; kk < 3; ++kk) Ga[i * 12 + 3 * l + kk] += dRh[comp * 3 + l] * dm[kk];
     }
   }
   return ORA_OK;
@@ -490,8 +551,9 @@ static int validate(const ora_system *s) {
     if (a < -1 || a >= s->n || b < -1 || b >= s->n) return ORA_EINVAL;
     if (a == b) return ORA_EINVAL;
     if (!is_dyn(s, a) && !is_dyn(s, b)) return ORA_EINVAL;
-    if (s->jtype[k] > 1) return ORA_EINVAL;
-    if (s->jtype[k] == 1 && !(s->cp_len[k] > 0.0)) return ORA_EINVAL;
+    if (s->jtype[k] > 3) return ORA_EINVAL;
+    if (s->jtype[k] >= 1 && !(s->cp_len[k] > 0.0)) return ORA_EINVAL;
+    if (s->jtype[k] == 2 && !s->axis2) return ORA_EINVAL;
   }
   return ORA_OK;
 }

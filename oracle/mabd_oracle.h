@@ -24,11 +24,12 @@ typedef struct {
   const uint8_t *pinned;   /* n  1 = kinematic body held at q0                     */
   const double *q0;        /* n*12 creation state: pinned poses, hinge axes       */
   int32_t m;
-  const uint8_t *jtype;    /* m  0 ball, 1 hinge                                   */
+  const uint8_t *jtype;    /* m  0 ball, 1 hinge, 2 universal, 3 prismatic         */
   const int32_t *ja, *jb;  /* m  body indices, -1 = world                         */
   const double *pa, *pb;   /* m*3 CP1 in the rest frame of a / b (world if -1)    */
-  const double *axis;      /* m*3 hinge axis in a's rest frame (world if a = -1)  */
-  const double *cp_len;    /* m  CP1 -> CP2 spacing along the hinge axis          */
+  const double *axis;      /* m*3 hinge / prismatic axis, universal first axis a1, in
+                              a's rest frame (world if a = -1)                     */
+  const double *cp_len;    /* m  spacing of the further control points            */
   double gravity[3];
   int32_t material;        /* 0: mu = 4 k_A, lambda = 0 ; 1: Lame from (E, nu)     */
   int32_t hinge_grad;      /* 0: frozen frame + A-linearized rotation term; 2: frozen only */
@@ -36,6 +37,9 @@ typedef struct {
   const double *wrench;    /* n*6 external spatial wrench [tau; f] per body, world
                               frame, about the COM (Eq. module1-wrench-map); NULL:
                               none                                                 */
+  const double *axis2;     /* m*3 universal joints: the second axis a2 (orthogonal
+                              to axis, a's rest frame or world if a = -1); NULL if
+                              there is no universal joint                          */
 } ora_system;
 
 /* diag[] slots written by ora_step / ora_finish */

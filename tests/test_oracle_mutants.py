@@ -18,6 +18,7 @@ import oracle
 import test_gnn_ref as gnn_pins
 import test_oracle_pins as pins
 import test_oracle_verifier as vpins
+import test_oracle_joint_pins as jpins
 import test_oracle_wrench_pins as wpins
 
 ORACLE_DIR = os.path.dirname(os.path.abspath(oracle.__file__))
@@ -60,6 +61,16 @@ def wrench_pins():
     wpins.test_hanging_box_carries_its_weight()
 
 
+def joint_pins():
+    jpins.test_universal_kinematics()
+    jpins.test_prismatic_kinematics()
+    for t in (1, 2, 3):
+        jpins.test_gradient_away_from_rest(t)
+    for name, asm in jpins.mixed_assemblies():
+        jpins.test_mixed_joints_match_dense_kkt_lu(name, asm)
+    jpins.test_vertical_slider_falls_freely()
+
+
 # (name, text in the oracle, planted replacement, pin that must fail)
 MUTANTS = [
     # Eq. variation_energy: gravity enters the force with its own sign
@@ -97,8 +108,8 @@ MUTANTS = [
     # Sec. 4.3 hinge frame: the second-order Rodrigues term with the wrong sign
     ("hinge_frame_sign", "+ K2[i] / (1.0 + a[1]);", "- K2[i] / (1.0 + a[1]);", hinge_pins),
     # Eq. r_gradient, A-linearised: the rotation term with A's indices transposed
-    ("hinge_rotation_term_transposed", "G[i * 12 + 3 * l + kk] += dRh[comp[i] * 3 + l] * dm[kk];",
-     "G[i * 12 + 3 * kk + l] += dRh[comp[i] * 3 + l] * dm[kk];",
+    ("hinge_rotation_term_transposed", "Ga[i * 12 + 3 * l + kk] += dRh[comp * 3 + l] * dm[kk];",
+     "Ga[i * 12 + 3 * kk + l] += dRh[comp * 3 + l] * dm[kk];",
      vpins.test_hinge_gradient_along_rigid_motions_away_from_rest),
     # the verifier: a dual residual that reads zero
     ("verifier_rho_d_zeroed", "*rho_d = nr > 0.0 ? sqrt(nd / nr) : sqrt(nd);",
@@ -121,6 +132,15 @@ MUTANTS = [
     # Eq. module2-E: E(A)^T with the cross product reversed (E instead of -E)
     ("wrench_moment_sign", "o[1] += a[2] * fc[0] - a[0] * fc[2];", "o[1] -= a[2] * fc[0] - a[0] * fc[2];",
      wrench_pins),
+    # Eq. universal: the fourth row on the wrong local component of the frame
+    ("universal_row_component", "{1, 3, 2}, {0, 0, 2}},  /* universal */",
+     "{2, 3, 2}, {0, 0, 2}},  /* universal */", joint_pins),
+    # Eq. prismatic: the anti-twist point placed along the frame's x instead of z
+    ("prismatic_third_point", "if (type == 3) memcpy(da3, dRh + 6, sizeof da3);",
+     "if (type == 3) memcpy(da3, dRh + 0, sizeof da3);", joint_pins),
+    # Eq. prismatic: the axis rows compare b's second point with a's first
+    ("prismatic_axis_rows", "{0, 3, 2}, {2, 3, 2}, {0, 4, 2}}}; /* prismatic */",
+     "{0, 3, 0}, {2, 3, 2}, {0, 4, 2}}}; /* prismatic */", joint_pins),
     # the joint force taken as +G^T lambda instead of -G^T lambda
     ("wrench_force_sign", "f[12 * (size_t)b + c] -= G[i * 12 + c] * lam[off + i];",
      "f[12 * (size_t)b + c] += G[i * 12 + c] * lam[off + i];", wrench_pins),

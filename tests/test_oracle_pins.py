@@ -286,7 +286,7 @@ def kkt_matrix(asm, s, q, qd, h):
     dyn = [i for i in range(asm.n) if not asm.pinned[i]]
     col = {b: 12 * k for k, b in enumerate(dyn)}
     nq = 12 * len(dyn)
-    rows = [5 if t == 1 else 3 for t in asm.jtype]
+    rows = [mi.JOINT_ROWS[t] for t in asm.jtype]
     nl = sum(rows)
     K = np.zeros((nq + nl, nq + nl)); rhs = np.zeros(nq + nl)
     for b in dyn:
@@ -394,7 +394,7 @@ def test_dual_matrix_structure():
     S = S.toarray()
     assert np.allclose(S, S.T, rtol=0, atol=1e-12 * np.abs(S).max())
     np.linalg.cholesky(S)
-    rows = [5 if t == 1 else 3 for t in asm.jtype]
+    rows = [mi.JOINT_ROWS[t] for t in asm.jtype]
     off = np.concatenate([[0], np.cumsum(rows)])
     for k in range(asm.m):
         for l in range(asm.m):
