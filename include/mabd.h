@@ -69,18 +69,37 @@ typedef struct {
   const double *q0, *qd0;  /* n*12 initial state (qd0 may be NULL: zero)                  */
 } mabd_bodies;
 
-/* m joints.  type 0: ball joint, 3 rows (Eq. ball).  type 1: hinge, 5 rows
-   (Eq. hinge): CP1 of both bodies coincide, CP2 = CP1 + cp_len * axis lies on
-   the axis and only its two off-axis local coordinates are constrained;
-   body a owns the hinge frame R_H = Rod(axis) R_a^T (Sec. 4.3, Eq. r_gradient). */
+/* m joints.  type 0: ball joint, 3 rows (Eq. ball): the points P1 of both
+   bodies coincide.  The other types are rows of a rotated frame owned by body
+   a, R_J = dR R_a^T (R_a the polar rotation of a, dR the joint's frame at
+   rest), each row one local component of R_J (y_X - y_Y) for control points
+   X, Y (Secs. 4.3-4.5; gradient with the A-linearised rotation term of Eq.
+   r_gradient):
+     type 1, hinge, 5 rows (Eq. hinge): dR = Rod(axis) (rows r_x, axis, r_z);
+       P2 = P1 + cp_len * axis on both bodies; rows x, y, z of P1a - P1b and
+       x, z of P2a - P2b;
+     type 2, universal, 4 rows (Eq. universal): dR rows (a1 x a2, a1, a2) for
+       axis = a1 and axis2 = a2 (orthogonal); b's P2 = P1 + cp_len * a2; rows
+       x, y, z of P1a - P1b and y of P2b - P1b (b's second axis stays normal
+       to a's first);
+     type 3, prismatic, 5 rows (Eq. prismatic): dR = Rod(axis); b's P2 = P1 +
+       cp_len * axis and P3 = P1 + cp_len * n, n the frame's local z at rest;
+       rows x, z of P1a - P1b, x, z of P2b - P1b and x of P3b - P1b (b slides
+       along the axis and may not turn).
+   Directions given in a's rest frame enter b's as the same world direction
+   at creation.  The paper's six-row linear hinge (an edge-edge constraint)
+   is two ball joints at the two points of its axis. */
 typedef struct {
   int32_t m;
-  const uint8_t *type;     /* m    0 ball, 1 hinge                                        */
+  const uint8_t *type;     /* m    0 ball, 1 hinge, 2 universal, 3 prismatic             */
   const int32_t *a, *b;    /* m    body indices, -1 = world; a != b; one side dynamic      */
-  const double *pa, *pb;   /* m*3  CP1 in the rest frame of a / b (world coords if -1)    */
-  const double *axis;      /* m*3  hinge axis in a's rest frame (world if a = -1); may be
-                                   NULL if there is no hinge                              */
-  const double *cp_len;    /* m    CP1 -> CP2 spacing (> 0 for hinges; may be NULL)       */
+  const double *pa, *pb;   /* m*3  P1 in the rest frame of a / b (world coords if -1)     */
+  const double *axis;      /* m*3  hinge / prismatic axis, universal a1, in a's rest frame
+                                   (world if a = -1); may be NULL if all joints are balls */
+  const double *cp_len;    /* m    spacing of the further control points (> 0 except for
+                                   ball joints; may be NULL if all joints are balls)      */
+  const double *axis2;     /* m*3  universal a2, orthogonal to axis (a's rest frame);
+                                   may be NULL if there is no universal joint            */
 } mabd_joints;
 
 typedef struct {
@@ -140,7 +159,8 @@ typedef struct {
      refinement's (chains, precision 1), and -1 / 0 where nothing evaluated them */
   double rho_p, rho_d;     /* |H^-1 r_p|/|H^-1 f_A|, |r_d|/|G H^-1 f_A + C|                */
   double kkt;              /* max(rho_p, rho_d)                                           */
-  double c_ball, c_hinge;  /* max |C| at the new state per joint type (diagnostics bit 0) */
+  double c_ball, c_hinge;  /* max |C| at the new state of the ball joints and of the other
+                              (rotated-frame) joints (diagnostics bit 0)                 */
   int32_t ir_sweeps;       /* refinement sweeps of the last step (precision 1)           */
   int32_t warm_accepted;   /* 1 if the GNN warm start was kept                            */
   int32_t n_chain, n_tree, n_graph;  /* components per solver class                     */

@@ -46,7 +46,7 @@ class Joints(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32),
                 ("type", ctypes.c_void_p), ("a", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("pa", ctypes.c_void_p), ("pb", ctypes.c_void_p), ("axis", ctypes.c_void_p),
-                ("cp_len", ctypes.c_void_p)]
+                ("cp_len", ctypes.c_void_p), ("axis2", ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
@@ -154,13 +154,13 @@ class Context:
                     pinned=_c(asm.pinned, u8), q0=_c(asm.q0, f64), qd0=_c(asm.qd0, f64),
                     type=_c(asm.jtype, u8), a=_c(asm.ja, i32), b=_c(asm.jb, i32),
                     pa=_c(asm.pa, f64), pb=_c(asm.pb, f64), axis=_c(asm.axis, f64),
-                    cp_len=_c(asm.cp_len, f64))
+                    cp_len=_c(asm.cp_len, f64), axis2=_c(getattr(asm, "axis2", None), f64))
         self._keep.append(arrs)
         p = lambda x: None if x is None else x.ctypes.data
         B = Bodies(asm.n, p(arrs["dims"]), p(arrs["density"]), p(arrs["k_orth"]),
                    p(arrs["poisson"]), p(arrs["pinned"]), p(arrs["q0"]), p(arrs["qd0"]))
         J = Joints(asm.m, p(arrs["type"]), p(arrs["a"]), p(arrs["b"]), p(arrs["pa"]),
-                   p(arrs["pb"]), p(arrs["axis"]), p(arrs["cp_len"]))
+                   p(arrs["pb"]), p(arrs["axis"]), p(arrs["cp_len"]), p(arrs["axis2"]))
         opts.setdefault("gravity", tuple(asm.gravity))
         opts.setdefault("material", asm.material)
         if stream is not None:

@@ -5,16 +5,39 @@
 namespace mabd {
 
 // One joint in the generic path.  Side a/b: solver-order dynamic body index,
-// or -1 when that side is the world or a pinned body, in which case p1*/p2*
-// hold the constant world positions of its control points.
+// or -1 when that side is the world or a pinned body, in which case p1*/p2*/p3b
+// hold the constant world positions of its control points.  Joints other than
+// the ball are rows of one rotated frame R_J = dR R_a^T owned by side a.
 struct GJoint {
-  int32_t type;       // 0 ball (3 rows), 1 hinge (5 rows)
-  int32_t flags;      // bit0: hinge frame owner (side a) is static -> dR holds R_H itself
+  int32_t type;       // 0 ball (3 rows), 1 hinge (5), 2 universal (4), 3 prismatic (5)
+  int32_t flags;      // bit0: the frame owner (side a) is static -> dR holds R_J itself
   int32_t sa, sb;
-  double p1a[3], p1b[3];  // CP1 (rest frame of the side's body, or world)
-  double p2a[3], p2b[3];  // CP2 for hinges
-  double dR[9];           // dR_H = Rod(axis) (rows r_x, a, r_z), or constant R_H
+  double p1a[3], p1b[3];  // P1 (rest frame of the side's body, or world)
+  double p2a[3], p2b[3];  // P2: hinge (both sides), universal and prismatic (side b)
+  double p3b[3];          // P3 of side b: prismatic
+  double dR[9];           // the joint's frame at rest (hinge, prismatic: Rod(axis),
+                          // rows r_x, axis, r_z; universal: rows a1 x a2, a1, a2),
+                          // or the constant R_J of a static owner
 };
+
+// constraint rows per joint type (Eqs. ball, hinge, universal, prismatic)
+__host__ __device__ inline int joint_rows(int type) { return type == 0 ? 3 : (type == 2 ? 4 : 5); }
+
+// Rows of the rotated-frame joints: row i is local component comp of
+// R_J (y_X - y_Y), y the world position of a control point; points 0 P1 of a,
+// 1 P2 of a, 2 P1 of b, 3 P2 of b, 4 P3 of b (Secs. 4.3-4.5).
+struct JointRow { int8_t comp, x, y; };
+__host__ __device__ inline JointRow joint_row(int type, int i) {
+  // hinge: x y z of P1a - P1b, x z of P2a - P2b
+  // universal: x y z of P1a - P1b, y of P2b - P1b
+  // prismatic: x z of P1a - P1b, x z of P2b - P1b, x of P3b - P1b
+  constexpr int8_t T[3][5][3] = {{{0, 0, 2}, {1, 0, 2}, {2, 0, 2}, {0, 1, 3}, {2, 1, 3}},
+                                 {{0, 0, 2}, {1, 0, 2}, {2, 0, 2}, {1, 3, 2}, {0, 0, 2}},
+                                 {{0, 0, 2}, {2, 0, 2}, {0, 3, 2}, {2, 3, 2}, {0, 4, 2}}};
+  const int8_t *r = T[type - 1][i];
+  return JointRow{r[0], r[1], r[2]};
+}
+__host__ __device__ inline int point_side(int p) { return p >= 2 ? 1 : 0; }
 
 constexpr int GJ_FLAG_STATIC_OWNER = 1;
 
@@ -26,13 +49,13 @@ enum { GL_C = 0, GL_LA = 8, GL_LB = 68 };
 constexpr int GT_STRIDE = 64;
 enum { GT_SIG = 0, GT_RHO = 25, GT_A = 30, GT_E = 35 };
 
-// absorbed-joint entry of a tree body: joint index << 3 | hinge << 2 | side << 1
-// | unary (the hinge bit gives the joint's rows, 5 or 3, without a lookup)
-inline int32_t abs_pack(int32_t k, int hinge, int side, int unary) {
-  return (k << 3) | (hinge << 2) | (side << 1) | unary;
+// absorbed-joint entry of a tree body: joint index << 4 | (rows - 3) << 2 |
+// side << 1 | unary (the joint's rows, 3 to 5, without a lookup)
+inline int32_t abs_pack(int32_t k, int rows, int side, int unary) {
+  return (k << 4) | ((rows - 3) << 2) | (side << 1) | unary;
 }
-__host__ __device__ inline int abs_joint(int32_t t) { return t >> 3; }
-__host__ __device__ inline int abs_rows(int32_t t) { return (t & 4) ? 5 : 3; }
+__host__ __device__ inline int abs_joint(int32_t t) { return t >> 4; }
+__host__ __device__ inline int abs_rows(int32_t t) { return 3 + ((t >> 2) & 3); }
 
 constexpr int TEAM = 16;              // lanes per body in the tree elimination
 constexpr int TREE_KLDS = 16;         // cliques up to this many rows are factored in LDS

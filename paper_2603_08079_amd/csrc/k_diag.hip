@@ -84,7 +84,7 @@ __global__ __launch_bounds__(DNT) void gdiag_body_kernel(
     for (int e = inc_off[b]; e < inc_off[b + 1]; ++e) {
       const int ent = inc[e];
       const int k = ent >> 1, side = ent & 1;
-      const int rows = J[k].type ? 5 : 3;
+      const int rows = joint_rows(J[k].type);
       const double *L = gl + (int64_t)GL_STRIDE * k + (side ? GL_LB : GL_LA);
       for (int rr = 0; rr < rows; ++rr) {
         const double lr = glam[5 * (int64_t)k + rr];
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(DNT) void gdiag_joint_kernel(
   double v[DIAG_PART] = {0, 0, 0, 0, 0, 0};
   if (k < m && !skip_step(status, 0)) {
     const GJoint j = J[k];
-    const int rows = j.type ? 5 : 3;
+    const int rows = joint_rows(j.type);
     const double *G = gl + (int64_t)GL_STRIDE * k;
     double rd[5], rr[5];
     for (int i = 0; i < rows; ++i) rd[i] = rr[i] = G[GL_C + i];
@@ -152,21 +152,20 @@ __global__ __launch_bounds__(DNT) void gdiag_joint_kernel(
       v[2] += rr[i] * rr[i];
       v[3] += rd[i] * rd[i];
     }
-    // joint values at the new state (Eq. ball; Eq. hinge with R_H from the
-    // polar rotation of side a's new affine block)
+    // joint values at the new state (Eq. ball; Eqs. hinge, universal,
+    // prismatic with R_J from the polar rotation of side a's new affine block)
     auto point_diff = [&](const double *pa_, const double *pb_, double *d) {
       double wa[3], wb[3];
       mat3_vec(An[0], pa_, wa);
       mat3_vec(An[1], pb_, wb);
       for (int i = 0; i < 3; ++i) d[i] = (tn[0][i] - tn[1][i]) + (wa[i] - wb[i]);
     };
-    double d1[3];
-    point_diff(j.p1a, j.p1b, d1);
     if (j.type == 0) {
+      double d1[3];
+      point_diff(j.p1a, j.p1b, d1);
       v[4] = fmax(fabs(d1[0]), fmax(fabs(d1[1]), fabs(d1[2])));
     } else {
-      double d2[3], RH[9], e1[3], e2[3];
-      point_diff(j.p2a, j.p2b, d2);
+      double RH[9];
       if (j.flags & GJ_FLAG_STATIC_OWNER) {
         for (int i = 0; i < 9; ++i) RH[i] = j.dR[i];
       } else {
@@ -175,9 +174,19 @@ __global__ __launch_bounds__(DNT) void gdiag_joint_kernel(
           for (int i = 0; i < 9; ++i) Ra[i] = (i % 4 == 0) ? 1.0 : 0.0;
         mat3_mul_bt(j.dR, Ra, RH);
       }
-      mat3_vec(RH, d1, e1);
-      mat3_vec(RH, d2, e2);
-      v[5] = fmax(fmax(fabs(e1[0]), fabs(e1[1])), fmax(fabs(e1[2]), fmax(fabs(e2[0]), fabs(e2[2]))));
+      const double *P[5] = {j.p1a, j.p2a, j.p1b, j.p2b, j.p3b};
+      for (int i = 0; i < rows; ++i) {
+        const JointRow jr = joint_row(j.type, i);
+        double d[3];
+        if (point_side(jr.x) != point_side(jr.y)) {
+          point_diff(P[jr.x], P[jr.y], d);
+        } else {
+          const double dp[3] = {P[jr.x][0] - P[jr.y][0], P[jr.x][1] - P[jr.y][1], P[jr.x][2] - P[jr.y][2]};
+          mat3_vec(An[point_side(jr.x)], dp, d);
+        }
+        const double *rh = RH + 3 * jr.comp;
+        v[5] = fmax(v[5], fabs(rh[0] * d[0] + rh[1] * d[1] + rh[2] * d[2]));
+      }
     }
   }
   block_partials(v, part + DIAG_PART * (int64_t)blockIdx.x);
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(DNT) void gwrench_kernel(int b0, int b1, const doub
   for (int e = inc_off[b]; e < inc_off[b + 1]; ++e) {
     const int ent = inc[e];
     const int k = ent >> 1, side = ent & 1;
-    const int rows = J[k].type ? 5 : 3;
+    const int rows = joint_rows(J[k].type);
     const double *L = gl + (int64_t)GL_STRIDE * k + (side ? GL_LB : GL_LA);
     for (int r = 0; r < rows; ++r) {
       const double l = glam[5 * (int64_t)k + r];

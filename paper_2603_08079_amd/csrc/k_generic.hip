@@ -84,10 +84,12 @@ __global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double
 
 // ------------------------------------------------------- (b) generic joints
 // Constraint value C and the local-frame gradients L = G diag4(R) of both
-// sides (Eq. ball; Eq. hinge with Eqs. pcpq, pcpr, r_gradient).  For a ball
-// end L = s R J(p); for the hinge frame owner L = S_H diag2(dR_H)[J(p1); J(p2)]
-// plus the A-linearised rotation term (rbar_c (x) R_a^T d_m) on the A columns;
-// for the other side L = -S_H diag2(R_H R_b)[J(p1); J(p2)].
+// sides (Eq. ball; Eqs. hinge, universal, prismatic with Eqs. pcpq, pcpr,
+// r_gradient).  For a ball end L = s R J(p).  A rotated-frame joint's row is
+// component comp of R_J (y_X - y_Y): on the frame owner a its frozen part is
+// dR_comp J(p) for a's points, plus the A-linearised rotation term
+// (dR_comp (x) R_a^T d) on the A columns; on side b it is (R_J R_b)_comp J(p)
+// for b's points (with the signs of X and Y).
 __global__ __launch_bounds__(128) void gjoint_kernel(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns,
                               int hinge_grad, double *gl) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -134,52 +136,55 @@ __global__ __launch_bounds__(128) void gjoint_kernel(int m, const GJoint *J, con
     }
     return;
   }
-  double d1[3], d2[3];
-  point_diff(j.p1a, j.p1b, d1);
-  point_diff(j.p2a, j.p2b, d2);
+  // rotated-frame joints (hinge, universal, prismatic; Secs. 4.3-4.5): row i
+  // is component comp of R_J (y_X - y_Y) with R_J = dR R_a^T
   double RH[9];
   if (j.flags & GJ_FLAG_STATIC_OWNER) {
     for (int i = 0; i < 9; ++i) RH[i] = j.dR[i];
   } else {
-    mat3_mul_bt(j.dR, Ra, RH);  // R_H = dR_H R_a^T
+    mat3_mul_bt(j.dR, Ra, RH);  // R_J = dR R_a^T
   }
-  double e1[3], e2[3];
-  mat3_vec(RH, d1, e1);
-  mat3_vec(RH, d2, e2);
-  out[GL_C + 0] = e1[0]; out[GL_C + 1] = e1[1]; out[GL_C + 2] = e1[2];
-  out[GL_C + 3] = e2[0]; out[GL_C + 4] = e2[2];
-  const int cpi[5] = {0, 0, 0, 1, 1};
-  const int comp[5] = {0, 1, 2, 0, 2};
-  if (da) {
-    // frozen part: dR_H rows times J(p_m)
-    double *L = out + GL_LA;
-    double Rtd[2][3];
-    mat3t_vec(Ra, d1, Rtd[0]);
-    mat3t_vec(Ra, d2, Rtd[1]);
-    for (int i = 0; i < 5; ++i) {
-      const double *p = cpi[i] == 0 ? j.p1a : j.p2a;
-      const double *rr = j.dR + 3 * comp[i];
-      for (int jj = 0; jj < 3; ++jj) {
-        for (int c = 0; c < 3; ++c) L[12 * i + 3 * c + jj] = rr[jj] * p[c];
-        L[12 * i + 9 + jj] = rr[jj];
-      }
-      if (hinge_grad == 0) {
-        const double *w = Rtd[cpi[i]];
-        for (int l = 0; l < 3; ++l)
-          for (int kk = 0; kk < 3; ++kk) L[12 * i + 3 * l + kk] += rr[l] * w[kk];
-      }
+  double Q[9];  // R_J R_b: rows of side b's local-frame gradient
+  if (db) mat3_mul(RH, Rb, Q);
+  const double *P[5] = {j.p1a, j.p2a, j.p1b, j.p2b, j.p3b};
+  const int rows = joint_rows(j.type);
+  double *La = out + GL_LA, *Lb = out + GL_LB;
+  for (int i = 0; i < rows; ++i) {
+    const JointRow jr = joint_row(j.type, i);
+    // y_X - y_Y: across the joint translation difference first; on one body
+    // its affine block times the difference of the rest points
+    double d[3];
+    if (point_side(jr.x) != point_side(jr.y)) {
+      point_diff(P[jr.x], P[jr.y], d);
+    } else {
+      const double dp[3] = {P[jr.x][0] - P[jr.y][0], P[jr.x][1] - P[jr.y][1], P[jr.x][2] - P[jr.y][2]};
+      mat3_vec(point_side(jr.x) ? Ab : Aa, dp, d);
     }
-  }
-  if (db) {
-    double Q[9];
-    mat3_mul(RH, Rb, Q);
-    double *L = out + GL_LB;
-    for (int i = 0; i < 5; ++i) {
-      const double *p = cpi[i] == 0 ? j.p1b : j.p2b;
-      const double *rr = Q + 3 * comp[i];
-      for (int jj = 0; jj < 3; ++jj) {
-        for (int c = 0; c < 3; ++c) L[12 * i + 3 * c + jj] = -rr[jj] * p[c];
-        L[12 * i + 9 + jj] = -rr[jj];
+    const double *rh = RH + 3 * jr.comp;
+    out[GL_C + i] = rh[0] * d[0] + rh[1] * d[1] + rh[2] * d[2];
+    for (int side = 0; side < 2; ++side) {
+      if (side == 0 ? !da : !db) continue;
+      double *L = (side == 0 ? La : Lb) + 12 * i;
+      // frozen frame: the rotated row times J(p) in the side's local frame
+      // (dR row on side a, since J(p) diag4(R_a) = R_a J(p); (R_J R_b) row on b)
+      const double *rr = side == 0 ? j.dR + 3 * jr.comp : Q + 3 * jr.comp;
+      for (int c = 0; c < 12; ++c) L[c] = 0.0;
+      for (int pt = 0; pt < 2; ++pt) {
+        const int id = pt == 0 ? jr.x : jr.y;
+        if (point_side(id) != side) continue;
+        const double sg = pt == 0 ? 1.0 : -1.0;
+        for (int jj = 0; jj < 3; ++jj) {
+          for (int c = 0; c < 3; ++c) L[3 * c + jj] += sg * rr[jj] * P[id][c];
+          L[9 + jj] += sg * rr[jj];
+        }
+      }
+      if (side == 0 && hinge_grad == 0) {
+        // A-linearised rotation term of the frame owner (Eqs. pcpr,
+        // r_gradient): dR_comp (x) R_a^T d on a's A columns
+        double w[3];
+        mat3t_vec(Ra, d, w);
+        for (int l = 0; l < 3; ++l)
+          for (int kk = 0; kk < 3; ++kk) L[3 * l + kk] += rr[l] * w[kk];
       }
     }
   }
@@ -267,7 +272,7 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
         un = t & 1;
       } else {
         k = kpar;
-        rows = ptype ? 5 : 3;
+        rows = joint_rows(ptype);
         side = pk & 1;
         un = 1;  // parent rows take C_k only
       }
@@ -1121,10 +1126,13 @@ DEV void tcw_compress_back_body(const TreeArgs &a, const GJoint *J, int op0, int
   }
   if (ln < 5) a.glam[5 * (int64_t)op.e + ln] = ln < ce ? le[ln] : 0.0;
   // v's private rows, boundary [e; kcur]
-  double lb[10];  // [lambda_e; lambda_kcur], e has 3 or 5 rows
+  double lb[10];  // [lambda_e; lambda_kcur], e has 3, 4 or 5 rows
   if (ce == 3) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) lb[r] = r < 3 ? le[r] : (r < 8 ? lk[r - 3] : 0.0);
+  } else if (ce == 4) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) lb[r] = r < 4 ? le[r] : (r < 9 ? lk[r - 4] : 0.0);
   } else {
 #pragma unroll
     for (int r = 0; r < 10; ++r) lb[r] = r < 5 ? le[r] : lk[r - 5];
@@ -1201,7 +1209,7 @@ __global__ __launch_bounds__(256) void gapply_kernel(int b0, int b1, const int32
   for (int e = inc_off[b]; e < inc_off[b + 1]; ++e) {
     const int ent = inc[e];
     const int k = ent >> 1, side = ent & 1;
-    const int c = J[k].type ? 5 : 3;
+    const int c = joint_rows(J[k].type);
     const double *L = gl + (int64_t)GL_STRIDE * k + (side ? GL_LB : GL_LA);
     for (int r = 0; r < c; ++r) {
       const double lr = glam[5 * (int64_t)k + r];

@@ -23,7 +23,7 @@ namespace mabd {
 
 constexpr int PCG_THREADS = 256;
 
-DEV int jrows(const GJoint *J, int k) { return J[k].type ? 5 : 3; }
+DEV int jrows(const GJoint *J, int k) { return joint_rows(J[k].type); }
 
 // block-level sum of a per-thread value, result valid in thread 0
 DEV double block_sum(double v, double *sh) {
@@ -64,7 +64,7 @@ DEV void body_pass(const PcgArgs &a, const double *x, int tid, int nth) {
 // y_k = sum_b L_kb z_b
 DEV void joint_pass_one(const PcgArgs &a, int k, double *y) {
   const GJoint &j = a.J[k];
-  const int c = j.type ? 5 : 3;
+  const int c = joint_rows(j.type);
   for (int rr = 0; rr < 5; ++rr) y[rr] = 0.0;
   for (int side = 0; side < 2; ++side) {
     const int64_t b = side ? j.sb : j.sa;
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(PCG_THREADS) void pcg_kernel(PcgArgs a) {
   for (int k = tid; k < a.mj; k += nth) {
     if (!a.jmask[k]) continue;
     const GJoint &j = a.J[k];
-    const int c = j.type ? 5 : 3;
+    const int c = joint_rows(j.type);
     double D[25];
     for (int i = 0; i < 25; ++i) D[i] = 0.0;
     for (int side = 0; side < 2; ++side) {
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(PCG_THREADS) void pcg_kernel(PcgArgs a) {
   for (int k = tid; k < a.mj; k += nth) {
     if (!a.jmask[k]) continue;
     const GJoint &j = a.J[k];
-    const int c = j.type ? 5 : 3;
+    const int c = joint_rows(j.type);
     double bk[5];
     for (int rr = 0; rr < c; ++rr) bk[rr] = a.gl[(int64_t)GL_STRIDE * k + GL_C + rr];
     for (int side = 0; side < 2; ++side) {

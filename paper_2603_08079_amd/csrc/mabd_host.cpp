@@ -563,19 +563,29 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   for (int k = 0; k < m; ++k) {
     const int a = Jn->a[k], b = Jn->b[k];
     const std::string jk = "joint " + std::to_string(k) + ": ";
-    if (Jn->type[k] > 1) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "type must be 0 or 1");
+    if (Jn->type[k] > 3) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "type must be 0, 1, 2 or 3");
     if (a < -1 || a >= n || b < -1 || b >= n) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "body index");
     if (a == b) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "a == b");
     if (!dyn(a) && !dyn(b)) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "no dynamic side");
     if (!finite_all(Jn->pa + 3 * k, 3) || !finite_all(Jn->pb + 3 * k, 3))
       return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "anchor not finite");
-    if (Jn->type[k] == 1) {
-      if (!Jn->axis || !Jn->cp_len) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "hinge needs axis, cp_len");
+    if (Jn->type[k] != 0) {
+      if (!Jn->axis || !Jn->cp_len)
+        return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "hinge, universal and prismatic joints need axis, cp_len");
       const double *ax = Jn->axis + 3 * k;
       double nrm = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
       if (!(nrm > 1e-12) || !std::isfinite(nrm)) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "zero hinge axis");
       if (!(Jn->cp_len[k] > 0) || !std::isfinite(Jn->cp_len[k]))
         return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "cp_len must be > 0");
+      if (Jn->type[k] == 2) {
+        if (!Jn->axis2) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "universal joint needs axis2");
+        const double *a2 = Jn->axis2 + 3 * k;
+        const double n2 = std::sqrt(a2[0] * a2[0] + a2[1] * a2[1] + a2[2] * a2[2]);
+        if (!(n2 > 1e-12) || !std::isfinite(n2)) return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "zero axis2");
+        const double cs = (ax[0] * a2[0] + ax[1] * a2[1] + ax[2] * a2[2]) / (nrm * n2);
+        if (!(std::fabs(cs) <= 1e-6))
+          return fail(nullptr, MABD_ERR_INVALID_ARG, jk + "axis2 must be orthogonal to axis");
+      }
     }
   }
 
@@ -589,7 +599,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (B->qd0) c->qd0_in.assign(B->qd0, B->qd0 + (size_t)12 * n);
   c->jtype.assign(Jn ? Jn->type : nullptr, Jn ? Jn->type + m : nullptr);
   c->jrow_off.resize(m + 1, 0);
-  for (int k = 0; k < m; ++k) c->jrow_off[k + 1] = c->jrow_off[k] + (c->jtype[k] ? 5 : 3);
+  for (int k = 0; k < m; ++k) c->jrow_off[k + 1] = c->jrow_off[k] + joint_rows(c->jtype[k]);
   c->nrows_total = c->jrow_off[m];
 
   // ------------------------------------------------------------ components
@@ -803,12 +813,12 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
           if (parent_joint.count(b) && parent_joint[b] == k) continue;
           const int side = Jn->a[k] == b ? 0 : 1;
           const bool unary = !dyn(Jn->a[k]) || !dyn(Jn->b[k]);
-          if (unary) unary_rows += Jn->type[k] ? 5 : 3;
-          c->tabs.push_back(abs_pack(gidx[k], Jn->type[k] ? 1 : 0, side, unary ? 1 : 0));
+          if (unary) unary_rows += joint_rows(Jn->type[k]);
+          c->tabs.push_back(abs_pack(gidx[k], joint_rows(Jn->type[k]), side, unary ? 1 : 0));
         }
         int ne = 0;
         for (int e = c->tabs_off.back(); e < (int)c->tabs.size(); ++e) ne += abs_rows(c->tabs[e]);
-        const int nr = ne + (pk >= 0 ? (Jn->type[parent_joint[b]] ? 5 : 3) : 0);
+        const int nr = ne + (pk >= 0 ? joint_rows(Jn->type[parent_joint[b]]) : 0);
         if (nr > TREE_KMAX) {
           delete c;
           return fail(nullptr, MABD_ERR_TOPOLOGY, "a tree body has more than 64 joint rows around it");
@@ -841,7 +851,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       const int other = Jn->a[kin] == me ? Jn->b[kin] : Jn->a[kin];
       par[s] = slot_of[c->in2sol[other]];
       kcur[s] = pk >> 1;
-      ckcur[s] = Jn->type[kin] ? 5 : 3;
+      ckcur[s] = joint_rows(Jn->type[kin]);
       kids[par[s]].push_back(s);
     }
     // slots are stored leaves first (by height): parents come after children
@@ -936,7 +946,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     for (int s = 0; s < nsl; ++s) {
       const int LD = c->tne[s] + 5;
       const int pk = c->tpk[s];
-      const int nr0 = c->tne[s] + (pk >= 0 ? (Jn->type[c->gj_in[pk >> 1]] ? 5 : 3) : 0);
+      const int nr0 = c->tne[s] + (pk >= 0 ? joint_rows(Jn->type[c->gj_in[pk >> 1]]) : 0);
       c->foff.push_back(c->fac_size);
       c->fac_size += (int64_t)LD * LD + LD + (nr0 > TREE_KLDS ? 24 * (int64_t)nr0 : 0);
     }
@@ -1007,7 +1017,12 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     else world_point(a, pa, g.p1a);
     if (g.sb >= 0) std::memcpy(g.p1b, pb, sizeof g.p1b);
     else world_point(b, pb, g.p1b);
-    if (g.type == 1) {
+    if (g.type != 0) {
+      // rotated-frame joints: the frame dR at rest and the further control
+      // points (hinge: P2 on both sides along the axis; universal: b's P2
+      // along a2; prismatic: b's P2 along the axis and P3 along the frame's
+      // local z); a direction fixed in a's rest frame enters b's rest frame
+      // as the same world direction at creation
       double ax[3];
       std::memcpy(ax, Jn->axis + 3 * k, sizeof ax);
       const double nrm = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
@@ -1021,26 +1036,54 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       };
       rot0(a, Ra0);
       rot0(b, Rb0);
-      double wax[3], axb[3];
-      mat3_vec_h(Ra0, ax, wax);
-      if (b >= 0) mat3t_vec_h(Rb0, wax, axb);
-      else std::memcpy(axb, wax, sizeof axb);
+      double dR[9];
+      if (g.type == 2) {
+        double a2[3];
+        std::memcpy(a2, Jn->axis2 + 3 * k, sizeof a2);
+        const double dt = ax[0] * a2[0] + ax[1] * a2[1] + ax[2] * a2[2];
+        for (int i = 0; i < 3; ++i) a2[i] -= dt * ax[i];
+        const double n2 = std::sqrt(a2[0] * a2[0] + a2[1] * a2[1] + a2[2] * a2[2]);
+        for (double &v : a2) v /= n2;
+        const double x[3] = {ax[1] * a2[2] - ax[2] * a2[1], ax[2] * a2[0] - ax[0] * a2[2],
+                             ax[0] * a2[1] - ax[1] * a2[0]};
+        for (int i = 0; i < 3; ++i) {
+          dR[i] = x[i];
+          dR[3 + i] = ax[i];
+          dR[6 + i] = a2[i];
+        }
+      } else {
+        hinge_rod(ax, dR);
+      }
+      auto in_b = [&](const double *dir_a, double *dir_b) {
+        double w[3];
+        mat3_vec_h(Ra0, dir_a, w);
+        if (b >= 0) mat3t_vec_h(Rb0, w, dir_b);
+        else std::memcpy(dir_b, w, sizeof w);
+      };
+      const double zero[3] = {0.0, 0.0, 0.0};
+      double db2[3], db3[3];
+      in_b(g.type == 2 ? dR + 6 : ax, db2);
+      in_b(g.type == 3 ? dR + 6 : zero, db3);
       const double ell = Jn->cp_len[k];
-      double p2a[3], p2b[3];
+      double p2a[3], p2b[3], p3b[3];
       for (int i = 0; i < 3; ++i) {
         p2a[i] = pa[i] + ell * ax[i];
-        p2b[i] = pb[i] + ell * axb[i];
+        p2b[i] = pb[i] + ell * db2[i];
+        p3b[i] = pb[i] + ell * db3[i];
       }
       if (g.sa >= 0) std::memcpy(g.p2a, p2a, sizeof p2a);
       else world_point(a, p2a, g.p2a);
-      if (g.sb >= 0) std::memcpy(g.p2b, p2b, sizeof p2b);
-      else world_point(b, p2b, g.p2b);
-      double dR[9];
-      hinge_rod(ax, dR);
+      if (g.sb >= 0) {
+        std::memcpy(g.p2b, p2b, sizeof p2b);
+        std::memcpy(g.p3b, p3b, sizeof p3b);
+      } else {
+        world_point(b, p2b, g.p2b);
+        world_point(b, p3b, g.p3b);
+      }
       if (g.sa >= 0) {
         std::memcpy(g.dR, dR, sizeof dR);
       } else {
-        // static frame owner: R_H = dR_H R_a0^T is constant
+        // static frame owner: R_J = dR R_a0^T is constant
         for (int r = 0; r < 3; ++r)
           for (int cc = 0; cc < 3; ++cc)
             g.dR[3 * r + cc] = dR[3 * r] * Ra0[3 * cc] + dR[3 * r + 1] * Ra0[3 * cc + 1] +
@@ -2091,7 +2134,7 @@ mabd_status mabd_multipliers(const mabd_ctx *cc, double *lam) {
   }
   for (size_t gk = 0; gk < c->gj.size(); ++gk) {
     const int k = c->gj_in[gk];
-    const int rk = c->jtype[k] ? 5 : 3;
+    const int rk = joint_rows(c->jtype[k]);
     for (int i = 0; i < rk; ++i) lam[c->jrow_off[k] + i] = gl[5 * gk + i];
   }
   return MABD_OK;

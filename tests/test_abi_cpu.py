@@ -72,6 +72,13 @@ def test_invalid_inputs_are_rejected_before_device_work():
     _expect(base, pk.ERR_INVALID_ARG, hinge_grad=1)
     assert "precision" in _expect(base, pk.ERR_INVALID_ARG, precision=2)
     assert "ir_max_sweeps" in _expect(base, pk.ERR_INVALID_ARG, precision=1, ir_max_sweeps=-1)
+    u = mi.mix_joint_types(mi.chain(5, seed=1), seed=2, probs=(0, 0, 1, 0))
+    a = u.copy(); a.axis2[2] = a.axis[2]
+    assert "orthogonal" in _expect(a, pk.ERR_INVALID_ARG)
+    a = u.copy(); a.axis2 = None
+    assert "axis2" in _expect(a, pk.ERR_INVALID_ARG)
+    a = u.copy(); a.jtype[1] = 4
+    assert "type" in _expect(a, pk.ERR_INVALID_ARG)
 
 
 def test_missing_library_fails_loudly():
