@@ -73,6 +73,7 @@ class _Sys(ctypes.Structure):
         ("newton_iters", ctypes.c_int32),
         ("wrench", ctypes.c_void_p),
         ("axis2", ctypes.c_void_p),
+        ("body_solve", ctypes.c_int32),
     ]
 
 
@@ -145,7 +146,7 @@ class System:
     """Holds contiguous copies of an assembly's arrays and the C struct."""
 
     def __init__(self, asm, material: Optional[int] = None, hinge_grad: int = 0,
-                 newton_iters: int = 1, gravity=None, wrench=None, L=None):
+                 newton_iters: int = 1, gravity=None, wrench=None, L=None, body_solve: int = 0):
         # L: an oracle library loaded with load() (the same source built for
         # the host, for the CPU baseline timing); default: the test build
         self.L = lib() if L is None else L
@@ -178,6 +179,7 @@ class System:
         s.material = asm.material if material is None else material
         s.hinge_grad = hinge_grad
         s.newton_iters = newton_iters
+        s.body_solve = body_solve
         self.s = s
         self.rows = self.L.ora_rows(ctypes.byref(s))
 
@@ -301,7 +303,8 @@ def polar(A):
 def run(asm, steps=None, solver=AUTO, **kw):
     """Integrate `steps` steps from the assembly's initial state."""
     sysm = System(asm, **{k: v for k, v in kw.items() if k in ("material", "hinge_grad",
-                                                                "newton_iters", "gravity", "wrench")})
+                                                                "newton_iters", "gravity", "wrench",
+                                                                "body_solve")})
     q, qd = asm.q0.copy(), asm.qd0.copy()
     diags = []
     for _ in range(asm.steps if steps is None else steps):

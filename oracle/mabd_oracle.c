@@ -1154,11 +1154,96 @@ static void back_project(const ora_system *s, const stepdata *d, const double *l
 }
 
 /* rho_p = |H^{-1} r_p| / |H^{-1} f|, rho_d = |G dq + C| / |G H^{-1} f + C| */
+/* length-preserving stand-in for a rotation (Eq. len_preserving): M x scaled
+   to the length of x; x itself if M x vanishes */
+static void lenpres(const double *M, int transpose, const double *x, double *y) {
+  if (transpose) mtm(3, 3, 1, M, x, y);
+  else mm(3, 3, 1, M, x, y);
+  double lx = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  double ly = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+  if (ly > 0.0)
+    for (int r = 0; r < 3; ++r) y[r] *= lx / ly;
+  else
+    for (int r = 0; r < 3; ++r) y[r] = x[r];
+}
+
+/* a dynamic body that no joint touches */
+static int unjointed(const ora_system *s, int b) {
+  for (int k = 0; k < s->m; ++k)
+    if (s->ja[k] == b || s->jb[k] == b) return 0;
+  return 1;
+}
+
+/* The polar-free single-body solve of Alg. 1 for body i at the iterate qi:
+   every rotation of a 3-block by R (Eq. polar) is replaced by the
+   length-preserving action of A (Eq. len_preserving): R^T x by A^T x scaled to
+   |x|, R y by A y scaled to |y|.  The forces of the Newton step (inertia,
+   gravity, external wrench; Eq. variation_energy) are taken to the body frame
+   so, the rotated elastic force -V P(R^T A) (Eq. reduced_K) uses the same
+   stand-in for R^T A column by column, the constant Hbar (Eq. abd_final) is
+   solved, and the increment is taken back to the world frame block by
+   block. */
+static int polar_free_dq(const ora_system *s, double h, const double *qi, const double *qn,
+                         const double *qdn, int i, double *dq) {
+  double A[9], Mbar[4], V, m, mu, lam, Hb[144];
+  q_to_A(qi, A);
+  box_mass(s, i, Mbar, &V, &m);
+  lame(s, i, &mu, &lam);
+  hbar(s, i, h, Hb);
+  double w[12];
+  for (int a = 0; a < 12; ++a) {
+    int c = a / 3, r = a % 3;
+    double M = Mbar[c];
+    double fext = (c == 3) ? m * s->gravity[r] : 0.0;
+    w[a] = M * qdn[a] / h - M * (qi[a] - qn[a]) / (h * h) + fext;
+  }
+  if (s->wrench) {
+    const double *tau = s->wrench + 6 * i, *fw = tau + 3;
+    for (int c = 0; c < 3; ++c) {
+      const double *qc = qi + 3 * c;
+      w[3 * c + 0] += 0.5 * (tau[1] * qc[2] - tau[2] * qc[1]);
+      w[3 * c + 1] += 0.5 * (tau[2] * qc[0] - tau[0] * qc[2]);
+      w[3 * c + 2] += 0.5 * (tau[0] * qc[1] - tau[1] * qc[0]);
+    }
+    for (int r = 0; r < 3; ++r) w[9 + r] += fw[r];
+  }
+  /* R^T A column by column, then P of Sec. 3.3 in the body frame */
+  double Sh[9], P[9];
+  for (int c = 0; c < 3; ++c) {
+    double col[3] = {A[c], A[3 + c], A[6 + c]}, x[3];
+    lenpres(A, 1, col, x);
+    for (int r = 0; r < 3; ++r) Sh[r * 3 + c] = x[r];
+  }
+  double tr = Sh[0] + Sh[4] + Sh[8] - 3.0;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      P[r * 3 + c] = mu * (Sh[r * 3 + c] + Sh[c * 3 + r] - 2.0 * (r == c)) + lam * tr * (r == c);
+  double phi[12];
+  for (int k = 0; k < 4; ++k) lenpres(A, 1, w + 3 * k, phi + 3 * k);
+  for (int c = 0; c < 3; ++c)
+    for (int r = 0; r < 3; ++r) phi[3 * c + r] -= V * P[r * 3 + c];
+  double L[144], dp[12];
+  memcpy(L, Hb, sizeof L);
+  if (chol(12, L)) return ORA_ESINGULAR;
+  memcpy(dp, phi, sizeof dp);
+  chol_solve(12, L, dp);
+  for (int k = 0; k < 4; ++k) lenpres(A, 0, dp + 3 * k, dq + 3 * k);
+  for (int a = 0; a < 12; ++a)
+    if (!isfinite(dq[a])) return ORA_ENONFINITE;
+  return ORA_OK;
+}
+
+/* bodies that take the polar-free solve: unjointed dynamic bodies, when asked */
+static int polar_free_body(const ora_system *s, int b) {
+  return s->body_solve == 1 && is_dyn(s, b) && unjointed(s, b);
+}
+
 static void kkt_residual(const ora_system *s, const stepdata *d, const double *lam,
                          const double *dq, double *rho_p, double *rho_d) {
   double np = 0.0, nf = 0.0, nd = 0.0, nr = 0.0;
   for (int b = 0; b < s->n; ++b) {
-    if (!is_dyn(s, b)) continue;
+    /* a polar-free body does not solve the co-rotated system of Eq. kkt */
+    if (!is_dyn(s, b) || polar_free_body(s, b)) continue;
     double rp[12], hf[12];
     mm(12, 12, 1, d->H + 144 * b, dq + 12 * b, rp);
     for (int c = 0; c < 12; ++c) rp[c] -= d->f[12 * b + c];
@@ -1244,6 +1329,9 @@ int32_t ora_step(const ora_system *s, double h, double *q, double *qd, int32_t s
     }
     if (!st || st == ORA_ENOTCONV) {
       back_project(s, &d, lw, dq);
+      for (int b = 0; b < s->n && !st; ++b)
+        if (polar_free_body(s, b))
+          st = polar_free_dq(s, h, qi + 12 * b, qn + 12 * b, qd + 12 * b, b, dq + 12 * b);
       kkt_residual(s, &d, lw, dq, &rp, &rd);
       for (size_t a = 0; a < 12 * n; ++a) {
         qi[a] += dq[a];
@@ -1326,6 +1414,9 @@ int32_t ora_finish(const ora_system *s, double h, const double *q, const double 
   size_t n = s->n;
   double *dq = malloc(sizeof(double) * 12 * (n + 1));
   back_project(s, &d, lam, dq);
+  for (int b = 0; b < s->n && !st; ++b)
+    if (polar_free_body(s, b)) st = polar_free_dq(s, h, q + 12 * b, q + 12 * b, qd + 12 * b, b, dq + 12 * b);
+  if (st) { free(dq); free_sd(&d); return st; }
   double rp, rd;
   kkt_residual(s, &d, lam, dq, &rp, &rd);
   for (size_t b = 0; b < n; ++b)

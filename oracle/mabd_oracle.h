@@ -40,6 +40,8 @@ typedef struct {
   const double *axis2;     /* m*3 universal joints: the second axis a2 (orthogonal
                               to axis, a's rest frame or world if a = -1); NULL if
                               there is no universal joint                          */
+  int32_t body_solve;      /* 0: polar rotation (Eq. polar); 1: bodies without
+                              joints take the polar-free solve of Alg. 1         */
 } ora_system;
 
 /* diag[] slots written by ora_step / ora_finish */

@@ -19,6 +19,7 @@ import test_gnn_ref as gnn_pins
 import test_oracle_pins as pins
 import test_oracle_verifier as vpins
 import test_oracle_joint_pins as jpins
+import test_oracle_polarfree_pins as ppins
 import test_oracle_wrench_pins as wpins
 
 ORACLE_DIR = os.path.dirname(os.path.abspath(oracle.__file__))
@@ -69,6 +70,12 @@ def joint_pins():
     for name, asm in jpins.mixed_assemblies():
         jpins.test_mixed_joints_match_dense_kkt_lu(name, asm)
     jpins.test_vertical_slider_falls_freely()
+
+
+def polar_free_pins():
+    ppins.test_equals_polar_step_for_rotations()
+    ppins.test_equals_polar_step_for_scaled_rotations()
+    ppins.test_free_fall_closed_form()
 
 
 # (name, text in the oracle, planted replacement, pin that must fail)
@@ -141,6 +148,12 @@ MUTANTS = [
     # Eq. prismatic: the axis rows compare b's second point with a's first
     ("prismatic_axis_rows", "{0, 3, 2}, {2, 3, 2}, {0, 4, 2}}}; /* prismatic */",
      "{0, 3, 0}, {2, 3, 2}, {0, 4, 2}}}; /* prismatic */", joint_pins),
+    # Alg. 1: the forces taken to the body frame by A instead of A^T
+    ("polar_free_force_untransposed", "for (int k = 0; k < 4; ++k) lenpres(A, 1, w + 3 * k, phi + 3 * k);",
+     "for (int k = 0; k < 4; ++k) lenpres(A, 0, w + 3 * k, phi + 3 * k);", polar_free_pins),
+    # Eq. len_preserving: the rescaling to the original length dropped
+    ("polar_free_length_dropped", "for (int r = 0; r < 3; ++r) y[r] *= lx / ly;",
+     "for (int r = 0; r < 3; ++r) y[r] *= 1.0;", polar_free_pins),
     # the joint force taken as +G^T lambda instead of -G^T lambda
     ("wrench_force_sign", "f[12 * (size_t)b + c] -= G[i * 12 + c] * lam[off + i];",
      "f[12 * (size_t)b + c] += G[i * 12 + c] * lam[off + i];", wrench_pins),
