@@ -1194,7 +1194,7 @@ static int polar_free_dq(const ora_system *s, double h, const double *qi, const 
   for (int a = 0; a < 12; ++a) {
     int c = a / 3, r = a % 3;
     double M = Mbar[c];
-    double fext = (c == 3) ? m * s->gravity[r] : 0.0;
+    double fext = (c == 3) ? s->gravity[r] * m : 0.0;
     w[a] = M * qdn[a] / h - M * (qi[a] - qn[a]) / (h * h) + fext;
   }
   if (s->wrench) {
