@@ -142,6 +142,14 @@ typedef struct {
                               ~3.9M rows need (both for testing)                         */
   int32_t ir_max_sweeps;   /* precision 1: correction sweeps before NOT_CONVERGED, 0..16,
                               default 4                                                 */
+  int32_t body_solve;      /* 0 (default): every body rotates its forces and increment by
+                              its polar rotation R (Eqs. polar, abd_final); 1: bodies
+                              without joints take the polar-free solve of Alg. 1 instead:
+                              R^T x and R y replaced block by block by A^T x and A y
+                              scaled to the lengths of x and y (Eq. len_preserving),
+                              also in the rotated elastic force.  Exact where A is a
+                              scaled rotation, first order in the deformation otherwise;
+                              such bodies are left out of rho_p (diagnostics)          */
   void *stream;            /* hipStream_t, or NULL for a library-owned stream             */
 } mabd_options;
 

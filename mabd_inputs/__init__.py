@@ -368,6 +368,42 @@ def free_body(dims=(0.1, 0.1, 0.1), density=1000.0, k_orth=1e8, A=None, t=(0.0, 
                     meta=dict(kind="free"))
 
 
+def spinning_boxes(n: int, seed: int = 0, dim_range=(0.05, 0.5), density: float = 1000.0,
+                   k_orth: float = 1e8, omega: float = 5.0, speed: float = 1.0, h: float = 1e-2,
+                   steps: int = 100) -> Assembly:
+    """n unjointed boxes on a grid (1 m pitch), each turned to a uniformly
+    random orientation and moving rigidly: angular velocity N(0, omega^2) per
+    axis, linear velocity N(0, speed^2) per axis (the rigid-body scenes of the
+    single-body comparison, Sec. 6.1, as a batch)."""
+    rng = np.random.default_rng(seed)
+    dims = rng.uniform(dim_range[0], dim_range[1], size=(n, 3))
+    side = int(math.ceil(n ** (1.0 / 3.0)))
+    idx = np.arange(n)
+    centres = np.stack([idx % side, (idx // side) % side, idx // (side * side)], axis=1).astype(float)
+    # uniform rotations from unit quaternions
+    qu = rng.normal(size=(n, 4))
+    qu /= np.linalg.norm(qu, axis=1, keepdims=True)
+    w, x, y, z = qu.T
+    R = np.stack([np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+                  np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+                  np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)],
+                 axis=1)
+    om = rng.normal(0.0, omega, size=(n, 3))
+    v = rng.normal(0.0, speed, size=(n, 3))
+    q0 = np.zeros((n, 12))
+    qd0 = np.zeros((n, 12))
+    for c in range(3):
+        q0[:, 3 * c:3 * c + 3] = R[:, :, c]
+        qd0[:, 3 * c:3 * c + 3] = np.cross(om, R[:, :, c])
+    q0[:, 9:] = centres
+    qd0[:, 9:] = v
+    jt, ja, jb, pa, pb, ax, ell = _joint_arrays(0)
+    return Assembly(name=f"boxes{n}", dims=dims, density=np.full(n, density),
+                    k_orth=np.full(n, k_orth), pinned=np.zeros(n, np.uint8), q0=q0, qd0=qd0,
+                    jtype=jt, ja=ja, jb=jb, pa=pa, pb=pb, axis=ax, cp_len=ell, h=h, steps=steps,
+                    meta=dict(kind="boxes", seed=seed))
+
+
 # The configurations the benchmark and tests run (sizes and settings of the
 # paper-shaped workloads; `small` variants finish on the CPU oracle in seconds).
 def config(name: str, seed: int = 0) -> Assembly:
@@ -383,4 +419,6 @@ def config(name: str, seed: int = 0) -> Assembly:
         return lattice(512, seed=seed, steps=100)
     if name == "rgg100k":
         return rgg(100000, seed=seed, steps=100)
+    if name == "boxes1m":
+        return spinning_boxes(1 << 20, seed=seed, steps=100)
     raise KeyError(name)

@@ -56,7 +56,7 @@ class Options(ctypes.Structure):
                 ("hinge_grad", ctypes.c_int32), ("material", ctypes.c_int32),
                 ("diagnostics", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("ir_max_sweeps", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("body_solve", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 NPHASES = 10

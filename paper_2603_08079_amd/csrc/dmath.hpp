@@ -333,4 +333,75 @@ DEV void local_force(const double *sh, const real *R, const real *A, const real 
   }
 }
 
+// ------------------------------------------------ polar-free body solve
+// Length-preserving stand-in for a rotation (Eq. len_preserving): y = M x
+// (M^T x if transpose) scaled to |x|; x itself if M x vanishes.  M is a
+// row-major 3x3 (the affine block A).
+DEV void lenpres(const double *M, bool transpose, const double *x, double *y) {
+  if (transpose) mat3t_vec(M, x, y);
+  else mat3_vec(M, x, y);
+  const double lx = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  const double ly = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+  if (ly > 0.0) {
+    const double s = lx / ly;
+    y[0] *= s; y[1] *= s; y[2] *= s;
+  } else {
+    y[0] = x[0]; y[1] = x[1]; y[2] = x[2];
+  }
+}
+
+// Body-frame force of the polar-free solve (Alg. 1): the world forces of
+// local_force (inertia, gravity, wrench) taken to the body frame block by
+// block with A^T scaled to length instead of R^T, and the rotated elastic
+// force -V P(R^T A) with the same stand-in for R^T A, column by column.
+DEV void local_force_lp(const double *sh, const double *A, const double *q, const double *qn,
+                        const double *qd, const double *g, double h, double *phi,
+                        const double *wr, int64_t ws, int64_t wb) {
+  const double ih = 1.0 / h, ih2 = 1.0 / (h * h);
+  double Sh[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double col[3] = {A[c], A[3 + c], A[6 + c]};
+    double x[3];
+    lenpres(A, true, col, x);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) Sh[3 * r + c] = x[r];
+  }
+  const double mu = sh[5], lam = sh[6], V = sh[4];
+  const double tr = Sh[0] + Sh[4] + Sh[8] - 3.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double M = sh[c];
+    double w[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) w[i] = M * qd[3 * c + i] * ih - M * (q[3 * c + i] - qn[3 * c + i]) * ih2;
+    if (c == 3) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) w[i] += sh[3] * g[i];
+    }
+    if (wr) {
+      if (c < 3) {
+        const double t0 = wr[wb], t1 = wr[ws + wb], t2 = wr[2 * ws + wb];
+        const double *qc = q + 3 * c;
+        w[0] += 0.5 * (t1 * qc[2] - t2 * qc[1]);
+        w[1] += 0.5 * (t2 * qc[0] - t0 * qc[2]);
+        w[2] += 0.5 * (t0 * qc[1] - t1 * qc[0]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) w[i] += wr[(3 + i) * ws + wb];
+      }
+    }
+    double v[3];
+    lenpres(A, true, w, v);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      if (c < 3) {
+        const double P = mu * (Sh[3 * r + c] + Sh[3 * c + r] - 2.0 * double(r == c)) + lam * tr * double(r == c);
+        v[r] -= V * P;
+      }
+      phi[3 * c + r] = v[r];
+    }
+  }
+}
+
 }  // namespace mabd

@@ -49,10 +49,13 @@ __global__ __launch_bounds__(DNT) void gdiag_body_kernel(
     double dq_scale, int64_t ns, const int32_t *shp, const double *hinv, const double *shape,
     double g0, double g1, double g2, double h, const double *Rg, const int32_t *inc_off,
     const int32_t *inc, const GJoint *J, const double *gl, const double *glam, const double *wr,
-    const uint32_t *status, double *part) {
+    const uint32_t *status, double *part, int polar_free) {
   const int64_t b = (int64_t)b0 + blockIdx.x * DNT + threadIdx.x;
   double v[DIAG_PART] = {0, 0, 0, 0, 0, 0};
-  if (b < b1 && !skip_step(status, 0)) {
+  // a body that took the polar-free solve does not solve the co-rotated
+  // system of Eq. kkt: it is left out of rho_p
+  const bool pf = b < b1 && polar_free && inc_off[b] == inc_off[b + 1];
+  if (b < b1 && !pf && !skip_step(status, 0)) {
     double qq[12], qnn[12], qd[12], dq[12], A[9], R[9];
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
@@ -226,11 +229,11 @@ void launch_gdiag_body(int b0, int b1, const double *q, const double *qn, const 
                        const double *hinv, const double *shape, const double *g, double h,
                        const double *Rg, const int32_t *inc_off, const int32_t *inc, const GJoint *J,
                        const double *gl, const double *glam, const double *wr, const uint32_t *status,
-                       double *part, hipStream_t s) {
+                       double *part, int polar_free, hipStream_t s) {
   if (b1 <= b0) return;
   hipLaunchKernelGGL(gdiag_body_kernel, dim3(diag_body_blocks(b1 - b0)), dim3(DNT), 0, s, b0, b1, q,
                      qn, qdn, dqv, dq_scale, ns, shp, hinv, shape, g[0], g[1], g[2], h, Rg, inc_off,
-                     inc, J, gl, glam, wr, status, part);
+                     inc, J, gl, glam, wr, status, part, polar_free);
 }
 
 void launch_gdiag_joint(int m, const GJoint *J, const double *gl, const double *Rg, const double *ug,

@@ -48,12 +48,40 @@ __global__ void prefactor_kernel(const double *shape, int nshape, double h, doub
 // R and the local unconstrained increment u = Hbar^{-1} diag4(R^T) f_A for
 // bodies [b0, b1) (Eqs. polar, abd_final).  q is the current iterate, qn/qdn
 // the state at the start of the step.
+// With pf_inc (the bodies' incidence offsets) given, bodies without joints
+// take the polar-free solve of Alg. 1 instead: no polar decomposition, the
+// length-preserving stand-ins of local_force_lp, R stored as the identity
+// (unused: the back-projection applies the stand-in again).
 __global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double *q, const double *qn, const double *qdn,
                              int64_t ns, const int32_t *shp, const double *hinv,
                              const double *shape, double g0, double g1, double g2, double h,
-                             double *Rg, double *ug, uint32_t *status, int step, const double *wr) {
+                             double *Rg, double *ug, uint32_t *status, int step, const double *wr,
+                             const int32_t *pf_inc) {
   int64_t b = (int64_t)b0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= b1 || skip_step(status, step)) return;
+  if (pf_inc && pf_inc[b] == pf_inc[b + 1]) {
+    double qq[12], qnn[12], qd[12], A[9];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      qq[c] = q[c * ns + b];
+      qnn[c] = qn[c * ns + b];
+      qd[c] = qdn[c * ns + b];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) A[3 * i + c] = qq[3 * c + i];
+    const int s = shp[b];
+    const double g[3] = {g0, g1, g2};
+    double phi[12], u[12];
+    local_force_lp(shape + (int64_t)SHAPE_STRIDE * s, A, qq, qnn, qd, g, h, phi, wr, ns, b);
+    hinv_apply(hinv + (int64_t)HINV_STRIDE * s, phi, u);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Rg[i * ns + b] = (i % 4 == 0) ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) ug[i * ns + b] = u[i];
+    return;
+  }
   double qq[12], qnn[12], qd[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
@@ -1201,9 +1229,35 @@ __global__ __launch_bounds__(256) void gapply_kernel(int b0, int b1, const int32
                               const double *ug, int64_t ns, const int32_t *shp, const double *hinv,
                               const double *q_cur, double *q_out, double *qd_out, double h,
                               int accumulate, uint32_t *status, const GJoint *J, int step,
-                              double *dq_save) {
+                              double *dq_save, int polar_free) {
   int64_t b = (int64_t)b0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= b1 || skip_step(status, step)) return;
+  if (polar_free && inc_off[b] == inc_off[b + 1]) {
+    // polar-free solve (Alg. 1): dq = the length-preserving stand-in of R
+    // applied to each block of u
+    double A[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) A[3 * i + c] = q_cur[(3 * c + i) * ns + b];
+    const double ih = 1.0 / h;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double dp[3], dq[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dp[i] = ug[(3 * c + i) * ns + b];
+      lenpres(A, false, dp, dq);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int64_t o = (int64_t)(3 * c + i) * ns + b;
+        q_out[o] = q_cur[o] + dq[i];
+        qd_out[o] = (accumulate ? qd_out[o] : 0.0) + dq[i] * ih;
+        if (dq_save) dq_save[o] = dq[i];
+        if (!isfinite(dq[i])) raise_flag(status, FLAG_NONFINITE, step);
+      }
+    }
+    return;
+  }
   double g12[12];
   for (int i = 0; i < 12; ++i) g12[i] = 0.0;
   for (int e = inc_off[b]; e < inc_off[b + 1]; ++e) {
@@ -1314,10 +1368,10 @@ void launch_prefactor(const double *shape, int nshape, double h, double *hinv, h
 void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
                   const int32_t *shp, const double *hinv, const double *shape, const double *g,
                   double h, double *Rg, double *ug, uint32_t *status, int step, const double *wr,
-                  hipStream_t s) {
+                  const int32_t *pf_inc, hipStream_t s) {
   if (b1 > b0)
     hipLaunchKernelGGL(gbody_kernel, dim3((b1 - b0 + 255) / 256), dim3(256), 0, s, b0, b1, q, qn, qdn,
-                       ns, shp, hinv, shape, g[0], g[1], g[2], h, Rg, ug, status, step, wr);
+                       ns, shp, hinv, shape, g[0], g[1], g[2], h, Rg, ug, status, step, wr, pf_inc);
 }
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
                    double *gl, hipStream_t s) {
@@ -1391,11 +1445,11 @@ void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, c
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
                    double *qd_out, double h, int acc, uint32_t *status, const GJoint *J,
-                   int step, double *dq_save, hipStream_t s) {
+                   int step, double *dq_save, int polar_free, hipStream_t s) {
   if (b1 > b0)
     hipLaunchKernelGGL(gapply_kernel, dim3((b1 - b0 + 255) / 256), dim3(256), 0, s, b0, b1, inc_off,
                        inc, gl, glam, Rg, ug, ns, shp, hinv, q_cur, q_out, qd_out, h, acc, status, J,
-                       step, dq_save);
+                       step, dq_save, polar_free);
 }
 void launch_gather_state(int nd, const int32_t *sol2in, const double *const *q, const double *const *qd,
                          int cur, int cur0, const uint32_t *status, int64_t ns, double *qo, double *qdo,

@@ -42,7 +42,7 @@ void launch_prefactor(const double *shape, int nshape, double h, double *hinv, h
 void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
                   const int32_t *shp, const double *hinv, const double *shape, const double *g,
                   double h, double *Rg, double *ug, uint32_t *status, int step, const double *wr,
-                  hipStream_t s);
+                  const int32_t *pf_inc, hipStream_t s);
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
                    double *gl, hipStream_t s);
 void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
@@ -51,7 +51,7 @@ void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, c
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
                    double *qd_out, double h, int acc, uint32_t *status, const GJoint *J,
-                   int step, double *dq_save, hipStream_t s);
+                   int step, double *dq_save, int polar_free, hipStream_t s);
 void launch_gather_state(int nd, const int32_t *sol2in, const double *const *q, const double *const *qd,
                          int cur, int cur0, const uint32_t *status, int64_t ns, double *qo, double *qdo,
                          hipStream_t s);
@@ -61,7 +61,7 @@ void launch_gdiag_body(int b0, int b1, const double *q, const double *qn, const 
                        const double *hinv, const double *shape, const double *g, double h,
                        const double *Rg, const int32_t *inc_off, const int32_t *inc, const GJoint *J,
                        const double *gl, const double *glam, const double *wr, const uint32_t *status,
-                       double *part, hipStream_t s);
+                       double *part, int polar_free, hipStream_t s);
 void launch_gdiag_joint(int m, const GJoint *J, const double *gl, const double *Rg, const double *ug,
                         const double *dqv, double dq_scale, const double *q_new, int64_t ns,
                         const uint32_t *status, double *part, hipStream_t s);
@@ -481,6 +481,7 @@ void mabd_options_default(mabd_options *o) {
   o->use_graph = 1;
   o->autotune = 1;
   o->ir_max_sweeps = 4;
+  o->body_solve = 0;
   o->stream = nullptr;
 }
 
@@ -534,6 +535,8 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     return fail(nullptr, MABD_ERR_INVALID_ARG, "precision must be 0 or 1");
   if (opt.ir_max_sweeps < 0 || opt.ir_max_sweeps > 16)
     return fail(nullptr, MABD_ERR_INVALID_ARG, "ir_max_sweeps must be in 0..16");
+  if (opt.body_solve != 0 && opt.body_solve != 1)
+    return fail(nullptr, MABD_ERR_INVALID_ARG, "body_solve must be 0 or 1");
   if (!finite_all(opt.gravity, 3)) return fail(nullptr, MABD_ERR_INVALID_ARG, "gravity not finite");
   // ------------------------------------------------------------ validate
   for (int i = 0; i < n; ++i) {
@@ -1482,7 +1485,8 @@ hipError_t gnn_prepare(mabd_ctx *c, double h, PcgBallArgs &pb) {
   launch_begin_step(c->d_status, s);
   const int a = c->cur;
   launch_gbody(c->gb0, c->gb1, c->d_q[a], c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv, c->d_shape,
-               c->opt.gravity, h, c->d_Rg, c->d_ug, c->d_status, 0, c->wr_on ? c->d_wr : nullptr, s);
+               c->opt.gravity, h, c->d_Rg, c->d_ug, c->d_status, 0, c->wr_on ? c->d_wr : nullptr,
+               nullptr, s);  // network bodies have joints: always the polar solve
   launch_gjoint((int)c->gj.size(), c->d_gj, c->d_q[a], c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
   pb = make_ball_args(c, c->opt.kkt_tol, c->opt.max_iters, 0);
   launch_pb_setup(pb, s);
@@ -1628,7 +1632,7 @@ void issue_residual(mabd_ctx *c, double h, int a, int b, const double *q_it, con
   launch_gdiag_body(c->gb0, c->gb1, q_it, c->d_q[a], c->d_qd[a], dqv, dq_scale, c->ns, c->d_shp,
                     c->d_hinv, c->d_shape, c->opt.gravity, h, c->d_Rg, c->d_inc_off, c->d_inc, c->d_gj,
                     c->d_gl, c->d_glam, c->wr_on ? c->d_wr : nullptr, c->d_status,
-                    part + DIAG_PART * off, s);
+                    part + DIAG_PART * off, c->opt.body_solve, s);
   off += diag_body_blocks(c->gb1 - c->gb0);
   launch_gdiag_joint((int)c->gj.size(), c->d_gj, c->d_gl, c->d_Rg, c->d_ug, dqv, dq_scale, c->d_q[b],
                      c->ns, c->d_status, part + DIAG_PART * off, s);
@@ -1694,7 +1698,8 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       const double *qcur = it == 0 ? c->d_q[a] : c->d_q[b];
       tm.run(3, [&] {
         launch_gbody(c->gb0, c->gb1, qcur, c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv,
-                     c->d_shape, g, h, c->d_Rg, c->d_ug, c->d_status, 0, c->wr_on ? c->d_wr : nullptr, s);
+                     c->d_shape, g, h, c->d_Rg, c->d_ug, c->d_status, 0, c->wr_on ? c->d_wr : nullptr,
+                     c->opt.body_solve == 1 ? c->d_inc_off : nullptr, s);
       });
       tm.run(4, [&] {
         launch_gjoint((int)c->gj.size(), c->d_gj, qcur, c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
@@ -1776,7 +1781,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       tm.run(6, [&] {
         launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_glam, c->d_Rg, c->d_ug,
                       c->ns, c->d_shp, c->d_hinv, qcur, c->d_q[b], c->d_qd[b], h, it > 0 ? 1 : 0,
-                      c->d_status, c->d_gj, 0, dg_it ? c->d_dqit : nullptr, s);
+                      c->d_status, c->d_gj, 0, dg_it ? c->d_dqit : nullptr, c->opt.body_solve, s);
       });
       if (dg_it) {
         const int slot = std::min(it, MABD_NEWTON_DIAG - 1);
