@@ -190,6 +190,11 @@ typedef struct {
   double kkt_newton[MABD_NEWTON_DIAG]; /* diagnostics bit 0: KKT residual of each Newton
                               iteration of the last step (a ninth and later iterations
                               share the last entry), -1 where not evaluated             */
+  int32_t n_loop;          /* components with a few closed loops, solved by the loop-
+                              breaker Schur complement (Sec. 5, Case III): a spanning
+                              tree by the tree contraction, the loop-closing joints (at
+                              most 48 rows per component) by a dense Schur system;
+                              components with more loop rows are networks (PCG)       */
 } mabd_step_stats;
 
 /* Fills *opt with the defaults listed above. */
@@ -197,7 +202,9 @@ void mabd_options_default(mabd_options *opt);
 
 /* Validates and copies the assembly, classifies every connected component of
    dynamic bodies (chain: the dual graph of Fig. dual_mat is a path with only
-   ball joints; tree: body/joint incidence graph acyclic; graph: otherwise),
+   ball joints; tree: body/joint incidence graph acyclic; loop: a spanning
+   tree plus loop-closing joints of at most 48 rows (Case III); graph:
+   otherwise),
    builds the solve schedules and uploads state and schedules to the device.
    Pinned bodies become constant world-side anchors.  opt may be NULL
    (defaults).  On success *out receives a context to free with mabd_destroy.

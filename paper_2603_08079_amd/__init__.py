@@ -74,7 +74,8 @@ class StepStats(ctypes.Structure):
                 ("phase_ms", ctypes.c_double * NPHASES), ("phase_calls", ctypes.c_int64 * NPHASES),
                 ("tile_threads", ctypes.c_int32), ("graph_replay", ctypes.c_int32),
                 ("tree_rounds", ctypes.c_int32), ("tile_packed", ctypes.c_int32),
-                ("ir_stalled", ctypes.c_int32), ("kkt_newton", ctypes.c_double * NEWTON_DIAG)]
+                ("ir_stalled", ctypes.c_int32), ("kkt_newton", ctypes.c_double * NEWTON_DIAG),
+                ("n_loop", ctypes.c_int32)]
 
     PHASES = ("chain_reduce", "chain_global", "chain_apply", "body", "joint", "tree", "apply",
               "pcg", "chain_resid", "chain_finish")

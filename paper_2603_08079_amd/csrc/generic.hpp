@@ -84,7 +84,14 @@ struct TreeArgs {
   double *fac;              // per slot: K (LD x LD, LD = absorbed rows + 5), y (LD), scratch
   const struct TcOp *ops;   // contraction schedule
   double *crec;             // compress records
+  int zero_c;               // 1: the joints' constraint values are taken as zero (the
+                            // loop-breaker's solves with other right-hand sides)
 };
+
+// A component with a few closed loops (Sec. 5, Case III): its joints split
+// into a spanning tree A, solved by the tree contraction, and loop breakers
+// D.  Loop rows (joint << 3 | row) of component c are lrow[off[c], off[c+1]).
+constexpr int LOOP_MAX_ROWS = 48;  // rows of D per component (the dense Schur system)
 
 // One operation of the tree contraction.  rake: eliminate the private rows of
 // slot v (absorbed joints: condensed children and one-sided joints) and pass

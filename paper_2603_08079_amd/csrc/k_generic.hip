@@ -348,7 +348,7 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
     cv[k] = 0.0;
     if (i < nr) {
       const int e = S.rowent[i], ei = S.ei[e];
-      if (ei & 2) cv[k] = a.gl[(int64_t)GL_STRIDE * S.ek[e] + GL_C + (i - (ei >> 8))];
+      if ((ei & 2) && !a.zero_c) cv[k] = a.gl[(int64_t)GL_STRIDE * S.ek[e] + GL_C + (i - (ei >> 8))];
     }
   }
   //    clique rows L (nr x 12), eight independent loads per lane in flight

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <set>
 #include <numeric>
 #include <string>
 #include <tuple>
@@ -69,6 +70,15 @@ void launch_diag_reduce(const double *part, int nblk, double *out, const uint32_
                         hipStream_t s);
 int resid_static_blocks();
 hipError_t resid_scratch(int device, double **out);
+void launch_loop_inject(int nloop, const int32_t *loff, const int32_t *lrow, int j, const GJoint *J,
+                        const double *gl, const int32_t *shp, const double *hinv, int64_t ns, double *uloop,
+                        int set, hipStream_t s);
+void launch_loop_schur(int nloop, const int32_t *loff, const int32_t *lrow, const GJoint *J, const double *gl,
+                       const double *ug, const int32_t *shp, const double *hinv, int64_t ns,
+                       const int32_t *inc_off, const int32_t *inc, const int32_t *jloop, const double *wcol,
+                       int64_t wstride, double *glam, double *lamD, uint32_t *status, hipStream_t s);
+void launch_loop_correct(int mj, const int32_t *jloop, const int32_t *loff, const double *wcol, int64_t wstride,
+                         const double *lamD, double *glam, const uint32_t *status, hipStream_t s);
 void launch_twists(int nd, const int32_t *sol2in, const double *q, const double *qd, int64_t ns,
                    double *V, hipStream_t s);
 void launch_joint_wrenches(const ChainDesc *chains, int nchains, int nchain_bodies, const double *pl,
@@ -107,7 +117,7 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-enum Cls { CLS_CHAIN = 1, CLS_TREE = 2, CLS_GRAPH = 3 };
+enum Cls { CLS_CHAIN = 1, CLS_TREE = 2, CLS_GRAPH = 3, CLS_LOOP = 4 };
 
 // ------------------------------------------------------------ host 3x3 help
 void polar_host(const double *A, double *R) {
@@ -187,6 +197,15 @@ struct mabd_ctx {
   std::vector<int32_t> gj_in;
   int gb0 = 0, gb1 = 0;
   int ntree = 0, ngraph = 0;
+  // components with a few loops (loop-breaker Schur complement): per generic
+  // joint its loop component (-1 none, -2 a loop-closing joint), per
+  // component its loop rows (joint << 3 | row), the columns S_AA^{-1} S_AD
+  // (loop_maxr of 5 per generic joint), l_D, and the zero-based increments
+  // of the column solves
+  int nloop = 0, loop_maxr = 0;
+  std::vector<int32_t> jloop, loff{0}, lrow;
+  int32_t *d_jloop = nullptr, *d_loff = nullptr, *d_lrow = nullptr;
+  double *d_wcol = nullptr, *d_lamD = nullptr, *d_uloop = nullptr;
   std::vector<int32_t> comp_lvl, lvl_off, tbody, tpk, tabs_off, tabs, inc_off, inc, tne;
   std::vector<int64_t> foff;
   int64_t fac_size = 0;
@@ -637,6 +656,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     if (dyn(b)) binc[b].push_back(k);
   }
   std::vector<int> cls(ncomp);
+  std::vector<uint8_t> is_loop_joint(m, 0);
   for (int ci = 0; ci < ncomp; ++ci) {
     long edges = 0;
     int maxdeg = 0;
@@ -648,7 +668,30 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     for (int b : cbodies[ci]) maxdeg = std::max<int>(maxdeg, (int)binc[b].size());
     const long nodes = (long)cbodies[ci].size() + (long)cjoints[ci].size();
     const bool acyclic = edges == nodes - 1;
-    if (!acyclic) cls[ci] = CLS_GRAPH;
+    if (!acyclic) {
+      // few loops: loop-breaker Schur complement (Case III) on a spanning
+      // tree, when its loop-closing joints have at most LOOP_MAX_ROWS rows
+      std::set<int> seen{cbodies[ci][0]}, used;
+      std::vector<int> order{cbodies[ci][0]};
+      for (size_t h = 0; h < order.size(); ++h)
+        for (int k : binc[order[h]]) {
+          const int o = Jn->a[k] == order[h] ? Jn->b[k] : Jn->a[k];
+          if (!dyn(o) || seen.count(o)) continue;
+          seen.insert(o);
+          used.insert(k);
+          order.push_back(o);
+        }
+      int rows_d = 0;
+      std::vector<int> dk;
+      for (int k : cjoints[ci])
+        if (dyn(Jn->a[k]) && dyn(Jn->b[k]) && !used.count(k)) {
+          rows_d += joint_rows(Jn->type[k]);
+          dk.push_back(k);
+        }
+      cls[ci] = (rows_d > 0 && rows_d <= LOOP_MAX_ROWS) ? CLS_LOOP : CLS_GRAPH;
+      if (cls[ci] == CLS_LOOP)
+        for (int k : dk) is_loop_joint[k] = 1;
+    }
     else if (all_ball && maxdeg <= 2 && cjoints[ci].size() >= 2 && opt.newton_iters == 1)
       cls[ci] = CLS_CHAIN;
     else cls[ci] = CLS_TREE;
@@ -753,7 +796,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   std::vector<int> gidx(m, -1);  // input joint -> generic joint
   std::vector<int32_t> gj_graph;
   for (int ci = 0; ci < ncomp; ++ci) {
-    if (cls[ci] != CLS_TREE && cls[ci] != CLS_GRAPH) continue;
+    if (cls[ci] != CLS_TREE && cls[ci] != CLS_GRAPH && cls[ci] != CLS_LOOP) continue;
     for (int k : cjoints[ci]) {
       gidx[k] = (int)c->gj_in.size();
       c->gj_in.push_back(k);
@@ -764,8 +807,15 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   c->comp_lvl.push_back(0);
   c->lvl_off.push_back(0);
   for (int ci = 0; ci < ncomp; ++ci) {
-    if (cls[ci] != CLS_TREE) continue;
+    if (cls[ci] != CLS_TREE && cls[ci] != CLS_LOOP) continue;
     const auto &bs = cbodies[ci];
+    if (cjoints[ci].empty()) {
+      // a body without joints: its step is the body solve and the update
+      // alone, no elimination slot
+      add_body(bs[0]);
+      c->ntree++;
+      continue;
+    }
     int root = bs[0];
     for (int b : bs) {
       bool has_unary = false;
@@ -779,6 +829,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     for (size_t h = 0; h < order.size(); ++h) {
       int b = order[h];
       for (int k : binc[b]) {
+        if (is_loop_joint[k]) continue;  // loop breakers stay out of the tree
         int o = Jn->a[k] == b ? Jn->b[k] : Jn->a[k];
         if (!dyn(o) || seen.count(o)) continue;
         seen[o] = 1;
@@ -814,6 +865,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
         int unary_rows = 0;
         for (int k : binc[b]) {
           if (parent_joint.count(b) && parent_joint[b] == k) continue;
+          if (is_loop_joint[k]) continue;
           const int side = Jn->a[k] == b ? 0 : 1;
           const bool unary = !dyn(Jn->a[k]) || !dyn(Jn->b[k]);
           if (unary) unary_rows += joint_rows(Jn->type[k]);
@@ -834,7 +886,22 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       c->lvl_off.push_back((int)c->tbody.size());
     }
     c->comp_lvl.push_back((int)c->lvl_off.size() - 1);
-    c->ntree++;
+    if (cls[ci] == CLS_LOOP) {
+      // loop rows and the joint -> loop component map (generic indices)
+      if (c->jloop.empty()) c->jloop.assign(c->gj_in.size(), -1);
+      int nr = 0;
+      for (int k : cjoints[ci]) {
+        c->jloop[gidx[k]] = is_loop_joint[k] ? -2 : c->nloop;
+        if (!is_loop_joint[k]) continue;
+        for (int r = 0; r < joint_rows(Jn->type[k]); ++r) c->lrow.push_back((gidx[k] << 3) | r);
+        nr += joint_rows(Jn->type[k]);
+      }
+      c->loff.push_back((int)c->lrow.size());
+      c->loop_maxr = std::max(c->loop_maxr, nr);
+      c->nloop++;
+    } else {
+      c->ntree++;
+    }
   }
   c->tabs_off.push_back((int)c->tabs.size());
   // ---- tree contraction schedule: rounds of rakes (slots with no live
@@ -1223,6 +1290,15 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(dalloc(c, &c->d_fac, (size_t)std::max<int64_t>(c->fac_size, 1)));
   if (e == hipSuccess) chk(upload(c, &c->d_tc_ops, c->tc_ops));
   if (e == hipSuccess) chk(dalloc(c, &c->d_crec, (size_t)std::max<int64_t>(c->crec_size, 1)));
+  if (c->nloop > 0) {
+    if (e == hipSuccess) chk(upload(c, &c->d_jloop, c->jloop));
+    if (e == hipSuccess) chk(upload(c, &c->d_loff, c->loff));
+    if (e == hipSuccess) chk(upload(c, &c->d_lrow, c->lrow));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_lamD, c->lrow.size()));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_uloop, 12 * (size_t)ns));
+    if (e == hipSuccess) chk(hipMemset(c->d_uloop, 0, 12 * (size_t)ns * sizeof(double)));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_wcol, (size_t)c->loop_maxr * 5 * mg));
+  }
   if (e == hipSuccess) chk(upload(c, &c->d_inc_off, c->inc_off));
   if (e == hipSuccess) chk(upload(c, &c->d_inc, c->inc));
   if (e == hipSuccess) chk(upload(c, &c->d_sol2in, c->sol2in));
@@ -1353,6 +1429,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   c->stats.n_chain = (int)c->chains.size();
   c->stats.n_tree = c->ntree;
   c->stats.n_graph = c->ngraph;
+  c->stats.n_loop = c->nloop;
   c->stats.n_dyn = c->nd;
   c->stats.tile_threads = c->tile_threads;
   c->stats.tile_packed = c->tile_pack ? 1 : 0;
@@ -1728,6 +1805,30 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       tm.run(5, [&] {
         launch_tree(ta, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
                     ((int)c->tc_rounds.size() - 1) / 7, s);
+        if (c->nloop > 0) {
+          // loop-breaker Schur complement (Case III): the columns
+          // S_AA^{-1} S_AD e_j by tree solves of the loop rows' increments
+          // with zero constraint values, then the Schur system per component
+          // and the tree joints' correction
+          const int64_t ws = 5 * (int64_t)c->gj.size();
+          TreeArgs tw = ta;
+          tw.u = c->d_uloop;
+          tw.zero_c = 1;
+          for (int j = 0; j < c->loop_maxr; ++j) {
+            launch_loop_inject(c->nloop, c->d_loff, c->d_lrow, j, c->d_gj, c->d_gl, c->d_shp, c->d_hinv, c->ns,
+                               c->d_uloop, 1, s);
+            tw.glam = c->d_wcol + (size_t)j * ws;
+            launch_tree(tw, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
+                        ((int)c->tc_rounds.size() - 1) / 7, s);
+            launch_loop_inject(c->nloop, c->d_loff, c->d_lrow, j, c->d_gj, c->d_gl, c->d_shp, c->d_hinv, c->ns,
+                               c->d_uloop, 0, s);
+          }
+          launch_loop_schur(c->nloop, c->d_loff, c->d_lrow, c->d_gj, c->d_gl, c->d_ug, c->d_shp, c->d_hinv,
+                            c->ns, c->d_inc_off, c->d_inc, c->d_jloop, c->d_wcol, ws, c->d_glam, c->d_lamD,
+                            c->d_status, s);
+          launch_loop_correct((int)c->gj.size(), c->d_jloop, c->d_loff, c->d_wcol, ws, c->d_lamD, c->d_glam,
+                              c->d_status, s);
+        }
       });
       if (c->ngraph > 0) {
         PcgArgs pa{};

@@ -436,7 +436,8 @@ def test_full_size_lattice_one_step():
 
 def test_full_size_rgg_one_step():
     """The 100,000-body random geometric network (244,291 ball joints, six
-    network components and twelve trees) at full size: one cold-start PCG
+    network components, five of them with few enough loops for the
+    loop-breaker, and twelve trees) at full size: one cold-start PCG
     step to relative residual 1e-2, a tolerance block-Jacobi PCG reaches on
     this over-constrained graph within a few thousand iterations (1e-10 is
     out of its reach).  The oracle back-projects the GPU multipliers in FP64
@@ -451,7 +452,9 @@ def test_full_size_rgg_one_step():
     lam_g = ctx.multipliers()
     qg, qdg = ctx.state()
     ctx.close()
-    assert st["n_graph"] == 6 and st["last_status"] == 0
+    # six network components: the five with few loops are solved exactly by
+    # the loop-breaker, the large one by PCG
+    assert st["n_graph"] + st["n_loop"] == 6 and st["n_graph"] >= 1 and st["last_status"] == 0
     assert 0 < st["pcg_iters"] < 100000 and st["rho_d"] <= tol
     s = oracle.System(asm)
     qv, qdv, dv = s.finish(asm.h, asm.q0, asm.qd0, lam_g)
@@ -461,6 +464,7 @@ def test_full_size_rgg_one_step():
     eq, eqd = state_errors(qg, qdg, qv, qdv)
     say("state vs the oracle's back-projection of the GPU multipliers", eq, eqd)
     assert eq < TOL and eqd < TOL
-    # the GPU's own true residual of the networks and the oracle's over all
-    # rows (the trees' rows are solved exactly) are the same number
-    assert abs(dv[oracle.RHO_D] - st["rho_d"]) <= 1e-4 * st["rho_d"]
+    # the GPU's own true residual of the PCG network and the oracle's over
+    # all rows (the other components' rows are solved exactly) are the same
+    # number up to the share of the exactly solved rows in the norm of r
+    assert abs(dv[oracle.RHO_D] - st["rho_d"]) <= 1e-2 * st["rho_d"]
