@@ -224,12 +224,19 @@ def main():
 
     def timed(c):
         """--repeats timed regions of exactly --steps steps, each bracketed by
-        a device synchronisation; the median region is reported."""
-        if args.warmup:
-            run(c, args.warmup)
-        torch.cuda.synchronize()
+        a device synchronisation; the median region is reported.  Every
+        region times the same steps of the workload's trajectory, steps
+        [warmup, warmup + steps): before it (untimed) the state goes back to
+        the workload's initial state and the warmup steps run again.  (On the
+        random trees a few light links carry subtrees thousands of times
+        their mass and leave the small-deformation regime after some tens of
+        steps; the repeats never reach that far.)"""
         reps = []
         for _ in range(max(1, args.repeats)):
+            c.set_state(asm.q0, asm.qd0)
+            if args.warmup:
+                run(c, args.warmup)
+            torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()

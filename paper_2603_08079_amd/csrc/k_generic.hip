@@ -1392,14 +1392,16 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
   // later one), so every LDS-staged class of a round shares one launch, in
   // both directions.  When the 16-row classes hold many operations
   // (throughput-bound: their small LDS footprint keeps more of them
-  // resident) they get a launch of their own.
+  // resident) they get a launch of their own.  Within a launch the classes
+  // go largest first (workgroups are dispatched in index order, so the
+  // longest operations start first and the short ones fill the tail).
   static const int tw[TC_NCLASS] = {16, 64, 64, 16, 64, 64};
   static const size_t lds_fwd[TC_NCLASS] = {4 * sizeof(TcwMat<16>),  sizeof(TcwMat<32>),
                                             sizeof(TcwMat<64>),      4 * sizeof(TcwComp<16>),
                                             sizeof(TcwComp<32>),     sizeof(TcwComp<48>)};
   static const size_t lds_back[TC_NCLASS] = {4 * 136 * 8, 528 * 8, 2080 * 8, 4 * 136 * 8, 528 * 8, 1176 * 8};
-  static const int all[TC_NCLASS] = {TC_RAKE16, TC_COMP16, TC_RAKE32, TC_RAKE64, TC_COMP32, TC_COMP48};
-  static const int *small = all, *large = all + 2;
+  static const int all[TC_NCLASS] = {TC_RAKE64, TC_COMP48, TC_RAKE32, TC_COMP32, TC_RAKE16, TC_COMP16};
+  static const int *small = all + 4, *large = all;
   constexpr int SPLIT_OPS = 6000;
   auto launch_classes = [&](const int32_t *o, const int *cl, int ncl, bool back) {
     TcwLaunch L{};
