@@ -105,6 +105,35 @@ __global__ __launch_bounds__(DNT) void gdiag_body_kernel(
   block_partials(v, part + DIAG_PART * (int64_t)blockIdx.x);
 }
 
+// max |row value| of a rotated-frame joint of type TYPE at the new state
+// (Eqs. hinge, universal, prismatic): row i is component comp of
+// R_J (y_X - y_Y); the row loop is unrolled over the compile-time table.
+template <int TYPE>
+DEV double rot_joint_value(const GJoint &j, const double *Aa, const double *ta, const double *Ab,
+                           const double *tb, const double *RH) {
+  const double *P[5] = {j.p1a, j.p2a, j.p1b, j.p2b, j.p3b};
+  constexpr int ROWS = TYPE == 2 ? 4 : 5;
+  double v = 0.0;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    const JointRow jr = joint_row(TYPE, i);
+    double d[3];
+    if (point_side(jr.x) != point_side(jr.y)) {
+      double wa[3], wb[3];
+      mat3_vec(Aa, P[jr.x], wa);
+      mat3_vec(Ab, P[jr.y], wb);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) d[r] = (ta[r] - tb[r]) + (wa[r] - wb[r]);
+    } else {
+      const double dp[3] = {P[jr.x][0] - P[jr.y][0], P[jr.x][1] - P[jr.y][1], P[jr.x][2] - P[jr.y][2]};
+      mat3_vec(point_side(jr.x) ? Ab : Aa, dp, d);
+    }
+    const double *rh = RH + 3 * jr.comp;
+    v = fmax(v, fabs(rh[0] * d[0] + rh[1] * d[1] + rh[2] * d[2]));
+  }
+  return v;
+}
+
 // Dual part and joint values, one generic joint per thread.  gl holds the
 // iteration's rows L = G diag4(R) and C, ug its local increments
 // u = Hbar^-1 diag4(R^T) f_A, Rg its rotations; dq as above; q_new the state
@@ -177,19 +206,9 @@ __global__ __launch_bounds__(DNT) void gdiag_joint_kernel(
           for (int i = 0; i < 9; ++i) Ra[i] = (i % 4 == 0) ? 1.0 : 0.0;
         mat3_mul_bt(j.dR, Ra, RH);
       }
-      const double *P[5] = {j.p1a, j.p2a, j.p1b, j.p2b, j.p3b};
-      for (int i = 0; i < rows; ++i) {
-        const JointRow jr = joint_row(j.type, i);
-        double d[3];
-        if (point_side(jr.x) != point_side(jr.y)) {
-          point_diff(P[jr.x], P[jr.y], d);
-        } else {
-          const double dp[3] = {P[jr.x][0] - P[jr.y][0], P[jr.x][1] - P[jr.y][1], P[jr.x][2] - P[jr.y][2]};
-          mat3_vec(An[point_side(jr.x)], dp, d);
-        }
-        const double *rh = RH + 3 * jr.comp;
-        v[5] = fmax(v[5], fabs(rh[0] * d[0] + rh[1] * d[1] + rh[2] * d[2]));
-      }
+      v[5] = j.type == 1   ? rot_joint_value<1>(j, An[0], tn[0], An[1], tn[1], RH)
+             : j.type == 2 ? rot_joint_value<2>(j, An[0], tn[0], An[1], tn[1], RH)
+                           : rot_joint_value<3>(j, An[0], tn[0], An[1], tn[1], RH);
     }
   }
   block_partials(v, part + DIAG_PART * (int64_t)blockIdx.x);

@@ -118,90 +118,61 @@ __global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double
 // dR_comp J(p) for a's points, plus the A-linearised rotation term
 // (dR_comp (x) R_a^T d) on the A columns; on side b it is (R_J R_b)_comp J(p)
 // for b's points (with the signs of X and Y).
-__global__ __launch_bounds__(128) void gjoint_kernel(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns,
-                              int hinge_grad, double *gl) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= m) return;
-  const GJoint j = J[k];
-  double *out = gl + (int64_t)GL_STRIDE * k;
-  double Aa[9], ta[3], Ab[9], tb[3], Ra[9], Rb[9];
-  const bool da = j.sa >= 0, db = j.sb >= 0;
-  for (int side = 0; side < 2; ++side) {
-    const int64_t b = side == 0 ? j.sa : j.sb;
-    double *A = side == 0 ? Aa : Ab, *t = side == 0 ? ta : tb, *R = side == 0 ? Ra : Rb;
-    if (b >= 0) {
-      for (int i = 0; i < 3; ++i) {
-        for (int c = 0; c < 3; ++c) A[3 * i + c] = q[(3 * c + i) * ns + b];
-        t[i] = q[(9 + i) * ns + b];
-      }
-      for (int i = 0; i < 9; ++i) R[i] = Rg[i * ns + b];
-    } else {
-      for (int i = 0; i < 9; ++i) { A[i] = (i % 4 == 0) ? 1.0 : 0.0; R[i] = A[i]; }
-      t[0] = t[1] = t[2] = 0.0;
-    }
-  }
-  auto point_diff = [&](const double *pa_, const double *pb_, double *d) {
-    double wa[3], wb[3];
-    mat3_vec(Aa, pa_, wa);
-    mat3_vec(Ab, pb_, wb);
-    for (int i = 0; i < 3; ++i) d[i] = (ta[i] - tb[i]) + (wa[i] - wb[i]);
-  };
-  if (j.type == 0) {
-    double C[3];
-    point_diff(j.p1a, j.p1b, C);
-    for (int i = 0; i < 3; ++i) out[GL_C + i] = C[i];
-    for (int side = 0; side < 2; ++side) {
-      if (side == 0 ? !da : !db) continue;
-      const double *R = side == 0 ? Ra : Rb;
-      const double *p = side == 0 ? j.p1a : j.p1b;
-      const double s = side == 0 ? 1.0 : -1.0;
-      double *L = out + (side == 0 ? GL_LA : GL_LB);
-      for (int r = 0; r < 3; ++r)
-        for (int i = 0; i < 3; ++i) {
-          for (int c = 0; c < 3; ++c) L[12 * r + 3 * c + i] = s * R[3 * r + i] * p[c];
-          L[12 * r + 9 + i] = s * R[3 * r + i];
-        }
-    }
-    return;
-  }
-  // rotated-frame joints (hinge, universal, prismatic; Secs. 4.3-4.5): row i
-  // is component comp of R_J (y_X - y_Y) with R_J = dR R_a^T
+// Rows of a rotated-frame joint (hinge, universal, prismatic; Secs. 4.3-4.5)
+// of type TYPE: row i is component comp of R_J (y_X - y_Y) with
+// R_J = dR R_a^T.  The row loop is unrolled over the compile-time row table,
+// so every point and component index is a constant (the joint record stays
+// in registers).
+template <int TYPE>
+DEV void gjoint_rot_rows(const GJoint &j, const double *Aa, const double *ta, const double *Ab,
+                         const double *tb, const double *Ra, const double *Rb, bool da, bool db,
+                         int hinge_grad, double *out) {
   double RH[9];
   if (j.flags & GJ_FLAG_STATIC_OWNER) {
+#pragma unroll
     for (int i = 0; i < 9; ++i) RH[i] = j.dR[i];
   } else {
     mat3_mul_bt(j.dR, Ra, RH);  // R_J = dR R_a^T
   }
   double Q[9];  // R_J R_b: rows of side b's local-frame gradient
-  if (db) mat3_mul(RH, Rb, Q);
+  mat3_mul(RH, Rb, Q);
   const double *P[5] = {j.p1a, j.p2a, j.p1b, j.p2b, j.p3b};
-  const int rows = joint_rows(j.type);
-  double *La = out + GL_LA, *Lb = out + GL_LB;
-  for (int i = 0; i < rows; ++i) {
-    const JointRow jr = joint_row(j.type, i);
+  constexpr int ROWS = TYPE == 2 ? 4 : 5;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    const JointRow jr = joint_row(TYPE, i);
     // y_X - y_Y: across the joint translation difference first; on one body
     // its affine block times the difference of the rest points
     double d[3];
     if (point_side(jr.x) != point_side(jr.y)) {
-      point_diff(P[jr.x], P[jr.y], d);
+      double wa[3], wb[3];
+      mat3_vec(Aa, P[jr.x], wa);
+      mat3_vec(Ab, P[jr.y], wb);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) d[r] = (ta[r] - tb[r]) + (wa[r] - wb[r]);
     } else {
       const double dp[3] = {P[jr.x][0] - P[jr.y][0], P[jr.x][1] - P[jr.y][1], P[jr.x][2] - P[jr.y][2]};
       mat3_vec(point_side(jr.x) ? Ab : Aa, dp, d);
     }
     const double *rh = RH + 3 * jr.comp;
     out[GL_C + i] = rh[0] * d[0] + rh[1] * d[1] + rh[2] * d[2];
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
       if (side == 0 ? !da : !db) continue;
-      double *L = (side == 0 ? La : Lb) + 12 * i;
       // frozen frame: the rotated row times J(p) in the side's local frame
       // (dR row on side a, since J(p) diag4(R_a) = R_a J(p); (R_J R_b) row on b)
       const double *rr = side == 0 ? j.dR + 3 * jr.comp : Q + 3 * jr.comp;
+      double L[12];
+#pragma unroll
       for (int c = 0; c < 12; ++c) L[c] = 0.0;
+#pragma unroll
       for (int pt = 0; pt < 2; ++pt) {
         const int id = pt == 0 ? jr.x : jr.y;
         if (point_side(id) != side) continue;
         const double sg = pt == 0 ? 1.0 : -1.0;
+#pragma unroll
         for (int jj = 0; jj < 3; ++jj) {
+#pragma unroll
           for (int c = 0; c < 3; ++c) L[3 * c + jj] += sg * rr[jj] * P[id][c];
           L[9 + jj] += sg * rr[jj];
         }
@@ -211,11 +182,77 @@ __global__ __launch_bounds__(128) void gjoint_kernel(int m, const GJoint *J, con
         // r_gradient): dR_comp (x) R_a^T d on a's A columns
         double w[3];
         mat3t_vec(Ra, d, w);
+#pragma unroll
         for (int l = 0; l < 3; ++l)
+#pragma unroll
           for (int kk = 0; kk < 3; ++kk) L[3 * l + kk] += rr[l] * w[kk];
       }
+      double *Lo = out + (side == 0 ? GL_LA : GL_LB) + 12 * i;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) Lo[c] = L[c];
     }
   }
+}
+
+__global__ __launch_bounds__(128) void gjoint_kernel(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns,
+                              int hinge_grad, double *gl) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const GJoint j = J[k];
+  double *out = gl + (int64_t)GL_STRIDE * k;
+  double Aa[9], ta[3], Ab[9], tb[3], Ra[9], Rb[9];
+  const bool da = j.sa >= 0, db = j.sb >= 0;
+  auto load_side = [&](int64_t b, double *A, double *t, double *R) {
+    if (b >= 0) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) A[3 * i + c] = q[(3 * c + i) * ns + b];
+        t[i] = q[(9 + i) * ns + b];
+      }
+#pragma unroll
+      for (int i = 0; i < 9; ++i) R[i] = Rg[i * ns + b];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) { A[i] = (i % 4 == 0) ? 1.0 : 0.0; R[i] = A[i]; }
+      t[0] = t[1] = t[2] = 0.0;
+    }
+  };
+  load_side(j.sa, Aa, ta, Ra);
+  load_side(j.sb, Ab, tb, Rb);
+  if (j.type == 0) {
+    double C[3], wa[3], wb[3];
+    mat3_vec(Aa, j.p1a, wa);
+    mat3_vec(Ab, j.p1b, wb);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      C[i] = (ta[i] - tb[i]) + (wa[i] - wb[i]);
+      out[GL_C + i] = C[i];
+    }
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (side == 0 ? !da : !db) continue;
+      const double *R = side == 0 ? Ra : Rb;
+      const double *p = side == 0 ? j.p1a : j.p1b;
+      const double s = side == 0 ? 1.0 : -1.0;
+      double *L = out + (side == 0 ? GL_LA : GL_LB);
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) L[12 * r + 3 * c + i] = s * R[3 * r + i] * p[c];
+          L[12 * r + 9 + i] = s * R[3 * r + i];
+        }
+    }
+    return;
+  }
+  if (j.type == 1)
+    gjoint_rot_rows<1>(j, Aa, ta, Ab, tb, Ra, Rb, da, db, hinge_grad, out);
+  else if (j.type == 2)
+    gjoint_rot_rows<2>(j, Aa, ta, Ab, tb, Ra, Rb, da, db, hinge_grad, out);
+  else
+    gjoint_rot_rows<3>(j, Aa, ta, Ab, tb, Ra, Rb, da, db, hinge_grad, out);
 }
 
 // ------------------------------------------------------ (c2) tree solve
