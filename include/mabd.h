@@ -134,7 +134,12 @@ typedef struct {
   int32_t autotune;        /* 1 (default): at the first step of a context with at least
                               20,000 chain rows, time the chain tile forms (packed
                               60-row tiles; 64, 128, 256 threads) and keep the fastest;
-                              without it packed tiles are used.  The environment
+                              with at least 20,000 tree-contraction slots and no
+                              network component, also the tree schedules (threshold
+                              above which a round's 16-row cliques launch apart: 1,500,
+                              6,000 or never; clique classes largest or smallest first
+                              in a launch); schedules change no result.  Without it
+                              packed tiles, 6,000 and largest first.  The environment
                               variable MABD_CHAIN_TILE_THREADS = 64p, 64, 128 or 256
                               fixes the form at mabd_create instead, and
                               MABD_CHAIN_TOP_GLOBAL=1 sends every chain's top system
@@ -150,6 +155,14 @@ typedef struct {
                               also in the rotated elastic force.  Exact where A is a
                               scaled rotation, first order in the deformation otherwise;
                               such bodies are left out of rho_p (diagnostics)          */
+  const char *tune_cache;  /* path of a tuning cache file, or NULL (default): with
+                              autotune on, a context whose device and schedule shape
+                              (chain rows and count, tree slots and rounds) have an
+                              entry takes that entry's choices at mabd_create instead
+                              of timing them; a context that times them appends its
+                              entry.  Text, one "key = values" line per entry; an
+                              unreadable file counts as empty, a failed append is
+                              ignored (the choices still apply).  Copied at create.  */
   void *stream;            /* hipStream_t, or NULL for a library-owned stream             */
 } mabd_options;
 
@@ -195,6 +208,11 @@ typedef struct {
                               tree by the tree contraction, the loop-closing joints (at
                               most 48 rows per component) by a dense Schur system;
                               components with more loop rows are networks (PCG)       */
+  int32_t tree_split;      /* tree schedule in use: 16-row classes launch apart above
+                              this many operations per round (INT32_MAX: never)      */
+  int32_t tree_order;      /* 0 clique classes largest first in a launch, 1 smallest   */
+  int32_t tune_source;     /* 0 default schedules, 1 timed by the autotuner, 2 read from
+                              the tuning cache                                        */
 } mabd_step_stats;
 
 /* Fills *opt with the defaults listed above. */

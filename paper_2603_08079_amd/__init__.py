@@ -56,7 +56,8 @@ class Options(ctypes.Structure):
                 ("hinge_grad", ctypes.c_int32), ("material", ctypes.c_int32),
                 ("diagnostics", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("ir_max_sweeps", ctypes.c_int32),
-                ("body_solve", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("body_solve", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
+                ("stream", ctypes.c_void_p)]
 
 
 NPHASES = 10
@@ -75,7 +76,8 @@ class StepStats(ctypes.Structure):
                 ("tile_threads", ctypes.c_int32), ("graph_replay", ctypes.c_int32),
                 ("tree_rounds", ctypes.c_int32), ("tile_packed", ctypes.c_int32),
                 ("ir_stalled", ctypes.c_int32), ("kkt_newton", ctypes.c_double * NEWTON_DIAG),
-                ("n_loop", ctypes.c_int32)]
+                ("n_loop", ctypes.c_int32), ("tree_split", ctypes.c_int32),
+                ("tree_order", ctypes.c_int32), ("tune_source", ctypes.c_int32)]
 
     PHASES = ("chain_reduce", "chain_global", "chain_apply", "body", "joint", "tree", "apply",
               "pcg", "chain_resid", "chain_finish")
@@ -134,6 +136,8 @@ def default_options(**kw) -> Options:
     for k, v in kw.items():
         if k == "gravity":
             o.gravity[0], o.gravity[1], o.gravity[2] = v
+        elif k == "tune_cache":
+            o.tune_cache = None if v is None else os.fsencode(v)
         else:
             setattr(o, k, v)
     return o

@@ -1418,7 +1418,7 @@ void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, in
 // operations of [o0, o1) with TW-lane teams, TCW / TW per workgroup
 
 void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
-                 hipStream_t s) {
+                 int split_ops, int order, hipStream_t s) {
   if (nslots <= 0) return;
   hipLaunchKernelGGL(tree_prep_kernel, dim3((nslots + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J, nslots);
   // per round, 7 segments of the operation list (o[7] starts the next round):
@@ -1427,19 +1427,22 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
   // global slots).  The planner keeps a round's rakes and compresses
   // independent (a node with a child raked in the round is compressed in a
   // later one), so every LDS-staged class of a round shares one launch, in
-  // both directions.  When the 16-row classes hold many operations
-  // (throughput-bound: their small LDS footprint keeps more of them
-  // resident) they get a launch of their own.  Within a launch the classes
-  // go largest first (workgroups are dispatched in index order, so the
-  // longest operations start first and the short ones fill the tail).
+  // both directions.  When the 16-row classes hold more than split_ops
+  // operations (throughput-bound: their small LDS footprint keeps more of
+  // them resident) they get a launch of their own.  Within a launch the
+  // classes go largest first with order 0 (workgroups are dispatched in
+  // index order, so the longest operations start first and the short ones
+  // fill the tail), smallest first with order 1.  Both are schedule choices
+  // only: every operation of a round is independent of the others.
   static const int tw[TC_NCLASS] = {16, 64, 64, 16, 64, 64};
   static const size_t lds_fwd[TC_NCLASS] = {4 * sizeof(TcwMat<16>),  sizeof(TcwMat<32>),
                                             sizeof(TcwMat<64>),      4 * sizeof(TcwComp<16>),
                                             sizeof(TcwComp<32>),     sizeof(TcwComp<48>)};
   static const size_t lds_back[TC_NCLASS] = {4 * 136 * 8, 528 * 8, 2080 * 8, 4 * 136 * 8, 528 * 8, 1176 * 8};
-  static const int all[TC_NCLASS] = {TC_RAKE64, TC_COMP48, TC_RAKE32, TC_COMP32, TC_RAKE16, TC_COMP16};
-  static const int *small = all + 4, *large = all;
-  constexpr int SPLIT_OPS = 6000;
+  static const int by_size[2][TC_NCLASS] = {{TC_RAKE64, TC_COMP48, TC_RAKE32, TC_COMP32, TC_RAKE16, TC_COMP16},
+                                            {TC_RAKE16, TC_COMP16, TC_RAKE32, TC_RAKE64, TC_COMP32, TC_COMP48}};
+  const int *all = by_size[order == 1 ? 1 : 0];
+  const int *small = order == 1 ? all : all + 4, *large = order == 1 ? all + 2 : all;
   auto launch_classes = [&](const int32_t *o, const int *cl, int ncl, bool back) {
     TcwLaunch L{};
     int nb = 0;
@@ -1459,7 +1462,7 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
       hipLaunchKernelGGL(tcw_round_kernel<false>, dim3(nb), dim3(TCW), lds, s, a, J, L);
   };
   auto launch_round = [&](const int32_t *o, bool back) {
-    if ((o[TC_RAKE16 + 1] - o[TC_RAKE16]) + (o[TC_COMP16 + 1] - o[TC_COMP16]) > SPLIT_OPS) {
+    if ((o[TC_RAKE16 + 1] - o[TC_RAKE16]) + (o[TC_COMP16 + 1] - o[TC_COMP16]) > split_ops) {
       launch_classes(o, small, 2, back);
       launch_classes(o, large, 4, back);
     } else {

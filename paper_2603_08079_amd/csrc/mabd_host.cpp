@@ -47,7 +47,7 @@ void launch_gbody(int b0, int b1, const double *q, const double *qn, const doubl
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
                    double *gl, hipStream_t s);
 void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
-                 hipStream_t s);
+                 int split_ops, int order, hipStream_t s);
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
@@ -239,6 +239,13 @@ struct mabd_ctx {
   // chain_global_kernel (the path of chains beyond ~3.9M rows), for testing
   bool force_top_global = false;
   bool tuned = false;
+  // tree contraction schedule (autotuned): a round's 16-row classes launch
+  // apart when they hold more than tree_split operations; class order within
+  // a launch, 0 largest cliques first, 1 smallest first
+  int tree_split = 6000;
+  int tree_order = 0;
+  int tune_source = 0;     // 0 defaults, 1 timed, 2 read from the tuning cache
+  std::string tune_cache;  // path of the tuning cache file ("" none)
   // captured step graphs, one per state-buffer parity
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   // external wrenches: 6 x ns doubles (solver order, SoA), used while wr_on
@@ -427,6 +434,12 @@ struct PhaseTimer {
 }  // namespace
 
 namespace {
+bool tune_chain(const mabd_ctx *c);
+bool tune_tree(const mabd_ctx *c);
+bool tune_cache_read(const mabd_ctx *c, int &tt, int &pack, int &split, int &order);
+}  // namespace
+
+namespace {
 // Tiles of tile_threads - 2 rows (PACK_T rows for packed tiles) and groups of
 // GROUP_T + 1 interface rows for every chain; descriptors go to preallocated
 // device buffers (sized for the smallest tiles), so re-tuning only rewrites
@@ -501,6 +514,7 @@ void mabd_options_default(mabd_options *o) {
   o->autotune = 1;
   o->ir_max_sweeps = 4;
   o->body_solve = 0;
+  o->tune_cache = nullptr;
   o->stream = nullptr;
 }
 
@@ -613,6 +627,8 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
 
   mabd_ctx *c = new mabd_ctx();
   c->opt = opt;
+  if (opt.tune_cache) c->tune_cache = opt.tune_cache;
+  c->opt.tune_cache = nullptr;  // the context keeps its own copy
   c->n = n;
   c->m = m;
   c->pinned = pinned;
@@ -1431,8 +1447,25 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   c->stats.n_graph = c->ngraph;
   c->stats.n_loop = c->nloop;
   c->stats.n_dyn = c->nd;
+  if (e == hipSuccess && !c->tuned && opt.autotune && (tune_chain(c) || tune_tree(c))) {
+    int tt, pk, split, order;
+    if (tune_cache_read(c, tt, pk, split, order)) {
+      if (!c->chains.empty()) e = build_tiles(c, tt, pk != 0);
+      c->tree_split = split;
+      c->tree_order = order;
+      c->tuned = true;
+      c->tune_source = 2;
+      if (e != hipSuccess) {
+        mabd_destroy(c);
+        return fail(nullptr, MABD_ERR_DEVICE, std::string("device setup failed: ") + hipGetErrorString(e));
+      }
+    }
+  }
   c->stats.tile_threads = c->tile_threads;
   c->stats.tile_packed = c->tile_pack ? 1 : 0;
+  c->stats.tree_split = c->tree_split;
+  c->stats.tree_order = c->tree_order;
+  c->stats.tune_source = c->tune_source;
   c->stats.tree_rounds = ((int)c->tc_rounds.size() - 1) / 7;
   c->stats.rho_p = c->stats.rho_d = c->stats.kkt = -1.0;
   *out = c;
@@ -1804,7 +1837,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       ta.crec = c->d_crec;
       tm.run(5, [&] {
         launch_tree(ta, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
-                    ((int)c->tc_rounds.size() - 1) / 7, s);
+                    ((int)c->tc_rounds.size() - 1) / 7, c->tree_split, c->tree_order, s);
         if (c->nloop > 0) {
           // loop-breaker Schur complement (Case III): the columns
           // S_AA^{-1} S_AD e_j by tree solves of the loop rows' increments
@@ -1819,7 +1852,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
                                c->d_uloop, 1, s);
             tw.glam = c->d_wcol + (size_t)j * ws;
             launch_tree(tw, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
-                        ((int)c->tc_rounds.size() - 1) / 7, s);
+                        ((int)c->tc_rounds.size() - 1) / 7, c->tree_split, c->tree_order, s);
             launch_loop_inject(c->nloop, c->d_loff, c->d_lrow, j, c->d_gj, c->d_gl, c->d_shp, c->d_hinv, c->ns,
                                c->d_uloop, 0, s);
           }
@@ -1909,38 +1942,125 @@ struct NoTimer {
   void run(int, F &&f) { f(); }
 };
 
-// time the whole step for every chain tile size and keep the fastest
+// contexts large enough for the autotuner to time their schedules
+constexpr int TUNE_MIN_ROWS = 20000;
+bool tune_chain(const mabd_ctx *c) { return c->nchain_rows >= TUNE_MIN_ROWS; }
+bool tune_tree(const mabd_ctx *c) { return (int)c->tbody.size() >= TUNE_MIN_ROWS && c->ngraph == 0; }
+
+// Times the whole step for every chain tile form, then for every tree
+// schedule, and keeps the fastest of each.  Every timed step reads the
+// current state and writes only the scratch buffer, so the state does not
+// advance.
 hipError_t autotune(mabd_ctx *c, double h) {
   hipStream_t s = c->stream;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return hipErrorUnknown;
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return hipErrorUnknown; }
   NoTimer nt;
-  int best = c->tile_threads;
-  bool best_pack = c->tile_pack;
-  float best_ms = 1e30f;
   hipError_t e = hipSuccess;
-  const std::pair<int, bool> cand[] = {{64, true}, {64, false}, {128, false}, {256, false}};
-  for (const auto &cv : cand) {
-    const int tt = cv.first;
-    e = build_tiles(c, tt, cv.second);
-    if (e != hipSuccess) break;
+  // one untimed step, then the mean of three
+  auto time_step = [&](float &ms) {
     launch_reset_status(c->d_status, s);
-    e = issue_step(c, h, c->cur, 1 - c->cur, nt);  // writes only the scratch buffer
-    if (e != hipSuccess) break;
+    e = issue_step(c, h, c->cur, 1 - c->cur, nt);
+    if (e != hipSuccess) return;
     (void)hipEventRecord(e0, s);
     for (int r = 0; r < 3; ++r) issue_step(c, h, c->cur, 1 - c->cur, nt);
     (void)hipEventRecord(e1, s);
     e = hipEventSynchronize(e1);
-    if (e != hipSuccess) break;
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_ms) { best_ms = ms; best = tt; best_pack = cv.second; }
+    if (e == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+  };
+  if (tune_chain(c)) {
+    int best = c->tile_threads;
+    bool best_pack = c->tile_pack;
+    float best_ms = 1e30f;
+    const std::pair<int, bool> cand[] = {{64, true}, {64, false}, {128, false}, {256, false}};
+    for (const auto &cv : cand) {
+      e = build_tiles(c, cv.first, cv.second);
+      if (e != hipSuccess) break;
+      float ms = 0.f;
+      time_step(ms);
+      if (e != hipSuccess) break;
+      if (ms < best_ms) { best_ms = ms; best = cv.first; best_pack = cv.second; }
+    }
+    if (e == hipSuccess) e = build_tiles(c, best, best_pack);
+  }
+  if (e == hipSuccess && tune_tree(c)) {
+    const std::pair<int, int> cand[] = {{6000, 0}, {1500, 0}, {INT_MAX, 0}, {6000, 1}, {1500, 1}, {INT_MAX, 1}};
+    std::pair<int, int> best = cand[0];
+    float best_ms = 1e30f;
+    for (const auto &cv : cand) {
+      c->tree_split = cv.first;
+      c->tree_order = cv.second;
+      float ms = 0.f;
+      time_step(ms);
+      if (e != hipSuccess) break;
+      if (ms < best_ms) { best_ms = ms; best = cv; }
+    }
+    c->tree_split = best.first;
+    c->tree_order = best.second;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (e == hipSuccess) e = build_tiles(c, best, best_pack);
   return e;
+}
+
+// Tuning cache: the key names the device and the shape of the schedules
+// (chain rows and count, tree slots and an FNV-1a hash of the contraction
+// rounds' operation offsets); the value is tile threads, packed, tree split
+// threshold and tree class order.
+std::string tune_key(const mabd_ctx *c) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (char &ch : arch)
+    if (ch == ' ' || ch == '=') ch = '_';
+  uint64_t hsh = 1469598103934665603ull;
+  for (int32_t v : c->tc_rounds) {
+    uint32_t u = (uint32_t)v;
+    for (int b = 0; b < 4; ++b) {
+      hsh ^= (u >> (8 * b)) & 0xffu;
+      hsh *= 1099511628211ull;
+    }
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "mabd1 %s cu%d chain %lld/%zu tree %zu/%016llx", arch.c_str(), cus,
+                (long long)c->nchain_rows, c->chains.size(), c->tbody.size(), (unsigned long long)hsh);
+  return buf;
+}
+
+// the cached choices for this context, if the file has its key
+bool tune_cache_read(const mabd_ctx *c, int &tt, int &pack, int &split, int &order) {
+  if (c->tune_cache.empty()) return false;
+  FILE *f = std::fopen(c->tune_cache.c_str(), "r");
+  if (!f) return false;
+  const std::string key = tune_key(c) + " = ";
+  bool found = false;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    if (std::strncmp(line, key.c_str(), key.size()) != 0) continue;
+    int a, b, d, e;
+    if (std::sscanf(line + key.size(), "%d %d %d %d", &a, &b, &d, &e) == 4 &&
+        (a == 64 || a == 128 || a == 256) && (b == 0 || b == 1) && d >= 0 && (e == 0 || e == 1)) {
+      tt = a; pack = b; split = d; order = e;
+      found = true;  // the last valid entry wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_append(const mabd_ctx *c) {
+  if (c->tune_cache.empty()) return;
+  FILE *f = std::fopen(c->tune_cache.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%s = %d %d %d %d\n", tune_key(c).c_str(), c->tile_threads, c->tile_pack ? 1 : 0,
+               c->tree_split, c->tree_order);
+  std::fclose(f);
 }
 
 void drop_graphs(mabd_ctx *c) {
@@ -2080,12 +2200,14 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
     c->h_last = h;
     drop_graphs(c);
   }
-  if (c->opt.autotune && !c->tuned && c->nchain_rows >= 20000) {
+  if (c->opt.autotune && !c->tuned && (tune_chain(c) || tune_tree(c))) {
     const mabd_status st = resolve(c);  // tuning clears the status word
     if (st != MABD_OK) return st;
     hipError_t te = autotune(c, h);
     if (te != hipSuccess) return fail(c, MABD_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(te));
     c->tuned = true;
+    c->tune_source = 1;
+    tune_cache_append(c);
     drop_graphs(c);
   }
   PhaseTimer tm(c);
@@ -2100,6 +2222,9 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
   c->stats.graph_replay = graph ? 1 : 0;
   c->stats.tile_threads = c->tile_threads;
   c->stats.tile_packed = c->tile_pack ? 1 : 0;
+  c->stats.tree_split = c->tree_split;
+  c->stats.tree_order = c->tree_order;
+  c->stats.tune_source = c->tune_source;
   for (int st = 0; st < nsteps; ++st) {
     const int a = c->cur, b = 1 - c->cur;
     hipError_t le;
