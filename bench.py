@@ -149,8 +149,9 @@ def main():
     ap.add_argument("--kkt-tol", type=float, default=1e-10, help="PCG stopping tolerance")
     ap.add_argument("--max-iters", type=int, default=200000, help="PCG iteration cap")
     ap.add_argument("--precision", choices=("auto", "0", "1"), default="auto",
-                    help="0 plain FP64, 1 FP32 bulk + FP64 factor + FP64 refinement (chains), "
-                         "auto: time both on chain workloads and report the faster")
+                    help="0 plain FP64, 1 FP32 bulk + FP64 factor + FP64 refinement (chains, and "
+                         "trees in contexts without loops or networks), auto: time both where form "
+                         "1 applies and report the faster")
     ap.add_argument("--ir-tol", type=float, default=1e-12,
                     help="precision 1: target KKT residual of the refinement")
     ap.add_argument("--wrenches", action="store_true",
@@ -266,7 +267,10 @@ def main():
     forms = {}
     if args.precision in ("auto", "0"):
         forms[0] = timed(ctx)
-    if args.precision in ("auto", "1") and st0["n_chain"]:
+    # form 1 covers chain components and, in contexts without loop or
+    # network components, tree components
+    form1 = st0["n_chain"] or (st0["n_tree"] and not st0["n_graph"] and not st0["n_loop"])
+    if args.precision in ("auto", "1") and form1:
         ctx1 = make(1)
         forms[1] = timed(ctx1)
         if args.precision == "1":

@@ -115,7 +115,16 @@ typedef struct {
                               formed from (where the dual right-hand side all but
                               vanishes, as for a freely falling chain, rho_d is O(1)
                               for any FP64 solution);
-                              NOT_CONVERGED otherwise.  Trees and graphs stay FP64     */
+                              NOT_CONVERGED otherwise.  Tree components (contexts with
+                              newton_iters = 1 and no loop or network component): the
+                              force and local solve (the polar rotation stays FP64)
+                              and the clique matrices L Hbar^{-1} L^T in FP32, the
+                              contraction in FP64, then the FP64 residual of the tree
+                              bodies and joints and correction sweeps (the tree solve
+                              with Hbar^{-1} R^T r_p and r_d as right-hand sides)
+                              under the same rules except the rounding test, checked
+                              on the host: such steps wait.  Loops and networks stay
+                              FP64                                                      */
   double kkt_tol;          /* PCG stop: |r - S lam| <= kkt_tol |r|; precision-1 target of
                               the chain KKT residual; default 1e-10                      */
   int32_t max_iters;       /* PCG iteration cap, default 200000                           */
@@ -236,7 +245,8 @@ mabd_status mabd_create(const mabd_bodies *bodies, const mabd_joints *joints,
    previous call the per-shape factors Hbar^{-1} are rebuilt first (Eq.
    abd_final).  Asynchronous on the context's stream: it returns once the
    steps are queued, except for assemblies with a network component (PCG under
-   host control) and kernel timing (diagnostics bit 1), which wait.  A step
+   host control), precision-1 tree components (refinement under host control)
+   and kernel timing (diagnostics bit 1), which wait.  A step
    that fails (NONFINITE, NOT_CONVERGED, SINGULAR) makes the later queued
    steps do nothing and leaves the state at the last completed step; the
    failure is returned by the next call that reads the outcome (mabd_state,

@@ -86,6 +86,10 @@ struct TreeArgs {
   double *crec;             // compress records
   int zero_c;               // 1: the joints' constraint values are taken as zero (the
                             // loop-breaker's solves with other right-hand sides)
+  const double *cc;         // if set: constraint values read from cc (5 per joint)
+                            // instead of the joint rows (refinement right-hand sides)
+  int f32;                  // 1: the clique matrices K0 = L Hbar^{-1} L^T are formed in
+                            // FP32 (precision form 1; the factorisation stays FP64)
 };
 
 // A component with a few closed loops (Sec. 5, Case III): its joints split

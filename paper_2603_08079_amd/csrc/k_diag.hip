@@ -49,9 +49,12 @@ __global__ __launch_bounds__(DNT) void gdiag_body_kernel(
     double dq_scale, int64_t ns, const int32_t *shp, const double *hinv, const double *shape,
     double g0, double g1, double g2, double h, const double *Rg, const int32_t *inc_off,
     const int32_t *inc, const GJoint *J, const double *gl, const double *glam, const double *wr,
-    const uint32_t *status, double *part, int polar_free) {
+    const uint32_t *status, double *part, int polar_free, double *ucorr) {
   const int64_t b = (int64_t)b0 + blockIdx.x * DNT + threadIdx.x;
   double v[DIAG_PART] = {0, 0, 0, 0, 0, 0};
+  // refinement: a polar-free body takes no correction
+  if (ucorr && b < b1 && polar_free && inc_off[b] == inc_off[b + 1] && !skip_step(status, 0))
+    for (int i = 0; i < 12; ++i) ucorr[i * ns + b] = 0.0;
   // a body that took the polar-free solve does not solve the co-rotated
   // system of Eq. kkt: it is left out of rho_p
   const bool pf = b < b1 && polar_free && inc_off[b] == inc_off[b + 1];
@@ -101,6 +104,11 @@ __global__ __launch_bounds__(DNT) void gdiag_body_kernel(
       v[0] += y[i] * y[i];
       v[1] += u[i] * u[i];
     }
+    // refinement: the correction's local solve Hbar^{-1} R^T r_p (body frame),
+    // the right-hand side in place of u
+    if (ucorr)
+#pragma unroll
+      for (int i = 0; i < 12; ++i) ucorr[i * ns + b] = y[i];
   }
   block_partials(v, part + DIAG_PART * (int64_t)blockIdx.x);
 }
@@ -141,7 +149,7 @@ DEV double rot_joint_value(const GJoint &j, const double *Aa, const double *ta, 
 __global__ __launch_bounds__(DNT) void gdiag_joint_kernel(
     int m, const GJoint *J, const double *gl, const double *Rg, const double *ug,
     const double *dqv, double dq_scale, const double *q_new, int64_t ns, const uint32_t *status,
-    double *part) {
+    double *part, double *ccorr) {
   const int k = blockIdx.x * DNT + threadIdx.x;
   double v[DIAG_PART] = {0, 0, 0, 0, 0, 0};
   if (k < m && !skip_step(status, 0)) {
@@ -184,6 +192,10 @@ __global__ __launch_bounds__(DNT) void gdiag_joint_kernel(
       v[2] += rr[i] * rr[i];
       v[3] += rd[i] * rd[i];
     }
+    // refinement: the correction solves G ddq = -r_d, i.e. the dual system
+    // with r_d in place of C
+    if (ccorr)
+      for (int i = 0; i < 5; ++i) ccorr[5 * (int64_t)k + i] = i < rows ? rd[i] : 0.0;
     // joint values at the new state (Eq. ball; Eqs. hinge, universal,
     // prismatic with R_J from the polar rotation of side a's new affine block)
     auto point_diff = [&](const double *pa_, const double *pb_, double *d) {
@@ -248,19 +260,19 @@ void launch_gdiag_body(int b0, int b1, const double *q, const double *qn, const 
                        const double *hinv, const double *shape, const double *g, double h,
                        const double *Rg, const int32_t *inc_off, const int32_t *inc, const GJoint *J,
                        const double *gl, const double *glam, const double *wr, const uint32_t *status,
-                       double *part, int polar_free, hipStream_t s) {
+                       double *part, int polar_free, double *ucorr, hipStream_t s) {
   if (b1 <= b0) return;
   hipLaunchKernelGGL(gdiag_body_kernel, dim3(diag_body_blocks(b1 - b0)), dim3(DNT), 0, s, b0, b1, q,
                      qn, qdn, dqv, dq_scale, ns, shp, hinv, shape, g[0], g[1], g[2], h, Rg, inc_off,
-                     inc, J, gl, glam, wr, status, part, polar_free);
+                     inc, J, gl, glam, wr, status, part, polar_free, ucorr);
 }
 
 void launch_gdiag_joint(int m, const GJoint *J, const double *gl, const double *Rg, const double *ug,
                         const double *dqv, double dq_scale, const double *q_new, int64_t ns,
-                        const uint32_t *status, double *part, hipStream_t s) {
+                        const uint32_t *status, double *part, double *ccorr, hipStream_t s) {
   if (m <= 0) return;
   hipLaunchKernelGGL(gdiag_joint_kernel, dim3(diag_body_blocks(m)), dim3(DNT), 0, s, m, J, gl, Rg, ug,
-                     dqv, dq_scale, q_new, ns, status, part);
+                     dqv, dq_scale, q_new, ns, status, part, ccorr);
 }
 
 void launch_diag_reduce(const double *part, int nblk, double *out, const uint32_t *status,

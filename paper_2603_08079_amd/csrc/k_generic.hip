@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double
                              int64_t ns, const int32_t *shp, const double *hinv,
                              const double *shape, double g0, double g1, double g2, double h,
                              double *Rg, double *ug, uint32_t *status, int step, const double *wr,
-                             const int32_t *pf_inc) {
+                             const int32_t *pf_inc, int f32) {
   int64_t b = (int64_t)b0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= b1 || skip_step(status, step)) return;
   if (pf_inc && pf_inc[b] == pf_inc[b + 1]) {
@@ -101,11 +101,34 @@ __global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double
   }
   const int s = shp[b];
   const double g[3] = {g0, g1, g2};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Rg[i * ns + b] = R[i];
+  if (f32) {
+    // precision form 1: the rotation stays FP64 (it defines the system the
+    // FP64 refinement solves); force and local solve in FP32.  The force
+    // is formed from the iterate's offset to the step's start, so that FP32
+    // sees only the step's increments, not absolute positions.
+    float Rf[9], Af[9], qf[12], qnf[12], qdf[12], phif[12], uf[12];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      Rf[i] = (float)R[i];
+      Af[i] = (float)A[i];
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      qnf[c] = (float)qnn[c];
+      qf[c] = qnf[c] + (float)(qq[c] - qnn[c]);
+      qdf[c] = (float)qd[c];
+    }
+    local_force<float>(shape + (int64_t)SHAPE_STRIDE * s, Rf, Af, qf, qnf, qdf, g, h, phif, wr, ns, b);
+    hinv_apply(hinv + (int64_t)HINV_STRIDE * s, phif, uf);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) ug[i * ns + b] = (double)uf[i];
+    return;
+  }
   double phi[12], u[12];
   local_force<double>(shape + (int64_t)SHAPE_STRIDE * s, R, A, qq, qnn, qd, g, h, phi, wr, ns, b);
   hinv_apply(hinv + (int64_t)HINV_STRIDE * s, phi, u);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) Rg[i * ns + b] = R[i];
 #pragma unroll
   for (int i = 0; i < 12; ++i) ug[i * ns + b] = u[i];
 }
@@ -385,7 +408,9 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
     cv[k] = 0.0;
     if (i < nr) {
       const int e = S.rowent[i], ei = S.ei[e];
-      if ((ei & 2) && !a.zero_c) cv[k] = a.gl[(int64_t)GL_STRIDE * S.ek[e] + GL_C + (i - (ei >> 8))];
+      if ((ei & 2) && !a.zero_c)
+        cv[k] = a.cc ? a.cc[5 * (int64_t)S.ek[e] + (i - (ei >> 8))]
+                     : a.gl[(int64_t)GL_STRIDE * S.ek[e] + GL_C + (i - (ei >> 8))];
     }
   }
   //    clique rows L (nr x 12), eight independent loads per lane in flight
@@ -412,7 +437,18 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   if (!big) {
     // 2-3) K0 = L Hbar^{-1} L^T (lower triangle): lane j holds
     //      y_j = Hbar^{-1} L_j^T in registers and forms column j
-    if (ln < nr) {
+    if (ln < nr && a.f32) {
+      float lf[12], yv[12];
+#pragma unroll
+      for (int s = 0; s < 12; ++s) lf[s] = (float)Lm[12 * ln + s];
+      hinv_apply(S.th, lf, yv);
+      for (int i = ln; i < nr; ++i) {
+        float v = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 12; ++s) v += (float)Lm[12 * i + s] * yv[s];
+        fac[i * LD + ln] = (double)v;
+      }
+    } else if (ln < nr) {
       double yv[12];
       hinv_apply(S.th, Lm + 12 * ln, yv);
       for (int i = ln; i < nr; ++i) {
@@ -437,9 +473,15 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
       while (i * (i + 1) / 2 > idx) --i;
       while ((i + 1) * (i + 2) / 2 <= idx) ++i;
       const int jj = idx - i * (i + 1) / 2;
-      double v = 0.0;
-      for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * Ym[s * nr + jj];
-      fac[i * LD + jj] = v;
+      if (a.f32) {
+        float v = 0.0f;
+        for (int s = 0; s < 12; ++s) v += (float)Lm[12 * i + s] * (float)Ym[s * nr + jj];
+        fac[i * LD + jj] = (double)v;
+      } else {
+        double v = 0.0;
+        for (int s = 0; s < 12; ++s) v += Lm[12 * i + s] * Ym[s * nr + jj];
+        fac[i * LD + jj] = v;
+      }
     }
   }
   //    y0 = L u + C of one-sided and parent rows
@@ -1405,10 +1447,26 @@ void launch_prefactor(const double *shape, int nshape, double h, double *hinv, h
 void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
                   const int32_t *shp, const double *hinv, const double *shape, const double *g,
                   double h, double *Rg, double *ug, uint32_t *status, int step, const double *wr,
-                  const int32_t *pf_inc, hipStream_t s) {
+                  const int32_t *pf_inc, int f32, hipStream_t s) {
   if (b1 > b0)
     hipLaunchKernelGGL(gbody_kernel, dim3((b1 - b0 + 255) / 256), dim3(256), 0, s, b0, b1, q, qn, qdn,
-                       ns, shp, hinv, shape, g[0], g[1], g[2], h, Rg, ug, status, step, wr, pf_inc);
+                       ns, shp, hinv, shape, g[0], g[1], g[2], h, Rg, ug, status, step, wr, pf_inc, f32);
+}
+// glam += dlam over n entries (refinement: the correction's multipliers)
+__global__ void lam_add_kernel(int64_t n, double *glam, const double *dlam, const uint32_t *status) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n || skip_step(status, 0)) return;
+  glam[i] += dlam[i];
+}
+void launch_lam_add(int64_t n, double *glam, const double *dlam, const uint32_t *status, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(lam_add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, glam, dlam, status);
+}
+// raise a status flag for the current step from the host's decision
+__global__ void raise_kernel(uint32_t *status, uint32_t flag) {
+  if (threadIdx.x == 0 && !skip_step(status, 0)) raise_flag(status, flag, 0);
+}
+void launch_raise(uint32_t *status, uint32_t flag, hipStream_t s) {
+  hipLaunchKernelGGL(raise_kernel, dim3(1), dim3(64), 0, s, status, flag);
 }
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
                    double *gl, hipStream_t s) {

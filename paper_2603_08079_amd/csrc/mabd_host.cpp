@@ -43,7 +43,9 @@ void launch_prefactor(const double *shape, int nshape, double h, double *hinv, h
 void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
                   const int32_t *shp, const double *hinv, const double *shape, const double *g,
                   double h, double *Rg, double *ug, uint32_t *status, int step, const double *wr,
-                  const int32_t *pf_inc, hipStream_t s);
+                  const int32_t *pf_inc, int f32, hipStream_t s);
+void launch_lam_add(int64_t n, double *glam, const double *dlam, const uint32_t *status, hipStream_t s);
+void launch_raise(uint32_t *status, uint32_t flag, hipStream_t s);
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
                    double *gl, hipStream_t s);
 void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
@@ -62,10 +64,10 @@ void launch_gdiag_body(int b0, int b1, const double *q, const double *qn, const 
                        const double *hinv, const double *shape, const double *g, double h,
                        const double *Rg, const int32_t *inc_off, const int32_t *inc, const GJoint *J,
                        const double *gl, const double *glam, const double *wr, const uint32_t *status,
-                       double *part, int polar_free, hipStream_t s);
+                       double *part, int polar_free, double *ucorr, hipStream_t s);
 void launch_gdiag_joint(int m, const GJoint *J, const double *gl, const double *Rg, const double *ug,
                         const double *dqv, double dq_scale, const double *q_new, int64_t ns,
-                        const uint32_t *status, double *part, hipStream_t s);
+                        const uint32_t *status, double *part, double *ccorr, hipStream_t s);
 void launch_diag_reduce(const double *part, int nblk, double *out, const uint32_t *status,
                         hipStream_t s);
 int resid_static_blocks();
@@ -245,6 +247,13 @@ struct mabd_ctx {
   int tree_split = 6000;
   int tree_order = 0;
   int tune_source = 0;     // 0 defaults, 1 timed, 2 read from the tuning cache
+  // precision form 1 on the generic components (trees): FP32 local solves
+  // and clique assembly, FP64 factor, host-controlled FP64 refinement
+  bool gen_ir = false;
+  double *d_uc = nullptr, *d_cc = nullptr, *d_dlam = nullptr;  // correction rhs, multipliers
+  double *d_irpart = nullptr, *d_irout = nullptr, *h_irout = nullptr;
+  int gir_sweeps = 0, gir_stalled = 0;
+  double gir_rho_p = -1.0, gir_rho_d = -1.0, gir_kkt = -1.0;
   std::string tune_cache;  // path of the tuning cache file ("" none)
   // captured step graphs, one per state-buffer parity
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -533,6 +542,7 @@ void mabd_destroy(mabd_ctx *c) {
   if (c->h_pb_si) (void)hipHostFree(c->h_pb_si);
   if (c->h_gsc) (void)hipHostFree(c->h_gsc);
   if (c->h_diag) (void)hipHostFree(c->h_diag);
+  if (c->h_irout) (void)hipHostFree(c->h_irout);
   if (c->pend_ev) (void)hipEventDestroy(c->pend_ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -1417,6 +1427,21 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   }
   if (e == hipSuccess) chk(dalloc(c, &c->d_diag, DIAG_VALUES));
   if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_diag, DIAG_VALUES * sizeof(double)));
+  // precision form 1 on the generic components: one Newton iteration, no
+  // loop or network component (those stay FP64)
+  c->gen_ir = opt.precision == 1 && opt.newton_iters == 1 && c->gb1 > c->gb0 && c->ngraph == 0 &&
+              c->nloop == 0;
+  if (c->gen_ir) {
+    const size_t mgi = std::max<size_t>(c->gj.size(), 1);
+    if (e == hipSuccess) chk(dalloc(c, &c->d_uc, (size_t)12 * ns));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_cc, 5 * mgi));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_dlam, 5 * mgi));
+    if (e == hipSuccess)
+      chk(dalloc(c, &c->d_irpart, (size_t)DIAG_PART * (diag_body_blocks(c->gb1 - c->gb0) +
+                                                      diag_body_blocks((int)c->gj.size()))));
+    if (e == hipSuccess) chk(dalloc(c, &c->d_irout, 5));
+    if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_irout, 6 * sizeof(double)));
+  }
   if (opt.diagnostics & 1) {
     // sized here, while the tiles are the smallest (most numerous) form
     if (e == hipSuccess) chk(dalloc(c, &c->d_dpart, (size_t)DIAG_PART * diag_nblk(c)));
@@ -1596,7 +1621,7 @@ hipError_t gnn_prepare(mabd_ctx *c, double h, PcgBallArgs &pb) {
   const int a = c->cur;
   launch_gbody(c->gb0, c->gb1, c->d_q[a], c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv, c->d_shape,
                c->opt.gravity, h, c->d_Rg, c->d_ug, c->d_status, 0, c->wr_on ? c->d_wr : nullptr,
-               nullptr, s);  // network bodies have joints: always the polar solve
+               nullptr, 0, s);  // network bodies have joints: always the polar solve
   launch_gjoint((int)c->gj.size(), c->d_gj, c->d_q[a], c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
   pb = make_ball_args(c, c->opt.kkt_tol, c->opt.max_iters, 0);
   launch_pb_setup(pb, s);
@@ -1742,12 +1767,81 @@ void issue_residual(mabd_ctx *c, double h, int a, int b, const double *q_it, con
   launch_gdiag_body(c->gb0, c->gb1, q_it, c->d_q[a], c->d_qd[a], dqv, dq_scale, c->ns, c->d_shp,
                     c->d_hinv, c->d_shape, c->opt.gravity, h, c->d_Rg, c->d_inc_off, c->d_inc, c->d_gj,
                     c->d_gl, c->d_glam, c->wr_on ? c->d_wr : nullptr, c->d_status,
-                    part + DIAG_PART * off, c->opt.body_solve, s);
+                    part + DIAG_PART * off, c->opt.body_solve, nullptr, s);
   off += diag_body_blocks(c->gb1 - c->gb0);
   launch_gdiag_joint((int)c->gj.size(), c->d_gj, c->d_gl, c->d_Rg, c->d_ug, dqv, dq_scale, c->d_q[b],
-                     c->ns, c->d_status, part + DIAG_PART * off, s);
+                     c->ns, c->d_status, part + DIAG_PART * off, nullptr, s);
   off += diag_body_blocks((int)c->gj.size());
   launch_diag_reduce(part, (int)off, out, c->d_status, s);
+}
+
+// Precision form 1 on the generic components (trees): after the FP32 solve
+// of the step, the FP64 KKT residual of the generic bodies and joints (read
+// by the host) decides: converged, stalled at the rounding floor (a sweep
+// that no longer halves it; accepted within 10 kkt_tol), or a correction
+// sweep: the same tree solve with Hbar^{-1} R^T r_p in place of u and r_d
+// in place of C, whose increment and multipliers are added to the step's.
+// Host-controlled: each check waits for the stream.
+hipError_t generic_refine(mabd_ctx *c, double h, int a, int b, const TreeArgs &ta) {
+  hipStream_t s = c->stream;
+  const int mg = (int)c->gj.size();
+  const double tol = c->opt.kkt_tol;
+  const int nsw = c->opt.ir_max_sweeps;
+  c->gir_sweeps = 0;
+  c->gir_stalled = 0;
+  double prev = 0.0;
+  for (int sw = 0;; ++sw) {
+    const bool last = sw == nsw;
+    double *uc = last ? nullptr : c->d_uc, *cc = last ? nullptr : c->d_cc;
+    launch_gdiag_body(c->gb0, c->gb1, c->d_q[a], c->d_q[a], c->d_qd[a], c->d_qd[b], h, c->ns, c->d_shp,
+                      c->d_hinv, c->d_shape, c->opt.gravity, h, c->d_Rg, c->d_inc_off, c->d_inc, c->d_gj,
+                      c->d_gl, c->d_glam, c->wr_on ? c->d_wr : nullptr, c->d_status, c->d_irpart,
+                      c->opt.body_solve, uc, s);
+    const int off = diag_body_blocks(c->gb1 - c->gb0);
+    launch_gdiag_joint(mg, c->d_gj, c->d_gl, c->d_Rg, c->d_ug, c->d_qd[b], h, c->d_q[b], c->ns, c->d_status,
+                       c->d_irpart + DIAG_PART * (int64_t)off, cc, s);
+    launch_diag_reduce(c->d_irpart, off + diag_body_blocks(mg), c->d_irout, c->d_status, s);
+    hipError_t e = hipMemcpyAsync(c->h_irout, c->d_irout, 5 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->h_irout + 5, c->d_status, 2 * sizeof(uint32_t),
+                                            hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    uint32_t st[2];
+    std::memcpy(st, c->h_irout + 5, sizeof st);
+    if (st[0] != 0u) return hipSuccess;  // an earlier failure of this step: nothing to refine
+    const double kkt = c->h_irout[2];
+    c->gir_rho_p = c->h_irout[0];
+    c->gir_rho_d = c->h_irout[1];
+    c->gir_kkt = kkt;
+    if (!std::isfinite(kkt)) {
+      launch_raise(c->d_status, FLAG_NONFINITE, s);
+      break;
+    }
+    if (kkt <= tol) break;
+    if (sw > 0 && !(kkt < 0.5 * prev)) {
+      if (kkt <= 10.0 * tol) c->gir_stalled = 1;
+      else launch_raise(c->d_status, FLAG_NOTCONV, s);
+      break;
+    }
+    if (last) {
+      launch_raise(c->d_status, FLAG_NOTCONV, s);
+      break;
+    }
+    prev = kkt;
+    TreeArgs tc = ta;
+    tc.u = c->d_uc;
+    tc.cc = c->d_cc;
+    tc.glam = c->d_dlam;
+    tc.f32 = 1;
+    launch_tree(tc, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(), ((int)c->tc_rounds.size() - 1) / 7,
+                c->tree_split, c->tree_order, s);
+    launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_dlam, c->d_Rg, c->d_uc, c->ns,
+                  c->d_shp, c->d_hinv, c->d_q[b], c->d_q[b], c->d_qd[b], h, 1, c->d_status, c->d_gj, 0,
+                  nullptr, c->opt.body_solve, s);
+    launch_lam_add(5 * (int64_t)mg, c->d_glam, c->d_dlam, c->d_status, s);
+    ++c->gir_sweeps;
+  }
+  return hipGetLastError();
 }
 
 // Launch sequence of one step reading state buffer a and writing buffer b.
@@ -1809,7 +1903,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       tm.run(3, [&] {
         launch_gbody(c->gb0, c->gb1, qcur, c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv,
                      c->d_shape, g, h, c->d_Rg, c->d_ug, c->d_status, 0, c->wr_on ? c->d_wr : nullptr,
-                     c->opt.body_solve == 1 ? c->d_inc_off : nullptr, s);
+                     c->opt.body_solve == 1 ? c->d_inc_off : nullptr, c->gen_ir ? 1 : 0, s);
       });
       tm.run(4, [&] {
         launch_gjoint((int)c->gj.size(), c->d_gj, qcur, c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
@@ -1835,6 +1929,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       ta.fac = c->d_fac;
       ta.ops = c->d_tc_ops;
       ta.crec = c->d_crec;
+      ta.f32 = c->gen_ir ? 1 : 0;
       tm.run(5, [&] {
         launch_tree(ta, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
                     ((int)c->tc_rounds.size() - 1) / 7, c->tree_split, c->tree_order, s);
@@ -1917,6 +2012,11 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
                       c->ns, c->d_shp, c->d_hinv, qcur, c->d_q[b], c->d_qd[b], h, it > 0 ? 1 : 0,
                       c->d_status, c->d_gj, 0, dg_it ? c->d_dqit : nullptr, c->opt.body_solve, s);
       });
+      if (c->gen_ir) {
+        hipError_t re = hipSuccess;
+        tm.run(8, [&] { re = generic_refine(c, h, a, b, ta); });
+        if (re != hipSuccess) return re;
+      }
       if (dg_it) {
         const int slot = std::min(it, MABD_NEWTON_DIAG - 1);
         issue_residual(c, h, a, b, it > 0 ? c->d_qit : c->d_q[a], c->d_dqit, 1.0, c->d_dpart,
@@ -2126,6 +2226,15 @@ mabd_status resolve(mabd_ctx *c) {
     c->stats.rho_d = c->h_ir[3];
     c->stats.kkt = c->h_ir[4];
   }
+  if (c->gen_ir) {
+    // and of the generic components (the larger of the two where both exist)
+    const bool both = c->d_ir != nullptr;
+    c->stats.ir_sweeps = both ? std::max(c->stats.ir_sweeps, c->gir_sweeps) : c->gir_sweeps;
+    c->stats.ir_stalled = (both && c->stats.ir_stalled) || c->gir_stalled ? 1 : 0;
+    c->stats.rho_p = both ? std::max(c->stats.rho_p, c->gir_rho_p) : c->gir_rho_p;
+    c->stats.rho_d = both ? std::max(c->stats.rho_d, c->gir_rho_d) : c->gir_rho_d;
+    c->stats.kkt = both ? std::max(c->stats.kkt, c->gir_kkt) : c->gir_kkt;
+  }
   for (int i = 0; i < MABD_NEWTON_DIAG; ++i) c->stats.kkt_newton[i] = -1.0;
   if ((c->opt.diagnostics & 1) && c->d_dpart) {
     // the FP64 KKT residual of the last step evaluated on the device
@@ -2216,7 +2325,7 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
     c->pend_cur0 = c->cur;
     c->pend_steps = 0;
   }
-  bool graph = c->opt.use_graph && c->ngraph == 0 && !tm.on && !c->graph_failed;
+  bool graph = c->opt.use_graph && c->ngraph == 0 && !c->gen_ir && !tm.on && !c->graph_failed;
   if (graph && !c->gexec[0]) capture_graphs(c, h);
   graph = graph && c->gexec[0] && c->gexec[1];
   c->stats.graph_replay = graph ? 1 : 0;
@@ -2252,7 +2361,7 @@ mabd_status mabd_step(mabd_ctx *c, double h, int32_t nsteps) {
   c->pending = true;
   // networks are solved under host control and kernel timing needs the
   // events: those steps have synchronised already, so read the status now
-  if (c->ngraph > 0 || tm.on) {
+  if (c->ngraph > 0 || c->gen_ir || tm.on) {
     const mabd_status st = resolve(c);
     tm.collect();
     return st;

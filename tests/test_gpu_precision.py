@@ -1,6 +1,9 @@
-"""Precision form 1 on chain components: FP32 body solve and dual assembly,
-FP64 factor, FP64 KKT residual and correction sweeps until the KKT residual
-max(rho_p, rho_d) is at most kkt_tol.
+"""Precision form 1: FP32 body solve and dual assembly, FP64 factor, FP64 KKT
+residual and correction sweeps until the KKT residual max(rho_p, rho_d) is at
+most kkt_tol.  Chain components run it on the fused chain path (device-side
+sweep control); tree components (contexts without loop or network
+components) in the tree contraction, the force and local solve and the
+clique matrices in FP32, the sweeps under host control.
 
 Form 1 must land on the same per-step KKT solution as the plain FP64 path, so
 it is held to the same parity bar against the oracle (relative 1e-10 on q and
@@ -67,7 +70,8 @@ def test_form1_reports_residual_and_sweeps():
 
 
 def test_form1_mixed_with_tree():
-    """Form 1 covers chain components; a tree in the same context stays FP64."""
+    """Form 1 on a chain and a tree in one context lands on the plain FP64
+    solution."""
     import paper_2603_08079_amd as pk
 
     parts = [mi.chain(700, seed=105), mi.tree(200, seed=106, origin=(0.0, 25.0, 0.0))]
@@ -140,3 +144,133 @@ def test_form1_full_size_chain_one_step():
     # the same KKT residual as the oracle's direct FP64 solve reaches there
     assert st["kkt"] <= max(1e-12, 2 * d[oracle.KKT])
     assert eq < TOL and eqd < TOL
+
+
+# ------------------------------------------------------------ tree components
+def test_form1_tree_parity():
+    """Trees (ball and hinge joints), a hinge chain (tree path) and a tree of
+    all four joint types, every step against the oracle at the FP64 bar."""
+    t = mi.tree(400, seed=111)
+    t.qd0[1:] = np.random.default_rng(111).normal(0, 0.05, (t.n - 1, 12))
+    say("form 1 tree of 400")
+    say("worst", teacher_forced(t, 3, tol_v=TOL, **F1))
+    c = mi.chain(500, seed=112, hinge_frac=0.5)
+    c.qd0[1:] = np.random.default_rng(112).normal(0, 0.05, (c.n - 1, 12))
+    say("form 1 hinge chain of 500")
+    say("worst", teacher_forced(c, 3, tol_v=TOL, **F1))
+    m = mi.mix_joint_types(mi.tree(300, seed=113), seed=114)
+    m.qd0[1:] = np.random.default_rng(113).normal(0, 0.05, (m.n - 1, 12))
+    say("form 1 mixed-joint tree of 300")
+    say("worst", teacher_forced(m, 3, tol_v=TOL, **F1))
+
+
+def test_form1_tree_world_joints():
+    from test_oracle_joint_pins import mixed_assemblies
+
+    for name, asm in mixed_assemblies():
+        say("form 1", name)
+        say("worst", teacher_forced(asm, 2, tol_v=TOL, **F1))
+
+
+def test_form1_tree_reports_residual_and_sweeps():
+    import paper_2603_08079_amd as pk
+
+    t = mi.tree(3000, seed=115)
+    t.qd0[1:] = np.random.default_rng(115).normal(0, 0.05, (t.n - 1, 12))
+    ctx = pk.Context(t, **F1)
+    plain = pk.Context(t, diagnostics=1)
+    for n in range(3):
+        ctx.step(t.h, 1)
+        plain.step(t.h, 1)
+        st, sp = ctx.stats(), plain.stats()
+        say(n, "sweeps", st["ir_sweeps"], "stalled", st["ir_stalled"], "kkt", st["kkt"],
+            "plain FP64 kkt", sp["kkt"])
+        assert 1 <= st["ir_sweeps"] <= 4 and st["last_status"] == 0
+        assert st["kkt"] == max(st["rho_p"], st["rho_d"])
+        assert st["kkt"] <= F1["kkt_tol"] or (st["ir_stalled"] and st["kkt"] <= 10 * F1["kkt_tol"])
+    q1, qd1 = ctx.state()
+    q0, qd0 = plain.state()
+    eq, eqd = state_errors(q1, qd1, q0, qd0)
+    say("form 1 vs plain after 3 steps", eq, eqd)
+    assert eq < TOL and eqd < TOL
+
+
+def test_form1_tree_not_converged_keeps_state():
+    """Without correction sweeps the FP32 tree solve stays above the target;
+    the step waits for its checks, so mabd_step itself reports it."""
+    import paper_2603_08079_amd as pk
+
+    t = mi.tree(500, seed=116)
+    ctx = pk.Context(t, precision=1, kkt_tol=1e-12, ir_max_sweeps=0)
+    q0, qd0 = ctx.state()
+    with pytest.raises(pk.MabdError) as ei:
+        ctx.step(t.h, 2)
+    assert ei.value.status == pk.ERR_NOT_CONVERGED
+    st = ctx.stats()
+    say("kkt of the FP32 tree solve", st["kkt"])
+    assert st["ir_sweeps"] == 0 and st["kkt"] > 1e-12 and st["steps_done"] == 0
+    q1, qd1 = ctx.state()
+    assert np.array_equal(q0, q1) and np.array_equal(qd0, qd1)
+
+
+def test_form1_batch_of_chains_and_trees():
+    """A small batch: ball chains in the fused form 1, hinge chains and trees
+    in the tree form 1, against the plain FP64 solve of the same context
+    shape."""
+    import paper_2603_08079_amd as pk
+
+    asm = mi.concat([mi.batch(24, seed=117, hi=600), mi.chain(800, seed=119, origin=(0.0, -30.0, 0.0))],
+                    h=1e-2, steps=2)
+    asm.qd0[:] = np.random.default_rng(117).normal(0, 0.05, asm.qd0.shape)
+    asm.qd0[asm.pinned == 1] = 0.0
+    f1 = pk.Context(asm, **F1)
+    p0 = pk.Context(asm)
+    st0 = f1.stats()
+    say("batch of 24:", asm.n, "bodies, chains", st0["n_chain"], "trees", st0["n_tree"])
+    assert st0["n_chain"] >= 1 and st0["n_tree"] >= 1
+    for _ in range(2):
+        f1.step(asm.h, 1)
+        p0.step(asm.h, 1)
+        st = f1.stats()
+        assert st["last_status"] == 0 and st["ir_sweeps"] >= 1
+    q1, qd1 = f1.state()
+    q0, qd0 = p0.state()
+    eq, eqd = state_errors(q1, qd1, q0, qd0)
+    say("form 1 vs plain", eq, eqd, "kkt", f1.stats()["kkt"])
+    assert eq < TOL and eqd < TOL
+
+
+def test_form1_with_loops_stays_fp64():
+    """A context with a loop component keeps its generic components FP64 (no
+    sweeps are reported for them)."""
+    import paper_2603_08079_amd as pk
+    from test_gpu_loops import ring
+
+    asm = ring(64, seed=118)
+    f1 = pk.Context(asm, **F1)
+    p0 = pk.Context(asm)
+    assert f1.stats()["n_loop"] == 1
+    f1.step(asm.h, 1)
+    p0.step(asm.h, 1)
+    assert f1.stats()["ir_sweeps"] == 0
+    q1, qd1 = f1.state()
+    q0, qd0 = p0.state()
+    assert np.array_equal(q1, q0) and np.array_equal(qd1, qd0)
+
+
+def test_form1_full_size_tree_one_step():
+    """The 262,144-body tree in form 1 against the plain FP64 GPU solve (both
+    at the FP64 floor), as the benchmark runs it."""
+    import paper_2603_08079_amd as pk
+
+    asm = mi.config("tree256k")
+    f1 = pk.Context(asm, precision=1, kkt_tol=1e-12)
+    p0 = pk.Context(asm, diagnostics=1)
+    f1.step(asm.h, 1)
+    p0.step(asm.h, 1)
+    st, sp = f1.stats(), p0.stats()
+    q1, qd1 = f1.state()
+    q0, qd0 = p0.state()
+    eq, eqd = state_errors(q1, qd1, q0, qd0)
+    say("tree256k form 1: sweeps", st["ir_sweeps"], "kkt", st["kkt"], "plain kkt", sp["kkt"], "err", eq, eqd)
+    assert st["kkt"] <= 1e-12 and eq < TOL and eqd < TOL
