@@ -39,12 +39,50 @@ ALG_BYTES = {
 # residual kernel is priced: q, qdot, dq read (288 B), anchors, flags and shape
 # index (53 B), multipliers read (24 B), residuals written (96 + 24 B).
 ALG_BYTES_F1 = {"chain_resid": 288 + 53 + 24 + 120}
+JOINT_ROWS = (3, 5, 4, 5)  # ball, hinge, universal, prismatic
+
+
+def generic_alg_bytes(asm, phase):
+    """Algorithmic HBM bytes per launch of a kernel group of the generic
+    (tree) path, FP64, for a context without chain components.  A joint row
+    on one dynamic side is 12 doubles (96 B); a body's state q, qdot is 192 B,
+    its rotation 72 B, its local solve 96 B, its shape index 4 B; a joint's
+    record is 200 B, its values C and multipliers 8 B per row.
+      body:  q, qdot, shape index read; R and u written.
+      joint: records, both sides' A, t and R read (168 B per dynamic side);
+             rows and C written.
+      tree:  u and shape index read per body, every row and C read, the
+             multipliers written (the clique matrices are intermediate).
+      apply: rows and multipliers of the incident joints, R, u, shape index
+             and q, qdot read; q, qdot written."""
+    import numpy as np
+
+    dyn = np.asarray(asm.pinned) == 0
+    nb = int(dyn.sum())
+    rows = np.asarray(JOINT_ROWS)[np.asarray(asm.jtype, int)] if asm.m else np.zeros(0, int)
+    ja, jb = np.asarray(asm.ja), np.asarray(asm.jb)
+    sides = ((ja >= 0) & dyn[np.clip(ja, 0, None)]).astype(int) + ((jb >= 0) & dyn[np.clip(jb, 0, None)]).astype(int)
+    side_rows = int((rows * sides).sum())
+    nrows = int(rows.sum())
+    if phase == "body":
+        return nb * (192 + 4 + 72 + 96)
+    if phase == "joint":
+        return int(asm.m) * 200 + int(sides.sum()) * 168 + side_rows * 96 + nrows * 8
+    if phase == "tree":
+        return nb * (96 + 4) + side_rows * 96 + nrows * 16
+    if phase == "apply":
+        return nb * (72 + 96 + 4 + 192 + 192) + side_rows * (96 + 8)
+    return None
 # HBM bytes per launch of the dominant kernel measured with rocprofv3 --pmc
 # (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, scales from a plain 512 MiB copy),
 # keyed by workload, kernel, tile threads and tile packing, together with the
 # SHA-256 (first 16 hex digits) of the kernel source the counters were taken
 # on: once that source changes the figure is stale and `traffic` is null.
-PMC_TRAFFIC = {}
+PMC_TRAFFIC = {
+    # profiles/chain1m_fp64_kernels.md: FETCH_SIZE 149,036.9 KiB x2.000,
+    # WRITE_SIZE 221,791.7 KiB x1.000 per dispatch of the packed apply kernel
+    ("chain1m", "chain_apply", 64, 1): ("0a0ad516dddf1630", 532342272),
+}
 PMC_SOURCE = os.path.join(ROOT, "paper_2603_08079_amd", "csrc", "k_chain.hip")
 
 
@@ -312,8 +350,10 @@ def main():
     dom = max(per_launch, key=lambda k: per_launch[k] * sp["phase_calls"][phases.index(k)])
     roof = None
     ab = ALG_BYTES if chosen == 0 else ALG_BYTES_F1
-    if dom in ab:
-        alg = ab[dom] * n_dyn
+    alg = ab[dom] * n_dyn if dom in ab else None
+    if alg is None and chosen == 0 and st0["n_chain"] == 0 and not st0["n_graph"]:
+        alg = generic_alg_bytes(asm, dom)
+    if alg is not None:
         ach = alg / (per_launch[dom] * 1e-3) / 1e9
         key = (args.workload, dom, st["tile_threads"], st["tile_packed"])
         traffic = None
