@@ -127,7 +127,7 @@ def slice_bodies(asm, nb):
         cp_len=asm.cp_len[jm], meta={})
 
 
-def cpu_baseline(asm, wrench, q, qd, workload, nb, steps):
+def cpu_baseline(asm, wrench, q, qd, workload, nb, steps, body_solve=0):
     """The FP64 oracle (the same C source, built -O3 -march=native for this
     host) timed on `steps` steps of a bounded sample of the workload: its
     first `nb` bodies, from the benchmark's final state.  Two legs: one
@@ -153,7 +153,7 @@ def cpu_baseline(asm, wrench, q, qd, workload, nb, steps):
                     threads = int(ctypes.CDLL("libgomp.so.1").omp_get_max_threads())
                 except OSError:
                     threads = os.cpu_count()
-            sysm = oracle.System(sub, wrench=w, L=L)
+            sysm = oracle.System(sub, wrench=w, L=L, body_solve=body_solve)
             qq, qqd = q[:nb].copy(), qd[:nb].copy()
             t0 = time.perf_counter()
             for _ in range(steps):
@@ -192,6 +192,8 @@ def main():
                          "1 applies and report the faster")
     ap.add_argument("--ir-tol", type=float, default=1e-12,
                     help="precision 1: target KKT residual of the refinement")
+    ap.add_argument("--body-solve", type=int, choices=(0, 1), default=0,
+                    help="1: bodies without joints take the polar-free solve (Alg. 1)")
     ap.add_argument("--wrenches", action="store_true",
                     help="apply a seeded wind-like load at every step: force 0.2 m g along +x with "
                          "2 %% noise, torques of 1 %% of m g times the body size")
@@ -247,7 +249,7 @@ def main():
     def make(precision, **kw):
         tol = args.ir_tol if precision == 1 else args.kkt_tol
         c = pk.Context(asm, stream=stream.cuda_stream, precision=precision, kkt_tol=tol,
-                       max_iters=args.max_iters, **kw)
+                       max_iters=args.max_iters, body_solve=args.body_solve, **kw)
         if wrench is not None:
             c.set_wrenches(wrench)
         return c
@@ -374,7 +376,7 @@ def main():
     if not args.no_kkt_check or not args.no_cpu_baseline:
         import oracle
 
-        s = oracle.System(asm, wrench=wrench)
+        s = oracle.System(asm, wrench=wrench, body_solve=args.body_solve)
         q_n, qd_n = ctx.state()
     if not args.no_kkt_check:
         # one more GPU step from the current (moving) state, verified by the
@@ -392,7 +394,8 @@ def main():
                "device_residual": dres}
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(asm, wrench, q_n, qd_n, args.workload,
-                           min(args.cpu_sample_bodies, asm.n), args.cpu_sample_steps)
+                           min(args.cpu_sample_bodies, asm.n), args.cpu_sample_steps,
+                           body_solve=args.body_solve)
         print(f"# cpu baseline {cpu}", file=sys.stderr, flush=True)
         if kkt is not None and asm.n <= 2_000_000:
             # the oracle's own full step from the same state: the KKT residual
@@ -415,6 +418,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "bodies": asm.n, "dynamic_bodies": n_dyn,
                    "joints": asm.m, "h": h, "newton_iters": 1, "wrenches": bool(args.wrenches),
+                   "body_solve": args.body_solve,
                    "form": FORMS[chosen], "graph_replay": bool(st["graph_replay"]),
                    "chain_tile_threads": st["tile_threads"],
                    "chain_tiles_packed": bool(st["tile_packed"])},
