@@ -157,12 +157,75 @@ __global__ __launch_bounds__(GR * NO / 16) void gnn_gemm_kernel(const float *X, 
   }
 }
 
+// The same product on the matrix cores: v_mfma_f32_16x16x4_f32 takes a
+// 16 x 4 block of A (lane l: row l mod 16, column l / 16), a 4 x 16 block of
+// B (lane l: row l / 16, column l mod 16) and accumulates the 16 x 16 block
+// of D in four registers (lane l, register j: row 4 (l / 16) + j, column
+// l mod 16).  A workgroup of four waves takes 64 rows; each wave its 16 rows
+// times all NO outputs (NO / 16 blocks), K / 4 steps of the contraction.
+// X (rows padded to K + 1 floats) and W are staged in LDS.
+typedef float gnn_v4f __attribute__((ext_vector_type(4)));
+constexpr int MR = 64;  // rows per workgroup of the MFMA kernels
+template <int K, int NO, bool RELU, bool TW, bool MASK>
+__global__ __launch_bounds__(256) void gnn_mfma_gemm_kernel(const float *X, const float *W, const float *c,
+                                                            const float *M, float *Y, int N) {
+  static_assert(K % 4 == 0 && NO % 16 == 0, "MFMA blocks");
+  constexpr int KP = K + 1, NB = NO / 16;
+  __shared__ float Xs[MR * KP];
+  __shared__ float Ws[K * NO];
+  const int r0 = blockIdx.x * MR;
+  for (int i = threadIdx.x; i < K * NO; i += 256) {
+    const int k = i / NO, o = i % NO;
+    Ws[i] = TW ? W[o * K + k] : W[i];
+  }
+  for (int i = threadIdx.x; i < MR * K; i += 256) {
+    const int r = i / K, k = i % K;
+    Xs[r * KP + k] = (r0 + r < N) ? X[(int64_t)(r0 + r) * K + k] : 0.0f;
+  }
+  __syncthreads();
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  const int ar = w * 16 + (l & 15), kq = l >> 4;
+  gnn_v4f acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = gnn_v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const float a = Xs[ar * KP + k0 + kq];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Ws[(k0 + kq) * NO + b * 16 + (l & 15)], acc[b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int col = b * 16 + (l & 15);
+    const float cv = c ? c[col] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = r0 + w * 16 + 4 * kq + j;
+      if (row < N) {
+        float v = acc[b][j] + cv;
+        if (RELU) v = v > 0.0f ? v : 0.0f;
+        if (MASK) v = M[(int64_t)row * NO + col] > 0.0f ? v : 0.0f;
+        Y[(int64_t)row * NO + col] = v;
+      }
+    }
+  }
+}
+
+// products whose contraction is a multiple of 4 run on the matrix cores; the
+// decoder's transposed product (K = 3) stays on the FMA kernel
 template <int K, int NO, bool RELU, bool TW, bool MASK>
 static void gemm(const float *X, const float *W, const float *c, const float *M, float *Y, int N,
                  hipStream_t s) {
-  const unsigned nb = (unsigned)std::max(1, (N + GR - 1) / GR);
-  hipLaunchKernelGGL((gnn_gemm_kernel<K, NO, RELU, TW, MASK>), dim3(nb), dim3(GR * NO / 16), 0, s, X, W, c, M,
-                     Y, N);
+  if constexpr (K % 4 == 0 && NO % 16 == 0) {
+    const unsigned nb = (unsigned)std::max(1, (N + MR - 1) / MR);
+    hipLaunchKernelGGL((gnn_mfma_gemm_kernel<K, NO, RELU, TW, MASK>), dim3(nb), dim3(256), 0, s, X, W, c, M, Y,
+                       N);
+  } else {
+    const unsigned nb = (unsigned)std::max(1, (N + GR - 1) / GR);
+    hipLaunchKernelGGL((gnn_gemm_kernel<K, NO, RELU, TW, MASK>), dim3(nb), dim3(GR * NO / 16), 0, s, X, W, c, M,
+                       Y, N);
+  }
 }
 
 // decoder: y = h W_d + c_d (3 outputs), one joint per thread
@@ -229,6 +292,65 @@ __global__ __launch_bounds__(GT) void gnn_wgrad_kernel(const float *X, const flo
   for (int p = 0; p < PER; ++p) {
     const int o = threadIdx.x + GT * p;
     if (o < NOUT) wpart[(int64_t)blockIdx.x * NOUT + o] = acc[p];
+  }
+}
+
+// The weight gradient on the matrix cores: per block of `rows` rows, the
+// (K + 1) x NO partial [X, 1]^T dZ as MFMA blocks (A = [X, 1]^T: lane l
+// takes feature m0 + l mod 16 of row r + l / 16; B = dZ: row r + l / 16,
+// output n0 + l mod 16), 64 rows staged in LDS at a time.  The (K + 1) rows
+// of the output are padded to whole blocks of 16; the four waves split the
+// output blocks between them.
+template <int K, int NO>
+__global__ __launch_bounds__(256) void gnn_mfma_wgrad_kernel(const float *X, const float *dZ, int N, int rows,
+                                                             float *wpart) {
+  static_assert(NO % 16 == 0, "MFMA blocks");
+  constexpr int MP = (K + 1 + 15) / 16, NB = NO / 16, NBLK = MP * NB, PER = (NBLK + 3) / 4;
+  constexpr int XP = MP * 16 + 1, NOUT = (K + 1) * NO;
+  __shared__ float Xs[64 * XP];
+  __shared__ float Zs[64 * NO];
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64, kq = l >> 4;
+  gnn_v4f acc[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) acc[p] = gnn_v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  const int rb0 = blockIdx.x * rows, rb1 = min(N, rb0 + rows);
+  for (int r0 = rb0; r0 < rb1; r0 += 64) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * MP * 16; i += 256) {
+      const int r = i / (MP * 16), m = i % (MP * 16);
+      const bool in = r0 + r < rb1;
+      Xs[r * XP + m] = !in || m > K ? 0.0f : (m == K ? 1.0f : X[(int64_t)(r0 + r) * K + m]);
+    }
+    for (int i = threadIdx.x; i < 64 * NO; i += 256) {
+      const int r = i / NO;
+      Zs[i] = r0 + r < rb1 ? dZ[(int64_t)(r0 + r) * NO + (i % NO)] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < 64; rr += 4) {
+#pragma unroll
+      for (int p = 0; p < PER; ++p) {
+        const int blk = w + 4 * p;
+        if (blk < NBLK) {
+          const int mb = blk / NB, nb = blk % NB;
+          const float a = Xs[(rr + kq) * XP + mb * 16 + (l & 15)];
+          const float b = Zs[(rr + kq) * NO + nb * 16 + (l & 15)];
+          acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[p], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int blk = w + 4 * p;
+    if (blk < NBLK) {
+      const int mb = blk / NB, nb = blk % NB;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = mb * 16 + 4 * kq + j, n = nb * 16 + (l & 15);
+        if (m <= K) wpart[(int64_t)blockIdx.x * NOUT + m * NO + n] = acc[p][j];
+      }
+    }
   }
 }
 
@@ -392,7 +514,10 @@ void launch_gnn_loss(const PcgBallArgs &a, const GnnBufs &g, hipStream_t s) {
 template <int K, int NO>
 static void wgrad(const float *X, const float *dZ, int nj, float *wpart, float *out, hipStream_t s) {
   const int nb = gnn_wgrad_blocks(nj);
-  hipLaunchKernelGGL((gnn_wgrad_kernel<K, NO>), dim3(nb), dim3(GT), 0, s, X, dZ, nj, WROWS, wpart);
+  if constexpr (NO % 16 == 0)
+    hipLaunchKernelGGL((gnn_mfma_wgrad_kernel<K, NO>), dim3(nb), dim3(256), 0, s, X, dZ, nj, WROWS, wpart);
+  else
+    hipLaunchKernelGGL((gnn_wgrad_kernel<K, NO>), dim3(nb), dim3(GT), 0, s, X, dZ, nj, WROWS, wpart);
   hipLaunchKernelGGL(gnn_wgrad_reduce_kernel, dim3(blocks_of((K + 1) * NO)), dim3(GT), 0, s, wpart, nb,
                      (K + 1) * NO, out);
 }
