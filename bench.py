@@ -127,12 +127,16 @@ def slice_bodies(asm, nb):
         cp_len=asm.cp_len[jm], meta={})
 
 
-def cpu_baseline(asm, wrench, q, qd, workload, nb, steps, body_solve=0):
+def cpu_baseline(asm, wrench, q, qd, workload, nb, steps, body_solve=0, network=False, tol=1e-10,
+                 max_iters=200000):
     """The FP64 oracle (the same C source, built -O3 -march=native for this
     host) timed on `steps` steps of a bounded sample of the workload: its
     first `nb` bodies, from the benchmark's final state.  Two legs: one
     thread (the paper's design point) and OpenMP over the per-body phases on
-    the host's cores (the chain / tree eliminations stay serial)."""
+    the host's cores (the chain / tree eliminations stay serial).  Workloads
+    with loops or networks take the oracle's block-Jacobi PCG to the same
+    tolerance on one step of a sample of at most 4,096 bodies (its direct
+    solvers are dense at that point; one such step is ~10 s)."""
     import ctypes
     import tempfile
 
@@ -140,6 +144,8 @@ def cpu_baseline(asm, wrench, q, qd, workload, nb, steps, body_solve=0):
 
     import oracle
 
+    if network:
+        nb, steps = min(nb, 4096), min(steps, 1)
     sub = slice_bodies(asm, nb)
     w = None if wrench is None else wrench[:nb]
     n_dyn = int((sub.pinned == 0).sum())
@@ -157,7 +163,10 @@ def cpu_baseline(asm, wrench, q, qd, workload, nb, steps, body_solve=0):
             qq, qqd = q[:nb].copy(), qd[:nb].copy()
             t0 = time.perf_counter()
             for _ in range(steps):
-                qq, qqd, _, _ = sysm.step(sub.h, qq, qqd)
+                if network:
+                    qq, qqd, _, _ = sysm.step(sub.h, qq, qqd, solver=oracle.PCG, tol=tol, max_iters=max_iters)
+                else:
+                    qq, qqd, _, _ = sysm.step(sub.h, qq, qqd)
             dt = time.perf_counter() - t0
             legs[name] = {"body_steps_per_s": round(n_dyn * steps / dt, 1), "threads": threads,
                           "seconds": round(dt, 2)}
@@ -167,7 +176,8 @@ def cpu_baseline(asm, wrench, q, qd, workload, nb, steps, body_solve=0):
             "cores": legs[best]["threads"], "kind": "oracle",
             "sample": f"{steps} steps of the first {nb} bodies ({n_dyn} dynamic) of the {workload} "
                       f"workload from the benchmark's final state; FP64 oracle built -O3 "
-                      f"-march=native; value = the faster leg ({best})",
+                      f"-march=native" + (f", block-Jacobi PCG to {tol:g}" if network else "") +
+                      f"; value = the faster leg ({best})",
             "legs": legs, "cpu_model": model, "nproc": ncpu, "usable_cpus": usable}
 
 
@@ -393,11 +403,14 @@ def main():
                "pcg_not_converged": kkt_notconv,
                "device_residual": dres}
     if not args.no_cpu_baseline:
+        network = bool(st0["n_graph"] or st0["n_loop"])
         cpu = cpu_baseline(asm, wrench, q_n, qd_n, args.workload,
                            min(args.cpu_sample_bodies, asm.n), args.cpu_sample_steps,
-                           body_solve=args.body_solve)
+                           body_solve=args.body_solve, network=network, tol=args.kkt_tol,
+                           max_iters=args.max_iters)
         print(f"# cpu baseline {cpu}", file=sys.stderr, flush=True)
-        if kkt is not None and asm.n <= 2_000_000:
+        # (networks: the oracle's direct solvers are dense, so no full step)
+        if kkt is not None and asm.n <= 2_000_000 and not network:
             # the oracle's own full step from the same state: the KKT residual
             # its direct FP64 solve reaches there
             qo1, qdo1, lam_o, diag_o = s.step(h, q_n, qd_n)
