@@ -274,3 +274,22 @@ def test_form1_full_size_tree_one_step():
     eq, eqd = state_errors(q1, qd1, q0, qd0)
     say("tree256k form 1: sweeps", st["ir_sweeps"], "kkt", st["kkt"], "plain kkt", sp["kkt"], "err", eq, eqd)
     assert st["kkt"] <= 1e-12 and eq < TOL and eqd < TOL
+
+
+def test_form1_tree_stall_far_above_target_is_not_converged():
+    """An unreachable target: the tree refinement stalls at the FP64 floor
+    (or runs out of sweeps) far above it and reports NOT_CONVERGED."""
+    import paper_2603_08079_amd as pk
+
+    t = mi.tree(800, seed=120)
+    t.qd0[1:] = np.random.default_rng(120).normal(0, 0.05, (t.n - 1, 12))
+    ctx = pk.Context(t, precision=1, kkt_tol=1e-17, ir_max_sweeps=6)
+    q0, qd0 = ctx.state()
+    with pytest.raises(pk.MabdError) as ei:
+        ctx.step(t.h, 1)
+    assert ei.value.status == pk.ERR_NOT_CONVERGED
+    st = ctx.stats()
+    say("stalled at", st["kkt"], "after", st["ir_sweeps"], "sweeps")
+    assert st["kkt"] > 1e-16 and st["ir_sweeps"] >= 1 and st["ir_stalled"] == 0
+    q1, qd1 = ctx.state()
+    assert np.array_equal(q0, q1) and np.array_equal(qd0, qd1)
