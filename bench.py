@@ -273,20 +273,26 @@ def main():
                 raise
             return str(e)
 
-    def timed(c):
+    def timed(c, restart):
         """--repeats timed regions of exactly --steps steps, each bracketed by
-        a device synchronisation; the median region is reported.  Every
-        region times the same steps of the workload's trajectory, steps
-        [warmup, warmup + steps): before it (untimed) the state goes back to
-        the workload's initial state and the warmup steps run again.  (On the
-        random trees a few light links carry subtrees thousands of times
-        their mass and leave the small-deformation regime after some tens of
-        steps; the repeats never reach that far.)"""
+        a device synchronisation; the median region is reported.  With
+        `restart` (contexts with tree components) every region times the same
+        steps of the workload's trajectory, steps [warmup, warmup + steps):
+        before it (untimed) the state goes back to the workload's initial
+        state and the warmup steps run again, since on the random trees a few
+        light links carry subtrees thousands of times their mass and leave
+        the small-deformation regime after some tens of steps.  Otherwise the
+        regions follow each other on one trajectory after one warmup
+        (restarting measured 0.305-0.310 against 0.289 ms/step on the 1M
+        chain, on one box)."""
         reps = []
+        if not restart and args.warmup:
+            run(c, args.warmup)
         for _ in range(max(1, args.repeats)):
-            c.set_state(asm.q0, asm.qd0)
-            if args.warmup:
-                run(c, args.warmup)
+            if restart:
+                c.set_state(asm.q0, asm.qd0)
+                if args.warmup:
+                    run(c, args.warmup)
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -315,14 +321,15 @@ def main():
           f"chains {st0['n_chain']} trees {st0['n_tree']} graphs {st0['n_graph']}",
           file=sys.stderr, flush=True)
     forms = {}
+    restart = st0["n_tree"] > 0
     if args.precision in ("auto", "0"):
-        forms[0] = timed(ctx)
+        forms[0] = timed(ctx, restart)
     # form 1 covers chain components and, in contexts without loop or
     # network components, tree components
     form1 = st0["n_chain"] or (st0["n_tree"] and not st0["n_graph"] and not st0["n_loop"])
     if args.precision in ("auto", "1") and form1:
         ctx1 = make(1)
-        forms[1] = timed(ctx1)
+        forms[1] = timed(ctx1, restart)
         if args.precision == "1":
             ctx.close()
             ctx = ctx1
@@ -436,6 +443,7 @@ def main():
                    "chain_tile_threads": st["tile_threads"],
                    "chain_tiles_packed": bool(st["tile_packed"])},
         "repeats": {"count": max(1, args.repeats), "statistic": "median",
+                    "restart_from_initial_state": restart,
                     "walls_ms": res["walls_ms"]},
         "forms": {FORMS[k]: {"ms_per_step": round(v["wall"] * 1e3 / args.steps, 4),
                              "body_steps_per_s": round(n_dyn * args.steps / v["wall"], 1),

@@ -1789,6 +1789,7 @@ hipError_t generic_refine(mabd_ctx *c, double h, int a, int b, const TreeArgs &t
   const int nsw = c->opt.ir_max_sweeps;
   c->gir_sweeps = 0;
   c->gir_stalled = 0;
+  c->gir_rho_p = c->gir_rho_d = c->gir_kkt = -1.0;
   double prev = 0.0;
   for (int sw = 0;; ++sw) {
     const bool last = sw == nsw;
