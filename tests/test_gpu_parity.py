@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Bar (from the benchmark spec): the GPU state matches the oracle's state to
+Bar: the GPU state matches the oracle's state to
 relative 1e-10 per step in FP64.  Positions are compared relative to the
 largest coordinate, velocities relative to the largest velocity (a stricter
 check of the increment itself).  Multipliers are compared relative to their
