@@ -97,6 +97,12 @@ struct TreeArgs {
 // D.  Loop rows (joint << 3 | row) of component c are lrow[off[c], off[c+1]).
 constexpr int LOOP_MAX_ROWS = 48;  // rows of D per component (the dense Schur system)
 
+// Offsets per round of the tree contraction plan: the round's first
+// operation, the ends of the rake classes (cliques of <= 10, 16, 32, 64 rows)
+// and of the compress classes (<= 10, 16, 32, 48 rows); the compresses from
+// the last end to the next round's first operation have larger cliques.
+constexpr int TC_NSEG = 9;
+
 // One operation of the tree contraction.  rake: eliminate the private rows of
 // slot v (absorbed joints: condensed children and one-sided joints) and pass
 // the Schur complement on its current parent joint kcur up (none at a root).

@@ -1254,7 +1254,8 @@ DEV void tcw_compress_back_body(const TreeArgs &a, const GJoint *J, int op0, int
 // of the slowest operation instead of the sum over the classes.  Block b
 // belongs to the last segment whose first block is <= b; the dynamic LDS is
 // sized by the host for the largest class in the launch.
-enum { TC_RAKE16, TC_RAKE32, TC_RAKE64, TC_COMP16, TC_COMP32, TC_COMP48, TC_NCLASS };
+enum { TC_RAKE10, TC_RAKE16, TC_RAKE32, TC_RAKE64, TC_COMP10, TC_COMP16, TC_COMP32, TC_COMP48, TC_NCLASS };
+static_assert(TC_NSEG == TC_NCLASS + 1, "one plan segment per class, then the large compresses");
 struct TcwSeg {
   int32_t cls, op0, op1, blk0;
 };
@@ -1263,7 +1264,10 @@ struct TcwLaunch {
   int32_t nseg;
 };
 
-template <bool BACK>
+// SMALL: the 10-row classes only, in a kernel of their own (compiled beside
+// the other classes their code raised the register count of every class
+// from 72 to 141 VGPRs)
+template <bool BACK, bool SMALL>
 __global__ __launch_bounds__(TCW) void tcw_round_kernel(TreeArgs a, const GJoint *J, TcwLaunch L) {
   extern __shared__ double tcw_smem[];
   const StepGate gate = step_gate(a.status);  // tested by each operation with its first read
@@ -1279,7 +1283,15 @@ __global__ __launch_bounds__(TCW) void tcw_round_kernel(TreeArgs a, const GJoint
     }
   }
   const int blk = (int)blockIdx.x - blk0;
-  if constexpr (!BACK) {
+  if constexpr (SMALL) {
+    if constexpr (!BACK) {
+      if (cls == TC_RAKE10) tcw_rake_body<10, 16>(a, J, op0, op1, blk, tcw_smem, gate);
+      else tcw_compress_body<10, 16>(a, J, op0, op1, blk, tcw_smem, gate);
+    } else {
+      if (cls == TC_RAKE10) tcw_rake_back_body<10, 16>(a, J, op0, op1, blk, tcw_smem, gate);
+      else tcw_compress_back_body<10, 16>(a, J, op0, op1, blk, tcw_smem, gate);
+    }
+  } else if constexpr (!BACK) {
     switch (cls) {
       case TC_RAKE16: tcw_rake_body<16, 16>(a, J, op0, op1, blk, tcw_smem, gate); break;
       case TC_RAKE32: tcw_rake_body<32, 64>(a, J, op0, op1, blk, tcw_smem, gate); break;
@@ -1479,29 +1491,33 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
                  int split_ops, int order, hipStream_t s) {
   if (nslots <= 0) return;
   hipLaunchKernelGGL(tree_prep_kernel, dim3((nslots + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J, nslots);
-  // per round, 7 segments of the operation list (o[7] starts the next round):
-  // rakes with cliques of <= 16, <= 32, <= 64 rows, then compresses with
-  // cliques of <= 16, <= 32, <= 48 rows and larger (team kernels on the
-  // global slots).  The planner keeps a round's rakes and compresses
-  // independent (a node with a child raked in the round is compressed in a
-  // later one), so every LDS-staged class of a round shares one launch, in
-  // both directions.  When the 16-row classes hold more than split_ops
-  // operations (throughput-bound: their small LDS footprint keeps more of
-  // them resident) they get a launch of their own.  Within a launch the
+  // per round, TC_NSEG offsets of the operation list (o[TC_NSEG] starts the
+  // next round): rakes with cliques of <= 10, 16, 32, 64 rows, then
+  // compresses with cliques of <= 10, 16, 32, 48 rows and larger (team
+  // kernels on the global slots).  The planner keeps a round's rakes and
+  // compresses independent (a node with a child raked in the round is
+  // compressed in a later one), so every LDS-staged class of a round shares
+  // one launch, in both directions, except that the 10-row classes take a
+  // kernel of their own and the 16-row classes a launch of their own when
+  // they hold more than split_ops operations: those are throughput-bound,
+  // and a launch is sized (LDS per workgroup, hence occupancy) by its
+  // largest class.  Within a launch the
   // classes go largest first with order 0 (workgroups are dispatched in
   // index order, so the longest operations start first and the short ones
   // fill the tail), smallest first with order 1.  Both are schedule choices
   // only: every operation of a round is independent of the others.
-  static const int tw[TC_NCLASS] = {16, 64, 64, 16, 64, 64};
-  static const size_t lds_fwd[TC_NCLASS] = {4 * sizeof(TcwMat<16>),  sizeof(TcwMat<32>),
-                                            sizeof(TcwMat<64>),      4 * sizeof(TcwComp<16>),
+  static const int tw[TC_NCLASS] = {16, 16, 64, 64, 16, 16, 64, 64};
+  static const size_t lds_fwd[TC_NCLASS] = {4 * sizeof(TcwMat<10>),  4 * sizeof(TcwMat<16>),
+                                            sizeof(TcwMat<32>),      sizeof(TcwMat<64>),
+                                            4 * sizeof(TcwComp<10>), 4 * sizeof(TcwComp<16>),
                                             sizeof(TcwComp<32>),     sizeof(TcwComp<48>)};
-  static const size_t lds_back[TC_NCLASS] = {4 * 136 * 8, 528 * 8, 2080 * 8, 4 * 136 * 8, 528 * 8, 1176 * 8};
-  static const int by_size[2][TC_NCLASS] = {{TC_RAKE64, TC_COMP48, TC_RAKE32, TC_COMP32, TC_RAKE16, TC_COMP16},
-                                            {TC_RAKE16, TC_COMP16, TC_RAKE32, TC_RAKE64, TC_COMP32, TC_COMP48}};
+  static const size_t lds_back[TC_NCLASS] = {4 * 55 * 8, 4 * 136 * 8, 528 * 8, 2080 * 8,
+                                             4 * 55 * 8, 4 * 136 * 8, 528 * 8, 1176 * 8};
+  static const int by_size[2][TC_NCLASS] = {
+      {TC_RAKE64, TC_COMP48, TC_RAKE32, TC_COMP32, TC_RAKE16, TC_COMP16, TC_RAKE10, TC_COMP10},
+      {TC_RAKE10, TC_COMP10, TC_RAKE16, TC_COMP16, TC_RAKE32, TC_RAKE64, TC_COMP32, TC_COMP48}};
   const int *all = by_size[order == 1 ? 1 : 0];
-  const int *small = order == 1 ? all : all + 4, *large = order == 1 ? all + 2 : all;
-  auto launch_classes = [&](const int32_t *o, const int *cl, int ncl, bool back) {
+  auto launch_classes = [&](const int32_t *o, const int *cl, int ncl, bool back, bool small) {
     TcwLaunch L{};
     int nb = 0;
     size_t lds = 0;
@@ -1514,30 +1530,47 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
       lds = std::max(lds, back ? lds_back[c] : lds_fwd[c]);
     }
     if (nb == 0) return;
-    if (back)
-      hipLaunchKernelGGL(tcw_round_kernel<true>, dim3(nb), dim3(TCW), lds, s, a, J, L);
-    else
-      hipLaunchKernelGGL(tcw_round_kernel<false>, dim3(nb), dim3(TCW), lds, s, a, J, L);
-  };
-  auto launch_round = [&](const int32_t *o, bool back) {
-    if ((o[TC_RAKE16 + 1] - o[TC_RAKE16]) + (o[TC_COMP16 + 1] - o[TC_COMP16]) > split_ops) {
-      launch_classes(o, small, 2, back);
-      launch_classes(o, large, 4, back);
+    if (small) {
+      if (back)
+        hipLaunchKernelGGL((tcw_round_kernel<true, true>), dim3(nb), dim3(TCW), lds, s, a, J, L);
+      else
+        hipLaunchKernelGGL((tcw_round_kernel<false, true>), dim3(nb), dim3(TCW), lds, s, a, J, L);
+    } else if (back) {
+      hipLaunchKernelGGL((tcw_round_kernel<true, false>), dim3(nb), dim3(TCW), lds, s, a, J, L);
     } else {
-      launch_classes(o, all, TC_NCLASS, back);
+      hipLaunchKernelGGL((tcw_round_kernel<false, false>), dim3(nb), dim3(TCW), lds, s, a, J, L);
     }
   };
+  auto launch_round = [&](const int32_t *o, bool back) {
+    // the 10-row classes are non-empty only where the planner kept them apart
+    // from the 16-row ones (more operations than the 16-row kernel runs at
+    // once): they always take their own kernel
+    auto ops = [&](int c) { return o[c + 1] - o[c]; };
+    const bool apart16 = ops(TC_RAKE16) + ops(TC_COMP16) > split_ops;
+    int rest[TC_NCLASS], nrest = 0;
+    for (int i = 0; i < TC_NCLASS; ++i) {
+      const int c = all[i];
+      const bool c10 = c == TC_RAKE10 || c == TC_COMP10, c16 = c == TC_RAKE16 || c == TC_COMP16;
+      if (c10 || (c16 && apart16)) continue;
+      rest[nrest++] = c;
+    }
+    static const int g10[2] = {TC_RAKE10, TC_COMP10}, g16[2] = {TC_RAKE16, TC_COMP16};
+    launch_classes(o, g10, 2, back, true);
+    if (apart16) launch_classes(o, g16, 2, back, false);
+    launch_classes(o, rest, nrest, back, false);
+  };
   for (int r = 0; r < nround; ++r) {
-    const int32_t *o = rounds + 7 * r;
+    const int32_t *o = rounds + TC_NSEG * r;
     launch_round(o, false);
-    if (o[7] > o[6])
-      hipLaunchKernelGGL(tc_compress_kernel, dim3((o[7] - o[6] + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J,
-                         o[6], o[7]);
+    if (o[TC_NSEG] > o[TC_NCLASS])
+      hipLaunchKernelGGL(tc_compress_kernel, dim3((o[TC_NSEG] - o[TC_NCLASS] + TEAMS - 1) / TEAMS),
+                         dim3(TREE_BLOCK), 0, s, a, J, o[TC_NCLASS], o[TC_NSEG]);
   }
   for (int r = nround - 1; r >= 0; --r) {
-    const int32_t *o = rounds + 7 * r;
-    if (o[7] > o[6])
-      hipLaunchKernelGGL(tc_compress_back_kernel, dim3((o[7] - o[6] + 255) / 256), dim3(256), 0, s, a, J, o[6], o[7]);
+    const int32_t *o = rounds + TC_NSEG * r;
+    if (o[TC_NSEG] > o[TC_NCLASS])
+      hipLaunchKernelGGL(tc_compress_back_kernel, dim3((o[TC_NSEG] - o[TC_NCLASS] + 255) / 256), dim3(256), 0, s,
+                         a, J, o[TC_NCLASS], o[TC_NSEG]);
     launch_round(o, true);
   }
 }

@@ -213,7 +213,7 @@ struct mabd_ctx {
   int64_t fac_size = 0;
   // tree contraction schedule
   std::vector<TcOp> tc_ops;
-  std::vector<int32_t> tc_rounds;  // 7 * rounds + 1 offsets into tc_ops (segments by kind and size)
+  std::vector<int32_t> tc_rounds;  // TC_NSEG * rounds + 1 offsets into tc_ops (segments by kind and size)
   int64_t crec_size = 0;
   TcOp *d_tc_ops = nullptr;
   double *d_crec = nullptr;
@@ -979,10 +979,13 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
           raked_child[par[s]] = 1;
         }
       }
-      {  // rakes by clique size: <= 16, <= 32, <= 64 rows (TREE_KMAX)
-        const int rows[3] = {16, 32, 64};
-        const int cap[3] = {1 << 30, 4096, 1024};  // operations the kernel runs at once
-        segment_ops(c->tc_ops, c->tc_rounds, [](const TcOp &o) { return o.nv; }, rows, cap, 3);
+      {  // rakes by clique size: <= 10, <= 16, <= 32, <= 64 rows (TREE_KMAX)
+        // operations the kernel runs at once; the 10-row class stays apart
+        // (its own kernel, twice the workgroups per CU of the 16-row one)
+        // only in rounds large enough to pay for the extra launch
+        const int rows[4] = {10, 16, 32, 64};
+        const int cap[4] = {1 << 30, 200000, 4096, 1024};
+        segment_ops(c->tc_ops, c->tc_rounds, [](const TcOp &o) { return o.nv; }, rows, cap, 4);
       }
       // a compress of v adds the condensed sides of v's other children, and a
       // child raked in this round writes its side in this round: such v wait
@@ -1025,13 +1028,13 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       }
       for (int i = round0; i < (int)c->tc_ops.size(); ++i)
         if (c->tc_ops[i].c < 0 && par[c->tc_ops[i].v] >= 0) raked_child[par[c->tc_ops[i].v]] = 0;
-      {  // compresses by the larger of v's and c's staged cliques: <= 16, <= 32,
-         // <= 48 rows, more (team kernels on the global slots)
-        const int rows[3] = {16, 32, 48};
-        const int cap[3] = {1 << 30, 2048, 768};
+      {  // compresses by the larger of v's and c's staged cliques: <= 10, <= 16,
+         // <= 32, <= 48 rows, more (team kernels on the global slots)
+        const int rows[4] = {10, 16, 32, 48};
+        const int cap[4] = {1 << 30, 200000, 2048, 768};
         segment_ops(c->tc_ops, c->tc_rounds,
                     [&](const TcOp &o) { return std::max(o.nv, c->tne[o.c] + std::max(o.ce, o.ck)); }, rows,
-                    cap, 3);
+                    cap, 4);
       }
     }
     c->tc_rounds.push_back((int)c->tc_ops.size());
@@ -1491,7 +1494,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   c->stats.tree_split = c->tree_split;
   c->stats.tree_order = c->tree_order;
   c->stats.tune_source = c->tune_source;
-  c->stats.tree_rounds = ((int)c->tc_rounds.size() - 1) / 7;
+  c->stats.tree_rounds = ((int)c->tc_rounds.size() - 1) / TC_NSEG;
   c->stats.rho_p = c->stats.rho_d = c->stats.kkt = -1.0;
   *out = c;
   return MABD_OK;
@@ -1834,7 +1837,7 @@ hipError_t generic_refine(mabd_ctx *c, double h, int a, int b, const TreeArgs &t
     tc.cc = c->d_cc;
     tc.glam = c->d_dlam;
     tc.f32 = 1;
-    launch_tree(tc, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(), ((int)c->tc_rounds.size() - 1) / 7,
+    launch_tree(tc, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(), ((int)c->tc_rounds.size() - 1) / TC_NSEG,
                 c->tree_split, c->tree_order, s);
     launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_dlam, c->d_Rg, c->d_uc, c->ns,
                   c->d_shp, c->d_hinv, c->d_q[b], c->d_q[b], c->d_qd[b], h, 1, c->d_status, c->d_gj, 0,
@@ -1933,7 +1936,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       ta.f32 = c->gen_ir ? 1 : 0;
       tm.run(5, [&] {
         launch_tree(ta, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
-                    ((int)c->tc_rounds.size() - 1) / 7, c->tree_split, c->tree_order, s);
+                    ((int)c->tc_rounds.size() - 1) / TC_NSEG, c->tree_split, c->tree_order, s);
         if (c->nloop > 0) {
           // loop-breaker Schur complement (Case III): the columns
           // S_AA^{-1} S_AD e_j by tree solves of the loop rows' increments
@@ -1948,7 +1951,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
                                c->d_uloop, 1, s);
             tw.glam = c->d_wcol + (size_t)j * ws;
             launch_tree(tw, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
-                        ((int)c->tc_rounds.size() - 1) / 7, c->tree_split, c->tree_order, s);
+                        ((int)c->tc_rounds.size() - 1) / TC_NSEG, c->tree_split, c->tree_order, s);
             launch_loop_inject(c->nloop, c->d_loff, c->d_lrow, j, c->d_gj, c->d_gl, c->d_shp, c->d_hinv, c->ns,
                                c->d_uloop, 0, s);
           }
