@@ -52,13 +52,35 @@ __global__ void prefactor_kernel(const double *shape, int nshape, double h, doub
 // take the polar-free solve of Alg. 1 instead: no polar decomposition, the
 // length-preserving stand-ins of local_force_lp, R stored as the identity
 // (unused: the back-projection applies the stand-in again).
+// With fa.inc_off given, a body without joints also takes its back-projection
+// here (it has no multipliers: dq = R u, or the stand-in of Alg. 1), exactly
+// as gapply_kernel would, which then skips it: q_out = q + dq and
+// qd_out = (fa.acc ? qd_out : 0) + dq / h, without the round trip of u.
+struct FreeApply {
+  const int32_t *inc_off;  // null: no body is applied here
+  double *q_out, *qd_out, *dq_save;
+  int acc;
+};
+DEV void free_apply(const FreeApply &fa, int64_t ns, int64_t b, const double *q, const double *dq, double h,
+                    uint32_t *status, int step) {
+  const double ih = 1.0 / h;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const int64_t o = (int64_t)i * ns + b;
+    fa.q_out[o] = q[i] + dq[i];
+    fa.qd_out[o] = (fa.acc ? fa.qd_out[o] : 0.0) + dq[i] * ih;
+    if (fa.dq_save) fa.dq_save[o] = dq[i];
+    if (!isfinite(dq[i])) raise_flag(status, FLAG_NONFINITE, step);
+  }
+}
 __global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double *q, const double *qn, const double *qdn,
                              int64_t ns, const int32_t *shp, const double *hinv,
                              const double *shape, double g0, double g1, double g2, double h,
                              double *Rg, double *ug, uint32_t *status, int step, const double *wr,
-                             const int32_t *pf_inc, int f32) {
+                             const int32_t *pf_inc, int f32, FreeApply fa) {
   int64_t b = (int64_t)b0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= b1 || skip_step(status, step)) return;
+  const bool fused = fa.inc_off && fa.inc_off[b] == fa.inc_off[b + 1];
   if (pf_inc && pf_inc[b] == pf_inc[b + 1]) {
     double qq[12], qnn[12], qd[12], A[9];
 #pragma unroll
@@ -78,6 +100,13 @@ __global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double
     hinv_apply(hinv + (int64_t)HINV_STRIDE * s, phi, u);
 #pragma unroll
     for (int i = 0; i < 9; ++i) Rg[i * ns + b] = (i % 4 == 0) ? 1.0 : 0.0;
+    if (fused) {
+      double dq[12];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) lenpres(A, false, u + 3 * c, dq + 3 * c);
+      free_apply(fa, ns, b, qq, dq, h, status, step);
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < 12; ++i) ug[i * ns + b] = u[i];
     return;
@@ -122,6 +151,15 @@ __global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double
     }
     local_force<float>(shape + (int64_t)SHAPE_STRIDE * s, Rf, Af, qf, qnf, qdf, g, h, phif, wr, ns, b);
     hinv_apply(hinv + (int64_t)HINV_STRIDE * s, phif, uf);
+    if (fused) {
+      double u[12], dq[12];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) u[i] = (double)uf[i];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) mat3_vec(R, u + 3 * c, dq + 3 * c);
+      free_apply(fa, ns, b, qq, dq, h, status, step);
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < 12; ++i) ug[i * ns + b] = (double)uf[i];
     return;
@@ -129,6 +167,13 @@ __global__ __launch_bounds__(256) void gbody_kernel(int b0, int b1, const double
   double phi[12], u[12];
   local_force<double>(shape + (int64_t)SHAPE_STRIDE * s, R, A, qq, qnn, qd, g, h, phi, wr, ns, b);
   hinv_apply(hinv + (int64_t)HINV_STRIDE * s, phi, u);
+  if (fused) {
+    double dq[12];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) mat3_vec(R, u + 3 * c, dq + 3 * c);
+    free_apply(fa, ns, b, qq, dq, h, status, step);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 12; ++i) ug[i * ns + b] = u[i];
 }
@@ -1320,9 +1365,10 @@ __global__ __launch_bounds__(256) void gapply_kernel(int b0, int b1, const int32
                               const double *ug, int64_t ns, const int32_t *shp, const double *hinv,
                               const double *q_cur, double *q_out, double *qd_out, double h,
                               int accumulate, uint32_t *status, const GJoint *J, int step,
-                              double *dq_save, int polar_free) {
+                              double *dq_save, int polar_free, int skip_free) {
   int64_t b = (int64_t)b0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= b1 || skip_step(status, step)) return;
+  if (skip_free && inc_off[b] == inc_off[b + 1]) return;  // applied by gbody_kernel
   if (polar_free && inc_off[b] == inc_off[b + 1]) {
     // polar-free solve (Alg. 1): dq = the length-preserving stand-in of R
     // applied to each block of u
@@ -1459,10 +1505,12 @@ void launch_prefactor(const double *shape, int nshape, double h, double *hinv, h
 void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
                   const int32_t *shp, const double *hinv, const double *shape, const double *g,
                   double h, double *Rg, double *ug, uint32_t *status, int step, const double *wr,
-                  const int32_t *pf_inc, int f32, hipStream_t s) {
+                  const int32_t *pf_inc, int f32, const int32_t *free_inc, double *q_out, double *qd_out,
+                  int acc, double *dq_save, hipStream_t s) {
+  const FreeApply fa{free_inc, q_out, qd_out, dq_save, acc};
   if (b1 > b0)
     hipLaunchKernelGGL(gbody_kernel, dim3((b1 - b0 + 255) / 256), dim3(256), 0, s, b0, b1, q, qn, qdn,
-                       ns, shp, hinv, shape, g[0], g[1], g[2], h, Rg, ug, status, step, wr, pf_inc, f32);
+                       ns, shp, hinv, shape, g[0], g[1], g[2], h, Rg, ug, status, step, wr, pf_inc, f32, fa);
 }
 // glam += dlam over n entries (refinement: the correction's multipliers)
 __global__ void lam_add_kernel(int64_t n, double *glam, const double *dlam, const uint32_t *status) {
@@ -1578,11 +1626,11 @@ void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, c
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
                    double *qd_out, double h, int acc, uint32_t *status, const GJoint *J,
-                   int step, double *dq_save, int polar_free, hipStream_t s) {
+                   int step, double *dq_save, int polar_free, int skip_free, hipStream_t s) {
   if (b1 > b0)
     hipLaunchKernelGGL(gapply_kernel, dim3((b1 - b0 + 255) / 256), dim3(256), 0, s, b0, b1, inc_off,
                        inc, gl, glam, Rg, ug, ns, shp, hinv, q_cur, q_out, qd_out, h, acc, status, J,
-                       step, dq_save, polar_free);
+                       step, dq_save, polar_free, skip_free);
 }
 void launch_gather_state(int nd, const int32_t *sol2in, const double *const *q, const double *const *qd,
                          int cur, int cur0, const uint32_t *status, int64_t ns, double *qo, double *qdo,

@@ -43,7 +43,8 @@ void launch_prefactor(const double *shape, int nshape, double h, double *hinv, h
 void launch_gbody(int b0, int b1, const double *q, const double *qn, const double *qdn, int64_t ns,
                   const int32_t *shp, const double *hinv, const double *shape, const double *g,
                   double h, double *Rg, double *ug, uint32_t *status, int step, const double *wr,
-                  const int32_t *pf_inc, int f32, hipStream_t s);
+                  const int32_t *pf_inc, int f32, const int32_t *free_inc, double *q_out, double *qd_out,
+                  int acc, double *dq_save, hipStream_t s);
 void launch_lam_add(int64_t n, double *glam, const double *dlam, const uint32_t *status, hipStream_t s);
 void launch_raise(uint32_t *status, uint32_t flag, hipStream_t s);
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
@@ -54,7 +55,7 @@ void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, c
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
                    double *qd_out, double h, int acc, uint32_t *status, const GJoint *J,
-                   int step, double *dq_save, int polar_free, hipStream_t s);
+                   int step, double *dq_save, int polar_free, int skip_free, hipStream_t s);
 void launch_gather_state(int nd, const int32_t *sol2in, const double *const *q, const double *const *qd,
                          int cur, int cur0, const uint32_t *status, int64_t ns, double *qo, double *qdo,
                          hipStream_t s);
@@ -1624,7 +1625,7 @@ hipError_t gnn_prepare(mabd_ctx *c, double h, PcgBallArgs &pb) {
   const int a = c->cur;
   launch_gbody(c->gb0, c->gb1, c->d_q[a], c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv, c->d_shape,
                c->opt.gravity, h, c->d_Rg, c->d_ug, c->d_status, 0, c->wr_on ? c->d_wr : nullptr,
-               nullptr, 0, s);  // network bodies have joints: always the polar solve
+               nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr, s);  // network bodies have joints: the polar solve
   launch_gjoint((int)c->gj.size(), c->d_gj, c->d_q[a], c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
   pb = make_ball_args(c, c->opt.kkt_tol, c->opt.max_iters, 0);
   launch_pb_setup(pb, s);
@@ -1841,7 +1842,7 @@ hipError_t generic_refine(mabd_ctx *c, double h, int a, int b, const TreeArgs &t
                 c->tree_split, c->tree_order, s);
     launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_dlam, c->d_Rg, c->d_uc, c->ns,
                   c->d_shp, c->d_hinv, c->d_q[b], c->d_q[b], c->d_qd[b], h, 1, c->d_status, c->d_gj, 0,
-                  nullptr, c->opt.body_solve, s);
+                  nullptr, c->opt.body_solve, 0, s);
     launch_lam_add(5 * (int64_t)mg, c->d_glam, c->d_dlam, c->d_status, s);
     ++c->gir_sweeps;
   }
@@ -1902,12 +1903,17 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
     }
   }
   if (c->gb1 > c->gb0) {
+    // bodies without joints take their back-projection in the body kernel,
+    // except when every iteration's residual is kept (it copies the iterate
+    // before the back-projection updates it)
+    const bool fuse_free = !(diag && c->opt.newton_iters > 1);
     for (int it = 0; it < c->opt.newton_iters; ++it) {
       const double *qcur = it == 0 ? c->d_q[a] : c->d_q[b];
       tm.run(3, [&] {
         launch_gbody(c->gb0, c->gb1, qcur, c->d_q[a], c->d_qd[a], c->ns, c->d_shp, c->d_hinv,
                      c->d_shape, g, h, c->d_Rg, c->d_ug, c->d_status, 0, c->wr_on ? c->d_wr : nullptr,
-                     c->opt.body_solve == 1 ? c->d_inc_off : nullptr, c->gen_ir ? 1 : 0, s);
+                     c->opt.body_solve == 1 ? c->d_inc_off : nullptr, c->gen_ir ? 1 : 0,
+                     fuse_free ? c->d_inc_off : nullptr, c->d_q[b], c->d_qd[b], it > 0 ? 1 : 0, nullptr, s);
       });
       tm.run(4, [&] {
         launch_gjoint((int)c->gj.size(), c->d_gj, qcur, c->d_Rg, c->ns, c->opt.hinge_grad, c->d_gl, s);
@@ -2014,7 +2020,8 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       tm.run(6, [&] {
         launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_glam, c->d_Rg, c->d_ug,
                       c->ns, c->d_shp, c->d_hinv, qcur, c->d_q[b], c->d_qd[b], h, it > 0 ? 1 : 0,
-                      c->d_status, c->d_gj, 0, dg_it ? c->d_dqit : nullptr, c->opt.body_solve, s);
+                      c->d_status, c->d_gj, 0, dg_it ? c->d_dqit : nullptr, c->opt.body_solve,
+                      fuse_free ? 1 : 0, s);
       });
       if (c->gen_ir) {
         hipError_t re = hipSuccess;
