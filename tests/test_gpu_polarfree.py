@@ -77,3 +77,25 @@ def test_polar_free_speed_on_a_million_boxes():
         ctx.close()
     say("ms per step: polar", times[0], "polar-free", times[1])
     assert times[1] <= 1.05 * times[0]
+
+
+@pytest.mark.parametrize("body_solve", [0, 1])
+def test_fused_back_projection_of_free_bodies(body_solve):
+    """Bodies without joints take their back-projection in the body kernel,
+    except where every Newton iteration's residual is recorded (diagnostics
+    with several iterations keep the separate kernel): both give the same
+    state bitwise, beside jointed assemblies, over two iterations a step."""
+    import paper_2603_08079_amd as pk
+
+    asm = mixed_scene()
+    out = []
+    for diag in (0, 1):
+        ctx = pk.Context(asm, body_solve=body_solve, newton_iters=2, diagnostics=diag)
+        ctx.step(asm.h, 3)
+        q, qd = ctx.state()
+        st = ctx.stats()
+        ctx.close()
+        assert st["last_status"] == 0
+        out.append((q, qd))
+    say("body_solve", body_solve, "max |q|", np.abs(out[0][0]).max())
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
