@@ -150,3 +150,32 @@ def test_gnn_needs_a_ball_network():
     with pytest.raises(pk.MabdError) as ei:
         ctx.gnn_init(0)
     assert ei.value.status == pk.ERR_INVALID_ARG
+
+
+def test_learned_start_gain_on_held_out_networks(capsys):
+    """The training driver end to end at a small size: train on random
+    networks of seeds 0-3, evaluate cold, previous-step and learned starts
+    on held-out seeds 100-101 at the same tolerance, and state the gain.
+    Every start must reach the tolerance; the learned start may not cost
+    more iterations than the previous-step start it refines (the energy test
+    keeps the base start when the correction does not lower the energy)."""
+    import argparse
+    import json
+
+    from paper_2603_08079_amd import gnn_train as T
+
+    with tempfile.TemporaryDirectory() as d:
+        w = os.path.join(d, "w.bin")
+        T.train(argparse.Namespace(n=400, seeds="0-3", steps=3, iters=20, lr=1e-3, tol=1e-6,
+                                   max_iters=200000, init_seed=0, out=w))
+        T.evaluate(argparse.Namespace(weights=w, n=400, seeds="100-101", steps=3, tol=1e-6,
+                                      max_iters=200000))
+    lines = [json.loads(l) for l in capsys.readouterr().out.splitlines() if l.startswith("{")]
+    ev = [l for l in lines if l["command"] == "eval"][0]
+    cold, prev, learned = ev["cold"], ev["previous"], ev["learned"]
+    say("mean PCG iterations to 1e-6: cold", cold["mean_iters"], "previous", prev["mean_iters"],
+        "learned", learned["mean_iters"], "(accepted", ev["learned_accepted"], ")")
+    say("gain of the learned start: vs cold", 1 - learned["mean_iters"] / cold["mean_iters"],
+        "vs previous", 1 - learned["mean_iters"] / prev["mean_iters"])
+    assert cold["not_converged"] == prev["not_converged"] == learned["not_converged"] == 0
+    assert learned["mean_iters"] <= 1.05 * prev["mean_iters"] + 20
