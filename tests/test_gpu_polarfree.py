@@ -99,3 +99,30 @@ def test_fused_back_projection_of_free_bodies(body_solve):
         out.append((q, qd))
     say("body_solve", body_solve, "max |q|", np.abs(out[0][0]).max())
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("body_solve", [0, 1])
+def test_full_size_boxes_sampled(body_solve):
+    """The 1,048,576 spinning boxes as the benchmark runs them, two steps;
+    the bodies are independent, so a sample of 2,000 of them stepped by the
+    oracle alone must match the GPU's state of the same bodies."""
+    import paper_2603_08079_amd as pk
+
+    asm = mi.config("boxes1m")
+    ctx = pk.Context(asm, body_solve=body_solve)
+    ctx.step(asm.h, 2)
+    qg, qdg = ctx.state()
+    ctx.close()
+    idx = np.sort(np.random.default_rng(131).choice(asm.n, 2000, replace=False))
+    sub = mi.spinning_boxes(1, seed=0)  # template of an unjointed assembly
+    sub.dims, sub.density, sub.k_orth = asm.dims[idx], asm.density[idx], asm.k_orth[idx]
+    sub.pinned, sub.q0, sub.qd0 = asm.pinned[idx], asm.q0[idx], asm.qd0[idx]
+    if asm.poisson is not None:
+        sub.poisson = asm.poisson[idx]
+    s = oracle.System(sub, body_solve=body_solve)
+    q, qd = sub.q0.copy(), sub.qd0.copy()
+    for _ in range(2):
+        q, qd, _, _ = s.step(asm.h, q, qd)
+    eq, eqd = state_errors(qg[idx], qdg[idx], q, qd)
+    say("boxes1m body_solve", body_solve, "sampled errors", eq, eqd)
+    assert eq < 1e-10 and eqd < 1e-10

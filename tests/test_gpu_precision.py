@@ -293,3 +293,25 @@ def test_form1_tree_stall_far_above_target_is_not_converged():
     assert st["kkt"] > 1e-16 and st["ir_sweeps"] >= 1 and st["ir_stalled"] == 0
     q1, qd1 = ctx.state()
     assert np.array_equal(q0, q1) and np.array_equal(qd0, qd1)
+
+
+def test_form1_full_size_batch_one_step():
+    """The 4,096-assembly batch (2.95M bodies) in form 1, one step from a
+    moving state, against the plain FP64 GPU solve of the same step (both
+    at the FP64 floor)."""
+    import paper_2603_08079_amd as pk
+
+    asm = mi.config("batch4096")
+    asm.qd0[:, 9:] = np.random.default_rng(22).normal(0, 0.05, (asm.n, 3))
+    asm.qd0[asm.pinned == 1] = 0.0
+    f1 = pk.Context(asm, precision=1, kkt_tol=1e-12)
+    p0 = pk.Context(asm, diagnostics=1)
+    f1.step(asm.h, 1)
+    p0.step(asm.h, 1)
+    st, sp = f1.stats(), p0.stats()
+    q1, qd1 = f1.state()
+    q0, qd0 = p0.state()
+    eq, eqd = state_errors(q1, qd1, q0, qd0)
+    say("batch4096 form 1: sweeps", st["ir_sweeps"], "kkt", st["kkt"], "plain kkt", sp["kkt"], "err", eq, eqd)
+    assert st["last_status"] == 0 and st["kkt"] <= 1e-12
+    assert eq < TOL and eqd < TOL
