@@ -1,18 +1,22 @@
 /*
  * mabd.h -- C ABI of libmabd, an MI355X (gfx950) implementation of the
- * per-time-step solve of M-ABD: co-rotated affine bodies joined by ball and
- * hinge joints, one implicit-Euler Newton step per call with the joints
- * enforced exactly through the KKT system (arXiv 2603.08079, Secs. 3-5).
+ * per-time-step solve of M-ABD: co-rotated affine bodies joined by ball,
+ * hinge, universal and prismatic joints, one implicit-Euler Newton step per
+ * call (or several) with the joints enforced exactly through the KKT system
+ * (arXiv 2603.08079, Secs. 3-5).
  *
  * One step does, on the GPU:
  *   (a) per body: polar rotation R = A (A^T A)^{-1/2} (Eq. polar), force
  *       f_A (Eq. variation_energy, Eq. reduced_K) and the unconstrained local
- *       solve with the constant pre-factorised Hbar (Eq. abd_final);
+ *       solve with the constant pre-factorised Hbar (Eq. abd_final), or for
+ *       bodies without joints optionally the polar-free solve of Alg. 1;
  *   (b) the dual (Schur) system  grad C H^{-1} grad C^T  with right-hand side
  *       grad C H^{-1} f_A + C  (Eq. dual; -C as in the footnote of Eq. kkt);
- *   (c) its solution: block cyclic reduction on chains (Eq. chain-btd),
- *       leaf-to-root elimination on trees (Sec. 5.3), preconditioned CG on
- *       graphs with loops (Sec. 5.4-5.5);
+ *   (c) its solution: block cyclic reduction on ball chains (Eq. chain-btd),
+ *       a rake/compress elimination on trees and hinge chains (Sec. 5.3), a
+ *       spanning tree plus a dense Schur system over the loop-closing joints
+ *       for components with a few loops (Sec. 5, Case III, Eq. loop), and
+ *       preconditioned CG on networks (Secs. 5.4-5.5);
  *   (d) the primal back-projection dq = H^{-1}(f_A - grad C^T dlambda)
  *       (Eq. primal) and the state update q += dq, qdot = dq / h.
  *
