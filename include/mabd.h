@@ -168,6 +168,18 @@ typedef struct {
                               also in the rotated elastic force.  Exact where A is a
                               scaled rotation, first order in the deformation otherwise;
                               such bodies are left out of rho_p (diagnostics)          */
+  int32_t path_solver;     /* 1 (default): tree components whose bodies carry at most two
+                              joints each (paths: chains with hinge, universal or
+                              prismatic joints, free-floating chains) are solved as
+                              block-tridiagonal systems over their joints, segments of
+                              up to 16 joints (4 above the first level) eliminated one
+                              per lane, level by level over the segments' last joints;
+                              0: by the tree
+                              contraction like every other tree.  Both are exact
+                              (Sec. 5.3) and agree to rounding.  The environment
+                              variable MABD_PATH_SEGMENT = T or T0,T1 (2..64) sets the
+                              segment length (T0 at the first level, T1 above) at
+                              mabd_create (for testing)                                */
   const char *tune_cache;  /* path of a tuning cache file, or NULL (default): with
                               autotune on, a context whose device and schedule shape
                               (chain rows and count, tree slots and rounds) have an
@@ -226,6 +238,9 @@ typedef struct {
   int32_t tree_order;      /* 0 clique classes largest first in a launch, 1 smallest   */
   int32_t tune_source;     /* 0 default schedules, 1 timed by the autotuner, 2 read from
                               the tuning cache                                        */
+  int32_t n_path;          /* tree components solved as paths (path_solver; counted in
+                              n_tree too)                                             */
+  int32_t path_levels;     /* levels of the path solve (0: none)                      */
 } mabd_step_stats;
 
 /* Fills *opt with the defaults listed above. */

@@ -56,7 +56,7 @@ class Options(ctypes.Structure):
                 ("hinge_grad", ctypes.c_int32), ("material", ctypes.c_int32),
                 ("diagnostics", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("ir_max_sweeps", ctypes.c_int32),
-                ("body_solve", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
+                ("body_solve", ctypes.c_int32), ("path_solver", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -77,7 +77,8 @@ class StepStats(ctypes.Structure):
                 ("tree_rounds", ctypes.c_int32), ("tile_packed", ctypes.c_int32),
                 ("ir_stalled", ctypes.c_int32), ("kkt_newton", ctypes.c_double * NEWTON_DIAG),
                 ("n_loop", ctypes.c_int32), ("tree_split", ctypes.c_int32),
-                ("tree_order", ctypes.c_int32), ("tune_source", ctypes.c_int32)]
+                ("tree_order", ctypes.c_int32), ("tune_source", ctypes.c_int32),
+                ("n_path", ctypes.c_int32), ("path_levels", ctypes.c_int32)]
 
     PHASES = ("chain_reduce", "chain_global", "chain_apply", "body", "joint", "tree", "apply",
               "pcg", "chain_resid", "chain_finish")

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmabd.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["k_chain.hip", "k_generic.hip", "k_diag.hip", "k_loop.hip", "k_pcg.hip", "k_pcg_ball.hip",
-           "k_gnn.hip", "mabd_host.cpp"]
+           "k_gnn.hip", "k_path.hip", "mabd_host.cpp"]
 ARCH = os.environ.get("MABD_ARCH", "gfx950")
 
 FLAGS = [

@@ -183,3 +183,58 @@ struct PcgBallArgs {
 };
 
 }  // namespace mabd
+
+namespace mabd {
+
+// Paths: tree components whose bodies carry at most two joints each (chains
+// with hinges, universal or prismatic joints, free-floating chains).  Their
+// joints, in path order, are the units of a block-tridiagonal dual: unit i
+// couples only with i-1 and i+1, through the body the two joints share.
+// Every block is padded to 5 rows (identity on the padding), so the kernels
+// work on fixed 5x5 blocks in registers.  A level splits each path into
+// segments of at most T units; a segment eliminates its units but the last
+// (its separator) in order, which leaves a block-tridiagonal system over the
+// separators (the next level).  A path with one segment at a level solves
+// its separator there; back-substitution runs the levels in reverse.
+constexpr int PATH_MAXLEVEL = 32;
+constexpr int PATH_UREC = 65;  // level >= 1 unit: D (15, packed lower), y (5), F (25: coupling
+                               // from the previous unit, its rows x ours), dD (15), dy (5)
+constexpr int PATH_FREC = 70;  // per eliminated unit: L (15, the reciprocals of the pivots on
+                               // its diagonal), z (5), W (25), G (25)
+enum { PU_D = 0, PU_Y = 15, PU_F = 20, PU_DD = 45, PU_DY = 60 };
+enum { PF_L = 0, PF_Z = 15, PF_W = 20, PF_G = 45 };
+
+// a level-0 unit: one joint of a path, and the clique matrices (K0, y0 of the
+// tree pre-pass, lower triangle, leading dimension ld) of the bodies before and
+// after it on the path, with the first clique row of this joint and of the
+// neighbouring joint there (-1: none)
+struct PathUnit0 {
+  int64_t fb, fa;    // factor slot offsets of the bodies before / after (-1: none)
+  int32_t ldb, lda;
+  int32_t ob, obp;   // body before: rows of this joint, of the previous joint
+  int32_t oa, oan;   // body after: rows of this joint, of the next joint
+  int32_t r, gj;     // rows, generic joint index (multipliers at 5 gj)
+};
+
+struct PathSeg {
+  int32_t u0, t;     // first unit (index within the level) and unit count
+  int32_t k;         // the separator's unit index at the next level
+  int32_t flags;     // bit 0: a left separator (the previous segment's);
+                     // bit 1: the path's last segment at this level;
+                     // bit 2: the path's only segment (its separator is solved here)
+};
+
+struct PathPlan {
+  int nlevel;                              // levels with segments
+  const PathUnit0 *u0;
+  const PathSeg *seg;                      // level l: [seg_off[l], seg_off[l+1])
+  const int32_t *rows;                     // units of levels >= 1
+  double *unit;                            // PATH_UREC per unit of levels >= 1
+  double *lam;                             // 5 per unit of levels >= 1
+  double *fac;                             // level l at fac_off[l]: (T-1) x PATH_FREC x segments
+  int32_t seg_off[PATH_MAXLEVEL + 1];
+  int64_t unit_off[PATH_MAXLEVEL + 2];     // level l >= 1 units from unit_off[l]
+  int64_t fac_off[PATH_MAXLEVEL + 1];
+};
+
+}  // namespace mabd

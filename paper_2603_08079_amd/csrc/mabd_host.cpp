@@ -50,7 +50,7 @@ void launch_raise(uint32_t *status, uint32_t flag, hipStream_t s);
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
                    double *gl, hipStream_t s);
 void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
-                 int split_ops, int order, hipStream_t s);
+                 int split_ops, int order, const PathPlan *path, hipStream_t s);
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
@@ -218,6 +218,19 @@ struct mabd_ctx {
   int64_t crec_size = 0;
   TcOp *d_tc_ops = nullptr;
   double *d_crec = nullptr;
+  // paths: tree components whose bodies carry at most two joints, solved as
+  // block-tridiagonal systems over their joints (segments of path_T units
+  // per lane, level by level); per path its input joints in path order and
+  // the dynamic bodies before and after each (-1: none)
+  // segment lengths: 16 units per lane at level 0; 4 above, where the few
+  // separators leave the lanes' dependent steps, not memory, as the bound
+  int npath = 0, path_T = 16, path_T1 = 4;
+  std::vector<std::vector<int>> path_j, path_bb, path_ba;
+  std::vector<char> path_slot;  // tree slot -> solved as part of a path
+  PathPlan pplan{};
+  std::vector<PathUnit0> pu0;
+  std::vector<PathSeg> pseg;
+  std::vector<int32_t> prows;
   int32_t *d_tne = nullptr;
   int64_t *d_foff = nullptr;
   double *d_fac = nullptr;
@@ -524,6 +537,7 @@ void mabd_options_default(mabd_options *o) {
   o->autotune = 1;
   o->ir_max_sweeps = 4;
   o->body_solve = 0;
+  o->path_solver = 1;
   o->tune_cache = nullptr;
   o->stream = nullptr;
 }
@@ -581,6 +595,8 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     return fail(nullptr, MABD_ERR_INVALID_ARG, "ir_max_sweeps must be in 0..16");
   if (opt.body_solve != 0 && opt.body_solve != 1)
     return fail(nullptr, MABD_ERR_INVALID_ARG, "body_solve must be 0 or 1");
+  if (opt.path_solver != 0 && opt.path_solver != 1)
+    return fail(nullptr, MABD_ERR_INVALID_ARG, "path_solver must be 0 or 1");
   if (!finite_all(opt.gravity, 3)) return fail(nullptr, MABD_ERR_INVALID_ARG, "gravity not finite");
   // ------------------------------------------------------------ validate
   for (int i = 0; i < n; ++i) {
@@ -843,6 +859,12 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       c->ntree++;
       continue;
     }
+    // a path: every body carries at most two joints (a tree, so its joints
+    // form one sequence, consecutive joints sharing a body)
+    bool is_path = opt.path_solver != 0 && cls[ci] == CLS_TREE;
+    for (int b : bs)
+      if (binc[b].size() > 2) is_path = false;
+    const int slot0 = (int)c->tbody.size();
     int root = bs[0];
     for (int b : bs) {
       bool has_unary = false;
@@ -913,6 +935,59 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       c->lvl_off.push_back((int)c->tbody.size());
     }
     c->comp_lvl.push_back((int)c->lvl_off.size() - 1);
+    if (is_path) {
+      const auto &js = cjoints[ci];
+      std::map<int, std::vector<int>> jadj;  // joints sharing a body
+      for (int b : bs)
+        if (binc[b].size() == 2) {
+          jadj[binc[b][0]].push_back(binc[b][1]);
+          jadj[binc[b][1]].push_back(binc[b][0]);
+        }
+      int start = js[0];
+      for (int k : js)
+        if (jadj[k].size() < 2) { start = k; break; }
+      std::vector<int> seq{start};
+      std::set<int> used{start};
+      for (;;) {
+        int nxt = -1;
+        for (int k2 : jadj[seq.back()])
+          if (!used.count(k2)) nxt = k2;
+        if (nxt < 0) break;
+        used.insert(nxt);
+        seq.push_back(nxt);
+      }
+      if (seq.size() != js.size()) {
+        delete c;
+        return fail(nullptr, MABD_ERR_TOPOLOGY, "path component: joints do not form one sequence");
+      }
+      auto shared = [&](int k1, int k2) {
+        for (int s1 : {Jn->a[k1], Jn->b[k1]})
+          if (dyn(s1) && (s1 == Jn->a[k2] || s1 == Jn->b[k2])) return s1;
+        return -1;
+      };
+      auto other = [&](int k, int excl) {  // a dynamic side of k other than excl
+        for (int s1 : {Jn->a[k], Jn->b[k]})
+          if (dyn(s1) && s1 != excl) return s1;
+        return -1;
+      };
+      const int M = (int)seq.size();
+      std::vector<int> bb(M), ba(M);
+      for (int i = 0; i < M; ++i) {
+        if (M == 1) {
+          bb[0] = dyn(Jn->a[seq[0]]) ? Jn->a[seq[0]] : -1;
+          ba[0] = dyn(Jn->b[seq[0]]) ? Jn->b[seq[0]] : -1;
+          break;
+        }
+        bb[i] = i > 0 ? shared(seq[i - 1], seq[i]) : other(seq[0], shared(seq[0], seq[1]));
+        ba[i] = i < M - 1 ? shared(seq[i], seq[i + 1]) : other(seq[M - 1], shared(seq[M - 2], seq[M - 1]));
+      }
+      c->path_j.push_back(seq);
+      c->path_bb.push_back(bb);
+      c->path_ba.push_back(ba);
+      c->path_slot.resize(c->tbody.size(), 0);
+      for (int sl = slot0; sl < (int)c->tbody.size(); ++sl) c->path_slot[sl] = 1;
+      c->npath++;
+    }
     if (cls[ci] == CLS_LOOP) {
       // loop rows and the joint -> loop component map (generic indices)
       if (c->jloop.empty()) c->jloop.assign(c->gj_in.size(), -1);
@@ -960,6 +1035,12 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     std::vector<int> nalive(nsl), alive(nsl, 1), sel(nsl, 0), live_child(nsl, -1), raked_child(nsl, 0);
     for (int s = 0; s < nsl; ++s) nalive[s] = (int)kids[s].size();
     int remaining = nsl;
+    c->path_slot.resize(nsl, 0);
+    for (int sl = 0; sl < nsl; ++sl)
+      if (c->path_slot[sl]) {
+        alive[sl] = 0;
+        --remaining;
+      }
     std::vector<int> chosen;
     while (remaining > 0) {
       const int round0 = (int)c->tc_ops.size();
@@ -1063,6 +1144,110 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
         op.fc = c->foff[op.c];
       }
     }
+  }
+  // ---- path plan: level-0 units (one per path joint) with the clique rows
+  // of their bodies, then levels of segments of at most path_T units
+  if (c->npath > 0) {
+    if (const char *ps = std::getenv("MABD_PATH_SEGMENT")) {  // "T" or "T0,T1"
+      int v0 = 0, v1 = 0;
+      const int got = std::sscanf(ps, "%d,%d", &v0, &v1);
+      if (got >= 1 && v0 >= 2 && v0 <= 64) c->path_T = c->path_T1 = v0;
+      if (got == 2 && v1 >= 2 && v1 <= 64) c->path_T1 = v1;
+    }
+    std::vector<int> slot_of(c->sol2in.size(), -1);
+    for (int sl = 0; sl < (int)c->tbody.size(); ++sl) slot_of[c->tbody[sl]] = sl;
+    auto clique_row = [&](int sl, int gk) {  // first row of generic joint gk in slot sl's clique
+      int r = 0;
+      for (int e = c->tabs_off[sl]; e < c->tabs_off[sl + 1]; ++e) {
+        if (abs_joint(c->tabs[e]) == gk) return r;
+        r += abs_rows(c->tabs[e]);
+      }
+      return (c->tpk[sl] >= 0 && (c->tpk[sl] >> 1) == gk) ? r : -1;
+    };
+    std::vector<int> pstart;  // first level-0 unit of each path
+    bool ok = true;
+    for (int p = 0; p < c->npath; ++p) {
+      const auto &seq = c->path_j[p];
+      const int M = (int)seq.size();
+      pstart.push_back((int)c->pu0.size());
+      for (int i = 0; i < M; ++i) {
+        PathUnit0 u{};
+        const int gk = gidx[seq[i]];
+        u.r = joint_rows(Jn->type[seq[i]]);
+        u.gj = gk;
+        u.fb = u.fa = -1;
+        u.ob = u.obp = u.oa = u.oan = -1;
+        if (c->path_bb[p][i] >= 0) {
+          const int sl = slot_of[c->in2sol[c->path_bb[p][i]]];
+          u.fb = c->foff[sl];
+          u.ldb = c->tne[sl] + 5;
+          u.ob = clique_row(sl, gk);
+          u.obp = i > 0 ? clique_row(sl, gidx[seq[i - 1]]) : -1;
+          ok = ok && u.ob >= 0 && (i == 0 || u.obp >= 0);
+        }
+        if (c->path_ba[p][i] >= 0) {
+          const int sl = slot_of[c->in2sol[c->path_ba[p][i]]];
+          u.fa = c->foff[sl];
+          u.lda = c->tne[sl] + 5;
+          u.oa = clique_row(sl, gk);
+          u.oan = i < M - 1 ? clique_row(sl, gidx[seq[i + 1]]) : -1;
+          ok = ok && u.oa >= 0 && (i == M - 1 || u.oan >= 0);
+        }
+        ok = ok && (i == M - 1 || u.fa >= 0);  // consecutive joints share a body
+        c->pu0.push_back(u);
+      }
+    }
+    if (!ok) {
+      delete c;
+      return fail(nullptr, MABD_ERR_TOPOLOGY, "path component: clique rows not found");
+    }
+    // levels: each live path's units split evenly into ceil(count / T)
+    // segments; the segments' last units are the next level's units
+    struct Live { int start, count; };
+    std::vector<Live> live;
+    std::vector<int32_t> rows_cur;
+    for (int p = 0; p < c->npath; ++p) live.push_back({pstart[p], (int)c->path_j[p].size()});
+    for (const PathUnit0 &u : c->pu0) rows_cur.push_back(u.r);
+    PathPlan &P = c->pplan;
+    P.seg_off[0] = 0;
+    P.unit_off[0] = P.unit_off[1] = 0;
+    P.fac_off[0] = 0;
+    int lvl = 0;
+    while (!live.empty()) {
+      if (lvl >= PATH_MAXLEVEL) {
+        delete c;
+        return fail(nullptr, MABD_ERR_TOPOLOGY, "path component: too many levels");
+      }
+      std::vector<Live> nxt;
+      std::vector<int32_t> rows_next;
+      const int seg0 = (int)c->pseg.size();
+      const int T = lvl == 0 ? c->path_T : c->path_T1;
+      for (const Live &L : live) {
+        const int g = (L.count + T - 1) / T;
+        int u0 = L.start;
+        const int k0 = (int)rows_next.size();
+        for (int j = 0; j < g; ++j) {
+          PathSeg sg{};
+          sg.u0 = u0;
+          sg.t = L.count / g + (j < L.count % g ? 1 : 0);
+          sg.k = k0 + j;
+          sg.flags = (j > 0 ? 1 : 0) | (j == g - 1 ? 2 : 0) | (g == 1 ? 4 : 0);
+          c->pseg.push_back(sg);
+          rows_next.push_back(rows_cur[u0 + sg.t - 1]);
+          u0 += sg.t;
+        }
+        if (g > 1) nxt.push_back({k0, g});
+      }
+      const int nseg = (int)c->pseg.size() - seg0;
+      P.seg_off[lvl + 1] = (int32_t)c->pseg.size();
+      P.fac_off[lvl + 1] = P.fac_off[lvl] + (int64_t)(T - 1) * PATH_FREC * nseg;
+      P.unit_off[lvl + 2] = P.unit_off[lvl + 1] + (int64_t)rows_next.size();
+      c->prows.insert(c->prows.end(), rows_next.begin(), rows_next.end());
+      rows_cur.swap(rows_next);
+      live.swap(nxt);
+      ++lvl;
+    }
+    P.nlevel = lvl;
   }
   // graph components: bodies after the trees, solved by PCG
   std::vector<int32_t> graph_bodies;
@@ -1320,6 +1505,25 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(dalloc(c, &c->d_fac, (size_t)std::max<int64_t>(c->fac_size, 1)));
   if (e == hipSuccess) chk(upload(c, &c->d_tc_ops, c->tc_ops));
   if (e == hipSuccess) chk(dalloc(c, &c->d_crec, (size_t)std::max<int64_t>(c->crec_size, 1)));
+  if (c->npath > 0) {
+    PathPlan &P = c->pplan;
+    const int64_t nu = std::max<int64_t>(P.unit_off[P.nlevel + 1], 1);
+    PathUnit0 *du0 = nullptr;
+    PathSeg *dseg = nullptr;
+    int32_t *drows = nullptr;
+    if (e == hipSuccess) chk(upload(c, &du0, c->pu0));
+    if (e == hipSuccess) chk(upload(c, &dseg, c->pseg));
+    if (e == hipSuccess) {
+      if (c->prows.empty()) c->prows.push_back(0);
+      chk(upload(c, &drows, c->prows));
+    }
+    if (e == hipSuccess) chk(dalloc(c, &P.unit, (size_t)(PATH_UREC * nu)));
+    if (e == hipSuccess) chk(dalloc(c, &P.lam, (size_t)(5 * nu)));
+    if (e == hipSuccess) chk(dalloc(c, &P.fac, (size_t)std::max<int64_t>(P.fac_off[P.nlevel], 1)));
+    P.u0 = du0;
+    P.seg = dseg;
+    P.rows = drows;
+  }
   if (c->nloop > 0) {
     if (e == hipSuccess) chk(upload(c, &c->d_jloop, c->jloop));
     if (e == hipSuccess) chk(upload(c, &c->d_loff, c->loff));
@@ -1473,6 +1677,8 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   }
   c->stats.n_chain = (int)c->chains.size();
   c->stats.n_tree = c->ntree;
+  c->stats.n_path = c->npath;
+  c->stats.path_levels = c->npath > 0 ? c->pplan.nlevel : 0;
   c->stats.n_graph = c->ngraph;
   c->stats.n_loop = c->nloop;
   c->stats.n_dyn = c->nd;
@@ -1839,7 +2045,7 @@ hipError_t generic_refine(mabd_ctx *c, double h, int a, int b, const TreeArgs &t
     tc.glam = c->d_dlam;
     tc.f32 = 1;
     launch_tree(tc, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(), ((int)c->tc_rounds.size() - 1) / TC_NSEG,
-                c->tree_split, c->tree_order, s);
+                c->tree_split, c->tree_order, c->npath ? &c->pplan : nullptr, s);
     launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_dlam, c->d_Rg, c->d_uc, c->ns,
                   c->d_shp, c->d_hinv, c->d_q[b], c->d_q[b], c->d_qd[b], h, 1, c->d_status, c->d_gj, 0,
                   nullptr, c->opt.body_solve, 0, s);
@@ -1942,7 +2148,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       ta.f32 = c->gen_ir ? 1 : 0;
       tm.run(5, [&] {
         launch_tree(ta, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
-                    ((int)c->tc_rounds.size() - 1) / TC_NSEG, c->tree_split, c->tree_order, s);
+                    ((int)c->tc_rounds.size() - 1) / TC_NSEG, c->tree_split, c->tree_order, c->npath ? &c->pplan : nullptr, s);
         if (c->nloop > 0) {
           // loop-breaker Schur complement (Case III): the columns
           // S_AA^{-1} S_AD e_j by tree solves of the loop rows' increments
@@ -1957,7 +2163,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
                                c->d_uloop, 1, s);
             tw.glam = c->d_wcol + (size_t)j * ws;
             launch_tree(tw, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
-                        ((int)c->tc_rounds.size() - 1) / TC_NSEG, c->tree_split, c->tree_order, s);
+                        ((int)c->tc_rounds.size() - 1) / TC_NSEG, c->tree_split, c->tree_order, c->npath ? &c->pplan : nullptr, s);
             launch_loop_inject(c->nloop, c->d_loff, c->d_lrow, j, c->d_gj, c->d_gl, c->d_shp, c->d_hinv, c->ns,
                                c->d_uloop, 0, s);
           }
@@ -2056,7 +2262,10 @@ struct NoTimer {
 // contexts large enough for the autotuner to time their schedules
 constexpr int TUNE_MIN_ROWS = 20000;
 bool tune_chain(const mabd_ctx *c) { return c->nchain_rows >= TUNE_MIN_ROWS; }
-bool tune_tree(const mabd_ctx *c) { return (int)c->tbody.size() >= TUNE_MIN_ROWS && c->ngraph == 0; }
+bool tune_tree(const mabd_ctx *c) {  // slots of the contraction (path slots take no part)
+  const int contracted = (int)c->tbody.size() - (int)std::count(c->path_slot.begin(), c->path_slot.end(), 1);
+  return contracted >= TUNE_MIN_ROWS && c->ngraph == 0;
+}
 
 // Times the whole step for every chain tile form, then for every tree
 // schedule, and keeps the fastest of each.  Every timed step reads the

@@ -204,11 +204,12 @@ def test_tree_and_hinge_paths():
 
 def test_deep_hinge_chain_contraction():
     """3,000 hinge-jointed links: a path of 5-row blocks, eliminated almost
-    entirely by compress rounds of the tree contraction."""
+    entirely by compress rounds of the tree contraction (the path solver off;
+    tests/test_gpu_paths.py covers it)."""
     asm = mi.chain(3000, seed=41, hinge_frac=1.0)
     asm.qd0[1:] = np.random.default_rng(41).normal(0, 0.05, (asm.n - 1, 12))
     say("all-hinge chain 3000")
-    say("worst", teacher_forced(asm, 2, tol_v=TOL_V_TREE))
+    say("worst", teacher_forced(asm, 2, tol_v=TOL_V_TREE, path_solver=0))
 
 
 def test_wide_tree_contraction():
