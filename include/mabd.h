@@ -177,9 +177,9 @@ typedef struct {
                               0: by the tree
                               contraction like every other tree.  Both are exact
                               (Sec. 5.3) and agree to rounding.  The environment
-                              variable MABD_PATH_SEGMENT = T or T0,T1 (2..64) sets the
-                              segment length (T0 at the first level, T1 above) at
-                              mabd_create (for testing)                                */
+                              variable MABD_PATH_SEGMENT = T or T0,T1 sets the segment
+                              length (T0 = 2..16 at the first level, T1 = 2..64 above)
+                              at mabd_create (for testing)                             */
   const char *tune_cache;  /* path of a tuning cache file, or NULL (default): with
                               autotune on, a context whose device and schedule shape
                               (chain rows and count, tree slots and rounds) have an

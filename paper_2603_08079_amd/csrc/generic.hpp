@@ -197,6 +197,7 @@ namespace mabd {
 // separators (the next level).  A path with one segment at a level solves
 // its separator there; back-substitution runs the levels in reverse.
 constexpr int PATH_MAXLEVEL = 32;
+constexpr int PATH_TMAX = 16;  // longest level-0 segment (its unit records are staged in LDS)
 constexpr int PATH_UREC = 65;  // level >= 1 unit: D (15, packed lower), y (5), F (25: coupling
                                // from the previous unit, its rows x ours), dD (15), dy (5)
 constexpr int PATH_FREC = 70;  // per eliminated unit: L (15, the reciprocals of the pivots on
@@ -204,16 +205,13 @@ constexpr int PATH_FREC = 70;  // per eliminated unit: L (15, the reciprocals of
 enum { PU_D = 0, PU_Y = 15, PU_F = 20, PU_DD = 45, PU_DY = 60 };
 enum { PF_L = 0, PF_Z = 15, PF_W = 20, PF_G = 45 };
 
-// a level-0 unit: one joint of a path, and the clique matrices (K0, y0 of the
-// tree pre-pass, lower triangle, leading dimension ld) of the bodies before and
-// after it on the path, with the first clique row of this joint and of the
-// neighbouring joint there (-1: none)
-struct PathUnit0 {
-  int64_t fb, fa;    // factor slot offsets of the bodies before / after (-1: none)
-  int32_t ldb, lda;
-  int32_t ob, obp;   // body before: rows of this joint, of the previous joint
-  int32_t oa, oan;   // body after: rows of this joint, of the next joint
-  int32_t r, gj;     // rows, generic joint index (multipliers at 5 gj)
+// a level-0 unit: one joint of a path, with the dynamic bodies before and
+// after it on the path (solver index, -1: none) and its side of the joint
+// there (0: a, 1: b), which selects the joint rows L_a or L_b
+struct PathUnitF {
+  int32_t gj, r;     // generic joint index (multipliers at 5 gj), rows
+  int32_t bb, sb;    // body before, its side
+  int32_t ba, sa;    // body after, its side
 };
 
 struct PathSeg {
@@ -226,12 +224,15 @@ struct PathSeg {
 
 struct PathPlan {
   int nlevel;                              // levels with segments
-  const PathUnit0 *u0;
+  int T0;                                  // segment length of level 0
+  const PathUnitF *uf;
   const PathSeg *seg;                      // level l: [seg_off[l], seg_off[l+1])
   const int32_t *rows;                     // units of levels >= 1
   double *unit;                            // PATH_UREC per unit of levels >= 1
   double *lam;                             // 5 per unit of levels >= 1
-  double *fac;                             // level l at fac_off[l]: (T-1) x PATH_FREC x segments
+  double *fac;                             // level l at fac_off[l]: (T-1) x PATH_FREC per segment,
+                                           // level 0 segment-major, levels >= 1 interleaved
+                                           // across the segments
   int32_t seg_off[PATH_MAXLEVEL + 1];
   int64_t unit_off[PATH_MAXLEVEL + 2];     // level l >= 1 units from unit_off[l]
   int64_t fac_off[PATH_MAXLEVEL + 1];

@@ -1539,6 +1539,8 @@ void launch_path(const TreeArgs &a, const PathPlan &P, hipStream_t s);
 
 void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
                  int split_ops, int order, const PathPlan *path, hipStream_t s) {
+  // path components (no slots): their own solve
+  if (path && path->nlevel > 0) launch_path(a, *path, s);
   if (nslots <= 0) return;
   hipLaunchKernelGGL(tree_prep_kernel, dim3((nslots + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J, nslots);
   // per round, TC_NSEG offsets of the operation list (o[TC_NSEG] starts the
@@ -1623,8 +1625,6 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
                          a, J, o[TC_NCLASS], o[TC_NSEG]);
     launch_round(o, true);
   }
-  // path components: their slots take no part in the rounds
-  if (path && path->nlevel > 0) launch_path(a, *path, s);
 }
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,
                    const double *glam, const double *Rg, const double *ug, int64_t ns,

@@ -226,9 +226,8 @@ struct mabd_ctx {
   // separators leave the lanes' dependent steps, not memory, as the bound
   int npath = 0, path_T = 16, path_T1 = 4;
   std::vector<std::vector<int>> path_j, path_bb, path_ba;
-  std::vector<char> path_slot;  // tree slot -> solved as part of a path
   PathPlan pplan{};
-  std::vector<PathUnit0> pu0;
+  std::vector<PathUnitF> pu0;
   std::vector<PathSeg> pseg;
   std::vector<int32_t> prows;
   int32_t *d_tne = nullptr;
@@ -860,11 +859,70 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       continue;
     }
     // a path: every body carries at most two joints (a tree, so its joints
-    // form one sequence, consecutive joints sharing a body)
+    // form one sequence, consecutive joints sharing a body).  Its bodies
+    // take no tree slot: they go into the solver order along the path, and
+    // the path solve forms its blocks from the joint rows
     bool is_path = opt.path_solver != 0 && cls[ci] == CLS_TREE;
     for (int b : bs)
       if (binc[b].size() > 2) is_path = false;
-    const int slot0 = (int)c->tbody.size();
+    if (is_path) {
+      const auto &js = cjoints[ci];
+      std::map<int, std::vector<int>> jadj;  // joints sharing a body
+      for (int b : bs)
+        if (binc[b].size() == 2) {
+          jadj[binc[b][0]].push_back(binc[b][1]);
+          jadj[binc[b][1]].push_back(binc[b][0]);
+        }
+      int start = js[0];
+      for (int k : js)
+        if (jadj[k].size() < 2) { start = k; break; }
+      std::vector<int> seq{start};
+      std::set<int> used{start};
+      for (;;) {
+        int nxt = -1;
+        for (int k2 : jadj[seq.back()])
+          if (!used.count(k2)) nxt = k2;
+        if (nxt < 0) break;
+        used.insert(nxt);
+        seq.push_back(nxt);
+      }
+      auto shared = [&](int k1, int k2) {
+        for (int s1 : {Jn->a[k1], Jn->b[k1]})
+          if (dyn(s1) && (s1 == Jn->a[k2] || s1 == Jn->b[k2])) return s1;
+        return -1;
+      };
+      auto other = [&](int k, int excl) {  // a dynamic side of k other than excl
+        for (int s1 : {Jn->a[k], Jn->b[k]})
+          if (dyn(s1) && s1 != excl) return s1;
+        return -1;
+      };
+      const int M = (int)seq.size();
+      std::vector<int> bb(M), ba(M);
+      for (int i = 0; i < M; ++i) {
+        if (M == 1) {
+          bb[0] = dyn(Jn->a[seq[0]]) ? Jn->a[seq[0]] : -1;
+          ba[0] = dyn(Jn->b[seq[0]]) ? Jn->b[seq[0]] : -1;
+          break;
+        }
+        bb[i] = i > 0 ? shared(seq[i - 1], seq[i]) : other(seq[0], shared(seq[0], seq[1]));
+        ba[i] = i < M - 1 ? shared(seq[i], seq[i + 1]) : other(seq[M - 1], shared(seq[M - 2], seq[M - 1]));
+      }
+      // bodies along the path
+      int added = 0;
+      if (bb[0] >= 0) { add_body(bb[0]); ++added; }
+      for (int i = 0; i < M; ++i)
+        if (ba[i] >= 0 && (i == M - 1 || ba[i] == bb[i + 1])) { add_body(ba[i]); ++added; }
+      if ((int)seq.size() != (int)js.size() || added != (int)bs.size()) {
+        delete c;
+        return fail(nullptr, MABD_ERR_TOPOLOGY, "path component: joints do not form one sequence");
+      }
+      c->path_j.push_back(seq);
+      c->path_bb.push_back(bb);
+      c->path_ba.push_back(ba);
+      c->npath++;
+      c->ntree++;
+      continue;
+    }
     int root = bs[0];
     for (int b : bs) {
       bool has_unary = false;
@@ -935,59 +993,6 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       c->lvl_off.push_back((int)c->tbody.size());
     }
     c->comp_lvl.push_back((int)c->lvl_off.size() - 1);
-    if (is_path) {
-      const auto &js = cjoints[ci];
-      std::map<int, std::vector<int>> jadj;  // joints sharing a body
-      for (int b : bs)
-        if (binc[b].size() == 2) {
-          jadj[binc[b][0]].push_back(binc[b][1]);
-          jadj[binc[b][1]].push_back(binc[b][0]);
-        }
-      int start = js[0];
-      for (int k : js)
-        if (jadj[k].size() < 2) { start = k; break; }
-      std::vector<int> seq{start};
-      std::set<int> used{start};
-      for (;;) {
-        int nxt = -1;
-        for (int k2 : jadj[seq.back()])
-          if (!used.count(k2)) nxt = k2;
-        if (nxt < 0) break;
-        used.insert(nxt);
-        seq.push_back(nxt);
-      }
-      if (seq.size() != js.size()) {
-        delete c;
-        return fail(nullptr, MABD_ERR_TOPOLOGY, "path component: joints do not form one sequence");
-      }
-      auto shared = [&](int k1, int k2) {
-        for (int s1 : {Jn->a[k1], Jn->b[k1]})
-          if (dyn(s1) && (s1 == Jn->a[k2] || s1 == Jn->b[k2])) return s1;
-        return -1;
-      };
-      auto other = [&](int k, int excl) {  // a dynamic side of k other than excl
-        for (int s1 : {Jn->a[k], Jn->b[k]})
-          if (dyn(s1) && s1 != excl) return s1;
-        return -1;
-      };
-      const int M = (int)seq.size();
-      std::vector<int> bb(M), ba(M);
-      for (int i = 0; i < M; ++i) {
-        if (M == 1) {
-          bb[0] = dyn(Jn->a[seq[0]]) ? Jn->a[seq[0]] : -1;
-          ba[0] = dyn(Jn->b[seq[0]]) ? Jn->b[seq[0]] : -1;
-          break;
-        }
-        bb[i] = i > 0 ? shared(seq[i - 1], seq[i]) : other(seq[0], shared(seq[0], seq[1]));
-        ba[i] = i < M - 1 ? shared(seq[i], seq[i + 1]) : other(seq[M - 1], shared(seq[M - 2], seq[M - 1]));
-      }
-      c->path_j.push_back(seq);
-      c->path_bb.push_back(bb);
-      c->path_ba.push_back(ba);
-      c->path_slot.resize(c->tbody.size(), 0);
-      for (int sl = slot0; sl < (int)c->tbody.size(); ++sl) c->path_slot[sl] = 1;
-      c->npath++;
-    }
     if (cls[ci] == CLS_LOOP) {
       // loop rows and the joint -> loop component map (generic indices)
       if (c->jloop.empty()) c->jloop.assign(c->gj_in.size(), -1);
@@ -1035,12 +1040,6 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     std::vector<int> nalive(nsl), alive(nsl, 1), sel(nsl, 0), live_child(nsl, -1), raked_child(nsl, 0);
     for (int s = 0; s < nsl; ++s) nalive[s] = (int)kids[s].size();
     int remaining = nsl;
-    c->path_slot.resize(nsl, 0);
-    for (int sl = 0; sl < nsl; ++sl)
-      if (c->path_slot[sl]) {
-        alive[sl] = 0;
-        --remaining;
-      }
     std::vector<int> chosen;
     while (remaining > 0) {
       const int round0 = (int)c->tc_ops.size();
@@ -1153,53 +1152,24 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       const int got = std::sscanf(ps, "%d,%d", &v0, &v1);
       if (got >= 1 && v0 >= 2 && v0 <= 64) c->path_T = c->path_T1 = v0;
       if (got == 2 && v1 >= 2 && v1 <= 64) c->path_T1 = v1;
+      c->path_T = std::min(c->path_T, PATH_TMAX);
     }
-    std::vector<int> slot_of(c->sol2in.size(), -1);
-    for (int sl = 0; sl < (int)c->tbody.size(); ++sl) slot_of[c->tbody[sl]] = sl;
-    auto clique_row = [&](int sl, int gk) {  // first row of generic joint gk in slot sl's clique
-      int r = 0;
-      for (int e = c->tabs_off[sl]; e < c->tabs_off[sl + 1]; ++e) {
-        if (abs_joint(c->tabs[e]) == gk) return r;
-        r += abs_rows(c->tabs[e]);
-      }
-      return (c->tpk[sl] >= 0 && (c->tpk[sl] >> 1) == gk) ? r : -1;
-    };
     std::vector<int> pstart;  // first level-0 unit of each path
-    bool ok = true;
     for (int p = 0; p < c->npath; ++p) {
       const auto &seq = c->path_j[p];
-      const int M = (int)seq.size();
       pstart.push_back((int)c->pu0.size());
-      for (int i = 0; i < M; ++i) {
-        PathUnit0 u{};
-        const int gk = gidx[seq[i]];
-        u.r = joint_rows(Jn->type[seq[i]]);
-        u.gj = gk;
-        u.fb = u.fa = -1;
-        u.ob = u.obp = u.oa = u.oan = -1;
-        if (c->path_bb[p][i] >= 0) {
-          const int sl = slot_of[c->in2sol[c->path_bb[p][i]]];
-          u.fb = c->foff[sl];
-          u.ldb = c->tne[sl] + 5;
-          u.ob = clique_row(sl, gk);
-          u.obp = i > 0 ? clique_row(sl, gidx[seq[i - 1]]) : -1;
-          ok = ok && u.ob >= 0 && (i == 0 || u.obp >= 0);
-        }
-        if (c->path_ba[p][i] >= 0) {
-          const int sl = slot_of[c->in2sol[c->path_ba[p][i]]];
-          u.fa = c->foff[sl];
-          u.lda = c->tne[sl] + 5;
-          u.oa = clique_row(sl, gk);
-          u.oan = i < M - 1 ? clique_row(sl, gidx[seq[i + 1]]) : -1;
-          ok = ok && u.oa >= 0 && (i == M - 1 || u.oan >= 0);
-        }
-        ok = ok && (i == M - 1 || u.fa >= 0);  // consecutive joints share a body
+      for (int i = 0; i < (int)seq.size(); ++i) {
+        const int k = seq[i];
+        PathUnitF u{};
+        u.gj = gidx[k];
+        u.r = joint_rows(Jn->type[k]);
+        const int bb = c->path_bb[p][i], ba = c->path_ba[p][i];
+        u.bb = bb >= 0 ? c->in2sol[bb] : -1;
+        u.sb = bb >= 0 && Jn->b[k] == bb ? 1 : 0;
+        u.ba = ba >= 0 ? c->in2sol[ba] : -1;
+        u.sa = ba >= 0 && Jn->b[k] == ba ? 1 : 0;
         c->pu0.push_back(u);
       }
-    }
-    if (!ok) {
-      delete c;
-      return fail(nullptr, MABD_ERR_TOPOLOGY, "path component: clique rows not found");
     }
     // levels: each live path's units split evenly into ceil(count / T)
     // segments; the segments' last units are the next level's units
@@ -1207,7 +1177,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     std::vector<Live> live;
     std::vector<int32_t> rows_cur;
     for (int p = 0; p < c->npath; ++p) live.push_back({pstart[p], (int)c->path_j[p].size()});
-    for (const PathUnit0 &u : c->pu0) rows_cur.push_back(u.r);
+    for (const PathUnitF &u : c->pu0) rows_cur.push_back(u.r);
     PathPlan &P = c->pplan;
     P.seg_off[0] = 0;
     P.unit_off[0] = P.unit_off[1] = 0;
@@ -1248,6 +1218,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       ++lvl;
     }
     P.nlevel = lvl;
+    P.T0 = c->path_T;
   }
   // graph components: bodies after the trees, solved by PCG
   std::vector<int32_t> graph_bodies;
@@ -1508,7 +1479,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (c->npath > 0) {
     PathPlan &P = c->pplan;
     const int64_t nu = std::max<int64_t>(P.unit_off[P.nlevel + 1], 1);
-    PathUnit0 *du0 = nullptr;
+    PathUnitF *du0 = nullptr;
     PathSeg *dseg = nullptr;
     int32_t *drows = nullptr;
     if (e == hipSuccess) chk(upload(c, &du0, c->pu0));
@@ -1520,7 +1491,7 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     if (e == hipSuccess) chk(dalloc(c, &P.unit, (size_t)(PATH_UREC * nu)));
     if (e == hipSuccess) chk(dalloc(c, &P.lam, (size_t)(5 * nu)));
     if (e == hipSuccess) chk(dalloc(c, &P.fac, (size_t)std::max<int64_t>(P.fac_off[P.nlevel], 1)));
-    P.u0 = du0;
+    P.uf = du0;
     P.seg = dseg;
     P.rows = drows;
   }
@@ -2262,10 +2233,7 @@ struct NoTimer {
 // contexts large enough for the autotuner to time their schedules
 constexpr int TUNE_MIN_ROWS = 20000;
 bool tune_chain(const mabd_ctx *c) { return c->nchain_rows >= TUNE_MIN_ROWS; }
-bool tune_tree(const mabd_ctx *c) {  // slots of the contraction (path slots take no part)
-  const int contracted = (int)c->tbody.size() - (int)std::count(c->path_slot.begin(), c->path_slot.end(), 1);
-  return contracted >= TUNE_MIN_ROWS && c->ngraph == 0;
-}
+bool tune_tree(const mabd_ctx *c) { return (int)c->tbody.size() >= TUNE_MIN_ROWS && c->ngraph == 0; }
 
 // Times the whole step for every chain tile form, then for every tree
 // schedule, and keeps the fastest of each.  Every timed step reads the
