@@ -1538,10 +1538,14 @@ void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, in
 void launch_path(const TreeArgs &a, const PathPlan &P, hipStream_t s);
 
 void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
-                 int split_ops, int order, const PathPlan *path, hipStream_t s) {
+                 int split_ops, int order, const PathPlan *path, hipStream_t s, int hook_round,
+                 void (*hook)(void *), void *hook_arg) {
   // path components (no slots): their own solve
   if (path && path->nlevel > 0) launch_path(a, *path, s);
-  if (nslots <= 0) return;
+  if (nslots <= 0) {
+    if (hook) hook(hook_arg);
+    return;
+  }
   hipLaunchKernelGGL(tree_prep_kernel, dim3((nslots + TEAMS - 1) / TEAMS), dim3(TREE_BLOCK), 0, s, a, J, nslots);
   // per round, TC_NSEG offsets of the operation list (o[TC_NSEG] starts the
   // next round): rakes with cliques of <= 10, 16, 32, 64 rows, then
@@ -1611,13 +1615,21 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
     if (apart16) launch_classes(o, g16, 2, back, false);
     launch_classes(o, rest, nrest, back, false);
   };
+  // the hook (work launched elsewhere, e.g. on another stream) runs before
+  // forward round hook_round, or after the last one
+  bool hooked = false;
   for (int r = 0; r < nround; ++r) {
     const int32_t *o = rounds + TC_NSEG * r;
+    if (hook && r == hook_round) {
+      hook(hook_arg);
+      hooked = true;
+    }
     launch_round(o, false);
     if (o[TC_NSEG] > o[TC_NCLASS])
       hipLaunchKernelGGL(tc_compress_kernel, dim3((o[TC_NSEG] - o[TC_NCLASS] + TEAMS - 1) / TEAMS),
                          dim3(TREE_BLOCK), 0, s, a, J, o[TC_NCLASS], o[TC_NSEG]);
   }
+  if (hook && !hooked) hook(hook_arg);
   for (int r = nround - 1; r >= 0; --r) {
     const int32_t *o = rounds + TC_NSEG * r;
     if (o[TC_NSEG] > o[TC_NCLASS])

@@ -50,7 +50,9 @@ void launch_raise(uint32_t *status, uint32_t flag, hipStream_t s);
 void launch_gjoint(int m, const GJoint *J, const double *q, const double *Rg, int64_t ns, int hg,
                    double *gl, hipStream_t s);
 void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *rounds, int nround,
-                 int split_ops, int order, const PathPlan *path, hipStream_t s);
+                 int split_ops, int order, const PathPlan *path, hipStream_t s, int hook_round = -1,
+                 void (*hook)(void *) = nullptr, void *hook_arg = nullptr);
+void launch_path(const TreeArgs &a, const PathPlan &P, hipStream_t s);
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
@@ -228,6 +230,12 @@ struct mabd_ctx {
   std::vector<std::vector<int>> path_j, path_bb, path_ba;
   PathPlan pplan{};
   std::vector<PathUnitF> pu0;
+  // with both paths (at least 16,384 joints) and contracted trees: the
+  // step's path solve runs on a second stream beside the contraction rounds
+  // (forked and joined by events)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int fork_round = 0;  // forward round of the contraction before which the paths fork
   std::vector<PathSeg> pseg;
   std::vector<int32_t> prows;
   int32_t *d_tne = nullptr;
@@ -558,6 +566,9 @@ void mabd_destroy(mabd_ctx *c) {
   if (c->h_diag) (void)hipHostFree(c->h_diag);
   if (c->h_irout) (void)hipHostFree(c->h_irout);
   if (c->pend_ev) (void)hipEventDestroy(c->pend_ev);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->side) (void)hipStreamDestroy(c->side);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1119,6 +1130,12 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
       }
     }
     c->tc_rounds.push_back((int)c->tc_ops.size());
+    // the paths fork before the third-to-last forward round: the last rounds
+    // hold few operations and leave most of the GPU idle (forking before
+    // the first round made the path kernels compete with the large rounds;
+    // measured on the 4,096-assembly batch: 9.89 ms at round 0, 9.78 ms at
+    // round 10 of 13)
+    c->fork_round = std::max(0, ((int)c->tc_rounds.size() - 1) / TC_NSEG - 3);
     // factor slots: K and y with leading dimension absorbed rows + 5, plus
     // the pre-pass scratch of large cliques
     c->foff.clear();
@@ -1598,6 +1615,12 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
   if (e == hipSuccess) chk(dalloc(c, &c->d_status, 4));
   if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_status, 4 * sizeof(uint32_t)));
   if (e == hipSuccess) chk(hipEventCreateWithFlags(&c->pend_ev, hipEventDisableTiming));
+  // (a few short paths beside a large tree are not worth the fork's events)
+  if (e == hipSuccess && c->pu0.size() >= 16384 && !c->tbody.empty()) {
+    chk(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    if (e == hipSuccess) chk(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    if (e == hipSuccess) chk(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  }
   {
     // the fixed scratch of mabd_residual_noalloc on this (current) device
     int dev = 0;
@@ -2118,8 +2141,25 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       ta.crec = c->d_crec;
       ta.f32 = c->gen_ir ? 1 : 0;
       tm.run(5, [&] {
+        // paths beside the contraction rounds (whose tail rounds leave most
+        // of the GPU idle); sequential when kernel groups are timed
+        const bool fork = c->side && (c->opt.diagnostics & 2) == 0;
+        struct Fork {
+          mabd_ctx *c;
+          const TreeArgs *ta;
+          hipStream_t s;
+        } fk{c, &ta, s};
+        auto do_fork = [](void *p) {
+          const Fork &f = *static_cast<Fork *>(p);
+          (void)hipEventRecord(f.c->ev_fork, f.s);
+          (void)hipStreamWaitEvent(f.c->side, f.c->ev_fork, 0);
+          launch_path(*f.ta, f.c->pplan, f.c->side);
+          (void)hipEventRecord(f.c->ev_join, f.c->side);
+        };
         launch_tree(ta, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(),
-                    ((int)c->tc_rounds.size() - 1) / TC_NSEG, c->tree_split, c->tree_order, c->npath ? &c->pplan : nullptr, s);
+                    ((int)c->tc_rounds.size() - 1) / TC_NSEG, c->tree_split, c->tree_order,
+                    !fork && c->npath ? &c->pplan : nullptr, s, c->fork_round, fork ? +do_fork : nullptr, &fk);
+        if (fork) (void)hipStreamWaitEvent(s, c->ev_join, 0);
         if (c->nloop > 0) {
           // loop-breaker Schur complement (Case III): the columns
           // S_AA^{-1} S_AD e_j by tree solves of the loop rows' increments

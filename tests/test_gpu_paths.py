@@ -115,11 +115,11 @@ def test_path_ends():
         say("worst", teacher_forced(asm, 2))
 
 
-def ragged_batch(seed):
+def ragged_batch(seed, count=40, longest=90):
     rng = np.random.default_rng(seed)
     parts = []
-    for i in range(40):
-        n = int(rng.integers(2, 90))
+    for i in range(count):
+        n = int(rng.integers(2, longest))
         if i % 5 == 4:
             parts.append(mi.tree(n + 5, seed=seed + i, window=4, origin=(0.0, 10.0 * i, 0.0)))
         elif i % 7 == 6:
@@ -155,6 +155,22 @@ def test_path_solver_matches_contraction(seg, monkeypatch):
     # 1.7e-15, qdot 2.1e-11, multipliers 1.2e-10 of the largest); an indexing
     # mistake in either would show at O(1)
     assert eq < 1e-12 and eqd < 1e-10 and el < 1e-9
+
+
+def test_forked_path_solve_equals_sequential():
+    """With trees beside the paths the step's path solve runs on a second
+    stream, joined before the back-projection; with kernel groups timed
+    (diagnostics bit 1) it runs in sequence.  The two solves touch disjoint
+    data, so the states are bitwise equal, eagerly and from a replayed
+    graph."""
+    asm = ragged_batch(270, count=400, longest=160)  # over 16,384 path joints: forked
+    q0, qd0, l0, s0 = run(asm, 4, diagnostics=2)
+    q1, qd1, l1, s1 = run(asm, 4)
+    q2, qd2, l2, s2 = run(asm, 4, use_graph=0)
+    say("graph replay", s1["graph_replay"], "eager", s2["graph_replay"])
+    assert s1["graph_replay"] == 1 and s2["graph_replay"] == 0
+    for q, qd, lam in ((q1, qd1, l1), (q2, qd2, l2)):
+        assert np.array_equal(q, q0) and np.array_equal(qd, qd0) and np.array_equal(lam, l0)
 
 
 def test_path_form1():
