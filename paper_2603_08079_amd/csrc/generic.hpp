@@ -41,9 +41,11 @@ __host__ __device__ inline int point_side(int p) { return p >= 2 ? 1 : 0; }
 
 constexpr int GJ_FLAG_STATIC_OWNER = 1;
 
-// per-joint generic data: C (5), L_a (5x12), L_b (5x12), padded to 128 doubles
-constexpr int GL_STRIDE = 128;
-enum { GL_C = 0, GL_LA = 8, GL_LB = 68 };
+// per-joint generic data: C (5), L_a (5x12), L_b (5x12), each block starting
+// on a 128-byte line (a record is 9 lines), so that a gather of one side's
+// rows touches only the lines it uses
+constexpr int GL_STRIDE = 144;
+enum { GL_C = 0, GL_LA = 16, GL_LB = 80 };
 
 // per-joint tree data: Sigma (5x5), rho (5) of the condensed child side
 constexpr int GT_STRIDE = 64;
@@ -90,6 +92,8 @@ struct TreeArgs {
                             // instead of the joint rows (refinement right-hand sides)
   int f32;                  // 1: the clique matrices K0 = L Hbar^{-1} L^T are formed in
                             // FP32 (precision form 1; the factorisation stays FP64)
+  const uint8_t *jrows;     // rows per generic joint (a byte each, read instead of the
+                            // joint record)
 };
 
 // A component with a few closed loops (Sec. 5, Case III): its joints split

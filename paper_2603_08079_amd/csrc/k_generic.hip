@@ -386,7 +386,7 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
   const double u0 = ln < 12 ? a.u[(int64_t)ln * a.ns + b] : 0.0;
   const int ta = ln < nabs ? a.tabs[e0 + ln] : 0;
   const int tb = ln + TEAM < nabs ? a.tabs[e0 + ln + TEAM] : 0;
-  const int ptype = kpar >= 0 ? J[kpar].type : 0;
+  const int prow = kpar >= 0 ? a.jrows[kpar] : 0;
   const double *Th = a.hinv + (int64_t)HINV_STRIDE * shp;
   const double t0 = Th[ln], t1 = ln + TEAM < HINV_STRIDE ? Th[ln + TEAM] : 0.0;
   //    clique entries (absorbed joints in list order, then the parent joint),
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(TREE_BLOCK) void tree_prep_kernel(TreeArgs a, const
         un = t & 1;
       } else {
         k = kpar;
-        rows = joint_rows(ptype);
+        rows = prow;
         side = pk & 1;
         un = 1;  // parent rows take C_k only
       }
@@ -1364,7 +1364,7 @@ __global__ __launch_bounds__(256) void gapply_kernel(int b0, int b1, const int32
                               const double *gl, const double *glam, const double *Rg,
                               const double *ug, int64_t ns, const int32_t *shp, const double *hinv,
                               const double *q_cur, double *q_out, double *qd_out, double h,
-                              int accumulate, uint32_t *status, const GJoint *J, int step,
+                              int accumulate, uint32_t *status, const uint8_t *jrows, int step,
                               double *dq_save, int polar_free, int skip_free) {
   int64_t b = (int64_t)b0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= b1 || skip_step(status, step)) return;
@@ -1400,7 +1400,7 @@ __global__ __launch_bounds__(256) void gapply_kernel(int b0, int b1, const int32
   for (int e = inc_off[b]; e < inc_off[b + 1]; ++e) {
     const int ent = inc[e];
     const int k = ent >> 1, side = ent & 1;
-    const int c = joint_rows(J[k].type);
+    const int c = jrows[k];
     const double *L = gl + (int64_t)GL_STRIDE * k + (side ? GL_LB : GL_LA);
     for (int r = 0; r < c; ++r) {
       const double lr = glam[5 * (int64_t)k + r];
@@ -1641,11 +1641,11 @@ void launch_tree(const TreeArgs &a, const GJoint *J, int nslots, const int32_t *
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
-                   double *qd_out, double h, int acc, uint32_t *status, const GJoint *J,
+                   double *qd_out, double h, int acc, uint32_t *status, const uint8_t *jrows,
                    int step, double *dq_save, int polar_free, int skip_free, hipStream_t s) {
   if (b1 > b0)
     hipLaunchKernelGGL(gapply_kernel, dim3((b1 - b0 + 255) / 256), dim3(256), 0, s, b0, b1, inc_off,
-                       inc, gl, glam, Rg, ug, ns, shp, hinv, q_cur, q_out, qd_out, h, acc, status, J,
+                       inc, gl, glam, Rg, ug, ns, shp, hinv, q_cur, q_out, qd_out, h, acc, status, jrows,
                        step, dq_save, polar_free, skip_free);
 }
 void launch_gather_state(int nd, const int32_t *sol2in, const double *const *q, const double *const *qd,

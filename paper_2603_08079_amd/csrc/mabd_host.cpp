@@ -56,7 +56,7 @@ void launch_path(const TreeArgs &a, const PathPlan &P, hipStream_t s);
 void launch_gapply(int b0, int b1, const int32_t *inc_off, const int32_t *inc, const double *gl,
                    const double *glam, const double *Rg, const double *ug, int64_t ns,
                    const int32_t *shp, const double *hinv, const double *q_cur, double *q_out,
-                   double *qd_out, double h, int acc, uint32_t *status, const GJoint *J,
+                   double *qd_out, double h, int acc, uint32_t *status, const uint8_t *jrows,
                    int step, double *dq_save, int polar_free, int skip_free, hipStream_t s);
 void launch_gather_state(int nd, const int32_t *sol2in, const double *const *q, const double *const *qd,
                          int cur, int cur0, const uint32_t *status, int64_t ns, double *qo, double *qdo,
@@ -286,6 +286,7 @@ struct mabd_ctx {
   uint8_t *d_flag = nullptr;
   double *d_tilerec = nullptr, *d_grow = nullptr, *d_xg = nullptr, *d_clam = nullptr;
   GJoint *d_gj = nullptr;
+  uint8_t *d_jrows = nullptr;  // rows per generic joint
   double *d_gl = nullptr, *d_gt = nullptr, *d_glam = nullptr, *d_Rg = nullptr, *d_ug = nullptr;
   int32_t *d_comp_lvl = nullptr, *d_lvl_off = nullptr, *d_tbody = nullptr, *d_tpk = nullptr,
           *d_tabs_off = nullptr, *d_tabs = nullptr, *d_inc_off = nullptr, *d_inc = nullptr;
@@ -1476,6 +1477,11 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     if (e == hipSuccess) chk(hipHostMalloc((void **)&c->h_ir, 8 * sizeof(double)));
   }
   if (e == hipSuccess) chk(upload(c, &c->d_gj, c->gj));
+  if (e == hipSuccess) {
+    std::vector<uint8_t> jr(c->gj.size());
+    for (size_t k = 0; k < c->gj.size(); ++k) jr[k] = (uint8_t)joint_rows(c->gj[k].type);
+    chk(upload(c, &c->d_jrows, jr));
+  }
   const size_t mg = c->gj.size();
   if (e == hipSuccess) chk(dalloc(c, &c->d_gl, GL_STRIDE * mg));
   if (e == hipSuccess) chk(dalloc(c, &c->d_gt, GT_STRIDE * mg));
@@ -2041,7 +2047,7 @@ hipError_t generic_refine(mabd_ctx *c, double h, int a, int b, const TreeArgs &t
     launch_tree(tc, c->d_gj, (int)c->tbody.size(), c->tc_rounds.data(), ((int)c->tc_rounds.size() - 1) / TC_NSEG,
                 c->tree_split, c->tree_order, c->npath ? &c->pplan : nullptr, s);
     launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_dlam, c->d_Rg, c->d_uc, c->ns,
-                  c->d_shp, c->d_hinv, c->d_q[b], c->d_q[b], c->d_qd[b], h, 1, c->d_status, c->d_gj, 0,
+                  c->d_shp, c->d_hinv, c->d_q[b], c->d_q[b], c->d_qd[b], h, 1, c->d_status, c->d_jrows, 0,
                   nullptr, c->opt.body_solve, 0, s);
     launch_lam_add(5 * (int64_t)mg, c->d_glam, c->d_dlam, c->d_status, s);
     ++c->gir_sweeps;
@@ -2140,6 +2146,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       ta.ops = c->d_tc_ops;
       ta.crec = c->d_crec;
       ta.f32 = c->gen_ir ? 1 : 0;
+      ta.jrows = c->d_jrows;
       tm.run(5, [&] {
         // paths beside the contraction rounds (whose tail rounds leave most
         // of the GPU idle); sequential when kernel groups are timed
@@ -2237,7 +2244,7 @@ hipError_t issue_step(mabd_ctx *c, double h, int a, int b, Timer &tm) {
       tm.run(6, [&] {
         launch_gapply(c->gb0, c->gb1, c->d_inc_off, c->d_inc, c->d_gl, c->d_glam, c->d_Rg, c->d_ug,
                       c->ns, c->d_shp, c->d_hinv, qcur, c->d_q[b], c->d_qd[b], h, it > 0 ? 1 : 0,
-                      c->d_status, c->d_gj, 0, dg_it ? c->d_dqit : nullptr, c->opt.body_solve,
+                      c->d_status, c->d_jrows, 0, dg_it ? c->d_dqit : nullptr, c->opt.body_solve,
                       fuse_free ? 1 : 0, s);
       });
       if (c->gen_ir) {
