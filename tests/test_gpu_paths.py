@@ -10,8 +10,11 @@ block-tridiagonal elimination of the dual over their joints (Sec. 5.3).
   paths then take several levels of separators;
 * the same assemblies through the tree contraction (path_solver = 0): both
   are exact, so states agree to rounding;
-* a batch of ragged paths beside trees and ball chains, the form-1
-  refinement on paths, and a full-size batch against the contraction."""
+* a batch of ragged paths beside trees and ball chains, the path solve on
+  a second stream beside the contraction (bitwise the sequential step), the
+  form-1 refinement on paths, paths beside a loop-breaker component, several
+  Newton iterations, external wrenches, the device KKT residual, and a
+  full-size batch against the contraction."""
 import numpy as np
 import pytest
 
@@ -202,3 +205,56 @@ def test_full_size_batch_against_contraction():
     _, _, dv = s.finish(asm.h, asm.q0, asm.qd0, l1)
     say("oracle kkt of the path solver's multipliers", dv[:3])
     assert dv[oracle.KKT] < 1e-10
+
+
+def test_paths_beside_a_loop_component():
+    """A hinge chain (path) and a tree closed by two extra joints (the
+    loop-breaker's component) in one context: the loop-breaker's extra tree
+    solves run the path solve into their own columns, the step's multipliers
+    stay those of the direct solve."""
+    from test_gpu_loops import run_against_direct, tree_with_loops
+
+    h = moving(mi.chain(200, seed=280, hinge_frac=0.5, origin=(0.0, 30.0, 0.0)), 280)
+    asm = mi.concat([h, tree_with_loops(300, 2, 281)], h=1e-2, steps=2)
+    st = stats_of(asm)
+    say("paths", st["n_path"], "loops", st["n_loop"])
+    assert st["n_path"] >= 1
+    say("worst", run_against_direct(asm, 2, expect_loops=1))
+
+
+def test_path_newton_iterations():
+    asm = moving(mi.chain(200, seed=282, hinge_frac=0.5), 282)
+    say("worst", teacher_forced(asm, 2, newton_iters=3))
+
+
+def test_path_wrenches():
+    from test_gpu_wrench import compare, wrenches
+
+    asm = moving(mi.mix_joint_types(mi.chain(200, seed=283), seed=284), 283)
+    say("worst", compare(asm, wrenches(asm, 285), 2))
+
+
+def test_path_device_residual():
+    """Diagnostics bit 0 on a path: the device's FP64 KKT residual and the
+    oracle's verifier on the same GPU step are both at rounding level, and
+    the hinges' value after the linearised step agrees closely."""
+    from test_gpu_boundary import oracle_check, rounding_level
+
+    asm = moving(mi.chain(400, seed=286, hinge_frac=0.5), 286)
+    import paper_2603_08079_amd as pk
+
+    ctx = pk.Context(asm, diagnostics=1)
+    q, qd = asm.q0.copy(), asm.qd0.copy()
+    for n in range(2):
+        ctx.step(asm.h, 1)
+        st = ctx.stats()
+        qg, qdg = ctx.state()
+        lam = ctx.multipliers()
+        o = oracle_check(asm, q, qd, qg, qdg, lam)
+        say(n, "device", {k: st[k] for k in ("rho_p", "rho_d", "kkt", "c_ball", "c_hinge")}, "oracle", o)
+        assert st["n_path"] == 1
+        assert rounding_level(st["rho_p"], o["rho_p"], 1e-11)
+        assert rounding_level(st["rho_d"], o["rho_d"], 1e-10)
+        assert o["c_hinge"] > 1e-9 and abs(st["c_hinge"] - o["c_hinge"]) <= 1e-6 * o["c_hinge"]
+        q, qd = qg, qdg
+    ctx.close()
