@@ -42,9 +42,41 @@ ALG_BYTES_F1 = {"chain_resid": 288 + 53 + 24 + 120}
 JOINT_ROWS = (3, 5, 4, 5)  # ball, hinge, universal, prismatic
 
 
+def generic_parts(asm):
+    """Masks of the bodies and joints outside the fused chain path: the
+    library takes a component (dynamic bodies connected by joints) as a
+    chain when it is acyclic, every joint is a ball joint, every body carries
+    at most two joints and there are at least two joints (one Newton
+    iteration); everything else is solved on the generic path."""
+    import numpy as np
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    n, m = int(asm.n), int(asm.m)
+    dyn = np.asarray(asm.pinned) == 0
+    ja, jb = np.asarray(asm.ja, np.int64), np.asarray(asm.jb, np.int64)
+    da = (ja >= 0) & dyn[np.clip(ja, 0, None)]
+    db = (jb >= 0) & dyn[np.clip(jb, 0, None)]
+    two = da & db
+    g = coo_matrix((np.ones(int(two.sum())), (ja[two], jb[two])), shape=(n, n))
+    _, comp = connected_components(g, directed=False)
+    jcomp = np.where(da, comp[np.clip(ja, 0, None)], comp[np.clip(jb, 0, None)])
+    inc = np.bincount(ja[da], minlength=n) + np.bincount(jb[db], minlength=n)
+    nc = int(comp.max()) + 1 if n else 0
+    nb = np.bincount(comp[dyn], minlength=nc)
+    nj = np.bincount(jcomp, minlength=nc)
+    edges = np.bincount(jcomp, weights=da.astype(int) + db.astype(int), minlength=nc)
+    nonball = np.bincount(jcomp, weights=(np.asarray(asm.jtype) != 0).astype(int), minlength=nc)
+    maxinc = np.zeros(nc, int)
+    np.maximum.at(maxinc, comp[dyn], inc[dyn])
+    chain = (edges == nb + nj - 1) & (nonball == 0) & (maxinc <= 2) & (nj >= 2)
+    return dyn & ~chain[comp], ~chain[jcomp]
+
+
 def generic_alg_bytes(asm, phase):
     """Algorithmic HBM bytes per launch of a kernel group of the generic
-    (tree) path, FP64, for a context without chain components.  A joint row
+    (tree) path, FP64, counted over the bodies and joints outside the fused
+    chain path (generic_parts).  A joint row
     on one dynamic side is 12 doubles (96 B); a body's state q, qdot is 192 B,
     its rotation 72 B, its local solve 96 B, its shape index 4 B; a joint's
     record is 200 B, its values C and multipliers 8 B per row.
@@ -58,16 +90,18 @@ def generic_alg_bytes(asm, phase):
     import numpy as np
 
     dyn = np.asarray(asm.pinned) == 0
-    nb = int(dyn.sum())
+    bmask, jmask = generic_parts(asm)
+    nb = int(bmask.sum())
     rows = np.asarray(JOINT_ROWS)[np.asarray(asm.jtype, int)] if asm.m else np.zeros(0, int)
     ja, jb = np.asarray(asm.ja), np.asarray(asm.jb)
     sides = ((ja >= 0) & dyn[np.clip(ja, 0, None)]).astype(int) + ((jb >= 0) & dyn[np.clip(jb, 0, None)]).astype(int)
+    rows, sides = rows * jmask, sides * jmask
     side_rows = int((rows * sides).sum())
     nrows = int(rows.sum())
     if phase == "body":
         return nb * (192 + 4 + 72 + 96)
     if phase == "joint":
-        return int(asm.m) * 200 + int(sides.sum()) * 168 + side_rows * 96 + nrows * 8
+        return int(jmask.sum()) * 200 + int(sides.sum()) * 168 + side_rows * 96 + nrows * 8
     if phase == "tree":
         return nb * (96 + 4) + side_rows * 96 + nrows * 16
     if phase == "apply":
@@ -370,7 +404,7 @@ def main():
     roof = None
     ab = ALG_BYTES if chosen == 0 else ALG_BYTES_F1
     alg = ab[dom] * n_dyn if dom in ab else None
-    if alg is None and chosen == 0 and st0["n_chain"] == 0 and not st0["n_graph"]:
+    if alg is None and chosen == 0 and not st0["n_graph"]:
         alg = generic_alg_bytes(asm, dom)
     if alg is not None:
         ach = alg / (per_launch[dom] * 1e-3) / 1e9
