@@ -899,45 +899,58 @@ DEV void tcw_add_children(const TreeArgs &a, int tab, int nent, double *K, doubl
   }
 }
 
-// partial Cholesky of the first np of nr (<= TW + 1) rows of a packed LDS
+// partial Cholesky of the first np of nr (<= R <= TW) rows of a packed LDS
 // clique (the factorisation of tc_partial_cholesky, blocked): pivots are
-// taken in panels of PB columns.  Within a panel, lane i scales row
-// p + 1 + i of the pivot column and updates its row in the panel's later
-// columns; then the trailing triangle gets one rank-PB update, lane i owning
-// column p0 + PB + i, in batches of RB independent rows.
+// taken in panels of PB columns.  Within a panel lane r holds row r's panel
+// entries and y_r in registers; a pivot's value, its right-hand side and
+// the new column entries of the panel's later rows travel by wave shuffles
+// (no LDS round trip or barrier per pivot, one reciprocal square root per
+// pivot instead of a division per row); the panel then goes back to LDS and
+// the trailing triangle gets one rank-PB update, lane i owning column
+// p0 + PB + i, in batches of RB independent rows.
 template <int R, int TW>
 DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, int np) {
+  static_assert(R <= TW, "a lane per clique row");
   constexpr int PB = R >= 32 ? 8 : 4;  // panel width
   constexpr int RB = R >= 32 ? 4 : 8;  // rows per batch of the trailing update
   const int ln = tlane<TW>();
+  const bool mine = ln < nr;  // lane ln holds row ln
+  double yr = mine ? y[ln] : 0.0;
   for (int p0 = 0; p0 < np; p0 += PB) {
     const int pe = p0 + PB < np ? p0 + PB : np;  // panel columns [p0, pe)
-    for (int p = p0; p < pe; ++p) {
-      double d = K[tri(p) + p];
+    double kp[PB];
+#pragma unroll
+    for (int q = 0; q < PB; ++q) kp[q] = mine && p0 + q < pe && p0 + q <= ln ? K[tri(ln) + p0 + q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int p = p0 + q;
+      if (p >= pe) break;  // uniform
+      double d = __shfl(kp[q], p, TW);  // the pivot, updated by the panel's earlier columns
       if (!(d > 0.0)) {
         if (ln == 0) raise_flag(a.status, FLAG_SINGULAR, a.step);
         d = 1.0;
       }
-      d = sqrt(d);
-      const double yp = y[p] / d;
-      const int i = p + 1 + ln;
+      const double sd = sqrt(d), inv = 1.0 / sd;
       double lip = 0.0;
-      if (i < nr) lip = K[tri(i) + p] / d;
-      team_sync();
-      if (ln == 0) {
-        K[tri(p) + p] = d;
-        y[p] = yp;
+      if (ln == p) {
+        kp[q] = sd;
+        yr *= inv;
+      } else if (mine && ln > p) {
+        lip = kp[q] * inv;
+        kp[q] = lip;
       }
-      if (i < nr) {
-        K[tri(i) + p] = lip;
-        y[i] -= lip * yp;
+      const double yp = __shfl(yr, p, TW);
+      if (mine && ln > p) yr -= lip * yp;
+#pragma unroll
+      for (int q2 = q + 1; q2 < PB; ++q2) {  // row ln, panel column j = p0 + q2 <= ln
+        const double ljp = __shfl(kp[q], p0 + q2, TW);  // L[j][p], lane j's new entry
+        if (mine && p0 + q2 < pe && p0 + q2 <= ln) kp[q2] -= lip * ljp;
       }
-      team_sync();
-      if (i < nr) {  // row i, panel columns j in (p, pe), j <= i
-        for (int j = p + 1; j < pe && j <= i; ++j) K[tri(i) + j] -= lip * K[tri(j) + p];
-      }
-      team_sync();
     }
+#pragma unroll
+    for (int q = 0; q < PB; ++q)
+      if (mine && p0 + q < pe && p0 + q <= ln) K[tri(ln) + p0 + q] = kp[q];
+    team_sync();
     const int j = pe + ln;  // trailing column of this lane: rows r >= j
     if (pe < nr && j < nr) {
       double lj[PB];
@@ -962,6 +975,8 @@ DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, i
     }
     team_sync();
   }
+  if (mine) y[ln] = yr;
+  team_sync();
 }
 
 template <int R, int TW>
