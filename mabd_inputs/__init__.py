@@ -18,7 +18,8 @@ Layout conventions (paper Sec. 3.1 and Sec. 4.1):
 Workloads (the paper's scenes are not reproducible: their geometry is not
 published, so these stand in for them at the configurations' sizes):
   chain    -- boxes 1.0 x 0.1 x 0.1 m along x, ball joints at end centres,
-              body 0 pinned (pulley chain, Sec. 6.3 "Joint chain");
+              body 0 pinned (pulley chain, Sec. 6.3 "Joint chain"); with
+              hinge_frac > 0 a share of the joints are hinges (hchain1m);
   tree     -- random tree, parent of body i uniform over the previous `window`
               bodies, ball/hinge 50/50, box edges U(0.05, 0.5) m (Sec. 6.3
               "Joint hierarchy");
@@ -421,4 +422,6 @@ def config(name: str, seed: int = 0) -> Assembly:
         return rgg(100000, seed=seed, steps=100)
     if name == "boxes1m":
         return spinning_boxes(1 << 20, seed=seed, steps=100)
+    if name == "hchain1m":  # the C1 chain at 1M links, ball and hinge joints 50/50
+        return chain(1 << 20, seed=seed, hinge_frac=0.5, steps=100)
     raise KeyError(name)

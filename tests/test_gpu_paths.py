@@ -258,3 +258,27 @@ def test_path_device_residual():
         assert o["c_hinge"] > 1e-9 and abs(st["c_hinge"] - o["c_hinge"]) <= 1e-6 * o["c_hinge"]
         q, qd = qg, qdg
     ctx.close()
+
+
+def test_full_size_hinge_chain_one_step():
+    """A 1,048,576-body chain with ball and hinge joints 50/50 (nine levels
+    of separators), one step from a moving state in the launch configuration
+    the benchmark times, against the oracle's sparse direct solve."""
+    asm = moving(mi.config("hchain1m"), 290, sd=0.02)
+    import paper_2603_08079_amd as pk
+
+    ctx = pk.Context(asm)
+    ctx.step(asm.h, 1)
+    st = ctx.stats()
+    qg, qdg = ctx.state()
+    lam_g = ctx.multipliers()
+    ctx.close()
+    say("hchain1m: paths", st["n_path"], "levels", st["path_levels"], "graph replay", st["graph_replay"])
+    assert st["n_path"] == 1 and st["path_levels"] >= 8 and st["graph_replay"] == 1
+    s = oracle.System(asm)
+    q1, qd1, lam, d = s.step_sparse(asm.h, asm.q0, asm.qd0)
+    eq, eqd = state_errors(qg, qdg, q1, qd1)
+    _, _, dv = s.finish(asm.h, asm.q0, asm.qd0, lam_g)
+    say("errors", eq, eqd, "oracle kkt", d[:3], "kkt of GPU multipliers", dv[:3])
+    assert eq < TOL and eqd < TOL
+    assert dv[oracle.KKT] <= max(10 * d[oracle.KKT], 1e-11)
