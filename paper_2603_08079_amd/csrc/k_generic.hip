@@ -904,8 +904,7 @@ DEV void tcw_add_children(const TreeArgs &a, int tab, int nent, double *K, doubl
 // taken in panels of PB columns.  Within a panel lane r holds row r's panel
 // entries and y_r in registers; a pivot's value, its right-hand side and
 // the new column entries of the panel's later rows travel by wave shuffles
-// (no LDS round trip or barrier per pivot, one reciprocal square root per
-// pivot instead of a division per row); the panel then goes back to LDS and
+// (no LDS round trip or barrier per pivot); the panel then goes back to LDS and
 // the trailing triangle gets one rank-PB update, lane i owning column
 // p0 + PB + i, in batches of RB independent rows.
 template <int R, int TW>
@@ -930,13 +929,13 @@ DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, i
         if (ln == 0) raise_flag(a.status, FLAG_SINGULAR, a.step);
         d = 1.0;
       }
-      const double sd = sqrt(d), inv = 1.0 / sd;
+      const double sd = sqrt(d);
       double lip = 0.0;
       if (ln == p) {
         kp[q] = sd;
-        yr *= inv;
+        yr /= sd;
       } else if (mine && ln > p) {
-        lip = kp[q] * inv;
+        lip = kp[q] / sd;
         kp[q] = lip;
       }
       const double yp = __shfl(yr, p, TW);
