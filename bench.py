@@ -238,6 +238,9 @@ def main():
                     help="precision 1: target KKT residual of the refinement")
     ap.add_argument("--body-solve", type=int, choices=(0, 1), default=0,
                     help="1: bodies without joints take the polar-free solve (Alg. 1)")
+    ap.add_argument("--path-solver", type=int, choices=(0, 1), default=1,
+                    help="0: tree components that are paths go through the tree contraction "
+                         "instead of the path solver")
     ap.add_argument("--wrenches", action="store_true",
                     help="apply a seeded wind-like load at every step: force 0.2 m g along +x with "
                          "2 %% noise, torques of 1 %% of m g times the body size")
@@ -293,7 +296,8 @@ def main():
     def make(precision, **kw):
         tol = args.ir_tol if precision == 1 else args.kkt_tol
         c = pk.Context(asm, stream=stream.cuda_stream, precision=precision, kkt_tol=tol,
-                       max_iters=args.max_iters, body_solve=args.body_solve, **kw)
+                       max_iters=args.max_iters, body_solve=args.body_solve,
+                       path_solver=args.path_solver, **kw)
         if wrench is not None:
             c.set_wrenches(wrench)
         return c
@@ -472,7 +476,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "bodies": asm.n, "dynamic_bodies": n_dyn,
                    "joints": asm.m, "h": h, "newton_iters": 1, "wrenches": bool(args.wrenches),
-                   "body_solve": args.body_solve,
+                   "body_solve": args.body_solve, "path_solver": args.path_solver,
                    "form": FORMS[chosen], "graph_replay": bool(st["graph_replay"]),
                    "chain_tile_threads": st["tile_threads"],
                    "chain_tiles_packed": bool(st["tile_packed"])},
