@@ -171,11 +171,13 @@ typedef struct {
   int32_t path_solver;     /* 1 (default): tree components whose bodies carry at most two
                               joints each (paths: chains with hinge, universal or
                               prismatic joints, free-floating chains) are solved as
-                              block-tridiagonal systems over their joints, segments of
-                              up to 16 joints (4 above the first level) eliminated one
-                              per lane, level by level over the segments' last joints;
-                              0: by the tree
-                              contraction like every other tree.  Both are exact
+                              block-tridiagonal systems over their joints: segments of
+                              up to 16 joints, each eliminated by a team of 16 lanes
+                              that forms the joints' blocks from the joint rows, then
+                              level by level over the segments' last joints (segments
+                              of 4, one lane each); the solve runs on a second stream
+                              beside the tree contraction when both are large.  0: by
+                              the tree contraction like every other tree.  Both are exact
                               (Sec. 5.3) and agree to rounding.  The environment
                               variable MABD_PATH_SEGMENT = T or T0,T1 sets the segment
                               length (T0 = 2..16 at the first level, T1 = 2..64 above)
