@@ -250,9 +250,9 @@ void mabd_options_default(mabd_options *opt);
 
 /* Validates and copies the assembly, classifies every connected component of
    dynamic bodies (chain: the dual graph of Fig. dual_mat is a path with only
-   ball joints; tree: body/joint incidence graph acyclic; loop: a spanning
-   tree plus loop-closing joints of at most 48 rows (Case III); graph:
-   otherwise),
+   ball joints; tree: body/joint incidence graph acyclic, a path when every
+   body carries at most two joints (path_solver); loop: a spanning tree plus
+   loop-closing joints of at most 48 rows (Case III); graph: otherwise),
    builds the solve schedules and uploads state and schedules to the device.
    Pinned bodies become constant world-side anchors.  opt may be NULL
    (defaults).  On success *out receives a context to free with mabd_destroy.
