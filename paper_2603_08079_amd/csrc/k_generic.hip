@@ -950,16 +950,25 @@ DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, i
     for (int q = 0; q < PB; ++q)
       if (mine && p0 + q < pe && p0 + q <= ln) K[tri(ln) + p0 + q] = kp[q];
     team_sync();
-    const int j = pe + ln;  // trailing column of this lane: rows r >= j
-    if (pe < nr && j < nr) {
+    // trailing column pe + c, rows [rb, re): lane c < ntr owns column c; the
+    // lanes past the last column (nh of them) take the lower halves of the
+    // nh longest columns, so the longest chain of rows is about halved
+    const int ntr = nr - pe;
+    const int nh = ntr < TW - ntr ? ntr : TW - ntr;
+    const int c = ln < ntr ? ln : ln - ntr;
+    const int j = pe + c;
+    const int mid = j + ((nr - j + 1) >> 1);
+    const int rb = ln < ntr ? j : (c < nh ? mid : nr);
+    const int re = ln < ntr && c < nh ? mid : nr;
+    if (pe < nr && rb < re) {
       double lj[PB];
 #pragma unroll
       for (int q = 0; q < PB; ++q) lj[q] = p0 + q < pe ? K[tri(j) + p0 + q] : 0.0;
-      for (int r = j; r < nr; r += RB) {
+      for (int r = rb; r < re; r += RB) {
         double kv[RB], upd[RB];
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
-          const int rr = r + u < nr ? r + u : nr - 1;
+          const int rr = r + u < re ? r + u : re - 1;
           const double *row = K + tri(rr);
           kv[u] = row[j];
           double t = 0.0;
@@ -969,7 +978,7 @@ DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, i
         }
 #pragma unroll
         for (int u = 0; u < RB; ++u)
-          if (r + u < nr) K[tri(r + u) + j] = kv[u] - upd[u];
+          if (r + u < re) K[tri(r + u) + j] = kv[u] - upd[u];
       }
     }
     team_sync();
