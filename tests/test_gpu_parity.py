@@ -223,6 +223,20 @@ def test_wide_tree_contraction():
     say("worst", teacher_forced(asm, 2, tol_v=TOL_V_TREE))
 
 
+def test_largest_clique_rake():
+    """Hinge tree below a pinned body 0 and one link (body 1): bodies 2-12
+    each carry eleven 5-row leaf joints under a 5-row parent joint, so they
+    are raked with cliques of 60 rows (the largest LDS-staged class, within
+    4 of the 64-row limit) and the partial Cholesky's trailing triangles are
+    wider than half a wave; body 1 ends with a 60-row root clique."""
+    parents = np.array([0, 0] + [1] * 11 + [2 + j // 11 for j in range(121)])
+    n = len(parents)
+    asm = mi.tree(n, seed=49, parents=parents, hinge_frac=1.0)
+    asm.qd0[1:] = np.random.default_rng(49).normal(0, 0.05, (n - 1, 12))
+    say("11-ary hinge tree", n)
+    say("worst", teacher_forced(asm, 2, tol_v=TOL_V_TREE))
+
+
 def test_large_clique_compress():
     """A body with ten hinge leaves and one hinge child chain, under a short
     chain: after the leaves are raked it has a single live child, so it is
