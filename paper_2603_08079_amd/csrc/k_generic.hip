@@ -1198,13 +1198,22 @@ DEV void tcw_private_back(const TreeArgs &a, const GJoint *J, const TcOp &op, in
   double t = 0.0;
   if (ln < np) t = yg[ln];
   team_sync();
+  double dg = 1.0, rdg = 1.0;  // this lane's diagonal entry and its reciprocal
   if (ln < np) {
+    dg = Ks[tri(ln) + ln];
+    rdg = 1.0 / dg;  // formed before the substitution's dependent chain
 #pragma unroll
     for (int f = 0; f < 10; ++f)
       if (f < nb) t -= Ks[tri(np + f) + ln] * lb[f];
   }
   for (int l = np - 1; l >= 0; --l) {
-    if (ln == l) t /= Ks[tri(l) + l];
+    if (ln == l) {
+      // t / dg from the correctly rounded reciprocal with one remainder step
+      // (Markstein's division): the correctly rounded quotient, so the same
+      // value as the division, in three dependent operations
+      const double q0 = t * rdg;
+      t = fma(fma(-q0, dg, t), rdg, q0);
+    }
     const double tl = __shfl(t, l, TW);
     if (ln < l) t -= Ks[tri(l) + ln] * tl;
   }
@@ -1289,6 +1298,12 @@ DEV void tcw_compress_back_body(const TreeArgs &a, const GJoint *J, int op0, int
     }
     le[p] = v;
   }
+  double dp[5], rdp[5];  // Lp's diagonal and its reciprocals, before the chain
+#pragma unroll
+  for (int p = 0; p < 5; ++p) {
+    dp[p] = p < ce ? Lp[5 * p + p] : 1.0;
+    rdp[p] = 1.0 / dp[p];
+  }
 #pragma unroll
   for (int p = 4; p >= 0; --p) {
     if (p < ce) {
@@ -1296,7 +1311,8 @@ DEV void tcw_compress_back_body(const TreeArgs &a, const GJoint *J, int op0, int
 #pragma unroll
       for (int q = p + 1; q < 5; ++q)
         if (q < ce) s -= Lp[5 * q + p] * le[q];
-      le[p] = s / Lp[5 * p + p];
+      const double q0 = s * rdp[p];  // s / dp[p], correctly rounded (as in tcw_private_back)
+      le[p] = fma(fma(-q0, dp[p], s), rdp[p], q0);
     }
   }
   if (ln < 5) a.glam[5 * (int64_t)op.e + ln] = ln < ce ? le[ln] : 0.0;
