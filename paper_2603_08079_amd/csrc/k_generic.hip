@@ -906,7 +906,8 @@ DEV void tcw_add_children(const TreeArgs &a, int tab, int nent, double *K, doubl
 // the new column entries of the panel's later rows travel by wave shuffles
 // (no LDS round trip or barrier per pivot); the panel then goes back to LDS and
 // the trailing triangle gets one rank-PB update, lane i owning column
-// p0 + PB + i, in batches of RB independent rows.
+// p0 + PB + i, in batches of RB independent rows, and the lanes past the
+// last column taking the lower halves of the longest columns.
 template <int R, int TW>
 DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, int np) {
   static_assert(R <= TW, "a lane per clique row");
