@@ -181,7 +181,9 @@ typedef struct {
                               (Sec. 5.3) and agree to rounding.  The environment
                               variable MABD_PATH_SEGMENT = T or T0,T1 sets the segment
                               length (T0 = 2..16 at the first level, T1 = 2..64 above)
-                              at mabd_create (for testing)                             */
+                              and MABD_PATH_FORK = n the number of forward contraction
+                              rounds left when the second stream forks (default 3), at
+                              mabd_create (for testing)                                */
   const char *tune_cache;  /* path of a tuning cache file, or NULL (default): with
                               autotune on, a context whose device and schedule shape
                               (chain rows and count, tree slots and rounds) have an

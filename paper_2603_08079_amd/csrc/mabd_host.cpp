@@ -1136,7 +1136,9 @@ mabd_status mabd_create(const mabd_bodies *B, const mabd_joints *Jn, const mabd_
     // the first round made the path kernels compete with the large rounds;
     // measured on the 4,096-assembly batch: 9.89 ms at round 0, 9.78 ms at
     // round 10 of 13)
-    c->fork_round = std::max(0, ((int)c->tc_rounds.size() - 1) / TC_NSEG - 3);
+    int fork_back = 3;  // MABD_PATH_FORK: forward rounds after the fork
+    if (const char *pf = std::getenv("MABD_PATH_FORK")) fork_back = std::max(0, std::atoi(pf));
+    c->fork_round = std::max(0, ((int)c->tc_rounds.size() - 1) / TC_NSEG - fork_back);
     // factor slots: K and y with leading dimension absorbed rows + 5, plus
     // the pre-pass scratch of large cliques
     c->foff.clear();
