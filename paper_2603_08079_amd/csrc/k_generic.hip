@@ -912,7 +912,7 @@ template <int R, int TW>
 DEV void tcw_partial_cholesky(const TreeArgs &a, double *K, double *y, int nr, int np) {
   static_assert(R <= TW, "a lane per clique row");
   constexpr int PB = R >= 32 ? 8 : 4;  // panel width
-  constexpr int RB = R >= 32 ? 4 : 8;  // rows per batch of the trailing update
+  constexpr int RB = 4;  // rows per batch of the trailing update
   const int ln = tlane<TW>();
   const bool mine = ln < nr;  // lane ln holds row ln
   double yr = mine ? y[ln] : 0.0;
